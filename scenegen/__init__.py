@@ -1,0 +1,9 @@
+"""Seeded synthetic scene generator shared by the oracle side and the GPU side.
+
+It produces inputs only (cameras, features, groups, measurements,
+associations); see ``scenegen.scene``.
+"""
+from .scene import (CONFIGS, DEFAULT_LOSS, OBS_POINT, OBS_LINE, ASSOC_PLANE_POINT,  # noqa: F401
+                    ASSOC_PLANE_LINE, ASSOC_VP_LINE, ASSOC_JUNCTION, LOSS_TRIVIAL,
+                    LOSS_HUBER, LOSS_CAUCHY, make_scene, scene_counts, small_config,
+                    config_seed, quaternion_to_matrix, matrix_to_quaternion)
