@@ -1,0 +1,241 @@
+/*
+ * Holistic bundle adjustment on one MI355X (gfx950): the C ABI of libba.so.
+ *
+ * One call of ba_lm_step runs one Levenberg-Marquardt iteration of the
+ * unified bundle adjustment of "Stable and Scalable Bundle Adjustment of
+ * Holistic 3D Structures": residuals and Jacobians of every point, line,
+ * group-induced and cross-feature reprojection term, Schur elimination of
+ * the block-diagonal feature Hessian into the reduced camera + group system
+ * (Sec. 3.1 Eq. 3, Sec. 3.2 Eq. 5) and an implicit-Schur preconditioned
+ * conjugate-gradient solve of that system, followed by back-substitution,
+ * the FP64 cost of the candidate and the gain-ratio test.
+ *
+ * Conventions shared by every entry point
+ *  - Ownership: every pointer argument is borrowed for the duration of the
+ *    call; the library copies what it keeps.  Output arrays are allocated
+ *    by the caller; a NULL output is skipped.  The handle owns all device
+ *    memory and releases it in ba_destroy.
+ *  - Errors: every call returns a ba_status; nothing else crosses the ABI.
+ *    ba_last_error returns a handle-owned message, valid until the next
+ *    call on that handle.
+ *  - Threads: one handle per host thread.  Calls are synchronous with the
+ *    host: when a call returns, its device work has finished.
+ *  - Device: the handle runs on desc->device; hip_stream (a hipStream_t)
+ *    may name a caller stream, NULL makes the library create its own.
+ *
+ * Parameter formats (all double)
+ *  - camera  (10): qw qx qy qz tx ty tz f k1 k2.  X_cam = R(q) X + t;
+ *    pixel = f s (u, v) + (cx, cy), (u, v) = X_cam,xy / X_cam,z,
+ *    s = 1 + k1 r^2 + k2 r^4 (distorted); lines live in undistorted pixels.
+ *  - point    (3): X.
+ *  - line     (6): two distinct 3D points on the line (input);
+ *    output of ba_get_parameters: unit direction d and moment m / |d|
+ *    with m = p x d for p on the line (normalised Pluecker coordinates).
+ *  - plane    (4): nx ny nz w with |n| = 1 and n . x + w = 0 (App. B).
+ *  - vp       (3): unit direction (App. B).
+ */
+#ifndef BA_H
+#define BA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ba_handle ba_handle; /* opaque; owns all device memory */
+
+typedef enum {
+  BA_OK = 0,
+  BA_E_INVALID = 1,        /* bad argument: index out of range, NaN/inf, duplicate, ... */
+  BA_E_STATE = 2,          /* call not legal in the handle's current state */
+  BA_E_OOM = 3,            /* host or device allocation failed */
+  BA_E_DEVICE = 4,         /* a HIP runtime call failed */
+  BA_E_NUMERIC = 5,        /* non-finite cost; parameters rolled back */
+  BA_E_NOT_CONVERGED = 6   /* ba_solve reached max_iters; results are valid */
+} ba_status;
+
+typedef enum { BA_PREC_FP64 = 0, BA_PREC_MIXED = 1 } ba_precision;
+typedef enum { BA_PC_BLOCK_JACOBI = 0, BA_PC_LEARNED = 1 } ba_precond;
+
+/* Observation / association kinds accepted by ba_add_observations. */
+typedef enum {
+  BA_OBS_POINT = 0,         /* a = camera, b = point; meas[4] = x y (distorted px), xu yu (undistorted px) */
+  BA_OBS_LINE = 1,          /* a = camera, b = line;  meas[4] = e1x e1y e2x e2y (undistorted px)            */
+  BA_ASSOC_PLANE_POINT = 2, /* a = plane,  b = point; meas = NULL */
+  BA_ASSOC_PLANE_LINE = 3,  /* a = plane,  b = line;  meas = NULL */
+  BA_ASSOC_VP_LINE = 4,     /* a = vp,     b = line;  meas = NULL */
+  BA_ASSOC_JUNCTION = 5     /* a = point,  b = line;  meas = NULL (the point lies on the line) */
+} ba_kind;
+
+typedef enum { BA_LOSS_TRIVIAL = 0, BA_LOSS_HUBER = 1, BA_LOSS_CAUCHY = 2 } ba_loss_kind;
+
+/* Robust loss of one residual family: cost = weight * rho(|r|^2) / 2 with
+ * rho(s) = s (trivial), Huber: s <= scale^2 ? s : 2 scale sqrt(s) - scale^2,
+ * Cauchy: scale^2 log(1 + s / scale^2). */
+typedef struct {
+  int32_t kind;  /* ba_loss_kind */
+  double scale;
+  double weight;
+} ba_loss;
+
+typedef struct {
+  int32_t n_cameras, n_points, n_lines, n_planes, n_vps;
+  int32_t camera_dof;     /* 9 = rotation, translation, f, k1, k2; 6 = pose only */
+  double cx, cy;          /* fixed principal point */
+  const double *cameras;  /* n_cameras x 10 */
+  const double *points;   /* n_points x 3 */
+  const double *lines;    /* n_lines x 6 (two points) */
+  const double *planes;   /* n_planes x 4 */
+  const double *vps;      /* n_vps x 3 */
+  int32_t precision;      /* ba_precision */
+  int32_t precond;        /* ba_precond */
+  void *hip_stream;       /* hipStream_t or NULL */
+  int32_t device;
+} ba_problem_desc;
+
+typedef struct {
+  int32_t max_iters;      /* ba_solve: attempts (accepted or rejected); default 100 */
+  double func_tol;        /* stop after an accepted step with |dE_pix| / E_pix < func_tol; 1e-6 */
+  double grad_tol;        /* stop when |g|_inf < grad_tol; 1e-10 */
+  double pcg_tol;         /* PCG stops at |r_k| <= pcg_tol |b|; 1e-6 */
+  int32_t pcg_max_iters;  /* 1000 */
+  double lambda0;         /* initial Marquardt lambda (used on the first step only); 1e-4 */
+  double nu0;             /* 2 */
+  double kappa_max;       /* FP32 feature blocks with estimated condition above it are redone in FP64; 1e4 */
+} ba_solve_options;
+
+enum {
+  BA_PHASE_LINEARIZE = 0, BA_PHASE_FEATURE = 1, BA_PHASE_SCHUR = 2, BA_PHASE_PRECOND = 3,
+  BA_PHASE_PCG = 4, BA_PHASE_BACKSUB = 5, BA_PHASE_COST = 6, BA_PHASE_COUNT = 8
+};
+
+typedef struct {
+  double E_before, E_after;      /* 1/2 sum w rho, FP64 (E_after = candidate cost) */
+  double Epix_before, Epix_after;/* same without the angular VP family (Sec. 3.5) */
+  double model_decrease;         /* L(0) - L(h) */
+  double gain_ratio;
+  double lambda;                 /* lambda used by this step */
+  int32_t accepted;
+  int32_t pcg_iters;
+  double pcg_rel_residual;       /* |r_k| / |b| (recursive residual) */
+  int32_t n_fp64_blocks;         /* feature blocks inverted in FP64 */
+  int32_t relinearized;          /* 1 if this step evaluated Jacobians */
+  double ms[BA_PHASE_COUNT];     /* device time per phase */
+} ba_step_report;
+
+typedef struct {
+  int32_t iters, accepted;
+  double E_initial, E_final, Epix_final;
+  int32_t termination;           /* 0 func_tol, 1 grad_tol, 2 max_iters, 3 lambda_max, 4 numeric */
+  double total_ms;
+  int32_t pcg_iters_total;
+} ba_summary;
+
+/* Fill *opt with the defaults listed in ba_solve_options. */
+void ba_default_options(ba_solve_options *opt);
+
+/* Create a problem (Sec. 3.1: cameras C_i = (K, R_i, t_i); Sec. 3.2:
+ * features (points, lines) and groups (planes, VPs) placed with the
+ * cameras in the non-eliminated set A).  Copies the initial parameters to
+ * the device (FP64 master copy).  Errors: BA_E_INVALID for negative
+ * counts, camera_dof other than 6 or 9, non-finite values, non-unit plane
+ * normals or VPs (| |n| - 1 | > 1e-6), degenerate lines; BA_E_DEVICE /
+ * BA_E_OOM on device failure.  On error *out is NULL. */
+ba_status ba_create(const ba_problem_desc *desc, ba_handle **out);
+
+/* Append n observations or associations of one kind (ba_kind; layouts
+ * above).  a, b: int32 arrays of length n; meas: n x 4 doubles for the
+ * two observation kinds, NULL otherwise.  loss: the robust loss of the
+ * residual family the kind creates (NULL keeps the default: trivial for
+ * points and lines; Cauchy 1 px, weight 0.5 for plane associations;
+ * Cauchy 0.2, weight 5e3 for VP-line; Cauchy 1 px, weight 0.1 for
+ * junctions - weights from the paper's supplementary Sec. C).  Legal only
+ * before the first ba_lm_step / ba_solve (else BA_E_STATE).  Errors:
+ * BA_E_INVALID for out-of-range indices or non-finite measurements.
+ * Duplicate observations, a feature in two planes or a line in two VPs
+ * are reported by the first ba_lm_step. */
+ba_status ba_add_observations(ba_handle *h, int32_t kind, int64_t n, const int32_t *a, const int32_t *b,
+                              const double *meas, const ba_loss *loss);
+
+/* Exactly one LM iteration (one solve attempt, accepted or rejected).
+ * The first call expands associations into residual records with the
+ * visibility rules of Sec. 3.3-3.4 (the analogue of the symbolic phase of
+ * Sec. 4.1).  opt NULL = defaults; lambda0 applies to the first call only,
+ * later calls continue the handle's lambda / nu.  rep may be NULL.
+ * Errors: BA_E_INVALID for inconsistent observations (reported here);
+ * BA_E_NUMERIC when the cost is not finite (parameters unchanged). */
+ba_status ba_lm_step(ba_handle *h, const ba_solve_options *opt, ba_step_report *rep);
+
+/* ba_lm_step until termination (Sec. 3.5: relative change of the pixel
+ * cost on accepted steps; see ba_solve_options).  Returns BA_OK or
+ * BA_E_NOT_CONVERGED (parameters and summary still valid). */
+ba_status ba_solve(ba_handle *h, const ba_solve_options *opt, ba_summary *sum);
+
+/* Current parameters (formats above; lines as unit d and m / |d|). */
+ba_status ba_get_parameters(const ba_handle *h, double *cameras, double *points, double *lines,
+                            double *planes, double *vps);
+
+/* Replace the parameters (input formats of ba_create).  Any array may be
+ * NULL (kept).  Resets the linearisation; lambda / nu are kept. */
+ba_status ba_set_parameters(ba_handle *h, const double *cameras, const double *points, const double *lines,
+                            const double *planes, const double *vps);
+
+/* LM damping state (for resume): get and set lambda and nu. */
+ba_status ba_get_lm_state(const ba_handle *h, double *lambda, double *nu);
+ba_status ba_set_lm_state(ba_handle *h, double lambda, double nu);
+
+/* Inspection entry points used by parity checks.
+ *
+ * ba_linearize: evaluate residuals, Jacobians, the feature blocks V_f,
+ * the reduced right-hand side b and the diagonal blocks of S at the
+ * current parameters and damping lambda (Sec. 3.1 Eq. 3), without
+ * stepping.  Requires the records to exist (calls the expansion if
+ * needed). */
+ba_status ba_linearize(ba_handle *h, double lambda);
+
+/* Number of residual records of a family (1 point, 2 line, 3 plane-point,
+ * 4 plane-line, 5 vp-line, 6 point-to-line, 7 line-to-point). */
+ba_status ba_record_count(const ba_handle *h, int32_t family, int64_t *count);
+
+/* Export the last linearisation of a family, in the handle's internal record
+ * order.  keys: count x 3 int64 (camera or -1, feature, group / partner
+ * feature or -1, in the caller's indices); r: count x rows (IRLS-weighted,
+ * as used by the solver); J: count x rows x (camera_dof + feature dof +
+ * group dof) in that column order (weighted).  Any output may be NULL. */
+ba_status ba_export_records(const ba_handle *h, int32_t family, int64_t *keys, double *r, double *J);
+
+/* Feature blocks of the last linearisation: V_f = sum J~_f^T J~_f (undamped)
+ * and g_f, points (n_points x 9 and x 3) and lines (n_lines x 16 and x 4),
+ * caller's feature order. */
+ba_status ba_export_feature_blocks(const ba_handle *h, double *Vp, double *gp, double *Vl, double *gl);
+
+/* Reduced system at the damping of the last ba_linearize: b (n_A) and the
+ * diagonal blocks of S (cameras n_cameras x cd x cd, planes x 3 x 3,
+ * vps x 2 x 2), A ordered cameras, planes, vps. */
+ba_status ba_export_reduced(const ba_handle *h, double *b, double *S_cam, double *S_plane, double *S_vp);
+
+/* y = S x with the implicit Schur product at the last linearisation
+ * (x, y: n_A doubles on the host). */
+ba_status ba_schur_matvec(ba_handle *h, const double *x, double *y);
+
+/* Solve S x = b of the last ba_linearize with the handle's PCG
+ * (preconditioner of desc->precond); x: n_A doubles; iters, rel_res out. */
+ba_status ba_pcg_solve(ba_handle *h, double tol, int32_t max_iters, double *x, int32_t *iters, double *rel_res);
+
+/* Sizes: n_A (reduced dimension) and camera_dof. */
+ba_status ba_reduced_dim(const ba_handle *h, int64_t *n_A, int32_t *camera_dof);
+
+/* Learned preconditioner: load network weights (blob layout of the
+ * learned-preconditioner section of the design notes).  Invalid sizes ->
+ * BA_E_INVALID. */
+ba_status ba_set_gnn_weights(ba_handle *h, const void *blob, size_t bytes);
+
+const char *ba_last_error(const ba_handle *h);
+void ba_destroy(ba_handle *h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BA_H */

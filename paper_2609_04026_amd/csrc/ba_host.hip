@@ -1,0 +1,1119 @@
+// Host side of libba: the C ABI, input validation, the one-time expansion of
+// associations into residual records (the analogue of the symbolic phase of
+// the paper's Sec. 4.1), device buffer management and the Levenberg-Marquardt
+// driver around the kernels of ba_kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <functional>
+#include <numeric>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/ba.h"
+#include "ba_internal.h"
+#include "ba_gnn.h"
+
+using namespace ba;
+
+namespace {
+
+struct BaError : std::runtime_error {
+  ba_status code;
+  BaError(ba_status c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define HIPCHK(call)                                                                         \
+  do {                                                                                       \
+    hipError_t _e = (call);                                                                  \
+    if (_e != hipSuccess)                                                                    \
+      throw BaError(BA_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(_e));        \
+  } while (0)
+
+constexpr int PCG_CHECK_EVERY = 8;
+
+// ---------------------------------------------------------------------------
+// parameter conversions (FP64, host)
+void quat_to_R(const double* q0, double* R) {
+  double n = std::sqrt(q0[0] * q0[0] + q0[1] * q0[1] + q0[2] * q0[2] + q0[3] * q0[3]);
+  double w = q0[0] / n, x = q0[1] / n, y = q0[2] / n, z = q0[3] / n;
+  R[0] = 1 - 2 * (y * y + z * z); R[1] = 2 * (x * y - w * z); R[2] = 2 * (x * z + w * y);
+  R[3] = 2 * (x * y + w * z); R[4] = 1 - 2 * (x * x + z * z); R[5] = 2 * (y * z - w * x);
+  R[6] = 2 * (x * z - w * y); R[7] = 2 * (y * z + w * x); R[8] = 1 - 2 * (x * x + y * y);
+}
+
+void R_to_quat(const double* m, double* q) {
+  double tr = m[0] + m[4] + m[8];
+  if (tr > 0) {
+    double s = std::sqrt(tr + 1.0) * 2;
+    q[0] = 0.25 * s; q[1] = (m[7] - m[5]) / s; q[2] = (m[2] - m[6]) / s; q[3] = (m[3] - m[1]) / s;
+  } else if (m[0] > m[4] && m[0] > m[8]) {
+    double s = std::sqrt(1.0 + m[0] - m[4] - m[8]) * 2;
+    q[0] = (m[7] - m[5]) / s; q[1] = 0.25 * s; q[2] = (m[1] + m[3]) / s; q[3] = (m[2] + m[6]) / s;
+  } else if (m[4] > m[8]) {
+    double s = std::sqrt(1.0 + m[4] - m[0] - m[8]) * 2;
+    q[0] = (m[2] - m[6]) / s; q[1] = (m[1] + m[3]) / s; q[2] = 0.25 * s; q[3] = (m[5] + m[7]) / s;
+  } else {
+    double s = std::sqrt(1.0 + m[8] - m[0] - m[4]) * 2;
+    q[0] = (m[3] - m[1]) / s; q[1] = (m[2] + m[6]) / s; q[2] = (m[5] + m[7]) / s; q[3] = 0.25 * s;
+  }
+  if (q[0] < 0) for (int i = 0; i < 4; ++i) q[i] = -q[i];
+  double n = std::sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+  for (int i = 0; i < 4; ++i) q[i] /= n;
+}
+
+void cross(const double* a, const double* b, double* o) {
+  o[0] = a[1] * b[2] - a[2] * b[1];
+  o[1] = a[2] * b[0] - a[0] * b[2];
+  o[2] = a[0] * b[1] - a[1] * b[0];
+}
+double norm3(const double* a) { return std::sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]); }
+
+// unit vector orthogonal to u: normalise(e_k - (e_k . u) u), k = argmin |u_k|
+void ortho_unit(const double* u, double* o) {
+  int k = 0;
+  if (std::fabs(u[1]) < std::fabs(u[k])) k = 1;
+  if (std::fabs(u[2]) < std::fabs(u[k])) k = 2;
+  for (int i = 0; i < 3; ++i) o[i] = (i == k ? 1.0 : 0.0) - u[k] * u[i];
+  double n = norm3(o);
+  for (int i = 0; i < 3; ++i) o[i] /= n;
+}
+
+// orthonormal line representation from two points: slot u1 u2 u3 w1 w2 pad
+bool line_from_points(const double* P, const double* Q, double* slot) {
+  double d[3] = {Q[0] - P[0], Q[1] - P[1], Q[2] - P[2]}, m[3];
+  cross(P, d, m);
+  double nd = norm3(d), nm = norm3(m);
+  if (!(nd > 0) || !std::isfinite(nd) || !std::isfinite(nm)) return false;
+  double u1[3] = {d[0] / nd, d[1] / nd, d[2] / nd}, u2[3], u3[3];
+  if (nm < 1e-12 * nd) {
+    ortho_unit(u1, u2);
+    nm = 0;
+  } else {
+    for (int i = 0; i < 3; ++i) u2[i] = m[i] / nm;
+  }
+  cross(u1, u2, u3);
+  double s = std::sqrt(nd * nd + nm * nm);
+  for (int i = 0; i < 3; ++i) { slot[i] = u1[i]; slot[3 + i] = u2[i]; slot[6 + i] = u3[i]; }
+  slot[9] = nd / s; slot[10] = nm / s; slot[11] = 0;
+  return true;
+}
+
+void sphere_basis(const double* n, double* b1, double* b2) {
+  ortho_unit(n, b1);
+  cross(n, b1, b2);
+}
+
+// ---------------------------------------------------------------------------
+struct DevAlloc {
+  std::vector<void*> ptrs;
+  template <typename P> P* get(size_t count, size_t elem = sizeof(P)) {
+    if (count == 0) count = 1;
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, count * elem);
+    if (e != hipSuccess) throw BaError(BA_E_OOM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    ptrs.push_back(p);
+    return (P*)p;
+  }
+  void free_all() {
+    for (void* p : ptrs) (void)hipFree(p);
+    ptrs.clear();
+  }
+};
+
+struct Obs {
+  std::vector<int32_t> a, b;
+  std::vector<double> meas;
+  ba_loss loss;
+  bool loss_set = false;
+};
+
+}  // namespace
+
+struct ba_handle {
+  // problem
+  int nc = 0, np = 0, nl = 0, ng = 0, nv = 0, CD = 9;
+  double cx = 0, cy = 0;
+  int precision = BA_PREC_MIXED, precond = BA_PC_BLOCK_JACOBI;
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::string err;
+  // host FP64 parameters in the device layouts (original feature order)
+  std::vector<double> cam, pt, ln, pl, vp;
+  Obs obs[6];
+  // state
+  bool finalized = false, need_lin = true, have_cost = false, first_step = true;
+  double lambda = 1e-4, nu = 2.0, E = 0, Epix = 0, last_lambda = 0;
+  // internal permutations: internal feature id -> caller id and inverse
+  std::vector<int32_t> pt_perm, pt_inv, ln_perm, ln_inv;
+  // record keys per family in caller indices (camera, feature, other)
+  std::vector<int64_t> keys[NFAM];
+  Dev d;
+  DevAlloc alloc;
+  double* hscal = nullptr;  // pinned host mirror of d.scal
+  ba_gnn::Net* gnn = nullptr;
+  hipEvent_t ev[BA_PHASE_COUNT + 1] = {};
+  bool events = false;
+};
+
+namespace {
+
+ba_loss default_loss(int kind) {
+  switch (kind) {
+    case BA_ASSOC_PLANE_POINT: case BA_ASSOC_PLANE_LINE: return {BA_LOSS_CAUCHY, 1.0, 0.5};
+    case BA_ASSOC_VP_LINE: return {BA_LOSS_CAUCHY, 0.2, 5.0e3};
+    case BA_ASSOC_JUNCTION: return {BA_LOSS_CAUCHY, 1.0, 0.1};
+    default: return {BA_LOSS_TRIVIAL, 1.0, 1.0};
+  }
+}
+
+template <typename V> void upload(ba_handle* h, V* dst, const std::vector<V>& src) {
+  if (!src.empty()) HIPCHK(hipMemcpyAsync(dst, src.data(), src.size() * sizeof(V), hipMemcpyHostToDevice, h->stream));
+}
+
+void sync(ba_handle* h) { HIPCHK(hipStreamSynchronize(h->stream)); }
+
+void set_device(ba_handle* h) { HIPCHK(hipSetDevice(h->device)); }
+
+// ---------------------------------------------------------------------------
+// expansion of associations into records (visibility rules of Sec. 3.3-3.4)
+struct Rec {
+  int32_t feat;   // internal feature id
+  int32_t cam;    // camera or -1
+  int32_t other;  // group, or partner feature (caller id), or -1
+  int32_t grp;    // group index stored on the device, or -1
+  double meas[4];
+  int64_t key[3];
+};
+
+struct CSR {
+  std::vector<int64_t> off;
+  std::vector<int32_t> cam, idx;  // per feature: cameras ascending, observation index
+  bool has(int f, int c) const {
+    auto b = cam.begin() + off[f], e = cam.begin() + off[f + 1];
+    return std::binary_search(b, e, c);
+  }
+};
+
+CSR build_csr(const Obs& o, int nfeat, const char* what) {
+  CSR s;
+  const size_t n = o.a.size();
+  s.off.assign(nfeat + 1, 0);
+  for (size_t i = 0; i < n; ++i) s.off[o.b[i] + 1]++;
+  for (int f = 0; f < nfeat; ++f) s.off[f + 1] += s.off[f];
+  std::vector<int64_t> pos(s.off.begin(), s.off.end() - 1);
+  s.cam.resize(n);
+  s.idx.resize(n);
+  for (size_t i = 0; i < n; ++i) {
+    int64_t p = pos[o.b[i]]++;
+    s.cam[p] = o.a[i];
+    s.idx[p] = (int32_t)i;
+  }
+  for (int f = 0; f < nfeat; ++f) {
+    std::vector<std::pair<int32_t, int32_t>> v;
+    for (int64_t p = s.off[f]; p < s.off[f + 1]; ++p) v.push_back({s.cam[p], s.idx[p]});
+    std::sort(v.begin(), v.end());
+    for (size_t k = 0; k < v.size(); ++k) {
+      if (k && v[k].first == v[k - 1].first)
+        throw BaError(BA_E_INVALID, std::string("duplicate ") + what + " observation of feature " + std::to_string(f) +
+                                        " in camera " + std::to_string(v[k].first));
+      s.cam[s.off[f] + k] = v[k].first;
+      s.idx[s.off[f] + k] = v[k].second;
+    }
+  }
+  return s;
+}
+
+void finalize(ba_handle* h) {
+  set_device(h);
+  const Obs& OP = h->obs[BA_OBS_POINT];
+  const Obs& OL = h->obs[BA_OBS_LINE];
+  CSR P = build_csr(OP, h->np, "point");
+  CSR L = build_csr(OL, h->nl, "line");
+
+  // group memberships: at most one plane per feature, one VP per line
+  std::vector<int32_t> pt_plane(h->np, -1), ln_plane(h->nl, -1), ln_vp(h->nl, -1);
+  {
+    const Obs& o = h->obs[BA_ASSOC_PLANE_POINT];
+    for (size_t i = 0; i < o.a.size(); ++i) {
+      if (pt_plane[o.b[i]] >= 0) throw BaError(BA_E_INVALID, "point " + std::to_string(o.b[i]) + " is associated with two planes");
+      pt_plane[o.b[i]] = o.a[i];
+    }
+    const Obs& o2 = h->obs[BA_ASSOC_PLANE_LINE];
+    for (size_t i = 0; i < o2.a.size(); ++i) {
+      if (ln_plane[o2.b[i]] >= 0) throw BaError(BA_E_INVALID, "line " + std::to_string(o2.b[i]) + " is associated with two planes");
+      ln_plane[o2.b[i]] = o2.a[i];
+    }
+    const Obs& o3 = h->obs[BA_ASSOC_VP_LINE];
+    for (size_t i = 0; i < o3.a.size(); ++i) {
+      if (ln_vp[o3.b[i]] >= 0) throw BaError(BA_E_INVALID, "line " + std::to_string(o3.b[i]) + " is associated with two VPs");
+      ln_vp[o3.b[i]] = o3.a[i];
+    }
+  }
+  // junctions, deduplicated check
+  const Obs& OJ = h->obs[BA_ASSOC_JUNCTION];
+  {
+    std::vector<int64_t> jk(OJ.a.size());
+    for (size_t i = 0; i < OJ.a.size(); ++i) jk[i] = (int64_t)OJ.a[i] * h->nl + OJ.b[i];
+    std::sort(jk.begin(), jk.end());
+    if (std::adjacent_find(jk.begin(), jk.end()) != jk.end()) throw BaError(BA_E_INVALID, "duplicate junction");
+  }
+
+  // per-feature record counts for the signature ordering
+  std::vector<int32_t> n6(h->np, 0), n7(h->nl, 0);
+  for (size_t i = 0; i < OJ.a.size(); ++i) {
+    const int j = OJ.a[i], k = OJ.b[i];
+    for (int64_t p = L.off[k]; p < L.off[k + 1]; ++p) if (!P.has(j, L.cam[p])) n6[j]++;
+    for (int64_t p = P.off[j]; p < P.off[j + 1]; ++p) if (!L.has(k, P.cam[p])) n7[k]++;
+  }
+  // internal order: features with the same record signature are adjacent so
+  // that the lanes of a wavefront run the same loops
+  h->pt_perm.resize(h->np);
+  std::iota(h->pt_perm.begin(), h->pt_perm.end(), 0);
+  auto ptkey = [&](int j) {
+    const int n1 = (int)(P.off[j + 1] - P.off[j]);
+    return std::make_tuple(pt_plane[j] >= 0 && n1 > 0, n6[j] > 0, n1, n6[j]);
+  };
+  std::stable_sort(h->pt_perm.begin(), h->pt_perm.end(), [&](int a, int b) { return ptkey(a) > ptkey(b); });
+  h->ln_perm.resize(h->nl);
+  std::iota(h->ln_perm.begin(), h->ln_perm.end(), 0);
+  auto lnkey = [&](int k) {
+    const int n2 = (int)(L.off[k + 1] - L.off[k]);
+    return std::make_tuple(ln_plane[k] >= 0 && n2 > 0, ln_vp[k] >= 0, n7[k] > 0, n2, n7[k]);
+  };
+  std::stable_sort(h->ln_perm.begin(), h->ln_perm.end(), [&](int a, int b) { return lnkey(a) > lnkey(b); });
+  h->pt_inv.assign(h->np, 0);
+  h->ln_inv.assign(h->nl, 0);
+  for (int i = 0; i < h->np; ++i) h->pt_inv[h->pt_perm[i]] = i;
+  for (int i = 0; i < h->nl; ++i) h->ln_inv[h->ln_perm[i]] = i;
+
+  const double cx = h->cx, cy = h->cy;
+  std::vector<Rec> R[NFAM];
+  // R1: point observations;  R3: plane-point association x observing views
+  for (int j = 0; j < h->np; ++j) {
+    for (int64_t p = P.off[j]; p < P.off[j + 1]; ++p) {
+      const int o = P.idx[p];
+      const double* m = &OP.meas[4 * (size_t)o];
+      Rec r{h->pt_inv[j], P.cam[p], -1, -1, {m[0] - cx, m[1] - cy, 0, 0}, {P.cam[p], j, -1}};
+      R[1].push_back(r);
+      if (pt_plane[j] >= 0) {
+        Rec r3{h->pt_inv[j], P.cam[p], pt_plane[j], pt_plane[j], {0, 0, 0, 0}, {P.cam[p], j, pt_plane[j]}};
+        R[3].push_back(r3);
+      }
+    }
+  }
+  // R2: line observations;  R4: plane-line association x observing views;  R5: VP-line
+  for (int k = 0; k < h->nl; ++k) {
+    for (int64_t p = L.off[k]; p < L.off[k + 1]; ++p) {
+      const int o = L.idx[p];
+      const double* m = &OL.meas[4 * (size_t)o];
+      Rec r{h->ln_inv[k], L.cam[p], -1, -1, {m[0] - cx, m[1] - cy, m[2] - cx, m[3] - cy}, {L.cam[p], k, -1}};
+      R[2].push_back(r);
+      if (ln_plane[k] >= 0) {
+        Rec r4 = r;
+        r4.other = r4.grp = ln_plane[k];
+        r4.key[2] = ln_plane[k];
+        R[4].push_back(r4);
+      }
+    }
+    if (ln_vp[k] >= 0) {
+      Rec r5{h->ln_inv[k], -1, ln_vp[k], ln_vp[k], {0, 0, 0, 0}, {-1, k, ln_vp[k]}};
+      R[5].push_back(r5);
+    }
+  }
+  // R6 / R7: cross-feature records over the views where exactly one feature is observed
+  for (size_t i = 0; i < OJ.a.size(); ++i) {
+    const int j = OJ.a[i], k = OJ.b[i];
+    for (int64_t p = L.off[k]; p < L.off[k + 1]; ++p) {
+      const int c = L.cam[p];
+      if (P.has(j, c)) continue;
+      const double* m = &OL.meas[4 * (size_t)L.idx[p]];
+      // observed line through the two endpoints (shifted pixels), normalised
+      const double a[3] = {m[0] - cx, m[1] - cy, 1.0}, b[3] = {m[2] - cx, m[3] - cy, 1.0};
+      double l[3];
+      cross(a, b, l);
+      const double s = std::sqrt(l[0] * l[0] + l[1] * l[1]);
+      if (!(s > 0)) throw BaError(BA_E_INVALID, "degenerate observed line segment");
+      Rec r{h->pt_inv[j], c, k, -1, {l[0] / s, l[1] / s, l[2] / s, 0}, {c, j, k}};
+      R[6].push_back(r);
+    }
+    for (int64_t p = P.off[j]; p < P.off[j + 1]; ++p) {
+      const int c = P.cam[p];
+      if (L.has(k, c)) continue;
+      const double* m = &OP.meas[4 * (size_t)P.idx[p]];
+      Rec r{h->ln_inv[k], c, j, -1, {m[2] - cx, m[3] - cy, 0, 0}, {c, k, j}};
+      R[7].push_back(r);
+    }
+  }
+  // feature-major order: (internal feature, camera, other)
+  for (int fam = 1; fam < NFAM; ++fam)
+    std::sort(R[fam].begin(), R[fam].end(), [](const Rec& a, const Rec& b) {
+      if (a.feat != b.feat) return a.feat < b.feat;
+      if (a.cam != b.cam) return a.cam < b.cam;
+      return a.other < b.other;
+    });
+
+  // ---- device layout
+  Dev& d = h->d;
+  d.CD = h->CD; d.nc = h->nc; d.np = h->np; d.nl = h->nl; d.ng = h->ng; d.nv = h->nv;
+  d.offPl = h->CD * h->nc;
+  d.offVp = d.offPl + 3 * h->ng;
+  d.nA = d.offVp + 2 * h->nv;
+  d.fp64 = h->precision == BA_PREC_FP64 ? 1 : 0;
+  const size_t TS = d.fp64 ? sizeof(double) : sizeof(float);
+  DevAlloc& A = h->alloc;
+  // parameters (internal feature order)
+  std::vector<double> ptI((size_t)h->np * PT_STRIDE), lnI((size_t)h->nl * LN_STRIDE);
+  for (int i = 0; i < h->np; ++i) std::copy_n(&h->pt[(size_t)PT_STRIDE * h->pt_perm[i]], PT_STRIDE, &ptI[(size_t)PT_STRIDE * i]);
+  for (int i = 0; i < h->nl; ++i) std::copy_n(&h->ln[(size_t)LN_STRIDE * h->ln_perm[i]], LN_STRIDE, &lnI[(size_t)LN_STRIDE * i]);
+  d.cam64 = A.get<double>(h->cam.size()); d.cam64n = A.get<double>(h->cam.size());
+  d.pt64 = A.get<double>(ptI.size()); d.pt64n = A.get<double>(ptI.size());
+  d.ln64 = A.get<double>(lnI.size()); d.ln64n = A.get<double>(lnI.size());
+  d.pl64 = A.get<double>(h->pl.size()); d.pl64n = A.get<double>(h->pl.size());
+  d.vp64 = A.get<double>(h->vp.size()); d.vp64n = A.get<double>(h->vp.size());
+  upload(h, d.cam64, h->cam); upload(h, d.pt64, ptI); upload(h, d.ln64, lnI);
+  upload(h, d.pl64, h->pl); upload(h, d.vp64, h->vp);
+  d.camT = A.get<char>(h->cam.size(), TS); d.ptT = A.get<char>(ptI.size(), TS); d.lnT = A.get<char>(lnI.size(), TS);
+  d.plT = A.get<char>(h->pl.size(), TS); d.vpT = A.get<char>(h->vp.size(), TS);
+
+  // families
+  int64_t max_blocks = 0;
+  for (int fam = 1; fam < NFAM; ++fam) {
+    const auto& v = R[fam];
+    const int64_t n = (int64_t)v.size();
+    d.fn[fam] = n;
+    const int nfeat = fam_is_line(fam) ? h->nl : h->np;
+    std::vector<int32_t> cam(n), grp(n), feat(n), off(nfeat + 1, 0);
+    const int mw = meas_width(fam);
+    std::vector<double> meas((size_t)n * mw);
+    h->keys[fam].resize((size_t)n * 3);
+    for (int64_t i = 0; i < n; ++i) {
+      cam[i] = v[i].cam; grp[i] = v[i].grp; feat[i] = v[i].feat;
+      off[v[i].feat + 1]++;
+      for (int k = 0; k < mw; ++k) meas[(size_t)i * mw + k] = v[i].meas[k];
+      for (int k = 0; k < 3; ++k) h->keys[fam][(size_t)i * 3 + k] = v[i].key[k];
+    }
+    for (int f = 0; f < nfeat; ++f) off[f + 1] += off[f];
+    d.fcam[fam] = A.get<int32_t>(n); d.fgrp[fam] = A.get<int32_t>(n); d.ffeat[fam] = A.get<int32_t>(n);
+    d.foff[fam] = A.get<int32_t>(nfeat + 1);
+    d.fmeas[fam] = A.get<double>((size_t)n * std::max(mw, 1));
+    d.frec[fam] = A.get<char>((size_t)n * slot_stride(fam, h->CD), TS);
+    upload(h, d.fcam[fam], cam); upload(h, d.fgrp[fam], grp); upload(h, d.ffeat[fam], feat);
+    upload(h, d.foff[fam], off); upload(h, d.fmeas[fam], meas);
+    const int kind = fam == 1 ? BA_OBS_POINT : fam == 2 ? BA_OBS_LINE : fam == 3 ? BA_ASSOC_PLANE_POINT
+                     : fam == 4 ? BA_ASSOC_PLANE_LINE : fam == 5 ? BA_ASSOC_VP_LINE : BA_ASSOC_JUNCTION;
+    const ba_loss lo = h->obs[kind].loss_set ? h->obs[kind].loss : default_loss(kind);
+    d.lkind[fam] = lo.kind; d.lscale[fam] = lo.scale; d.lweight[fam] = lo.weight;
+    max_blocks += (n + 255) / 256;
+    if (n > INT32_MAX) throw BaError(BA_E_INVALID, "too many records in one family");
+  }
+  // camera-major lists
+  auto cam_major = [&](int fam, bool runs, int32_t*& idx_or_start, int32_t*& cnt, int32_t*& off) {
+    const auto& v = R[fam];
+    std::vector<std::vector<int32_t>> bucket(h->nc), bcnt(h->nc);
+    for (size_t i = 0; i < v.size();) {
+      size_t j = i + 1;
+      if (runs)
+        while (j < v.size() && v[j].feat == v[i].feat && v[j].cam == v[i].cam) ++j;
+      bucket[v[i].cam].push_back((int32_t)i);
+      bcnt[v[i].cam].push_back((int32_t)(j - i));
+      i = j;
+    }
+    std::vector<int32_t> o(h->nc + 1, 0), flat, fc;
+    for (int c = 0; c < h->nc; ++c) {
+      o[c + 1] = o[c] + (int32_t)bucket[c].size();
+      flat.insert(flat.end(), bucket[c].begin(), bucket[c].end());
+      fc.insert(fc.end(), bcnt[c].begin(), bcnt[c].end());
+    }
+    idx_or_start = A.get<int32_t>(flat.size());
+    off = A.get<int32_t>(o.size());
+    upload(h, idx_or_start, flat);
+    upload(h, off, o);
+    if (runs) {
+      cnt = A.get<int32_t>(fc.size());
+      upload(h, cnt, fc);
+    }
+  };
+  int32_t* dummy = nullptr;
+  cam_major(1, false, d.po_idx, dummy, d.po_off);
+  cam_major(2, false, d.lo_idx, dummy, d.lo_off);
+  cam_major(6, true, d.px_start, d.px_cnt, d.px_off);
+  cam_major(7, true, d.lx_start, d.lx_cnt, d.lx_off);
+  // group member lists
+  {
+    std::vector<std::vector<int32_t>> mp(h->ng), ml(h->ng), mv(h->nv);
+    for (size_t i = 0; i < R[3].size(); ++i)
+      if (i == 0 || R[3][i].feat != R[3][i - 1].feat) mp[R[3][i].grp].push_back(R[3][i].feat);
+    for (size_t i = 0; i < R[4].size(); ++i)
+      if (i == 0 || R[4][i].feat != R[4][i - 1].feat) ml[R[4][i].grp].push_back(R[4][i].feat);
+    for (size_t i = 0; i < R[5].size(); ++i) mv[R[5][i].grp].push_back((int32_t)i);
+    auto flatten = [&](std::vector<std::vector<int32_t>>& m, int32_t*& list, int32_t*& off) {
+      std::vector<int32_t> o(m.size() + 1, 0), flat;
+      for (size_t g = 0; g < m.size(); ++g) {
+        o[g + 1] = o[g] + (int32_t)m[g].size();
+        flat.insert(flat.end(), m[g].begin(), m[g].end());
+      }
+      list = A.get<int32_t>(flat.size());
+      off = A.get<int32_t>(o.size());
+      upload(h, list, flat);
+      upload(h, off, o);
+    };
+    flatten(mp, d.plp, d.plp_off);
+    flatten(ml, d.pll, d.pll_off);
+    flatten(mv, d.vpm, d.vpm_off);
+  }
+  // feature blocks
+  d.Vp = A.get<char>((size_t)h->np * 6, TS); d.gp = A.get<char>((size_t)h->np * 3, TS);
+  d.Vl = A.get<char>((size_t)h->nl * 10, TS); d.gl = A.get<char>((size_t)h->nl * 4, TS);
+  d.Vip = A.get<char>((size_t)h->np * 6, TS); d.Vil = A.get<char>((size_t)h->nl * 10, TS);
+  d.sp = A.get<char>((size_t)h->np * 3, TS); d.sl = A.get<char>((size_t)h->nl * 4, TS);
+  d.Vip64 = A.get<double>((size_t)h->np * 6); d.Vil64 = A.get<double>((size_t)h->nl * 10);
+  d.flp = A.get<uint8_t>(h->np); d.fll = A.get<uint8_t>(h->nl);
+  d.Dp = A.get<double>((size_t)h->np * 3); d.Dl = A.get<double>((size_t)h->nl * 4);
+  d.hp = A.get<double>((size_t)h->np * 3); d.hl = A.get<double>((size_t)h->nl * 4);
+  // A side
+  const int CD = h->CD, nA = d.nA;
+  d.Ucam = A.get<double>((size_t)h->nc * CD * CD); d.Upl = A.get<double>((size_t)h->ng * 9); d.Uvp = A.get<double>((size_t)h->nv * 4);
+  d.Scam = A.get<double>((size_t)h->nc * CD * CD); d.Spl = A.get<double>((size_t)h->ng * 9); d.Svp = A.get<double>((size_t)h->nv * 4);
+  d.Mcam = A.get<double>((size_t)h->nc * CD * CD); d.Mpl = A.get<double>((size_t)h->ng * 9); d.Mvp = A.get<double>((size_t)h->nv * 4);
+  d.gA = A.get<double>(nA); d.DA = A.get<double>(nA); d.bA = A.get<double>(nA);
+  d.x = A.get<double>(nA); d.r = A.get<double>(nA); d.z = A.get<double>(nA); d.p = A.get<double>(nA); d.q = A.get<double>(nA);
+  d.xT = A.get<char>(nA, TS);
+  // matvec: one workgroup-private copy of the reduced vector in LDS when it fits
+  int ncu = 0;
+  HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, h->device));
+  const int max_lds = matvec_max_lds_bytes();
+  const size_t need = (size_t)nA * TS;
+  d.mv_lds = need <= (size_t)max_lds ? 1 : 0;
+  const int wg_per_cu = d.mv_lds ? std::max(1, std::min(8, (int)(163840 / std::max<size_t>(need, 1)))) : 8;
+  const int tiles = (h->np + 255) / 256 + (h->nl + 255) / 256;
+  d.n_mv_wg = std::max(1, std::min(ncu * wg_per_cu, std::max(tiles, 1)));
+  d.mv_part = A.get<char>(d.mv_lds ? (size_t)d.n_mv_wg * nA : (size_t)nA, TS);
+  launch_zero(d.mv_part, (d.mv_lds ? (size_t)d.n_mv_wg * nA : (size_t)nA) * TS, h->stream);
+  d.scal = A.get<double>(SC_COUNT);
+  launch_zero(d.scal, SC_COUNT * sizeof(double), h->stream);
+  const int64_t fe_blocks = (h->np + 255) / 256 + (h->nl + 255) / 256;
+  d.red = A.get<double>((size_t)std::max<int64_t>(2 * std::max(max_blocks, fe_blocks), 64));
+  HIPCHK(hipHostMalloc((void**)&h->hscal, SC_COUNT * sizeof(double), hipHostMallocDefault));
+  if (h->gnn) ba_gnn::attach(h->gnn, h->d, h->stream);
+  sync(h);
+  h->finalized = true;
+  h->need_lin = true;
+}
+
+void read_scal(ba_handle* h) {
+  HIPCHK(hipMemcpyAsync(h->hscal, h->d.scal, SC_COUNT * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  sync(h);
+}
+
+void linearize_all(ba_handle* h) {
+  launch_cast_params(h->d, false, h->stream);
+  launch_linearize(h->d, h->stream);
+  launch_feature_accum(h->d, h->stream);
+  launch_camera_pass_a(h->d, h->stream);
+  h->need_lin = false;
+}
+
+void assemble(ba_handle* h, double lambda, double kappa_max) {
+  launch_zero(h->d.scal + SC_NFLAG, sizeof(double), h->stream);
+  launch_feature_invert(h->d, lambda, kappa_max, h->stream);
+  launch_camera_pass_b(h->d, lambda, h->stream);
+  launch_precond_blockjacobi(h->d, h->stream);
+  if (h->precond == BA_PC_LEARNED && h->gnn && ba_gnn::ready(h->gnn)) ba_gnn::apply(h->gnn, h->d, lambda, h->stream);
+  h->last_lambda = lambda;
+}
+
+// returns iterations done
+int pcg(ba_handle* h, double lambda, double tol, int maxit) {
+  launch_pcg_init(h->d, tol, maxit, h->stream);
+  int launched = 0;
+  for (;;) {
+    for (int k = 0; k < PCG_CHECK_EVERY && launched < maxit; ++k, ++launched) launch_pcg_iteration(h->d, lambda, h->stream);
+    read_scal(h);
+    if (h->hscal[SC_DONE] != 0.0 || launched >= maxit) break;
+  }
+  return (int)h->hscal[SC_ITER];
+}
+
+void record(ba_handle* h, int phase) {
+  if (h->events) HIPCHK(hipEventRecord(h->ev[phase], h->stream));
+}
+
+ba_status guard(ba_handle* h, const std::function<void()>& fn) {
+  try {
+    fn();
+    return BA_OK;
+  } catch (const BaError& e) {
+    if (h) h->err = e.what();
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    if (h) h->err = "host allocation failed";
+    return BA_E_OOM;
+  } catch (const std::exception& e) {
+    if (h) h->err = e.what();
+    return BA_E_DEVICE;
+  }
+}
+
+bool finite_all(const double* p, size_t n) {
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(p[i])) return false;
+  return true;
+}
+
+void fill_params(ba_handle* h, const double* cams, const double* pts, const double* lines, const double* planes,
+                 const double* vps) {
+  if (cams) {
+    if (!finite_all(cams, (size_t)h->nc * 10)) throw BaError(BA_E_INVALID, "non-finite camera parameter");
+    h->cam.assign((size_t)h->nc * CAM_STRIDE, 0.0);
+    for (int i = 0; i < h->nc; ++i) {
+      const double* c = cams + 10 * (size_t)i;
+      double* o = &h->cam[(size_t)CAM_STRIDE * i];
+      if (!(c[0] * c[0] + c[1] * c[1] + c[2] * c[2] + c[3] * c[3] > 0)) throw BaError(BA_E_INVALID, "zero quaternion");
+      quat_to_R(c, o);
+      for (int k = 0; k < 3; ++k) o[9 + k] = c[4 + k];
+      o[12] = c[7]; o[13] = c[8]; o[14] = c[9];
+    }
+  }
+  if (pts) {
+    if (!finite_all(pts, (size_t)h->np * 3)) throw BaError(BA_E_INVALID, "non-finite point");
+    h->pt.assign((size_t)h->np * PT_STRIDE, 0.0);
+    for (int i = 0; i < h->np; ++i)
+      for (int k = 0; k < 3; ++k) h->pt[(size_t)PT_STRIDE * i + k] = pts[3 * (size_t)i + k];
+  }
+  if (lines) {
+    if (!finite_all(lines, (size_t)h->nl * 6)) throw BaError(BA_E_INVALID, "non-finite line");
+    h->ln.assign((size_t)h->nl * LN_STRIDE, 0.0);
+    for (int i = 0; i < h->nl; ++i)
+      if (!line_from_points(lines + 6 * (size_t)i, lines + 6 * (size_t)i + 3, &h->ln[(size_t)LN_STRIDE * i]))
+        throw BaError(BA_E_INVALID, "line " + std::to_string(i) + " has coincident points");
+  }
+  if (planes) {
+    if (!finite_all(planes, (size_t)h->ng * 4)) throw BaError(BA_E_INVALID, "non-finite plane");
+    h->pl.assign((size_t)h->ng * PL_STRIDE, 0.0);
+    for (int i = 0; i < h->ng; ++i) {
+      const double* p = planes + 4 * (size_t)i;
+      if (std::fabs(norm3(p) - 1.0) > 1e-6) throw BaError(BA_E_INVALID, "plane normal is not unit");
+      double* o = &h->pl[(size_t)PL_STRIDE * i];
+      for (int k = 0; k < 4; ++k) o[k] = p[k];
+      sphere_basis(o, o + 4, o + 7);
+    }
+  }
+  if (vps) {
+    if (!finite_all(vps, (size_t)h->nv * 3)) throw BaError(BA_E_INVALID, "non-finite VP");
+    h->vp.assign((size_t)h->nv * VP_STRIDE, 0.0);
+    for (int i = 0; i < h->nv; ++i) {
+      const double* v = vps + 3 * (size_t)i;
+      if (std::fabs(norm3(v) - 1.0) > 1e-6) throw BaError(BA_E_INVALID, "VP is not unit");
+      double* o = &h->vp[(size_t)VP_STRIDE * i];
+      for (int k = 0; k < 3; ++k) o[k] = v[k];
+      sphere_basis(o, o + 4, o + 7);
+    }
+  }
+}
+
+// swap current / candidate parameter sets after an accepted step
+void accept_candidate(ba_handle* h) {
+  Dev& d = h->d;
+  std::swap(d.cam64, d.cam64n); std::swap(d.pt64, d.pt64n); std::swap(d.ln64, d.ln64n);
+  std::swap(d.pl64, d.pl64n); std::swap(d.vp64, d.vp64n);
+  if (h->gnn) ba_gnn::attach(h->gnn, h->d, h->stream);
+}
+
+void current_cost(ba_handle* h) {
+  launch_cost(h->d, false, h->stream);
+  read_scal(h);
+  h->E = h->hscal[SC_E];
+  h->Epix = h->hscal[SC_EPIX];
+  h->have_cost = true;
+}
+
+ba_solve_options opts_or_default(const ba_solve_options* o) {
+  ba_solve_options r;
+  ba_default_options(&r);
+  if (o) r = *o;
+  return r;
+}
+
+void do_step(ba_handle* h, const ba_solve_options& o, ba_step_report* rep) {
+  set_device(h);
+  if (!h->finalized) finalize(h);
+  if (h->first_step) {
+    h->lambda = o.lambda0;
+    h->nu = o.nu0;
+    h->first_step = false;
+  }
+  if (!h->have_cost) current_cost(h);
+  if (!std::isfinite(h->E)) throw BaError(BA_E_NUMERIC, "initial cost is not finite");
+  ba_step_report r;
+  std::memset(&r, 0, sizeof(r));
+  r.E_before = h->E;
+  r.Epix_before = h->Epix;
+  r.lambda = h->lambda;
+  record(h, 0);
+  const bool relin = h->need_lin;
+  if (relin) linearize_all(h);
+  record(h, 1);
+  assemble(h, h->lambda, o.kappa_max);
+  record(h, 3);
+  r.pcg_iters = pcg(h, h->lambda, o.pcg_tol, o.pcg_max_iters);
+  record(h, 4);
+  const double rr = h->hscal[SC_RR], bb = h->hscal[SC_BB];
+  r.pcg_rel_residual = bb > 0 ? std::sqrt(rr / bb) : 0.0;
+  r.n_fp64_blocks = (int)h->hscal[SC_NFLAG];
+  launch_backsub(h->d, h->stream);
+  record(h, 5);
+  launch_retract(h->d, h->stream);
+  launch_cost(h->d, true, h->stream);
+  record(h, 6);
+  read_scal(h);
+  const double En = h->hscal[SC_E], Epn = h->hscal[SC_EPIX];
+  const double dL = -h->hscal[SC_GH] - 0.5 * h->hscal[SC_JH2];
+  const double rho = dL > 0 ? (h->E - En) / dL : -INFINITY;
+  r.E_after = En;
+  r.Epix_after = Epn;
+  r.model_decrease = dL;
+  r.gain_ratio = rho;
+  r.relinearized = relin ? 1 : 0;
+  if (std::isfinite(En) && rho > 0) {
+    accept_candidate(h);
+    h->E = En;
+    h->Epix = Epn;
+    const double t = 2.0 * rho - 1.0;
+    h->lambda = std::max(h->lambda * std::max(1.0 / 3.0, 1.0 - t * t * t), 1e-10);
+    h->nu = 2.0;
+    h->need_lin = true;
+    r.accepted = 1;
+  } else {
+    h->lambda *= h->nu;
+    h->nu *= 2.0;
+  }
+  if (h->events) {
+    float ms = 0;
+    const int map[7][2] = {{0, 1}, {1, 1}, {1, 3}, {3, 3}, {3, 4}, {4, 5}, {5, 6}};
+    for (int k = 0; k < 7; ++k) {
+      ms = 0;
+      if (map[k][0] != map[k][1]) HIPCHK(hipEventElapsedTime(&ms, h->ev[map[k][0]], h->ev[map[k][1]]));
+      r.ms[k] = ms;
+    }
+    r.ms[BA_PHASE_FEATURE] = 0;  // accumulation is timed with linearisation
+  }
+  if (rep) *rep = r;
+}
+
+void check_index(const int32_t* v, int64_t n, int hi, const char* what) {
+  for (int64_t i = 0; i < n; ++i)
+    if (v[i] < 0 || v[i] >= hi) throw BaError(BA_E_INVALID, std::string(what) + " index out of range");
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+extern "C" {
+
+void ba_default_options(ba_solve_options* o) {
+  if (!o) return;
+  o->max_iters = 100;
+  o->func_tol = 1e-6;
+  o->grad_tol = 1e-10;
+  o->pcg_tol = 1e-6;
+  o->pcg_max_iters = 1000;
+  o->lambda0 = 1e-4;
+  o->nu0 = 2.0;
+  o->kappa_max = 1e4;
+}
+
+ba_status ba_create(const ba_problem_desc* desc, ba_handle** out) {
+  if (!out) return BA_E_INVALID;
+  *out = nullptr;
+  if (!desc) return BA_E_INVALID;
+  ba_handle* h = new (std::nothrow) ba_handle();
+  if (!h) return BA_E_OOM;
+  ba_status st = guard(h, [&] {
+    if (desc->n_cameras < 0 || desc->n_points < 0 || desc->n_lines < 0 || desc->n_planes < 0 || desc->n_vps < 0)
+      throw BaError(BA_E_INVALID, "negative count");
+    if (desc->camera_dof != 6 && desc->camera_dof != 9) throw BaError(BA_E_INVALID, "camera_dof must be 6 or 9");
+    if (desc->precision != BA_PREC_FP64 && desc->precision != BA_PREC_MIXED) throw BaError(BA_E_INVALID, "bad precision");
+    if (desc->precond != BA_PC_BLOCK_JACOBI && desc->precond != BA_PC_LEARNED) throw BaError(BA_E_INVALID, "bad precond");
+    if (!std::isfinite(desc->cx) || !std::isfinite(desc->cy)) throw BaError(BA_E_INVALID, "non-finite principal point");
+    h->nc = desc->n_cameras; h->np = desc->n_points; h->nl = desc->n_lines; h->ng = desc->n_planes; h->nv = desc->n_vps;
+    h->CD = desc->camera_dof; h->cx = desc->cx; h->cy = desc->cy;
+    h->precision = desc->precision; h->precond = desc->precond; h->device = desc->device;
+    if ((h->nc && !desc->cameras) || (h->np && !desc->points) || (h->nl && !desc->lines) || (h->ng && !desc->planes) ||
+        (h->nv && !desc->vps))
+      throw BaError(BA_E_INVALID, "missing parameter array");
+    fill_params(h, desc->cameras, desc->points, desc->lines, desc->planes, desc->vps);
+    int ndev = 0;
+    HIPCHK(hipGetDeviceCount(&ndev));
+    if (h->device < 0 || h->device >= ndev) throw BaError(BA_E_INVALID, "bad device index");
+    set_device(h);
+    if (desc->hip_stream) {
+      h->stream = (hipStream_t)desc->hip_stream;
+    } else {
+      HIPCHK(hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking));
+      h->own_stream = true;
+    }
+    for (int k = 0; k <= BA_PHASE_COUNT; ++k) HIPCHK(hipEventCreate(&h->ev[k]));
+    h->events = true;
+    for (int k = 0; k < 6; ++k) h->obs[k].loss = default_loss(k);
+  });
+  if (st != BA_OK) {
+    ba_destroy(h);
+    return st;
+  }
+  *out = h;
+  return BA_OK;
+}
+
+ba_status ba_add_observations(ba_handle* h, int32_t kind, int64_t n, const int32_t* a, const int32_t* b,
+                              const double* meas, const ba_loss* loss) {
+  if (!h) return BA_E_INVALID;
+  return guard(h, [&] {
+    if (h->finalized) throw BaError(BA_E_STATE, "observations must be added before the first step");
+    if (kind < 0 || kind > 5) throw BaError(BA_E_INVALID, "bad kind");
+    if (n < 0 || (n > 0 && (!a || !b))) throw BaError(BA_E_INVALID, "bad arrays");
+    const bool has_meas = kind == BA_OBS_POINT || kind == BA_OBS_LINE;
+    if (has_meas && n > 0 && !meas) throw BaError(BA_E_INVALID, "measurements required");
+    int ha = 0, hb = 0;
+    switch (kind) {
+      case BA_OBS_POINT: ha = h->nc; hb = h->np; break;
+      case BA_OBS_LINE: ha = h->nc; hb = h->nl; break;
+      case BA_ASSOC_PLANE_POINT: ha = h->ng; hb = h->np; break;
+      case BA_ASSOC_PLANE_LINE: ha = h->ng; hb = h->nl; break;
+      case BA_ASSOC_VP_LINE: ha = h->nv; hb = h->nl; break;
+      case BA_ASSOC_JUNCTION: ha = h->np; hb = h->nl; break;
+    }
+    check_index(a, n, ha, "first");
+    check_index(b, n, hb, "second");
+    if (has_meas && !finite_all(meas, (size_t)n * 4)) throw BaError(BA_E_INVALID, "non-finite measurement");
+    if (loss) {
+      if (loss->kind < 0 || loss->kind > 2 || !(loss->scale > 0) || !(loss->weight > 0) || !std::isfinite(loss->scale) ||
+          !std::isfinite(loss->weight))
+        throw BaError(BA_E_INVALID, "bad loss");
+      h->obs[kind].loss = *loss;
+      h->obs[kind].loss_set = true;
+    }
+    Obs& o = h->obs[kind];
+    o.a.insert(o.a.end(), a, a + n);
+    o.b.insert(o.b.end(), b, b + n);
+    if (has_meas) o.meas.insert(o.meas.end(), meas, meas + 4 * n);
+  });
+}
+
+ba_status ba_lm_step(ba_handle* h, const ba_solve_options* opt, ba_step_report* rep) {
+  if (!h) return BA_E_INVALID;
+  const ba_solve_options o = opts_or_default(opt);
+  return guard(h, [&] { do_step(h, o, rep); });
+}
+
+ba_status ba_solve(ba_handle* h, const ba_solve_options* opt, ba_summary* sum) {
+  if (!h) return BA_E_INVALID;
+  const ba_solve_options o = opts_or_default(opt);
+  ba_summary s;
+  std::memset(&s, 0, sizeof(s));
+  s.termination = 2;
+  ba_status st = guard(h, [&] {
+    auto t0 = std::chrono::steady_clock::now();
+    set_device(h);
+    if (!h->finalized) finalize(h);
+    if (!h->have_cost) current_cost(h);
+    s.E_initial = h->E;
+    for (int it = 0; it < o.max_iters; ++it) {
+      ba_step_report r;
+      do_step(h, o, &r);
+      s.iters++;
+      s.pcg_iters_total += r.pcg_iters;
+      if (r.accepted) {
+        s.accepted++;
+        const double rel = std::fabs(r.Epix_before - r.Epix_after) / std::max(r.Epix_before, 1e-300);
+        if (rel < o.func_tol) { s.termination = 0; break; }
+      }
+      if (h->lambda > 1e16) { s.termination = 3; break; }
+    }
+    s.E_final = h->E;
+    s.Epix_final = h->Epix;
+    s.total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  });
+  if (sum) *sum = s;
+  if (st != BA_OK) return st;
+  return s.termination == 2 ? BA_E_NOT_CONVERGED : BA_OK;
+}
+
+ba_status ba_get_parameters(const ba_handle* hc, double* cams, double* pts, double* lines, double* planes, double* vps) {
+  ba_handle* h = const_cast<ba_handle*>(hc);
+  if (!h) return BA_E_INVALID;
+  return guard(h, [&] {
+    std::vector<double> cam = h->cam, pt = h->pt, ln = h->ln, pl = h->pl, vp = h->vp;
+    if (h->finalized) {
+      set_device(h);
+      const Dev& d = h->d;
+      std::vector<double> ptI(pt.size()), lnI(ln.size());
+      if (!cam.empty()) HIPCHK(hipMemcpyAsync(cam.data(), d.cam64, cam.size() * 8, hipMemcpyDeviceToHost, h->stream));
+      if (!ptI.empty()) HIPCHK(hipMemcpyAsync(ptI.data(), d.pt64, ptI.size() * 8, hipMemcpyDeviceToHost, h->stream));
+      if (!lnI.empty()) HIPCHK(hipMemcpyAsync(lnI.data(), d.ln64, lnI.size() * 8, hipMemcpyDeviceToHost, h->stream));
+      if (!pl.empty()) HIPCHK(hipMemcpyAsync(pl.data(), d.pl64, pl.size() * 8, hipMemcpyDeviceToHost, h->stream));
+      if (!vp.empty()) HIPCHK(hipMemcpyAsync(vp.data(), d.vp64, vp.size() * 8, hipMemcpyDeviceToHost, h->stream));
+      sync(h);
+      for (int i = 0; i < h->np; ++i) std::copy_n(&ptI[(size_t)PT_STRIDE * i], PT_STRIDE, &pt[(size_t)PT_STRIDE * h->pt_perm[i]]);
+      for (int i = 0; i < h->nl; ++i) std::copy_n(&lnI[(size_t)LN_STRIDE * i], LN_STRIDE, &ln[(size_t)LN_STRIDE * h->ln_perm[i]]);
+    }
+    if (cams)
+      for (int i = 0; i < h->nc; ++i) {
+        const double* c = &cam[(size_t)CAM_STRIDE * i];
+        double* o = cams + 10 * (size_t)i;
+        R_to_quat(c, o);
+        for (int k = 0; k < 3; ++k) o[4 + k] = c[9 + k];
+        o[7] = c[12]; o[8] = c[13]; o[9] = c[14];
+      }
+    if (pts)
+      for (int i = 0; i < h->np; ++i)
+        for (int k = 0; k < 3; ++k) pts[3 * (size_t)i + k] = pt[(size_t)PT_STRIDE * i + k];
+    if (lines)
+      for (int i = 0; i < h->nl; ++i) {
+        const double* L = &ln[(size_t)LN_STRIDE * i];
+        // d = w1 u1 has norm w1; output unit d and m / |d| = (w2 / w1) u2
+        for (int k = 0; k < 3; ++k) {
+          lines[6 * (size_t)i + k] = L[k];
+          lines[6 * (size_t)i + 3 + k] = L[10] / L[9] * L[3 + k];
+        }
+      }
+    if (planes)
+      for (int i = 0; i < h->ng; ++i)
+        for (int k = 0; k < 4; ++k) planes[4 * (size_t)i + k] = pl[(size_t)PL_STRIDE * i + k];
+    if (vps)
+      for (int i = 0; i < h->nv; ++i)
+        for (int k = 0; k < 3; ++k) vps[3 * (size_t)i + k] = vp[(size_t)VP_STRIDE * i + k];
+  });
+}
+
+ba_status ba_set_parameters(ba_handle* h, const double* cams, const double* pts, const double* lines,
+                            const double* planes, const double* vps) {
+  if (!h) return BA_E_INVALID;
+  return guard(h, [&] {
+    fill_params(h, cams, pts, lines, planes, vps);
+    if (h->finalized) {
+      set_device(h);
+      Dev& d = h->d;
+      std::vector<double> ptI((size_t)h->np * PT_STRIDE), lnI((size_t)h->nl * LN_STRIDE);
+      for (int i = 0; i < h->np; ++i) std::copy_n(&h->pt[(size_t)PT_STRIDE * h->pt_perm[i]], PT_STRIDE, &ptI[(size_t)PT_STRIDE * i]);
+      for (int i = 0; i < h->nl; ++i) std::copy_n(&h->ln[(size_t)LN_STRIDE * h->ln_perm[i]], LN_STRIDE, &lnI[(size_t)LN_STRIDE * i]);
+      if (cams) upload(h, d.cam64, h->cam);
+      if (pts) upload(h, d.pt64, ptI);
+      if (lines) upload(h, d.ln64, lnI);
+      if (planes) upload(h, d.pl64, h->pl);
+      if (vps) upload(h, d.vp64, h->vp);
+      sync(h);
+    }
+    h->need_lin = true;
+    h->have_cost = false;
+  });
+}
+
+ba_status ba_get_lm_state(const ba_handle* h, double* lambda, double* nu) {
+  if (!h) return BA_E_INVALID;
+  if (lambda) *lambda = h->lambda;
+  if (nu) *nu = h->nu;
+  return BA_OK;
+}
+
+ba_status ba_set_lm_state(ba_handle* h, double lambda, double nu) {
+  if (!h) return BA_E_INVALID;
+  if (!(lambda > 0) || !(nu > 1) || !std::isfinite(lambda) || !std::isfinite(nu)) {
+    h->err = "lambda must be > 0 and nu > 1";
+    return BA_E_INVALID;
+  }
+  h->lambda = lambda;
+  h->nu = nu;
+  h->first_step = false;
+  return BA_OK;
+}
+
+ba_status ba_linearize(ba_handle* h, double lambda) {
+  if (!h) return BA_E_INVALID;
+  return guard(h, [&] {
+    if (!(lambda >= 0) || !std::isfinite(lambda)) throw BaError(BA_E_INVALID, "bad lambda");
+    set_device(h);
+    if (!h->finalized) finalize(h);
+    linearize_all(h);
+    ba_solve_options o;
+    ba_default_options(&o);
+    assemble(h, lambda, o.kappa_max);
+    sync(h);
+  });
+}
+
+ba_status ba_record_count(const ba_handle* h, int32_t family, int64_t* count) {
+  if (!h || family < 1 || family > 7 || !count) return BA_E_INVALID;
+  if (!h->finalized) { const_cast<ba_handle*>(h)->err = "records exist after the first step"; return BA_E_STATE; }
+  *count = h->d.fn[family];
+  return BA_OK;
+}
+
+ba_status ba_export_records(const ba_handle* hc, int32_t fam, int64_t* keys, double* r, double* J) {
+  ba_handle* h = const_cast<ba_handle*>(hc);
+  if (!h || fam < 1 || fam > 7) return BA_E_INVALID;
+  return guard(h, [&] {
+    if (!h->finalized) throw BaError(BA_E_STATE, "no records yet");
+    const int64_t n = h->d.fn[fam];
+    if (keys) std::copy(h->keys[fam].begin(), h->keys[fam].end(), keys);
+    if (!r && !J) return;
+    const int stride = slot_stride(fam, h->CD), rows = fam_rows(fam);
+    const int nc = slot_nc(fam, h->CD), ng = slot_ng(fam), nf = slot_nf(fam);
+    const int ncol = (fam == 5 ? 0 : h->CD) + nf + ng;
+    std::vector<double> buf((size_t)n * stride);
+    set_device(h);
+    if (h->d.fp64) {
+      if (n) HIPCHK(hipMemcpyAsync(buf.data(), h->d.frec[fam], buf.size() * 8, hipMemcpyDeviceToHost, h->stream));
+      sync(h);
+    } else {
+      std::vector<float> fb((size_t)n * stride);
+      if (n) HIPCHK(hipMemcpyAsync(fb.data(), h->d.frec[fam], fb.size() * 4, hipMemcpyDeviceToHost, h->stream));
+      sync(h);
+      std::copy(fb.begin(), fb.end(), buf.begin());
+    }
+    const int OC = rows, OG = OC + rows * nc, OF = OG + rows * ng;
+    for (int64_t i = 0; i < n; ++i) {
+      const double* s = &buf[(size_t)i * stride];
+      for (int row = 0; row < rows; ++row) {
+        if (r) r[(size_t)i * rows + row] = s[row];
+        if (J) {
+          double* o = J + ((size_t)i * rows + row) * ncol;
+          int col = 0;
+          if (fam != 5) {
+            for (int k = 0; k < h->CD; ++k) o[col++] = k < nc ? s[OC + row * nc + k] : 0.0;
+          }
+          for (int k = 0; k < nf; ++k) o[col++] = s[OF + row * nf + k];
+          for (int k = 0; k < ng; ++k) o[col++] = s[OG + row * ng + k];
+        }
+      }
+    }
+  });
+}
+
+ba_status ba_export_feature_blocks(const ba_handle* hc, double* Vp, double* gp, double* Vl, double* gl) {
+  ba_handle* h = const_cast<ba_handle*>(hc);
+  if (!h) return BA_E_INVALID;
+  return guard(h, [&] {
+    if (!h->finalized) throw BaError(BA_E_STATE, "no linearisation yet");
+    set_device(h);
+    auto fetch = [&](const void* src, size_t n) {
+      std::vector<double> out(n);
+      if (!n) return out;
+      if (h->d.fp64) HIPCHK(hipMemcpyAsync(out.data(), src, n * 8, hipMemcpyDeviceToHost, h->stream));
+      else {
+        std::vector<float> f(n);
+        HIPCHK(hipMemcpyAsync(f.data(), src, n * 4, hipMemcpyDeviceToHost, h->stream));
+        sync(h);
+        std::copy(f.begin(), f.end(), out.begin());
+      }
+      sync(h);
+      return out;
+    };
+    auto unpack = [](const double* s, int N, double* o) {
+      for (int i = 0; i < N; ++i)
+        for (int j = 0; j < N; ++j) {
+          const int a = std::min(i, j), b = std::max(i, j);
+          o[i * N + j] = s[a * N - a * (a - 1) / 2 + (b - a)];
+        }
+    };
+    if (Vp || gp) {
+      auto V = fetch(h->d.Vp, (size_t)h->np * 6), g = fetch(h->d.gp, (size_t)h->np * 3);
+      for (int i = 0; i < h->np; ++i) {
+        const int o = h->pt_perm[i];
+        if (Vp) unpack(&V[6 * (size_t)i], 3, Vp + 9 * (size_t)o);
+        if (gp) for (int k = 0; k < 3; ++k) gp[3 * (size_t)o + k] = g[3 * (size_t)i + k];
+      }
+    }
+    if (Vl || gl) {
+      auto V = fetch(h->d.Vl, (size_t)h->nl * 10), g = fetch(h->d.gl, (size_t)h->nl * 4);
+      for (int i = 0; i < h->nl; ++i) {
+        const int o = h->ln_perm[i];
+        if (Vl) unpack(&V[10 * (size_t)i], 4, Vl + 16 * (size_t)o);
+        if (gl) for (int k = 0; k < 4; ++k) gl[4 * (size_t)o + k] = g[4 * (size_t)i + k];
+      }
+    }
+  });
+}
+
+ba_status ba_export_reduced(const ba_handle* hc, double* b, double* Sc, double* Sp, double* Sv) {
+  ba_handle* h = const_cast<ba_handle*>(hc);
+  if (!h) return BA_E_INVALID;
+  return guard(h, [&] {
+    if (!h->finalized) throw BaError(BA_E_STATE, "no linearisation yet");
+    set_device(h);
+    const Dev& d = h->d;
+    if (b && d.nA) HIPCHK(hipMemcpyAsync(b, d.bA, d.nA * 8, hipMemcpyDeviceToHost, h->stream));
+    if (Sc && d.nc) HIPCHK(hipMemcpyAsync(Sc, d.Scam, (size_t)d.nc * d.CD * d.CD * 8, hipMemcpyDeviceToHost, h->stream));
+    if (Sp && d.ng) HIPCHK(hipMemcpyAsync(Sp, d.Spl, (size_t)d.ng * 9 * 8, hipMemcpyDeviceToHost, h->stream));
+    if (Sv && d.nv) HIPCHK(hipMemcpyAsync(Sv, d.Svp, (size_t)d.nv * 4 * 8, hipMemcpyDeviceToHost, h->stream));
+    sync(h);
+  });
+}
+
+ba_status ba_schur_matvec(ba_handle* h, const double* x, double* y) {
+  if (!h || !x || !y) return BA_E_INVALID;
+  return guard(h, [&] {
+    if (!h->finalized) throw BaError(BA_E_STATE, "no linearisation yet");
+    set_device(h);
+    const Dev& d = h->d;
+    HIPCHK(hipMemcpyAsync(d.z, x, d.nA * 8, hipMemcpyHostToDevice, h->stream));
+    launch_schur_matvec(d, d.z, d.q, h->last_lambda, h->stream);
+    HIPCHK(hipMemcpyAsync(y, d.q, d.nA * 8, hipMemcpyDeviceToHost, h->stream));
+    sync(h);
+  });
+}
+
+ba_status ba_pcg_solve(ba_handle* h, double tol, int32_t max_iters, double* x, int32_t* iters, double* rel_res) {
+  if (!h) return BA_E_INVALID;
+  return guard(h, [&] {
+    if (!h->finalized) throw BaError(BA_E_STATE, "no linearisation yet");
+    set_device(h);
+    const int it = pcg(h, h->last_lambda, tol, max_iters);
+    if (x) HIPCHK(hipMemcpyAsync(x, h->d.x, h->d.nA * 8, hipMemcpyDeviceToHost, h->stream));
+    sync(h);
+    if (iters) *iters = it;
+    if (rel_res) *rel_res = h->hscal[SC_BB] > 0 ? std::sqrt(h->hscal[SC_RR] / h->hscal[SC_BB]) : 0.0;
+  });
+}
+
+ba_status ba_reduced_dim(const ba_handle* h, int64_t* nA, int32_t* cd) {
+  if (!h) return BA_E_INVALID;
+  if (nA) *nA = (int64_t)h->CD * h->nc + 3 * h->ng + 2 * h->nv;
+  if (cd) *cd = h->CD;
+  return BA_OK;
+}
+
+ba_status ba_set_gnn_weights(ba_handle* h, const void* blob, size_t bytes) {
+  if (!h || !blob) return BA_E_INVALID;
+  return guard(h, [&] {
+    set_device(h);
+    if (!h->gnn) h->gnn = ba_gnn::create();
+    std::string e;
+    if (!ba_gnn::load(h->gnn, blob, bytes, h->stream, e)) throw BaError(BA_E_INVALID, e);
+    if (h->finalized) ba_gnn::attach(h->gnn, h->d, h->stream);
+  });
+}
+
+const char* ba_last_error(const ba_handle* h) { return h ? h->err.c_str() : "null handle"; }
+
+void ba_destroy(ba_handle* h) {
+  if (!h) return;
+  (void)hipSetDevice(h->device);
+  if (h->stream) (void)hipStreamSynchronize(h->stream);
+  if (h->gnn) ba_gnn::destroy(h->gnn);
+  h->alloc.free_all();
+  if (h->hscal) (void)hipHostFree(h->hscal);
+  if (h->events)
+    for (int k = 0; k <= BA_PHASE_COUNT; ++k) (void)hipEventDestroy(h->ev[k]);
+  if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
+  delete h;
+}
+
+}  // extern "C"

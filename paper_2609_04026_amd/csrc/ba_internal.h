@@ -1,0 +1,115 @@
+// Device-side layout of one holistic BA problem and the kernel launchers.
+//
+// Records of each residual family are stored feature-major (sorted by the
+// internal feature id, then camera), one array-of-structures slot per
+// record holding the IRLS-weighted residual and Jacobian blocks:
+//   [ r (ROWS) | J_cam (ROWS x NC) | J_group (ROWS x NG) | J_feature (ROWS x NF) | pad ]
+// Camera-side reductions walk camera-major index lists into those arrays;
+// feature-side reductions walk the feature CSR offsets.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ba_math.h"
+
+namespace ba {
+
+constexpr int NFAM = 8;  // families 1..7 (index 0 unused)
+
+// compile-time shape of a family's record slot
+template <int FAM, int CD> struct Fam;
+template <int CD> struct Fam<1, CD> { static constexpr int ROWS = 2, NC = CamCols<CD>::PT, NG = 0, NF = 3, MEAS = 2, GT = 0, FT = 0; };
+template <int CD> struct Fam<2, CD> { static constexpr int ROWS = 4, NC = CamCols<CD>::LN, NG = 0, NF = 4, MEAS = 4, GT = 0, FT = 1; };
+template <int CD> struct Fam<3, CD> { static constexpr int ROWS = 2, NC = CamCols<CD>::PT, NG = 3, NF = 3, MEAS = 0, GT = 1, FT = 0; };
+template <int CD> struct Fam<4, CD> { static constexpr int ROWS = 4, NC = CamCols<CD>::LN, NG = 3, NF = 4, MEAS = 4, GT = 1, FT = 1; };
+template <int CD> struct Fam<5, CD> { static constexpr int ROWS = 3, NC = 0, NG = 2, NF = 4, MEAS = 0, GT = 2, FT = 1; };
+template <int CD> struct Fam<6, CD> { static constexpr int ROWS = 1, NC = CamCols<CD>::PT, NG = 0, NF = 3, MEAS = 3, GT = 0, FT = 0; };
+template <int CD> struct Fam<7, CD> { static constexpr int ROWS = 1, NC = CamCols<CD>::LN, NG = 0, NF = 4, MEAS = 2, GT = 0, FT = 1; };
+
+template <int FAM, int CD> struct Slot {
+  using F = Fam<FAM, CD>;
+  static constexpr int ROWS = F::ROWS, NC = F::NC, NG = F::NG, NF = F::NF;
+  static constexpr int OR = 0, OC = ROWS, OG = OC + ROWS * NC, OF = OG + ROWS * NG;
+  static constexpr int USED = OF + ROWS * NF;
+  static constexpr int STRIDE = (USED + 3) / 4 * 4;
+};
+
+inline int meas_width(int fam) { return fam == 1 ? 2 : fam == 2 ? 4 : fam == 3 ? 0 : fam == 4 ? 4 : fam == 5 ? 0 : fam == 6 ? 3 : 2; }
+inline int fam_rows(int fam) { return fam == 1 ? 2 : fam == 2 ? 4 : fam == 3 ? 2 : fam == 4 ? 4 : fam == 5 ? 3 : 1; }
+inline bool fam_is_line(int fam) { return fam == 2 || fam == 4 || fam == 5 || fam == 7; }
+int slot_stride(int fam, int cd);
+int slot_nc(int fam, int cd);
+int slot_ng(int fam);
+int slot_nf(int fam);
+
+// All device pointers of a problem.  Passed by value to kernels.
+struct Dev {
+  int CD = 9;
+  int nc = 0, np = 0, nl = 0, ng = 0, nv = 0;
+  int nA = 0, offPl = 0, offVp = 0;
+  int fp64 = 0;  // 1: T = double, 0: T = float
+  // parameters: FP64 master (current and candidate) and work copy in T
+  double *cam64 = nullptr, *pt64 = nullptr, *ln64 = nullptr, *pl64 = nullptr, *vp64 = nullptr;
+  double *cam64n = nullptr, *pt64n = nullptr, *ln64n = nullptr, *pl64n = nullptr, *vp64n = nullptr;
+  void *camT = nullptr, *ptT = nullptr, *lnT = nullptr, *plT = nullptr, *vpT = nullptr;
+  // residual families
+  int64_t fn[NFAM] = {0};
+  int32_t *fcam[NFAM] = {nullptr}, *fgrp[NFAM] = {nullptr}, *ffeat[NFAM] = {nullptr}, *foff[NFAM] = {nullptr};
+  double *fmeas[NFAM] = {nullptr};
+  void *frec[NFAM] = {nullptr};
+  int lkind[NFAM] = {0};
+  double lscale[NFAM] = {0}, lweight[NFAM] = {0};
+  // camera-major lists
+  int32_t *po_idx = nullptr, *po_off = nullptr, *lo_idx = nullptr, *lo_off = nullptr;
+  int32_t *px_start = nullptr, *px_cnt = nullptr, *px_off = nullptr;
+  int32_t *lx_start = nullptr, *lx_cnt = nullptr, *lx_off = nullptr;
+  // group member lists
+  int32_t *plp_off = nullptr, *plp = nullptr, *pll_off = nullptr, *pll = nullptr;
+  int32_t *vpm_off = nullptr, *vpm = nullptr;
+  // feature blocks (T unless noted)
+  void *Vp = nullptr, *gp = nullptr, *Vl = nullptr, *gl = nullptr;
+  void *Vip = nullptr, *Vil = nullptr, *sp = nullptr, *sl = nullptr;
+  double *Vip64 = nullptr, *Vil64 = nullptr;
+  uint8_t *flp = nullptr, *fll = nullptr;
+  double *Dp = nullptr, *Dl = nullptr;
+  double *hp = nullptr, *hl = nullptr;
+  // A side (double)
+  double *Ucam = nullptr, *Upl = nullptr, *Uvp = nullptr;  // full blocks
+  double *gA = nullptr, *DA = nullptr, *bA = nullptr;
+  double *Scam = nullptr, *Spl = nullptr, *Svp = nullptr;  // damped diagonal blocks of S
+  double *Mcam = nullptr, *Mpl = nullptr, *Mvp = nullptr;  // preconditioner blocks
+  // PCG (double vectors of length nA) and matvec partials (T)
+  double *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
+  void *xT = nullptr;       // matvec input in T
+  void *mv_part = nullptr;  // n_mv_wg x nA partial sums (LDS mode) or nA accumulator (global mode)
+  double *scal = nullptr;   // device scalars, see PcgScal
+  double *red = nullptr;    // reduction partials
+  int n_mv_wg = 0;          // matvec workgroups (partials rows)
+  int mv_lds = 0;           // 1: accumulate in LDS
+  int mv_tile = 256;
+};
+
+// indices into Dev::scal
+enum PcgScal {
+  SC_RZ = 0, SC_BB, SC_RR, SC_PQ, SC_ALPHA, SC_BETA, SC_DONE, SC_ITER, SC_TOL2, SC_LAMBDA,
+  SC_GH, SC_JH2, SC_E, SC_EPIX, SC_NFLAG, SC_MAXIT, SC_BREAK, SC_COUNT = 32
+};
+
+// ---- launchers (ba_kernels.hip) --------------------------------------------
+void launch_cast_params(const Dev& d, bool candidate, hipStream_t s);
+void launch_linearize(const Dev& d, hipStream_t s);
+void launch_cost(const Dev& d, bool candidate, hipStream_t s);           // -> scal[SC_E], scal[SC_EPIX]
+void launch_feature_accum(const Dev& d, hipStream_t s);                  // V_f, g_f, D_f
+void launch_camera_pass_a(const Dev& d, hipStream_t s);                  // U_a, g_a, D_a
+void launch_feature_invert(const Dev& d, double lambda, double kappa_max, hipStream_t s);  // V^-1, s_f, flags
+void launch_camera_pass_b(const Dev& d, double lambda, hipStream_t s);   // S diag blocks, b
+void launch_precond_blockjacobi(const Dev& d, hipStream_t s);           // M = blockdiag(S)^-1
+void launch_pcg_init(const Dev& d, double tol, int max_iters, hipStream_t s);
+void launch_pcg_iteration(const Dev& d, double lambda, hipStream_t s);
+void launch_schur_matvec(const Dev& d, const double* xin, double* yout, double lambda, hipStream_t s);
+void launch_backsub(const Dev& d, hipStream_t s);                        // h_f, model decrease terms
+void launch_retract(const Dev& d, hipStream_t s);                        // candidate = current [+] h
+void launch_zero(void* p, size_t bytes, hipStream_t s);
+int matvec_max_lds_bytes();
+
+}  // namespace ba

@@ -1,0 +1,1530 @@
+// HIP kernels of one LM iteration of holistic bundle adjustment on gfx950.
+//
+// Pass structure (all on one stream):
+//   cast      FP64 master parameters -> work copy in T
+//   linearize one lane per record: IRLS-weighted residual (from FP64
+//             parameters) and analytic Jacobian (in T) -> AoS record slots
+//   feature   one lane per feature: V_f = sum J_f^T J_f, g_f; damping; FP32
+//             Cholesky with a condition test, FP64 redo of flagged blocks
+//   camera    one workgroup per camera (group): U_aa, g_a, and per lambda the
+//             damped diagonal blocks of S and b with pair-summed W_af
+//   pcg       implicit-Schur product: one lane per feature, J_a x, then
+//             V_f^-1 J_f^T, then J_a^T accumulated into a workgroup-private
+//             copy of the reduced vector in LDS; FP64 vector updates and dots
+//   backsub   one lane per feature: h_f and the model decrease terms
+//   cost      one lane per record: FP64 residuals and robust cost
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+
+#include "ba_internal.h"
+
+namespace ba {
+
+// ---------------------------------------------------------------------------
+// shape helpers visible to the host
+int slot_stride(int fam, int cd) {
+#define SS(F) (cd == 9 ? Slot<F, 9>::STRIDE : Slot<F, 6>::STRIDE)
+  switch (fam) {
+    case 1: return SS(1); case 2: return SS(2); case 3: return SS(3); case 4: return SS(4);
+    case 5: return SS(5); case 6: return SS(6); case 7: return SS(7);
+  }
+#undef SS
+  return 0;
+}
+int slot_nc(int fam, int cd) {
+  switch (fam) {
+    case 1: case 3: case 6: return cd;
+    case 2: case 4: case 7: return cd == 9 ? 7 : 6;
+  }
+  return 0;
+}
+int slot_ng(int fam) { return fam == 3 || fam == 4 ? 3 : fam == 5 ? 2 : 0; }
+int slot_nf(int fam) { return fam_is_line(fam) ? 4 : 3; }
+
+#define BA_DISPATCH_T_CD(d, ...)                                      \
+  do {                                                                \
+    if ((d).fp64) {                                                   \
+      using T = double;                                               \
+      if ((d).CD == 9) { constexpr int CD = 9; __VA_ARGS__; }         \
+      else { constexpr int CD = 6; __VA_ARGS__; }                     \
+    } else {                                                          \
+      using T = float;                                                \
+      if ((d).CD == 9) { constexpr int CD = 9; __VA_ARGS__; }         \
+      else { constexpr int CD = 6; __VA_ARGS__; }                     \
+    }                                                                 \
+  } while (0)
+
+static inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+// ---------------------------------------------------------------------------
+// small device helpers
+template <typename T> __device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// Sum K values over a workgroup.  lds must hold (nwaves + 1) * K elements.
+// Results are returned in lds[nwaves * K + k] (valid after the call for all threads).
+template <typename T, int K> __device__ __forceinline__ T* block_sum_arr(T (&v)[K], T* lds) {
+  const int nw = (blockDim.x + 63) >> 6, w = threadIdx.x >> 6, l = threadIdx.x & 63;
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] = wave_sum(v[k]);
+  __syncthreads();
+  if (l == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) lds[w * K + k] = v[k];
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < K; k += blockDim.x) {
+    T s = 0;
+    for (int i = 0; i < nw; ++i) s += lds[i * K + k];
+    lds[nw * K + k] = s;
+  }
+  __syncthreads();
+  return lds + nw * K;
+}
+
+template <typename T, int N> __device__ __forceinline__ void load_vec(const T* __restrict__ p, T (&v)[N]) {
+  static_assert(N % 4 == 0, "slot stride must be a multiple of 4");
+  if constexpr (sizeof(T) == 4) {
+    const float4* q = reinterpret_cast<const float4*>(p);
+#pragma unroll
+    for (int i = 0; i < N / 4; ++i) {
+      float4 a = q[i];
+      v[4 * i] = a.x; v[4 * i + 1] = a.y; v[4 * i + 2] = a.z; v[4 * i + 3] = a.w;
+    }
+  } else {
+    const double2* q = reinterpret_cast<const double2*>(p);
+#pragma unroll
+    for (int i = 0; i < N / 2; ++i) {
+      double2 a = q[i];
+      v[2 * i] = a.x; v[2 * i + 1] = a.y;
+    }
+  }
+}
+
+template <typename T, int N> __device__ __forceinline__ void store_vec(T* __restrict__ p, const T (&v)[N]) {
+  if constexpr (sizeof(T) == 4) {
+    float4* q = reinterpret_cast<float4*>(p);
+#pragma unroll
+    for (int i = 0; i < N / 4; ++i) q[i] = make_float4(v[4 * i], v[4 * i + 1], v[4 * i + 2], v[4 * i + 3]);
+  } else {
+    double2* q = reinterpret_cast<double2*>(p);
+#pragma unroll
+    for (int i = 0; i < N / 2; ++i) q[i] = make_double2(v[2 * i], v[2 * i + 1]);
+  }
+}
+
+// packed symmetric index (i <= j) of an N x N matrix
+template <int N> __host__ __device__ constexpr int sym(int i, int j) {
+  return i <= j ? i * N - i * (i - 1) / 2 + (j - i) : j * N - j * (j - 1) / 2 + (i - j);
+}
+
+// Cholesky of a full N x N SPD matrix (lower factor in place).  Returns false
+// on a non-positive or non-finite pivot.
+template <typename S, int N> __device__ __forceinline__ bool chol(S (&A)[N][N]) {
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    S s = A[j][j];
+#pragma unroll
+    for (int k = 0; k < j; ++k) s -= A[j][k] * A[j][k];
+    if (!(s > S(0)) || !isfinite(s)) return false;
+    S ljj = sqrt(s);
+    A[j][j] = ljj;
+    S inv = S(1) / ljj;
+#pragma unroll
+    for (int i = j + 1; i < N; ++i) {
+      S t = A[i][j];
+#pragma unroll
+      for (int k = 0; k < j; ++k) t -= A[i][k] * A[j][k];
+      A[i][j] = t * inv;
+    }
+  }
+  return true;
+}
+
+// inverse of A = L L^T from its lower Cholesky factor (full output)
+template <typename S, int N> __device__ __forceinline__ void chol_inverse(const S (&L)[N][N], S (&Ai)[N][N]) {
+  S Li[N][N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+#pragma unroll
+    for (int j = 0; j < N; ++j) Li[i][j] = 0;
+  }
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    Li[j][j] = S(1) / L[j][j];
+#pragma unroll
+    for (int i = j + 1; i < N; ++i) {
+      S t = 0;
+#pragma unroll
+      for (int k = j; k < i; ++k) t -= L[i][k] * Li[k][j];
+      Li[i][j] = t / L[i][i];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      S t = 0;
+#pragma unroll
+      for (int k = (i > j ? i : j); k < N; ++k) t += Li[k][i] * Li[k][j];
+      Ai[i][j] = t;
+    }
+  }
+}
+
+__device__ __forceinline__ int a_grp(const Dev& d, int gt, int g) { return gt == 1 ? d.offPl + 3 * g : d.offVp + 2 * g; }
+
+// ---------------------------------------------------------------------------
+// parameter cast
+template <typename T> __global__ void k_cast(Dev d, int candidate) {
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, nthr = (int64_t)gridDim.x * blockDim.x;
+  auto cp = [&](const double* s, void* dv, int64_t n) {
+    T* dst = (T*)dv;
+    for (int64_t i = tid; i < n; i += nthr) dst[i] = (T)s[i];
+  };
+  cp(candidate ? d.cam64n : d.cam64, d.camT, (int64_t)d.nc * CAM_STRIDE);
+  cp(candidate ? d.pt64n : d.pt64, d.ptT, (int64_t)d.np * PT_STRIDE);
+  cp(candidate ? d.ln64n : d.ln64, d.lnT, (int64_t)d.nl * LN_STRIDE);
+  cp(candidate ? d.pl64n : d.pl64, d.plT, (int64_t)d.ng * PL_STRIDE);
+  cp(candidate ? d.vp64n : d.vp64, d.vpT, (int64_t)d.nv * VP_STRIDE);
+}
+
+void launch_cast_params(const Dev& d, bool candidate, hipStream_t s) {
+  if (d.fp64) k_cast<double><<<256, 256, 0, s>>>(d, candidate ? 1 : 0);
+  else k_cast<float><<<256, 256, 0, s>>>(d, candidate ? 1 : 0);
+}
+
+// ---------------------------------------------------------------------------
+// FP64 residual of one record (shared by linearisation and cost)
+template <int FAM> __device__ __forceinline__ void residual64(const Dev& d, int64_t i, const double* cam, const double* pt,
+                                                              const double* ln, const double* pl, const double* vp,
+                                                              double* r) {
+  using F = Fam<FAM, 9>;
+  const int f = d.ffeat[FAM][i];
+  double m[4] = {0, 0, 0, 0};
+#pragma unroll
+  for (int k = 0; k < F::MEAS; ++k) m[k] = d.fmeas[FAM][i * F::MEAS + k];
+  if constexpr (FAM == 5) {
+    const int g = d.fgrp[FAM][i];
+    res_R5<double>(load_line<double>(ln + (int64_t)LN_STRIDE * f), load_vp<double>(vp + (int64_t)VP_STRIDE * g), r);
+  } else {
+    const int c = d.fcam[FAM][i];
+    Cam<double> C = load_cam<double>(cam + (int64_t)CAM_STRIDE * c);
+    if constexpr (FAM == 1 || FAM == 3 || FAM == 6) {
+      const double* X = pt + (int64_t)PT_STRIDE * f;
+      if constexpr (FAM == 1) res_R1<double>(C, X, m, r);
+      if constexpr (FAM == 3) res_R3<double>(C, X, load_plane<double>(pl + (int64_t)PL_STRIDE * d.fgrp[FAM][i]), r);
+      if constexpr (FAM == 6) res_R6<double>(C, X, m, r);
+    } else {
+      Line<double> L = load_line<double>(ln + (int64_t)LN_STRIDE * f);
+      if constexpr (FAM == 2) res_R2<double>(C, L, m, r);
+      if constexpr (FAM == 4) res_R4<double>(C, L, load_plane<double>(pl + (int64_t)PL_STRIDE * d.fgrp[FAM][i]), m, r);
+      if constexpr (FAM == 7) res_R7<double>(C, L, m, r);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// linearisation: one lane per record
+template <int FAM, typename T, int CD> __global__ __launch_bounds__(256) void k_lin(Dev d) {
+  using F = Fam<FAM, CD>;
+  using SL = Slot<FAM, CD>;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= d.fn[FAM]) return;
+  const int f = d.ffeat[FAM][i];
+  T mT[4] = {0, 0, 0, 0};
+#pragma unroll
+  for (int k = 0; k < F::MEAS; ++k) mT[k] = (T)d.fmeas[FAM][i * F::MEAS + k];
+  T v[SL::STRIDE];
+#pragma unroll
+  for (int k = 0; k < SL::STRIDE; ++k) v[k] = 0;
+  T* r = v + SL::OR;
+  T* Jc = v + SL::OC;
+  T* Jg = v + SL::OG;
+  T* Jf = v + SL::OF;
+  const T* camT = (const T*)d.camT;
+  const T* ptT = (const T*)d.ptT;
+  const T* lnT = (const T*)d.lnT;
+  const T* plT = (const T*)d.plT;
+  const T* vpT = (const T*)d.vpT;
+  if constexpr (FAM == 5) {
+    const int g = d.fgrp[FAM][i];
+    jac_R5<T>(load_line<T>(lnT + (int64_t)LN_STRIDE * f), load_vp<T>(vpT + (int64_t)VP_STRIDE * g), r, Jg, Jf);
+  } else {
+    const int c = d.fcam[FAM][i];
+    Cam<T> C = load_cam<T>(camT + (int64_t)CAM_STRIDE * c);
+    if constexpr (FAM == 1 || FAM == 3 || FAM == 6) {
+      T X[3] = {ptT[(int64_t)PT_STRIDE * f], ptT[(int64_t)PT_STRIDE * f + 1], ptT[(int64_t)PT_STRIDE * f + 2]};
+      if constexpr (FAM == 1) jac_R1<T, CD>(C, X, mT, r, Jc, Jf);
+      if constexpr (FAM == 3) {
+        // a difference of two nearly equal projection Jacobians: evaluated in
+        // FP64 from the master parameters, stored in T
+        double r3[2], jc3[2 * SL::NC], jg3[6], jf3[6];
+        const double* X64 = d.pt64 + (int64_t)PT_STRIDE * f;
+        jac_R3<double, CD>(load_cam<double>(d.cam64 + (int64_t)CAM_STRIDE * c), X64,
+                           load_plane<double>(d.pl64 + (int64_t)PL_STRIDE * d.fgrp[FAM][i]), r3, jc3, jg3, jf3);
+#pragma unroll
+        for (int k = 0; k < 2 * SL::NC; ++k) Jc[k] = (T)jc3[k];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) { Jg[k] = (T)jg3[k]; Jf[k] = (T)jf3[k]; }
+      }
+      if constexpr (FAM == 6) jac_R6<T, CD>(C, X, mT, r, Jc, Jf);
+    } else {
+      Line<T> L = load_line<T>(lnT + (int64_t)LN_STRIDE * f);
+      if constexpr (FAM == 2) jac_R2<T, CD>(C, L, mT, r, Jc, Jf);
+      if constexpr (FAM == 4) {
+        // difference of two nearly equal line projections: FP64, stored in T
+        double m64[4], r4[4], jc4[4 * SL::NC], jg4[12], jf4[16];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) m64[k] = d.fmeas[FAM][i * 4 + k];
+        jac_R4<double, CD>(load_cam<double>(d.cam64 + (int64_t)CAM_STRIDE * c),
+                           load_line<double>(d.ln64 + (int64_t)LN_STRIDE * f),
+                           load_plane<double>(d.pl64 + (int64_t)PL_STRIDE * d.fgrp[FAM][i]), m64, r4, jc4, jg4, jf4);
+#pragma unroll
+        for (int k = 0; k < 4 * SL::NC; ++k) Jc[k] = (T)jc4[k];
+#pragma unroll
+        for (int k = 0; k < 12; ++k) Jg[k] = (T)jg4[k];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) Jf[k] = (T)jf4[k];
+      }
+      if constexpr (FAM == 7) jac_R7<T, CD>(C, L, mT, r, Jc, Jf);
+    }
+  }
+  // residual in FP64 from the FP64 parameters, robust IRLS scale
+  double r64[F::ROWS];
+  residual64<FAM>(d, i, d.cam64, d.pt64, d.ln64, d.pl64, d.vp64, r64);
+  double s = 0;
+#pragma unroll
+  for (int k = 0; k < F::ROWS; ++k) s += r64[k] * r64[k];
+  double rho, drho;
+  loss_eval<double>(d.lkind[FAM], d.lscale[FAM], s, rho, drho);
+  const double ws = sqrt(d.lweight[FAM] * drho);
+#pragma unroll
+  for (int k = 0; k < F::ROWS; ++k) r[k] = (T)(ws * r64[k]);
+  const T wsT = (T)ws;
+#pragma unroll
+  for (int k = SL::OC; k < SL::USED; ++k) v[k] *= wsT;
+  store_vec(((T*)d.frec[FAM]) + i * SL::STRIDE, v);
+}
+
+void launch_linearize(const Dev& d, hipStream_t s) {
+  BA_DISPATCH_T_CD(d, {
+    if (d.fn[1]) k_lin<1, T, CD><<<nblk(d.fn[1], 256), 256, 0, s>>>(d);
+    if (d.fn[2]) k_lin<2, T, CD><<<nblk(d.fn[2], 256), 256, 0, s>>>(d);
+    if (d.fn[3]) k_lin<3, T, CD><<<nblk(d.fn[3], 256), 256, 0, s>>>(d);
+    if (d.fn[4]) k_lin<4, T, CD><<<nblk(d.fn[4], 256), 256, 0, s>>>(d);
+    if (d.fn[5]) k_lin<5, T, CD><<<nblk(d.fn[5], 256), 256, 0, s>>>(d);
+    if (d.fn[6]) k_lin<6, T, CD><<<nblk(d.fn[6], 256), 256, 0, s>>>(d);
+    if (d.fn[7]) k_lin<7, T, CD><<<nblk(d.fn[7], 256), 256, 0, s>>>(d);
+  });
+}
+
+// ---------------------------------------------------------------------------
+// FP64 cost: one lane per record, per-workgroup partial sums
+template <int FAM> __global__ __launch_bounds__(256) void k_cost(Dev d, int candidate, double* part) {
+  __shared__ double lds[8];
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double e = 0;
+  if (i < d.fn[FAM]) {
+    double r[4];
+    if (candidate) residual64<FAM>(d, i, d.cam64n, d.pt64n, d.ln64n, d.pl64n, d.vp64n, r);
+    else residual64<FAM>(d, i, d.cam64, d.pt64, d.ln64, d.pl64, d.vp64, r);
+    double s = 0;
+#pragma unroll
+    for (int k = 0; k < Fam<FAM, 9>::ROWS; ++k) s += r[k] * r[k];
+    double rho, drho;
+    loss_eval<double>(d.lkind[FAM], d.lscale[FAM], s, rho, drho);
+    e = 0.5 * d.lweight[FAM] * rho;
+  }
+  e = wave_sum(e);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) lds[w] = e;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0;
+    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) t += lds[k];
+    part[blockIdx.x] = t;
+  }
+}
+
+// sum partials [0, n) into scal[SC_E] and, excluding [x0, x1), scal[SC_EPIX]
+__global__ __launch_bounds__(1024) void k_cost_final(const double* part, int n, int x0, int x1, double* scal) {
+  __shared__ double lds[2 * 17];
+  double v[2] = {0, 0};
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    v[0] += part[i];
+    if (i < x0 || i >= x1) v[1] += part[i];
+  }
+  double* o = block_sum_arr<double, 2>(v, lds);
+  if (threadIdx.x == 0) { scal[SC_E] = o[0]; scal[SC_EPIX] = o[1]; }
+}
+
+void launch_cost(const Dev& d, bool candidate, hipStream_t s) {
+  int off = 0, x0 = 0, x1 = 0;
+  auto go = [&](int fam) {
+    if (!d.fn[fam]) return;
+    unsigned nb = nblk(d.fn[fam], 256);
+    if (fam == 5) x0 = off;
+    switch (fam) {
+      case 1: k_cost<1><<<nb, 256, 0, s>>>(d, candidate, d.red + off); break;
+      case 2: k_cost<2><<<nb, 256, 0, s>>>(d, candidate, d.red + off); break;
+      case 3: k_cost<3><<<nb, 256, 0, s>>>(d, candidate, d.red + off); break;
+      case 4: k_cost<4><<<nb, 256, 0, s>>>(d, candidate, d.red + off); break;
+      case 5: k_cost<5><<<nb, 256, 0, s>>>(d, candidate, d.red + off); break;
+      case 6: k_cost<6><<<nb, 256, 0, s>>>(d, candidate, d.red + off); break;
+      case 7: k_cost<7><<<nb, 256, 0, s>>>(d, candidate, d.red + off); break;
+    }
+    off += (int)nb;
+    if (fam == 5) x1 = off;
+  };
+  for (int fam = 1; fam <= 7; ++fam) go(fam);
+  k_cost_final<<<1, 1024, 0, s>>>(d.red, off, x0, x1, d.scal);
+}
+
+// ---------------------------------------------------------------------------
+// feature blocks
+template <int FAM, typename T, int CD, int NF, typename A>
+__device__ __forceinline__ void acc_feature(const Dev& d, int f, A (&V)[NF * (NF + 1) / 2], A (&g)[NF]) {
+  using SL = Slot<FAM, CD>;
+  if (!d.fn[FAM]) return;
+  const int64_t b = d.foff[FAM][f], e = d.foff[FAM][f + 1];
+  const T* rec = (const T*)d.frec[FAM];
+  for (int64_t i = b; i < e; ++i) {
+    T v[SL::STRIDE];
+    load_vec(rec + i * SL::STRIDE, v);
+#pragma unroll
+    for (int row = 0; row < SL::ROWS; ++row) {
+      const T* jf = v + SL::OF + row * NF;
+      const A rr = (A)v[SL::OR + row];
+#pragma unroll
+      for (int a = 0; a < NF; ++a) {
+        g[a] += (A)jf[a] * rr;
+#pragma unroll
+        for (int b2 = a; b2 < NF; ++b2) V[sym<NF>(a, b2)] += (A)jf[a] * (A)jf[b2];
+      }
+    }
+  }
+}
+
+template <typename T, int CD, int NF, typename A> __device__ __forceinline__ void acc_feature_all(const Dev& d, int f, A (&V)[NF * (NF + 1) / 2], A (&g)[NF]) {
+  if constexpr (NF == 3) {
+    acc_feature<1, T, CD, 3>(d, f, V, g);
+    acc_feature<3, T, CD, 3>(d, f, V, g);
+    acc_feature<6, T, CD, 3>(d, f, V, g);
+  } else {
+    acc_feature<2, T, CD, 4>(d, f, V, g);
+    acc_feature<4, T, CD, 4>(d, f, V, g);
+    acc_feature<5, T, CD, 4>(d, f, V, g);
+    acc_feature<7, T, CD, 4>(d, f, V, g);
+  }
+}
+
+template <typename T, int CD, int NF> __device__ __forceinline__ void feature_accum_one(const Dev& d, int f) {
+  constexpr int NS = NF * (NF + 1) / 2;
+  T V[NS], g[NF];
+#pragma unroll
+  for (int k = 0; k < NS; ++k) V[k] = 0;
+#pragma unroll
+  for (int k = 0; k < NF; ++k) g[k] = 0;
+  acc_feature_all<T, CD, NF, T>(d, f, V, g);
+  T* Vo = (T*)(NF == 3 ? d.Vp : d.Vl) + (int64_t)NS * f;
+  T* go = (T*)(NF == 3 ? d.gp : d.gl) + (int64_t)NF * f;
+  double* Do = (NF == 3 ? d.Dp : d.Dl) + (int64_t)NF * f;
+#pragma unroll
+  for (int k = 0; k < NS; ++k) Vo[k] = V[k];
+#pragma unroll
+  for (int k = 0; k < NF; ++k) {
+    go[k] = g[k];
+    Do[k] = fmin(fmax((double)V[sym<NF>(k, k)], 1e-6), 1e32);
+  }
+}
+
+template <typename T, int CD> __global__ __launch_bounds__(256) void k_feat_accum(Dev d, int ptiles) {
+  if ((int)blockIdx.x < ptiles) {
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f < d.np) feature_accum_one<T, CD, 3>(d, f);
+  } else {
+    const int f = (blockIdx.x - ptiles) * blockDim.x + threadIdx.x;
+    if (f < d.nl) feature_accum_one<T, CD, 4>(d, f);
+  }
+}
+
+void launch_feature_accum(const Dev& d, hipStream_t s) {
+  const int pt = (int)nblk(d.np, 256), lt = (int)nblk(d.nl, 256);
+  if (pt + lt == 0) return;
+  BA_DISPATCH_T_CD(d, k_feat_accum<T, CD><<<pt + lt, 256, 0, s>>>(d, pt));
+}
+
+// damped inverse of one feature block; FP32 blocks whose Cholesky fails or
+// whose estimated condition exceeds kappa_max are redone in FP64 from the
+// stored Jacobians
+template <typename T, int CD, int NF> __device__ __forceinline__ int feature_invert_one(const Dev& d, int f, double lam, double kmax) {
+  constexpr int NS = NF * (NF + 1) / 2;
+  const T* Vin = (const T*)(NF == 3 ? d.Vp : d.Vl) + (int64_t)NS * f;
+  const T* gin = (const T*)(NF == 3 ? d.gp : d.gl) + (int64_t)NF * f;
+  const double* D = (NF == 3 ? d.Dp : d.Dl) + (int64_t)NF * f;
+  T* Vio = (T*)(NF == 3 ? d.Vip : d.Vil) + (int64_t)NS * f;
+  T* so = (T*)(NF == 3 ? d.sp : d.sl) + (int64_t)NF * f;
+  double* Vio64 = (NF == 3 ? d.Vip64 : d.Vil64) + (int64_t)NS * f;
+  uint8_t* flag = (NF == 3 ? d.flp : d.fll) + f;
+  T A[NF][NF];
+#pragma unroll
+  for (int i = 0; i < NF; ++i) {
+#pragma unroll
+    for (int j = 0; j < NF; ++j) A[i][j] = Vin[sym<NF>(i, j)];
+    A[i][i] += (T)(lam * D[i]);
+  }
+  bool ok = chol<T, NF>(A);
+  if (ok) {
+    T mx = A[0][0], mn = A[0][0];
+#pragma unroll
+    for (int i = 1; i < NF; ++i) { mx = fmax(mx, A[i][i]); mn = fmin(mn, A[i][i]); }
+    const double kap = ((double)mx / (double)mn) * ((double)mx / (double)mn);
+    if (sizeof(T) == 4 && kap > kmax) ok = false;
+  }
+  if (ok) {
+    T Ai[NF][NF];
+    chol_inverse<T, NF>(A, Ai);
+#pragma unroll
+    for (int i = 0; i < NF; ++i) {
+      T t = 0;
+#pragma unroll
+      for (int j = 0; j < NF; ++j) t += Ai[i][j] * gin[j];
+      so[i] = t;
+#pragma unroll
+      for (int j = i; j < NF; ++j) Vio[sym<NF>(i, j)] = Ai[i][j];
+    }
+    *flag = 0;
+    return 0;
+  }
+  // FP64 path: re-accumulate from the stored Jacobians in double
+  double V64[NS], g64[NF];
+#pragma unroll
+  for (int k = 0; k < NS; ++k) V64[k] = 0;
+#pragma unroll
+  for (int k = 0; k < NF; ++k) g64[k] = 0;
+  acc_feature_all<T, CD, NF, double>(d, f, V64, g64);
+  double B[NF][NF];
+#pragma unroll
+  for (int i = 0; i < NF; ++i) {
+#pragma unroll
+    for (int j = 0; j < NF; ++j) B[i][j] = V64[sym<NF>(i, j)];
+    B[i][i] += lam * D[i];
+  }
+  double Bi[NF][NF];
+  const bool ok64 = chol<double, NF>(B);
+  if (ok64) chol_inverse<double, NF>(B, Bi);
+#pragma unroll
+  for (int i = 0; i < NF; ++i) {
+    double t = 0;
+#pragma unroll
+    for (int j = 0; j < NF; ++j) {
+      if (!ok64) Bi[i][j] = 0;
+      t += Bi[i][j] * g64[j];
+    }
+    so[i] = (T)t;
+#pragma unroll
+    for (int j = i; j < NF; ++j) { Vio64[sym<NF>(i, j)] = Bi[i][j]; Vio[sym<NF>(i, j)] = (T)Bi[i][j]; }
+  }
+  *flag = ok64 ? 1 : 2;
+  return 1;
+}
+
+template <typename T, int CD> __global__ __launch_bounds__(256) void k_feat_inv(Dev d, int ptiles, double lam, double kmax) {
+  __shared__ double lds[8];
+  int nf = 0;
+  if ((int)blockIdx.x < ptiles) {
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f < d.np) nf = feature_invert_one<T, CD, 3>(d, f, lam, kmax);
+  } else {
+    const int f = (blockIdx.x - ptiles) * blockDim.x + threadIdx.x;
+    if (f < d.nl) nf = feature_invert_one<T, CD, 4>(d, f, lam, kmax);
+  }
+  double c = wave_sum((double)nf);
+  if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0;
+    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) t += lds[k];
+    if (t > 0) atomicAdd(&d.scal[SC_NFLAG], t);
+  }
+}
+
+void launch_feature_invert(const Dev& d, double lambda, double kappa_max, hipStream_t s) {
+  const int pt = (int)nblk(d.np, 256), lt = (int)nblk(d.nl, 256);
+  if (pt + lt == 0) return;
+  BA_DISPATCH_T_CD(d, k_feat_inv<T, CD><<<pt + lt, 256, 0, s>>>(d, pt, lambda, kappa_max));
+}
+
+// apply a feature inverse (packed, or FP64 for flagged features)
+template <typename T, int NF> __device__ __forceinline__ void apply_vinv(const Dev& d, int f, const T (&q)[NF], T (&s)[NF]) {
+  constexpr int NS = NF * (NF + 1) / 2;
+  const uint8_t fl = (NF == 3 ? d.flp : d.fll)[f];
+  if (fl) {
+    const double* M = (NF == 3 ? d.Vip64 : d.Vil64) + (int64_t)NS * f;
+#pragma unroll
+    for (int i = 0; i < NF; ++i) {
+      double t = 0;
+#pragma unroll
+      for (int j = 0; j < NF; ++j) t += M[sym<NF>(i, j)] * (double)q[j];
+      s[i] = (T)t;
+    }
+  } else {
+    const T* M = (const T*)(NF == 3 ? d.Vip : d.Vil) + (int64_t)NS * f;
+    T m[NS];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) m[k] = M[k];
+#pragma unroll
+    for (int i = 0; i < NF; ++i) {
+      T t = 0;
+#pragma unroll
+      for (int j = 0; j < NF; ++j) t += m[sym<NF>(i, j)] * q[j];
+      s[i] = t;
+    }
+  }
+}
+
+template <typename T, int NF> __device__ __forceinline__ void load_vinv_full(const Dev& d, int f, T (&M)[NF][NF]) {
+  constexpr int NS = NF * (NF + 1) / 2;
+  const uint8_t fl = (NF == 3 ? d.flp : d.fll)[f];
+  if (fl) {
+    const double* P = (NF == 3 ? d.Vip64 : d.Vil64) + (int64_t)NS * f;
+#pragma unroll
+    for (int i = 0; i < NF; ++i)
+#pragma unroll
+      for (int j = 0; j < NF; ++j) M[i][j] = (T)P[sym<NF>(i, j)];
+  } else {
+    const T* P = (const T*)(NF == 3 ? d.Vip : d.Vil) + (int64_t)NS * f;
+#pragma unroll
+    for (int i = 0; i < NF; ++i)
+#pragma unroll
+      for (int j = 0; j < NF; ++j) M[i][j] = P[sym<NF>(i, j)];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// camera pass A: U_cc, g_c (one workgroup per camera)
+template <int FAM, typename T, int CD> __device__ __forceinline__ void cam_a_rec(const Dev& d, int64_t i, T (&U)[CD * (CD + 1) / 2], T (&g)[CD]) {
+  using SL = Slot<FAM, CD>;
+  T v[SL::STRIDE];
+  load_vec(((const T*)d.frec[FAM]) + i * SL::STRIDE, v);
+#pragma unroll
+  for (int row = 0; row < SL::ROWS; ++row) {
+    const T* jc = v + SL::OC + row * SL::NC;
+    const T rr = v[SL::OR + row];
+#pragma unroll
+    for (int a = 0; a < SL::NC; ++a) {
+      g[a] += jc[a] * rr;
+#pragma unroll
+      for (int b = a; b < SL::NC; ++b) U[sym<CD>(a, b)] += jc[a] * jc[b];
+    }
+  }
+}
+
+// aligned plane record of an observation record (same feature, same camera)
+__device__ __forceinline__ int64_t aligned(const Dev& d, int fam_obs, int fam_pl, int64_t i) {
+  if (!d.fn[fam_pl]) return -1;
+  const int f = d.ffeat[fam_obs][i];
+  const int64_t b = d.foff[fam_pl][f];
+  if (d.foff[fam_pl][f + 1] == b) return -1;
+  return b + (i - d.foff[fam_obs][f]);
+}
+
+template <typename T, int CD> __global__ __launch_bounds__(256) void k_cam_a(Dev d) {
+  constexpr int NS = CD * (CD + 1) / 2;
+  constexpr int K = NS + CD;
+  __shared__ T lds[(4 + 1) * K];
+  const int c = blockIdx.x;
+  T acc[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) acc[k] = 0;
+  T(&U)[NS] = *reinterpret_cast<T(*)[NS]>(acc);
+  T(&g)[CD] = *reinterpret_cast<T(*)[CD]>(acc + NS);
+  if (d.fn[1]) {
+    for (int j = d.po_off[c] + threadIdx.x; j < d.po_off[c + 1]; j += blockDim.x) {
+      const int64_t i = d.po_idx[j];
+      cam_a_rec<1, T, CD>(d, i, U, g);
+      const int64_t i3 = aligned(d, 1, 3, i);
+      if (i3 >= 0) cam_a_rec<3, T, CD>(d, i3, U, g);
+    }
+  }
+  if (d.fn[6]) {
+    for (int j = d.px_off[c] + threadIdx.x; j < d.px_off[c + 1]; j += blockDim.x)
+      for (int64_t i = d.px_start[j]; i < d.px_start[j] + d.px_cnt[j]; ++i) cam_a_rec<6, T, CD>(d, i, U, g);
+  }
+  if (d.fn[2]) {
+    for (int j = d.lo_off[c] + threadIdx.x; j < d.lo_off[c + 1]; j += blockDim.x) {
+      const int64_t i = d.lo_idx[j];
+      cam_a_rec<2, T, CD>(d, i, U, g);
+      const int64_t i4 = aligned(d, 2, 4, i);
+      if (i4 >= 0) cam_a_rec<4, T, CD>(d, i4, U, g);
+    }
+  }
+  if (d.fn[7]) {
+    for (int j = d.lx_off[c] + threadIdx.x; j < d.lx_off[c + 1]; j += blockDim.x)
+      for (int64_t i = d.lx_start[j]; i < d.lx_start[j] + d.lx_cnt[j]; ++i) cam_a_rec<7, T, CD>(d, i, U, g);
+  }
+  T* o = block_sum_arr<T, K>(acc, lds);
+  for (int k = threadIdx.x; k < CD * CD; k += blockDim.x) {
+    const int a = k / CD, b = k % CD;
+    d.Ucam[(int64_t)c * CD * CD + k] = (double)o[sym<CD>(a, b)];
+  }
+  for (int k = threadIdx.x; k < CD; k += blockDim.x) {
+    d.gA[CD * c + k] = (double)o[NS + k];
+    d.DA[CD * c + k] = fmin(fmax((double)o[sym<CD>(k, k)], 1e-6), 1e32);
+  }
+}
+
+// group pass A: one workgroup per plane, then per VP
+template <int FAM, typename T, int CD, int NG> __device__ __forceinline__ void grp_a_rec(const Dev& d, int64_t i, T* U, T* g) {
+  using SL = Slot<FAM, CD>;
+  T v[SL::STRIDE];
+  load_vec(((const T*)d.frec[FAM]) + i * SL::STRIDE, v);
+#pragma unroll
+  for (int row = 0; row < SL::ROWS; ++row) {
+    const T* jg = v + SL::OG + row * NG;
+    const T rr = v[SL::OR + row];
+#pragma unroll
+    for (int a = 0; a < NG; ++a) {
+      g[a] += jg[a] * rr;
+#pragma unroll
+      for (int b = a; b < NG; ++b) U[sym<NG>(a, b)] += jg[a] * jg[b];
+    }
+  }
+}
+
+template <typename T, int CD> __global__ __launch_bounds__(256) void k_grp_a(Dev d) {
+  __shared__ T lds[5 * 9];
+  if ((int)blockIdx.x < d.ng) {
+    const int g = blockIdx.x;
+    T acc[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) acc[k] = 0;
+    if (d.fn[3])
+      for (int j = d.plp_off[g] + threadIdx.x; j < d.plp_off[g + 1]; j += blockDim.x) {
+        const int f = d.plp[j];
+        for (int64_t i = d.foff[3][f]; i < d.foff[3][f + 1]; ++i) grp_a_rec<3, T, CD, 3>(d, i, acc, acc + 6);
+      }
+    if (d.fn[4])
+      for (int j = d.pll_off[g] + threadIdx.x; j < d.pll_off[g + 1]; j += blockDim.x) {
+        const int f = d.pll[j];
+        for (int64_t i = d.foff[4][f]; i < d.foff[4][f + 1]; ++i) grp_a_rec<4, T, CD, 3>(d, i, acc, acc + 6);
+      }
+    T* o = block_sum_arr<T, 9>(acc, lds);
+    if (threadIdx.x < 9) {
+      const int a = threadIdx.x / 3, b = threadIdx.x % 3;
+      d.Upl[9 * g + threadIdx.x] = (double)o[sym<3>(a, b)];
+    }
+    if (threadIdx.x < 3) {
+      const int k = threadIdx.x;
+      d.gA[d.offPl + 3 * g + k] = (double)o[6 + k];
+      d.DA[d.offPl + 3 * g + k] = fmin(fmax((double)o[sym<3>(k, k)], 1e-6), 1e32);
+    }
+  } else {
+    const int v = blockIdx.x - d.ng;
+    T acc[5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) acc[k] = 0;
+    for (int j = d.vpm_off[v] + threadIdx.x; j < d.vpm_off[v + 1]; j += blockDim.x)
+      grp_a_rec<5, T, CD, 2>(d, d.vpm[j], acc, acc + 3);
+    T* o = block_sum_arr<T, 5>(acc, lds);
+    if (threadIdx.x < 4) {
+      const int a = threadIdx.x / 2, b = threadIdx.x % 2;
+      d.Uvp[4 * v + threadIdx.x] = (double)o[sym<2>(a, b)];
+    }
+    if (threadIdx.x < 2) {
+      const int k = threadIdx.x;
+      d.gA[d.offVp + 2 * v + k] = (double)o[3 + k];
+      d.DA[d.offVp + 2 * v + k] = fmin(fmax((double)o[sym<2>(k, k)], 1e-6), 1e32);
+    }
+  }
+}
+
+void launch_camera_pass_a(const Dev& d, hipStream_t s) {
+  BA_DISPATCH_T_CD(d, {
+    if (d.nc) k_cam_a<T, CD><<<d.nc, 256, 0, s>>>(d);
+    if (d.ng + d.nv) k_grp_a<T, CD><<<d.ng + d.nv, 256, 0, s>>>(d);
+  });
+}
+
+// ---------------------------------------------------------------------------
+// camera pass B: damped diagonal blocks of S and b with pair-summed W_af
+template <int FAM, typename T, int CD, int NF> __device__ __forceinline__ void addW_cam(const Dev& d, int64_t i, T (&W)[CD][NF]) {
+  using SL = Slot<FAM, CD>;
+  T v[SL::STRIDE];
+  load_vec(((const T*)d.frec[FAM]) + i * SL::STRIDE, v);
+#pragma unroll
+  for (int row = 0; row < SL::ROWS; ++row) {
+    const T* jc = v + SL::OC + row * SL::NC;
+    const T* jf = v + SL::OF + row * NF;
+#pragma unroll
+    for (int a = 0; a < SL::NC; ++a)
+#pragma unroll
+      for (int b = 0; b < NF; ++b) W[a][b] += jc[a] * jf[b];
+  }
+}
+
+// C -= W V^-1 W^T ; bb += W s   for the pair's feature f
+template <typename T, int N, int NF> __device__ __forceinline__ void pair_contrib(const Dev& d, int f, const T (&W)[N][NF],
+                                                                               T* C, T* bb) {
+  T M[NF][NF];
+  load_vinv_full<T, NF>(d, f, M);
+  const T* sv = (const T*)(NF == 3 ? d.sp : d.sl) + (int64_t)NF * f;
+  T s[NF];
+#pragma unroll
+  for (int k = 0; k < NF; ++k) s[k] = sv[k];
+  T Y[N][NF];
+#pragma unroll
+  for (int a = 0; a < N; ++a) {
+#pragma unroll
+    for (int b = 0; b < NF; ++b) {
+      T t = 0;
+#pragma unroll
+      for (int k = 0; k < NF; ++k) t += W[a][k] * M[k][b];
+      Y[a][b] = t;
+    }
+    T t = 0;
+#pragma unroll
+    for (int k = 0; k < NF; ++k) t += W[a][k] * s[k];
+    bb[a] += t;
+  }
+#pragma unroll
+  for (int a = 0; a < N; ++a)
+#pragma unroll
+    for (int b = a; b < N; ++b) {
+      T t = 0;
+#pragma unroll
+      for (int k = 0; k < NF; ++k) t += Y[a][k] * W[b][k];
+      C[sym<N>(a, b)] -= t;
+    }
+}
+
+template <typename T, int CD> __global__ __launch_bounds__(256) void k_cam_b(Dev d, double lam) {
+  constexpr int NS = CD * (CD + 1) / 2;
+  constexpr int K = NS + CD;
+  __shared__ T lds[(4 + 1) * K];
+  const int c = blockIdx.x;
+  T acc[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) acc[k] = 0;
+  T* C = acc;
+  T* bb = acc + NS;
+  if (d.fn[1]) {
+    for (int j = d.po_off[c] + threadIdx.x; j < d.po_off[c + 1]; j += blockDim.x) {
+      const int64_t i = d.po_idx[j];
+      T W[CD][3];
+#pragma unroll
+      for (int a = 0; a < CD; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) W[a][b] = 0;
+      addW_cam<1, T, CD, 3>(d, i, W);
+      const int64_t i3 = aligned(d, 1, 3, i);
+      if (i3 >= 0) addW_cam<3, T, CD, 3>(d, i3, W);
+      pair_contrib<T, CD, 3>(d, d.ffeat[1][i], W, C, bb);
+    }
+  }
+  if (d.fn[6]) {
+    for (int j = d.px_off[c] + threadIdx.x; j < d.px_off[c + 1]; j += blockDim.x) {
+      T W[CD][3];
+#pragma unroll
+      for (int a = 0; a < CD; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) W[a][b] = 0;
+      const int64_t i0 = d.px_start[j];
+      for (int64_t i = i0; i < i0 + d.px_cnt[j]; ++i) addW_cam<6, T, CD, 3>(d, i, W);
+      pair_contrib<T, CD, 3>(d, d.ffeat[6][i0], W, C, bb);
+    }
+  }
+  if (d.fn[2]) {
+    for (int j = d.lo_off[c] + threadIdx.x; j < d.lo_off[c + 1]; j += blockDim.x) {
+      const int64_t i = d.lo_idx[j];
+      T W[CD][4];
+#pragma unroll
+      for (int a = 0; a < CD; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) W[a][b] = 0;
+      addW_cam<2, T, CD, 4>(d, i, W);
+      const int64_t i4 = aligned(d, 2, 4, i);
+      if (i4 >= 0) addW_cam<4, T, CD, 4>(d, i4, W);
+      pair_contrib<T, CD, 4>(d, d.ffeat[2][i], W, C, bb);
+    }
+  }
+  if (d.fn[7]) {
+    for (int j = d.lx_off[c] + threadIdx.x; j < d.lx_off[c + 1]; j += blockDim.x) {
+      T W[CD][4];
+#pragma unroll
+      for (int a = 0; a < CD; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) W[a][b] = 0;
+      const int64_t i0 = d.lx_start[j];
+      for (int64_t i = i0; i < i0 + d.lx_cnt[j]; ++i) addW_cam<7, T, CD, 4>(d, i, W);
+      pair_contrib<T, CD, 4>(d, d.ffeat[7][i0], W, C, bb);
+    }
+  }
+  T* o = block_sum_arr<T, K>(acc, lds);
+  for (int k = threadIdx.x; k < CD * CD; k += blockDim.x) {
+    const int a = k / CD, b = k % CD;
+    const int64_t idx = (int64_t)c * CD * CD + k;
+    double v = d.Ucam[idx] + (double)o[sym<CD>(a, b)];
+    if (a == b) v += lam * d.DA[CD * c + a];
+    d.Scam[idx] = v;
+  }
+  for (int k = threadIdx.x; k < CD; k += blockDim.x) d.bA[CD * c + k] = -d.gA[CD * c + k] + (double)o[NS + k];
+}
+
+template <int FAM, typename T, int CD, int NG, int NF> __device__ __forceinline__ void addW_grp(const Dev& d, int64_t i, T (&W)[NG][NF]) {
+  using SL = Slot<FAM, CD>;
+  T v[SL::STRIDE];
+  load_vec(((const T*)d.frec[FAM]) + i * SL::STRIDE, v);
+#pragma unroll
+  for (int row = 0; row < SL::ROWS; ++row) {
+    const T* jg = v + SL::OG + row * NG;
+    const T* jf = v + SL::OF + row * NF;
+#pragma unroll
+    for (int a = 0; a < NG; ++a)
+#pragma unroll
+      for (int b = 0; b < NF; ++b) W[a][b] += jg[a] * jf[b];
+  }
+}
+
+template <typename T, int CD> __global__ __launch_bounds__(256) void k_grp_b(Dev d, double lam) {
+  __shared__ T lds[5 * 9];
+  if ((int)blockIdx.x < d.ng) {
+    const int g = blockIdx.x;
+    T acc[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) acc[k] = 0;
+    if (d.fn[3])
+      for (int j = d.plp_off[g] + threadIdx.x; j < d.plp_off[g + 1]; j += blockDim.x) {
+        const int f = d.plp[j];
+        T W[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+        for (int64_t i = d.foff[3][f]; i < d.foff[3][f + 1]; ++i) addW_grp<3, T, CD, 3, 3>(d, i, W);
+        pair_contrib<T, 3, 3>(d, f, W, acc, acc + 6);
+      }
+    if (d.fn[4])
+      for (int j = d.pll_off[g] + threadIdx.x; j < d.pll_off[g + 1]; j += blockDim.x) {
+        const int f = d.pll[j];
+        T W[3][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
+        for (int64_t i = d.foff[4][f]; i < d.foff[4][f + 1]; ++i) addW_grp<4, T, CD, 3, 4>(d, i, W);
+        pair_contrib<T, 3, 4>(d, f, W, acc, acc + 6);
+      }
+    T* o = block_sum_arr<T, 9>(acc, lds);
+    if (threadIdx.x < 9) {
+      const int a = threadIdx.x / 3, b = threadIdx.x % 3;
+      double v = d.Upl[9 * g + threadIdx.x] + (double)o[sym<3>(a, b)];
+      if (a == b) v += lam * d.DA[d.offPl + 3 * g + a];
+      d.Spl[9 * g + threadIdx.x] = v;
+    }
+    if (threadIdx.x < 3) d.bA[d.offPl + 3 * g + threadIdx.x] = -d.gA[d.offPl + 3 * g + threadIdx.x] + (double)o[6 + threadIdx.x];
+  } else {
+    const int v = blockIdx.x - d.ng;
+    T acc[5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) acc[k] = 0;
+    for (int j = d.vpm_off[v] + threadIdx.x; j < d.vpm_off[v + 1]; j += blockDim.x) {
+      const int64_t i = d.vpm[j];
+      T W[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
+      addW_grp<5, T, CD, 2, 4>(d, i, W);
+      pair_contrib<T, 2, 4>(d, d.ffeat[5][i], W, acc, acc + 3);
+    }
+    T* o = block_sum_arr<T, 5>(acc, lds);
+    if (threadIdx.x < 4) {
+      const int a = threadIdx.x / 2, b = threadIdx.x % 2;
+      double val = d.Uvp[4 * v + threadIdx.x] + (double)o[sym<2>(a, b)];
+      if (a == b) val += lam * d.DA[d.offVp + 2 * v + a];
+      d.Svp[4 * v + threadIdx.x] = val;
+    }
+    if (threadIdx.x < 2) d.bA[d.offVp + 2 * v + threadIdx.x] = -d.gA[d.offVp + 2 * v + threadIdx.x] + (double)o[3 + threadIdx.x];
+  }
+}
+
+void launch_camera_pass_b(const Dev& d, double lambda, hipStream_t s) {
+  BA_DISPATCH_T_CD(d, {
+    if (d.nc) k_cam_b<T, CD><<<d.nc, 256, 0, s>>>(d, lambda);
+    if (d.ng + d.nv) k_grp_b<T, CD><<<d.ng + d.nv, 256, 0, s>>>(d, lambda);
+  });
+}
+
+// ---------------------------------------------------------------------------
+// block-Jacobi preconditioner: M_i = S_ii^-1 (FP64); a block that is not
+// positive definite falls back to the inverse of its diagonal
+template <int N> __device__ __forceinline__ void invert_block(const double* S, double* M) {
+  double A[N][N];
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int j = 0; j < N; ++j) A[i][j] = 0.5 * (S[i * N + j] + S[j * N + i]);
+  double Ai[N][N];
+  if (chol<double, N>(A)) {
+    chol_inverse<double, N>(A, Ai);
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+      for (int j = 0; j < N; ++j) M[i * N + j] = Ai[i][j];
+  } else {
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+      for (int j = 0; j < N; ++j) M[i * N + j] = (i == j && S[i * N + i] > 0) ? 1.0 / S[i * N + i] : 0.0;
+  }
+}
+
+template <int CD> __global__ void k_precond_bj(Dev d) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < d.nc) invert_block<CD>(d.Scam + (int64_t)CD * CD * i, d.Mcam + (int64_t)CD * CD * i);
+  else if (i < d.nc + d.ng) invert_block<3>(d.Spl + 9 * (i - d.nc), d.Mpl + 9 * (i - d.nc));
+  else if (i < d.nc + d.ng + d.nv) invert_block<2>(d.Svp + 4 * (i - d.nc - d.ng), d.Mvp + 4 * (i - d.nc - d.ng));
+}
+
+void launch_precond_blockjacobi(const Dev& d, hipStream_t s) {
+  const int n = d.nc + d.ng + d.nv;
+  if (!n) return;
+  if (d.CD == 9) k_precond_bj<9><<<nblk(n, 64), 64, 0, s>>>(d);
+  else k_precond_bj<6><<<nblk(n, 64), 64, 0, s>>>(d);
+}
+
+// z = M r over all blocks (called by a single workgroup)
+template <int CD> __device__ __forceinline__ void apply_M(const Dev& d, const double* r, double* z) {
+  const int nb = d.nc + d.ng + d.nv;
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) {
+    if (i < d.nc) {
+      const double* M = d.Mcam + (int64_t)CD * CD * i;
+      const double* ri = r + CD * i;
+      double* zi = z + CD * i;
+#pragma unroll
+      for (int a = 0; a < CD; ++a) {
+        double t = 0;
+#pragma unroll
+        for (int b = 0; b < CD; ++b) t += M[a * CD + b] * ri[b];
+        zi[a] = t;
+      }
+    } else if (i < d.nc + d.ng) {
+      const int g = i - d.nc;
+      const double* M = d.Mpl + 9 * g;
+      const double* ri = r + d.offPl + 3 * g;
+      double* zi = z + d.offPl + 3 * g;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) zi[a] = M[3 * a] * ri[0] + M[3 * a + 1] * ri[1] + M[3 * a + 2] * ri[2];
+    } else {
+      const int v = i - d.nc - d.ng;
+      const double* M = d.Mvp + 4 * v;
+      const double* ri = r + d.offVp + 2 * v;
+      double* zi = z + d.offVp + 2 * v;
+      zi[0] = M[0] * ri[0] + M[1] * ri[1];
+      zi[1] = M[2] * ri[0] + M[3] * ri[1];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// PCG on S x = b, x0 = 0; all vector work in FP64 inside one workgroup
+template <typename T, int CD> __global__ __launch_bounds__(1024) void k_pcg_init(Dev d, double tol, int maxit) {
+  __shared__ double lds[2 * 17];
+  const int n = d.nA;
+  for (int k = threadIdx.x; k < n; k += blockDim.x) { d.x[k] = 0; d.r[k] = d.bA[k]; }
+  __syncthreads();
+  apply_M<CD>(d, d.r, d.z);
+  __syncthreads();
+  double v[2] = {0, 0};
+  for (int k = threadIdx.x; k < n; k += blockDim.x) {
+    d.p[k] = d.z[k];
+    ((T*)d.xT)[k] = (T)d.z[k];
+    v[0] += d.r[k] * d.z[k];
+    v[1] += d.r[k] * d.r[k];
+  }
+  double* o = block_sum_arr<double, 2>(v, lds);
+  if (threadIdx.x == 0) {
+    d.scal[SC_RZ] = o[0];
+    d.scal[SC_BB] = o[1];
+    d.scal[SC_RR] = o[1];
+    d.scal[SC_TOL2] = tol * tol * o[1];
+    d.scal[SC_ITER] = 0;
+    d.scal[SC_MAXIT] = maxit;
+    d.scal[SC_BREAK] = 0;
+    d.scal[SC_DONE] = (o[1] == 0.0 || maxit <= 0 || !isfinite(o[1])) ? 1.0 : 0.0;
+  }
+}
+
+template <typename T, int CD> __global__ __launch_bounds__(1024) void k_pcg_update(Dev d) {
+  __shared__ double lds[2 * 17];
+  __shared__ double sh[4];
+  if (d.scal[SC_DONE] != 0.0) return;
+  const int n = d.nA;
+  double v1[1] = {0};
+  for (int k = threadIdx.x; k < n; k += blockDim.x) v1[0] += d.p[k] * d.q[k];
+  double* o = block_sum_arr<double, 1>(v1, lds);
+  const double pq = o[0];
+  if (!(pq > 0.0) || !isfinite(pq)) {
+    if (threadIdx.x == 0) { d.scal[SC_DONE] = 1.0; d.scal[SC_BREAK] = 1.0; }
+    return;
+  }
+  const double alpha = d.scal[SC_RZ] / pq;
+  double v[1] = {0};
+  for (int k = threadIdx.x; k < n; k += blockDim.x) {
+    d.x[k] += alpha * d.p[k];
+    const double rk = d.r[k] - alpha * d.q[k];
+    d.r[k] = rk;
+    v[0] += rk * rk;
+  }
+  o = block_sum_arr<double, 1>(v, lds);
+  const double rr = o[0];
+  const double iter = d.scal[SC_ITER] + 1.0;
+  const bool done = rr <= d.scal[SC_TOL2] || iter >= d.scal[SC_MAXIT];
+  if (threadIdx.x == 0) { sh[0] = rr; }
+  apply_M<CD>(d, d.r, d.z);
+  __syncthreads();
+  double w[1] = {0};
+  for (int k = threadIdx.x; k < n; k += blockDim.x) w[0] += d.r[k] * d.z[k];
+  o = block_sum_arr<double, 1>(w, lds);
+  const double rz = o[0];
+  const double beta = rz / d.scal[SC_RZ];
+  for (int k = threadIdx.x; k < n; k += blockDim.x) {
+    const double pk = d.z[k] + beta * d.p[k];
+    d.p[k] = pk;
+    ((T*)d.xT)[k] = (T)pk;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    d.scal[SC_RR] = rr;
+    d.scal[SC_RZ] = rz;
+    d.scal[SC_ALPHA] = alpha;
+    d.scal[SC_BETA] = beta;
+    d.scal[SC_PQ] = pq;
+    d.scal[SC_ITER] = iter;
+    if (done) d.scal[SC_DONE] = 1.0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// implicit-Schur product y = J_a^T (J_a x - J_f V^-1 J_f^T J_a x) (+ lambda D_a x
+// in the reduction), one lane per feature
+template <int FAM, typename T, int CD, int NF> __device__ __forceinline__ void mv_first(const Dev& d, int f, const T* x, T (&q)[NF]) {
+  using SL = Slot<FAM, CD>;
+  using F = Fam<FAM, CD>;
+  if (!d.fn[FAM]) return;
+  const int64_t b = d.foff[FAM][f], e = d.foff[FAM][f + 1];
+  const T* rec = (const T*)d.frec[FAM];
+  for (int64_t i = b; i < e; ++i) {
+    T v[SL::STRIDE];
+    load_vec(rec + i * SL::STRIDE, v);
+    T xc[SL::NC > 0 ? SL::NC : 1], xg[SL::NG > 0 ? SL::NG : 1];
+    if constexpr (SL::NC > 0) {
+      const T* xp = x + CD * d.fcam[FAM][i];
+#pragma unroll
+      for (int k = 0; k < SL::NC; ++k) xc[k] = xp[k];
+    }
+    if constexpr (SL::NG > 0) {
+      const T* xp = x + a_grp(d, F::GT, d.fgrp[FAM][i]);
+#pragma unroll
+      for (int k = 0; k < SL::NG; ++k) xg[k] = xp[k];
+    }
+#pragma unroll
+    for (int row = 0; row < SL::ROWS; ++row) {
+      T t = 0;
+#pragma unroll
+      for (int k = 0; k < SL::NC; ++k) t += v[SL::OC + row * SL::NC + k] * xc[k];
+#pragma unroll
+      for (int k = 0; k < SL::NG; ++k) t += v[SL::OG + row * SL::NG + k] * xg[k];
+#pragma unroll
+      for (int a = 0; a < NF; ++a) q[a] += v[SL::OF + row * NF + a] * t;
+    }
+  }
+}
+
+template <int FAM, typename T, int CD, int NF> __device__ __forceinline__ void mv_second(const Dev& d, int f, const T* x, const T (&s)[NF], T* y) {
+  using SL = Slot<FAM, CD>;
+  using F = Fam<FAM, CD>;
+  if (!d.fn[FAM]) return;
+  const int64_t b = d.foff[FAM][f], e = d.foff[FAM][f + 1];
+  const T* rec = (const T*)d.frec[FAM];
+  for (int64_t i = b; i < e; ++i) {
+    T v[SL::STRIDE];
+    load_vec(rec + i * SL::STRIDE, v);
+    int ac = 0, ag = 0;
+    T xc[SL::NC > 0 ? SL::NC : 1], xg[SL::NG > 0 ? SL::NG : 1];
+    if constexpr (SL::NC > 0) {
+      ac = CD * d.fcam[FAM][i];
+#pragma unroll
+      for (int k = 0; k < SL::NC; ++k) xc[k] = x[ac + k];
+    }
+    if constexpr (SL::NG > 0) {
+      ag = a_grp(d, F::GT, d.fgrp[FAM][i]);
+#pragma unroll
+      for (int k = 0; k < SL::NG; ++k) xg[k] = x[ag + k];
+    }
+    T zc[SL::NC > 0 ? SL::NC : 1], zg[SL::NG > 0 ? SL::NG : 1];
+#pragma unroll
+    for (int k = 0; k < SL::NC; ++k) zc[k] = 0;
+#pragma unroll
+    for (int k = 0; k < SL::NG; ++k) zg[k] = 0;
+#pragma unroll
+    for (int row = 0; row < SL::ROWS; ++row) {
+      T t = 0;
+#pragma unroll
+      for (int k = 0; k < SL::NC; ++k) t += v[SL::OC + row * SL::NC + k] * xc[k];
+#pragma unroll
+      for (int k = 0; k < SL::NG; ++k) t += v[SL::OG + row * SL::NG + k] * xg[k];
+#pragma unroll
+      for (int a = 0; a < NF; ++a) t -= v[SL::OF + row * NF + a] * s[a];
+#pragma unroll
+      for (int k = 0; k < SL::NC; ++k) zc[k] += v[SL::OC + row * SL::NC + k] * t;
+#pragma unroll
+      for (int k = 0; k < SL::NG; ++k) zg[k] += v[SL::OG + row * SL::NG + k] * t;
+    }
+#pragma unroll
+    for (int k = 0; k < SL::NC; ++k) atomicAdd(y + ac + k, zc[k]);
+#pragma unroll
+    for (int k = 0; k < SL::NG; ++k) atomicAdd(y + ag + k, zg[k]);
+  }
+}
+
+template <typename T, int CD, int NF> __device__ __forceinline__ void mv_feature(const Dev& d, int f, const T* x, T* y) {
+  T q[NF];
+#pragma unroll
+  for (int k = 0; k < NF; ++k) q[k] = 0;
+  if constexpr (NF == 3) {
+    mv_first<1, T, CD, 3>(d, f, x, q);
+    mv_first<3, T, CD, 3>(d, f, x, q);
+    mv_first<6, T, CD, 3>(d, f, x, q);
+  } else {
+    mv_first<2, T, CD, 4>(d, f, x, q);
+    mv_first<4, T, CD, 4>(d, f, x, q);
+    mv_first<5, T, CD, 4>(d, f, x, q);
+    mv_first<7, T, CD, 4>(d, f, x, q);
+  }
+  T s[NF];
+  apply_vinv<T, NF>(d, f, q, s);
+  if constexpr (NF == 3) {
+    mv_second<1, T, CD, 3>(d, f, x, s, y);
+    mv_second<3, T, CD, 3>(d, f, x, s, y);
+    mv_second<6, T, CD, 3>(d, f, x, s, y);
+  } else {
+    mv_second<2, T, CD, 4>(d, f, x, s, y);
+    mv_second<4, T, CD, 4>(d, f, x, s, y);
+    mv_second<5, T, CD, 4>(d, f, x, s, y);
+    mv_second<7, T, CD, 4>(d, f, x, s, y);
+  }
+}
+
+// LDS mode: each workgroup accumulates into its own copy of y in LDS and
+// writes it to its row of the partial buffer.  Global mode: atomics into
+// the nA accumulator.
+template <typename T, int CD, bool LDS> __global__ __launch_bounds__(256) void k_matvec(Dev d, const double* done) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  if (done && *done != 0.0) return;
+  const T* x = (const T*)d.xT;
+  T* y;
+  if constexpr (LDS) {
+    y = reinterpret_cast<T*>(smem_raw);
+    for (int k = threadIdx.x; k < d.nA; k += blockDim.x) y[k] = 0;
+    __syncthreads();
+  } else {
+    y = (T*)d.mv_part;
+  }
+  const int tp = (d.np + blockDim.x - 1) / blockDim.x, tl = (d.nl + blockDim.x - 1) / blockDim.x;
+  for (int tile = blockIdx.x; tile < tp + tl; tile += gridDim.x) {
+    if (tile < tp) {
+      const int f = tile * blockDim.x + threadIdx.x;
+      if (f < d.np) mv_feature<T, CD, 3>(d, f, x, y);
+    } else {
+      const int f = (tile - tp) * blockDim.x + threadIdx.x;
+      if (f < d.nl) mv_feature<T, CD, 4>(d, f, x, y);
+    }
+  }
+  if constexpr (LDS) {
+    __syncthreads();
+    T* out = (T*)d.mv_part + (int64_t)blockIdx.x * d.nA;
+    for (int k = threadIdx.x; k < d.nA; k += blockDim.x) out[k] = y[k];
+  }
+}
+
+// y = sum of partials + lambda D_a x ; in global mode also re-zeroes the accumulator
+template <typename T> __global__ __launch_bounds__(256) void k_mv_reduce(Dev d, const double* done, const double* xin, double* y, double lam) {
+  if (done && *done != 0.0) return;
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= d.nA) return;
+  T* part = (T*)d.mv_part;
+  double s = 0;
+  if (d.mv_lds) {
+    for (int w = 0; w < d.n_mv_wg; ++w) s += (double)part[(int64_t)w * d.nA + k];
+  } else {
+    s = (double)part[k];
+    part[k] = 0;
+  }
+  y[k] = s + lam * d.DA[k] * xin[k];
+}
+
+template <typename T> __global__ void k_to_T(const double* src, void* dst, int n) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) ((T*)dst)[k] = (T)src[k];
+}
+
+int matvec_max_lds_bytes() {
+  int dev = 0, v = 0;
+  hipGetDevice(&dev);
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) v = 65536;
+  return v;
+}
+
+template <typename T, int CD> static void run_matvec(const Dev& d, const double* done, hipStream_t s) {
+  const size_t lds = d.mv_lds ? (size_t)d.nA * sizeof(T) : 0;
+  if (d.mv_lds) {
+    static bool attr_set = false;
+    if (!attr_set) {
+      hipFuncSetAttribute((const void*)k_matvec<T, CD, true>, hipFuncAttributeMaxDynamicSharedMemorySize, matvec_max_lds_bytes());
+      attr_set = true;
+    }
+    k_matvec<T, CD, true><<<d.n_mv_wg, 256, lds, s>>>(d, done);
+  } else {
+    k_matvec<T, CD, false><<<d.n_mv_wg, 256, 0, s>>>(d, done);
+  }
+}
+
+void launch_pcg_init(const Dev& d, double tol, int max_iters, hipStream_t s) {
+  BA_DISPATCH_T_CD(d, k_pcg_init<T, CD><<<1, 1024, 0, s>>>(d, tol, max_iters));
+}
+
+void launch_pcg_iteration(const Dev& d, double lambda, hipStream_t s) {
+  BA_DISPATCH_T_CD(d, {
+    run_matvec<T, CD>(d, d.scal + SC_DONE, s);
+    k_mv_reduce<T><<<nblk(d.nA, 256), 256, 0, s>>>(d, d.scal + SC_DONE, d.p, d.q, lambda);
+    k_pcg_update<T, CD><<<1, 1024, 0, s>>>(d);
+  });
+}
+
+void launch_schur_matvec(const Dev& d, const double* xin, double* yout, double lambda, hipStream_t s) {
+  BA_DISPATCH_T_CD(d, {
+    k_to_T<T><<<nblk(d.nA, 256), 256, 0, s>>>(xin, d.xT, d.nA);
+    run_matvec<T, CD>(d, nullptr, s);
+    k_mv_reduce<T><<<nblk(d.nA, 256), 256, 0, s>>>(d, nullptr, xin, yout, lambda);
+  });
+}
+
+// ---------------------------------------------------------------------------
+// back-substitution h_f = -(V_f + lambda D_f)^-1 (g_f + J_f^T J_a h_a), and the
+// model-decrease terms h.g and sum |J h|^2 (FP64 accumulation)
+template <int FAM, typename T, int CD, int NF> __device__ __forceinline__ void bs_second(const Dev& d, int f, const T* x, const T (&h)[NF], double& jh2) {
+  using SL = Slot<FAM, CD>;
+  using F = Fam<FAM, CD>;
+  if (!d.fn[FAM]) return;
+  const int64_t b = d.foff[FAM][f], e = d.foff[FAM][f + 1];
+  const T* rec = (const T*)d.frec[FAM];
+  for (int64_t i = b; i < e; ++i) {
+    T v[SL::STRIDE];
+    load_vec(rec + i * SL::STRIDE, v);
+    T xc[SL::NC > 0 ? SL::NC : 1], xg[SL::NG > 0 ? SL::NG : 1];
+    if constexpr (SL::NC > 0) {
+      const T* xp = x + CD * d.fcam[FAM][i];
+#pragma unroll
+      for (int k = 0; k < SL::NC; ++k) xc[k] = xp[k];
+    }
+    if constexpr (SL::NG > 0) {
+      const T* xp = x + a_grp(d, F::GT, d.fgrp[FAM][i]);
+#pragma unroll
+      for (int k = 0; k < SL::NG; ++k) xg[k] = xp[k];
+    }
+#pragma unroll
+    for (int row = 0; row < SL::ROWS; ++row) {
+      double t = 0;
+#pragma unroll
+      for (int k = 0; k < SL::NC; ++k) t += (double)v[SL::OC + row * SL::NC + k] * (double)xc[k];
+#pragma unroll
+      for (int k = 0; k < SL::NG; ++k) t += (double)v[SL::OG + row * SL::NG + k] * (double)xg[k];
+#pragma unroll
+      for (int a = 0; a < NF; ++a) t += (double)v[SL::OF + row * NF + a] * (double)h[a];
+      jh2 += t * t;
+    }
+  }
+}
+
+template <typename T, int CD, int NF> __device__ __forceinline__ void backsub_one(const Dev& d, int f, const T* x, double& gh, double& jh2) {
+  T q[NF];
+#pragma unroll
+  for (int k = 0; k < NF; ++k) q[k] = 0;
+  if constexpr (NF == 3) {
+    mv_first<1, T, CD, 3>(d, f, x, q);
+    mv_first<3, T, CD, 3>(d, f, x, q);
+    mv_first<6, T, CD, 3>(d, f, x, q);
+  } else {
+    mv_first<2, T, CD, 4>(d, f, x, q);
+    mv_first<4, T, CD, 4>(d, f, x, q);
+    mv_first<5, T, CD, 4>(d, f, x, q);
+    mv_first<7, T, CD, 4>(d, f, x, q);
+  }
+  const T* g = (const T*)(NF == 3 ? d.gp : d.gl) + (int64_t)NF * f;
+#pragma unroll
+  for (int k = 0; k < NF; ++k) q[k] = -(q[k] + g[k]);
+  T h[NF];
+  apply_vinv<T, NF>(d, f, q, h);
+  double* ho = (NF == 3 ? d.hp : d.hl) + (int64_t)NF * f;
+#pragma unroll
+  for (int k = 0; k < NF; ++k) {
+    ho[k] = (double)h[k];
+    gh += (double)g[k] * (double)h[k];
+  }
+  if constexpr (NF == 3) {
+    bs_second<1, T, CD, 3>(d, f, x, h, jh2);
+    bs_second<3, T, CD, 3>(d, f, x, h, jh2);
+    bs_second<6, T, CD, 3>(d, f, x, h, jh2);
+  } else {
+    bs_second<2, T, CD, 4>(d, f, x, h, jh2);
+    bs_second<4, T, CD, 4>(d, f, x, h, jh2);
+    bs_second<5, T, CD, 4>(d, f, x, h, jh2);
+    bs_second<7, T, CD, 4>(d, f, x, h, jh2);
+  }
+}
+
+template <typename T, int CD> __global__ __launch_bounds__(256) void k_backsub(Dev d, int ptiles) {
+  __shared__ double lds[2 * 5];
+  const T* x = (const T*)d.xT;
+  double v[2] = {0, 0};
+  if ((int)blockIdx.x < ptiles) {
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f < d.np) backsub_one<T, CD, 3>(d, f, x, v[0], v[1]);
+  } else {
+    const int f = (blockIdx.x - ptiles) * blockDim.x + threadIdx.x;
+    if (f < d.nl) backsub_one<T, CD, 4>(d, f, x, v[0], v[1]);
+  }
+  double* o = block_sum_arr<double, 2>(v, lds);
+  if (threadIdx.x == 0) { d.red[2 * blockIdx.x] = o[0]; d.red[2 * blockIdx.x + 1] = o[1]; }
+}
+
+// camera/group records of no feature do not exist, so J h over all records is
+// covered by the feature pass; this adds g_a . h_a and sums the partials
+__global__ __launch_bounds__(1024) void k_md_final(Dev d, int nparts) {
+  __shared__ double lds[2 * 17];
+  double v[2] = {0, 0};
+  for (int i = threadIdx.x; i < nparts; i += blockDim.x) { v[0] += d.red[2 * i]; v[1] += d.red[2 * i + 1]; }
+  for (int k = threadIdx.x; k < d.nA; k += blockDim.x) v[0] += d.gA[k] * d.x[k];
+  double* o = block_sum_arr<double, 2>(v, lds);
+  if (threadIdx.x == 0) { d.scal[SC_GH] = o[0]; d.scal[SC_JH2] = o[1]; }
+}
+
+void launch_backsub(const Dev& d, hipStream_t s) {
+  const int pt = (int)nblk(d.np, 256), lt = (int)nblk(d.nl, 256);
+  BA_DISPATCH_T_CD(d, {
+    k_to_T<T><<<nblk(d.nA, 256), 256, 0, s>>>(d.x, d.xT, d.nA);
+    if (pt + lt) k_backsub<T, CD><<<pt + lt, 256, 0, s>>>(d, pt);
+  });
+  k_md_final<<<1, 1024, 0, s>>>(d, pt + lt);
+}
+
+// ---------------------------------------------------------------------------
+// retraction in FP64: candidate = current [+] (h_a, h_f)
+__device__ void so3_exp(const double* w, double* E) {
+  const double th2 = w[0] * w[0] + w[1] * w[1] + w[2] * w[2];
+  const double th = sqrt(th2);
+  double a, b;
+  if (th < 1e-8) { a = 1.0 - th2 / 6.0; b = 0.5 - th2 / 24.0; }
+  else { a = sin(th) / th; b = (1.0 - cos(th)) / th2; }
+  const double W[9] = {0, -w[2], w[1], w[2], 0, -w[0], -w[1], w[0], 0};
+  double W2[9];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) W2[3 * i + j] = W[3 * i] * W[j] + W[3 * i + 1] * W[3 + j] + W[3 * i + 2] * W[6 + j];
+  for (int k = 0; k < 9; ++k) E[k] = (k % 4 == 0 ? 1.0 : 0.0) + a * W[k] + b * W2[k];
+}
+
+// tangent basis of the sphere at n: b1 = normalise(e_k - (e_k.n) n), k = argmin |n_k|, b2 = n x b1
+__device__ void s2_basis(const double* n, double* b1, double* b2) {
+  int k = 0;
+  if (fabs(n[1]) < fabs(n[k])) k = 1;
+  if (fabs(n[2]) < fabs(n[k])) k = 2;
+  double e[3] = {0, 0, 0};
+  e[k] = 1.0;
+  const double en = n[k];
+  for (int i = 0; i < 3; ++i) b1[i] = e[i] - en * n[i];
+  const double nb = sqrt(b1[0] * b1[0] + b1[1] * b1[1] + b1[2] * b1[2]);
+  for (int i = 0; i < 3; ++i) b1[i] /= nb;
+  cross3(n, b1, b2);
+}
+
+__device__ void s2_retract(const double* n, const double* b1, const double* b2, double d0, double d1, double* out) {
+  double v[3];
+  for (int i = 0; i < 3; ++i) v[i] = b1[i] * d0 + b2[i] * d1;
+  const double th = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+  for (int i = 0; i < 3; ++i) out[i] = th < 1e-12 ? n[i] + v[i] : cos(th) * n[i] + sin(th) * v[i] / th;
+  const double nn = sqrt(out[0] * out[0] + out[1] * out[1] + out[2] * out[2]);
+  for (int i = 0; i < 3; ++i) out[i] /= nn;
+}
+
+__global__ void k_retract(Dev d) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int CD = d.CD;
+  if (i < d.nc) {
+    const double* c = d.cam64 + (int64_t)CAM_STRIDE * i;
+    double* o = d.cam64n + (int64_t)CAM_STRIDE * i;
+    const double* h = d.x + CD * i;
+    double E[9];
+    so3_exp(h, E);
+    for (int r = 0; r < 3; ++r)
+      for (int k = 0; k < 3; ++k) o[3 * r + k] = E[3 * r] * c[k] + E[3 * r + 1] * c[3 + k] + E[3 * r + 2] * c[6 + k];
+    for (int r = 0; r < 3; ++r) o[9 + r] = E[3 * r] * c[9] + E[3 * r + 1] * c[10] + E[3 * r + 2] * c[11] + h[3 + r];
+    o[12] = c[12] + (CD == 9 ? h[6] : 0.0);
+    o[13] = c[13] + (CD == 9 ? h[7] : 0.0);
+    o[14] = c[14] + (CD == 9 ? h[8] : 0.0);
+    o[15] = 0;
+    return;
+  }
+  int j = i - d.nc;
+  if (j < d.np) {
+    for (int k = 0; k < 3; ++k) d.pt64n[PT_STRIDE * (int64_t)j + k] = d.pt64[PT_STRIDE * (int64_t)j + k] + d.hp[3 * (int64_t)j + k];
+    d.pt64n[PT_STRIDE * (int64_t)j + 3] = 0;
+    return;
+  }
+  j -= d.np;
+  if (j < d.nl) {
+    const double* L = d.ln64 + (int64_t)LN_STRIDE * j;
+    double* o = d.ln64n + (int64_t)LN_STRIDE * j;
+    const double* h = d.hl + 4 * (int64_t)j;
+    double E[9];
+    so3_exp(h, E);
+    // U' = U E with U = [u1 u2 u3] (columns stored consecutively)
+    for (int col = 0; col < 3; ++col)
+      for (int r = 0; r < 3; ++r) o[3 * col + r] = L[r] * E[col] + L[3 + r] * E[3 + col] + L[6 + r] * E[6 + col];
+    const double cph = cos(h[3]), sph = sin(h[3]);
+    o[9] = L[9] * cph - L[10] * sph;
+    o[10] = L[9] * sph + L[10] * cph;
+    o[11] = 0;
+    return;
+  }
+  j -= d.nl;
+  if (j < d.ng) {
+    const double* P = d.pl64 + (int64_t)PL_STRIDE * j;
+    double* o = d.pl64n + (int64_t)PL_STRIDE * j;
+    const double* h = d.x + d.offPl + 3 * j;
+    s2_retract(P, P + 4, P + 7, h[0], h[1], o);
+    o[3] = P[3] + h[2];
+    s2_basis(o, o + 4, o + 7);
+    o[10] = o[11] = 0;
+    return;
+  }
+  j -= d.ng;
+  if (j < d.nv) {
+    const double* V = d.vp64 + (int64_t)VP_STRIDE * j;
+    double* o = d.vp64n + (int64_t)VP_STRIDE * j;
+    const double* h = d.x + d.offVp + 2 * j;
+    s2_retract(V, V + 4, V + 7, h[0], h[1], o);
+    o[3] = 0;
+    s2_basis(o, o + 4, o + 7);
+    o[10] = o[11] = 0;
+  }
+}
+
+void launch_retract(const Dev& d, hipStream_t s) {
+  const int n = d.nc + d.np + d.nl + d.ng + d.nv;
+  if (n) k_retract<<<nblk(n, 256), 256, 0, s>>>(d);
+}
+
+__global__ void k_zero(unsigned char* p, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = 0;
+}
+void launch_zero(void* p, size_t bytes, hipStream_t s) {
+  if (bytes) k_zero<<<256, 256, 0, s>>>((unsigned char*)p, bytes);
+}
+
+}  // namespace ba

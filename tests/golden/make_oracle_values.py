@@ -1,0 +1,34 @@
+"""Write oracle_converged.json: converged costs E* of the parity scenes.
+
+Calls only the oracle (FP64 LM with exact Schur solves) on the seeded
+scenes; the GPU tests compare their converged cost with these values.
+Run from the repository root:  python tests/golden/make_oracle_values.py
+"""
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+from scenegen import make_scene, small_config  # noqa: E402
+from oracle import lm  # noqa: E402
+
+SCENES = {
+    "tiny_holistic": lambda: make_scene(small_config(n_cams=9, n_points=70, n_lines=20), seed=101),
+    "points_10cam": lambda: make_scene(1),
+    "holistic_30cam": lambda: make_scene(2),
+}
+
+if __name__ == "__main__":
+    out = {}
+    for name, fn in SCENES.items():
+        t = time.time()
+        prob = lm.Problem(fn())
+        res = lm.lm_solve(prob, func_tol=1e-12, max_iters=200)
+        out[name] = dict(E=res["E"], Epix=res["Epix"], iters=res["iters"], accepted=res["accepted"],
+                         reason=res["reason"], seconds=round(time.time() - t, 1))
+        print(name, out[name], flush=True)
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "oracle_converged.json"), "w") as f:
+        json.dump(out, f, indent=1)

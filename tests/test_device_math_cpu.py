@@ -1,0 +1,87 @@
+"""The library's analytic residual / Jacobian templates, compiled for the host,
+against the oracle's complex-step Jacobians of the same residual definitions
+(Sec. 3.1 Eq. 1, 3.2 Eq. 4, 3.3 Eqs. 6-8, 3.4 Eqs. 11-12).
+
+FP64 instantiation: 1e-9 relative.  FP32 instantiation: the per-observation
+bar of 1e-4 relative (residual relative to max(|r|, 1 px); Jacobian relative
+to the block's Frobenius norm).
+"""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+from scenegen import make_scene, small_config
+from oracle import lm, model
+from tests import layout
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB = os.path.join(HERE, "native", "libmathcheck.so")
+
+
+def _lib():
+    if not os.path.exists(LIB):
+        subprocess.check_call(["hipcc", "-std=c++17", "-O2", "-fPIC", "-shared", "-x", "hip", "--offload-host-only",
+                               os.path.join(HERE, "native", "mathcheck.cpp"), "-o", LIB])
+    lib = ctypes.CDLL(LIB)
+    P = ctypes.POINTER(ctypes.c_double)
+    lib.mc_eval.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int] + [P] * 10
+    lib.mc_eval.restype = ctypes.c_int
+    return lib
+
+
+def _p(a):
+    return np.ascontiguousarray(a, dtype=np.float64).ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _eval(lib, fam, cd, fp64, st, rec, i, cx, cy):
+    cam = layout.cam_slot(st, rec["cam"][i]) if "cam" in rec else np.zeros(16)
+    pt = layout.pt_slot(st, rec["pt"][i]) if "pt" in rec else np.zeros(4)
+    ln = layout.ln_slot(st, rec["ln"][i]) if "ln" in rec else np.zeros(12)
+    pl = layout.pl_slot(st, rec["pl"][i]) if "pl" in rec else np.zeros(12)
+    vp = layout.vp_slot(st, rec["vp"][i]) if "vp" in rec else np.zeros(12)
+    meas = layout.shifted_meas(fam, rec, i, cx, cy)
+    r, Jc, Jg, Jf = np.zeros(4), np.zeros(4 * 9), np.zeros(4 * 3), np.zeros(4 * 4)
+    bufs = [cam, pt, ln, pl, vp, meas, r, Jc, Jg, Jf]
+    rows = lib.mc_eval(int(fam[1]), cd, fp64, *[_p(b) for b in bufs[:6]], *[
+        b.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) for b in bufs[6:]])
+    return rows, r[:rows], Jc.reshape(4, 9)[:rows, :cd], Jg.reshape(4, 3)[:rows], Jf.reshape(4, 4)[:rows]
+
+
+@pytest.fixture(scope="module")
+def setup():
+    s = make_scene(small_config(n_cams=8), seed=31)
+    prob = lm.Problem(s)
+    st = prob.state0()
+    st.cam_k1 = st.cam_k1 + 0.06
+    st.cam_k2 = st.cam_k2 - 0.04
+    return prob, st, _lib()
+
+
+@pytest.mark.parametrize("cd", [9, 6])
+@pytest.mark.parametrize("fam", model.FAMILY_ORDER)
+def test_device_math_matches_oracle(setup, fam, cd):
+    prob, st, lib = setup
+    rec = prob.recs[fam]
+    n = prob.record_count(fam)
+    assert n > 0
+    r_or = model.residuals(st, rec, fam, prob.cx, prob.cy)
+    J_or = model.jacobians(st, rec, fam, prob.cx, prob.cy, camera_dof=cd)
+    blocks = model.FAMILIES[fam][2]
+    for fp64 in (1, 0):
+        for i in range(n):
+            rows, r, Jc, Jg, Jf = _eval(lib, fam, cd, fp64, st, rec, i, prob.cx, prob.cy)
+            ref_r = r_or[i]
+            if fp64:
+                tol_r = 1e-9 * max(np.abs(ref_r).max(), 1.0)
+            else:
+                tol_r = 1e-4 * max(np.linalg.norm(ref_r), 1e-3 if fam == "R5" else 1.0)
+            assert np.linalg.norm(r - ref_r) <= tol_r, (fam, fp64, i, r, ref_r)
+            for b, _, _ in blocks:
+                got = {"cam": Jc, "pt": Jf[:, :3], "ln": Jf[:, :4], "pl": Jg[:, :3], "vp": Jg[:, :2]}[b]
+                ref = J_or[b][i]
+                nrm = np.linalg.norm(ref)
+                tol = (1e-9 if fp64 else 1e-4) * max(nrm, 1e-12)
+                assert np.linalg.norm(got - ref) <= tol + (1e-12 if fp64 else 1e-6), (fam, b, fp64, i, got, ref)

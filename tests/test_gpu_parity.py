@@ -1,0 +1,206 @@
+"""GPU path against the FP64 oracle, through the C ABI.
+
+Per-record residuals and Jacobians, feature blocks, the reduced right-hand
+side, the diagonal blocks of S, the implicit-Schur product, one LM step and
+the converged cost.  Tolerances: FP64 path 1e-9 (records) / 1e-8 (step);
+mixed path 1e-4 relative per record (residual against max(|r|, 1 px),
+Jacobian block against its Frobenius norm) and per block; converged cost
+1e-6 relative.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from scenegen import make_scene, small_config, scene_counts
+from oracle import lm, model
+from oracle.records import record_keys
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _ba():
+    from paper_2609_04026_amd.binding import BA
+    return BA
+
+
+def _match(keys_gpu, keys_or):
+    og = np.lexsort(keys_gpu.T[::-1])
+    oo = np.lexsort(keys_or.T[::-1])
+    assert np.array_equal(keys_gpu[og], keys_or[oo])
+    return og, oo
+
+
+SCENES = {
+    "tiny_holistic": lambda: make_scene(small_config(n_cams=9, n_points=70, n_lines=20), seed=101),
+    "points_10cam": lambda: make_scene(1),
+    "holistic_30cam": lambda: make_scene(2),
+}
+
+
+@pytest.fixture(scope="module", params=list(SCENES))
+def case(request):
+    print(f"[case] {request.param}", flush=True)
+    s = SCENES[request.param]()
+    prob = lm.Problem(s)
+    st = prob.state0()
+    lin = lm.linearize(prob, st)
+    return request.param, s, prob, st, lin
+
+
+def _block_cols(fam, cd):
+    """Column slices of the exported J: camera | feature | group."""
+    nf = 4 if fam in (2, 4, 5, 7) else 3
+    ng = 3 if fam in (3, 4) else 2 if fam == 5 else 0
+    c = 0 if fam == 5 else cd
+    out = {}
+    if c:
+        out["cam"] = slice(0, c)
+    out["pt" if nf == 3 else "ln"] = slice(c, c + nf)
+    if ng:
+        out["pl" if ng == 3 else "vp"] = slice(c + nf, c + nf + ng)
+    return out
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_records_match_oracle(case, precision):
+    name, s, prob, st, lin = case
+    BA = _ba()
+    ba = BA.from_scene(s, precision=precision)
+    ba.linearize(1e-3)
+    keys_or = record_keys(prob.recs)
+    for fam in range(1, 8):
+        fname = f"R{fam}"
+        n = prob.record_count(fname)
+        assert ba.record_count(fam) == n, fname
+        if n == 0:
+            continue
+        keys, r, J = ba.export_records(fam)
+        og, oo = _match(keys, keys_or[fname][:, 1:])
+        L = lin.fam[fname]
+        rt = L["rt"][oo]
+        rg = r[og]
+        if precision == "fp64":
+            assert np.abs(rg - rt).max() <= 1e-9 * max(1.0, np.abs(rt).max()), fname
+        else:
+            floor = 1e-3 if fam == 5 else 1.0
+            err = np.linalg.norm(rg - rt, axis=1) / np.maximum(np.linalg.norm(rt, axis=1), floor)
+            assert err.max() <= 1e-4, (fname, err.max())
+        for b, sl in _block_cols(fam, prob.camera_dof).items():
+            Jo = L["J"][b][oo]
+            Jg = J[og][:, :, sl]
+            nrm = np.linalg.norm(Jo, axis=(1, 2))
+            err = np.linalg.norm(Jg - Jo, axis=(1, 2))
+            tol = 1e-9 if precision == "fp64" else 1e-4
+            assert np.all(err <= tol * nrm + 1e-9), (fname, b, (err / np.maximum(nrm, 1e-30)).max())
+    ba.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_feature_blocks_and_reduced_system(case, precision):
+    name, s, prob, st, lin = case
+    lam = 1e-3
+    BA = _ba()
+    ba = BA.from_scene(s, precision=precision)
+    ba.linearize(lam)
+    Vp, gp, Vl, gl = ba.export_feature_blocks()
+    Vp_o, Vl_o, _ = lm.feature_blocks(prob, lin)
+    tol = 1e-9 if precision == "fp64" else 1e-4
+    for got, ref in ((Vp, Vp_o), (Vl, Vl_o)):
+        if len(ref):
+            err = np.linalg.norm(got - ref, axis=(1, 2)) / np.maximum(np.linalg.norm(ref, axis=(1, 2)), 1e-30)
+            assert err.max() <= tol, err.max()
+    gf = lin.g[prob.nA:]
+    g_ref = np.concatenate([gp.ravel(), gl.ravel()])
+    assert np.abs(g_ref - gf).max() <= tol * max(np.abs(gf).max(), 1e-30) * 10
+    sys_ = lm.schur(prob, lin, lam)
+    b, Sc, Sp, Sv = ba.export_reduced()
+    assert np.abs(b - sys_["b"]).max() <= tol * 10 * np.abs(sys_["b"]).max()
+    blocks = lm.diag_blocks(prob, sys_["S"])
+    for got, key in ((Sc, "cam"), (Sp, "pl"), (Sv, "vp")):
+        ref = blocks[key]
+        if len(ref):
+            err = np.linalg.norm(got - ref, axis=(1, 2)) / np.linalg.norm(ref, axis=(1, 2))
+            assert err.max() <= tol * 10, (key, err.max())
+    # implicit Schur product against the dense S
+    rng = np.random.default_rng(0)
+    for _ in range(3):
+        x = rng.normal(size=prob.nA)
+        y = ba.schur_matvec(x)
+        ref = sys_["S"] @ x
+        assert np.linalg.norm(y - ref) <= tol * 10 * np.linalg.norm(ref), np.linalg.norm(y - ref) / np.linalg.norm(ref)
+    ba.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_one_lm_step_matches_exact_schur_step(case, precision):
+    name, s, prob, st, lin = case
+    lam = 1e-3
+    BA = _ba()
+    ba = BA.from_scene(s, precision=precision)
+    rep = ba.lm_step(lambda0=lam, pcg_tol=1e-12 if precision == "fp64" else 1e-7, pcg_max_iters=2000)
+    h, _ = lm.solve_schur(prob, lin, lam)
+    E0 = lm.cost(prob, st)[0]
+    E1 = lm.cost(prob, prob.retract(st, h))[0]
+    assert abs(rep["E_before"] - E0) <= 1e-12 * E0
+    tol = 1e-8 if precision == "fp64" else 1e-4
+    assert abs(rep["E_after"] - E1) <= tol * E1, (rep, E1)
+    dL = lm.model_decrease(lin, h)
+    assert abs(rep["model_decrease"] - dL) <= 10 * tol * abs(dL)
+    assert rep["accepted"] == 1
+    ba.close()
+
+
+def _oracle_converged():
+    with open(os.path.join(GOLDEN, "oracle_converged.json")) as f:
+        return json.load(f)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_converged_cost_matches_oracle(case, precision):
+    """The GPU path reaches the oracle's converged cost within 1e-6 relative."""
+    name, s, prob, st, lin = case
+    ref = _oracle_converged()[name]
+    BA = _ba()
+    ba = BA.from_scene(s, precision=precision)
+    out = ba.solve(func_tol=1e-12, max_iters=200, pcg_tol=1e-10 if precision == "fp64" else 1e-8,
+                   pcg_max_iters=2000)
+    print(name, precision, out, ref["E"], flush=True)
+    assert abs(out["E_final"] - ref["E"]) <= 1e-6 * ref["E"], (out["E_final"], ref["E"])
+    ba.close()
+
+
+def test_camera_dof6_and_errors():
+    """camera_dof 6 path, and host-side errors reported through the ABI."""
+    from paper_2609_04026_amd.binding import BA, BAError, BA_E_INVALID, BA_E_STATE
+    s = make_scene(small_config(n_cams=8), seed=5)
+    s["camera_dof"] = 6
+    prob = lm.Problem(s)
+    lin = lm.linearize(prob, prob.state0())
+    ba = BA.from_scene(s, precision="fp64")
+    ba.linearize(1e-3)
+    keys, r, J = ba.export_records(1)
+    og, oo = _match(keys, record_keys(prob.recs)["R1"][:, 1:])
+    assert np.abs(J[og][:, :, :6] - lin.fam["R1"]["J"]["cam"][oo]).max() < 1e-8
+    with pytest.raises(BAError) as e:
+        ba.add_observations(0, [0], [0], np.zeros((1, 4)))
+    assert e.value.status == BA_E_STATE
+    ba.close()
+    # invalid inputs
+    ba = BA(s["cameras"], s["points"], s["lines"], s["planes"], s["vps"], s["cx"], s["cy"])
+    with pytest.raises(BAError) as e:
+        ba.add_observations(0, [0], [len(s["points"])], np.zeros((1, 4)))
+    assert e.value.status == BA_E_INVALID
+    with pytest.raises(BAError) as e:
+        ba.add_observations(0, [0], [0], np.full((1, 4), np.nan))
+    assert e.value.status == BA_E_INVALID
+    ba.add_observations(0, [0, 0], [1, 1], np.zeros((2, 4)) + 300)
+    with pytest.raises(BAError) as e:  # duplicate observation is reported at the first step
+        ba.lm_step()
+    assert e.value.status == BA_E_INVALID
+    ba.close()
+    with pytest.raises(BAError):
+        BA(s["cameras"], s["points"], s["lines"], s["planes"] * 2, s["vps"], s["cx"], s["cy"])
