@@ -104,6 +104,8 @@ typedef struct {
   double lambda0;         /* initial Marquardt lambda (used on the first step only); 1e-4 */
   double nu0;             /* 2 */
   double kappa_max;       /* FP32 feature blocks with estimated condition above it are redone in FP64; 1e4 */
+  int32_t time_kernels;   /* 1: time every implicit-Schur product launch with HIP events
+                             (ba_step_report.matvec_ms / matvec_count); 0 */
 } ba_solve_options;
 
 enum {
@@ -123,6 +125,8 @@ typedef struct {
   int32_t n_fp64_blocks;         /* feature blocks inverted in FP64 */
   int32_t relinearized;          /* 1 if this step evaluated Jacobians */
   double ms[BA_PHASE_COUNT];     /* device time per phase */
+  double matvec_ms;              /* with time_kernels: summed duration of the PCG products */
+  int32_t matvec_count;          /* number of those products */
 } ba_step_report;
 
 typedef struct {

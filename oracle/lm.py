@@ -226,21 +226,29 @@ def damped_feature_inverse(prob, lin, lam):
     return Vinv, (Vp, Vl)
 
 
-def schur(prob, lin, lam):
-    """Reduced system of Sec. 3.1 Eq. 3 over A = cameras + groups.
-
-    S = U_lam - W V_lam^-1 W^T,  b = -g_a + W V_lam^-1 g_f."""
+def schur_terms(prob, lin, lam):
+    """Sparse terms of the reduced system of Sec. 3.1 Eq. 3 over A = cameras
+    + groups: U = J_a^T J_a, W = J_a^T J_f, (V + lam D_f)^-1, the elimination
+    term W V^-1 W^T and b = -g_a + W V^-1 g_f."""
     nA = prob.nA
     Ja = lin.J[:, :nA]
     Jf = lin.J[:, nA:]
-    U = (Ja.T @ Ja).toarray() + lam * np.diag(lin.D[:nA])
+    U = (Ja.T @ Ja).tocsr()
     W = (Ja.T @ Jf).tocsr()
     Vinv, _ = damped_feature_inverse(prob, lin, lam)
     WV = W @ Vinv
-    S = U - (WV @ W.T).toarray()
+    WVW = (WV @ W.T).tocsr()
     ga, gf = lin.g[:nA], lin.g[nA:]
     b = -ga + WV @ gf
-    return dict(S=S, b=b, W=W, Vinv=Vinv, U=U)
+    return dict(U=U, W=W, Vinv=Vinv, WVW=WVW, b=b)
+
+
+def schur(prob, lin, lam):
+    """Reduced system S = U + lam diag(D_a) - W V_lam^-1 W^T (dense) and b."""
+    t = schur_terms(prob, lin, lam)
+    U = t["U"].toarray() + lam * np.diag(lin.D[:prob.nA])
+    S = U - t["WVW"].toarray()
+    return dict(S=S, b=t["b"], W=t["W"], Vinv=t["Vinv"], U=U)
 
 
 def solve_schur(prob, lin, lam):

@@ -13,7 +13,8 @@ from ctypes import POINTER, c_double, c_int32, c_int64, c_size_t, c_void_p
 import numpy as np
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "libba.so")
+# BA_LIB_PATH selects another build of the same library (e.g. a debug build)
+LIB_PATH = os.environ.get("BA_LIB_PATH") or os.path.join(_PKG, "libba.so")
 
 BA_OK, BA_E_INVALID, BA_E_STATE, BA_E_OOM, BA_E_DEVICE, BA_E_NUMERIC, BA_E_NOT_CONVERGED = range(7)
 STATUS_NAMES = ["BA_OK", "BA_E_INVALID", "BA_E_STATE", "BA_E_OOM", "BA_E_DEVICE", "BA_E_NUMERIC",
@@ -44,14 +45,16 @@ class ProblemDesc(ctypes.Structure):
 
 class SolveOptions(ctypes.Structure):
     _fields_ = [("max_iters", c_int32), ("func_tol", c_double), ("grad_tol", c_double), ("pcg_tol", c_double),
-                ("pcg_max_iters", c_int32), ("lambda0", c_double), ("nu0", c_double), ("kappa_max", c_double)]
+                ("pcg_max_iters", c_int32), ("lambda0", c_double), ("nu0", c_double), ("kappa_max", c_double),
+                ("time_kernels", c_int32)]
 
 
 class StepReport(ctypes.Structure):
     _fields_ = [("E_before", c_double), ("E_after", c_double), ("Epix_before", c_double), ("Epix_after", c_double),
                 ("model_decrease", c_double), ("gain_ratio", c_double), ("lambda_", c_double),
                 ("accepted", c_int32), ("pcg_iters", c_int32), ("pcg_rel_residual", c_double),
-                ("n_fp64_blocks", c_int32), ("relinearized", c_int32), ("ms", c_double * 8)]
+                ("n_fp64_blocks", c_int32), ("relinearized", c_int32), ("ms", c_double * 8),
+                ("matvec_ms", c_double), ("matvec_count", c_int32)]
 
 
 class Summary(ctypes.Structure):

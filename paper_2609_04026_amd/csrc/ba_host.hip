@@ -8,6 +8,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <functional>
 #include <numeric>
@@ -160,6 +161,7 @@ struct ba_handle {
   ba_gnn::Net* gnn = nullptr;
   hipEvent_t ev[BA_PHASE_COUNT + 1] = {};
   bool events = false;
+  std::vector<hipEvent_t> mv_ev;  // pool for per-product timing
 };
 
 namespace {
@@ -180,6 +182,12 @@ template <typename V> void upload(ba_handle* h, V* dst, const std::vector<V>& sr
 void sync(ba_handle* h) { HIPCHK(hipStreamSynchronize(h->stream)); }
 
 void set_device(ba_handle* h) { HIPCHK(hipSetDevice(h->device)); }
+
+void check_launch(const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) throw BaError(BA_E_DEVICE, std::string(what) + ": kernel launch failed: " + hipGetErrorString(e));
+}
+
 
 // ---------------------------------------------------------------------------
 // expansion of associations into records (visibility rules of Sec. 3.3-3.4)
@@ -384,6 +392,7 @@ void finalize(ba_handle* h) {
 
   // families
   int64_t max_blocks = 0;
+  std::vector<int32_t> foff_h[NFAM];
   for (int fam = 1; fam < NFAM; ++fam) {
     const auto& v = R[fam];
     const int64_t n = (int64_t)v.size();
@@ -400,10 +409,12 @@ void finalize(ba_handle* h) {
       for (int k = 0; k < 3; ++k) h->keys[fam][(size_t)i * 3 + k] = v[i].key[k];
     }
     for (int f = 0; f < nfeat; ++f) off[f + 1] += off[f];
+    foff_h[fam] = off;
     d.fcam[fam] = A.get<int32_t>(n); d.fgrp[fam] = A.get<int32_t>(n); d.ffeat[fam] = A.get<int32_t>(n);
     d.foff[fam] = A.get<int32_t>(nfeat + 1);
     d.fmeas[fam] = A.get<double>((size_t)n * std::max(mw, 1));
     d.frec[fam] = A.get<char>((size_t)n * slot_stride(fam, h->CD), TS);
+    d.fres[fam] = A.get<char>((size_t)n * fam_rows(fam), TS);
     upload(h, d.fcam[fam], cam); upload(h, d.fgrp[fam], grp); upload(h, d.ffeat[fam], feat);
     upload(h, d.foff[fam], off); upload(h, d.fmeas[fam], meas);
     const int kind = fam == 1 ? BA_OBS_POINT : fam == 2 ? BA_OBS_LINE : fam == 3 ? BA_ASSOC_PLANE_POINT
@@ -485,25 +496,89 @@ void finalize(ba_handle* h) {
   d.gA = A.get<double>(nA); d.DA = A.get<double>(nA); d.bA = A.get<double>(nA);
   d.x = A.get<double>(nA); d.r = A.get<double>(nA); d.z = A.get<double>(nA); d.p = A.get<double>(nA); d.q = A.get<double>(nA);
   d.xT = A.get<char>(nA, TS);
-  // matvec: one workgroup-private copy of the reduced vector in LDS when it fits
+  // product tiles: runs of consecutive features whose records split into at
+  // most MV_MAX_CHUNKS single-family chunks of MV_CHUNK records
+  {
+    std::vector<int4> tiles, chunks;
+    std::vector<int32_t> bigp, bigl;
+    // BA_TILE_CHUNKS (1..16) lowers the chunk capacity of a tile; used by tests
+    // to route features through the large-feature path
+    int max_chunks = MV_MAX_CHUNKS;
+    if (const char* e = std::getenv("BA_TILE_CHUNKS")) max_chunks = std::max(1, std::min(MV_MAX_CHUNKS, std::atoi(e)));
+    auto build = [&](const std::vector<int>& fams, int nfeat, std::vector<int32_t>& big) {
+      int f = 0;
+      while (f < nfeat) {
+        const int fb = f;
+        int64_t cnt[NFAM] = {0};
+        while (f < nfeat && f - fb < MV_MAX_TF) {
+          int need_chunks = 0;
+          int64_t c2[NFAM];
+          for (int fam : fams) {
+            c2[fam] = cnt[fam] + (foff_h[fam][f + 1] - foff_h[fam][f]);
+            need_chunks += (int)((c2[fam] + MV_CHUNK - 1) / MV_CHUNK);
+          }
+          if (need_chunks > max_chunks) break;
+          for (int fam : fams) cnt[fam] = c2[fam];
+          ++f;
+        }
+        if (f == fb) {  // one feature with too many records for a tile
+          big.push_back(f);
+          ++f;
+          continue;
+        }
+        const int cb = (int)chunks.size();
+        for (int fam : fams)
+          for (int64_t r = foff_h[fam][fb]; r < foff_h[fam][f]; r += MV_CHUNK)
+            chunks.push_back(make_int4(fam, (int)r, (int)std::min<int64_t>(MV_CHUNK, foff_h[fam][f] - r), 0));
+        tiles.push_back(make_int4(fb, f, cb, (int)chunks.size() - cb));
+      }
+    };
+    build({1, 3, 6}, h->np, bigp);
+    d.n_ptiles = (int)tiles.size();
+    build({2, 4, 5, 7}, h->nl, bigl);
+    d.n_tiles = (int)tiles.size();
+    d.n_bigp = (int)bigp.size();
+    d.n_bigl = (int)bigl.size();
+    d.tiles = A.get<int4>(tiles.size());
+    d.chunks = A.get<int4>(chunks.size());
+    d.bigp = A.get<int32_t>(bigp.size());
+    d.bigl = A.get<int32_t>(bigl.size());
+    upload(h, d.tiles, tiles);
+    upload(h, d.chunks, chunks);
+    upload(h, d.bigp, bigp);
+    upload(h, d.bigl, bigl);
+  }
+  // the workgroup's copy of the reduced vector (and of the product input) in LDS when they fit
   int ncu = 0;
   HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, h->device));
   const int max_lds = matvec_max_lds_bytes();
-  const size_t need = (size_t)nA * TS;
-  d.mv_lds = need <= (size_t)max_lds ? 1 : 0;
-  const int wg_per_cu = d.mv_lds ? std::max(1, std::min(8, (int)(163840 / std::max<size_t>(need, 1)))) : 8;
-  const int tiles = (h->np + 255) / 256 + (h->nl + 255) / 256;
-  d.n_mv_wg = std::max(1, std::min(ncu * wg_per_cu, std::max(tiles, 1)));
-  d.mv_part = A.get<char>(d.mv_lds ? (size_t)d.n_mv_wg * nA : (size_t)nA, TS);
-  launch_zero(d.mv_part, (d.mv_lds ? (size_t)d.n_mv_wg * nA : (size_t)nA) * TS, h->stream);
+  const size_t base = 8 * 4 * MV_MAX_TF, need = (size_t)nA * 8;
+  d.mv_lds = base + need <= (size_t)max_lds ? 1 : 0;
+  d.mv_stage_x = 0;  // two workgroups per CU share the LDS; the input is read through the caches
+  const size_t lds_bytes = matvec_lds_bytes(d);
+  const int wg_per_cu = (int)std::max<size_t>(1, std::min<size_t>(2, 163840 / std::max<size_t>(lds_bytes, 1)));
+  d.n_mv_wg = std::max(1, std::min(ncu * wg_per_cu, d.n_tiles + (d.n_bigp + d.n_bigl + MV_THREADS - 1) / MV_THREADS));
+  d.mv_part = A.get<double>(d.mv_lds ? (size_t)d.n_mv_wg * nA : (size_t)nA);
+  d.cnt = A.get<unsigned int>(4);
+  launch_zero(d.cnt, 4 * sizeof(unsigned int), h->stream);
+  d.part2 = A.get<double>(2 * ((size_t)nA / 64 + 2) + 256);
+  launch_zero(d.mv_part, (d.mv_lds ? (size_t)d.n_mv_wg * nA : (size_t)nA) * sizeof(double), h->stream);
   d.scal = A.get<double>(SC_COUNT);
   launch_zero(d.scal, SC_COUNT * sizeof(double), h->stream);
   const int64_t fe_blocks = (h->np + 255) / 256 + (h->nl + 255) / 256;
   d.red = A.get<double>((size_t)std::max<int64_t>(2 * std::max(max_blocks, fe_blocks), 64));
   HIPCHK(hipHostMalloc((void**)&h->hscal, SC_COUNT * sizeof(double), hipHostMallocDefault));
   if (h->gnn) ba_gnn::attach(h->gnn, h->d, h->stream);
+  check_launch("finalize");
   sync(h);
   h->finalized = true;
+  if (std::getenv("BA_VERBOSE")) {
+    std::fprintf(stderr, "[libba] records:");
+    for (int fam = 1; fam < NFAM; ++fam) std::fprintf(stderr, " R%d=%lld", fam, (long long)d.fn[fam]);
+    std::fprintf(stderr, "; nA=%d; product: %s%s, %d workgroups, %d tiles (%d point), %d+%d large features, LDS %zu of %d B\n",
+                 nA, d.mv_lds ? "LDS-private y" : "global atomics", d.mv_stage_x ? " + LDS x" : "", d.n_mv_wg, d.n_tiles,
+                 d.n_ptiles, d.n_bigp, d.n_bigl, lds_bytes, max_lds);
+  }
   h->need_lin = true;
 }
 
@@ -517,6 +592,7 @@ void linearize_all(ba_handle* h) {
   launch_linearize(h->d, h->stream);
   launch_feature_accum(h->d, h->stream);
   launch_camera_pass_a(h->d, h->stream);
+  check_launch("linearize");
   h->need_lin = false;
 }
 
@@ -526,19 +602,50 @@ void assemble(ba_handle* h, double lambda, double kappa_max) {
   launch_camera_pass_b(h->d, lambda, h->stream);
   launch_precond_blockjacobi(h->d, h->stream);
   if (h->precond == BA_PC_LEARNED && h->gnn && ba_gnn::ready(h->gnn)) ba_gnn::apply(h->gnn, h->d, lambda, h->stream);
+  check_launch("assemble");
   h->last_lambda = lambda;
 }
 
-// returns iterations done
-int pcg(ba_handle* h, double lambda, double tol, int maxit) {
+// returns iterations done; with mv_ms, times every product launch with events
+int pcg(ba_handle* h, double lambda, double tol, int maxit, double* mv_ms = nullptr) {
+  if (h->d.nA == 0) {
+    for (int k = 0; k < SC_COUNT; ++k) h->hscal[k] = 0;
+    if (mv_ms) *mv_ms = 0;
+    return 0;
+  }
   launch_pcg_init(h->d, tol, maxit, h->stream);
   int launched = 0;
   for (;;) {
-    for (int k = 0; k < PCG_CHECK_EVERY && launched < maxit; ++k, ++launched) launch_pcg_iteration(h->d, lambda, h->stream);
+    for (int k = 0; k < PCG_CHECK_EVERY && launched < maxit; ++k, ++launched) {
+      if (mv_ms) {
+        while (h->mv_ev.size() < 2 * (size_t)(launched + 1)) {
+          hipEvent_t e;
+          HIPCHK(hipEventCreate(&e));
+          h->mv_ev.push_back(e);
+        }
+        HIPCHK(hipEventRecord(h->mv_ev[2 * launched], h->stream));
+      }
+      launch_pcg_product(h->d, h->stream);
+      if (mv_ms) HIPCHK(hipEventRecord(h->mv_ev[2 * launched + 1], h->stream));
+      launch_pcg_update(h->d, lambda, launched, h->stream);
+    }
+    check_launch("pcg");
     read_scal(h);
     if (h->hscal[SC_DONE] != 0.0 || launched >= maxit) break;
   }
-  return (int)h->hscal[SC_ITER];
+  const int iters = (int)h->hscal[SC_ITER];
+  if (mv_ms) {
+    // the products of the iterations that ran (later launches exit at once)
+    double t = 0;
+    const int real = std::min(launched, iters + (h->hscal[SC_BREAK] != 0.0 ? 1 : 0));
+    for (int k = 0; k < real; ++k) {
+      float ms = 0;
+      HIPCHK(hipEventElapsedTime(&ms, h->mv_ev[2 * k], h->mv_ev[2 * k + 1]));
+      t += ms;
+    }
+    *mv_ms = t;
+  }
+  return iters;
 }
 
 void record(ba_handle* h, int phase) {
@@ -662,7 +769,10 @@ void do_step(ba_handle* h, const ba_solve_options& o, ba_step_report* rep) {
   record(h, 1);
   assemble(h, h->lambda, o.kappa_max);
   record(h, 3);
-  r.pcg_iters = pcg(h, h->lambda, o.pcg_tol, o.pcg_max_iters);
+  double mv_ms = 0;
+  r.pcg_iters = pcg(h, h->lambda, o.pcg_tol, o.pcg_max_iters, o.time_kernels ? &mv_ms : nullptr);
+  r.matvec_ms = mv_ms;
+  r.matvec_count = o.time_kernels ? r.pcg_iters + (h->hscal[SC_BREAK] != 0.0 ? 1 : 0) : 0;
   record(h, 4);
   const double rr = h->hscal[SC_RR], bb = h->hscal[SC_BB];
   r.pcg_rel_residual = bb > 0 ? std::sqrt(rr / bb) : 0.0;
@@ -672,6 +782,7 @@ void do_step(ba_handle* h, const ba_solve_options& o, ba_step_report* rep) {
   launch_retract(h->d, h->stream);
   launch_cost(h->d, true, h->stream);
   record(h, 6);
+  check_launch("backsub / retract / cost");
   read_scal(h);
   const double En = h->hscal[SC_E], Epn = h->hscal[SC_EPIX];
   const double dL = -h->hscal[SC_GH] - 0.5 * h->hscal[SC_JH2];
@@ -728,6 +839,7 @@ void ba_default_options(ba_solve_options* o) {
   o->lambda0 = 1e-4;
   o->nu0 = 2.0;
   o->kappa_max = 1e4;
+  o->time_kernels = 0;
 }
 
 ba_status ba_create(const ba_problem_desc* desc, ba_handle** out) {
@@ -967,22 +1079,28 @@ ba_status ba_export_records(const ba_handle* hc, int32_t fam, int64_t* keys, dou
     const int stride = slot_stride(fam, h->CD), rows = fam_rows(fam);
     const int nc = slot_nc(fam, h->CD), ng = slot_ng(fam), nf = slot_nf(fam);
     const int ncol = (fam == 5 ? 0 : h->CD) + nf + ng;
-    std::vector<double> buf((size_t)n * stride);
     set_device(h);
-    if (h->d.fp64) {
-      if (n) HIPCHK(hipMemcpyAsync(buf.data(), h->d.frec[fam], buf.size() * 8, hipMemcpyDeviceToHost, h->stream));
-      sync(h);
-    } else {
-      std::vector<float> fb((size_t)n * stride);
-      if (n) HIPCHK(hipMemcpyAsync(fb.data(), h->d.frec[fam], fb.size() * 4, hipMemcpyDeviceToHost, h->stream));
-      sync(h);
-      std::copy(fb.begin(), fb.end(), buf.begin());
-    }
-    const int OC = rows, OG = OC + rows * nc, OF = OG + rows * ng;
+    auto fetch = [&](const void* src, size_t cnt) {
+      std::vector<double> out(cnt);
+      if (!cnt) return out;
+      if (h->d.fp64) {
+        HIPCHK(hipMemcpyAsync(out.data(), src, cnt * 8, hipMemcpyDeviceToHost, h->stream));
+        sync(h);
+      } else {
+        std::vector<float> fb(cnt);
+        HIPCHK(hipMemcpyAsync(fb.data(), src, cnt * 4, hipMemcpyDeviceToHost, h->stream));
+        sync(h);
+        std::copy(fb.begin(), fb.end(), out.begin());
+      }
+      return out;
+    };
+    const std::vector<double> buf = fetch(h->d.frec[fam], (size_t)n * stride);
+    const std::vector<double> res = fetch(h->d.fres[fam], (size_t)n * rows);
+    const int OC = 0, OG = OC + rows * nc, OF = OG + rows * ng;
     for (int64_t i = 0; i < n; ++i) {
       const double* s = &buf[(size_t)i * stride];
       for (int row = 0; row < rows; ++row) {
-        if (r) r[(size_t)i * rows + row] = s[row];
+        if (r) r[(size_t)i * rows + row] = res[(size_t)i * rows + row];
         if (J) {
           double* o = J + ((size_t)i * rows + row) * ncol;
           int col = 0;
@@ -1112,6 +1230,7 @@ void ba_destroy(ba_handle* h) {
   if (h->hscal) (void)hipHostFree(h->hscal);
   if (h->events)
     for (int k = 0; k <= BA_PHASE_COUNT; ++k) (void)hipEventDestroy(h->ev[k]);
+  for (hipEvent_t e : h->mv_ev) (void)hipEventDestroy(e);
   if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
   delete h;
 }

@@ -1,9 +1,9 @@
 // Device-side layout of one holistic BA problem and the kernel launchers.
 //
 // Records of each residual family are stored feature-major (sorted by the
-// internal feature id, then camera), one array-of-structures slot per
-// record holding the IRLS-weighted residual and Jacobian blocks:
-//   [ r (ROWS) | J_cam (ROWS x NC) | J_group (ROWS x NG) | J_feature (ROWS x NF) | pad ]
+// internal feature id, then camera): one array-of-structures slot per record
+// with its IRLS-weighted Jacobian blocks, and its weighted residual in a
+// separate array (the Schur product reads only the Jacobians).
 // Camera-side reductions walk camera-major index lists into those arrays;
 // feature-side reductions walk the feature CSR offsets.
 #pragma once
@@ -26,10 +26,12 @@ template <int CD> struct Fam<5, CD> { static constexpr int ROWS = 3, NC = 0, NG 
 template <int CD> struct Fam<6, CD> { static constexpr int ROWS = 1, NC = CamCols<CD>::PT, NG = 0, NF = 3, MEAS = 3, GT = 0, FT = 0; };
 template <int CD> struct Fam<7, CD> { static constexpr int ROWS = 1, NC = CamCols<CD>::LN, NG = 0, NF = 4, MEAS = 2, GT = 0, FT = 1; };
 
+// Jacobian slot of one record: [ J_cam (ROWS x NC) | J_group (ROWS x NG) | J_feature (ROWS x NF) | pad ];
+// the weighted residual lives in a separate ROWS-wide array
 template <int FAM, int CD> struct Slot {
   using F = Fam<FAM, CD>;
   static constexpr int ROWS = F::ROWS, NC = F::NC, NG = F::NG, NF = F::NF;
-  static constexpr int OR = 0, OC = ROWS, OG = OC + ROWS * NC, OF = OG + ROWS * NG;
+  static constexpr int OC = 0, OG = OC + ROWS * NC, OF = OG + ROWS * NG;
   static constexpr int USED = OF + ROWS * NF;
   static constexpr int STRIDE = (USED + 3) / 4 * 4;
 };
@@ -56,7 +58,8 @@ struct Dev {
   int64_t fn[NFAM] = {0};
   int32_t *fcam[NFAM] = {nullptr}, *fgrp[NFAM] = {nullptr}, *ffeat[NFAM] = {nullptr}, *foff[NFAM] = {nullptr};
   double *fmeas[NFAM] = {nullptr};
-  void *frec[NFAM] = {nullptr};
+  void *frec[NFAM] = {nullptr};   // Jacobian slots (T)
+  void *fres[NFAM] = {nullptr};   // weighted residuals (T), n x ROWS
   int lkind[NFAM] = {0};
   double lscale[NFAM] = {0}, lweight[NFAM] = {0};
   // camera-major lists
@@ -81,19 +84,36 @@ struct Dev {
   // PCG (double vectors of length nA) and matvec partials (T)
   double *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
   void *xT = nullptr;       // matvec input in T
-  void *mv_part = nullptr;  // n_mv_wg x nA partial sums (LDS mode) or nA accumulator (global mode)
+  double *mv_part = nullptr;  // n_mv_wg x nA partial sums (LDS mode) or nA accumulator (global mode)
   double *scal = nullptr;   // device scalars, see PcgScal
   double *red = nullptr;    // reduction partials
   int n_mv_wg = 0;          // matvec workgroups (partials rows)
   int mv_lds = 0;           // 1: accumulate in LDS
-  int mv_tile = 256;
+  int mv_stage_x = 0;       // 1: the product input is staged in LDS as well
+  // feature-aligned tiles of the product: int4 (feat_begin, feat_end, chunk_begin, n_chunks),
+  // point tiles first, then line tiles; chunks int4 (family, record_begin, record_count, 0)
+  int n_tiles = 0, n_ptiles = 0;
+  int4 *tiles = nullptr, *chunks = nullptr;
+  // features too large for one tile (handled one lane per feature)
+  int n_bigp = 0, n_bigl = 0;
+  int32_t *bigp = nullptr, *bigl = nullptr;
+  unsigned int *cnt = nullptr;  // grid-wide "last workgroup" counters (zeroed, self-resetting)
+  double *part2 = nullptr;      // per-workgroup partial dot products of the PCG kernels
 };
+
+// product tiles: one 1024-thread workgroup; one 64-lane wavefront per chunk of
+// at most 64 records of one family; at most MV_MAX_TF features per tile
+// (per-workgroup sums are accumulated in FP64 in LDS: FP32 LDS atomics are slow on gfx950)
+constexpr int MV_THREADS = 1024, MV_CHUNK = 64, MV_MAX_CHUNKS = MV_THREADS / MV_CHUNK, MV_MAX_TF = 120;
 
 // indices into Dev::scal
 enum PcgScal {
   SC_RZ = 0, SC_BB, SC_RR, SC_PQ, SC_ALPHA, SC_BETA, SC_DONE, SC_ITER, SC_TOL2, SC_LAMBDA,
-  SC_GH, SC_JH2, SC_E, SC_EPIX, SC_NFLAG, SC_MAXIT, SC_BREAK, SC_COUNT = 32
+  SC_GH, SC_JH2, SC_E, SC_EPIX, SC_NFLAG, SC_MAXIT, SC_BREAK,
+  // PCG accumulators, three sets rotated by iteration (k mod 3): p.q, r.r, r.z
+  SC_ACC = 20, SC_COUNT = 32
 };
+constexpr int ACC_PQ = 0, ACC_RR = 1, ACC_RZ = 2, ACC_STRIDE = 4;
 
 // ---- launchers (ba_kernels.hip) --------------------------------------------
 void launch_cast_params(const Dev& d, bool candidate, hipStream_t s);
@@ -105,11 +125,13 @@ void launch_feature_invert(const Dev& d, double lambda, double kappa_max, hipStr
 void launch_camera_pass_b(const Dev& d, double lambda, hipStream_t s);   // S diag blocks, b
 void launch_precond_blockjacobi(const Dev& d, hipStream_t s);           // M = blockdiag(S)^-1
 void launch_pcg_init(const Dev& d, double tol, int max_iters, hipStream_t s);
-void launch_pcg_iteration(const Dev& d, double lambda, hipStream_t s);
+void launch_pcg_product(const Dev& d, hipStream_t s);                  // q' = partial J_a^T(...) products
+void launch_pcg_update(const Dev& d, double lambda, int iter, hipStream_t s);  // q = S p, then the CG update
 void launch_schur_matvec(const Dev& d, const double* xin, double* yout, double lambda, hipStream_t s);
 void launch_backsub(const Dev& d, hipStream_t s);                        // h_f, model decrease terms
 void launch_retract(const Dev& d, hipStream_t s);                        // candidate = current [+] h
 void launch_zero(void* p, size_t bytes, hipStream_t s);
 int matvec_max_lds_bytes();
+size_t matvec_lds_bytes(const Dev& d);
 
 }  // namespace ba

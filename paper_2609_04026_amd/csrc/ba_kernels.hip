@@ -15,6 +15,7 @@
 //   cost      one lane per record: FP64 residuals and robust cost
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 
@@ -243,7 +244,7 @@ template <int FAM, typename T, int CD> __global__ __launch_bounds__(256) void k_
   T v[SL::STRIDE];
 #pragma unroll
   for (int k = 0; k < SL::STRIDE; ++k) v[k] = 0;
-  T* r = v + SL::OR;
+  T r[F::ROWS];
   T* Jc = v + SL::OC;
   T* Jg = v + SL::OG;
   T* Jf = v + SL::OF;
@@ -304,11 +305,12 @@ template <int FAM, typename T, int CD> __global__ __launch_bounds__(256) void k_
   double rho, drho;
   loss_eval<double>(d.lkind[FAM], d.lscale[FAM], s, rho, drho);
   const double ws = sqrt(d.lweight[FAM] * drho);
+  T* ro = ((T*)d.fres[FAM]) + i * F::ROWS;
 #pragma unroll
-  for (int k = 0; k < F::ROWS; ++k) r[k] = (T)(ws * r64[k]);
+  for (int k = 0; k < F::ROWS; ++k) ro[k] = (T)(ws * r64[k]);
   const T wsT = (T)ws;
 #pragma unroll
-  for (int k = SL::OC; k < SL::USED; ++k) v[k] *= wsT;
+  for (int k = 0; k < SL::USED; ++k) v[k] *= wsT;
   store_vec(((T*)d.frec[FAM]) + i * SL::STRIDE, v);
 }
 
@@ -394,13 +396,14 @@ __device__ __forceinline__ void acc_feature(const Dev& d, int f, A (&V)[NF * (NF
   if (!d.fn[FAM]) return;
   const int64_t b = d.foff[FAM][f], e = d.foff[FAM][f + 1];
   const T* rec = (const T*)d.frec[FAM];
+  const T* res = (const T*)d.fres[FAM];
   for (int64_t i = b; i < e; ++i) {
     T v[SL::STRIDE];
     load_vec(rec + i * SL::STRIDE, v);
 #pragma unroll
     for (int row = 0; row < SL::ROWS; ++row) {
       const T* jf = v + SL::OF + row * NF;
-      const A rr = (A)v[SL::OR + row];
+      const A rr = (A)res[i * SL::ROWS + row];
 #pragma unroll
       for (int a = 0; a < NF; ++a) {
         g[a] += (A)jf[a] * rr;
@@ -613,10 +616,11 @@ template <int FAM, typename T, int CD> __device__ __forceinline__ void cam_a_rec
   using SL = Slot<FAM, CD>;
   T v[SL::STRIDE];
   load_vec(((const T*)d.frec[FAM]) + i * SL::STRIDE, v);
+  const T* res = ((const T*)d.fres[FAM]) + i * SL::ROWS;
 #pragma unroll
   for (int row = 0; row < SL::ROWS; ++row) {
     const T* jc = v + SL::OC + row * SL::NC;
-    const T rr = v[SL::OR + row];
+    const T rr = res[row];
 #pragma unroll
     for (int a = 0; a < SL::NC; ++a) {
       g[a] += jc[a] * rr;
@@ -685,10 +689,11 @@ template <int FAM, typename T, int CD, int NG> __device__ __forceinline__ void g
   using SL = Slot<FAM, CD>;
   T v[SL::STRIDE];
   load_vec(((const T*)d.frec[FAM]) + i * SL::STRIDE, v);
+  const T* res = ((const T*)d.fres[FAM]) + i * SL::ROWS;
 #pragma unroll
   for (int row = 0; row < SL::ROWS; ++row) {
     const T* jg = v + SL::OG + row * NG;
-    const T rr = v[SL::OR + row];
+    const T rr = res[row];
 #pragma unroll
     for (int a = 0; a < NG; ++a) {
       g[a] += jg[a] * rr;
@@ -988,118 +993,6 @@ void launch_precond_blockjacobi(const Dev& d, hipStream_t s) {
   else k_precond_bj<6><<<nblk(n, 64), 64, 0, s>>>(d);
 }
 
-// z = M r over all blocks (called by a single workgroup)
-template <int CD> __device__ __forceinline__ void apply_M(const Dev& d, const double* r, double* z) {
-  const int nb = d.nc + d.ng + d.nv;
-  for (int i = threadIdx.x; i < nb; i += blockDim.x) {
-    if (i < d.nc) {
-      const double* M = d.Mcam + (int64_t)CD * CD * i;
-      const double* ri = r + CD * i;
-      double* zi = z + CD * i;
-#pragma unroll
-      for (int a = 0; a < CD; ++a) {
-        double t = 0;
-#pragma unroll
-        for (int b = 0; b < CD; ++b) t += M[a * CD + b] * ri[b];
-        zi[a] = t;
-      }
-    } else if (i < d.nc + d.ng) {
-      const int g = i - d.nc;
-      const double* M = d.Mpl + 9 * g;
-      const double* ri = r + d.offPl + 3 * g;
-      double* zi = z + d.offPl + 3 * g;
-#pragma unroll
-      for (int a = 0; a < 3; ++a) zi[a] = M[3 * a] * ri[0] + M[3 * a + 1] * ri[1] + M[3 * a + 2] * ri[2];
-    } else {
-      const int v = i - d.nc - d.ng;
-      const double* M = d.Mvp + 4 * v;
-      const double* ri = r + d.offVp + 2 * v;
-      double* zi = z + d.offVp + 2 * v;
-      zi[0] = M[0] * ri[0] + M[1] * ri[1];
-      zi[1] = M[2] * ri[0] + M[3] * ri[1];
-    }
-  }
-}
-
-// ---------------------------------------------------------------------------
-// PCG on S x = b, x0 = 0; all vector work in FP64 inside one workgroup
-template <typename T, int CD> __global__ __launch_bounds__(1024) void k_pcg_init(Dev d, double tol, int maxit) {
-  __shared__ double lds[2 * 17];
-  const int n = d.nA;
-  for (int k = threadIdx.x; k < n; k += blockDim.x) { d.x[k] = 0; d.r[k] = d.bA[k]; }
-  __syncthreads();
-  apply_M<CD>(d, d.r, d.z);
-  __syncthreads();
-  double v[2] = {0, 0};
-  for (int k = threadIdx.x; k < n; k += blockDim.x) {
-    d.p[k] = d.z[k];
-    ((T*)d.xT)[k] = (T)d.z[k];
-    v[0] += d.r[k] * d.z[k];
-    v[1] += d.r[k] * d.r[k];
-  }
-  double* o = block_sum_arr<double, 2>(v, lds);
-  if (threadIdx.x == 0) {
-    d.scal[SC_RZ] = o[0];
-    d.scal[SC_BB] = o[1];
-    d.scal[SC_RR] = o[1];
-    d.scal[SC_TOL2] = tol * tol * o[1];
-    d.scal[SC_ITER] = 0;
-    d.scal[SC_MAXIT] = maxit;
-    d.scal[SC_BREAK] = 0;
-    d.scal[SC_DONE] = (o[1] == 0.0 || maxit <= 0 || !isfinite(o[1])) ? 1.0 : 0.0;
-  }
-}
-
-template <typename T, int CD> __global__ __launch_bounds__(1024) void k_pcg_update(Dev d) {
-  __shared__ double lds[2 * 17];
-  __shared__ double sh[4];
-  if (d.scal[SC_DONE] != 0.0) return;
-  const int n = d.nA;
-  double v1[1] = {0};
-  for (int k = threadIdx.x; k < n; k += blockDim.x) v1[0] += d.p[k] * d.q[k];
-  double* o = block_sum_arr<double, 1>(v1, lds);
-  const double pq = o[0];
-  if (!(pq > 0.0) || !isfinite(pq)) {
-    if (threadIdx.x == 0) { d.scal[SC_DONE] = 1.0; d.scal[SC_BREAK] = 1.0; }
-    return;
-  }
-  const double alpha = d.scal[SC_RZ] / pq;
-  double v[1] = {0};
-  for (int k = threadIdx.x; k < n; k += blockDim.x) {
-    d.x[k] += alpha * d.p[k];
-    const double rk = d.r[k] - alpha * d.q[k];
-    d.r[k] = rk;
-    v[0] += rk * rk;
-  }
-  o = block_sum_arr<double, 1>(v, lds);
-  const double rr = o[0];
-  const double iter = d.scal[SC_ITER] + 1.0;
-  const bool done = rr <= d.scal[SC_TOL2] || iter >= d.scal[SC_MAXIT];
-  if (threadIdx.x == 0) { sh[0] = rr; }
-  apply_M<CD>(d, d.r, d.z);
-  __syncthreads();
-  double w[1] = {0};
-  for (int k = threadIdx.x; k < n; k += blockDim.x) w[0] += d.r[k] * d.z[k];
-  o = block_sum_arr<double, 1>(w, lds);
-  const double rz = o[0];
-  const double beta = rz / d.scal[SC_RZ];
-  for (int k = threadIdx.x; k < n; k += blockDim.x) {
-    const double pk = d.z[k] + beta * d.p[k];
-    d.p[k] = pk;
-    ((T*)d.xT)[k] = (T)pk;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    d.scal[SC_RR] = rr;
-    d.scal[SC_RZ] = rz;
-    d.scal[SC_ALPHA] = alpha;
-    d.scal[SC_BETA] = beta;
-    d.scal[SC_PQ] = pq;
-    d.scal[SC_ITER] = iter;
-    if (done) d.scal[SC_DONE] = 1.0;
-  }
-}
-
 // ---------------------------------------------------------------------------
 // implicit-Schur product y = J_a^T (J_a x - J_f V^-1 J_f^T J_a x) (+ lambda D_a x
 // in the reduction), one lane per feature
@@ -1136,7 +1029,7 @@ template <int FAM, typename T, int CD, int NF> __device__ __forceinline__ void m
   }
 }
 
-template <int FAM, typename T, int CD, int NF> __device__ __forceinline__ void mv_second(const Dev& d, int f, const T* x, const T (&s)[NF], T* y) {
+template <int FAM, typename T, int CD, int NF> __device__ __forceinline__ void mv_second(const Dev& d, int f, const T* x, const T (&s)[NF], double* y) {
   using SL = Slot<FAM, CD>;
   using F = Fam<FAM, CD>;
   if (!d.fn[FAM]) return;
@@ -1177,13 +1070,13 @@ template <int FAM, typename T, int CD, int NF> __device__ __forceinline__ void m
       for (int k = 0; k < SL::NG; ++k) zg[k] += v[SL::OG + row * SL::NG + k] * t;
     }
 #pragma unroll
-    for (int k = 0; k < SL::NC; ++k) atomicAdd(y + ac + k, zc[k]);
+    for (int k = 0; k < SL::NC; ++k) atomicAdd(y + ac + k, (double)zc[k]);
 #pragma unroll
-    for (int k = 0; k < SL::NG; ++k) atomicAdd(y + ag + k, zg[k]);
+    for (int k = 0; k < SL::NG; ++k) atomicAdd(y + ag + k, (double)zg[k]);
   }
 }
 
-template <typename T, int CD, int NF> __device__ __forceinline__ void mv_feature(const Dev& d, int f, const T* x, T* y) {
+template <typename T, int CD, int NF> __device__ __forceinline__ void mv_feature(const Dev& d, int f, const T* x, double* y) {
   T q[NF];
 #pragma unroll
   for (int k = 0; k < NF; ++k) q[k] = 0;
@@ -1211,52 +1104,250 @@ template <typename T, int CD, int NF> __device__ __forceinline__ void mv_feature
   }
 }
 
-// LDS mode: each workgroup accumulates into its own copy of y in LDS and
-// writes it to its row of the partial buffer.  Global mode: atomics into
-// the nA accumulator.
-template <typename T, int CD, bool LDS> __global__ __launch_bounds__(256) void k_matvec(Dev d, const double* done) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  if (done && *done != 0.0) return;
-  const T* x = (const T*)d.xT;
-  T* y;
-  if constexpr (LDS) {
-    y = reinterpret_cast<T*>(smem_raw);
-    for (int k = threadIdx.x; k < d.nA; k += blockDim.x) y[k] = 0;
-    __syncthreads();
+// ---------------------------------------------------------------------------
+// Tiled implicit-Schur product.  A tile is a run of consecutive features
+// (<= MV_MAX_TF) whose records (<= 1024) are split into single-family chunks
+// of <= 64 records; wavefront w of the 1024-thread workgroup takes chunk w,
+// one record per lane, and keeps that record's Jacobian in registers across
+// the tile's three phases:
+//   A  t = J_a x;  q_f += J_f^T t          (LDS atomics, per tile feature)
+//   B  s_f = (V_f + lambda D_f)^-1 q_f      (one thread per tile feature)
+//   C  u = t - J_f s_f;  y_a += J_a^T u     (LDS atomics into the workgroup's y)
+// The workgroup's y (and, when it fits, the input x) live in LDS; each
+// workgroup writes its y to its row of the partial buffer.
+template <int CD> struct MaxSlot { static constexpr int V = Slot<4, CD>::STRIDE; };
+
+template <int FAM, typename T, int CD>
+__device__ __forceinline__ void tile_phase_a(const Dev& d, int64_t i, const T* x, T (&qv)[4], int fb, T (&v)[MaxSlot<CD>::V],
+                                             T (&t)[4], int& ac, int& ag, int& lf) {
+  using SL = Slot<FAM, CD>;
+  using F = Fam<FAM, CD>;
+  const T* rec = (const T*)d.frec[FAM] + i * SL::STRIDE;
+  if constexpr (sizeof(T) == 4) {
+    const float4* q4 = reinterpret_cast<const float4*>(rec);
+#pragma unroll
+    for (int k = 0; k < SL::STRIDE / 4; ++k) {
+      float4 a = q4[k];
+      v[4 * k] = a.x; v[4 * k + 1] = a.y; v[4 * k + 2] = a.z; v[4 * k + 3] = a.w;
+    }
   } else {
-    y = (T*)d.mv_part;
-  }
-  const int tp = (d.np + blockDim.x - 1) / blockDim.x, tl = (d.nl + blockDim.x - 1) / blockDim.x;
-  for (int tile = blockIdx.x; tile < tp + tl; tile += gridDim.x) {
-    if (tile < tp) {
-      const int f = tile * blockDim.x + threadIdx.x;
-      if (f < d.np) mv_feature<T, CD, 3>(d, f, x, y);
-    } else {
-      const int f = (tile - tp) * blockDim.x + threadIdx.x;
-      if (f < d.nl) mv_feature<T, CD, 4>(d, f, x, y);
+    const double2* q2 = reinterpret_cast<const double2*>(rec);
+#pragma unroll
+    for (int k = 0; k < SL::STRIDE / 2; ++k) {
+      double2 a = q2[k];
+      v[2 * k] = a.x; v[2 * k + 1] = a.y;
     }
   }
-  if constexpr (LDS) {
-    __syncthreads();
-    T* out = (T*)d.mv_part + (int64_t)blockIdx.x * d.nA;
-    for (int k = threadIdx.x; k < d.nA; k += blockDim.x) out[k] = y[k];
+  lf = d.ffeat[FAM][i] - fb;
+  if constexpr (SL::NC > 0) ac = CD * d.fcam[FAM][i];
+  if constexpr (SL::NG > 0) ag = a_grp(d, F::GT, d.fgrp[FAM][i]);
+  T xc[SL::NC > 0 ? SL::NC : 1], xg[SL::NG > 0 ? SL::NG : 1];
+#pragma unroll
+  for (int k = 0; k < SL::NC; ++k) xc[k] = x[ac + k];
+#pragma unroll
+  for (int k = 0; k < SL::NG; ++k) xg[k] = x[ag + k];
+#pragma unroll
+  for (int row = 0; row < SL::ROWS; ++row) {
+    T tt = 0;
+#pragma unroll
+    for (int k = 0; k < SL::NC; ++k) tt += v[SL::OC + row * SL::NC + k] * xc[k];
+#pragma unroll
+    for (int k = 0; k < SL::NG; ++k) tt += v[SL::OG + row * SL::NG + k] * xg[k];
+    t[row] = tt;
+  }
+#pragma unroll
+  for (int a = 0; a < SL::NF; ++a) {
+    T qa = 0;
+#pragma unroll
+    for (int row = 0; row < SL::ROWS; ++row) qa += v[SL::OF + row * SL::NF + a] * t[row];
+    qv[a] = qa;
   }
 }
 
-// y = sum of partials + lambda D_a x ; in global mode also re-zeroes the accumulator
-template <typename T> __global__ __launch_bounds__(256) void k_mv_reduce(Dev d, const double* done, const double* xin, double* y, double lam) {
-  if (done && *done != 0.0) return;
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= d.nA) return;
-  T* part = (T*)d.mv_part;
-  double s = 0;
-  if (d.mv_lds) {
-    for (int w = 0; w < d.n_mv_wg; ++w) s += (double)part[(int64_t)w * d.nA + k];
-  } else {
-    s = (double)part[k];
-    part[k] = 0;
+template <int FAM, typename T, int CD>
+__device__ __forceinline__ void tile_phase_c(const T (&v)[MaxSlot<CD>::V], const T (&t)[4], int ac, int ag, int lf,
+                                             const double* qs, double* y);
+
+// FP64 records are reloaded for phase C instead of being held across the barriers
+template <int FAM, typename T, int CD>
+__device__ __forceinline__ void tile_phase_c_reload(const Dev& d, int64_t i, const T (&t)[4], int ac, int ag, int lf,
+                                                    const double* qs, double* y) {
+  using SL = Slot<FAM, CD>;
+  T v[MaxSlot<CD>::V];
+  const double2* q2 = reinterpret_cast<const double2*>((const T*)d.frec[FAM] + i * SL::STRIDE);
+#pragma unroll
+  for (int k = 0; k < SL::STRIDE / 2; ++k) {
+    double2 a = q2[k];
+    v[2 * k] = a.x; v[2 * k + 1] = a.y;
   }
-  y[k] = s + lam * d.DA[k] * xin[k];
+  tile_phase_c<FAM, T, CD>(v, t, ac, ag, lf, qs, y);
+}
+
+template <int FAM, typename T, int CD>
+__device__ __forceinline__ void tile_phase_c(const T (&v)[MaxSlot<CD>::V], const T (&t)[4], int ac, int ag, int lf,
+                                             const double* qs, double* y) {
+  using SL = Slot<FAM, CD>;
+  T sv[SL::NF];
+#pragma unroll
+  for (int a = 0; a < SL::NF; ++a) sv[a] = (T)qs[4 * lf + a];
+  T zc[SL::NC > 0 ? SL::NC : 1], zg[SL::NG > 0 ? SL::NG : 1];
+#pragma unroll
+  for (int k = 0; k < SL::NC; ++k) zc[k] = 0;
+#pragma unroll
+  for (int k = 0; k < SL::NG; ++k) zg[k] = 0;
+#pragma unroll
+  for (int row = 0; row < SL::ROWS; ++row) {
+    T u = t[row];
+#pragma unroll
+    for (int a = 0; a < SL::NF; ++a) u -= v[SL::OF + row * SL::NF + a] * sv[a];
+#pragma unroll
+    for (int k = 0; k < SL::NC; ++k) zc[k] += v[SL::OC + row * SL::NC + k] * u;
+#pragma unroll
+    for (int k = 0; k < SL::NG; ++k) zg[k] += v[SL::OG + row * SL::NG + k] * u;
+  }
+#pragma unroll
+  for (int k = 0; k < SL::NC; ++k) atomicAdd(y + ac + k, (double)zc[k]);
+#pragma unroll
+  for (int k = 0; k < SL::NG; ++k) atomicAdd(y + ag + k, (double)zg[k]);
+}
+
+template <typename T, int CD, bool LDSY, bool STAGEX>
+__global__ __launch_bounds__(MV_THREADS) void k_mv_tiled(Dev d, const double* done) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  if (done && *done != 0.0) return;
+  double* qs = reinterpret_cast<double*>(smem_raw);
+  double* ys = LDSY ? qs + 4 * MV_MAX_TF : d.mv_part;
+  const T* xg = (const T*)d.xT;
+  T* xs = reinterpret_cast<T*>(qs + 4 * MV_MAX_TF + (LDSY ? d.nA : 0));
+  const T* x = STAGEX ? xs : xg;
+  if constexpr (LDSY) {
+    for (int k = threadIdx.x; k < d.nA; k += blockDim.x) ys[k] = 0;
+  }
+  if constexpr (STAGEX) {
+    for (int k = threadIdx.x; k < d.nA; k += blockDim.x) xs[k] = xg[k];
+  }
+  __syncthreads();
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int tile = blockIdx.x; tile < d.n_tiles; tile += gridDim.x) {
+    const int4 tl = d.tiles[tile];
+    const int fb = tl.x, nf = tl.y - tl.x;
+    for (int k = threadIdx.x; k < 4 * nf; k += blockDim.x) qs[k] = 0;
+    // the damped inverse of this thread's tile feature, fetched while phase A runs
+    const bool ptile = tile < d.n_ptiles;
+    const bool owner = threadIdx.x < nf;
+    T Mi[10];
+    uint8_t mflag = 0;
+    if (owner) {
+      const int f = fb + threadIdx.x;
+      if (ptile) {
+        mflag = d.flp[f];
+        const T* M = (const T*)d.Vip + 6 * (int64_t)f;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) Mi[k] = M[k];
+      } else {
+        mflag = d.fll[f];
+        const T* M = (const T*)d.Vil + 10 * (int64_t)f;
+#pragma unroll
+        for (int k = 0; k < 10; ++k) Mi[k] = M[k];
+      }
+    }
+    __syncthreads();
+    int fam = 0;
+    int64_t i = 0;
+    bool active = false;
+    if (w < tl.w) {
+      const int4 ch = d.chunks[tl.z + w];
+      fam = ch.x;
+      active = lane < ch.z;
+      i = (int64_t)ch.y + lane;
+    }
+    T v[MaxSlot<CD>::V];
+    T t[4] = {0, 0, 0, 0};
+    T qv[4] = {0, 0, 0, 0};
+    int ac = 0, ag = 0, lf = -1;
+    if (active) {
+      switch (fam) {
+        case 1: tile_phase_a<1, T, CD>(d, i, x, qv, fb, v, t, ac, ag, lf); break;
+        case 2: tile_phase_a<2, T, CD>(d, i, x, qv, fb, v, t, ac, ag, lf); break;
+        case 3: tile_phase_a<3, T, CD>(d, i, x, qv, fb, v, t, ac, ag, lf); break;
+        case 4: tile_phase_a<4, T, CD>(d, i, x, qv, fb, v, t, ac, ag, lf); break;
+        case 5: tile_phase_a<5, T, CD>(d, i, x, qv, fb, v, t, ac, ag, lf); break;
+        case 6: tile_phase_a<6, T, CD>(d, i, x, qv, fb, v, t, ac, ag, lf); break;
+        case 7: tile_phase_a<7, T, CD>(d, i, x, qv, fb, v, t, ac, ag, lf); break;
+      }
+    }
+    if (lf >= 0) {
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+        if (a < 3 || fam == 2 || fam == 4 || fam == 5 || fam == 7) atomicAdd(qs + 4 * lf + a, (double)qv[a]);
+    }
+    __syncthreads();
+    if (owner) {
+      const int k = threadIdx.x;
+      if (ptile) {
+        T q[3] = {(T)qs[4 * k], (T)qs[4 * k + 1], (T)qs[4 * k + 2]}, sv[3];
+        if (mflag) apply_vinv<T, 3>(d, fb + k, q, sv);
+        else {
+#pragma unroll
+          for (int i2 = 0; i2 < 3; ++i2) {
+            T acc = 0;
+#pragma unroll
+            for (int j2 = 0; j2 < 3; ++j2) acc += Mi[sym<3>(i2, j2)] * q[j2];
+            sv[i2] = acc;
+          }
+        }
+        qs[4 * k] = sv[0]; qs[4 * k + 1] = sv[1]; qs[4 * k + 2] = sv[2];
+      } else {
+        T q[4] = {(T)qs[4 * k], (T)qs[4 * k + 1], (T)qs[4 * k + 2], (T)qs[4 * k + 3]}, sv[4];
+        if (mflag) apply_vinv<T, 4>(d, fb + k, q, sv);
+        else {
+#pragma unroll
+          for (int i2 = 0; i2 < 4; ++i2) {
+            T acc = 0;
+#pragma unroll
+            for (int j2 = 0; j2 < 4; ++j2) acc += Mi[sym<4>(i2, j2)] * q[j2];
+            sv[i2] = acc;
+          }
+        }
+        qs[4 * k] = sv[0]; qs[4 * k + 1] = sv[1]; qs[4 * k + 2] = sv[2]; qs[4 * k + 3] = sv[3];
+      }
+    }
+    __syncthreads();
+    if (active) {
+      if constexpr (sizeof(T) == 4) {
+        switch (fam) {
+          case 1: tile_phase_c<1, T, CD>(v, t, ac, ag, lf, qs, ys); break;
+          case 2: tile_phase_c<2, T, CD>(v, t, ac, ag, lf, qs, ys); break;
+          case 3: tile_phase_c<3, T, CD>(v, t, ac, ag, lf, qs, ys); break;
+          case 4: tile_phase_c<4, T, CD>(v, t, ac, ag, lf, qs, ys); break;
+          case 5: tile_phase_c<5, T, CD>(v, t, ac, ag, lf, qs, ys); break;
+          case 6: tile_phase_c<6, T, CD>(v, t, ac, ag, lf, qs, ys); break;
+          case 7: tile_phase_c<7, T, CD>(v, t, ac, ag, lf, qs, ys); break;
+        }
+      } else {
+        switch (fam) {
+          case 1: tile_phase_c_reload<1, T, CD>(d, i, t, ac, ag, lf, qs, ys); break;
+          case 2: tile_phase_c_reload<2, T, CD>(d, i, t, ac, ag, lf, qs, ys); break;
+          case 3: tile_phase_c_reload<3, T, CD>(d, i, t, ac, ag, lf, qs, ys); break;
+          case 4: tile_phase_c_reload<4, T, CD>(d, i, t, ac, ag, lf, qs, ys); break;
+          case 5: tile_phase_c_reload<5, T, CD>(d, i, t, ac, ag, lf, qs, ys); break;
+          case 6: tile_phase_c_reload<6, T, CD>(d, i, t, ac, ag, lf, qs, ys); break;
+          case 7: tile_phase_c_reload<7, T, CD>(d, i, t, ac, ag, lf, qs, ys); break;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // features whose records do not fit one tile: one lane per feature
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < d.n_bigp + d.n_bigl; k += gridDim.x * blockDim.x) {
+    if (k < d.n_bigp) mv_feature<T, CD, 3>(d, d.bigp[k], x, ys);
+    else mv_feature<T, CD, 4>(d, d.bigl[k - d.n_bigp], x, ys);
+  }
+  if constexpr (LDSY) {
+    __syncthreads();
+    double* out = d.mv_part + (int64_t)blockIdx.x * d.nA;
+    for (int k = threadIdx.x; k < d.nA; k += blockDim.x) out[k] = ys[k];
+  }
 }
 
 template <typename T> __global__ void k_to_T(const double* src, void* dst, int n) {
@@ -1271,29 +1362,226 @@ int matvec_max_lds_bytes() {
   return v;
 }
 
+size_t matvec_lds_bytes(const Dev& d) {
+  const size_t ts = d.fp64 ? 8 : 4;
+  return 8 * (4 * MV_MAX_TF + (d.mv_lds ? (size_t)d.nA : 0)) + (d.mv_stage_x ? ts * (size_t)d.nA : 0);
+}
+
+template <typename T, int CD, bool LDSY, bool STAGEX> static void launch_mv(const Dev& d, const double* done, hipStream_t s) {
+  static bool attr = false;
+  if (!attr) {
+    hipFuncSetAttribute((const void*)k_mv_tiled<T, CD, LDSY, STAGEX>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                        matvec_max_lds_bytes());
+    attr = true;
+  }
+  k_mv_tiled<T, CD, LDSY, STAGEX><<<d.n_mv_wg, MV_THREADS, matvec_lds_bytes(d), s>>>(d, done);
+}
+
 template <typename T, int CD> static void run_matvec(const Dev& d, const double* done, hipStream_t s) {
-  const size_t lds = d.mv_lds ? (size_t)d.nA * sizeof(T) : 0;
-  if (d.mv_lds) {
-    static bool attr_set = false;
-    if (!attr_set) {
-      hipFuncSetAttribute((const void*)k_matvec<T, CD, true>, hipFuncAttributeMaxDynamicSharedMemorySize, matvec_max_lds_bytes());
-      attr_set = true;
-    }
-    k_matvec<T, CD, true><<<d.n_mv_wg, 256, lds, s>>>(d, done);
-  } else {
-    k_matvec<T, CD, false><<<d.n_mv_wg, 256, 0, s>>>(d, done);
+  if (d.mv_lds && d.mv_stage_x) launch_mv<T, CD, true, true>(d, done, s);
+  else if (d.mv_lds) launch_mv<T, CD, true, false>(d, done, s);
+  else launch_mv<T, CD, false, false>(d, done, s);
+}
+
+// ---------------------------------------------------------------------------
+// PCG vector kernels, grid-wide.  Dot products are summed with one FP64
+// atomic per workgroup into accumulator set k mod 3 of iteration k; the next
+// kernel on the stream reads the sum.  Iteration k zeroes set (k + 1) mod 3,
+// whose last reader ran in iteration k - 2.
+__device__ __forceinline__ double* acc_set(const Dev& d, int k) { return d.scal + SC_ACC + ACC_STRIDE * (k % 3); }
+
+// z_b = M_b r_b for A-block b; returns the block's offset and size
+template <int CD> __device__ __forceinline__ void block_of(const Dev& d, int b, int& o, int& n, const double*& M) {
+  if (b < d.nc) { o = CD * b; n = CD; M = d.Mcam + (int64_t)CD * CD * b; }
+  else if (b < d.nc + d.ng) { const int g = b - d.nc; o = d.offPl + 3 * g; n = 3; M = d.Mpl + 9 * g; }
+  else { const int v = b - d.nc - d.ng; o = d.offVp + 2 * v; n = 2; M = d.Mvp + 4 * v; }
+}
+
+template <int CD> __device__ __forceinline__ void apply_M_block(const Dev& d, int b, const double* r, double* z, double& rz) {
+  int o, n;
+  const double* M;
+  block_of<CD>(d, b, o, n, M);
+  double rr[9];
+  for (int a = 0; a < n; ++a) rr[a] = r[o + a];
+  for (int a = 0; a < n; ++a) {
+    double t = 0;
+    for (int c = 0; c < n; ++c) t += M[a * n + c] * rr[c];
+    z[o + a] = t;
+    rz += rr[a] * t;
   }
 }
 
-void launch_pcg_init(const Dev& d, double tol, int max_iters, hipStream_t s) {
-  BA_DISPATCH_T_CD(d, k_pcg_init<T, CD><<<1, 1024, 0, s>>>(d, tol, max_iters));
+// one FP64 atomic per workgroup for each of K block sums
+template <int K> __device__ __forceinline__ void block_atomic_add(double (&v)[K], double* lds, double* const (&dst)[K]) {
+  double* o = block_sum_arr<double, K>(v, lds);
+  if (threadIdx.x < K) atomicAdd(dst[threadIdx.x], o[threadIdx.x]);
 }
 
-void launch_pcg_iteration(const Dev& d, double lambda, hipStream_t s) {
+// x = 0, r = b, z = M r, p = z; r.z -> set 2 (read as "previous r.z" by iteration 0), b.b -> SC_BB
+template <typename T, int CD> __global__ __launch_bounds__(256) void k_pcg_init(Dev d) {
+  __shared__ double lds[3 * 5];
+  const int nb = d.nc + d.ng + d.nv;
+  double v[2] = {0, 0};
+  for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < nb; b += gridDim.x * blockDim.x) {
+    int o, n;
+    const double* M;
+    block_of<CD>(d, b, o, n, M);
+    for (int a = 0; a < n; ++a) { d.x[o + a] = 0; d.r[o + a] = d.bA[o + a]; v[1] += d.bA[o + a] * d.bA[o + a]; }
+    apply_M_block<CD>(d, b, d.bA, d.z, v[0]);
+    for (int a = 0; a < n; ++a) { d.p[o + a] = d.z[o + a]; ((T*)d.xT)[o + a] = (T)d.z[o + a]; }
+  }
+  double* const dst[2] = {acc_set(d, 2) + ACC_RZ, d.scal + SC_BB};
+  block_atomic_add<2>(v, lds, dst);
+}
+
+// scalars of a new solve: accumulators cleared, tolerances set (one thread)
+__global__ void k_pcg_reset(Dev d, double tol, int maxit) {
+  for (int k = 0; k < 3 * ACC_STRIDE; ++k) d.scal[SC_ACC + k] = 0;
+  d.scal[SC_BB] = 0;
+  d.scal[SC_ITER] = 0;
+  d.scal[SC_MAXIT] = maxit;
+  d.scal[SC_BREAK] = 0;
+  d.scal[SC_DONE] = 0;
+  d.scal[SC_TOL2] = tol * tol;  // scaled by b.b in k_pcg_start
+}
+
+__global__ void k_pcg_start(Dev d) {
+  const double bb = d.scal[SC_BB];
+  d.scal[SC_RR] = bb;
+  d.scal[SC_RZ] = acc_set(d, 2)[ACC_RZ];
+  d.scal[SC_TOL2] *= bb;
+  if (bb == 0.0 || d.scal[SC_MAXIT] <= 0 || !isfinite(bb)) d.scal[SC_DONE] = 1.0;
+}
+
+// q = sum of the product partials + lambda D p; p.q -> set k
+// workgroup: 64 entries x 16 partial slices
+template <typename T> __global__ __launch_bounds__(1024) void k_pcg_q(Dev d, const double* done, const double* xin,
+                                                                     double* y, double lam, int k) {
+  __shared__ double red[16][65];
+  __shared__ double lds[2 * 17];
+  if (done && *done != 0.0) return;
+  if (k >= 0 && blockIdx.x == 0 && threadIdx.x < ACC_STRIDE) acc_set(d, k + 1)[threadIdx.x] = 0;
+  const int lane = threadIdx.x & 63, sl = threadIdx.x >> 6;
+  const int e = blockIdx.x * 64 + lane;
+  double* part = d.mv_part;
+  double s = 0;
+  if (e < d.nA) {
+    if (d.mv_lds) {
+      for (int w = sl; w < d.n_mv_wg; w += 16) s += part[(int64_t)w * d.nA + e];
+    } else if (sl == 0) {
+      s = part[e];
+      part[e] = 0;
+    }
+  }
+  red[sl][lane] = s;
+  __syncthreads();
+  double dot[1] = {0};
+  if (sl == 0 && e < d.nA) {
+    double t = 0;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) t += red[j][lane];
+    const double qv = t + lam * d.DA[e] * xin[e];
+    y[e] = qv;
+    dot[0] = xin[e] * qv;
+  }
+  if (k < 0) return;
+  double* const dst[1] = {acc_set(d, k) + ACC_PQ};
+  block_atomic_add<1>(dot, lds, dst);
+}
+
+// position of entry e of the reduced vector: its block's offset, size and preconditioner block
+template <int CD> __device__ __forceinline__ void entry_block(const Dev& d, int e, int& o, int& n, const double*& M) {
+  if (e < d.offPl) { const int b = e / CD; o = CD * b; n = CD; M = d.Mcam + (int64_t)CD * CD * b; }
+  else if (e < d.offVp) { const int g = (e - d.offPl) / 3; o = d.offPl + 3 * g; n = 3; M = d.Mpl + 9 * g; }
+  else { const int v = (e - d.offVp) / 2; o = d.offVp + 2 * v; n = 2; M = d.Mvp + 4 * v; }
+}
+
+// alpha = rz / pq; x += alpha p, r -= alpha q; r.r -> set k   (one thread per entry)
+__global__ __launch_bounds__(256) void k_pcg_xr(Dev d, int k) {
+  __shared__ double lds[5];
+  if (d.scal[SC_DONE] != 0.0) return;
+  const double pq = acc_set(d, k)[ACC_PQ];
+  if (!(pq > 0.0) || !isfinite(pq)) {  // breakdown: keep x, stop
+    if (blockIdx.x == 0 && threadIdx.x == 0) d.scal[SC_BREAK] = 1.0;
+    return;
+  }
+  const double alpha = d.scal[SC_RZ] / pq;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  double v[1] = {0};
+  if (e < d.nA) {
+    d.x[e] += alpha * d.p[e];
+    const double re = d.r[e] - alpha * d.q[e];
+    d.r[e] = re;
+    v[0] = re * re;
+  }
+  double* const dst[1] = {acc_set(d, k) + ACC_RR};
+  block_atomic_add<1>(v, lds, dst);
+}
+
+// z = M r (block diagonal); r.z -> set k   (one thread per entry)
+template <int CD> __global__ __launch_bounds__(256) void k_pcg_z(Dev d, int k) {
+  __shared__ double lds[5];
+  if (d.scal[SC_DONE] != 0.0 || d.scal[SC_BREAK] != 0.0) return;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  double v[1] = {0};
+  if (e < d.nA) {
+    int o, n;
+    const double* M;
+    entry_block<CD>(d, e, o, n, M);
+    const int row = e - o;
+    double t = 0;
+    for (int c = 0; c < n; ++c) t += M[row * n + c] * d.r[o + c];
+    d.z[e] = t;
+    v[0] = d.r[e] * t;
+  }
+  double* const dst[1] = {acc_set(d, k) + ACC_RZ};
+  block_atomic_add<1>(v, lds, dst);
+}
+
+// beta = rz_k / rz_(k-1); p = z + beta p; workgroup 0 updates the scalars and the stopping test
+template <typename T> __global__ __launch_bounds__(256) void k_pcg_p(Dev d, int k) {
+  if (d.scal[SC_DONE] != 0.0) return;
+  const double* A = acc_set(d, k);
+  if (d.scal[SC_BREAK] != 0.0) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) d.scal[SC_DONE] = 1.0;
+    return;
+  }
+  const double rz = A[ACC_RZ], rr = A[ACC_RR];
+  const double rz_prev = acc_set(d, k + 2)[ACC_RZ];  // set (k - 1) mod 3
+  const double beta = rz / rz_prev;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < d.nA) {
+    const double pk = d.z[e] + beta * d.p[e];
+    d.p[e] = pk;
+    ((T*)d.xT)[e] = (T)pk;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    const double iter = d.scal[SC_ITER] + 1.0;
+    d.scal[SC_ITER] = iter;
+    d.scal[SC_RR] = rr;
+    d.scal[SC_RZ] = rz;
+    d.scal[SC_PQ] = A[ACC_PQ];
+    d.scal[SC_BETA] = beta;
+    if (rr <= d.scal[SC_TOL2] || iter >= d.scal[SC_MAXIT] || !isfinite(rr)) d.scal[SC_DONE] = 1.0;
+  }
+}
+
+static unsigned pcg_blocks(const Dev& d) { return std::max(1u, std::min(64u, nblk(d.nc + d.ng + d.nv, 256))); }
+
+void launch_pcg_init(const Dev& d, double tol, int max_iters, hipStream_t s) {
+  k_pcg_reset<<<1, 1, 0, s>>>(d, tol, max_iters);
+  BA_DISPATCH_T_CD(d, k_pcg_init<T, CD><<<pcg_blocks(d), 256, 0, s>>>(d));
+  k_pcg_start<<<1, 1, 0, s>>>(d);
+}
+
+void launch_pcg_product(const Dev& d, hipStream_t s) { BA_DISPATCH_T_CD(d, run_matvec<T, CD>(d, d.scal + SC_DONE, s)); }
+
+void launch_pcg_update(const Dev& d, double lambda, int iter, hipStream_t s) {
   BA_DISPATCH_T_CD(d, {
-    run_matvec<T, CD>(d, d.scal + SC_DONE, s);
-    k_mv_reduce<T><<<nblk(d.nA, 256), 256, 0, s>>>(d, d.scal + SC_DONE, d.p, d.q, lambda);
-    k_pcg_update<T, CD><<<1, 1024, 0, s>>>(d);
+    k_pcg_q<T><<<nblk(d.nA, 64), 1024, 0, s>>>(d, d.scal + SC_DONE, d.p, d.q, lambda, iter);
+    k_pcg_xr<<<nblk(d.nA, 256), 256, 0, s>>>(d, iter);
+    k_pcg_z<CD><<<nblk(d.nA, 256), 256, 0, s>>>(d, iter);
+    k_pcg_p<T><<<nblk(d.nA, 256), 256, 0, s>>>(d, iter);
   });
 }
 
@@ -1301,7 +1589,7 @@ void launch_schur_matvec(const Dev& d, const double* xin, double* yout, double l
   BA_DISPATCH_T_CD(d, {
     k_to_T<T><<<nblk(d.nA, 256), 256, 0, s>>>(xin, d.xT, d.nA);
     run_matvec<T, CD>(d, nullptr, s);
-    k_mv_reduce<T><<<nblk(d.nA, 256), 256, 0, s>>>(d, nullptr, xin, yout, lambda);
+    k_pcg_q<T><<<nblk(d.nA, 64), 1024, 0, s>>>(d, nullptr, xin, yout, lambda, -1);
   });
 }
 

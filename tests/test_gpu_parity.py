@@ -204,3 +204,23 @@ def test_camera_dof6_and_errors():
     ba.close()
     with pytest.raises(BAError):
         BA(s["cameras"], s["points"], s["lines"], s["planes"] * 2, s["vps"], s["cx"], s["cy"])
+
+
+def test_large_feature_path_matches(monkeypatch):
+    """Features whose records exceed a product tile take the one-lane-per-
+    feature path; with the tile capacity forced to one chunk most features do,
+    and the implicit-Schur product must still equal the dense S x."""
+    monkeypatch.setenv("BA_TILE_CHUNKS", "1")
+    from paper_2609_04026_amd.binding import BA
+    s = make_scene(2)
+    prob = lm.Problem(s)
+    lin = lm.linearize(prob, prob.state0())
+    sys_ = lm.schur(prob, lin, 1e-3)
+    for precision, tol in (("fp64", 1e-9), ("mixed", 1e-4)):
+        ba = BA.from_scene(s, precision=precision)
+        ba.linearize(1e-3)
+        x = np.random.default_rng(1).normal(size=prob.nA)
+        ref = sys_["S"] @ x
+        y = ba.schur_matvec(x)
+        assert np.linalg.norm(y - ref) <= 10 * tol * np.linalg.norm(ref)
+        ba.close()
