@@ -251,15 +251,25 @@ def schur(prob, lin, lam):
     return dict(S=S, b=t["b"], W=t["W"], Vinv=t["Vinv"], U=U)
 
 
+def cholesky_solve(S, b):
+    """x = S^-1 b for symmetric positive definite S by a dense Cholesky
+    factorisation and two triangular solves; None when S is not positive
+    definite."""
+    import scipy.linalg
+    try:
+        c = scipy.linalg.cho_factor(S, lower=True, check_finite=False)
+    except np.linalg.LinAlgError:
+        return None
+    return scipy.linalg.cho_solve(c, b, check_finite=False)
+
+
 def solve_schur(prob, lin, lam):
     """Step h = (h_a, h_f) by dense Cholesky of S and back-substitution
     h_f = V^-1 (-g_f - W^T h_a).  Returns None when S is not positive definite."""
     sys_ = schur(prob, lin, lam)
-    try:
-        L = np.linalg.cholesky(sys_["S"])
-    except np.linalg.LinAlgError:
+    ha = cholesky_solve(sys_["S"], sys_["b"])
+    if ha is None:
         return None, sys_
-    ha = np.linalg.solve(L.T, np.linalg.solve(L, sys_["b"]))
     gf = lin.g[prob.nA:]
     hf = sys_["Vinv"] @ (-gf - sys_["W"].T @ ha)
     return np.concatenate([ha, hf]), sys_

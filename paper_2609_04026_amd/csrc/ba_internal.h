@@ -81,6 +81,10 @@ struct Dev {
   double *gA = nullptr, *DA = nullptr, *bA = nullptr;
   double *Scam = nullptr, *Spl = nullptr, *Svp = nullptr;  // damped diagonal blocks of S
   double *Mcam = nullptr, *Mpl = nullptr, *Mvp = nullptr;  // preconditioner blocks
+  // coarse correction of the preconditioner: P r = M r + Z E^-1 Z^T r with
+  // Z (COARSE_K columns of length nA, column-major) and E = Z^T S Z
+  int coarse = 0;              // host switch: the PCG kernels read Z (SC_COARSE decides on the device)
+  double *Zc = nullptr, *SZc = nullptr, *Einv = nullptr, *Ztb = nullptr;
   // PCG (double vectors of length nA) and matvec partials (T)
   double *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
   void *xT = nullptr;       // matvec input in T
@@ -111,9 +115,14 @@ enum PcgScal {
   SC_RZ = 0, SC_BB, SC_RR, SC_PQ, SC_ALPHA, SC_BETA, SC_DONE, SC_ITER, SC_TOL2, SC_LAMBDA,
   SC_GH, SC_JH2, SC_E, SC_EPIX, SC_NFLAG, SC_MAXIT, SC_BREAK,
   // PCG accumulators, three sets rotated by iteration (k mod 3): p.q, r.r, r.z
-  SC_ACC = 20, SC_COUNT = 32
+  SC_COARSE,  // 1: the coarse correction of the preconditioner is active for this solve
+  // PCG accumulators, three sets rotated by iteration (k mod 3): p.q, r.r, r.z, Z^T r
+  SC_ACC = 20, SC_COUNT = 64
 };
-constexpr int ACC_PQ = 0, ACC_RR = 1, ACC_RZ = 2, ACC_STRIDE = 4;
+// columns of the coarse space of the learned preconditioner
+constexpr int COARSE_K = 8;
+constexpr int ACC_PQ = 0, ACC_RR = 1, ACC_RZ = 2, ACC_ZR = 4, ACC_STRIDE = 4 + COARSE_K;
+static_assert(SC_ACC + 3 * ACC_STRIDE <= SC_COUNT, "PCG scalar area too small");
 
 // ---- launchers (ba_kernels.hip) --------------------------------------------
 void launch_cast_params(const Dev& d, bool candidate, hipStream_t s);
@@ -128,6 +137,8 @@ void launch_pcg_init(const Dev& d, double tol, int max_iters, hipStream_t s);
 void launch_pcg_product(const Dev& d, hipStream_t s);                  // q' = partial J_a^T(...) products
 void launch_pcg_update(const Dev& d, double lambda, int iter, hipStream_t s);  // q = S p, then the CG update
 void launch_schur_matvec(const Dev& d, const double* xin, double* yout, double lambda, hipStream_t s);
+// E = Z^T S Z from the coarse basis d.Zc (COARSE_K products), its inverse and SC_COARSE
+void launch_coarse_setup(const Dev& d, double lambda, hipStream_t s);
 void launch_backsub(const Dev& d, hipStream_t s);                        // h_f, model decrease terms
 void launch_retract(const Dev& d, hipStream_t s);                        // candidate = current [+] h
 void launch_zero(void* p, size_t bytes, hipStream_t s);

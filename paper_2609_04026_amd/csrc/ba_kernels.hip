@@ -1357,7 +1357,7 @@ template <typename T> __global__ void k_to_T(const double* src, void* dst, int n
 
 int matvec_max_lds_bytes() {
   int dev = 0, v = 0;
-  hipGetDevice(&dev);
+  if (hipGetDevice(&dev) != hipSuccess) dev = 0;
   if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) v = 65536;
   return v;
 }
@@ -1370,9 +1370,9 @@ size_t matvec_lds_bytes(const Dev& d) {
 template <typename T, int CD, bool LDSY, bool STAGEX> static void launch_mv(const Dev& d, const double* done, hipStream_t s) {
   static bool attr = false;
   if (!attr) {
-    hipFuncSetAttribute((const void*)k_mv_tiled<T, CD, LDSY, STAGEX>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                        matvec_max_lds_bytes());
-    attr = true;
+    // on failure the launch below reports the LDS request through the launch check
+    attr = hipFuncSetAttribute((const void*)k_mv_tiled<T, CD, LDSY, STAGEX>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               matvec_max_lds_bytes()) == hipSuccess;
   }
   k_mv_tiled<T, CD, LDSY, STAGEX><<<d.n_mv_wg, MV_THREADS, matvec_lds_bytes(d), s>>>(d, done);
 }
@@ -1417,26 +1417,67 @@ template <int K> __device__ __forceinline__ void block_atomic_add(double (&v)[K]
   if (threadIdx.x < K) atomicAdd(dst[threadIdx.x], o[threadIdx.x]);
 }
 
-// x = 0, r = b, z = M r, p = z; r.z -> set 2 (read as "previous r.z" by iteration 0), b.b -> SC_BB
-template <typename T, int CD> __global__ __launch_bounds__(256) void k_pcg_init(Dev d) {
+// coarse term of the preconditioner for entry e: sum_c Z[c][e] (E^-1 w)_c
+__device__ __forceinline__ double coarse_term(const Dev& d, int e, const double* w) {
+  double y = 0;
+#pragma unroll
+  for (int a = 0; a < COARSE_K; ++a) {
+    double t = 0;
+#pragma unroll
+    for (int b = 0; b < COARSE_K; ++b) t += d.Einv[a * COARSE_K + b] * w[b];
+    y += d.Zc[(int64_t)a * d.nA + e] * t;
+  }
+  return y;
+}
+
+// x = 0, r = b, z = P r, p = z; r.z -> set 2 (read as "previous r.z" by iteration 0), b.b -> SC_BB
+template <typename T, int CD, bool COARSE> __global__ __launch_bounds__(256) void k_pcg_init(Dev d) {
   __shared__ double lds[3 * 5];
   const int nb = d.nc + d.ng + d.nv;
+  const bool coarse = COARSE && d.scal[SC_COARSE] != 0.0;
   double v[2] = {0, 0};
   for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < nb; b += gridDim.x * blockDim.x) {
     int o, n;
     const double* M;
     block_of<CD>(d, b, o, n, M);
     for (int a = 0; a < n; ++a) { d.x[o + a] = 0; d.r[o + a] = d.bA[o + a]; v[1] += d.bA[o + a] * d.bA[o + a]; }
-    apply_M_block<CD>(d, b, d.bA, d.z, v[0]);
+    if (!coarse) {
+      apply_M_block<CD>(d, b, d.bA, d.z, v[0]);
+    } else {
+      double rz = 0;
+      apply_M_block<CD>(d, b, d.bA, d.z, rz);
+      for (int a = 0; a < n; ++a) {
+        const double zc = coarse_term(d, o + a, d.Ztb);
+        d.z[o + a] += zc;
+        rz += d.bA[o + a] * zc;
+      }
+      v[0] += rz;
+    }
     for (int a = 0; a < n; ++a) { d.p[o + a] = d.z[o + a]; ((T*)d.xT)[o + a] = (T)d.z[o + a]; }
   }
   double* const dst[2] = {acc_set(d, 2) + ACC_RZ, d.scal + SC_BB};
   block_atomic_add<2>(v, lds, dst);
 }
 
+// Ztb = Z^T b (COARSE_K dots; Ztb cleared by k_pcg_reset)
+__global__ __launch_bounds__(256) void k_coarse_ztb(Dev d) {
+  __shared__ double lds[5 * COARSE_K];
+  if (d.scal[SC_COARSE] == 0.0) return;
+  double v[COARSE_K];
+  for (int a = 0; a < COARSE_K; ++a) v[a] = 0;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < d.nA; e += gridDim.x * blockDim.x) {
+    const double be = d.bA[e];
+    for (int a = 0; a < COARSE_K; ++a) v[a] += d.Zc[(int64_t)a * d.nA + e] * be;
+  }
+  double* o = block_sum_arr<double, COARSE_K>(v, lds);
+  if (threadIdx.x < COARSE_K) atomicAdd(d.Ztb + threadIdx.x, o[threadIdx.x]);
+}
+
 // scalars of a new solve: accumulators cleared, tolerances set (one thread)
 __global__ void k_pcg_reset(Dev d, double tol, int maxit) {
   for (int k = 0; k < 3 * ACC_STRIDE; ++k) d.scal[SC_ACC + k] = 0;
+  if (d.Ztb)
+    for (int k = 0; k < COARSE_K; ++k) d.Ztb[k] = 0;
   d.scal[SC_BB] = 0;
   d.scal[SC_ITER] = 0;
   d.scal[SC_MAXIT] = maxit;
@@ -1496,9 +1537,10 @@ template <int CD> __device__ __forceinline__ void entry_block(const Dev& d, int 
   else { const int v = (e - d.offVp) / 2; o = d.offVp + 2 * v; n = 2; M = d.Mvp + 4 * v; }
 }
 
-// alpha = rz / pq; x += alpha p, r -= alpha q; r.r -> set k   (one thread per entry)
-__global__ __launch_bounds__(256) void k_pcg_xr(Dev d, int k) {
-  __shared__ double lds[5];
+// alpha = rz / pq; x += alpha p, r -= alpha q; r.r (and Z^T r) -> set k   (one thread per entry)
+template <bool COARSE> __global__ __launch_bounds__(256) void k_pcg_xr(Dev d, int k) {
+  constexpr int NV = COARSE ? 1 + COARSE_K : 1;
+  __shared__ double lds[5 * NV];
   if (d.scal[SC_DONE] != 0.0) return;
   const double pq = acc_set(d, k)[ACC_PQ];
   if (!(pq > 0.0) || !isfinite(pq)) {  // breakdown: keep x, stop
@@ -1507,19 +1549,33 @@ __global__ __launch_bounds__(256) void k_pcg_xr(Dev d, int k) {
   }
   const double alpha = d.scal[SC_RZ] / pq;
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  double v[1] = {0};
+  double v[NV];
+#pragma unroll
+  for (int a = 0; a < NV; ++a) v[a] = 0;
   if (e < d.nA) {
     d.x[e] += alpha * d.p[e];
     const double re = d.r[e] - alpha * d.q[e];
     d.r[e] = re;
     v[0] = re * re;
+    if constexpr (COARSE) {
+#pragma unroll
+      for (int a = 0; a < COARSE_K; ++a) v[1 + a] = d.Zc[(int64_t)a * d.nA + e] * re;
+    }
   }
-  double* const dst[1] = {acc_set(d, k) + ACC_RR};
-  block_atomic_add<1>(v, lds, dst);
+  if constexpr (COARSE) {
+    double* A = acc_set(d, k);
+    double* const dst[NV] = {A + ACC_RR, A + ACC_ZR, A + ACC_ZR + 1, A + ACC_ZR + 2, A + ACC_ZR + 3,
+                             A + ACC_ZR + 4, A + ACC_ZR + 5, A + ACC_ZR + 6, A + ACC_ZR + 7};
+    static_assert(COARSE_K == 8, "accumulator list written for 8 columns");
+    block_atomic_add<NV>(v, lds, dst);
+  } else {
+    double* const dst[1] = {acc_set(d, k) + ACC_RR};
+    block_atomic_add<1>(v, lds, dst);
+  }
 }
 
-// z = M r (block diagonal); r.z -> set k   (one thread per entry)
-template <int CD> __global__ __launch_bounds__(256) void k_pcg_z(Dev d, int k) {
+// z = M r (block diagonal) [+ Z E^-1 Z^T r]; r.z -> set k   (one thread per entry)
+template <int CD, bool COARSE> __global__ __launch_bounds__(256) void k_pcg_z(Dev d, int k) {
   __shared__ double lds[5];
   if (d.scal[SC_DONE] != 0.0 || d.scal[SC_BREAK] != 0.0) return;
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1531,6 +1587,9 @@ template <int CD> __global__ __launch_bounds__(256) void k_pcg_z(Dev d, int k) {
     const int row = e - o;
     double t = 0;
     for (int c = 0; c < n; ++c) t += M[row * n + c] * d.r[o + c];
+    if constexpr (COARSE) {
+      if (d.scal[SC_COARSE] != 0.0) t += coarse_term(d, e, acc_set(d, k) + ACC_ZR);
+    }
     d.z[e] = t;
     v[0] = d.r[e] * t;
   }
@@ -1570,7 +1629,12 @@ static unsigned pcg_blocks(const Dev& d) { return std::max(1u, std::min(64u, nbl
 
 void launch_pcg_init(const Dev& d, double tol, int max_iters, hipStream_t s) {
   k_pcg_reset<<<1, 1, 0, s>>>(d, tol, max_iters);
-  BA_DISPATCH_T_CD(d, k_pcg_init<T, CD><<<pcg_blocks(d), 256, 0, s>>>(d));
+  if (d.coarse) {
+    k_coarse_ztb<<<std::min(64u, nblk(d.nA, 256)), 256, 0, s>>>(d);
+    BA_DISPATCH_T_CD(d, k_pcg_init<T, CD, true><<<pcg_blocks(d), 256, 0, s>>>(d));
+  } else {
+    BA_DISPATCH_T_CD(d, k_pcg_init<T, CD, false><<<pcg_blocks(d), 256, 0, s>>>(d));
+  }
   k_pcg_start<<<1, 1, 0, s>>>(d);
 }
 
@@ -1579,8 +1643,13 @@ void launch_pcg_product(const Dev& d, hipStream_t s) { BA_DISPATCH_T_CD(d, run_m
 void launch_pcg_update(const Dev& d, double lambda, int iter, hipStream_t s) {
   BA_DISPATCH_T_CD(d, {
     k_pcg_q<T><<<nblk(d.nA, 64), 1024, 0, s>>>(d, d.scal + SC_DONE, d.p, d.q, lambda, iter);
-    k_pcg_xr<<<nblk(d.nA, 256), 256, 0, s>>>(d, iter);
-    k_pcg_z<CD><<<nblk(d.nA, 256), 256, 0, s>>>(d, iter);
+    if (d.coarse) {
+      k_pcg_xr<true><<<nblk(d.nA, 256), 256, 0, s>>>(d, iter);
+      k_pcg_z<CD, true><<<nblk(d.nA, 256), 256, 0, s>>>(d, iter);
+    } else {
+      k_pcg_xr<false><<<nblk(d.nA, 256), 256, 0, s>>>(d, iter);
+      k_pcg_z<CD, false><<<nblk(d.nA, 256), 256, 0, s>>>(d, iter);
+    }
     k_pcg_p<T><<<nblk(d.nA, 256), 256, 0, s>>>(d, iter);
   });
 }
@@ -1591,6 +1660,62 @@ void launch_schur_matvec(const Dev& d, const double* xin, double* yout, double l
     run_matvec<T, CD>(d, nullptr, s);
     k_pcg_q<T><<<nblk(d.nA, 64), 1024, 0, s>>>(d, nullptr, xin, yout, lambda, -1);
   });
+}
+
+// E[a][b] = Z_a . (S Z)_b, one workgroup per entry
+__global__ __launch_bounds__(256) void k_coarse_e(Dev d, double* E) {
+  __shared__ double lds[5];
+  const int a = blockIdx.x / COARSE_K, b = blockIdx.x % COARSE_K;
+  double v[1] = {0};
+  for (int e = threadIdx.x; e < d.nA; e += blockDim.x) v[0] += d.Zc[(int64_t)a * d.nA + e] * d.SZc[(int64_t)b * d.nA + e];
+  double* o = block_sum_arr<double, 1>(v, lds);
+  if (threadIdx.x == 0) E[blockIdx.x] = o[0];
+}
+
+// Einv = E^-1 by Cholesky of the symmetrised E; SC_COARSE = 0 when E is not
+// positive definite or the inverse is not finite (one thread)
+__global__ void k_coarse_inv(Dev d, const double* E) {
+  constexpr int Kc = COARSE_K;
+  double L[Kc][Kc], X[Kc][Kc];
+  bool ok = true;
+  for (int i = 0; i < Kc; ++i)
+    for (int j = 0; j < Kc; ++j) L[i][j] = 0.5 * (E[i * Kc + j] + E[j * Kc + i]);
+  for (int j = 0; j < Kc && ok; ++j) {
+    double s = L[j][j];
+    for (int k = 0; k < j; ++k) s -= L[j][k] * L[j][k];
+    if (!(s > 0.0) || !isfinite(s)) { ok = false; break; }
+    const double ljj = sqrt(s);
+    L[j][j] = ljj;
+    for (int r = j + 1; r < Kc; ++r) {
+      double u = L[r][j];
+      for (int k = 0; k < j; ++k) u -= L[r][k] * L[j][k];
+      L[r][j] = u / ljj;
+    }
+  }
+  if (ok) {
+    // X = L^-1, then E^-1 = X^T X
+    for (int c = 0; c < Kc; ++c)
+      for (int r = 0; r < Kc; ++r) {
+        double s = r == c ? 1.0 : 0.0;
+        for (int k = c; k < r; ++k) s -= L[r][k] * X[k][c];
+        X[r][c] = r < c ? 0.0 : s / L[r][r];
+      }
+    for (int i = 0; i < Kc; ++i)
+      for (int j = 0; j < Kc; ++j) {
+        double s = 0;
+        for (int k = 0; k < Kc; ++k) s += X[k][i] * X[k][j];
+        ok = ok && isfinite(s);
+        d.Einv[i * Kc + j] = s;
+      }
+  }
+  d.scal[SC_COARSE] = ok ? 1.0 : 0.0;
+}
+
+void launch_coarse_setup(const Dev& d, double lambda, hipStream_t s) {
+  for (int c = 0; c < COARSE_K; ++c) launch_schur_matvec(d, d.Zc + (int64_t)c * d.nA, d.SZc + (int64_t)c * d.nA, lambda, s);
+  double* E = d.Ztb + COARSE_K;  // K x K scratch after Z^T b
+  k_coarse_e<<<COARSE_K * COARSE_K, 256, 0, s>>>(d, E);
+  k_coarse_inv<<<1, 1, 0, s>>>(d, E);
 }
 
 // ---------------------------------------------------------------------------
