@@ -127,6 +127,7 @@ typedef struct {
   double ms[BA_PHASE_COUNT];     /* device time per phase */
   double matvec_ms;              /* with time_kernels: summed duration of the PCG products */
   int32_t matvec_count;          /* number of those products */
+  int32_t coarse;                /* 1: the learned coarse correction was active in this step's PCG */
 } ba_step_report;
 
 typedef struct {
@@ -231,10 +232,106 @@ ba_status ba_pcg_solve(ba_handle *h, double tol, int32_t max_iters, double *x, i
 /* Sizes: n_A (reduced dimension) and camera_dof. */
 ba_status ba_reduced_dim(const ba_handle *h, int64_t *n_A, int32_t *camera_dof);
 
-/* Learned preconditioner: load network weights (blob layout of the
- * learned-preconditioner section of the design notes).  Invalid sizes ->
- * BA_E_INVALID. */
+/* ---------------------------------------------------------------------------
+ * Learned coarse-space correction (this project's addition to the method:
+ * the paper preconditions the reduced-system CG with the inverses of its
+ * diagonal blocks, which leaves the slow global modes of BA, e.g. the
+ * similarity gauge, to CG).  A message-passing network predicts K = 8
+ * vectors per block, Z (n_A x 8), and PCG uses
+ *     P r = M r + Z E^-1 Z^T r,   M = blockdiag(S_ii)^-1,   E = Z^T S Z
+ * (M alone when E is not positive definite).
+ * Graph: one node per camera / plane / VP block of the reduced system, in
+ * that order; directed edges both ways between blocks that share a feature,
+ * sorted by destination, then source.
+ * Node input (64 floats): log diag(S_ii) minus its mean [0, n); strictly
+ * lower correlations S_pq / sqrt(S_pp S_qq), row by row, from 9;
+ * log(lambda) at 45; log(1 + records touching the block) at 46;
+ * log(1 + in-degree) at 47; type one-hot at 48..50; geometry from 51:
+ * camera R row-major then t / s0, plane n, w / s0, b1, b2, VP v, b1, b2
+ * ((b1, b2) the sphere tangent basis, s0 the RMS distance of the input
+ * camera centres from their mean, 1 if zero); zeros elsewhere.  Edge input
+ * (8 floats): log(1 + shared features), then one-hot camera-camera,
+ * camera-plane, camera-VP, group-group; zeros.
+ * Network, width 64, gelu(x) = x/2 (1 + tanh(sqrt(2/pi) (x + 0.044715 x^3))):
+ *   h = gelu(x W_in + b_in);  3 times: m_i = mean over edges j->i of
+ *   gelu([h_j, e_ji] W_e + b_e), h = gelu(h W_s + b_s + m) + h;
+ *   Y_i = h_i W_t + b_t for the node's type, read as n_t x 8 (row-major).
+ * Z_i = diag(u_i) Y_i with row scales u: camera (1,1,1, s0,s0,s0, 1,1,1),
+ * plane (1, 1, s0), VP (1, 1).  Training loss per system:
+ * tr((Z^T D Z)^-1 Z^T S Z), D = blockdiag(S_ii); a batch takes the mean.
+ * Parameters: float32 blob in the order W_in (64x64) b_in, (W_e (72x64)
+ * b_e W_s (64x64) b_s) x3, (W_t (64 x 8 n_t) b_t) for cameras, planes,
+ * VPs; matrices row-major.
+ * ------------------------------------------------------------------------- */
+
+/* Load network weights into a problem handle (used by BA_PC_LEARNED).  The
+ * solver uses block-Jacobi alone when no weights are loaded, when the
+ * problem has more than 6000 blocks (the graph is not built) or when E is
+ * not positive definite.  bytes must be 4 * ba_gnn_param_count(camera_dof),
+ * else BA_E_INVALID; non-finite weights give BA_E_INVALID.  The blob is
+ * copied. */
 ba_status ba_set_gnn_weights(ba_handle *h, const void *blob, size_t bytes);
+
+/* Number of float32 parameters of the network for a camera block size. */
+size_t ba_gnn_param_count(int32_t camera_dof);
+
+/* Graph of the reduced system at the last ba_linearize, for building
+ * training data.  Sizes first (NULL outputs skipped).  node_x: n x 64 at the
+ * last lambda and parameters; node_off: each block's offset in the reduced
+ * vector; node_unit: n x 9 row scales u_i (zero-padded); edge_rev[e]: index
+ * of the reverse edge; edge_x: m x 8.  BA_E_STATE before the first
+ * linearisation or when the graph is not built (more than 6000 blocks). */
+ba_status ba_export_gnn_graph(ba_handle *h, int32_t *n_nodes, int32_t *n_edges, float *node_x, int32_t *node_type,
+                              int32_t *node_off, float *node_unit, int32_t *edge_src, int32_t *edge_dst,
+                              int32_t *edge_rev, float *edge_x);
+
+/* The damped reduced matrix S of the last ba_linearize, dense (n_A x n_A
+ * doubles, row-major, caller-allocated), formed column by column with the
+ * implicit-Schur product (n_A products: meant for small systems, e.g.
+ * training data and tests).  Temporary device memory: 8 n_A^2 bytes. */
+ba_status ba_export_schur_dense(ba_handle *h, double *S);
+
+/* y = L^-1 S L^-T x with S_ii = L_i L_i^T (the block-normalised reduced
+ * system of the last ba_linearize); x, y: n_A doubles (host). */
+ba_status ba_normalized_matvec(ba_handle *h, const double *x, double *y);
+
+/* A batch of systems for training or evaluation.  Nodes sorted by type
+ * within the batch (cameras, planes, VPs); node_graph: each node's system,
+ * 0 .. n_graphs-1; node_unit: n x 9 row scales.  Edges join nodes of one
+ * system, sorted by destination, with edge_rev[e] the index of the reverse
+ * edge.  S blocks (FP64, row-major; needed for the loss): the damped
+ * diagonal block of node i (n_i x n_i) at s_node + s_node_off[i], the block
+ * S_{dst,src} of edge e (n_dst x n_src) at s_edge + s_edge_off[e]; the
+ * offsets must stay inside s_node_len / s_edge_len. */
+typedef struct {
+  int32_t n_nodes, n_edges, n_graphs;
+  const float *node_x;
+  const int32_t *node_type, *node_graph;
+  const float *node_unit;
+  const int32_t *edge_src, *edge_dst, *edge_rev;
+  const float *edge_x;
+  const double *s_node, *s_edge;
+  const int64_t *s_node_off, *s_edge_off;
+  int64_t s_node_len, s_edge_len;
+} ba_gnn_batch;
+
+typedef struct ba_gnn ba_gnn; /* network parameters, Adam state and work buffers on one device */
+
+/* precision: 0 = FP32 throughout (debug / gradient checks), 1 = BF16 MFMA
+ * products with FP32 accumulation (training and inference).  Parameters
+ * start at zero: set them before use. */
+ba_status ba_gnn_create(int32_t camera_dof, int32_t precision, int32_t device, ba_gnn **out);
+ba_status ba_gnn_set_params(ba_gnn *g, const float *params, size_t count);
+ba_status ba_gnn_get_params(const ba_gnn *g, float *params, size_t count);
+/* Forward pass: heads (n_nodes x 72 floats: Y_i row-major n_i x 8, rows
+ * zero-padded to 9) and, when loss is not NULL, the batch loss (needs the S
+ * blocks).  A system whose Z^T D Z is not positive definite adds zero. */
+ba_status ba_gnn_forward(ba_gnn *g, const ba_gnn_batch *b, float *heads, double *loss);
+/* Forward + backward: loss, gradient (param count floats, NULL skipped);
+ * with lr > 0 also one Adam step (beta1 0.9, beta2 0.999, eps 1e-8). */
+ba_status ba_gnn_train_step(ba_gnn *g, const ba_gnn_batch *b, double lr, double *loss, float *grad);
+const char *ba_gnn_last_error(const ba_gnn *g);
+void ba_gnn_destroy(ba_gnn *g);
 
 const char *ba_last_error(const ba_handle *h);
 void ba_destroy(ba_handle *h);

@@ -54,7 +54,16 @@ class StepReport(ctypes.Structure):
                 ("model_decrease", c_double), ("gain_ratio", c_double), ("lambda_", c_double),
                 ("accepted", c_int32), ("pcg_iters", c_int32), ("pcg_rel_residual", c_double),
                 ("n_fp64_blocks", c_int32), ("relinearized", c_int32), ("ms", c_double * 8),
-                ("matvec_ms", c_double), ("matvec_count", c_int32)]
+                ("matvec_ms", c_double), ("matvec_count", c_int32), ("coarse", c_int32)]
+
+
+class GnnBatch(ctypes.Structure):
+    _fields_ = [("n_nodes", c_int32), ("n_edges", c_int32), ("n_graphs", c_int32),
+                ("node_x", POINTER(ctypes.c_float)), ("node_type", POINTER(c_int32)), ("node_graph", POINTER(c_int32)),
+                ("node_unit", POINTER(ctypes.c_float)), ("edge_src", POINTER(c_int32)), ("edge_dst", POINTER(c_int32)),
+                ("edge_rev", POINTER(c_int32)), ("edge_x", POINTER(ctypes.c_float)), ("s_node", POINTER(c_double)),
+                ("s_edge", POINTER(c_double)), ("s_node_off", POINTER(c_int64)), ("s_edge_off", POINTER(c_int64)),
+                ("s_node_len", c_int64), ("s_edge_len", c_int64)]
 
 
 class Summary(ctypes.Structure):
@@ -72,6 +81,7 @@ def _load():
     D = POINTER(c_double)
     I32 = POINTER(c_int32)
     I64 = POINTER(c_int64)
+    F = POINTER(ctypes.c_float)
     sig = {
         "ba_default_options": (None, [POINTER(SolveOptions)]),
         "ba_create": (c_int32, [POINTER(ProblemDesc), POINTER(c_void_p)]),
@@ -91,6 +101,17 @@ def _load():
         "ba_pcg_solve": (c_int32, [H, c_double, c_int32, D, I32, D]),
         "ba_reduced_dim": (c_int32, [H, I64, I32]),
         "ba_set_gnn_weights": (c_int32, [H, c_void_p, c_size_t]),
+        "ba_gnn_param_count": (c_size_t, [c_int32]),
+        "ba_export_gnn_graph": (c_int32, [H, I32, I32, F, I32, I32, F, I32, I32, I32, F]),
+        "ba_normalized_matvec": (c_int32, [H, D, D]),
+        "ba_export_schur_dense": (c_int32, [H, D]),
+        "ba_gnn_create": (c_int32, [c_int32, c_int32, c_int32, POINTER(c_void_p)]),
+        "ba_gnn_set_params": (c_int32, [H, F, c_size_t]),
+        "ba_gnn_get_params": (c_int32, [H, F, c_size_t]),
+        "ba_gnn_forward": (c_int32, [H, POINTER(GnnBatch), F, D]),
+        "ba_gnn_train_step": (c_int32, [H, POINTER(GnnBatch), c_double, D, F]),
+        "ba_gnn_last_error": (ctypes.c_char_p, [H]),
+        "ba_gnn_destroy": (None, [H]),
         "ba_last_error": (ctypes.c_char_p, [H]),
         "ba_destroy": (None, [H]),
     }
@@ -282,3 +303,118 @@ class BA:
     def set_gnn_weights(self, blob: bytes):
         buf = ctypes.create_string_buffer(blob, len(blob))
         self._check(_lib.ba_set_gnn_weights(self._h, ctypes.cast(buf, c_void_p), len(blob)))
+
+    def export_gnn_graph(self):
+        """Block graph of the reduced system at the last linearisation (dict of arrays)."""
+        n, m = c_int32(), c_int32()
+        self._check(_lib.ba_export_gnn_graph(self._h, ctypes.byref(n), ctypes.byref(m), *([None] * 9)))
+        n, m = n.value, m.value
+        out = dict(node_x=np.zeros((n, 64), np.float32), node_type=np.zeros(n, np.int32),
+                   node_off=np.zeros(n, np.int32), node_unit=np.zeros((n, 9), np.float32),
+                   edge_src=np.zeros(m, np.int32), edge_dst=np.zeros(m, np.int32), edge_rev=np.zeros(m, np.int32),
+                   edge_x=np.zeros((m, 8), np.float32))
+        self._check(_lib.ba_export_gnn_graph(
+            self._h, None, None, _fp(out["node_x"]), _ip(out["node_type"]), _ip(out["node_off"]),
+            _fp(out["node_unit"]), _ip(out["edge_src"]), _ip(out["edge_dst"]), _ip(out["edge_rev"]),
+            _fp(out["edge_x"])))
+        return out
+
+    def export_schur_dense(self):
+        """Damped reduced matrix S of the last linearisation (dense, from n_A products)."""
+        nA, _ = self.reduced_dim()
+        S = np.zeros((nA, nA))
+        self._check(_lib.ba_export_schur_dense(self._h, _dp(S)))
+        return S
+
+    def normalized_matvec(self, x):
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        y = np.zeros_like(x)
+        self._check(_lib.ba_normalized_matvec(self._h, _dp(x), _dp(y)))
+        return y
+
+
+def _fp(a):
+    return None if a is None else a.ctypes.data_as(POINTER(ctypes.c_float))
+
+
+def _ip(a):
+    return None if a is None else a.ctypes.data_as(POINTER(c_int32))
+
+
+def _lp(a):
+    return None if a is None else a.ctypes.data_as(POINTER(c_int64))
+
+
+def gnn_param_count(camera_dof=9):
+    return int(_lib.ba_gnn_param_count(camera_dof))
+
+
+class GNNBatch:
+    """Host arrays of a ba_gnn_batch (kept alive while the struct is used)."""
+
+    def __init__(self, node_x, node_type, node_graph, node_unit, edge_src, edge_dst, edge_rev, edge_x, n_graphs,
+                 s_node=None, s_node_off=None, s_edge=None, s_edge_off=None):
+        self.a = dict(
+            node_x=np.ascontiguousarray(node_x, np.float32), node_type=np.ascontiguousarray(node_type, np.int32),
+            node_graph=np.ascontiguousarray(node_graph, np.int32), node_unit=np.ascontiguousarray(node_unit, np.float32),
+            edge_src=np.ascontiguousarray(edge_src, np.int32), edge_dst=np.ascontiguousarray(edge_dst, np.int32),
+            edge_rev=np.ascontiguousarray(edge_rev, np.int32), edge_x=np.ascontiguousarray(edge_x, np.float32))
+        for k in ("s_node", "s_edge"):
+            v = locals()[k]
+            self.a[k] = None if v is None else np.ascontiguousarray(v, np.float64)
+        for k in ("s_node_off", "s_edge_off"):
+            v = locals()[k]
+            self.a[k] = None if v is None else np.ascontiguousarray(v, np.int64)
+        a = self.a
+        self.n_nodes = len(a["node_type"])
+        self.s = GnnBatch(
+            self.n_nodes, len(a["edge_src"]), int(n_graphs), _fp(a["node_x"]), _ip(a["node_type"]),
+            _ip(a["node_graph"]), _fp(a["node_unit"]), _ip(a["edge_src"]), _ip(a["edge_dst"]), _ip(a["edge_rev"]),
+            _fp(a["edge_x"]), _dp(a["s_node"]), _dp(a["s_edge"]), _lp(a["s_node_off"]), _lp(a["s_edge_off"]),
+            0 if a["s_node"] is None else len(a["s_node"]), 0 if a["s_edge"] is None else len(a["s_edge"]))
+
+
+class GNN:
+    """The preconditioner network with its trainer on one device (include/ba.h)."""
+
+    def __init__(self, camera_dof=9, precision="bf16", device=0):
+        h = c_void_p()
+        st = _lib.ba_gnn_create(camera_dof, {"fp32": 0, "bf16": 1}[precision], device, ctypes.byref(h))
+        if st != BA_OK:
+            raise BAError(st, "ba_gnn_create failed")
+        self._h = h
+        self.camera_dof = camera_dof
+        self.n_params = gnn_param_count(camera_dof)
+
+    def _check(self, st):
+        if st != BA_OK:
+            raise BAError(st, _lib.ba_gnn_last_error(self._h).decode())
+
+    def close(self):
+        if self._h:
+            _lib.ba_gnn_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def set_params(self, p):
+        p = np.ascontiguousarray(p, np.float32)
+        self._check(_lib.ba_gnn_set_params(self._h, _fp(p), len(p)))
+
+    def get_params(self):
+        p = np.zeros(self.n_params, np.float32)
+        self._check(_lib.ba_gnn_get_params(self._h, _fp(p), len(p)))
+        return p
+
+    def forward(self, batch: GNNBatch, loss=False):
+        heads = np.zeros((batch.n_nodes, 72), np.float32)
+        L = c_double()
+        self._check(_lib.ba_gnn_forward(self._h, ctypes.byref(batch.s), _fp(heads), ctypes.byref(L) if loss else None))
+        return (heads, L.value) if loss else heads
+
+    def train_step(self, batch: GNNBatch, lr=0.0, want_grad=False):
+        L = c_double()
+        g = np.zeros(self.n_params, np.float32) if want_grad else None
+        self._check(_lib.ba_gnn_train_step(self._h, ctypes.byref(batch.s), float(lr), ctypes.byref(L), _fp(g)))
+        return (L.value, g) if want_grad else L.value

@@ -158,7 +158,13 @@ struct ba_handle {
   Dev d;
   DevAlloc alloc;
   double* hscal = nullptr;  // pinned host mirror of d.scal
-  ba_gnn::Net* gnn = nullptr;
+  // learned preconditioner: network (weights loaded by the caller) and the
+  // block graph of the reduced system, built at the symbolic phase
+  ba_gnn* gnn = nullptr;
+  ba_gnn_impl::Graph graph;
+  float* g_stat = nullptr;     // device copies of the structural node inputs and types
+  int32_t* g_type = nullptr;
+  float* g_x = nullptr;        // node input features of the last linearisation
   hipEvent_t ev[BA_PHASE_COUNT + 1] = {};
   bool events = false;
   std::vector<hipEvent_t> mv_ev;  // pool for per-product timing
@@ -424,6 +430,75 @@ void finalize(ba_handle* h) {
     max_blocks += (n + 255) / 256;
     if (n > INT32_MAX) throw BaError(BA_E_INVALID, "too many records in one family");
   }
+  // block graph of the reduced system: blocks are adjacent when they share a feature
+  {
+    const int nblocks = h->nc + h->ng + h->nv;
+    if (nblocks > 0 && nblocks <= ba_gnn_impl::MAX_GRAPH_NODES) {
+      const int nfeat = h->np + h->nl;
+      std::vector<int64_t> fb_off(nfeat + 1, 0), block_records(nblocks, 0);
+      auto block_of = [&](int fam, const Rec& r, int32_t out[2]) {
+        int k = 0;
+        if (r.cam >= 0) out[k++] = r.cam;
+        if (r.grp >= 0) out[k++] = (fam == 5 ? h->nc + h->ng : h->nc) + r.grp;
+        return k;
+      };
+      auto fid = [&](int fam, const Rec& r) { return fam_is_line(fam) ? h->np + r.feat : r.feat; };
+      for (int fam = 1; fam < NFAM; ++fam)
+        for (const Rec& r : R[fam]) {
+          int32_t b[2];
+          const int k = block_of(fam, r, b);
+          fb_off[fid(fam, r) + 1] += k;
+          for (int q = 0; q < k; ++q) block_records[b[q]]++;
+        }
+      for (int f = 0; f < nfeat; ++f) fb_off[f + 1] += fb_off[f];
+      std::vector<int32_t> fb(fb_off[nfeat]);
+      std::vector<int64_t> fill(fb_off.begin(), fb_off.end() - 1);
+      for (int fam = 1; fam < NFAM; ++fam)
+        for (const Rec& r : R[fam]) {
+          int32_t b[2];
+          const int k = block_of(fam, r, b);
+          for (int q = 0; q < k; ++q) fb[fill[fid(fam, r)]++] = b[q];
+        }
+      // distinct blocks per feature, compacted in place
+      std::vector<int64_t> off2(nfeat + 1, 0);
+      int64_t w = 0;
+      for (int f = 0; f < nfeat; ++f) {
+        auto b = fb.begin() + fb_off[f], e = fb.begin() + fb_off[f + 1];
+        std::sort(b, e);
+        e = std::unique(b, e);
+        for (auto it = b; it != e; ++it) fb[w++] = *it;
+        off2[f + 1] = w;
+      }
+      fb.resize(w);
+      // scene scale: RMS distance of the input camera centres -R^T t from their mean
+      double s0 = 0, mean[3] = {0, 0, 0};
+      std::vector<double> ctr((size_t)3 * h->nc);
+      for (int i = 0; i < h->nc; ++i) {
+        const double* c = &h->cam[(size_t)CAM_STRIDE * i];
+        for (int k = 0; k < 3; ++k) {
+          ctr[3 * i + k] = -(c[k] * c[9] + c[3 + k] * c[10] + c[6 + k] * c[11]);
+          mean[k] += ctr[3 * i + k] / h->nc;
+        }
+      }
+      for (int i = 0; i < h->nc; ++i)
+        for (int k = 0; k < 3; ++k) s0 += (ctr[3 * i + k] - mean[k]) * (ctr[3 * i + k] - mean[k]) / h->nc;
+      s0 = std::sqrt(s0);
+      if (!(s0 > 0) || !std::isfinite(s0)) s0 = 1.0;
+      ba_gnn_impl::build_graph(h->graph, h->nc, h->ng, h->nv, h->CD, off2, fb, block_records, s0);
+    }
+    if (h->graph.valid) {
+      const auto& G = h->graph;
+      h->g_stat = A.get<float>(G.node_static.size());
+      h->g_type = A.get<int32_t>(G.n_nodes);
+      h->g_x = A.get<float>(G.node_static.size());
+      d.Zc = A.get<double>((size_t)COARSE_K * d.nA);
+      d.SZc = A.get<double>((size_t)COARSE_K * d.nA);
+      d.Einv = A.get<double>((size_t)COARSE_K * COARSE_K);
+      d.Ztb = A.get<double>((size_t)COARSE_K + COARSE_K * COARSE_K);
+      upload(h, h->g_stat, G.node_static);
+      upload(h, h->g_type, G.node_type);
+    }
+  }
   // camera-major lists
   auto cam_major = [&](int fam, bool runs, int32_t*& idx_or_start, int32_t*& cnt, int32_t*& off) {
     const auto& v = R[fam];
@@ -568,7 +643,7 @@ void finalize(ba_handle* h) {
   const int64_t fe_blocks = (h->np + 255) / 256 + (h->nl + 255) / 256;
   d.red = A.get<double>((size_t)std::max<int64_t>(2 * std::max(max_blocks, fe_blocks), 64));
   HIPCHK(hipHostMalloc((void**)&h->hscal, SC_COUNT * sizeof(double), hipHostMallocDefault));
-  if (h->gnn) ba_gnn::attach(h->gnn, h->d, h->stream);
+  if (h->gnn) ba_gnn_impl::attach(h->gnn, h->graph);
   check_launch("finalize");
   sync(h);
   h->finalized = true;
@@ -601,7 +676,12 @@ void assemble(ba_handle* h, double lambda, double kappa_max) {
   launch_feature_invert(h->d, lambda, kappa_max, h->stream);
   launch_camera_pass_b(h->d, lambda, h->stream);
   launch_precond_blockjacobi(h->d, h->stream);
-  if (h->precond == BA_PC_LEARNED && h->gnn && ba_gnn::ready(h->gnn)) ba_gnn::apply(h->gnn, h->d, lambda, h->stream);
+  h->d.coarse = 0;
+  if (h->precond == BA_PC_LEARNED && ba_gnn_impl::ready(h->gnn) && h->d.Zc) {
+    ba_gnn_impl::apply(h->gnn, h->d, lambda, h->stream);
+    launch_coarse_setup(h->d, lambda, h->stream);
+    h->d.coarse = 1;
+  }
   check_launch("assemble");
   h->last_lambda = lambda;
 }
@@ -730,7 +810,6 @@ void accept_candidate(ba_handle* h) {
   Dev& d = h->d;
   std::swap(d.cam64, d.cam64n); std::swap(d.pt64, d.pt64n); std::swap(d.ln64, d.ln64n);
   std::swap(d.pl64, d.pl64n); std::swap(d.vp64, d.vp64n);
-  if (h->gnn) ba_gnn::attach(h->gnn, h->d, h->stream);
 }
 
 void current_cost(ba_handle* h) {
@@ -773,6 +852,7 @@ void do_step(ba_handle* h, const ba_solve_options& o, ba_step_report* rep) {
   r.pcg_iters = pcg(h, h->lambda, o.pcg_tol, o.pcg_max_iters, o.time_kernels ? &mv_ms : nullptr);
   r.matvec_ms = mv_ms;
   r.matvec_count = o.time_kernels ? r.pcg_iters + (h->hscal[SC_BREAK] != 0.0 ? 1 : 0) : 0;
+  r.coarse = h->d.coarse && h->hscal[SC_COARSE] != 0.0 ? 1 : 0;
   record(h, 4);
   const double rr = h->hscal[SC_RR], bb = h->hscal[SC_BB];
   r.pcg_rel_residual = bb > 0 ? std::sqrt(rr / bb) : 0.0;
@@ -1212,10 +1292,89 @@ ba_status ba_set_gnn_weights(ba_handle* h, const void* blob, size_t bytes) {
   if (!h || !blob) return BA_E_INVALID;
   return guard(h, [&] {
     set_device(h);
-    if (!h->gnn) h->gnn = ba_gnn::create();
+    if (!h->gnn) {
+      std::string e;
+      h->gnn = ba_gnn_impl::create(h->CD, 1, h->device, e);
+      if (!h->gnn) throw BaError(BA_E_DEVICE, e);
+    }
     std::string e;
-    if (!ba_gnn::load(h->gnn, blob, bytes, h->stream, e)) throw BaError(BA_E_INVALID, e);
-    if (h->finalized) ba_gnn::attach(h->gnn, h->d, h->stream);
+    if (!ba_gnn_impl::load(h->gnn, blob, bytes, e)) throw BaError(BA_E_INVALID, e);
+    if (h->finalized) ba_gnn_impl::attach(h->gnn, h->graph);
+  });
+}
+
+ba_status ba_export_gnn_graph(ba_handle* h, int32_t* n_nodes, int32_t* n_edges, float* node_x, int32_t* node_type,
+                              int32_t* node_off, float* node_unit, int32_t* edge_src, int32_t* edge_dst,
+                              int32_t* edge_rev, float* edge_x) {
+  if (!h) return BA_E_INVALID;
+  return guard(h, [&] {
+    if (!h->finalized) throw BaError(BA_E_STATE, "no linearisation yet");
+    const auto& G = h->graph;
+    if (!G.valid) throw BaError(BA_E_STATE, "the block graph is built for 1 to " +
+                                std::to_string(ba_gnn_impl::MAX_GRAPH_NODES) + " camera / plane / VP blocks");
+    if (n_nodes) *n_nodes = G.n_nodes;
+    if (n_edges) *n_edges = G.n_edges;
+    set_device(h);
+    if (node_x) {
+      ba_gnn_impl::launch_node_features(h->d, h->g_stat, h->g_type, G.n_nodes, h->last_lambda, G.scale, h->g_x,
+                                        h->stream);
+      check_launch("node features");
+      HIPCHK(hipMemcpyAsync(node_x, h->g_x, G.node_static.size() * 4, hipMemcpyDeviceToHost, h->stream));
+      sync(h);
+    }
+    if (node_type) std::copy(G.node_type.begin(), G.node_type.end(), node_type);
+    if (node_off) std::copy(G.node_off.begin(), G.node_off.end(), node_off);
+    if (node_unit)
+      for (int i = 0; i < G.n_nodes; ++i) {
+        float* u = node_unit + 9 * (size_t)i;
+        for (int k = 0; k < 9; ++k) u[k] = 0.0f;
+        const int t = G.node_type[i];
+        for (int k = 0; k < G.node_size[i]; ++k)
+          u[k] = (float)((t == 0 && k >= 3 && k < 6) || (t == 1 && k == 2) ? G.scale : 1.0);
+      }
+    if (edge_src) std::copy(G.edge_src.begin(), G.edge_src.end(), edge_src);
+    if (edge_dst) std::copy(G.edge_dst.begin(), G.edge_dst.end(), edge_dst);
+    if (edge_rev) std::copy(G.edge_rev.begin(), G.edge_rev.end(), edge_rev);
+    if (edge_x) std::copy(G.edge_x.begin(), G.edge_x.end(), edge_x);
+  });
+}
+
+ba_status ba_export_schur_dense(ba_handle* h, double* S) {
+  if (!h || !S) return BA_E_INVALID;
+  return guard(h, [&] {
+    if (!h->finalized) throw BaError(BA_E_STATE, "no linearisation yet");
+    set_device(h);
+    const Dev& d = h->d;
+    const size_t bytes = (size_t)d.nA * d.nA * sizeof(double);
+    if (bytes == 0) return;
+    double* Sd = nullptr;
+    HIPCHK(hipMalloc((void**)&Sd, bytes));
+    try {
+      launch_dense_schur(d, h->last_lambda, Sd, h->stream);
+      check_launch("dense reduced system");
+      HIPCHK(hipMemcpyAsync(S, Sd, bytes, hipMemcpyDeviceToHost, h->stream));
+      sync(h);
+    } catch (...) {
+      (void)hipFree(Sd);
+      throw;
+    }
+    HIPCHK(hipFree(Sd));
+  });
+}
+
+ba_status ba_normalized_matvec(ba_handle* h, const double* x, double* y) {
+  if (!h || !x || !y) return BA_E_INVALID;
+  return guard(h, [&] {
+    if (!h->finalized) throw BaError(BA_E_STATE, "no linearisation yet");
+    set_device(h);
+    const Dev& d = h->d;
+    HIPCHK(hipMemcpyAsync(d.z, x, d.nA * 8, hipMemcpyHostToDevice, h->stream));
+    ba_gnn_impl::launch_block_tri(d, d.z, d.p, true, h->stream);
+    launch_schur_matvec(d, d.p, d.q, h->last_lambda, h->stream);
+    ba_gnn_impl::launch_block_tri(d, d.q, d.z, false, h->stream);
+    check_launch("normalized product");
+    HIPCHK(hipMemcpyAsync(y, d.z, d.nA * 8, hipMemcpyDeviceToHost, h->stream));
+    sync(h);
   });
 }
 
@@ -1225,7 +1384,7 @@ void ba_destroy(ba_handle* h) {
   if (!h) return;
   (void)hipSetDevice(h->device);
   if (h->stream) (void)hipStreamSynchronize(h->stream);
-  if (h->gnn) ba_gnn::destroy(h->gnn);
+  if (h->gnn) ba_gnn_impl::destroy(h->gnn);
   h->alloc.free_all();
   if (h->hscal) (void)hipHostFree(h->hscal);
   if (h->events)

@@ -137,6 +137,8 @@ void launch_pcg_init(const Dev& d, double tol, int max_iters, hipStream_t s);
 void launch_pcg_product(const Dev& d, hipStream_t s);                  // q' = partial J_a^T(...) products
 void launch_pcg_update(const Dev& d, double lambda, int iter, hipStream_t s);  // q = S p, then the CG update
 void launch_schur_matvec(const Dev& d, const double* xin, double* yout, double lambda, hipStream_t s);
+// S (nA x nA, device; column c = S e_c) by nA products
+void launch_dense_schur(const Dev& d, double lambda, double* S, hipStream_t s);
 // E = Z^T S Z from the coarse basis d.Zc (COARSE_K products), its inverse and SC_COARSE
 void launch_coarse_setup(const Dev& d, double lambda, hipStream_t s);
 void launch_backsub(const Dev& d, hipStream_t s);                        // h_f, model decrease terms

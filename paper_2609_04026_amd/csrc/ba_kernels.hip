@@ -1662,6 +1662,17 @@ void launch_schur_matvec(const Dev& d, const double* xin, double* yout, double l
   });
 }
 
+__global__ void k_unit_vector(double* v, int n, int c) {
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) v[e] = e == c ? 1.0 : 0.0;
+}
+
+void launch_dense_schur(const Dev& d, double lambda, double* S, hipStream_t s) {
+  for (int c = 0; c < d.nA; ++c) {
+    k_unit_vector<<<std::min(64u, nblk(d.nA, 256)), 256, 0, s>>>(d.z, d.nA, c);
+    launch_schur_matvec(d, d.z, S + (int64_t)c * d.nA, lambda, s);
+  }
+}
+
 // E[a][b] = Z_a . (S Z)_b, one workgroup per entry
 __global__ __launch_bounds__(256) void k_coarse_e(Dev d, double* E) {
   __shared__ double lds[5];

@@ -1,0 +1,170 @@
+"""The learned coarse-space preconditioner on the GPU against the FP64 oracle.
+
+Through the C ABI: the block graph and node inputs the library builds, the
+network's forward pass, loss and gradient (FP32 debug precision and the
+BF16-MFMA training precision), one Adam step, the dense reduced matrix
+export, and PCG with the coarse correction against the oracle's PCG with
+the oracle's own coarse basis from the same weights.
+
+Tolerances: FP32 heads / loss 1e-4 relative, gradient 1e-3 of each
+tensor's norm (FP32 accumulation over all nodes and edges); BF16 (8-bit
+mantissa operands) 5e-2 on heads and loss, 0.15 of each gradient norm.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import gnn, lm
+from scenegen import make_scene, small_config
+
+pytestmark = pytest.mark.gpu
+
+
+def _oracle_system(sc, lam, precision_state=None):
+    prob = lm.Problem(sc)
+    st = prob.state0()
+    S = lm.schur(prob, lm.linearize(prob, st), lam)["S"]
+    S = 0.5 * (S + S.T)
+    g = gnn.block_graph(prob)
+    s0 = gnn.scene_scale(sc["cameras"])
+    x = gnn.node_inputs(g, [S[o:o + n, o:o + n] for o, n in zip(g["offsets"], g["sizes"])], lam, st, s0)
+    units = gnn.unit_scales(g, s0, prob.camera_dof)
+    return dict(prob=prob, st=st, S=S, graph=g, x=x, units=units, s0=s0, lam=lam)
+
+
+def _as_library_graph(o):
+    g = o["graph"]
+    return dict(node_x=o["x"].astype(np.float32), node_type=g["node_type"].astype(np.int32),
+                node_off=g["offsets"].astype(np.int32), node_unit=o["units"].astype(np.float32),
+                edge_src=g["edge_src"].astype(np.int32), edge_dst=g["edge_dst"].astype(np.int32),
+                edge_x=g["edge_x"].astype(np.float32))
+
+
+SCENES = [
+    lambda: make_scene(small_config(n_cams=6, n_points=30, n_lines=10, n_planes=2, n_vps=2), seed=7),
+    lambda: make_scene(small_config(n_cams=9, n_points=50, n_lines=16, n_planes=3, n_vps=3), seed=11),
+]
+
+
+@pytest.fixture(scope="module")
+def systems():
+    print("[case] gnn oracle systems", flush=True)
+    return [_oracle_system(f(), lam) for f, lam in zip(SCENES, (1e-3, 1e-2))]
+
+
+def test_graph_and_inputs_match_oracle(systems):
+    from paper_2609_04026_amd.binding import BA
+    for k, f in enumerate(SCENES):
+        o = systems[k]
+        ba = BA.from_scene(f(), precision="fp64")
+        ba.linearize(o["lam"])
+        g = ba.export_gnn_graph()
+        og = o["graph"]
+        assert np.array_equal(g["node_type"], og["node_type"])
+        assert np.array_equal(g["node_off"], og["offsets"])
+        assert np.array_equal(g["edge_src"], og["edge_src"]) and np.array_equal(g["edge_dst"], og["edge_dst"])
+        assert np.allclose(g["edge_x"], og["edge_x"], atol=1e-6)
+        assert np.array_equal(g["edge_src"][g["edge_rev"]], g["edge_dst"])
+        assert np.allclose(g["node_unit"], o["units"], rtol=1e-6)
+        assert np.allclose(g["node_x"], o["x"], atol=2e-5, rtol=1e-5), np.abs(g["node_x"] - o["x"]).max()
+        S = ba.export_schur_dense()
+        assert np.abs(S - o["S"]).max() <= 1e-9 * np.abs(o["S"]).max()
+        ba.close()
+
+
+def _batch(systems):
+    from paper_2609_04026_amd.precond_data import make_batch, system_from_dense
+    return make_batch([system_from_dense(_as_library_graph(o), o["S"]) for o in systems])
+
+
+def _oracle_heads_loss_grads(params, systems, cd=9):
+    sysd = [dict(node_x=o["x"].astype(np.float32).astype(np.float64), graph=o["graph"], S=o["S"], units=o["units"])
+            for o in systems]
+    L, grads = gnn.loss_and_grads(params, sysd, cd)
+    heads = []
+    for o in sysd:
+        g = o["graph"]
+        Y = gnn.forward(params, o["node_x"], g["node_type"], g["edge_src"], g["edge_dst"], g["edge_x"], cd)
+        for y in Y:
+            h = np.zeros((9, gnn.K))
+            h[:y.shape[0]] = y.detach().numpy()
+            heads.append(h.ravel())
+    return np.array(heads), L, grads
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_forward_loss_and_gradient_match_oracle(systems, precision):
+    from paper_2609_04026_amd.binding import GNN
+    print(f"[case] gnn forward/backward {precision}", flush=True)
+    params = gnn.init_params(9, seed=21)
+    # round the weights to FP32 on both sides
+    params = gnn.unpack(gnn.pack(params).tobytes())
+    heads_o, L_o, grads_o = _oracle_heads_loss_grads(params, systems)
+    batch = _batch(systems)
+    net = GNN(9, precision)
+    net.set_params(gnn.pack(params))
+    heads, L = net.forward(batch, loss=True)
+    heads = heads[np.argsort(batch.order)]  # back to the systems' node order
+    tol_h, tol_L, tol_g = (1e-4, 1e-4, 1e-3) if precision == "fp32" else (5e-2, 5e-2, 0.15)
+    err_h = np.linalg.norm(heads - heads_o) / np.linalg.norm(heads_o)
+    assert err_h <= tol_h, err_h
+    assert abs(L - L_o) <= tol_L * abs(L_o), (L, L_o)
+    L2, grad = net.train_step(batch, lr=0.0, want_grad=True)
+    assert abs(L2 - L) <= 1e-6 * abs(L)
+    g_o = gnn.pack(grads_o).astype(np.float64)
+    o = 0
+    for name, shp in gnn.param_shapes(9):
+        n = int(np.prod(shp))
+        a, b = grad[o:o + n].astype(np.float64), g_o[o:o + n]
+        err = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+        assert err <= tol_g, (name, err)
+        o += n
+    net.close()
+
+
+def test_adam_first_step(systems):
+    """With lr > 0 the first Adam step moves each weight by lr g / (|g| + eps)."""
+    from paper_2609_04026_amd.binding import GNN
+    params = gnn.pack(gnn.init_params(9, seed=22))
+    batch = _batch(systems)
+    net = GNN(9, "fp32")
+    net.set_params(params)
+    _, grad = net.train_step(batch, lr=0.0, want_grad=True)
+    lr = 1e-3
+    net.train_step(batch, lr=lr)
+    p1 = net.get_params().astype(np.float64)
+    g = grad.astype(np.float64)
+    expect = params.astype(np.float64) - lr * g / (np.abs(g) + 1e-8)
+    assert np.abs(p1 - expect).max() <= 1e-6, np.abs(p1 - expect).max()
+    net.close()
+
+
+def test_coarse_pcg_matches_oracle():
+    """PCG with the coarse correction from the same weights: the library and
+    the oracle reach the same solution in the same number of iterations (up
+    to the BF16 rounding of the network)."""
+    from paper_2609_04026_amd.binding import BA
+    sc = make_scene(small_config(n_cams=12, n_points=80, n_lines=20, n_planes=3, n_vps=3), seed=31)
+    lam = 1e-4
+    o = _oracle_system(sc, lam)
+    params = gnn.unpack(gnn.pack(gnn.init_params(9, seed=23)).tobytes())
+    g = o["graph"]
+    Y = gnn.forward(params, o["x"].astype(np.float32).astype(np.float64), g["node_type"], g["edge_src"],
+                    g["edge_dst"], g["edge_x"], 9)
+    Z = gnn.coarse_basis(Y, o["units"]).detach().numpy()
+    prob = o["prob"]
+    b = lm.schur(prob, lm.linearize(prob, o["st"]), lam)["b"]
+    x_ref = np.linalg.solve(o["S"], b)
+    _, it_bj = gnn.pcg(o["S"], b, gnn.two_level(o["S"], g["sizes"], None), tol=1e-8)
+    _, it_cs = gnn.pcg(o["S"], b, gnn.two_level(o["S"], g["sizes"], Z), tol=1e-8)
+    for precond, it_ref in (("jacobi", it_bj), ("learned", it_cs)):
+        ba = BA.from_scene(sc, precision="fp64", precond=precond)
+        ba.set_gnn_weights(gnn.pack(params).tobytes())
+        ba.linearize(lam)
+        x, it, rel = ba.pcg_solve(tol=1e-8, max_iters=500)
+        print(precond, "iterations", it, "oracle", it_ref, flush=True)
+        assert np.linalg.norm(x - x_ref) <= 1e-5 * np.linalg.norm(x_ref)
+        assert abs(it - it_ref) <= max(2, it_ref // 10), (precond, it, it_ref)
+        rep = ba.lm_step(pcg_tol=1e-8)
+        assert rep["coarse"] == (1 if precond == "learned" else 0)
+        ba.close()
