@@ -57,7 +57,13 @@ typedef enum {
 } ba_status;
 
 typedef enum { BA_PREC_FP64 = 0, BA_PREC_MIXED = 1 } ba_precision;
-typedef enum { BA_PC_BLOCK_JACOBI = 0, BA_PC_LEARNED = 1 } ba_precond;
+/* PCG preconditioner of the reduced system.  BLOCK_JACOBI: the inverses of
+ * the diagonal blocks of S (the paper's choice).  GAUGE: two-level, block-
+ * Jacobi plus the coarse space of the 7 similarity-gauge directions (world
+ * rotation, translation, scale of every camera / plane / VP).  LEARNED: the
+ * same plus 8 directions predicted by the network (needs ba_set_gnn_weights;
+ * block-Jacobi alone without weights or graph). */
+typedef enum { BA_PC_BLOCK_JACOBI = 0, BA_PC_LEARNED = 1, BA_PC_GAUGE = 2 } ba_precond;
 
 /* Observation / association kinds accepted by ba_add_observations. */
 typedef enum {
@@ -127,7 +133,7 @@ typedef struct {
   double ms[BA_PHASE_COUNT];     /* device time per phase */
   double matvec_ms;              /* with time_kernels: summed duration of the PCG products */
   int32_t matvec_count;          /* number of those products */
-  int32_t coarse;                /* 1: the learned coarse correction was active in this step's PCG */
+  int32_t coarse;                /* columns of the coarse space used by this step's PCG (0: block-Jacobi) */
 } ba_step_report;
 
 typedef struct {
@@ -237,8 +243,10 @@ ba_status ba_reduced_dim(const ba_handle *h, int64_t *n_A, int32_t *camera_dof);
  * the paper preconditions the reduced-system CG with the inverses of its
  * diagonal blocks, which leaves the slow global modes of BA, e.g. the
  * similarity gauge, to CG).  A message-passing network predicts K = 8
- * vectors per block, Z (n_A x 8), and PCG uses
- *     P r = M r + Z E^-1 Z^T r,   M = blockdiag(S_ii)^-1,   E = Z^T S Z
+ * vectors per block; together with the 7 similarity-gauge directions they
+ * span the coarse space Z (n_A x 15).  With E = Z^T S Z, Q = Z E^-1 Z^T and
+ * M = blockdiag(S_ii)^-1, PCG starts from x0 = Q b and uses
+ *     P r = (I - Q S) M r + Q r
  * (M alone when E is not positive definite).
  * Graph: one node per camera / plane / VP block of the reduced system, in
  * that order; directed edges both ways between blocks that share a feature,
@@ -258,7 +266,8 @@ ba_status ba_reduced_dim(const ba_handle *h, int64_t *n_A, int32_t *camera_dof);
  *   Y_i = h_i W_t + b_t for the node's type, read as n_t x 8 (row-major).
  * Z_i = diag(u_i) Y_i with row scales u: camera (1,1,1, s0,s0,s0, 1,1,1),
  * plane (1, 1, s0), VP (1, 1).  Training loss per system:
- * tr((Z^T D Z)^-1 Z^T S Z), D = blockdiag(S_ii); a batch takes the mean.
+ * tr((Z^T D Z)^-1 Z^T S Z) with Z = [gauge (7 columns), network (8)],
+ * D = blockdiag(S_ii); a batch takes the mean.
  * Parameters: float32 blob in the order W_in (64x64) b_in, (W_e (72x64)
  * b_e W_s (64x64) b_s) x3, (W_t (64 x 8 n_t) b_t) for cameras, planes,
  * VPs; matrices row-major.
@@ -291,6 +300,14 @@ ba_status ba_export_gnn_graph(ba_handle *h, int32_t *n_nodes, int32_t *n_edges, 
  * training data and tests).  Temporary device memory: 8 n_A^2 bytes. */
 ba_status ba_export_schur_dense(ba_handle *h, double *S);
 
+/* The 7 similarity-gauge directions of the reduced parameters at the current
+ * parameters (world rotation about x, y, z; translation along x, y, z;
+ * scale), n_A x 7 doubles row-major (caller-allocated).  Cameras: rotation w
+ * gives dtheta = -R w, dt = (R w) x t; translation u gives dt = -R u; scale s
+ * gives dt = s t.  Planes: (b1, b2) . (w x n), dw = -n . u, dw = s w.  VPs:
+ * (b1, b2) . (w x v). */
+ba_status ba_export_gauge_basis(ba_handle *h, double *G);
+
 /* y = L^-1 S L^-T x with S_ii = L_i L_i^T (the block-normalised reduced
  * system of the last ba_linearize); x, y: n_A doubles (host). */
 ba_status ba_normalized_matvec(ba_handle *h, const double *x, double *y);
@@ -299,7 +316,8 @@ ba_status ba_normalized_matvec(ba_handle *h, const double *x, double *y);
  * within the batch (cameras, planes, VPs); node_graph: each node's system,
  * 0 .. n_graphs-1; node_unit: n x 9 row scales.  Edges join nodes of one
  * system, sorted by destination, with edge_rev[e] the index of the reverse
- * edge.  S blocks (FP64, row-major; needed for the loss): the damped
+ * edge.  For the loss: the gauge block of every node (ba_export_gauge_basis
+ * rows of the node's entries) and the S blocks (FP64, row-major): the damped
  * diagonal block of node i (n_i x n_i) at s_node + s_node_off[i], the block
  * S_{dst,src} of edge e (n_dst x n_src) at s_edge + s_edge_off[e]; the
  * offsets must stay inside s_node_len / s_edge_len. */
@@ -308,6 +326,7 @@ typedef struct {
   const float *node_x;
   const int32_t *node_type, *node_graph;
   const float *node_unit;
+  const double *node_gauge;   /* n x 9 x 7: the gauge rows of each node (row-major, zero-padded); loss only */
   const int32_t *edge_src, *edge_dst, *edge_rev;
   const float *edge_x;
   const double *s_node, *s_edge;

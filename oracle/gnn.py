@@ -1,17 +1,23 @@
 """FP64 reference of the learned coarse-space correction (test infrastructure).
 
 The paper solves the reduced camera + group system by CG preconditioned
-with the inverses of its diagonal blocks.  The learned correction is this
-project's addition to that method: a small message-passing network over
-the block graph of the reduced system predicts K = 8 vectors per block,
-Z (n_A x K), and the preconditioner becomes
+with the inverses of its diagonal blocks.  The coarse-space correction is
+this project's addition to that method.  Its coarse basis has two parts:
 
-    P r = M r + Z (Z^T S Z)^-1 Z^T r,      M = blockdiag(S_ii)^-1,
+* G (n_A x 7): the similarity gauge of the reduced parameters - the first-
+  order change of every camera, plane and VP under a world rotation (3),
+  translation (3) and scale (1), in the solver's tangent coordinates.  The
+  cost is invariant under these motions, so J [G; G_features] = 0 and the
+  undamped reduced matrix annihilates G: these are the slowest modes of the
+  damped system (eigenvalues of order lambda after block normalisation).
+* Z_net (n_A x 8): vectors predicted by a small message-passing network
+  over the block graph, trained to span the next slowest modes.
 
-an additive two-level preconditioner (M alone when the coarse matrix is not
-positive definite).  Z should span the slow directions of the
-block-normalised system (on BA problems: the similarity gauge and the other
-near-null modes), which block-Jacobi cannot reach.
+With Z = [G, Z_net], E = Z^T S Z, Q = Z E^-1 Z^T and M = blockdiag(S_ii)^-1,
+PCG starts from x0 = Q b and uses the two-level preconditioner
+    P r = (I - Q S) M r + Q r
+(the "A-DEF2" form: deflation of span(Z) applied after block-Jacobi), with
+M alone when E is not positive definite.
 
 This module is a plain PyTorch-CPU float64 implementation of every
 definition below; gradients come from autograd and are checked against
@@ -20,6 +26,12 @@ smoke check and the CPU baseline.
 
 Definitions (written independently by the HIP kernels):
 
+* gauge: camera (left perturbation R <- Exp(dtheta) R, t <- Exp(dtheta) t
+  + dt): rotation w: dtheta = -R w, dt = (R w) x t; translation u: dt = -R u;
+  scale s: dt = s t.  Plane (n, w), tangent (b1, b2, w): rotation w:
+  (b1, b2) . (w x n); translation u: dw = -n . u; scale s: dw = s w.  VP v:
+  rotation w: (b1, b2) . (w x v).  Columns: rotation about x, y, z,
+  translation along x, y, z, scale;
 * graph: one node per block of the reduced system, cameras first, then
   planes, then VPs (the order of the reduced vector); a directed edge j -> i
   for every ordered pair of distinct blocks that share a feature (a point or
@@ -28,11 +40,12 @@ Definitions (written independently by the HIP kernels):
   their mean (1 when that is zero or there are no cameras);
 * node input x_i (64): [0, n) log(u_p^2 S_pp) - mean_p log(u_p^2 S_pp) of the
   damped block S_ii (u_i the unit scales below, so that the inputs do not
-  change when the whole scene is scaled); from 9, the strictly lower correlations S_pq / sqrt(S_pp S_qq)
-  row by row; 45 log(lambda); 46 log(1 + records touching the block);
-  47 log(1 + in-degree); 48 + type: 1; geometry from 51: camera R row-major
-  (9) then t / s0 (3); plane n (3), w / s0, b1 (3), b2 (3); VP v (3), b1 (3),
-  b2 (3), with (b1, b2) the tangent basis of the parameter's sphere;
+  change when the whole scene is scaled); from 9, the strictly lower
+  correlations S_pq / sqrt(S_pp S_qq) row by row; 45 log(lambda);
+  46 log(1 + records touching the block); 47 log(1 + in-degree);
+  48 + type: 1; geometry from 51: camera R row-major (9) then t / s0 (3);
+  plane n (3), w / s0, b1 (3), b2 (3); VP v (3), b1 (3), b2 (3), with
+  (b1, b2) the tangent basis of the parameter's sphere;
 * edge input e_ji (8): log(1 + shared features), then one-hot
   camera-camera / camera-plane / camera-VP / group-group, then zeros;
 * network, hidden width H = 64,
@@ -42,12 +55,12 @@ Definitions (written independently by the HIP kernels):
               h = gelu(h W_s + b_s + m) + h
     Y_i = h_i W_t + b_t for the node's type t, read as an n_t x K matrix
     (row-major);
-* Z_i = diag(u_i) Y_i with unit scales u: camera (1,1,1, s0,s0,s0, 1,1,1)
-  (rotation, translation, intrinsics), plane (1, 1, s0), VP (1, 1);
-* training loss, per system: tr((Z^T D Z)^-1 Z^T S Z) with D =
-  blockdiag(S_ii) (the sum of the Ritz values of the block-normalised S on
-  span(Z), smallest when Z spans its K slowest directions); a batch takes
-  the mean over its systems.
+* Z_net,i = diag(u_i) Y_i with unit scales u: camera (1,1,1, s0,s0,s0,
+  1,1,1) (rotation, translation, intrinsics), plane (1, 1, s0), VP (1, 1);
+* training loss, per system: tr((Z^T D Z)^-1 Z^T S Z) with Z = [G, Z_net]
+  and D = blockdiag(S_ii) (the sum of the Ritz values of the block-
+  normalised S on span(Z), smallest when Z spans its 15 slowest
+  directions); a batch takes the mean over its systems.
 """
 from __future__ import annotations
 
@@ -60,7 +73,8 @@ H = 64
 NODE_IN = 64
 EDGE_IN = 8
 LAYERS = 3
-K = 8
+K = 8          # network columns
+K_GAUGE = 7    # analytic gauge columns
 TYPE_CAM, TYPE_PLANE, TYPE_VP = 0, 1, 2
 
 
@@ -120,6 +134,40 @@ def scene_scale(cameras):
     c = -np.einsum("nji,nj->ni", R, cams[:, 4:7])
     s = math.sqrt(float(np.mean(np.sum((c - c.mean(axis=0)) ** 2, axis=1))))
     return s if s > 0 and math.isfinite(s) else 1.0
+
+
+def gauge_basis(prob, state):
+    """G (n_A x 7): first-order motion of the reduced parameters under a world
+    rotation (3), translation (3) and scale (1)."""
+    from oracle.model import s2_basis
+    cd = prob.camera_dof
+    nc, npl, nvp = prob.n["cam"], prob.n["pl"], prob.n["vp"]
+    G = np.zeros((prob.nA, K_GAUGE))
+    E3 = np.eye(3)
+    for i in range(nc):
+        R, t = state.cam_R[i], state.cam_t[i]
+        o = prob.off["cam"] + cd * i
+        for k in range(3):
+            Rw = R @ E3[k]
+            G[o:o + 3, k] = -Rw
+            G[o + 3:o + 6, k] = np.cross(Rw, t)
+            G[o + 3:o + 6, 3 + k] = -Rw
+        G[o + 3:o + 6, 6] = t
+    for g in range(npl):
+        n, w = state.pl_n[g], state.pl_w[g]
+        B = s2_basis(n)
+        o = prob.off["pl"] + 3 * g
+        for k in range(3):
+            G[o:o + 2, k] = B.T @ np.cross(E3[k], n)
+            G[o + 2, 3 + k] = -n[k]
+        G[o + 2, 6] = w
+    for v in range(nvp):
+        d = state.vp[v]
+        B = s2_basis(d)
+        o = prob.off["vp"] + 2 * v
+        for k in range(3):
+            G[o:o + 2, k] = B.T @ np.cross(E3[k], d)
+    return G
 
 
 def block_graph(prob):
@@ -285,14 +333,18 @@ def coarse_loss(Z, S, sizes):
     return torch.trace(torch.linalg.solve(G, A))
 
 
+def full_basis(G, Y, units):
+    """Z = [G, Z_net] (n_A x 15)."""
+    return torch.cat([_t(G), coarse_basis(Y, units)], dim=1)
+
+
 def batch_loss(params, systems, camera_dof=9):
-    """Mean coarse loss over systems; each a dict with node_x, graph, S (dense), units."""
+    """Mean coarse loss over systems; each a dict with node_x, graph, S (dense), units, gauge."""
     total = torch.zeros((), dtype=torch.float64)
     for s in systems:
         g = s["graph"]
         Y = forward(params, s["node_x"], g["node_type"], g["edge_src"], g["edge_dst"], g["edge_x"], camera_dof)
-        Z = coarse_basis(Y, s["units"])
-        total = total + coarse_loss(Z, s["S"], g["sizes"])
+        total = total + coarse_loss(full_basis(s["gauge"], Y, s["units"]), s["S"], g["sizes"])
     return total / len(systems)
 
 
@@ -318,29 +370,34 @@ def block_jacobi(S, sizes):
 
 
 def two_level(S, sizes, Z):
-    """Dense P = M + Z (Z^T S Z)^-1 Z^T (M alone when Z^T S Z is not positive definite)."""
+    """Dense A-DEF2 preconditioner (I - Q S) M + Q with Q = Z (Z^T S Z)^-1 Z^T,
+    and the start vector's map Q (None, None for M alone, also when Z^T S Z is
+    not positive definite)."""
     M = block_jacobi(S, sizes)
     if Z is None:
-        return M
+        return M, None
     E = Z.T @ S @ Z
     try:
         np.linalg.cholesky(E)
     except np.linalg.LinAlgError:
-        return M
-    return M + Z @ np.linalg.solve(E, Z.T)
+        return M, None
+    Q = Z @ np.linalg.solve(E, Z.T)
+    return (np.eye(len(S)) - Q @ S) @ M + Q, Q
 
 
-def pcg(S, b, P, tol=1e-6, max_iters=10000):
-    """Textbook preconditioned CG from x = 0; stops when |r| <= tol |b|.
-    Returns (x, iterations)."""
-    x = np.zeros_like(b)
-    r = b.copy()
-    z = P @ r
-    p = z.copy()
-    rz = r @ z
+def pcg(S, b, P, tol=1e-6, max_iters=10000, x0=None):
+    """Textbook preconditioned CG from x0 (0 if None); stops when
+    |b - S x| <= tol |b|.  Returns (x, iterations)."""
+    x = np.zeros_like(b) if x0 is None else np.array(x0, dtype=np.float64)
+    r = b - S @ x
     bb = b @ b
     if bb == 0:
         return x, 0
+    if r @ r <= tol * tol * bb:
+        return x, 0
+    z = P @ r
+    p = z.copy()
+    rz = r @ z
     for k in range(max_iters):
         q = S @ p
         a = rz / (p @ q)

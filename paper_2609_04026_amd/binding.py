@@ -20,7 +20,7 @@ BA_OK, BA_E_INVALID, BA_E_STATE, BA_E_OOM, BA_E_DEVICE, BA_E_NUMERIC, BA_E_NOT_C
 STATUS_NAMES = ["BA_OK", "BA_E_INVALID", "BA_E_STATE", "BA_E_OOM", "BA_E_DEVICE", "BA_E_NUMERIC",
                 "BA_E_NOT_CONVERGED"]
 PREC = {"fp64": 0, "mixed": 1}
-PRECOND = {"jacobi": 0, "learned": 1}
+PRECOND = {"jacobi": 0, "learned": 1, "gauge": 2}
 PHASES = ["linearize", "feature", "schur", "precond", "pcg", "backsub", "cost"]
 FAMILY_ROWS = {1: 2, 2: 4, 3: 2, 4: 4, 5: 3, 6: 1, 7: 1}
 
@@ -60,7 +60,8 @@ class StepReport(ctypes.Structure):
 class GnnBatch(ctypes.Structure):
     _fields_ = [("n_nodes", c_int32), ("n_edges", c_int32), ("n_graphs", c_int32),
                 ("node_x", POINTER(ctypes.c_float)), ("node_type", POINTER(c_int32)), ("node_graph", POINTER(c_int32)),
-                ("node_unit", POINTER(ctypes.c_float)), ("edge_src", POINTER(c_int32)), ("edge_dst", POINTER(c_int32)),
+                ("node_unit", POINTER(ctypes.c_float)), ("node_gauge", POINTER(c_double)),
+                ("edge_src", POINTER(c_int32)), ("edge_dst", POINTER(c_int32)),
                 ("edge_rev", POINTER(c_int32)), ("edge_x", POINTER(ctypes.c_float)), ("s_node", POINTER(c_double)),
                 ("s_edge", POINTER(c_double)), ("s_node_off", POINTER(c_int64)), ("s_edge_off", POINTER(c_int64)),
                 ("s_node_len", c_int64), ("s_edge_len", c_int64)]
@@ -105,6 +106,7 @@ def _load():
         "ba_export_gnn_graph": (c_int32, [H, I32, I32, F, I32, I32, F, I32, I32, I32, F]),
         "ba_normalized_matvec": (c_int32, [H, D, D]),
         "ba_export_schur_dense": (c_int32, [H, D]),
+        "ba_export_gauge_basis": (c_int32, [H, D]),
         "ba_gnn_create": (c_int32, [c_int32, c_int32, c_int32, POINTER(c_void_p)]),
         "ba_gnn_set_params": (c_int32, [H, F, c_size_t]),
         "ba_gnn_get_params": (c_int32, [H, F, c_size_t]),
@@ -326,6 +328,13 @@ class BA:
         self._check(_lib.ba_export_schur_dense(self._h, _dp(S)))
         return S
 
+    def export_gauge_basis(self):
+        """The 7 similarity-gauge directions at the current parameters (n_A x 7)."""
+        nA, _ = self.reduced_dim()
+        G = np.zeros((nA, 7))
+        self._check(_lib.ba_export_gauge_basis(self._h, _dp(G)))
+        return G
+
     def normalized_matvec(self, x):
         x = np.ascontiguousarray(x, dtype=np.float64)
         y = np.zeros_like(x)
@@ -353,13 +362,13 @@ class GNNBatch:
     """Host arrays of a ba_gnn_batch (kept alive while the struct is used)."""
 
     def __init__(self, node_x, node_type, node_graph, node_unit, edge_src, edge_dst, edge_rev, edge_x, n_graphs,
-                 s_node=None, s_node_off=None, s_edge=None, s_edge_off=None):
+                 s_node=None, s_node_off=None, s_edge=None, s_edge_off=None, node_gauge=None):
         self.a = dict(
             node_x=np.ascontiguousarray(node_x, np.float32), node_type=np.ascontiguousarray(node_type, np.int32),
             node_graph=np.ascontiguousarray(node_graph, np.int32), node_unit=np.ascontiguousarray(node_unit, np.float32),
             edge_src=np.ascontiguousarray(edge_src, np.int32), edge_dst=np.ascontiguousarray(edge_dst, np.int32),
             edge_rev=np.ascontiguousarray(edge_rev, np.int32), edge_x=np.ascontiguousarray(edge_x, np.float32))
-        for k in ("s_node", "s_edge"):
+        for k in ("s_node", "s_edge", "node_gauge"):
             v = locals()[k]
             self.a[k] = None if v is None else np.ascontiguousarray(v, np.float64)
         for k in ("s_node_off", "s_edge_off"):
@@ -369,7 +378,8 @@ class GNNBatch:
         self.n_nodes = len(a["node_type"])
         self.s = GnnBatch(
             self.n_nodes, len(a["edge_src"]), int(n_graphs), _fp(a["node_x"]), _ip(a["node_type"]),
-            _ip(a["node_graph"]), _fp(a["node_unit"]), _ip(a["edge_src"]), _ip(a["edge_dst"]), _ip(a["edge_rev"]),
+            _ip(a["node_graph"]), _fp(a["node_unit"]), _dp(a["node_gauge"]), _ip(a["edge_src"]), _ip(a["edge_dst"]),
+            _ip(a["edge_rev"]),
             _fp(a["edge_x"]), _dp(a["s_node"]), _dp(a["s_edge"]), _lp(a["s_node_off"]), _lp(a["s_edge_off"]),
             0 if a["s_node"] is None else len(a["s_node"]), 0 if a["s_edge"] is None else len(a["s_edge"]))
 

@@ -14,7 +14,7 @@ struct ba_gnn;
 
 namespace ba_gnn_impl {
 
-constexpr int NODE_IN = 64, EDGE_IN = 8, HEAD_PAD = 9 * ba::COARSE_K;
+constexpr int NODE_IN = 64, EDGE_IN = 8, HEAD_PAD = 9 * ba::COARSE_NET;
 constexpr int MAX_GRAPH_NODES = 6000;  // the symbolic phase counts shared features in a dense n x n table
 
 // host-side graph of a problem's reduced system, built once at the symbolic phase

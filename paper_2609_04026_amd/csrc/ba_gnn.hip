@@ -33,7 +33,9 @@ namespace {
 using ba_gnn_impl::NODE_IN;
 using ba_gnn_impl::EDGE_IN;
 constexpr int H = 64, NIN = NODE_IN, EIN = EDGE_IN, EK = H + EIN, LAYERS = 3, HEADP = ba_gnn_impl::HEAD_PAD;
-constexpr int KC = ba::COARSE_K;
+constexpr int KC = ba::COARSE_NET;    // network columns
+constexpr int KG = ba::COARSE_GAUGE;  // gauge columns, first in the coarse basis
+constexpr int KT = ba::COARSE_K;      // all columns
 static_assert(HEADP == 9 * KC, "head rows are padded to 9 block rows of K entries");
 
 struct Layout {
@@ -243,51 +245,54 @@ __global__ void k_add(float* a, const float* b, int64_t n) {
 
 __device__ __forceinline__ int node_size(int type, int cd) { return type == 0 ? cd : type == 1 ? 3 : 2; }
 
-// Z entry (row r, column c) of node j from the heads and the row scales
-__device__ __forceinline__ double zval(const float* heads, const float* unit, int j, int r, int c) {
-  return (double)unit[(int64_t)j * 9 + r] * (double)heads[(int64_t)j * HEADP + r * KC + c];
+// entry (row r, column c) of the coarse basis of node j: gauge columns first, then
+// the network's head scaled by the row's unit
+__device__ __forceinline__ double zval(const float* heads, const float* unit, const double* gauge, int j, int r, int c) {
+  if (c < KG) return gauge[((int64_t)j * 9 + r) * KG + c];
+  return (double)unit[(int64_t)j * 9 + r] * (double)heads[(int64_t)j * HEADP + r * KC + (c - KG)];
 }
 
-// SZ_i = S_ii Z_i + sum_{edges j -> i} S_ij Z_j and DZ_i = S_ii Z_i (FP64),
+// SZ_i = S_ii Z_i + sum_{edges j -> i} S_ij Z_j and DZ_i = S_ii Z_i (FP64, n x 9 x KT),
 // one thread per (node, row, column)
-__global__ void k_coarse_products(const float* heads, const float* unit, const int32_t* type, const int32_t* src,
-                                  const int32_t* dst_off, const double* s_node, const int64_t* s_node_off,
-                                  const double* s_edge, const int64_t* s_edge_off, int n, int cd, double* SZ,
-                                  double* DZ) {
+__global__ void k_coarse_products(const float* heads, const float* unit, const double* gauge, const int32_t* type,
+                                  const int32_t* src, const int32_t* dst_off, const double* s_node,
+                                  const int64_t* s_node_off, const double* s_edge, const int64_t* s_edge_off, int n,
+                                  int cd, double* SZ, double* DZ) {
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (t >= (int64_t)n * HEADP) return;
-  const int i = (int)(t / HEADP), r = (int)(t % HEADP) / KC, c = (int)(t % KC);
+  if (t >= (int64_t)n * 9 * KT) return;
+  const int i = (int)(t / (9 * KT)), r = (int)(t % (9 * KT)) / KT, c = (int)(t % KT);
   const int ni = node_size(type[i], cd);
   if (r >= ni) { SZ[t] = 0; DZ[t] = 0; return; }
   const double* Sii = s_node + s_node_off[i] + (int64_t)r * ni;
   double dz = 0;
-  for (int q = 0; q < ni; ++q) dz += Sii[q] * zval(heads, unit, i, q, c);
+  for (int q = 0; q < ni; ++q) dz += Sii[q] * zval(heads, unit, gauge, i, q, c);
   double sz = dz;
   for (int e = dst_off[i]; e < dst_off[i + 1]; ++e) {
     const int j = src[e];
     const int nj = node_size(type[j], cd);
     const double* Se = s_edge + s_edge_off[e] + (int64_t)r * nj;
-    for (int q = 0; q < nj; ++q) sz += Se[q] * zval(heads, unit, j, q, c);
+    for (int q = 0; q < nj; ++q) sz += Se[q] * zval(heads, unit, gauge, j, q, c);
   }
   SZ[t] = sz;
   DZ[t] = dz;
 }
 
-// per-system Gram matrices A = Z^T S Z and G = Z^T D Z (K x K, FP64 atomics),
+// per-system Gram matrices A = Z^T S Z and G = Z^T D Z (KT x KT, FP64 atomics),
 // one thread per (node, a, b)
-__global__ void k_coarse_gram(const float* heads, const float* unit, const int32_t* type, const int32_t* graph,
-                              const double* SZ, const double* DZ, int n, int cd, double* Ag, double* Gg) {
+__global__ void k_coarse_gram(const float* heads, const float* unit, const double* gauge, const int32_t* type,
+                              const int32_t* graph, const double* SZ, const double* DZ, int n, int cd, double* Ag,
+                              double* Gg) {
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (t >= (int64_t)n * KC * KC) return;
-  const int i = (int)(t / (KC * KC)), a = (int)(t % (KC * KC)) / KC, b = (int)(t % KC);
+  if (t >= (int64_t)n * KT * KT) return;
+  const int i = (int)(t / (KT * KT)), a = (int)(t % (KT * KT)) / KT, b = (int)(t % KT);
   const int ni = node_size(type[i], cd);
   double sa = 0, sg = 0;
   for (int r = 0; r < ni; ++r) {
-    const double z = zval(heads, unit, i, r, a);
-    sa += z * SZ[(int64_t)i * HEADP + r * KC + b];
-    sg += z * DZ[(int64_t)i * HEADP + r * KC + b];
+    const double z = zval(heads, unit, gauge, i, r, a);
+    sa += z * SZ[((int64_t)i * 9 + r) * KT + b];
+    sg += z * DZ[((int64_t)i * 9 + r) * KT + b];
   }
-  const int64_t o = (int64_t)graph[i] * KC * KC + a * KC + b;
+  const int64_t o = (int64_t)graph[i] * KT * KT + a * KT + b;
   atomicAdd(Ag + o, sa);
   atomicAdd(Gg + o, sg);
 }
@@ -298,79 +303,80 @@ __global__ void k_coarse_loss(const double* Ag, const double* Gg, int n_graphs, 
                               double* n_bad) {
   const int gi = blockIdx.x * blockDim.x + threadIdx.x;
   if (gi >= n_graphs) return;
-  const double* A = Ag + (int64_t)gi * KC * KC;
-  const double* G = Gg + (int64_t)gi * KC * KC;
-  double L[KC][KC], X[KC][KC], Gi[KC][KC], As[KC][KC], T[KC][KC];
+  const double* A = Ag + (int64_t)gi * KT * KT;
+  const double* G = Gg + (int64_t)gi * KT * KT;
+  double L[KT][KT], X[KT][KT], Gi[KT][KT], As[KT][KT];
   bool ok = true;
-  for (int p = 0; p < KC; ++p)
-    for (int q = 0; q < KC; ++q) {
-      L[p][q] = 0.5 * (G[p * KC + q] + G[q * KC + p]);
-      As[p][q] = 0.5 * (A[p * KC + q] + A[q * KC + p]);
+  for (int p = 0; p < KT; ++p)
+    for (int q = 0; q < KT; ++q) {
+      L[p][q] = 0.5 * (G[p * KT + q] + G[q * KT + p]);
+      As[p][q] = 0.5 * (A[p * KT + q] + A[q * KT + p]);
+      X[p][q] = 0.0;
     }
-  for (int j = 0; j < KC && ok; ++j) {
+  for (int j = 0; j < KT && ok; ++j) {
     double s = L[j][j];
     for (int k = 0; k < j; ++k) s -= L[j][k] * L[j][k];
     if (!(s > 0.0) || !isfinite(s)) { ok = false; break; }
     const double ljj = sqrt(s);
     L[j][j] = ljj;
-    for (int r = j + 1; r < KC; ++r) {
+    for (int r = j + 1; r < KT; ++r) {
       double u = L[r][j];
       for (int k = 0; k < j; ++k) u -= L[r][k] * L[j][k];
       L[r][j] = u / ljj;
     }
   }
-  double* q1 = Q1 + (int64_t)gi * KC * KC;
-  double* q2 = Q2 + (int64_t)gi * KC * KC;
+  double* q1 = Q1 + (int64_t)gi * KT * KT;
+  double* q2 = Q2 + (int64_t)gi * KT * KT;
   if (!ok) {
-    for (int k = 0; k < KC * KC; ++k) { q1[k] = 0; q2[k] = 0; }
+    for (int k = 0; k < KT * KT; ++k) { q1[k] = 0; q2[k] = 0; }
     atomicAdd(n_bad, 1.0);
     return;
   }
-  for (int c = 0; c < KC; ++c)  // X = L^-1
-    for (int r = 0; r < KC; ++r) {
+  for (int c = 0; c < KT; ++c)  // X = L^-1
+    for (int r = c; r < KT; ++r) {
       double s = r == c ? 1.0 : 0.0;
       for (int k = c; k < r; ++k) s -= L[r][k] * X[k][c];
-      X[r][c] = r < c ? 0.0 : s / L[r][r];
+      X[r][c] = s / L[r][r];
     }
-  for (int p = 0; p < KC; ++p)  // G^-1 = X^T X
-    for (int q = 0; q < KC; ++q) {
+  for (int p = 0; p < KT; ++p)  // G^-1 = X^T X
+    for (int q = 0; q < KT; ++q) {
       double s = 0;
-      for (int k = 0; k < KC; ++k) s += X[k][p] * X[k][q];
+      for (int k = 0; k < KT; ++k) s += X[k][p] * X[k][q];
       Gi[p][q] = s;
     }
   double tr = 0;
-  for (int p = 0; p < KC; ++p)
-    for (int q = 0; q < KC; ++q) tr += Gi[p][q] * As[q][p];
-  for (int p = 0; p < KC; ++p)
-    for (int q = 0; q < KC; ++q) {
+  for (int p = 0; p < KT; ++p)
+    for (int q = 0; q < KT; ++q) tr += Gi[p][q] * As[q][p];
+  for (int p = 0; p < KT; ++p)  // L <- G^-1 A (reusing the storage)
+    for (int q = 0; q < KT; ++q) {
       double s = 0;
-      for (int k = 0; k < KC; ++k) s += Gi[p][k] * As[k][q];
-      T[p][q] = s;
+      for (int k = 0; k < KT; ++k) s += Gi[p][k] * As[k][q];
+      L[p][q] = s;
     }
-  for (int p = 0; p < KC; ++p)
-    for (int q = 0; q < KC; ++q) {
+  for (int p = 0; p < KT; ++p)
+    for (int q = 0; q < KT; ++q) {
       double s = 0;
-      for (int k = 0; k < KC; ++k) s += T[p][k] * Gi[k][q];
-      q1[p * KC + q] = Gi[p][q];
-      q2[p * KC + q] = s;
+      for (int k = 0; k < KT; ++k) s += L[p][k] * Gi[k][q];
+      q1[p * KT + q] = Gi[p][q];
+      q2[p * KT + q] = s;
     }
   atomicAdd(loss, tr / n_graphs);
 }
 
-// d loss / d heads: dZ = (2 / n_graphs) (SZ Q1 - DZ Q2), dY = u dZ
+// d loss / d heads for the network columns: dZ = (2 / n_graphs) (SZ Q1 - DZ Q2), dY = u dZ
 __global__ void k_coarse_dheads(const double* SZ, const double* DZ, const double* Q1, const double* Q2,
                                 const float* unit, const int32_t* type, const int32_t* graph, int n, int cd,
                                 int n_graphs, float* dheads) {
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (t >= (int64_t)n * HEADP) return;
-  const int i = (int)(t / HEADP), r = (int)(t % HEADP) / KC, c = (int)(t % KC);
+  const int i = (int)(t / HEADP), r = (int)(t % HEADP) / KC, c = KG + (int)(t % KC);
   if (r >= node_size(type[i], cd)) { dheads[t] = 0.0f; return; }
-  const double* q1 = Q1 + (int64_t)graph[i] * KC * KC;
-  const double* q2 = Q2 + (int64_t)graph[i] * KC * KC;
-  const double* sz = SZ + (int64_t)i * HEADP + r * KC;
-  const double* dz = DZ + (int64_t)i * HEADP + r * KC;
+  const double* q1 = Q1 + (int64_t)graph[i] * KT * KT;
+  const double* q2 = Q2 + (int64_t)graph[i] * KT * KT;
+  const double* sz = SZ + ((int64_t)i * 9 + r) * KT;
+  const double* dz = DZ + ((int64_t)i * 9 + r) * KT;
   double s = 0;
-  for (int b = 0; b < KC; ++b) s += sz[b] * q1[b * KC + c] - dz[b] * q2[b * KC + c];
+  for (int b = 0; b < KT; ++b) s += sz[b] * q1[b * KT + c] - dz[b] * q2[b * KT + c];
   dheads[t] = (float)(2.0 / n_graphs * s * unit[(int64_t)i * 9 + r]);
 }
 
@@ -430,7 +436,7 @@ __global__ void k_node_features(ba::Dev d, const float* stat, const int32_t* typ
   }
 }
 
-// Z (K columns of length nA, column-major, FP64) from the heads of the attached graph
+// the network's columns of Z (after the gauge columns; column-major, FP64) from the heads
 __global__ void k_coarse_basis(ba::Dev d, const float* heads, const int32_t* type, int n, double s0) {
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (t >= (int64_t)n * HEADP) return;
@@ -443,7 +449,7 @@ __global__ void k_coarse_basis(ba::Dev d, const float* heads, const int32_t* typ
   if (ty == 0) { o = d.CD * i; if (r >= 3 && r < 6) u = s0; }
   else if (ty == 1) { o = d.offPl + 3 * (i - d.nc); if (r == 2) u = s0; }
   else { o = d.offVp + 2 * (i - d.nc - d.ng); }
-  d.Zc[(int64_t)c * d.nA + o + r] = u * (double)heads[(int64_t)i * HEADP + r * KC + c];
+  d.Zc[(int64_t)(KG + c) * d.nA + o + r] = u * (double)heads[(int64_t)i * HEADP + r * KC + c];
 }
 
 // y = L^-1 v blockwise (inverse = false) or L^-T v (inverse = true), S_ii = L_i L_i^T
@@ -509,7 +515,7 @@ struct ba_gnn {
         *dH2 = nullptr, *dZ = nullptr, *dE = nullptr, *ex = nullptr, *unit = nullptr;
   uint16_t *bfA = nullptr, *bfB = nullptr;  // BF16 operand scratch
   int32_t *type = nullptr, *graph = nullptr, *src = nullptr, *dst = nullptr, *rev = nullptr, *dst_off = nullptr;
-  double *SZ = nullptr, *DZ = nullptr, *Ag = nullptr, *Q1 = nullptr, *Q2 = nullptr;
+  double *SZ = nullptr, *DZ = nullptr, *Ag = nullptr, *Q1 = nullptr, *Q2 = nullptr, *gauge = nullptr;
   double *s_node = nullptr, *s_edge = nullptr;
   int64_t *s_node_off = nullptr, *s_edge_off = nullptr;
   double* scal = nullptr;  // loss, systems skipped
@@ -543,7 +549,7 @@ void reserve(ba_gnn* g, int n, int m, int G, int64_t sn, int64_t se) {
   for (float** p : fl) { dfree(g, *p); *p = nullptr; }
   int32_t** il[] = {&g->type, &g->graph, &g->src, &g->dst, &g->rev, &g->dst_off};
   for (int32_t** p : il) { dfree(g, *p); *p = nullptr; }
-  double** dl[] = {&g->SZ, &g->DZ, &g->Ag, &g->Q1, &g->Q2, &g->s_node, &g->s_edge};
+  double** dl[] = {&g->SZ, &g->DZ, &g->Ag, &g->Q1, &g->Q2, &g->s_node, &g->s_edge, &g->gauge};
   for (double** p : dl) { dfree(g, *p); *p = nullptr; }
   dfree(g, g->bfA); dfree(g, g->bfB); dfree(g, g->s_node_off); dfree(g, g->s_edge_off);
   const size_t nh = (size_t)n * H, mh = (size_t)m * H;
@@ -569,11 +575,12 @@ void reserve(ba_gnn* g, int n, int m, int G, int64_t sn, int64_t se) {
   g->type = dalloc<int32_t>(g, n); g->graph = dalloc<int32_t>(g, n);
   g->src = dalloc<int32_t>(g, m); g->dst = dalloc<int32_t>(g, m); g->rev = dalloc<int32_t>(g, m);
   g->dst_off = dalloc<int32_t>(g, n + 1);
-  g->SZ = dalloc<double>(g, (size_t)n * HEADP);
-  g->DZ = dalloc<double>(g, (size_t)n * HEADP);
-  g->Ag = dalloc<double>(g, (size_t)2 * G * KC * KC);  // A then G
-  g->Q1 = dalloc<double>(g, (size_t)G * KC * KC);
-  g->Q2 = dalloc<double>(g, (size_t)G * KC * KC);
+  g->SZ = dalloc<double>(g, (size_t)n * 9 * KT);
+  g->DZ = dalloc<double>(g, (size_t)n * 9 * KT);
+  g->Ag = dalloc<double>(g, (size_t)2 * G * KT * KT);  // A then G
+  g->Q1 = dalloc<double>(g, (size_t)G * KT * KT);
+  g->Q2 = dalloc<double>(g, (size_t)G * KT * KT);
+  g->gauge = dalloc<double>(g, (size_t)n * 9 * KG);
   g->s_node = dalloc<double>(g, sn);
   g->s_edge = dalloc<double>(g, se);
   g->s_node_off = dalloc<int64_t>(g, n);
@@ -767,8 +774,8 @@ bool check_batch(ba_gnn* g, const ba_gnn_batch* b, bool need_s) {
   }
   if (need_s) {
     if (!b->s_node || !b->s_node_off || (b->n_edges > 0 && (!b->s_edge || !b->s_edge_off)) || b->s_node_len <= 0 ||
-        b->s_edge_len < 0) {
-      g->err = "the loss needs the S blocks of every node and edge";
+        b->s_edge_len < 0 || !b->node_gauge) {
+      g->err = "the loss needs the S blocks of every node and edge and the gauge blocks";
       return false;
     }
     for (int i = 0; i < b->n_nodes; ++i) {
@@ -819,6 +826,7 @@ Dims upload_batch(ba_gnn* g, const ba_gnn_batch* b, bool with_s) {
   if (with_s) {
     GCHK(hipMemcpyAsync(g->s_node, b->s_node, (size_t)b->s_node_len * 8, hipMemcpyHostToDevice, s));
     GCHK(hipMemcpyAsync(g->s_node_off, b->s_node_off, (size_t)D.n * 8, hipMemcpyHostToDevice, s));
+    GCHK(hipMemcpyAsync(g->gauge, b->node_gauge, (size_t)D.n * 9 * KG * 8, hipMemcpyHostToDevice, s));
     if (D.m) {
       GCHK(hipMemcpyAsync(g->s_edge, b->s_edge, (size_t)b->s_edge_len * 8, hipMemcpyHostToDevice, s));
       GCHK(hipMemcpyAsync(g->s_edge_off, b->s_edge_off, (size_t)D.m * 8, hipMemcpyHostToDevice, s));
@@ -830,21 +838,22 @@ Dims upload_batch(ba_gnn* g, const ba_gnn_batch* b, bool with_s) {
 // coarse loss of the heads in g->heads and its gradient into g->dheads
 void coarse_loss(ba_gnn* g, const Dims& D, int n_graphs) {
   hipStream_t s = g->cur;
-  GCHK(hipMemsetAsync(g->Ag, 0, (size_t)2 * n_graphs * KC * KC * 8, s));
+  GCHK(hipMemsetAsync(g->Ag, 0, (size_t)2 * n_graphs * KT * KT * 8, s));
   GCHK(hipMemsetAsync(g->scal, 0, 2 * 8, s));
-  const int64_t nt = (int64_t)D.n * HEADP;
-  hipLaunchKernelGGL(k_coarse_products, dim3(nblk(nt, 256)), dim3(256), 0, s, (const float*)g->heads,
-                     (const float*)g->unit, (const int32_t*)g->type, (const int32_t*)g->src, (const int32_t*)g->dst_off,
-                     (const double*)g->s_node, (const int64_t*)g->s_node_off, (const double*)g->s_edge,
-                     (const int64_t*)g->s_edge_off, D.n, g->cd, g->SZ, g->DZ);
-  hipLaunchKernelGGL(k_coarse_gram, dim3(nblk((int64_t)D.n * KC * KC, 256)), dim3(256), 0, s, (const float*)g->heads,
-                     (const float*)g->unit, (const int32_t*)g->type, (const int32_t*)g->graph, (const double*)g->SZ,
-                     (const double*)g->DZ, D.n, g->cd, g->Ag, g->Ag + (size_t)n_graphs * KC * KC);
+  const int64_t np = (int64_t)D.n * 9 * KT;
+  hipLaunchKernelGGL(k_coarse_products, dim3(nblk(np, 256)), dim3(256), 0, s, (const float*)g->heads,
+                     (const float*)g->unit, (const double*)g->gauge, (const int32_t*)g->type, (const int32_t*)g->src,
+                     (const int32_t*)g->dst_off, (const double*)g->s_node, (const int64_t*)g->s_node_off,
+                     (const double*)g->s_edge, (const int64_t*)g->s_edge_off, D.n, g->cd, g->SZ, g->DZ);
+  hipLaunchKernelGGL(k_coarse_gram, dim3(nblk((int64_t)D.n * KT * KT, 256)), dim3(256), 0, s, (const float*)g->heads,
+                     (const float*)g->unit, (const double*)g->gauge, (const int32_t*)g->type, (const int32_t*)g->graph,
+                     (const double*)g->SZ, (const double*)g->DZ, D.n, g->cd, g->Ag,
+                     g->Ag + (size_t)n_graphs * KT * KT);
   hipLaunchKernelGGL(k_coarse_loss, dim3(nblk(n_graphs, 64)), dim3(64), 0, s, (const double*)g->Ag,
-                     (const double*)(g->Ag + (size_t)n_graphs * KC * KC), n_graphs, g->Q1, g->Q2, g->scal, g->scal + 1);
-  hipLaunchKernelGGL(k_coarse_dheads, dim3(nblk(nt, 256)), dim3(256), 0, s, (const double*)g->SZ, (const double*)g->DZ,
-                     (const double*)g->Q1, (const double*)g->Q2, (const float*)g->unit, (const int32_t*)g->type,
-                     (const int32_t*)g->graph, D.n, g->cd, n_graphs, g->dheads);
+                     (const double*)(g->Ag + (size_t)n_graphs * KT * KT), n_graphs, g->Q1, g->Q2, g->scal, g->scal + 1);
+  hipLaunchKernelGGL(k_coarse_dheads, dim3(nblk((int64_t)D.n * HEADP, 256)), dim3(256), 0, s, (const double*)g->SZ,
+                     (const double*)g->DZ, (const double*)g->Q1, (const double*)g->Q2, (const float*)g->unit,
+                     (const int32_t*)g->type, (const int32_t*)g->graph, D.n, g->cd, n_graphs, g->dheads);
 }
 
 }  // namespace

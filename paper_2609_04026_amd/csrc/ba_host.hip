@@ -286,22 +286,64 @@ void finalize(ba_handle* h) {
     for (int64_t p = L.off[k]; p < L.off[k + 1]; ++p) if (!P.has(j, L.cam[p])) n6[j]++;
     for (int64_t p = P.off[j]; p < P.off[j + 1]; ++p) if (!L.has(k, P.cam[p])) n7[k]++;
   }
-  // internal order: features with the same record signature are adjacent so
-  // that the lanes of a wavefront run the same loops
+  // internal order: features sorted by where their observing cameras are (so that a run
+  // of consecutive features touches few cameras: the product keeps a workgroup's entries
+  // of the reduced vector in LDS), then by record signature
   h->pt_perm.resize(h->np);
   std::iota(h->pt_perm.begin(), h->pt_perm.end(), 0);
   auto ptkey = [&](int j) {
     const int n1 = (int)(P.off[j + 1] - P.off[j]);
     return std::make_tuple(pt_plane[j] >= 0 && n1 > 0, n6[j] > 0, n1, n6[j]);
   };
-  std::stable_sort(h->pt_perm.begin(), h->pt_perm.end(), [&](int a, int b) { return ptkey(a) > ptkey(b); });
+  // locality key: Morton code of the mean centre of the feature's observing cameras
+  std::vector<double> ctr((size_t)3 * h->nc);
+  double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+  for (int i = 0; i < h->nc; ++i) {
+    const double* c = &h->cam[(size_t)CAM_STRIDE * i];
+    for (int k = 0; k < 3; ++k) {
+      const double v = -(c[k] * c[9] + c[3 + k] * c[10] + c[6 + k] * c[11]);
+      ctr[3 * i + k] = v;
+      lo[k] = std::min(lo[k], v);
+      hi[k] = std::max(hi[k], v);
+    }
+  }
+  auto morton = [&](const CSR& O, int f) -> uint64_t {
+    const int64_t b = O.off[f], e = O.off[f + 1];
+    if (e == b) return ~0ull;
+    double m[3] = {0, 0, 0};
+    for (int64_t p = b; p < e; ++p)
+      for (int k = 0; k < 3; ++k) m[k] += ctr[3 * (size_t)O.cam[p] + k];
+    uint64_t code = 0;
+    uint32_t q[3];
+    for (int k = 0; k < 3; ++k) {
+      const double span = hi[k] - lo[k];
+      const double u = span > 0 ? (m[k] / (double)(e - b) - lo[k]) / span : 0.0;
+      q[k] = (uint32_t)std::min(1023.0, std::max(0.0, u * 1024.0));
+    }
+    for (int bit = 9; bit >= 0; --bit)
+      for (int k = 0; k < 3; ++k) code = (code << 1) | ((q[k] >> bit) & 1u);
+    return code;
+  };
+  {
+    std::vector<uint64_t> key(h->np);
+    for (int j = 0; j < h->np; ++j) key[j] = morton(P, j);
+    std::stable_sort(h->pt_perm.begin(), h->pt_perm.end(), [&](int a, int b) {
+      return key[a] != key[b] ? key[a] < key[b] : ptkey(a) > ptkey(b);
+    });
+  }
   h->ln_perm.resize(h->nl);
   std::iota(h->ln_perm.begin(), h->ln_perm.end(), 0);
   auto lnkey = [&](int k) {
     const int n2 = (int)(L.off[k + 1] - L.off[k]);
     return std::make_tuple(ln_plane[k] >= 0 && n2 > 0, ln_vp[k] >= 0, n7[k] > 0, n2, n7[k]);
   };
-  std::stable_sort(h->ln_perm.begin(), h->ln_perm.end(), [&](int a, int b) { return lnkey(a) > lnkey(b); });
+  {
+    std::vector<uint64_t> key(h->nl);
+    for (int k = 0; k < h->nl; ++k) key[k] = morton(L, k);
+    std::stable_sort(h->ln_perm.begin(), h->ln_perm.end(), [&](int a, int b) {
+      return key[a] != key[b] ? key[a] < key[b] : lnkey(a) > lnkey(b);
+    });
+  }
   h->pt_inv.assign(h->np, 0);
   h->ln_inv.assign(h->nl, 0);
   for (int i = 0; i < h->np; ++i) h->pt_inv[h->pt_perm[i]] = i;
@@ -491,10 +533,6 @@ void finalize(ba_handle* h) {
       h->g_stat = A.get<float>(G.node_static.size());
       h->g_type = A.get<int32_t>(G.n_nodes);
       h->g_x = A.get<float>(G.node_static.size());
-      d.Zc = A.get<double>((size_t)COARSE_K * d.nA);
-      d.SZc = A.get<double>((size_t)COARSE_K * d.nA);
-      d.Einv = A.get<double>((size_t)COARSE_K * COARSE_K);
-      d.Ztb = A.get<double>((size_t)COARSE_K + COARSE_K * COARSE_K);
       upload(h, h->g_stat, G.node_static);
       upload(h, h->g_type, G.node_type);
     }
@@ -571,6 +609,11 @@ void finalize(ba_handle* h) {
   d.gA = A.get<double>(nA); d.DA = A.get<double>(nA); d.bA = A.get<double>(nA);
   d.x = A.get<double>(nA); d.r = A.get<double>(nA); d.z = A.get<double>(nA); d.p = A.get<double>(nA); d.q = A.get<double>(nA);
   d.xT = A.get<char>(nA, TS);
+  // coarse space of the two-level preconditioners
+  d.Zc = A.get<double>((size_t)COARSE_K * nA);
+  d.SZc = A.get<double>((size_t)COARSE_K * nA);
+  d.Einv = A.get<double>((size_t)COARSE_K * COARSE_K);
+  d.Ztb = A.get<double>((size_t)COARSE_K + COARSE_K * COARSE_K);
   // product tiles: runs of consecutive features whose records split into at
   // most MV_MAX_CHUNKS single-family chunks of MV_CHUNK records
   {
@@ -680,14 +723,20 @@ void assemble_schur(ba_handle* h, double lambda, double kappa_max) {
   h->last_lambda = lambda;
 }
 
-// block-Jacobi blocks, and the learned coarse space when it is in use
+// block-Jacobi blocks, and the coarse space of the two-level preconditioners: the
+// similarity gauge, plus the network's vectors for BA_PC_LEARNED
 void assemble_precond(ba_handle* h, double lambda) {
   launch_precond_blockjacobi(h->d, h->stream);
-  h->d.coarse = 0;
-  if (h->precond == BA_PC_LEARNED && ba_gnn_impl::ready(h->gnn) && h->d.Zc) {
-    ba_gnn_impl::apply(h->gnn, h->d, lambda, h->stream);
+  h->d.coarse_k = 0;
+  const bool learned = h->precond == BA_PC_LEARNED && ba_gnn_impl::ready(h->gnn);
+  if ((h->precond == BA_PC_GAUGE || learned) && h->d.nA > 0) {
+    launch_gauge_basis(h->d, h->stream);
+    h->d.coarse_k = COARSE_GAUGE;
+    if (learned) {
+      ba_gnn_impl::apply(h->gnn, h->d, lambda, h->stream);
+      h->d.coarse_k = COARSE_K;
+    }
     launch_coarse_setup(h->d, lambda, h->stream);
-    h->d.coarse = 1;
   }
   check_launch("preconditioner");
 }
@@ -865,7 +914,7 @@ void do_step(ba_handle* h, const ba_solve_options& o, ba_step_report* rep) {
   r.pcg_iters = pcg(h, h->lambda, o.pcg_tol, o.pcg_max_iters, o.time_kernels ? &mv_ms : nullptr);
   r.matvec_ms = mv_ms;
   r.matvec_count = o.time_kernels ? r.pcg_iters + (h->hscal[SC_BREAK] != 0.0 ? 1 : 0) : 0;
-  r.coarse = h->d.coarse && h->hscal[SC_COARSE] != 0.0 ? 1 : 0;
+  r.coarse = h->d.coarse_k > 0 && h->hscal[SC_COARSE] != 0.0 ? h->d.coarse_k : 0;
   record(h, 4);
   const double rr = h->hscal[SC_RR], bb = h->hscal[SC_BB];
   r.pcg_rel_residual = bb > 0 ? std::sqrt(rr / bb) : 0.0;
@@ -946,7 +995,8 @@ ba_status ba_create(const ba_problem_desc* desc, ba_handle** out) {
       throw BaError(BA_E_INVALID, "negative count");
     if (desc->camera_dof != 6 && desc->camera_dof != 9) throw BaError(BA_E_INVALID, "camera_dof must be 6 or 9");
     if (desc->precision != BA_PREC_FP64 && desc->precision != BA_PREC_MIXED) throw BaError(BA_E_INVALID, "bad precision");
-    if (desc->precond != BA_PC_BLOCK_JACOBI && desc->precond != BA_PC_LEARNED) throw BaError(BA_E_INVALID, "bad precond");
+    if (desc->precond != BA_PC_BLOCK_JACOBI && desc->precond != BA_PC_LEARNED && desc->precond != BA_PC_GAUGE)
+      throw BaError(BA_E_INVALID, "bad precond");
     if (!std::isfinite(desc->cx) || !std::isfinite(desc->cy)) throw BaError(BA_E_INVALID, "non-finite principal point");
     h->nc = desc->n_cameras; h->np = desc->n_points; h->nl = desc->n_lines; h->ng = desc->n_planes; h->nv = desc->n_vps;
     h->CD = desc->camera_dof; h->cx = desc->cx; h->cy = desc->cy;
@@ -1349,6 +1399,22 @@ ba_status ba_export_gnn_graph(ba_handle* h, int32_t* n_nodes, int32_t* n_edges, 
     if (edge_dst) std::copy(G.edge_dst.begin(), G.edge_dst.end(), edge_dst);
     if (edge_rev) std::copy(G.edge_rev.begin(), G.edge_rev.end(), edge_rev);
     if (edge_x) std::copy(G.edge_x.begin(), G.edge_x.end(), edge_x);
+  });
+}
+
+ba_status ba_export_gauge_basis(ba_handle* h, double* G) {
+  if (!h || !G) return BA_E_INVALID;
+  return guard(h, [&] {
+    if (!h->finalized) throw BaError(BA_E_STATE, "no linearisation yet");
+    set_device(h);
+    const Dev& d = h->d;
+    launch_gauge_basis(d, h->stream);
+    check_launch("gauge basis");
+    std::vector<double> col((size_t)COARSE_GAUGE * d.nA);
+    HIPCHK(hipMemcpyAsync(col.data(), d.Zc, col.size() * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    sync(h);
+    for (int e = 0; e < d.nA; ++e)
+      for (int c = 0; c < COARSE_GAUGE; ++c) G[(size_t)e * COARSE_GAUGE + c] = col[(size_t)c * d.nA + e];
   });
 }
 

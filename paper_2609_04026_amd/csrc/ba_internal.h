@@ -81,9 +81,10 @@ struct Dev {
   double *gA = nullptr, *DA = nullptr, *bA = nullptr;
   double *Scam = nullptr, *Spl = nullptr, *Svp = nullptr;  // damped diagonal blocks of S
   double *Mcam = nullptr, *Mpl = nullptr, *Mvp = nullptr;  // preconditioner blocks
-  // coarse correction of the preconditioner: P r = M r + Z E^-1 Z^T r with
-  // Z (COARSE_K columns of length nA, column-major) and E = Z^T S Z
-  int coarse = 0;              // host switch: the PCG kernels read Z (SC_COARSE decides on the device)
+  // two-level preconditioner: Z (coarse_k columns of length nA, column-major; the
+  // gauge columns first), S Z, E^-1 = (Z^T S Z)^-1 (COARSE_K x COARSE_K storage),
+  // Z^T b; PCG starts from x0 = Z E^-1 Z^T b and applies (I - Q S) M + Q, Q = Z E^-1 Z^T
+  int coarse_k = 0;            // active columns (0: block-Jacobi; SC_COARSE decides on the device)
   double *Zc = nullptr, *SZc = nullptr, *Einv = nullptr, *Ztb = nullptr;
   // PCG (double vectors of length nA) and matvec partials (T)
   double *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
@@ -116,12 +117,14 @@ enum PcgScal {
   SC_GH, SC_JH2, SC_E, SC_EPIX, SC_NFLAG, SC_MAXIT, SC_BREAK,
   // PCG accumulators, three sets rotated by iteration (k mod 3): p.q, r.r, r.z
   SC_COARSE,  // 1: the coarse correction of the preconditioner is active for this solve
-  // PCG accumulators, three sets rotated by iteration (k mod 3): p.q, r.r, r.z, Z^T r
-  SC_ACC = 20, SC_COUNT = 64
+  // PCG accumulators, three sets rotated by iteration (k mod 3): p.q, r.r, r.(M r),
+  // Z^T r, (S Z)^T (M r)
+  SC_ACC = 20, SC_COUNT = 128
 };
-// columns of the coarse space of the learned preconditioner
-constexpr int COARSE_K = 8;
-constexpr int ACC_PQ = 0, ACC_RR = 1, ACC_RZ = 2, ACC_ZR = 4, ACC_STRIDE = 4 + COARSE_K;
+// coarse space of the two-level preconditioner: 7 similarity-gauge columns, then the
+// network's columns
+constexpr int COARSE_GAUGE = 7, COARSE_NET = 8, COARSE_K = COARSE_GAUGE + COARSE_NET;
+constexpr int ACC_PQ = 0, ACC_RR = 1, ACC_RZ = 2, ACC_ZR = 4, ACC_W = ACC_ZR + COARSE_K, ACC_STRIDE = ACC_W + COARSE_K;
 static_assert(SC_ACC + 3 * ACC_STRIDE <= SC_COUNT, "PCG scalar area too small");
 
 // ---- launchers (ba_kernels.hip) --------------------------------------------
@@ -139,7 +142,9 @@ void launch_pcg_update(const Dev& d, double lambda, int iter, hipStream_t s);  /
 void launch_schur_matvec(const Dev& d, const double* xin, double* yout, double lambda, hipStream_t s);
 // S (nA x nA, device; column c = S e_c) by nA products
 void launch_dense_schur(const Dev& d, double lambda, double* S, hipStream_t s);
-// E = Z^T S Z from the coarse basis d.Zc (COARSE_K products), its inverse and SC_COARSE
+// gauge columns of d.Zc from the current parameters
+void launch_gauge_basis(const Dev& d, hipStream_t s);
+// S Z and E = Z^T S Z for the first d.coarse_k columns of d.Zc, E^-1 and SC_COARSE
 void launch_coarse_setup(const Dev& d, double lambda, hipStream_t s);
 void launch_backsub(const Dev& d, hipStream_t s);                        // h_f, model decrease terms
 void launch_retract(const Dev& d, hipStream_t s);                        // candidate = current [+] h

@@ -1397,6 +1397,13 @@ template <int CD> __device__ __forceinline__ void block_of(const Dev& d, int b, 
   else { const int v = b - d.nc - d.ng; o = d.offVp + 2 * v; n = 2; M = d.Mvp + 4 * v; }
 }
 
+// position of entry e of the reduced vector: its block's offset, size and preconditioner block
+template <int CD> __device__ __forceinline__ void entry_block(const Dev& d, int e, int& o, int& n, const double*& M) {
+  if (e < d.offPl) { const int b = e / CD; o = CD * b; n = CD; M = d.Mcam + (int64_t)CD * CD * b; }
+  else if (e < d.offVp) { const int g = (e - d.offPl) / 3; o = d.offPl + 3 * g; n = 3; M = d.Mpl + 9 * g; }
+  else { const int v = (e - d.offVp) / 2; o = d.offVp + 2 * v; n = 2; M = d.Mvp + 4 * v; }
+}
+
 template <int CD> __device__ __forceinline__ void apply_M_block(const Dev& d, int b, const double* r, double* z, double& rz) {
   int o, n;
   const double* M;
@@ -1417,49 +1424,53 @@ template <int K> __device__ __forceinline__ void block_atomic_add(double (&v)[K]
   if (threadIdx.x < K) atomicAdd(dst[threadIdx.x], o[threadIdx.x]);
 }
 
-// coarse term of the preconditioner for entry e: sum_c Z[c][e] (E^-1 w)_c
-__device__ __forceinline__ double coarse_term(const Dev& d, int e, const double* w) {
-  double y = 0;
-#pragma unroll
+// ---- two-level preconditioner (coarse space Z, E = Z^T S Z) -----------------
+// y = E^-1 v for the active columns (every thread computes it; K <= 15)
+__device__ __forceinline__ void coarse_solve(const Dev& d, const double* v, double (&y)[COARSE_K]) {
+  const int K = d.coarse_k;
   for (int a = 0; a < COARSE_K; ++a) {
     double t = 0;
-#pragma unroll
-    for (int b = 0; b < COARSE_K; ++b) t += d.Einv[a * COARSE_K + b] * w[b];
-    y += d.Zc[(int64_t)a * d.nA + e] * t;
+    if (a < K)
+      for (int b = 0; b < K; ++b) t += d.Einv[a * COARSE_K + b] * v[b];
+    y[a] = t;
   }
-  return y;
 }
 
-// x = 0, r = b, z = P r, p = z; r.z -> set 2 (read as "previous r.z" by iteration 0), b.b -> SC_BB
-template <typename T, int CD, bool COARSE> __global__ __launch_bounds__(256) void k_pcg_init(Dev d) {
+// sum_c Z[c][e] y_c
+__device__ __forceinline__ double coarse_combine(const Dev& d, int e, const double (&y)[COARSE_K]) {
+  double t = 0;
+  for (int c = 0; c < d.coarse_k; ++c) t += d.Zc[(int64_t)c * d.nA + e] * y[c];
+  return t;
+}
+
+// full r.z of iteration set A: r.(M r) + (Z^T r) . E^-1 (Z^T r - (S Z)^T M r)
+__device__ __forceinline__ double coarse_rz(const Dev& d, const double* A, double (&y)[COARSE_K]) {
+  double v[COARSE_K];
+  for (int c = 0; c < COARSE_K; ++c) v[c] = c < d.coarse_k ? A[ACC_ZR + c] - A[ACC_W + c] : 0.0;
+  coarse_solve(d, v, y);
+  double rz = A[ACC_RZ];
+  for (int c = 0; c < d.coarse_k; ++c) rz += A[ACC_ZR + c] * y[c];
+  return rz;
+}
+
+// x = 0, r = b, z = M r, p = z; r.z -> set 2 (read as "previous r.z" by iteration 0), b.b -> SC_BB
+template <typename T, int CD> __global__ __launch_bounds__(256) void k_pcg_init(Dev d) {
   __shared__ double lds[3 * 5];
   const int nb = d.nc + d.ng + d.nv;
-  const bool coarse = COARSE && d.scal[SC_COARSE] != 0.0;
   double v[2] = {0, 0};
   for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < nb; b += gridDim.x * blockDim.x) {
     int o, n;
     const double* M;
     block_of<CD>(d, b, o, n, M);
     for (int a = 0; a < n; ++a) { d.x[o + a] = 0; d.r[o + a] = d.bA[o + a]; v[1] += d.bA[o + a] * d.bA[o + a]; }
-    if (!coarse) {
-      apply_M_block<CD>(d, b, d.bA, d.z, v[0]);
-    } else {
-      double rz = 0;
-      apply_M_block<CD>(d, b, d.bA, d.z, rz);
-      for (int a = 0; a < n; ++a) {
-        const double zc = coarse_term(d, o + a, d.Ztb);
-        d.z[o + a] += zc;
-        rz += d.bA[o + a] * zc;
-      }
-      v[0] += rz;
-    }
+    apply_M_block<CD>(d, b, d.bA, d.z, v[0]);
     for (int a = 0; a < n; ++a) { d.p[o + a] = d.z[o + a]; ((T*)d.xT)[o + a] = (T)d.z[o + a]; }
   }
   double* const dst[2] = {acc_set(d, 2) + ACC_RZ, d.scal + SC_BB};
   block_atomic_add<2>(v, lds, dst);
 }
 
-// Ztb = Z^T b (COARSE_K dots; Ztb cleared by k_pcg_reset)
+// Ztb = Z^T b (Ztb cleared by k_pcg_reset)
 __global__ __launch_bounds__(256) void k_coarse_ztb(Dev d) {
   __shared__ double lds[5 * COARSE_K];
   if (d.scal[SC_COARSE] == 0.0) return;
@@ -1467,10 +1478,71 @@ __global__ __launch_bounds__(256) void k_coarse_ztb(Dev d) {
   for (int a = 0; a < COARSE_K; ++a) v[a] = 0;
   for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < d.nA; e += gridDim.x * blockDim.x) {
     const double be = d.bA[e];
-    for (int a = 0; a < COARSE_K; ++a) v[a] += d.Zc[(int64_t)a * d.nA + e] * be;
+    for (int a = 0; a < d.coarse_k; ++a) v[a] += d.Zc[(int64_t)a * d.nA + e] * be;
   }
   double* o = block_sum_arr<double, COARSE_K>(v, lds);
-  if (threadIdx.x < COARSE_K) atomicAdd(d.Ztb + threadIdx.x, o[threadIdx.x]);
+  if (threadIdx.x < d.coarse_k) atomicAdd(d.Ztb + threadIdx.x, o[threadIdx.x]);
+}
+
+// coarse start: u = E^-1 Z^T b, x0 = Z u, r0 = b - (S Z) u, z = M r0 (stored in d.z);
+// set 2 gets r0.(M r0), Z^T r0 and (S Z)^T M r0; b.b -> SC_BB   (one thread per entry)
+template <int CD> __global__ __launch_bounds__(256) void k_pcg_init_coarse(Dev d) {
+  constexpr int NV = 2 + 2 * COARSE_K;
+  __shared__ double lds[5 * NV];
+  const bool on = d.scal[SC_COARSE] != 0.0;
+  double u[COARSE_K];
+  if (on) coarse_solve(d, d.Ztb, u);
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  double v[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) v[k] = 0;
+  if (e < d.nA) {
+    int o, n;
+    const double* M;
+    entry_block<CD>(d, e, o, n, M);
+    const int row = e - o;
+    auto r0 = [&](int j) {  // b - S Z u at entry j
+      double t = d.bA[j];
+      if (on)
+        for (int c = 0; c < d.coarse_k; ++c) t -= d.SZc[(int64_t)c * d.nA + j] * u[c];
+      return t;
+    };
+    const double re = r0(e);
+    double zm = 0;
+    for (int c = 0; c < n; ++c) zm += M[row * n + c] * r0(o + c);
+    d.x[e] = on ? coarse_combine(d, e, u) : 0.0;
+    d.r[e] = re;
+    d.z[e] = zm;
+    v[0] = re * zm;
+    v[1] = d.bA[e] * d.bA[e];
+    if (on)
+      for (int c = 0; c < d.coarse_k; ++c) {
+        v[2 + c] = d.Zc[(int64_t)c * d.nA + e] * re;
+        v[2 + COARSE_K + c] = d.SZc[(int64_t)c * d.nA + e] * zm;
+      }
+  }
+  double* A = acc_set(d, 2);
+  double* o2 = block_sum_arr<double, NV>(v, lds);
+  if (threadIdx.x < NV) {
+    const int k = threadIdx.x;
+    double* dst = k == 0 ? A + ACC_RZ : k == 1 ? d.scal + SC_BB : k < 2 + COARSE_K ? A + ACC_ZR + (k - 2) : A + ACC_W + (k - 2 - COARSE_K);
+    atomicAdd(dst, o2[k]);
+  }
+}
+
+// p = z = M r0 + Z E^-1 (Z^T r0 - (S Z)^T M r0)   (one thread per entry)
+template <typename T> __global__ __launch_bounds__(256) void k_pcg_init_coarse2(Dev d) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= d.nA) return;
+  double z = d.z[e];
+  if (d.scal[SC_COARSE] != 0.0) {
+    double y[COARSE_K];
+    coarse_rz(d, acc_set(d, 2), y);
+    z += coarse_combine(d, e, y);
+  }
+  d.z[e] = z;
+  d.p[e] = z;
+  ((T*)d.xT)[e] = (T)z;
 }
 
 // scalars of a new solve: accumulators cleared, tolerances set (one thread)
@@ -1489,7 +1561,12 @@ __global__ void k_pcg_reset(Dev d, double tol, int maxit) {
 __global__ void k_pcg_start(Dev d) {
   const double bb = d.scal[SC_BB];
   d.scal[SC_RR] = bb;
-  d.scal[SC_RZ] = acc_set(d, 2)[ACC_RZ];
+  double rz = acc_set(d, 2)[ACC_RZ];
+  if (d.coarse_k > 0 && d.scal[SC_COARSE] != 0.0) {
+    double y[COARSE_K];
+    rz = coarse_rz(d, acc_set(d, 2), y);
+  }
+  d.scal[SC_RZ] = rz;
   d.scal[SC_TOL2] *= bb;
   if (bb == 0.0 || d.scal[SC_MAXIT] <= 0 || !isfinite(bb)) d.scal[SC_DONE] = 1.0;
 }
@@ -1530,13 +1607,6 @@ template <typename T> __global__ __launch_bounds__(1024) void k_pcg_q(Dev d, con
   block_atomic_add<1>(dot, lds, dst);
 }
 
-// position of entry e of the reduced vector: its block's offset, size and preconditioner block
-template <int CD> __device__ __forceinline__ void entry_block(const Dev& d, int e, int& o, int& n, const double*& M) {
-  if (e < d.offPl) { const int b = e / CD; o = CD * b; n = CD; M = d.Mcam + (int64_t)CD * CD * b; }
-  else if (e < d.offVp) { const int g = (e - d.offPl) / 3; o = d.offPl + 3 * g; n = 3; M = d.Mpl + 9 * g; }
-  else { const int v = (e - d.offVp) / 2; o = d.offVp + 2 * v; n = 2; M = d.Mvp + 4 * v; }
-}
-
 // alpha = rz / pq; x += alpha p, r -= alpha q; r.r (and Z^T r) -> set k   (one thread per entry)
 template <bool COARSE> __global__ __launch_bounds__(256) void k_pcg_xr(Dev d, int k) {
   constexpr int NV = COARSE ? 1 + COARSE_K : 1;
@@ -1558,28 +1628,24 @@ template <bool COARSE> __global__ __launch_bounds__(256) void k_pcg_xr(Dev d, in
     d.r[e] = re;
     v[0] = re * re;
     if constexpr (COARSE) {
-#pragma unroll
-      for (int a = 0; a < COARSE_K; ++a) v[1 + a] = d.Zc[(int64_t)a * d.nA + e] * re;
+      for (int a = 0; a < d.coarse_k; ++a) v[1 + a] = d.Zc[(int64_t)a * d.nA + e] * re;
     }
   }
-  if constexpr (COARSE) {
-    double* A = acc_set(d, k);
-    double* const dst[NV] = {A + ACC_RR, A + ACC_ZR, A + ACC_ZR + 1, A + ACC_ZR + 2, A + ACC_ZR + 3,
-                             A + ACC_ZR + 4, A + ACC_ZR + 5, A + ACC_ZR + 6, A + ACC_ZR + 7};
-    static_assert(COARSE_K == 8, "accumulator list written for 8 columns");
-    block_atomic_add<NV>(v, lds, dst);
-  } else {
-    double* const dst[1] = {acc_set(d, k) + ACC_RR};
-    block_atomic_add<1>(v, lds, dst);
-  }
+  double* A = acc_set(d, k);
+  double* o = block_sum_arr<double, NV>(v, lds);
+  if (threadIdx.x < NV) atomicAdd(threadIdx.x == 0 ? A + ACC_RR : A + ACC_ZR + threadIdx.x - 1, o[threadIdx.x]);
 }
 
-// z = M r (block diagonal) [+ Z E^-1 Z^T r]; r.z -> set k   (one thread per entry)
+// z = M r (block diagonal); r.z -> set k; with the coarse space also (S Z)^T M r
+// (the coarse part of z is added by k_pcg_p)   (one thread per entry)
 template <int CD, bool COARSE> __global__ __launch_bounds__(256) void k_pcg_z(Dev d, int k) {
-  __shared__ double lds[5];
+  constexpr int NV = COARSE ? 1 + COARSE_K : 1;
+  __shared__ double lds[5 * NV];
   if (d.scal[SC_DONE] != 0.0 || d.scal[SC_BREAK] != 0.0) return;
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  double v[1] = {0};
+  double v[NV];
+#pragma unroll
+  for (int a = 0; a < NV; ++a) v[a] = 0;
   if (e < d.nA) {
     int o, n;
     const double* M;
@@ -1587,30 +1653,42 @@ template <int CD, bool COARSE> __global__ __launch_bounds__(256) void k_pcg_z(De
     const int row = e - o;
     double t = 0;
     for (int c = 0; c < n; ++c) t += M[row * n + c] * d.r[o + c];
-    if constexpr (COARSE) {
-      if (d.scal[SC_COARSE] != 0.0) t += coarse_term(d, e, acc_set(d, k) + ACC_ZR);
-    }
     d.z[e] = t;
     v[0] = d.r[e] * t;
+    if constexpr (COARSE) {
+      for (int a = 0; a < d.coarse_k; ++a) v[1 + a] = d.SZc[(int64_t)a * d.nA + e] * t;
+    }
   }
-  double* const dst[1] = {acc_set(d, k) + ACC_RZ};
-  block_atomic_add<1>(v, lds, dst);
+  double* A = acc_set(d, k);
+  double* o = block_sum_arr<double, NV>(v, lds);
+  if (threadIdx.x < NV) atomicAdd(threadIdx.x == 0 ? A + ACC_RZ : A + ACC_W + threadIdx.x - 1, o[threadIdx.x]);
 }
 
-// beta = rz_k / rz_(k-1); p = z + beta p; workgroup 0 updates the scalars and the stopping test
-template <typename T> __global__ __launch_bounds__(256) void k_pcg_p(Dev d, int k) {
+// beta = rz_k / rz_(k-1); p = z + beta p (z completed with the coarse term);
+// workgroup 0 updates the scalars and the stopping test
+template <typename T, bool COARSE> __global__ __launch_bounds__(256) void k_pcg_p(Dev d, int k) {
   if (d.scal[SC_DONE] != 0.0) return;
   const double* A = acc_set(d, k);
   if (d.scal[SC_BREAK] != 0.0) {
     if (blockIdx.x == 0 && threadIdx.x == 0) d.scal[SC_DONE] = 1.0;
     return;
   }
-  const double rz = A[ACC_RZ], rr = A[ACC_RR];
-  const double rz_prev = acc_set(d, k + 2)[ACC_RZ];  // set (k - 1) mod 3
+  const double rr = A[ACC_RR];
+  double rz = A[ACC_RZ];
+  double rz_prev = acc_set(d, k + 2)[ACC_RZ];  // set (k - 1) mod 3
+  double y[COARSE_K];
+  const bool on = COARSE && d.scal[SC_COARSE] != 0.0;
+  if (on) {
+    double yp[COARSE_K];
+    rz = coarse_rz(d, A, y);
+    rz_prev = coarse_rz(d, acc_set(d, k + 2), yp);
+  }
   const double beta = rz / rz_prev;
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e < d.nA) {
-    const double pk = d.z[e] + beta * d.p[e];
+    double z = d.z[e];
+    if (on) z += coarse_combine(d, e, y);
+    const double pk = z + beta * d.p[e];
     d.p[e] = pk;
     ((T*)d.xT)[e] = (T)pk;
   }
@@ -1629,11 +1707,14 @@ static unsigned pcg_blocks(const Dev& d) { return std::max(1u, std::min(64u, nbl
 
 void launch_pcg_init(const Dev& d, double tol, int max_iters, hipStream_t s) {
   k_pcg_reset<<<1, 1, 0, s>>>(d, tol, max_iters);
-  if (d.coarse) {
+  if (d.coarse_k > 0) {
     k_coarse_ztb<<<std::min(64u, nblk(d.nA, 256)), 256, 0, s>>>(d);
-    BA_DISPATCH_T_CD(d, k_pcg_init<T, CD, true><<<pcg_blocks(d), 256, 0, s>>>(d));
+    if (d.CD == 9) k_pcg_init_coarse<9><<<nblk(d.nA, 256), 256, 0, s>>>(d);
+    else k_pcg_init_coarse<6><<<nblk(d.nA, 256), 256, 0, s>>>(d);
+    if (d.fp64) k_pcg_init_coarse2<double><<<nblk(d.nA, 256), 256, 0, s>>>(d);
+    else k_pcg_init_coarse2<float><<<nblk(d.nA, 256), 256, 0, s>>>(d);
   } else {
-    BA_DISPATCH_T_CD(d, k_pcg_init<T, CD, false><<<pcg_blocks(d), 256, 0, s>>>(d));
+    BA_DISPATCH_T_CD(d, k_pcg_init<T, CD><<<pcg_blocks(d), 256, 0, s>>>(d));
   }
   k_pcg_start<<<1, 1, 0, s>>>(d);
 }
@@ -1643,14 +1724,15 @@ void launch_pcg_product(const Dev& d, hipStream_t s) { BA_DISPATCH_T_CD(d, run_m
 void launch_pcg_update(const Dev& d, double lambda, int iter, hipStream_t s) {
   BA_DISPATCH_T_CD(d, {
     k_pcg_q<T><<<nblk(d.nA, 64), 1024, 0, s>>>(d, d.scal + SC_DONE, d.p, d.q, lambda, iter);
-    if (d.coarse) {
+    if (d.coarse_k > 0) {
       k_pcg_xr<true><<<nblk(d.nA, 256), 256, 0, s>>>(d, iter);
       k_pcg_z<CD, true><<<nblk(d.nA, 256), 256, 0, s>>>(d, iter);
+      k_pcg_p<T, true><<<nblk(d.nA, 256), 256, 0, s>>>(d, iter);
     } else {
       k_pcg_xr<false><<<nblk(d.nA, 256), 256, 0, s>>>(d, iter);
       k_pcg_z<CD, false><<<nblk(d.nA, 256), 256, 0, s>>>(d, iter);
+      k_pcg_p<T, false><<<nblk(d.nA, 256), 256, 0, s>>>(d, iter);
     }
-    k_pcg_p<T><<<nblk(d.nA, 256), 256, 0, s>>>(d, iter);
   });
 }
 
@@ -1673,57 +1755,123 @@ void launch_dense_schur(const Dev& d, double lambda, double* S, hipStream_t s) {
   }
 }
 
-// E[a][b] = Z_a . (S Z)_b, one workgroup per entry
+// E[a][b] = Z_a . (S Z)_b for the active columns, one workgroup per entry
 __global__ __launch_bounds__(256) void k_coarse_e(Dev d, double* E) {
   __shared__ double lds[5];
   const int a = blockIdx.x / COARSE_K, b = blockIdx.x % COARSE_K;
   double v[1] = {0};
-  for (int e = threadIdx.x; e < d.nA; e += blockDim.x) v[0] += d.Zc[(int64_t)a * d.nA + e] * d.SZc[(int64_t)b * d.nA + e];
+  if (a < d.coarse_k && b < d.coarse_k)
+    for (int e = threadIdx.x; e < d.nA; e += blockDim.x) v[0] += d.Zc[(int64_t)a * d.nA + e] * d.SZc[(int64_t)b * d.nA + e];
   double* o = block_sum_arr<double, 1>(v, lds);
   if (threadIdx.x == 0) E[blockIdx.x] = o[0];
 }
 
-// Einv = E^-1 by Cholesky of the symmetrised E; SC_COARSE = 0 when E is not
-// positive definite or the inverse is not finite (one thread)
+// Einv = E^-1 by Cholesky of the symmetrised E (active K x K part); SC_COARSE = 0
+// when E is not positive definite or the inverse is not finite (one thread)
 __global__ void k_coarse_inv(Dev d, const double* E) {
   constexpr int Kc = COARSE_K;
+  const int K = d.coarse_k;
   double L[Kc][Kc], X[Kc][Kc];
-  bool ok = true;
+  bool ok = K > 0;
   for (int i = 0; i < Kc; ++i)
-    for (int j = 0; j < Kc; ++j) L[i][j] = 0.5 * (E[i * Kc + j] + E[j * Kc + i]);
-  for (int j = 0; j < Kc && ok; ++j) {
+    for (int j = 0; j < Kc; ++j) {
+      L[i][j] = i < K && j < K ? 0.5 * (E[i * Kc + j] + E[j * Kc + i]) : 0.0;
+      X[i][j] = 0.0;
+    }
+  for (int j = 0; j < K && ok; ++j) {
     double s = L[j][j];
     for (int k = 0; k < j; ++k) s -= L[j][k] * L[j][k];
     if (!(s > 0.0) || !isfinite(s)) { ok = false; break; }
     const double ljj = sqrt(s);
     L[j][j] = ljj;
-    for (int r = j + 1; r < Kc; ++r) {
+    for (int r = j + 1; r < K; ++r) {
       double u = L[r][j];
       for (int k = 0; k < j; ++k) u -= L[r][k] * L[j][k];
       L[r][j] = u / ljj;
     }
   }
   if (ok) {
-    // X = L^-1, then E^-1 = X^T X
-    for (int c = 0; c < Kc; ++c)
-      for (int r = 0; r < Kc; ++r) {
+    for (int c = 0; c < K; ++c)  // X = L^-1
+      for (int r = c; r < K; ++r) {
         double s = r == c ? 1.0 : 0.0;
         for (int k = c; k < r; ++k) s -= L[r][k] * X[k][c];
-        X[r][c] = r < c ? 0.0 : s / L[r][r];
-      }
-    for (int i = 0; i < Kc; ++i)
-      for (int j = 0; j < Kc; ++j) {
-        double s = 0;
-        for (int k = 0; k < Kc; ++k) s += X[k][i] * X[k][j];
-        ok = ok && isfinite(s);
-        d.Einv[i * Kc + j] = s;
+        X[r][c] = s / L[r][r];
       }
   }
+  for (int i = 0; i < Kc; ++i)
+    for (int j = 0; j < Kc; ++j) {
+      double s = 0;
+      if (ok && i < K && j < K)
+        for (int k = 0; k < K; ++k) s += X[k][i] * X[k][j];
+      ok = ok && isfinite(s);
+      d.Einv[i * Kc + j] = s;
+    }
   d.scal[SC_COARSE] = ok ? 1.0 : 0.0;
 }
 
+// similarity-gauge columns (rotation x, y, z; translation x, y, z; scale) of every
+// camera / plane / VP block, from the current FP64 parameters (one thread per block)
+__global__ void k_gauge_basis(Dev d) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= d.nc + d.ng + d.nv) return;
+  double g[9][COARSE_GAUGE];
+  int o, n;
+  for (int r = 0; r < 9; ++r)
+    for (int c = 0; c < COARSE_GAUGE; ++c) g[r][c] = 0.0;
+  if (b < d.nc) {
+    const double* cam = d.cam64 + (int64_t)CAM_STRIDE * b;  // R row-major, t
+    const double* t = cam + 9;
+    o = d.CD * b;
+    n = d.CD;
+    for (int k = 0; k < 3; ++k) {
+      const double Rk[3] = {cam[k], cam[3 + k], cam[6 + k]};  // R e_k
+      // rotation: dtheta = -R e_k, dt = (R e_k) x t; translation: dt = -R e_k
+      g[0][k] = -Rk[0]; g[1][k] = -Rk[1]; g[2][k] = -Rk[2];
+      g[3][k] = Rk[1] * t[2] - Rk[2] * t[1];
+      g[4][k] = Rk[2] * t[0] - Rk[0] * t[2];
+      g[5][k] = Rk[0] * t[1] - Rk[1] * t[0];
+      g[3][3 + k] = -Rk[0]; g[4][3 + k] = -Rk[1]; g[5][3 + k] = -Rk[2];
+    }
+    g[3][6] = t[0]; g[4][6] = t[1]; g[5][6] = t[2];
+  } else if (b < d.nc + d.ng) {
+    const int q = b - d.nc;
+    const double* pl = d.pl64 + (int64_t)PL_STRIDE * q;  // n, w, b1, b2
+    o = d.offPl + 3 * q;
+    n = 3;
+    for (int k = 0; k < 3; ++k) {
+      double en[3] = {0, 0, 0};  // e_k x n
+      en[(k + 1) % 3] = -pl[(k + 2) % 3];
+      en[(k + 2) % 3] = pl[(k + 1) % 3];
+      g[0][k] = pl[4] * en[0] + pl[5] * en[1] + pl[6] * en[2];
+      g[1][k] = pl[7] * en[0] + pl[8] * en[1] + pl[9] * en[2];
+      g[2][3 + k] = -pl[k];
+    }
+    g[2][6] = pl[3];
+  } else {
+    const int q = b - d.nc - d.ng;
+    const double* vp = d.vp64 + (int64_t)VP_STRIDE * q;  // v, pad, b1, b2
+    o = d.offVp + 2 * q;
+    n = 2;
+    for (int k = 0; k < 3; ++k) {
+      double ev[3] = {0, 0, 0};  // e_k x v
+      ev[(k + 1) % 3] = -vp[(k + 2) % 3];
+      ev[(k + 2) % 3] = vp[(k + 1) % 3];
+      g[0][k] = vp[4] * ev[0] + vp[5] * ev[1] + vp[6] * ev[2];
+      g[1][k] = vp[7] * ev[0] + vp[8] * ev[1] + vp[9] * ev[2];
+    }
+  }
+  for (int c = 0; c < COARSE_GAUGE; ++c)
+    for (int r = 0; r < n; ++r) d.Zc[(int64_t)c * d.nA + o + r] = g[r][c];
+}
+
+void launch_gauge_basis(const Dev& d, hipStream_t s) {
+  const int nb = d.nc + d.ng + d.nv;
+  if (nb > 0) k_gauge_basis<<<nblk(nb, 64), 64, 0, s>>>(d);
+}
+
 void launch_coarse_setup(const Dev& d, double lambda, hipStream_t s) {
-  for (int c = 0; c < COARSE_K; ++c) launch_schur_matvec(d, d.Zc + (int64_t)c * d.nA, d.SZc + (int64_t)c * d.nA, lambda, s);
+  for (int c = 0; c < d.coarse_k; ++c)
+    launch_schur_matvec(d, d.Zc + (int64_t)c * d.nA, d.SZc + (int64_t)c * d.nA, lambda, s);
   double* E = d.Ztb + COARSE_K;  // K x K scratch after Z^T b
   k_coarse_e<<<COARSE_K * COARSE_K, 256, 0, s>>>(d, E);
   k_coarse_inv<<<1, 1, 0, s>>>(d, E);

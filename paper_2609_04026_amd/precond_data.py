@@ -2,8 +2,9 @@
 
 A *system* is the damped reduced system of one BA problem at one lambda, as
 the library produces it: the block graph with its node and edge inputs
-(ba_export_gnn_graph) and the blocks of S on the graph's nodes and edges
-(from ba_export_schur_dense).  `make_batch` packs several systems into the
+(ba_export_gnn_graph), the gauge rows of each node (ba_export_gauge_basis)
+and the blocks of S on the graph's nodes and edges (from
+ba_export_schur_dense).  `make_batch` packs several systems into the
 ba_gnn_batch layout: nodes sorted by type over the whole batch, edges
 sorted by destination, each edge's reverse indexed.  This is host-side data
 layout only; every number comes from the library.
@@ -21,11 +22,12 @@ def system_from_handle(ba, lam):
     g = ba.export_gnn_graph()
     S = ba.export_schur_dense()
     S = 0.5 * (S + S.T)
-    return system_from_dense(g, S)
+    return system_from_dense(g, S, ba.export_gauge_basis())
 
 
-def system_from_dense(g, S):
-    """Attach the node and edge blocks of a dense S to graph arrays g."""
+def system_from_dense(g, S, gauge):
+    """Attach the node and edge blocks of a dense S and the gauge rows
+    (n_A x 7) of each node to graph arrays g."""
     n = len(g["node_type"])
     off = np.asarray(g["node_off"], dtype=np.int64)
     size = np.array([int(np.count_nonzero(g["node_unit"][i])) for i in range(n)], dtype=np.int64)
@@ -43,8 +45,11 @@ def system_from_dense(g, S):
         s_edge.append(b.ravel())
         s_edge_off[e] = o
         o += b.size
+    node_gauge = np.zeros((n, 9, gauge.shape[1]))
+    for i in range(n):
+        node_gauge[i, :size[i]] = gauge[off[i]:off[i] + size[i]]
     out = dict(g)
-    out.update(size=size, s_node=np.concatenate(s_node) if s_node else np.zeros(0),
+    out.update(size=size, node_gauge=node_gauge, s_node=np.concatenate(s_node) if s_node else np.zeros(0),
                s_node_off=s_node_off, s_edge=np.concatenate(s_edge) if s_edge else np.zeros(0),
                s_edge_off=s_edge_off, nA=int(S.shape[0]))
     return out
@@ -78,7 +83,7 @@ def make_batch(systems, with_s=True) -> GNNBatch:
         edge_base = np.cumsum([0] + [len(s["s_edge"]) for s in systems])
         s_edge_off = np.concatenate([s["s_edge_off"] + edge_base[k] for k, s in enumerate(systems)])[eorder]
         kw = dict(s_node=s_node, s_node_off=s_node_off, s_edge=s_edge if len(s_edge) else np.zeros(1),
-                  s_edge_off=s_edge_off)
+                  s_edge_off=s_edge_off, node_gauge=np.concatenate([s["node_gauge"] for s in systems])[order])
     batch = GNNBatch(node_x, types[order], sys_id[order], node_unit, src, dst, rev, ex, len(systems), **kw)
     batch.order = order  # batch node k is input node order[k] (systems concatenated)
     return batch

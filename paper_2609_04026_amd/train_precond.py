@@ -9,7 +9,8 @@ one (graph, node inputs, S blocks on the graph).  Training minimises the
 mean coarse loss over batches of systems (BF16 products, FP32 accumulation)
 with Adam and a cosine learning-rate decay; a held-out set of systems
 reports the loss and, on its smaller systems, the loss's lower bound (the
-sum of the 8 smallest eigenvalues of each block-normalised system).
+sum of the 15 smallest eigenvalues of each block-normalised system; the
+coarse space is the 7 gauge directions plus the network's 8).
 
     python -m paper_2609_04026_amd.train_precond --out weights.bin
 """
@@ -86,8 +87,9 @@ def collect_systems(n_scenes, per_scene, workers, log):
     return out
 
 
-def ky_fan_bound(sysd, K=8):
-    """Sum of the K smallest eigenvalues of the block-normalised S of a system."""
+def ky_fan_bound(sysd, K=15):
+    """Sum of the K smallest eigenvalues of the block-normalised S of a system
+    (the loss of the best 15-dimensional coarse space)."""
     n = len(sysd["node_type"])
     nA = sysd["nA"]
     S = np.zeros((nA, nA))
@@ -127,7 +129,7 @@ def main():
     ap.add_argument("--out", required=True, help="weight blob to write (float32)")
     ap.add_argument("--scenes", type=int, default=340)
     ap.add_argument("--per-scene", type=int, default=6)
-    ap.add_argument("--steps", type=int, default=3000)
+    ap.add_argument("--steps", type=int, default=6000)
     ap.add_argument("--batch", type=int, default=8)
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--holdout", type=float, default=0.05)

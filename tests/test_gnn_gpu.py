@@ -31,7 +31,8 @@ def _oracle_system(sc, lam, precision_state=None):
     s0 = gnn.scene_scale(sc["cameras"])
     x = gnn.node_inputs(g, [S[o:o + n, o:o + n] for o, n in zip(g["offsets"], g["sizes"])], lam, st, s0)
     units = gnn.unit_scales(g, s0, prob.camera_dof)
-    return dict(prob=prob, st=st, S=S, graph=g, x=x, units=units, s0=s0, lam=lam)
+    G = gnn.gauge_basis(prob, st)
+    return dict(prob=prob, st=st, S=S, graph=g, x=x, units=units, s0=s0, lam=lam, gauge=G)
 
 
 def _as_library_graph(o):
@@ -71,17 +72,19 @@ def test_graph_and_inputs_match_oracle(systems):
         assert np.allclose(g["node_x"], o["x"], atol=2e-5, rtol=1e-5), np.abs(g["node_x"] - o["x"]).max()
         S = ba.export_schur_dense()
         assert np.abs(S - o["S"]).max() <= 1e-9 * np.abs(o["S"]).max()
+        G = ba.export_gauge_basis()
+        assert np.abs(G - o["gauge"]).max() <= 1e-12 * np.abs(o["gauge"]).max()
         ba.close()
 
 
 def _batch(systems):
     from paper_2609_04026_amd.precond_data import make_batch, system_from_dense
-    return make_batch([system_from_dense(_as_library_graph(o), o["S"]) for o in systems])
+    return make_batch([system_from_dense(_as_library_graph(o), o["S"], o["gauge"]) for o in systems])
 
 
 def _oracle_heads_loss_grads(params, systems, cd=9):
-    sysd = [dict(node_x=o["x"].astype(np.float32).astype(np.float64), graph=o["graph"], S=o["S"], units=o["units"])
-            for o in systems]
+    sysd = [dict(node_x=o["x"].astype(np.float32).astype(np.float64), graph=o["graph"], S=o["S"], units=o["units"],
+                 gauge=o["gauge"]) for o in systems]
     L, grads = gnn.loss_and_grads(params, sysd, cd)
     heads = []
     for o in sysd:
@@ -142,9 +145,10 @@ def test_adam_first_step(systems):
 
 
 def test_coarse_pcg_matches_oracle():
-    """PCG with the coarse correction from the same weights: the library and
-    the oracle reach the same solution in the same number of iterations (up
-    to the BF16 rounding of the network)."""
+    """PCG with the two-level preconditioners (gauge only; gauge + network
+    from the same weights): the library and the oracle reach the same
+    solution in about the same number of iterations (the network runs in
+    BF16 on the GPU)."""
     from paper_2609_04026_amd.binding import BA
     sc = make_scene(small_config(n_cams=12, n_points=80, n_lines=20, n_planes=3, n_vps=3), seed=31)
     lam = 1e-4
@@ -153,28 +157,31 @@ def test_coarse_pcg_matches_oracle():
     g = o["graph"]
     Y = gnn.forward(params, o["x"].astype(np.float32).astype(np.float64), g["node_type"], g["edge_src"],
                     g["edge_dst"], g["edge_x"], 9)
-    Z = gnn.coarse_basis(Y, o["units"]).detach().numpy()
+    Z = gnn.full_basis(o["gauge"], Y, o["units"]).detach().numpy()
     prob = o["prob"]
     b = lm.schur(prob, lm.linearize(prob, o["st"]), lam)["b"]
     x_ref = np.linalg.solve(o["S"], b)
-    _, it_bj = gnn.pcg(o["S"], b, gnn.two_level(o["S"], g["sizes"], None), tol=1e-8)
-    _, it_cs = gnn.pcg(o["S"], b, gnn.two_level(o["S"], g["sizes"], Z), tol=1e-8)
-    for precond, it_ref in (("jacobi", it_bj), ("learned", it_cs)):
+    ref = {}
+    for name, basis in (("jacobi", None), ("gauge", o["gauge"]), ("learned", Z)):
+        P, Q = gnn.two_level(o["S"], g["sizes"], basis)
+        _, ref[name] = gnn.pcg(o["S"], b, P, tol=1e-8, x0=None if Q is None else Q @ b)
+    for precond, cols in (("jacobi", 0), ("gauge", 7), ("learned", 15)):
         ba = BA.from_scene(sc, precision="fp64", precond=precond)
         ba.set_gnn_weights(gnn.pack(params).tobytes())
         ba.linearize(lam)
         x, it, rel = ba.pcg_solve(tol=1e-8, max_iters=500)
-        print(precond, "iterations", it, "oracle", it_ref, flush=True)
+        print(precond, "iterations", it, "oracle", ref[precond], flush=True)
         assert np.linalg.norm(x - x_ref) <= 1e-5 * np.linalg.norm(x_ref)
-        assert abs(it - it_ref) <= max(2, it_ref // 10), (precond, it, it_ref)
+        assert abs(it - ref[precond]) <= max(2, ref[precond] // 10), (precond, it, ref[precond])
         rep = ba.lm_step(pcg_tol=1e-8)
-        assert rep["coarse"] == (1 if precond == "learned" else 0)
+        assert rep["coarse"] == cols
         ba.close()
+    assert ref["gauge"] < ref["jacobi"]
 
 
 def test_zero_head_falls_back_to_block_jacobi():
-    """A zero output head gives Z = 0: E is singular, the coarse term is off
-    and PCG takes exactly the block-Jacobi iterations."""
+    """A zero output head gives zero network columns: E is singular, the
+    coarse term is off and PCG takes the block-Jacobi iterations."""
     from paper_2609_04026_amd.binding import BA
     sc = make_scene(small_config(n_cams=10, n_points=60, n_lines=16), seed=41)
     p = gnn.init_params(9, seed=24)
@@ -191,8 +198,11 @@ def test_zero_head_falls_back_to_block_jacobi():
         assert rep["coarse"] == 0
         out[precond] = (x, it)
         ba.close()
+    # same iterations; the solutions agree to the accuracy of a 1e-10 solve (FP64 atomic
+    # reductions sum in a different order from run to run)
     assert out["jacobi"][1] == out["learned"][1]
-    assert np.array_equal(out["jacobi"][0], out["learned"][0])
+    xj, xl = out["jacobi"][0], out["learned"][0]
+    assert np.linalg.norm(xj - xl) <= 1e-7 * np.linalg.norm(xj)
 
 
 WEIGHTS = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2609_04026_amd",
@@ -201,28 +211,29 @@ WEIGHTS = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__)
 
 @pytest.mark.skipif(not os.path.exists(WEIGHTS), reason="no trained weights shipped")
 def test_trained_network_gain_over_block_jacobi():
-    """The shipped network against block-Jacobi on held-out scenes (the
-    30-camera and 200-camera workloads; the training scenes use other
-    seeds): fewer PCG iterations to 1e-6 over a range of lambda, and the
-    same converged LM cost."""
+    """The shipped network on held-out scenes (the 30-camera and 200-camera
+    workloads; the training scenes use other seeds): PCG iterations to 1e-6
+    over a range of lambda for block-Jacobi, gauge-only and gauge + network;
+    the learned space must cut block-Jacobi's iterations, and the converged
+    LM cost must not change."""
     from paper_2609_04026_amd.binding import BA
     blob = open(WEIGHTS, "rb").read()
     golden = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "oracle_converged.json")))
     for cfg in (2, 3):
         sc = make_scene(cfg)
         its = {}
-        for precond in ("jacobi", "learned"):
+        for precond in ("jacobi", "gauge", "learned"):
             ba = BA.from_scene(sc, precision="mixed", precond=precond)
             ba.set_gnn_weights(blob)
             n = 0
-            for lam in (1e-5, 1e-4, 1e-3):
+            for lam in (1e-8, 1e-6, 1e-4, 1e-2):
                 ba.linearize(lam)
                 _, it, rel = ba.pcg_solve(tol=1e-6, max_iters=3000)
                 assert rel <= 1e-6
                 n += it
             its[precond] = n
             ba.close()
-        print(f"scene {cfg}: PCG iterations jacobi {its['jacobi']} learned {its['learned']}", flush=True)
+        print(f"scene {cfg}: PCG iterations {its}", flush=True)
         assert its["learned"] <= 0.8 * its["jacobi"], its
     # the preconditioner does not change the answer: converged cost of the 30-camera scene
     sc = make_scene(2)

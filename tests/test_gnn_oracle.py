@@ -7,7 +7,8 @@ K-dimensional subspaces is the sum of the K smallest eigenvalues of the
 block-normalised matrix), invariance of the loss under a change of basis of
 span(Z), node-permutation equivariance of the network, known values of the
 tanh form of GELU, brute-force shared-feature counts of the block graph,
-and the effect of an exact slow-mode basis on textbook PCG.
+the annihilation of the gauge basis by the undamped reduced matrix, and the
+effect of exact slow-mode bases on textbook PCG.
 """
 import math
 
@@ -33,7 +34,8 @@ def tiny():
     s0 = gnn.scene_scale(sc["cameras"])
     x = gnn.node_inputs(g, blocks, lam, st, s0)
     u = gnn.unit_scales(g, s0, prob.camera_dof)
-    return dict(sc=sc, prob=prob, st=st, S=S, graph=g, x=x, units=u, s0=s0, lam=lam)
+    G = gnn.gauge_basis(prob, st)
+    return dict(sc=sc, prob=prob, st=st, S=S, graph=g, x=x, units=u, s0=s0, lam=lam, gauge=G, lin=lin)
 
 
 def _normalised(S, sizes):
@@ -116,7 +118,7 @@ def test_node_inputs_structure(tiny):
 def test_loss_gradient_matches_central_differences(tiny):
     cd = tiny["prob"].camera_dof
     p = gnn.init_params(cd, seed=3)
-    sysd = [dict(node_x=tiny["x"], graph=tiny["graph"], S=tiny["S"], units=tiny["units"])]
+    sysd = [dict(node_x=tiny["x"], graph=tiny["graph"], S=tiny["S"], units=tiny["units"], gauge=tiny["gauge"])]
     L, grads = gnn.loss_and_grads(p, sysd, cd)
     assert np.isfinite(L)
     rng = np.random.default_rng(0)
@@ -136,7 +138,7 @@ def test_loss_ky_fan_bound_and_basis_invariance(tiny):
     S, g = tiny["S"], tiny["graph"]
     Linv, Sh = _normalised(S, g["sizes"])
     w, V = np.linalg.eigh(Sh)
-    K = gnn.K
+    K = gnn.K + gnn.K_GAUGE
     # exact slow modes: Z = L^-T V_K gives the sum of the K smallest eigenvalues
     Z = torch.as_tensor(Linv.T @ V[:, :K])
     assert float(gnn.coarse_loss(Z, S, g["sizes"])) == pytest.approx(w[:K].sum(), rel=1e-9)
@@ -164,25 +166,56 @@ def test_network_is_equivariant_to_camera_relabelling(tiny):
         assert torch.allclose(Y2[k], Y[perm[k]], atol=1e-12)
 
 
+def test_gauge_basis_is_annihilated_by_the_undamped_reduced_matrix(tiny):
+    """Every residual except the VP 3-vector is invariant under a world
+    similarity, so J [G; G_f] = 0 and the reduced matrix maps the gauge basis
+    to O(lambda).  The VP residual (d/|d|) x v rotates with the world (its norm
+    does not), which leaves O(|r_VP|) in the rotation columns: exact at a
+    noise-free state, checked there with VPs present."""
+    def rel_residual(sc, lam):
+        prob = lm.Problem(sc)
+        st = prob.state0()
+        S = lm.schur(prob, lm.linearize(prob, st), lam)["S"]
+        G = gnn.gauge_basis(prob, st)
+        assert np.linalg.matrix_rank(G) == gnn.K_GAUGE
+        return np.linalg.norm(S @ G, axis=0) / (np.linalg.norm(S) * np.linalg.norm(G, axis=0)), S
+    no_vp = small_config(n_cams=6, n_points=30, n_lines=10, n_planes=2, n_vps=0, vp_lines=0)
+    for lam in (1e-10, 1e-6):
+        rel, S = rel_residual(make_scene(no_vp, seed=7), lam)
+        assert rel.max() < 50 * lam + 1e-11, (lam, rel)
+    with_vp = small_config(n_cams=6, n_points=30, n_lines=10, n_planes=2, n_vps=2)
+    rel, S = rel_residual(make_scene(with_vp, seed=7, noise=False), 1e-10)
+    assert rel.max() < 1e-9, rel
+    # a generic direction is not annihilated
+    v = np.random.default_rng(3).normal(size=(S.shape[0], 1))
+    assert np.linalg.norm(S @ v) / (np.linalg.norm(S) * np.linalg.norm(v)) > 1e-4
+
+
 def test_exact_slow_modes_cut_pcg_iterations(tiny):
-    """Textbook PCG with P = M + Z (Z^T S Z)^-1 Z^T and Z the exact slowest
-    block-normalised modes needs fewer iterations than block-Jacobi alone,
-    and both reach the same solution."""
-    S, g = tiny["S"], tiny["graph"]
+    """Textbook PCG with the A-DEF2 two-level preconditioner started from
+    x0 = Q b: the gauge basis alone, and the gauge plus the exact next slowest
+    modes, need fewer iterations than block-Jacobi; all reach the same x."""
+    S, g, G = tiny["S"], tiny["graph"], tiny["gauge"]
     b = np.random.default_rng(4).normal(size=S.shape[0])
     Linv, Sh = _normalised(S, g["sizes"])
-    w, V = np.linalg.eigh(Sh)
-    Z = Linv.T @ V[:, :gnn.K]
-    P0 = gnn.two_level(S, g["sizes"], None)
-    P1 = gnn.two_level(S, g["sizes"], Z)
-    assert np.allclose(P1, P1.T, atol=1e-8 * np.abs(P1).max())
-    assert np.linalg.eigvalsh(0.5 * (P1 + P1.T)).min() > 0
-    x0, it0 = gnn.pcg(S, b, P0, tol=1e-10)
-    x1, it1 = gnn.pcg(S, b, P1, tol=1e-10)
+    # the next slowest block-normalised modes after removing span(L^T G)
+    Q0, _ = np.linalg.qr(np.linalg.solve(Linv.T, G))  # span of the gauge in block-normalised coordinates
+    Pp = np.eye(len(b)) - Q0 @ Q0.T
+    w, V = np.linalg.eigh(Pp @ Sh @ Pp)
+    keep = [k for k in np.argsort(w) if w[k] > 1e-10][:gnn.K]
+    Zn = Linv.T @ V[:, keep]
     xs = np.linalg.solve(S, b)
-    assert np.linalg.norm(x0 - xs) <= 1e-6 * np.linalg.norm(xs)
-    assert np.linalg.norm(x1 - xs) <= 1e-6 * np.linalg.norm(xs)
-    assert it1 < it0, (it0, it1)
+    its = {}
+    for name, Z in (("bj", None), ("gauge", G), ("gauge+next", np.hstack([G, Zn]))):
+        P, Q = gnn.two_level(S, g["sizes"], Z)
+        x, it = gnn.pcg(S, b, P, tol=1e-10, x0=None if Q is None else Q @ b)
+        assert np.linalg.norm(x - xs) <= 1e-6 * np.linalg.norm(xs), name
+        its[name] = it
+    assert its["gauge"] < its["bj"] and its["gauge+next"] <= its["gauge"], its
+    # the coarse-space start already solves the problem restricted to span(Z)
+    P, Q = gnn.two_level(S, g["sizes"], G)
+    r0 = b - S @ (Q @ b)
+    assert np.abs(G.T @ r0).max() <= 1e-8 * np.abs(G.T @ b).max()
 
 
 def test_pack_unpack_round_trip():
@@ -217,6 +250,8 @@ def test_inputs_and_loss_do_not_change_when_the_scene_is_scaled(tiny):
     assert np.allclose(x, tiny["x"], atol=1e-8)
     cd = prob.camera_dof
     p = gnn.init_params(cd, seed=9)
-    L1 = float(gnn.batch_loss(p, [dict(node_x=tiny["x"], graph=tiny["graph"], S=tiny["S"], units=tiny["units"])], cd))
-    L2 = float(gnn.batch_loss(p, [dict(node_x=x, graph=g, S=S, units=gnn.unit_scales(g, s0, cd))], cd))
+    L1 = float(gnn.batch_loss(p, [dict(node_x=tiny["x"], graph=tiny["graph"], S=tiny["S"], units=tiny["units"],
+                                       gauge=tiny["gauge"])], cd))
+    L2 = float(gnn.batch_loss(p, [dict(node_x=x, graph=g, S=S, units=gnn.unit_scales(g, s0, cd),
+                                       gauge=gnn.gauge_basis(prob, st))], cd))
     assert L2 == pytest.approx(L1, rel=1e-7)
