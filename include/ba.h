@@ -308,6 +308,12 @@ ba_status ba_export_schur_dense(ba_handle *h, double *S);
  * (b1, b2) . (w x v). */
 ba_status ba_export_gauge_basis(ba_handle *h, double *G);
 
+/* The coarse space of the last assembly (BA_PC_GAUGE / BA_PC_LEARNED): its
+ * column count k (0 for block-Jacobi), Z and S Z (n_A x k doubles each,
+ * row-major, caller-allocated, NULL skipped; size them with k from a first
+ * call with both NULL). */
+ba_status ba_export_coarse_space(ba_handle *h, int32_t *k, double *Z, double *SZ);
+
 /* y = L^-1 S L^-T x with S_ii = L_i L_i^T (the block-normalised reduced
  * system of the last ba_linearize); x, y: n_A doubles (host). */
 ba_status ba_normalized_matvec(ba_handle *h, const double *x, double *y);

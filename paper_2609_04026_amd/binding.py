@@ -107,6 +107,7 @@ def _load():
         "ba_normalized_matvec": (c_int32, [H, D, D]),
         "ba_export_schur_dense": (c_int32, [H, D]),
         "ba_export_gauge_basis": (c_int32, [H, D]),
+        "ba_export_coarse_space": (c_int32, [H, I32, D, D]),
         "ba_gnn_create": (c_int32, [c_int32, c_int32, c_int32, POINTER(c_void_p)]),
         "ba_gnn_set_params": (c_int32, [H, F, c_size_t]),
         "ba_gnn_get_params": (c_int32, [H, F, c_size_t]),
@@ -334,6 +335,17 @@ class BA:
         G = np.zeros((nA, 7))
         self._check(_lib.ba_export_gauge_basis(self._h, _dp(G)))
         return G
+
+    def export_coarse_space(self):
+        """(Z, S Z) of the last assembly's coarse space (n_A x k each), or None for block-Jacobi."""
+        k = c_int32()
+        self._check(_lib.ba_export_coarse_space(self._h, ctypes.byref(k), None, None))
+        if k.value == 0:
+            return None
+        nA, _ = self.reduced_dim()
+        Z, SZ = np.zeros((nA, k.value)), np.zeros((nA, k.value))
+        self._check(_lib.ba_export_coarse_space(self._h, None, _dp(Z), _dp(SZ)))
+        return Z, SZ
 
     def normalized_matvec(self, x):
         x = np.ascontiguousarray(x, dtype=np.float64)

@@ -8,6 +8,8 @@
 // Network (hidden width H = 64, gelu(x) = x/2 (1 + tanh(sqrt(2/pi)(x + 0.044715 x^3)))):
 //   h = gelu(x W_in + b_in)
 //   3 times:  m_i = mean_{edges j -> i} gelu([h_j, e_ji] W_e + b_e)
+//             (computed as (h W_h)_j + e_ji W_x + b_e: the h-part per node, then one
+//             pass over the edges)
 //             h = gelu(h W_s + b_s + m) + h
 //   Y_i = h_i W_t + b_t for the node's type t (row-major n_t x K)
 // Training loss per system: tr((Z^T D Z)^-1 Z^T S Z), D = blockdiag(S_ii)
@@ -190,42 +192,52 @@ __global__ void k_act_bwd(const float* dOut, const float* Zpre, float* dZ, int64
     dZ[i] = dOut[i] * gelu_d(Zpre[i]);
 }
 
-// edge input rows [h_src, e]
-__global__ void k_edge_input(const float* Hm, const float* ex, const int32_t* src, float* E, int m) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < (int64_t)m * EK; i += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t e = i / EK;
-    const int c = (int)(i % EK);
-    E[i] = c < H ? Hm[(int64_t)src[e] * H + c] : ex[e * EIN + (c - H)];
+// messages of one layer, with [h_j, e_ji] W_e = (h W_h)_j + e_ji W_x:
+// Ze_e = Ph[src_e] + e_e W_x + b_e (stored when Ze != null), m_i = mean over in-edges of gelu(Ze).
+// Work items are runs of <= EDGE_RUN in-edges of one node (high-degree nodes split
+// over several items); one thread per (item, channel) adds its run's share to Mm
+// (cleared before) with FP32 atomics.
+constexpr int EDGE_RUN = 32;
+__global__ void k_edge_msg(const float* Ph, const float* ex, const float* Wx, const float* be, const int32_t* src,
+                           const int32_t* off, const int2* runs, int n_runs, float* Ze, float* Mm) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < (int64_t)n_runs * H; i += (int64_t)gridDim.x * blockDim.x) {
+    const int2 run = runs[i / H];  // (node, first edge)
+    const int c = (int)(i % H), node = run.x;
+    const int e0 = run.y, e1 = min(off[node + 1], e0 + EDGE_RUN);
+    float w[EIN];
+#pragma unroll
+    for (int k = 0; k < EIN; ++k) w[k] = Wx[k * H + c];
+    const float bc = be[c];
+    float acc = 0;
+    static_assert(EIN == 8, "edge inputs are read as two float4");
+    for (int e = e0; e < e1; ++e) {
+      float z = Ph[(int64_t)src[e] * H + c] + bc;
+      const float4 x0 = reinterpret_cast<const float4*>(ex)[2 * (int64_t)e];
+      const float4 x1 = reinterpret_cast<const float4*>(ex)[2 * (int64_t)e + 1];
+      z += x0.x * w[0] + x0.y * w[1] + x0.z * w[2] + x0.w * w[3] + x1.x * w[4] + x1.y * w[5] + x1.z * w[6] + x1.w * w[7];
+      if (Ze) Ze[(int64_t)e * H + c] = z;
+      acc += gelu(z);
+    }
+    atomicAdd(Mm + (int64_t)node * H + c, acc / (float)(off[node + 1] - off[node]));
   }
 }
 
-// M_i = mean of msg over the edges into i (CSR by destination)
-__global__ void k_mean(const float* msg, const int32_t* off, float* Mo, int n) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < (int64_t)n * H; i += (int64_t)gridDim.x * blockDim.x) {
-    const int node = (int)(i / H), c = (int)(i % H);
-    const int b = off[node], e = off[node + 1];
-    float s = 0;
-    for (int k = b; k < e; ++k) s += msg[(int64_t)k * H + c];
-    Mo[i] = e > b ? s / (float)(e - b) : 0.0f;
-  }
-}
-
-__global__ void k_mean_bwd(const float* dM, const int32_t* dst, const int32_t* off, float* dmsg, int m) {
+// dZe_e = dM[dst_e] / deg(dst_e) * gelu'(Ze_e)   (one thread per edge entry)
+__global__ void k_edge_msg_bwd(const float* dM, const float* Ze, const int32_t* dst, const int32_t* off, float* dZe, int m) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < (int64_t)m * H; i += (int64_t)gridDim.x * blockDim.x) {
     const int e = (int)(i / H), c = (int)(i % H);
     const int d = dst[e];
-    dmsg[i] = dM[(int64_t)d * H + c] / (float)(off[d + 1] - off[d]);
+    dZe[i] = dM[(int64_t)d * H + c] / (float)(off[d + 1] - off[d]) * gelu_d(Ze[i]);
   }
 }
 
-// dH_i += sum over edges out of i of dE[e, 0:H]; the edges out of i are the
-// reverses of the edges into i
-__global__ void k_gather_rev(const float* dE, const int32_t* rev, const int32_t* off, float* dH, int n) {
+// dP_j = sum over edges out of j of dZe (the reverses of the edges into j), stride H
+__global__ void k_scatter_src(const float* dZe, const int32_t* rev, const int32_t* off, float* dP, int n) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < (int64_t)n * H; i += (int64_t)gridDim.x * blockDim.x) {
     const int node = (int)(i / H), c = (int)(i % H);
     float s = 0;
-    for (int k = off[node]; k < off[node + 1]; ++k) s += dE[(int64_t)rev[k] * EK + c];
-    dH[i] += s;
+    for (int k = off[node]; k < off[node + 1]; ++k) s += dZe[(int64_t)rev[k] * H + c];
+    dP[i] = s;
   }
 }
 
@@ -509,12 +521,17 @@ struct ba_gnn {
   bool attached_training = false;  // the batch buffers hold a training batch, not the attached graph
   // batch buffers (capacity in nodes, edges, systems, S entries)
   int cap_n = 0, cap_m = 0, cap_g = 0;
+  bool cap_train = false;  // the edge buffers of the backward pass exist
   int64_t cap_sn = 0, cap_se = 0;
-  float *X = nullptr, *Zin = nullptr, *Hs = nullptr /*4 x n x H*/, *E = nullptr /*LAYERS x m x EK*/, *Ze = nullptr,
-        *Msg = nullptr, *Mm = nullptr, *Zs = nullptr, *heads = nullptr, *dheads = nullptr, *dH = nullptr,
+  float *X = nullptr, *Zin = nullptr, *Hs = nullptr /*4 x n x H*/, *Ph = nullptr /*LAYERS x n x H*/,
+        *Ze = nullptr /*LAYERS x m x H, training only*/, *Mm = nullptr, *Zs = nullptr, *heads = nullptr, *dheads = nullptr, *dH = nullptr,
         *dH2 = nullptr, *dZ = nullptr, *dE = nullptr, *ex = nullptr, *unit = nullptr;
   uint16_t *bfA = nullptr, *bfB = nullptr;  // BF16 operand scratch
   int32_t *type = nullptr, *graph = nullptr, *src = nullptr, *dst = nullptr, *rev = nullptr, *dst_off = nullptr;
+  int2* runs = nullptr;  // edge runs of the message kernel (node, first edge)
+  int n_runs = 0;
+  std::vector<int32_t> h_off;  // host copies kept alive across the asynchronous uploads
+  std::vector<int2> h_runs;
   double *SZ = nullptr, *DZ = nullptr, *Ag = nullptr, *Q1 = nullptr, *Q2 = nullptr, *gauge = nullptr;
   double *s_node = nullptr, *s_edge = nullptr;
   int64_t *s_node_off = nullptr, *s_edge_off = nullptr;
@@ -540,41 +557,43 @@ void dfree(ba_gnn* g, void* p) {
   g->allocs.erase(std::remove(g->allocs.begin(), g->allocs.end(), p), g->allocs.end());
 }
 
-void reserve(ba_gnn* g, int n, int m, int G, int64_t sn, int64_t se) {
-  if (n <= g->cap_n && m <= g->cap_m && G <= g->cap_g && sn <= g->cap_sn && se <= g->cap_se) return;
+void reserve(ba_gnn* g, int n, int m, int G, int64_t sn, int64_t se, bool train) {
+  if (n <= g->cap_n && m <= g->cap_m && G <= g->cap_g && sn <= g->cap_sn && se <= g->cap_se && (!train || g->cap_train))
+    return;
+  train = train || g->cap_train;
   n = std::max(n, g->cap_n); m = std::max(m, g->cap_m); G = std::max(G, g->cap_g);
   sn = std::max(sn, g->cap_sn); se = std::max(se, g->cap_se);
-  float** fl[] = {&g->X, &g->Zin, &g->Hs, &g->E, &g->Ze, &g->Msg, &g->Mm, &g->Zs, &g->heads, &g->dheads,
+  float** fl[] = {&g->X, &g->Zin, &g->Hs, &g->Ph, &g->Ze, &g->Mm, &g->Zs, &g->heads, &g->dheads,
                   &g->dH, &g->dH2, &g->dZ, &g->dE, &g->ex, &g->unit};
   for (float** p : fl) { dfree(g, *p); *p = nullptr; }
   int32_t** il[] = {&g->type, &g->graph, &g->src, &g->dst, &g->rev, &g->dst_off};
   for (int32_t** p : il) { dfree(g, *p); *p = nullptr; }
   double** dl[] = {&g->SZ, &g->DZ, &g->Ag, &g->Q1, &g->Q2, &g->s_node, &g->s_edge, &g->gauge};
   for (double** p : dl) { dfree(g, *p); *p = nullptr; }
-  dfree(g, g->bfA); dfree(g, g->bfB); dfree(g, g->s_node_off); dfree(g, g->s_edge_off);
+  dfree(g, g->bfA); dfree(g, g->bfB); dfree(g, g->s_node_off); dfree(g, g->s_edge_off); dfree(g, g->runs);
   const size_t nh = (size_t)n * H, mh = (size_t)m * H;
   g->X = dalloc<float>(g, (size_t)n * NIN);
   g->Zin = dalloc<float>(g, nh);
   g->Hs = dalloc<float>(g, (LAYERS + 1) * nh);
-  g->E = dalloc<float>(g, (size_t)LAYERS * m * EK);
-  g->Ze = dalloc<float>(g, (size_t)LAYERS * mh);
-  g->Msg = dalloc<float>(g, (size_t)LAYERS * mh);
+  g->Ph = dalloc<float>(g, (size_t)LAYERS * nh);
+  g->Ze = dalloc<float>(g, train ? (size_t)LAYERS * mh : 1);
   g->Mm = dalloc<float>(g, (size_t)LAYERS * nh);
   g->Zs = dalloc<float>(g, (size_t)LAYERS * nh);
   g->heads = dalloc<float>(g, (size_t)n * HEADP);
   g->dheads = dalloc<float>(g, (size_t)n * HEADP);
   g->dH = dalloc<float>(g, nh);
   g->dH2 = dalloc<float>(g, nh);
-  g->dZ = dalloc<float>(g, std::max(nh, mh));
-  g->dE = dalloc<float>(g, (size_t)m * EK);
+  g->dZ = dalloc<float>(g, nh);
+  g->dE = dalloc<float>(g, train ? mh : 1);
   g->ex = dalloc<float>(g, (size_t)m * EIN);
   g->unit = dalloc<float>(g, (size_t)n * 9);
-  const size_t big = std::max({(size_t)m * EK, mh, nh, (size_t)n * HEADP});
+  const size_t big = std::max({train ? mh : 1, (size_t)m * EIN, nh, (size_t)n * HEADP});
   g->bfA = dalloc<uint16_t>(g, big);
   g->bfB = dalloc<uint16_t>(g, big);
   g->type = dalloc<int32_t>(g, n); g->graph = dalloc<int32_t>(g, n);
   g->src = dalloc<int32_t>(g, m); g->dst = dalloc<int32_t>(g, m); g->rev = dalloc<int32_t>(g, m);
   g->dst_off = dalloc<int32_t>(g, n + 1);
+  g->runs = dalloc<int2>(g, (size_t)m / EDGE_RUN + n + 1);
   g->SZ = dalloc<double>(g, (size_t)n * 9 * KT);
   g->DZ = dalloc<double>(g, (size_t)n * 9 * KT);
   g->Ag = dalloc<double>(g, (size_t)2 * G * KT * KT);  // A then G
@@ -585,7 +604,7 @@ void reserve(ba_gnn* g, int n, int m, int G, int64_t sn, int64_t se) {
   g->s_edge = dalloc<double>(g, se);
   g->s_node_off = dalloc<int64_t>(g, n);
   g->s_edge_off = dalloc<int64_t>(g, m);
-  g->cap_n = n; g->cap_m = m; g->cap_g = G; g->cap_sn = sn; g->cap_se = se;
+  g->cap_n = n; g->cap_m = m; g->cap_g = G; g->cap_sn = sn; g->cap_se = se; g->cap_train = train;
 }
 
 // C = A B  (A: M x K, B: K x N); operands FP32 in device memory with the given strides.
@@ -634,7 +653,9 @@ struct Dims {
 };
 
 // forward over the batch currently in the device buffers
-void forward(ba_gnn* g, const Dims& D) {
+// forward over the batch (or attached graph) in the device buffers; keep_edges stores
+// the edge pre-activations for the backward pass
+void forward(ba_gnn* g, const Dims& D, bool keep_edges) {
   const int n = D.n, m = D.m;
   const Layout& L = g->L;
   const float* P = g->params;
@@ -646,18 +667,17 @@ void forward(ba_gnn* g, const Dims& D) {
   for (int l = 0; l < LAYERS; ++l) {
     float* hl = g->Hs + (size_t)l * n * H;
     float* hn = g->Hs + (size_t)(l + 1) * n * H;
-    float* E = g->E + (size_t)l * m * EK;
-    float* Ze = g->Ze + (size_t)l * m * H;
-    float* Msg = g->Msg + (size_t)l * m * H;
+    float* Ph = g->Ph + (size_t)l * n * H;
     float* Mm = g->Mm + (size_t)l * n * H;
     float* Zs = g->Zs + (size_t)l * n * H;
-    if (m > 0) {
-      hipLaunchKernelGGL(k_edge_input, dim3(nblk((int64_t)m * EK, 256)), dim3(256), 0, g->cur, hl, g->ex, g->src, E, m);
-      gemm(g, m, H, EK, E, EK, 1, P + L.W_e[l], H, 1, Ze, H, 0, true, L.W_e[l]);
-      hipLaunchKernelGGL(k_bias_act, dim3(nblk((int64_t)m * H, 256)), dim3(256), 0, g->cur, Ze, P + L.b_e[l],
-                         (const float*)nullptr, (const float*)nullptr, Msg, m, H);
-    }
-    hipLaunchKernelGGL(k_mean, dim3(nblk((int64_t)n * H, 256)), dim3(256), 0, g->cur, Msg, g->dst_off, Mm, n);
+    // messages: the h-part of W_e applied per node, then one pass over the edges
+    gemm(g, n, H, H, hl, H, 1, P + L.W_e[l], H, 1, Ph, H, 0, true, L.W_e[l]);
+    GCHK(hipMemsetAsync(Mm, 0, (size_t)n * H * sizeof(float), g->cur));
+    if (g->n_runs > 0)
+      hipLaunchKernelGGL(k_edge_msg, dim3(nblk((int64_t)g->n_runs * H, 256)), dim3(256), 0, g->cur, (const float*)Ph,
+                         (const float*)g->ex, P + L.W_e[l] + (size_t)H * H, P + L.b_e[l], (const int32_t*)g->src,
+                         (const int32_t*)g->dst_off, (const int2*)g->runs, g->n_runs,
+                         keep_edges && m > 0 ? g->Ze + (size_t)l * m * H : (float*)nullptr, Mm);
     gemm(g, n, H, H, hl, H, 1, P + L.W_s[l], H, 1, Zs, H, 0, true, L.W_s[l]);
     hipLaunchKernelGGL(k_bias_act, dim3(nblk((int64_t)n * H, 256)), dim3(256), 0, g->cur, Zs, P + L.b_s[l],
                        (const float*)Mm, (const float*)hl, hn, n, H);
@@ -708,26 +728,28 @@ void backward(ba_gnn* g, const Dims& D) {
   float* dh2 = g->dH2; // gradient w.r.t. h_l
   for (int l = LAYERS - 1; l >= 0; --l) {
     const float* hl = g->Hs + (size_t)l * n * H;
-    const float* E = g->E + (size_t)l * m * EK;
     const float* Ze = g->Ze + (size_t)l * m * H;
     const float* Zs = g->Zs + (size_t)l * n * H;
     float* dZ = g->dZ;
-    // node update: h_{l+1} = gelu(Zs) + h_l
+    // node update: h_{l+1} = gelu(Zs) + h_l, Zs = h_l W_s + b_s + m
     hipLaunchKernelGGL(k_act_bwd, dim3(nblk((int64_t)n * H, 256)), dim3(256), 0, g->cur, dh, Zs, dZ, (int64_t)n * H);
     gemm(g, H, H, n, hl, 1, H, dZ, H, 1, G + L.W_s[l], H, 2);
     colsum(g, dZ, n, H, H, G + L.b_s[l]);
     GCHK(hipMemcpyAsync(dh2, dh, (size_t)n * H * sizeof(float), hipMemcpyDeviceToDevice, g->cur));
-    gemm(g, n, H, H, dZ, H, 1, P + L.W_s[l], 1, H, dh2, H, 1);
+    gemm(g, n, H, H, dZ, H, 1, P + L.W_s[l], 1, H, dh2, H, 1, true, L.W_s[l]);
     if (m > 0) {
-      // messages: dM = dZs; dmsg = dM[dst] / deg; dZe = dmsg gelu'(Ze)
-      float* dmsg = g->dE;  // m x H scratch (stride H) before dE is needed
-      hipLaunchKernelGGL(k_mean_bwd, dim3(nblk((int64_t)m * H, 256)), dim3(256), 0, g->cur, dZ, g->dst, g->dst_off, dmsg, m);
-      float* dZe = g->dZ;  // reuse: dZs no longer needed (m x H may exceed n x H: dZ holds max)
-      hipLaunchKernelGGL(k_act_bwd, dim3(nblk((int64_t)m * H, 256)), dim3(256), 0, g->cur, dmsg, Ze, dZe, (int64_t)m * H);
-      gemm(g, EK, H, m, E, 1, EK, dZe, H, 1, G + L.W_e[l], H, 2);
+      // messages: dZe = dm[dst] / deg * gelu'(Ze); db_e, dW_x = e^T dZe, dP[src] += dZe,
+      // dW_h = h^T dP, dh += dP W_h^T
+      float* dZe = g->dE;
+      hipLaunchKernelGGL(k_edge_msg_bwd, dim3(nblk((int64_t)m * H, 256)), dim3(256), 0, g->cur, (const float*)dZ, Ze,
+                         (const int32_t*)g->dst, (const int32_t*)g->dst_off, dZe, m);
       colsum(g, dZe, m, H, H, G + L.b_e[l]);
-      gemm(g, m, EK, H, dZe, H, 1, P + L.W_e[l], 1, H, g->dE, EK, 0);
-      hipLaunchKernelGGL(k_gather_rev, dim3(nblk((int64_t)n * H, 256)), dim3(256), 0, g->cur, g->dE, g->rev, g->dst_off, dh2, n);
+      gemm(g, EIN, H, m, g->ex, 1, EIN, dZe, H, 1, G + L.W_e[l] + (size_t)H * H, H, 2);
+      float* dP = g->dZ;  // dZs is consumed
+      hipLaunchKernelGGL(k_scatter_src, dim3(nblk((int64_t)n * H, 256)), dim3(256), 0, g->cur, (const float*)dZe,
+                         (const int32_t*)g->rev, (const int32_t*)g->dst_off, dP, n);
+      gemm(g, H, H, n, hl, 1, H, dP, H, 1, G + L.W_e[l], H, 2);
+      gemm(g, n, H, H, dP, H, 1, P + L.W_e[l], 1, H, dh2, H, 1, true, L.W_e[l]);
     }
     std::swap(dh, dh2);
   }
@@ -796,8 +818,20 @@ bool check_batch(ba_gnn* g, const ba_gnn_batch* b, bool need_s) {
   return true;
 }
 
+// runs of <= EDGE_RUN in-edges per node from the CSR offsets, uploaded with the offsets
+void upload_runs(ba_gnn* g, const int32_t* off, int n, hipStream_t s) {
+  g->h_off.assign(off, off + n + 1);
+  g->h_runs.clear();
+  for (int i = 0; i < n; ++i)
+    for (int e = off[i]; e < off[i + 1]; e += EDGE_RUN) g->h_runs.push_back(make_int2(i, e));
+  g->n_runs = (int)g->h_runs.size();
+  GCHK(hipMemcpyAsync(g->dst_off, g->h_off.data(), g->h_off.size() * 4, hipMemcpyHostToDevice, s));
+  if (g->n_runs) GCHK(hipMemcpyAsync(g->runs, g->h_runs.data(), g->h_runs.size() * sizeof(int2), hipMemcpyHostToDevice, s));
+}
+
 Dims upload_batch(ba_gnn* g, const ba_gnn_batch* b, bool with_s) {
-  reserve(g, b->n_nodes, b->n_edges, b->n_graphs, with_s ? b->s_node_len : 1, with_s ? std::max<int64_t>(b->s_edge_len, 1) : 1);
+  reserve(g, b->n_nodes, b->n_edges, b->n_graphs, with_s ? b->s_node_len : 1, with_s ? std::max<int64_t>(b->s_edge_len, 1) : 1,
+          with_s);
   g->attached_training = true;
   g->cur = g->stream;
   Dims D;
@@ -822,7 +856,7 @@ Dims upload_batch(ba_gnn* g, const ba_gnn_batch* b, bool with_s) {
     GCHK(hipMemcpyAsync(g->rev, b->edge_rev, (size_t)D.m * 4, hipMemcpyHostToDevice, s));
     GCHK(hipMemcpyAsync(g->ex, b->edge_x, (size_t)D.m * EIN * 4, hipMemcpyHostToDevice, s));
   }
-  GCHK(hipMemcpyAsync(g->dst_off, off.data(), off.size() * 4, hipMemcpyHostToDevice, s));
+  upload_runs(g, off.data(), D.n, s);
   if (with_s) {
     GCHK(hipMemcpyAsync(g->s_node, b->s_node, (size_t)b->s_node_len * 8, hipMemcpyHostToDevice, s));
     GCHK(hipMemcpyAsync(g->s_node_off, b->s_node_off, (size_t)D.n * 8, hipMemcpyHostToDevice, s));
@@ -984,7 +1018,7 @@ void build_graph(Graph& G, int nc, int ng, int nv, int cd, const std::vector<int
 void attach(ba_gnn* g, const Graph& G) {
   if (!G.valid) return;
   GCHK(hipSetDevice(g->device));
-  reserve(g, G.n_nodes, G.n_edges, 1, 1, 1);
+  reserve(g, G.n_nodes, G.n_edges, 1, 1, 1, false);
   g->gn = G.n_nodes;
   g->gm = G.n_edges;
   g->s0 = G.scale;
@@ -1002,7 +1036,7 @@ void attach(ba_gnn* g, const Graph& G) {
     GCHK(hipMemcpyAsync(g->rev, G.edge_rev.data(), G.n_edges * 4, hipMemcpyHostToDevice, s));
     GCHK(hipMemcpyAsync(g->ex, G.edge_x.data(), G.edge_x.size() * 4, hipMemcpyHostToDevice, s));
   }
-  GCHK(hipMemcpyAsync(g->dst_off, G.dst_off.data(), G.dst_off.size() * 4, hipMemcpyHostToDevice, s));
+  upload_runs(g, G.dst_off.data(), G.n_nodes, s);
   GCHK(hipStreamSynchronize(s));
   g->attached_training = false;
 }
@@ -1024,7 +1058,7 @@ void apply(ba_gnn* g, const ba::Dev& d, double lambda, hipStream_t s) {
   g->cur = s;  // ordered after the solver's assembly on its stream
   launch_node_features(d, g->gstat, g->type, g->gn, lambda, g->s0, g->X, s);
   Dims D{g->gn, g->gm, {g->type_end[0], g->type_end[1], g->type_end[2]}};
-  forward(g, D);
+  forward(g, D, false);
   hipLaunchKernelGGL(k_coarse_basis, dim3(nblk((int64_t)g->gn * HEADP, 256)), dim3(256), 0, s, d,
                      (const float*)g->heads, (const int32_t*)g->type, g->gn, g->s0);
   g->cur = g->stream;
@@ -1073,7 +1107,7 @@ ba_status ba_gnn_forward(ba_gnn* g, const ba_gnn_batch* b, float* heads, double*
   try {
     GCHK(hipSetDevice(g->device));
     Dims D = upload_batch(g, b, with_loss);
-    forward(g, D);
+    forward(g, D, false);
     if (with_loss) {
       coarse_loss(g, D, b->n_graphs);
       GCHK(hipMemcpyAsync(loss, g->scal, 8, hipMemcpyDeviceToHost, g->cur));
@@ -1094,7 +1128,7 @@ ba_status ba_gnn_train_step(ba_gnn* g, const ba_gnn_batch* b, double lr, double*
   try {
     GCHK(hipSetDevice(g->device));
     Dims D = upload_batch(g, b, true);
-    forward(g, D);
+    forward(g, D, true);
     coarse_loss(g, D, b->n_graphs);
     GCHK(hipMemsetAsync(g->grad, 0, g->L.total * 4, g->cur));
     backward(g, D);

@@ -614,6 +614,9 @@ void finalize(ba_handle* h) {
   d.SZc = A.get<double>((size_t)COARSE_K * nA);
   d.Einv = A.get<double>((size_t)COARSE_K * COARSE_K);
   d.Ztb = A.get<double>((size_t)COARSE_K + COARSE_K * COARSE_K);
+  d.szr = A.get<char>((size_t)nA * 8, TS);
+  d.szfp = A.get<char>((size_t)h->np * 3 * 8, TS);
+  d.szfl = A.get<char>((size_t)h->nl * 4 * 8, TS);
   // product tiles: runs of consecutive features whose records split into at
   // most MV_MAX_CHUNKS single-family chunks of MV_CHUNK records
   {
@@ -1399,6 +1402,28 @@ ba_status ba_export_gnn_graph(ba_handle* h, int32_t* n_nodes, int32_t* n_edges, 
     if (edge_dst) std::copy(G.edge_dst.begin(), G.edge_dst.end(), edge_dst);
     if (edge_rev) std::copy(G.edge_rev.begin(), G.edge_rev.end(), edge_rev);
     if (edge_x) std::copy(G.edge_x.begin(), G.edge_x.end(), edge_x);
+  });
+}
+
+ba_status ba_export_coarse_space(ba_handle* h, int32_t* k, double* Z, double* SZ) {
+  if (!h) return BA_E_INVALID;
+  return guard(h, [&] {
+    if (!h->finalized) throw BaError(BA_E_STATE, "no linearisation yet");
+    set_device(h);
+    const Dev& d = h->d;
+    const int K = d.coarse_k;
+    if (k) *k = K;
+    if (K == 0 || (!Z && !SZ)) return;
+    std::vector<double> col((size_t)K * d.nA);
+    for (int pass = 0; pass < 2; ++pass) {
+      double* out = pass == 0 ? Z : SZ;
+      if (!out) continue;
+      HIPCHK(hipMemcpyAsync(col.data(), pass == 0 ? d.Zc : d.SZc, col.size() * sizeof(double), hipMemcpyDeviceToHost,
+                            h->stream));
+      sync(h);
+      for (int e = 0; e < d.nA; ++e)
+        for (int c = 0; c < K; ++c) out[(size_t)e * K + c] = col[(size_t)c * d.nA + e];
+    }
   });
 }
 

@@ -86,6 +86,7 @@ struct Dev {
   // Z^T b; PCG starts from x0 = Z E^-1 Z^T b and applies (I - Q S) M + Q, Q = Z E^-1 Z^T
   int coarse_k = 0;            // active columns (0: block-Jacobi; SC_COARSE decides on the device)
   double *Zc = nullptr, *SZc = nullptr, *Einv = nullptr, *Ztb = nullptr;
+  void *szr = nullptr, *szfp = nullptr, *szfl = nullptr;  // S Z sweeps: Z rows, s_f of points / lines (T)
   // PCG (double vectors of length nA) and matvec partials (T)
   double *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
   void *xT = nullptr;       // matvec input in T

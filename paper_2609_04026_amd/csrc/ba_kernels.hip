@@ -1667,6 +1667,8 @@ template <int CD, bool COARSE> __global__ __launch_bounds__(256) void k_pcg_z(De
 // beta = rz_k / rz_(k-1); p = z + beta p (z completed with the coarse term);
 // workgroup 0 updates the scalars and the stopping test
 template <typename T, bool COARSE> __global__ __launch_bounds__(256) void k_pcg_p(Dev d, int k) {
+  __shared__ double ys[COARSE_K];
+  __shared__ double rzs[2];
   if (d.scal[SC_DONE] != 0.0) return;
   const double* A = acc_set(d, k);
   if (d.scal[SC_BREAK] != 0.0) {
@@ -1676,18 +1678,34 @@ template <typename T, bool COARSE> __global__ __launch_bounds__(256) void k_pcg_
   const double rr = A[ACC_RR];
   double rz = A[ACC_RZ];
   double rz_prev = acc_set(d, k + 2)[ACC_RZ];  // set (k - 1) mod 3
-  double y[COARSE_K];
   const bool on = COARSE && d.scal[SC_COARSE] != 0.0;
   if (on) {
-    double yp[COARSE_K];
-    rz = coarse_rz(d, A, y);
-    rz_prev = coarse_rz(d, acc_set(d, k + 2), yp);
+    // y = E^-1 (Z^T r - (S Z)^T M r) for this and the previous iteration, once per workgroup
+    const int K = d.coarse_k;
+    const double* Ap = acc_set(d, k + 2);
+    static_assert(COARSE_K <= 16, "one 16-lane group per set");
+    if (threadIdx.x < 32) {  // lanes 0-15: this iteration, 16-31: the previous one
+      const int set = threadIdx.x >> 4, c = threadIdx.x & 15;
+      const double* S = set == 0 ? A : Ap;
+      double y = 0;
+      if (c < K)
+        for (int b = 0; b < K; ++b) y += d.Einv[c * COARSE_K + b] * (S[ACC_ZR + b] - S[ACC_W + b]);
+      // r.z = r.(M r) + (Z^T r) . y
+      double part = c < K ? S[ACC_ZR + c] * y : 0.0;
+      for (int o = 8; o > 0; o >>= 1) part += __shfl_xor(part, o, 16);
+      if (set == 0 && c < COARSE_K) ys[c] = y;
+      if (c == 0) rzs[set] = part;
+    }
+    __syncthreads();
+    rz += rzs[0];
+    rz_prev += rzs[1];
   }
   const double beta = rz / rz_prev;
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e < d.nA) {
     double z = d.z[e];
-    if (on) z += coarse_combine(d, e, y);
+    if (on)
+      for (int c = 0; c < d.coarse_k; ++c) z += d.Zc[(int64_t)c * d.nA + e] * ys[c];
     const double pk = z + beta * d.p[e];
     d.p[e] = pk;
     ((T*)d.xT)[e] = (T)pk;
@@ -1766,47 +1784,42 @@ __global__ __launch_bounds__(256) void k_coarse_e(Dev d, double* E) {
   if (threadIdx.x == 0) E[blockIdx.x] = o[0];
 }
 
-// Einv = E^-1 by Cholesky of the symmetrised E (active K x K part); SC_COARSE = 0
-// when E is not positive definite or the inverse is not finite (one thread)
-__global__ void k_coarse_inv(Dev d, const double* E) {
+// Einv = E^-1 of the symmetrised E (active K x K part) by Gauss-Jordan elimination
+// without pivoting (E is symmetric positive definite: every pivot is a positive
+// Schur complement); SC_COARSE = 0 when a pivot is not positive or the inverse is
+// not finite.  One workgroup, one thread per entry of [E | I].
+__global__ __launch_bounds__(512) void k_coarse_inv(Dev d, const double* E) {
   constexpr int Kc = COARSE_K;
-  const int K = d.coarse_k;
-  double L[Kc][Kc], X[Kc][Kc];
-  bool ok = K > 0;
-  for (int i = 0; i < Kc; ++i)
-    for (int j = 0; j < Kc; ++j) {
-      L[i][j] = i < K && j < K ? 0.5 * (E[i * Kc + j] + E[j * Kc + i]) : 0.0;
-      X[i][j] = 0.0;
+  __shared__ double A[Kc][2 * Kc];
+  __shared__ int bad;
+  const int K = d.coarse_k, t = threadIdx.x;
+  const int r = t / (2 * Kc), c = t % (2 * Kc);
+  const bool mine = r < K && (c < K || (c >= Kc && c < Kc + K));
+  if (t == 0) bad = K <= 0 ? 1 : 0;
+  if (t < Kc * 2 * Kc) A[r][c] = !mine ? 0.0 : c < K ? 0.5 * (E[r * Kc + c] + E[c * Kc + r]) : (c - Kc == r ? 1.0 : 0.0);
+  __syncthreads();
+  for (int p = 0; p < K; ++p) {
+    const double piv = A[p][p];
+    const double f = t < Kc * 2 * Kc ? A[r][p] : 0.0;
+    const double prow = t < Kc * 2 * Kc ? A[p][c] : 0.0;
+    __syncthreads();
+    if (!(piv > 0.0) || !isfinite(piv)) {
+      if (t == 0) bad = 1;
+    } else if (mine) {
+      A[r][c] = r == p ? prow / piv : A[r][c] - f * prow / piv;
     }
-  for (int j = 0; j < K && ok; ++j) {
-    double s = L[j][j];
-    for (int k = 0; k < j; ++k) s -= L[j][k] * L[j][k];
-    if (!(s > 0.0) || !isfinite(s)) { ok = false; break; }
-    const double ljj = sqrt(s);
-    L[j][j] = ljj;
-    for (int r = j + 1; r < K; ++r) {
-      double u = L[r][j];
-      for (int k = 0; k < j; ++k) u -= L[r][k] * L[j][k];
-      L[r][j] = u / ljj;
-    }
+    __syncthreads();
   }
-  if (ok) {
-    for (int c = 0; c < K; ++c)  // X = L^-1
-      for (int r = c; r < K; ++r) {
-        double s = r == c ? 1.0 : 0.0;
-        for (int k = c; k < r; ++k) s -= L[r][k] * X[k][c];
-        X[r][c] = s / L[r][r];
-      }
+  const bool ok = bad == 0;
+  if (t < Kc * Kc) {
+    const int i = t / Kc, j = t % Kc;
+    double v = 0.0;
+    if (ok && i < K && j < K) v = 0.5 * (A[i][Kc + j] + A[j][Kc + i]);
+    d.Einv[t] = isfinite(v) ? v : 0.0;
+    if (!isfinite(v)) atomicAdd(&bad, 1);
   }
-  for (int i = 0; i < Kc; ++i)
-    for (int j = 0; j < Kc; ++j) {
-      double s = 0;
-      if (ok && i < K && j < K)
-        for (int k = 0; k < K; ++k) s += X[k][i] * X[k][j];
-      ok = ok && isfinite(s);
-      d.Einv[i * Kc + j] = s;
-    }
-  d.scal[SC_COARSE] = ok ? 1.0 : 0.0;
+  __syncthreads();
+  if (t == 0) d.scal[SC_COARSE] = bad == 0 ? 1.0 : 0.0;
 }
 
 // similarity-gauge columns (rotation x, y, z; translation x, y, z; scale) of every
@@ -1869,12 +1882,261 @@ void launch_gauge_basis(const Dev& d, hipStream_t s) {
   if (nb > 0) k_gauge_basis<<<nblk(nb, 64), 64, 0, s>>>(d);
 }
 
+// ---- S Z for up to 8 coarse columns in three sweeps over the records --------
+// S x = sum_r J_a,r^T (J_a,r x - J_f,r s_f) + lambda D_a x, s_f = V_f^-1 sum_{r in f} J_f,r^T J_a,r x
+// feature sweep: s_f for every column; camera / group sweeps: each workgroup owns one
+// block of the output and walks the records that touch it (no atomics)
+constexpr int SZ_COLS = 8;
+
+// Z rows in T for one sweep: Zr[e][c] = Z[col0 + c][e]
+template <typename T> __global__ void k_sz_rows(Dev d, T* Zr, int col0, int ncol) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= (int64_t)d.nA * SZ_COLS) return;
+  const int e = (int)(t / SZ_COLS), c = (int)(t % SZ_COLS);
+  Zr[t] = c < ncol ? (T)d.Zc[(int64_t)(col0 + c) * d.nA + e] : (T)0;
+}
+
+// t[row][c] = (J_a Z_r)[row][c] for one record
+template <int FAM, typename T, int CD>
+__device__ __forceinline__ void sz_record_t(const Dev& d, int64_t i, const T* Zr, const T (&v)[Slot<FAM, CD>::STRIDE],
+                                            T (&t)[4][SZ_COLS]) {
+  using SL = Slot<FAM, CD>;
+  using F = Fam<FAM, CD>;
+#pragma unroll
+  for (int row = 0; row < 4; ++row)
+#pragma unroll
+    for (int c = 0; c < SZ_COLS; ++c) t[row][c] = 0;
+  if constexpr (SL::NC > 0) {
+    const T* z = Zr + (int64_t)CD * d.fcam[FAM][i] * SZ_COLS;
+#pragma unroll
+    for (int k = 0; k < SL::NC; ++k)
+#pragma unroll
+      for (int c = 0; c < SZ_COLS; ++c) {
+        const T zk = z[k * SZ_COLS + c];
+#pragma unroll
+        for (int row = 0; row < SL::ROWS; ++row) t[row][c] += v[SL::OC + row * SL::NC + k] * zk;
+      }
+  }
+  if constexpr (SL::NG > 0) {
+    const T* z = Zr + (int64_t)a_grp(d, F::GT, d.fgrp[FAM][i]) * SZ_COLS;
+#pragma unroll
+    for (int k = 0; k < SL::NG; ++k)
+#pragma unroll
+      for (int c = 0; c < SZ_COLS; ++c) {
+        const T zk = z[k * SZ_COLS + c];
+#pragma unroll
+        for (int row = 0; row < SL::ROWS; ++row) t[row][c] += v[SL::OG + row * SL::NG + k] * zk;
+      }
+  }
+}
+
+template <int FAM, typename T, int CD, int NF>
+__device__ __forceinline__ void sz_feat_family(const Dev& d, int f, const T* Zr, T (&q)[NF][SZ_COLS]) {
+  using SL = Slot<FAM, CD>;
+  if (!d.fn[FAM]) return;
+  const T* rec = (const T*)d.frec[FAM];
+  for (int64_t i = d.foff[FAM][f]; i < d.foff[FAM][f + 1]; ++i) {
+    T v[SL::STRIDE];
+    load_vec(rec + i * SL::STRIDE, v);
+    T t[4][SZ_COLS];
+    sz_record_t<FAM, T, CD>(d, i, Zr, v, t);
+#pragma unroll
+    for (int a = 0; a < NF; ++a)
+#pragma unroll
+      for (int c = 0; c < SZ_COLS; ++c) {
+        T s = 0;
+#pragma unroll
+        for (int row = 0; row < SL::ROWS; ++row) s += v[SL::OF + row * NF + a] * t[row][c];
+        q[a][c] += s;
+      }
+  }
+}
+
+// s_f (NF x SZ_COLS, T) of every feature of one kind, one lane per feature
+template <typename T, int CD, int NF> __global__ __launch_bounds__(256) void k_sz_feat(Dev d, const T* Zr, T* sf) {
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= (NF == 3 ? d.np : d.nl)) return;
+  T q[NF][SZ_COLS];
+#pragma unroll
+  for (int a = 0; a < NF; ++a)
+#pragma unroll
+    for (int c = 0; c < SZ_COLS; ++c) q[a][c] = 0;
+  if constexpr (NF == 3) {
+    sz_feat_family<1, T, CD, 3>(d, f, Zr, q);
+    sz_feat_family<3, T, CD, 3>(d, f, Zr, q);
+    sz_feat_family<6, T, CD, 3>(d, f, Zr, q);
+  } else {
+    sz_feat_family<2, T, CD, 4>(d, f, Zr, q);
+    sz_feat_family<4, T, CD, 4>(d, f, Zr, q);
+    sz_feat_family<5, T, CD, 4>(d, f, Zr, q);
+    sz_feat_family<7, T, CD, 4>(d, f, Zr, q);
+  }
+  for (int c = 0; c < SZ_COLS; ++c) {
+    T qc[NF], sc[NF];
+#pragma unroll
+    for (int a = 0; a < NF; ++a) qc[a] = q[a][c];
+    apply_vinv<T, NF>(d, f, qc, sc);
+#pragma unroll
+    for (int a = 0; a < NF; ++a) sf[((int64_t)f * NF + a) * SZ_COLS + c] = sc[a];
+  }
+}
+
+// u = J_a Z - J_f s_f of one record (rows x SZ_COLS)
+template <int FAM, typename T, int CD>
+__device__ __forceinline__ void sz_record_u(const Dev& d, int64_t i, const T* Zr, const T* sf, T (&v)[Slot<FAM, CD>::STRIDE],
+                                            T (&u)[4][SZ_COLS]) {
+  using SL = Slot<FAM, CD>;
+  load_vec(((const T*)d.frec[FAM]) + i * SL::STRIDE, v);
+  sz_record_t<FAM, T, CD>(d, i, Zr, v, u);
+  const T* s = sf + (int64_t)d.ffeat[FAM][i] * SL::NF * SZ_COLS;
+#pragma unroll
+  for (int a = 0; a < SL::NF; ++a)
+#pragma unroll
+    for (int c = 0; c < SZ_COLS; ++c) {
+      const T sa = s[a * SZ_COLS + c];
+#pragma unroll
+      for (int row = 0; row < SL::ROWS; ++row) u[row][c] -= v[SL::OF + row * SL::NF + a] * sa;
+    }
+}
+
+template <int FAM, typename T, int CD>
+__device__ __forceinline__ void sz_cam_rec(const Dev& d, int64_t i, const T* Zr, const T* sf, double (&acc)[CD][SZ_COLS]) {
+  using SL = Slot<FAM, CD>;
+  T v[SL::STRIDE], u[4][SZ_COLS];
+  sz_record_u<FAM, T, CD>(d, i, Zr, sf, v, u);
+#pragma unroll
+  for (int k = 0; k < SL::NC; ++k)
+#pragma unroll
+    for (int c = 0; c < SZ_COLS; ++c) {
+      T s = 0;
+#pragma unroll
+      for (int row = 0; row < SL::ROWS; ++row) s += v[SL::OC + row * SL::NC + k] * u[row][c];
+      acc[k][c] += s;
+    }
+}
+
+template <int FAM, typename T, int CD, int NG>
+__device__ __forceinline__ void sz_grp_rec(const Dev& d, int64_t i, const T* Zr, const T* sf, double (&acc)[NG][SZ_COLS]) {
+  using SL = Slot<FAM, CD>;
+  T v[SL::STRIDE], u[4][SZ_COLS];
+  sz_record_u<FAM, T, CD>(d, i, Zr, sf, v, u);
+#pragma unroll
+  for (int k = 0; k < NG; ++k)
+#pragma unroll
+    for (int c = 0; c < SZ_COLS; ++c) {
+      T s = 0;
+#pragma unroll
+      for (int row = 0; row < SL::ROWS; ++row) s += v[SL::OG + row * NG + k] * u[row][c];
+      acc[k][c] += s;
+    }
+}
+
+// output rows of one camera (workgroup per camera): SZ = sum over its records J_c^T u + lambda D Z
+template <typename T, int CD>
+__global__ __launch_bounds__(256) void k_sz_cam(Dev d, const T* Zr, const T* sfp, const T* sfl, int col0, int ncol, double lam) {
+  constexpr int NV = CD * SZ_COLS;
+  __shared__ double lds[5 * NV];
+  const int c = blockIdx.x;
+  double acc[CD][SZ_COLS];  // FP64: the gauge columns of S Z are small differences of large sums
+#pragma unroll
+  for (int k = 0; k < CD; ++k)
+#pragma unroll
+    for (int q = 0; q < SZ_COLS; ++q) acc[k][q] = 0;
+  if (d.fn[1])
+    for (int j = d.po_off[c] + threadIdx.x; j < d.po_off[c + 1]; j += blockDim.x) {
+      const int64_t i = d.po_idx[j];
+      sz_cam_rec<1, T, CD>(d, i, Zr, sfp, acc);
+      const int64_t i3 = aligned(d, 1, 3, i);
+      if (i3 >= 0) sz_cam_rec<3, T, CD>(d, i3, Zr, sfp, acc);
+    }
+  if (d.fn[6])
+    for (int j = d.px_off[c] + threadIdx.x; j < d.px_off[c + 1]; j += blockDim.x)
+      for (int64_t i = d.px_start[j]; i < d.px_start[j] + d.px_cnt[j]; ++i) sz_cam_rec<6, T, CD>(d, i, Zr, sfp, acc);
+  if (d.fn[2])
+    for (int j = d.lo_off[c] + threadIdx.x; j < d.lo_off[c + 1]; j += blockDim.x) {
+      const int64_t i = d.lo_idx[j];
+      sz_cam_rec<2, T, CD>(d, i, Zr, sfl, acc);
+      const int64_t i4 = aligned(d, 2, 4, i);
+      if (i4 >= 0) sz_cam_rec<4, T, CD>(d, i4, Zr, sfl, acc);
+    }
+  if (d.fn[7])
+    for (int j = d.lx_off[c] + threadIdx.x; j < d.lx_off[c + 1]; j += blockDim.x)
+      for (int64_t i = d.lx_start[j]; i < d.lx_start[j] + d.lx_cnt[j]; ++i) sz_cam_rec<7, T, CD>(d, i, Zr, sfl, acc);
+  double* o = block_sum_arr<double, NV>(reinterpret_cast<double(&)[NV]>(acc), lds);
+  for (int k = threadIdx.x; k < NV; k += blockDim.x) {
+    const int row = k / SZ_COLS, col = k % SZ_COLS;
+    if (col >= ncol) continue;
+    const int e = CD * c + row;
+    d.SZc[(int64_t)(col0 + col) * d.nA + e] = (double)o[k] + lam * d.DA[e] * d.Zc[(int64_t)(col0 + col) * d.nA + e];
+  }
+}
+
+// output rows of one plane or VP (workgroup per group)
+template <typename T, int CD>
+__global__ __launch_bounds__(256) void k_sz_grp(Dev d, const T* Zr, const T* sfp, const T* sfl, int col0, int ncol, double lam) {
+  __shared__ double lds[5 * 3 * SZ_COLS];
+  if ((int)blockIdx.x < d.ng) {
+    const int g = blockIdx.x;
+    double acc[3][SZ_COLS];
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+      for (int q = 0; q < SZ_COLS; ++q) acc[k][q] = 0;
+    if (d.fn[3])
+      for (int j = d.plp_off[g] + threadIdx.x; j < d.plp_off[g + 1]; j += blockDim.x) {
+        const int f = d.plp[j];
+        for (int64_t i = d.foff[3][f]; i < d.foff[3][f + 1]; ++i) sz_grp_rec<3, T, CD, 3>(d, i, Zr, sfp, acc);
+      }
+    if (d.fn[4])
+      for (int j = d.pll_off[g] + threadIdx.x; j < d.pll_off[g + 1]; j += blockDim.x) {
+        const int f = d.pll[j];
+        for (int64_t i = d.foff[4][f]; i < d.foff[4][f + 1]; ++i) sz_grp_rec<4, T, CD, 3>(d, i, Zr, sfl, acc);
+      }
+    double* o = block_sum_arr<double, 3 * SZ_COLS>(reinterpret_cast<double(&)[3 * SZ_COLS]>(acc), lds);
+    for (int k = threadIdx.x; k < 3 * SZ_COLS; k += blockDim.x) {
+      const int row = k / SZ_COLS, col = k % SZ_COLS;
+      if (col >= ncol) continue;
+      const int e = d.offPl + 3 * g + row;
+      d.SZc[(int64_t)(col0 + col) * d.nA + e] = (double)o[k] + lam * d.DA[e] * d.Zc[(int64_t)(col0 + col) * d.nA + e];
+    }
+  } else {
+    const int v = blockIdx.x - d.ng;
+    double acc[2][SZ_COLS];
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+#pragma unroll
+      for (int q = 0; q < SZ_COLS; ++q) acc[k][q] = 0;
+    for (int j = d.vpm_off[v] + threadIdx.x; j < d.vpm_off[v + 1]; j += blockDim.x)
+      sz_grp_rec<5, T, CD, 2>(d, d.vpm[j], Zr, sfl, acc);
+    double* o = block_sum_arr<double, 2 * SZ_COLS>(reinterpret_cast<double(&)[2 * SZ_COLS]>(acc), lds);
+    for (int k = threadIdx.x; k < 2 * SZ_COLS; k += blockDim.x) {
+      const int row = k / SZ_COLS, col = k % SZ_COLS;
+      if (col >= ncol) continue;
+      const int e = d.offVp + 2 * v + row;
+      d.SZc[(int64_t)(col0 + col) * d.nA + e] = (double)o[k] + lam * d.DA[e] * d.Zc[(int64_t)(col0 + col) * d.nA + e];
+    }
+  }
+}
+
+template <typename T, int CD> static void launch_sz(const Dev& d, double lambda, hipStream_t s) {
+  T* Zr = (T*)d.szr;
+  T* sfp = (T*)d.szfp;
+  T* sfl = (T*)d.szfl;
+  for (int col0 = 0; col0 < d.coarse_k; col0 += SZ_COLS) {
+    const int ncol = std::min(SZ_COLS, d.coarse_k - col0);
+    k_sz_rows<T><<<nblk((int64_t)d.nA * SZ_COLS, 256), 256, 0, s>>>(d, Zr, col0, ncol);
+    if (d.np) k_sz_feat<T, CD, 3><<<nblk(d.np, 256), 256, 0, s>>>(d, Zr, sfp);
+    if (d.nl) k_sz_feat<T, CD, 4><<<nblk(d.nl, 256), 256, 0, s>>>(d, Zr, sfl);
+    if (d.nc) k_sz_cam<T, CD><<<d.nc, 256, 0, s>>>(d, Zr, sfp, sfl, col0, ncol, lambda);
+    if (d.ng + d.nv) k_sz_grp<T, CD><<<d.ng + d.nv, 256, 0, s>>>(d, Zr, sfp, sfl, col0, ncol, lambda);
+  }
+}
+
 void launch_coarse_setup(const Dev& d, double lambda, hipStream_t s) {
-  for (int c = 0; c < d.coarse_k; ++c)
-    launch_schur_matvec(d, d.Zc + (int64_t)c * d.nA, d.SZc + (int64_t)c * d.nA, lambda, s);
+  BA_DISPATCH_T_CD(d, launch_sz<T, CD>(d, lambda, s));
   double* E = d.Ztb + COARSE_K;  // K x K scratch after Z^T b
   k_coarse_e<<<COARSE_K * COARSE_K, 256, 0, s>>>(d, E);
-  k_coarse_inv<<<1, 1, 0, s>>>(d, E);
+  k_coarse_inv<<<1, 512, 0, s>>>(d, E);
 }
 
 // ---------------------------------------------------------------------------

@@ -179,6 +179,36 @@ def test_coarse_pcg_matches_oracle():
     assert ref["gauge"] < ref["jacobi"]
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_coarse_space_and_products_match_oracle(precision):
+    """The coarse basis the solver assembles (gauge columns exact, network
+    columns from the inference path in BF16) and its S Z (three sweeps over
+    the records) against the oracle's gauge, network and dense S."""
+    from paper_2609_04026_amd.binding import BA
+    sc = make_scene(small_config(n_cams=12, n_points=80, n_lines=20, n_planes=3, n_vps=3), seed=33)
+    lam = 1e-3
+    o = _oracle_system(sc, lam)
+    params = gnn.unpack(gnn.pack(gnn.init_params(9, seed=25)).tobytes())
+    g = o["graph"]
+    Y = gnn.forward(params, o["x"].astype(np.float32).astype(np.float64), g["node_type"], g["edge_src"],
+                    g["edge_dst"], g["edge_x"], 9)
+    Z_ref = gnn.full_basis(o["gauge"], Y, o["units"]).detach().numpy()
+    ba = BA.from_scene(sc, precision=precision, precond="learned")
+    ba.set_gnn_weights(gnn.pack(params).tobytes())
+    ba.linearize(lam)
+    Z, SZ = ba.export_coarse_space()
+    assert Z.shape == (o["S"].shape[0], 15)
+    G = Z[:, :7]
+    assert np.abs(G - o["gauge"]).max() <= 1e-12 * np.abs(o["gauge"]).max()
+    err = np.linalg.norm(Z[:, 7:] - Z_ref[:, 7:]) / np.linalg.norm(Z_ref[:, 7:])
+    assert err <= 5e-2, err
+    ref = o["S"] @ Z
+    tol = 1e-9 if precision == "fp64" else 1e-4
+    col_err = np.linalg.norm(SZ - ref, axis=0) / np.linalg.norm(o["S"] @ np.abs(Z), axis=0)
+    assert col_err.max() <= tol, col_err
+    ba.close()
+
+
 def test_zero_head_falls_back_to_block_jacobi():
     """A zero output head gives zero network columns: E is singular, the
     coarse term is off and PCG takes the block-Jacobi iterations."""
