@@ -101,6 +101,11 @@ typedef struct {
   int32_t device;
 } ba_problem_desc;
 
+/* ba_step_report.pcg_flags */
+#define BA_PCG_BREAKDOWN 1         /* p.Sp <= 0 or not finite: the solve stopped early */
+#define BA_PCG_COARSE_FALLBACK 2   /* the two-level solve broke down and was repeated with block-Jacobi */
+#define BA_PCG_NONFINITE_RHS 4     /* the reduced right-hand side was not finite: step rejected, relinearised next */
+
 typedef struct {
   int32_t max_iters;      /* ba_solve: attempts (accepted or rejected); default 100 */
   double func_tol;        /* stop after an accepted step with |dE_pix| / E_pix < func_tol; 1e-6 */
@@ -134,6 +139,15 @@ typedef struct {
   double matvec_ms;              /* with time_kernels: summed duration of the PCG products */
   int32_t matvec_count;          /* number of those products */
   int32_t coarse;                /* columns of the coarse space used by this step's PCG (0: block-Jacobi) */
+  int32_t pcg_flags;             /* BA_PCG_* bits */
+  int32_t n_degenerate;          /* records of this step's linearisation whose Jacobian was
+                                    scaled or dropped: a line-projection record (R2, R4, R7) at a
+                                    nearly degenerate image line, normal |(l1, l2)| = rel (|m| +
+                                    |t| |d|) with rel < 1e-3 (the line passes close to the camera
+                                    centre or lies near its principal plane), has its Jacobian
+                                    scaled by rel / 1e-3; a record whose working-precision
+                                    Jacobian is not finite has it dropped.  Residuals stay in the
+                                    cost. */
 } ba_step_report;
 
 typedef struct {
@@ -232,7 +246,9 @@ ba_status ba_export_reduced(const ba_handle *h, double *b, double *S_cam, double
 ba_status ba_schur_matvec(ba_handle *h, const double *x, double *y);
 
 /* Solve S x = b of the last ba_linearize with the handle's PCG
- * (preconditioner of desc->precond); x: n_A doubles; iters, rel_res out. */
+ * (preconditioner of desc->precond; a two-level solve that breaks down is
+ * repeated with block-Jacobi, as in ba_lm_step, and iters counts both);
+ * x: n_A doubles; iters, rel_res out. */
 ba_status ba_pcg_solve(ba_handle *h, double tol, int32_t max_iters, double *x, int32_t *iters, double *rel_res);
 
 /* Sizes: n_A (reduced dimension) and camera_dof. */
@@ -247,7 +263,11 @@ ba_status ba_reduced_dim(const ba_handle *h, int64_t *n_A, int32_t *camera_dof);
  * span the coarse space Z (n_A x 15).  With E = Z^T S Z, Q = Z E^-1 Z^T and
  * M = blockdiag(S_ii)^-1, PCG starts from x0 = Q b and uses
  *     P r = (I - Q S) M r + Q r
- * (M alone when E is not positive definite).
+ * (M alone when E is not positive definite).  The coarse space is used for
+ * lambda <= 0.1 only (above, block-Jacobi PCG needs fewer iterations than the
+ * coarse set-up costs in products) and, with FP32 records, lambda >= 1e-6
+ * (below, the FP32 product does not resolve S on the near-null gauge
+ * directions); otherwise M is used alone.
  * Graph: one node per camera / plane / VP block of the reduced system, in
  * that order; directed edges both ways between blocks that share a feature,
  * sorted by destination, then source.

@@ -442,13 +442,62 @@ def residuals(state, rec, fam, cx, cy):
     return np.real(fn(gather(state, rec, fam), rec, cx, cy))
 
 
+# Nearly degenerate image lines (a reading: the paper does not treat the
+# case).  At a line through the camera centre, or one lying in the camera's
+# principal plane, the image line has no direction: rho of Eq. 4 and the
+# distance of Eq. 12 stay bounded but are not differentiable, and their
+# derivatives grow like the inverse of the image-line normal.  Below this
+# relative normal a line-projection record keeps its residual, and its
+# Jacobian is scaled by (normal / DEGENERATE_IMAGE_LINE): the same direction,
+# with the magnitude it has at the threshold (continuous there).
+DEGENERATE_IMAGE_LINE = 1e-3
+
+
+def image_line_normal(R, t, d, m):
+    """|(m_c,x, m_c,y)| / (|m| + |t| |d|), the normal of the image line of
+    (d, m) relative to a bound on |m_c|; zero for a line through the camera
+    centre or in its principal plane.  Real inputs."""
+    dc = matvec(R, d)
+    mc = matvec(R, m) + cross(t, dc)
+    den = np.sqrt(dot(m, m)) + np.sqrt(dot(t, t)) * np.sqrt(dot(d, d))
+    return np.sqrt(mc[..., 0] ** 2 + mc[..., 1] ** 2) / den
+
+
+def line_record_normal(state, rec, fam):
+    """Relative image-line normal of each record of a line-projection family
+    (R2, R4, R7; +inf for the others).  For R4 the smaller of the line's and
+    of its plane projection's (a record whose projection is undefined is zero
+    already and keeps +inf for the projection)."""
+    n = len(next(iter(rec.values())))
+    if fam not in ("R2", "R4", "R7") or n == 0:
+        return np.full(n, np.inf)
+    R, t = state.cam_R[rec["cam"]], state.cam_t[rec["cam"]]
+    d, m = line_plucker(state.line_U[rec["ln"]], state.line_w[rec["ln"]])
+    rel = image_line_normal(R, t, d, m)
+    if fam == "R4":
+        n_, w_ = state.pl_n[rec["pl"]], state.pl_w[rec["pl"]]
+        d2, m2 = plane_project_line(d, m, n_, w_)
+        ok = dot(d2, d2) >= 1e-12 * dot(d, d)
+        d2 = np.where(ok[:, None], d2, d)
+        m2 = np.where(ok[:, None], m2, m)
+        rel = np.minimum(rel, np.where(ok, image_line_normal(R, t, d2, m2), np.inf))
+    return rel
+
+
+def degenerate_line_records(state, rec, fam):
+    """Mask of the records whose Jacobian jacobians() scales down."""
+    return line_record_normal(state, rec, fam) < DEGENERATE_IMAGE_LINE
+
+
 def jacobians(state, rec, fam, cx, cy, camera_dof=9, h=1e-30):
     """Complex-step Jacobians of a family w.r.t. each of its parameter blocks.
 
     Returns {block: (n, rows, dof)}.  The tangent step is first order, which
-    is all a derivative at zero sees."""
+    is all a derivative at zero sees.  Records at a nearly degenerate image
+    line have their rows scaled by normal / DEGENERATE_IMAGE_LINE."""
     fn, rows, blocks = FAMILIES[fam]
     n = len(next(iter(rec.values())))
+    scale = np.minimum(line_record_normal(state, rec, fam) / DEGENERATE_IMAGE_LINE, 1.0)
     out = {}
     for b, _, dof in blocks:
         if b == "cam":
@@ -458,7 +507,7 @@ def jacobians(state, rec, fam, cx, cy, camera_dof=9, h=1e-30):
             g = gather(state, rec, fam)
             g.perturb(b, k, 1j * h)
             J[:, :, k] = np.imag(fn(g, rec, cx, cy)) / h
-        out[b] = J
+        out[b] = J * scale[:, None, None]
     return out
 
 

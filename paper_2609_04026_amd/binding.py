@@ -54,7 +54,8 @@ class StepReport(ctypes.Structure):
                 ("model_decrease", c_double), ("gain_ratio", c_double), ("lambda_", c_double),
                 ("accepted", c_int32), ("pcg_iters", c_int32), ("pcg_rel_residual", c_double),
                 ("n_fp64_blocks", c_int32), ("relinearized", c_int32), ("ms", c_double * 8),
-                ("matvec_ms", c_double), ("matvec_count", c_int32), ("coarse", c_int32)]
+                ("matvec_ms", c_double), ("matvec_count", c_int32), ("coarse", c_int32),
+                ("pcg_flags", c_int32), ("n_degenerate", c_int32)]
 
 
 class GnnBatch(ctypes.Structure):

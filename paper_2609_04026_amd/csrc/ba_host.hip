@@ -709,6 +709,7 @@ void read_scal(ba_handle* h) {
 }
 
 void linearize_all(ba_handle* h) {
+  launch_zero(h->d.scal + SC_NDEG, sizeof(double), h->stream);
   launch_cast_params(h->d, false, h->stream);
   launch_linearize(h->d, h->stream);
   launch_feature_accum(h->d, h->stream);
@@ -732,7 +733,8 @@ void assemble_precond(ba_handle* h, double lambda) {
   launch_precond_blockjacobi(h->d, h->stream);
   h->d.coarse_k = 0;
   const bool learned = h->precond == BA_PC_LEARNED && ba_gnn_impl::ready(h->gnn);
-  if ((h->precond == BA_PC_GAUGE || learned) && h->d.nA > 0) {
+  const bool resolved = h->d.fp64 || lambda >= COARSE_MIN_DAMPING_FP32;
+  if ((h->precond == BA_PC_GAUGE || learned) && h->d.nA > 0 && resolved && lambda <= COARSE_MAX_DAMPING) {
     launch_gauge_basis(h->d, h->stream);
     h->d.coarse_k = COARSE_GAUGE;
     if (learned) {
@@ -915,13 +917,25 @@ void do_step(ba_handle* h, const ba_solve_options& o, ba_step_report* rep) {
   record(h, 3);
   double mv_ms = 0;
   r.pcg_iters = pcg(h, h->lambda, o.pcg_tol, o.pcg_max_iters, o.time_kernels ? &mv_ms : nullptr);
+  r.coarse = h->d.coarse_k > 0 && h->hscal[SC_COARSE] != 0.0 ? h->d.coarse_k : 0;
+  if (h->hscal[SC_BREAK] != 0.0) r.pcg_flags |= BA_PCG_BREAKDOWN;
+  if (r.coarse > 0 && (h->hscal[SC_BREAK] != 0.0 || !std::isfinite(h->hscal[SC_RR]) || !std::isfinite(h->hscal[SC_RZ]))) {
+    // the two-level solve broke down: solve again with block-Jacobi alone
+    h->d.coarse_k = 0;
+    r.coarse = 0;
+    r.pcg_flags |= BA_PCG_COARSE_FALLBACK;
+    double mv2 = 0;
+    r.pcg_iters += pcg(h, h->lambda, o.pcg_tol, o.pcg_max_iters, o.time_kernels ? &mv2 : nullptr);
+    mv_ms += mv2;
+  }
   r.matvec_ms = mv_ms;
   r.matvec_count = o.time_kernels ? r.pcg_iters + (h->hscal[SC_BREAK] != 0.0 ? 1 : 0) : 0;
-  r.coarse = h->d.coarse_k > 0 && h->hscal[SC_COARSE] != 0.0 ? h->d.coarse_k : 0;
   record(h, 4);
   const double rr = h->hscal[SC_RR], bb = h->hscal[SC_BB];
+  if (!std::isfinite(bb)) r.pcg_flags |= BA_PCG_NONFINITE_RHS;
   r.pcg_rel_residual = bb > 0 ? std::sqrt(rr / bb) : 0.0;
   r.n_fp64_blocks = (int)h->hscal[SC_NFLAG];
+  r.n_degenerate = (int)h->hscal[SC_NDEG];
   launch_backsub(h->d, h->stream);
   record(h, 5);
   launch_retract(h->d, h->stream);
@@ -949,6 +963,8 @@ void do_step(ba_handle* h, const ba_solve_options& o, ba_step_report* rep) {
   } else {
     h->lambda *= h->nu;
     h->nu *= 2.0;
+    // a non-finite reduced system is not cured by more damping of the same linearisation
+    if (r.pcg_flags & BA_PCG_NONFINITE_RHS) h->need_lin = true;
   }
   if (h->events) {
     float ms = 0;
@@ -1339,7 +1355,15 @@ ba_status ba_pcg_solve(ba_handle* h, double tol, int32_t max_iters, double* x, i
   return guard(h, [&] {
     if (!h->finalized) throw BaError(BA_E_STATE, "no linearisation yet");
     set_device(h);
-    const int it = pcg(h, h->last_lambda, tol, max_iters);
+    int it = pcg(h, h->last_lambda, tol, max_iters);
+    if (h->d.coarse_k > 0 && h->hscal[SC_COARSE] != 0.0 &&
+        (h->hscal[SC_BREAK] != 0.0 || !std::isfinite(h->hscal[SC_RR]) || !std::isfinite(h->hscal[SC_RZ]))) {
+      // as in ba_lm_step: a two-level solve that broke down is repeated with block-Jacobi
+      const int k = h->d.coarse_k;
+      h->d.coarse_k = 0;
+      it += pcg(h, h->last_lambda, tol, max_iters);
+      h->d.coarse_k = k;
+    }
     if (x) HIPCHK(hipMemcpyAsync(x, h->d.x, h->d.nA * 8, hipMemcpyDeviceToHost, h->stream));
     sync(h);
     if (iters) *iters = it;

@@ -116,8 +116,8 @@ constexpr int MV_THREADS = 1024, MV_CHUNK = 64, MV_MAX_CHUNKS = MV_THREADS / MV_
 enum PcgScal {
   SC_RZ = 0, SC_BB, SC_RR, SC_PQ, SC_ALPHA, SC_BETA, SC_DONE, SC_ITER, SC_TOL2, SC_LAMBDA,
   SC_GH, SC_JH2, SC_E, SC_EPIX, SC_NFLAG, SC_MAXIT, SC_BREAK,
-  // PCG accumulators, three sets rotated by iteration (k mod 3): p.q, r.r, r.z
   SC_COARSE,  // 1: the coarse correction of the preconditioner is active for this solve
+  SC_NDEG,    // records of the current linearisation with a scaled or dropped Jacobian
   // PCG accumulators, three sets rotated by iteration (k mod 3): p.q, r.r, r.(M r),
   // Z^T r, (S Z)^T (M r)
   SC_ACC = 20, SC_COUNT = 128
@@ -125,6 +125,13 @@ enum PcgScal {
 // coarse space of the two-level preconditioner: 7 similarity-gauge columns, then the
 // network's columns
 constexpr int COARSE_GAUGE = 7, COARSE_NET = 8, COARSE_K = COARSE_GAUGE + COARSE_NET;
+// With FP32 records the product resolves S Z only to ~1e-7 |S| |Z|, while on the
+// near-null (gauge) directions S Z ~ lambda D_A Z: below this damping the coarse
+// matrix E is not resolved, and the FP32 path preconditions with block-Jacobi alone.
+constexpr double COARSE_MIN_DAMPING_FP32 = 1e-6;
+// Above this damping S is dominated by its damped diagonal blocks and block-Jacobi
+// PCG needs a handful of iterations: fewer than the coarse set-up costs in products.
+constexpr double COARSE_MAX_DAMPING = 0.1;
 constexpr int ACC_PQ = 0, ACC_RR = 1, ACC_RZ = 2, ACC_ZR = 4, ACC_W = ACC_ZR + COARSE_K, ACC_STRIDE = ACC_W + COARSE_K;
 static_assert(SC_ACC + 3 * ACC_STRIDE <= SC_COUNT, "PCG scalar area too small");
 

@@ -231,6 +231,23 @@ template <int FAM> __device__ __forceinline__ void residual64(const Dev& d, int6
 }
 
 // ---------------------------------------------------------------------------
+// relative image-line normal of a line-projection record, from the FP64 master
+// parameters (for R4 the smaller of the line's and of its plane projection's)
+template <int FAM> __device__ __forceinline__ double line_record_normal(const Dev& d, int64_t i, int f) {
+  const Cam<double> C = load_cam<double>(d.cam64 + (int64_t)CAM_STRIDE * d.fcam[FAM][i]);
+  const Line<double> L = load_line<double>(d.ln64 + (int64_t)LN_STRIDE * f);
+  double dl[3], ml[3];
+  line_dm(L, dl, ml);
+  double rel = image_line_normal(C, dl, ml);
+  if constexpr (FAM == 4) {
+    PlaneLine<double> P;
+    plane_line(dl, ml, load_plane<double>(d.pl64 + (int64_t)PL_STRIDE * d.fgrp[FAM][i]), P, false);
+    if (!P.degenerate) rel = fmin(rel, image_line_normal(C, P.d2, P.m2));
+  }
+  return rel;
+}
+
+// ---------------------------------------------------------------------------
 // linearisation: one lane per record
 template <int FAM, typename T, int CD> __global__ __launch_bounds__(256) void k_lin(Dev d) {
   using F = Fam<FAM, CD>;
@@ -296,6 +313,34 @@ template <int FAM, typename T, int CD> __global__ __launch_bounds__(256) void k_
       if constexpr (FAM == 7) jac_R7<T, CD>(C, L, mT, r, Jc, Jf);
     }
   }
+  // nearly degenerate image line: FP64 Jacobian below FP64_IMAGE_LINE, scaled
+  // below DEGENERATE_IMAGE_LINE; a Jacobian that is still not finite in T is
+  // dropped (the residual stays in the cost either way)
+  double jscale = 1.0;
+  if constexpr (FAM == 2 || FAM == 4 || FAM == 7) {
+    const double rel = line_record_normal<FAM>(d, i, f);
+    if constexpr ((FAM == 2 || FAM == 7) && sizeof(T) < sizeof(double)) {
+      if (rel < FP64_IMAGE_LINE) {
+        double m64[4] = {0, 0, 0, 0}, r64j[4], jc64[F::ROWS * SL::NC], jf64[F::ROWS * 4];
+#pragma unroll
+        for (int k = 0; k < F::MEAS; ++k) m64[k] = d.fmeas[FAM][i * F::MEAS + k];
+        const Cam<double> C64 = load_cam<double>(d.cam64 + (int64_t)CAM_STRIDE * d.fcam[FAM][i]);
+        const Line<double> L64 = load_line<double>(d.ln64 + (int64_t)LN_STRIDE * f);
+        if constexpr (FAM == 2) jac_R2<double, CD>(C64, L64, m64, r64j, jc64, jf64);
+        else jac_R7<double, CD>(C64, L64, m64, r64j, jc64, jf64);
+#pragma unroll
+        for (int k = 0; k < F::ROWS * SL::NC; ++k) Jc[k] = (T)jc64[k];
+#pragma unroll
+        for (int k = 0; k < F::ROWS * 4; ++k) Jf[k] = (T)jf64[k];
+      }
+    }
+    jscale = fmin(1.0, rel / DEGENERATE_IMAGE_LINE);
+  }
+  bool finite = true;
+#pragma unroll
+  for (int k = 0; k < SL::USED; ++k) finite = finite && isfinite(v[k]);
+  if (!finite) jscale = 0.0;
+  if (jscale < 1.0) atomicAdd(&d.scal[SC_NDEG], 1.0);
   // residual in FP64 from the FP64 parameters, robust IRLS scale
   double r64[F::ROWS];
   residual64<FAM>(d, i, d.cam64, d.pt64, d.ln64, d.pl64, d.vp64, r64);
@@ -308,9 +353,9 @@ template <int FAM, typename T, int CD> __global__ __launch_bounds__(256) void k_
   T* ro = ((T*)d.fres[FAM]) + i * F::ROWS;
 #pragma unroll
   for (int k = 0; k < F::ROWS; ++k) ro[k] = (T)(ws * r64[k]);
-  const T wsT = (T)ws;
+  const T wsT = (T)(ws * jscale);
 #pragma unroll
-  for (int k = 0; k < SL::USED; ++k) v[k] *= wsT;
+  for (int k = 0; k < SL::USED; ++k) v[k] = jscale > 0.0 ? v[k] * wsT : T(0);
   store_vec(((T*)d.frec[FAM]) + i * SL::STRIDE, v);
 }
 

@@ -261,6 +261,23 @@ template <typename S> BA_HD void lproject(const Cam<S>& c, const S* d, const S* 
   o.l[0] = o.mc[0]; o.l[1] = o.mc[1]; o.l[2] = c.f * o.mc[2];
 }
 
+// Normal (l_1, l_2) of the image line of (d, m) in camera c, relative to
+// |m| + |t| |d|, a bound on |m_c|.  It vanishes for a line through the camera
+// centre or in the camera's principal plane: there the image line has no
+// direction and the line-projection residuals are not differentiable.
+template <typename S> BA_HD S image_line_normal(const Cam<S>& c, const S* d, const S* m) {
+  LProj<S> o;
+  lproject(c, d, m, o);
+  const S den = sqrt(dot3(m, m)) + sqrt(dot3(c.t, c.t)) * sqrt(dot3(d, d));
+  return den > S(0) ? sqrt(o.mc[0] * o.mc[0] + o.mc[1] * o.mc[1]) / den : S(0);
+}
+// Line-projection records (R2, R4, R7) whose image line is closer to degenerate
+// than DEGENERATE_IMAGE_LINE keep their residual, and their Jacobian is scaled by
+// (normal / DEGENERATE_IMAGE_LINE): same direction, the magnitude it has at the
+// threshold.  Below FP64_IMAGE_LINE the working-precision path evaluates their
+// Jacobian in FP64 (the image line is a difference of nearly equal terms there).
+constexpr double DEGENERATE_IMAGE_LINE = 1e-3, FP64_IMAGE_LINE = 1e-2;
+
 // endpoint vector and its derivative w.r.t. the image line (2 x 3)
 template <typename S> BA_HD void endpoint(const S* l, const S* e, S* rho, S G[2][3], bool jac) {
   S h = l[0] * e[0] + l[1] * e[1] + l[2];

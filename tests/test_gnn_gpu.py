@@ -235,6 +235,24 @@ def test_zero_head_falls_back_to_block_jacobi():
     assert np.linalg.norm(xj - xl) <= 1e-7 * np.linalg.norm(xj)
 
 
+def test_coarse_space_damping_window():
+    """The two-level preconditioners switch to block-Jacobi above lambda = 0.1
+    (block-Jacobi needs a few iterations there) and, with FP32 records, below
+    lambda = 1e-6 (the FP32 product does not resolve S on the gauge
+    directions); the FP64 path keeps them at small lambda.  All solve to 1e-6."""
+    from paper_2609_04026_amd.binding import BA
+    sc = make_scene(small_config(n_cams=10, n_points=60, n_lines=16), seed=41)
+    blob = gnn.pack(gnn.init_params(9, seed=3)).tobytes()
+    for precision, lam, cols in (("mixed", 1e-7, 0), ("mixed", 1e-5, 15), ("fp64", 1e-7, 15), ("mixed", 0.5, 0),
+                                 ("fp64", 0.5, 0), ("fp64", 0.05, 15)):
+        ba = BA.from_scene(sc, precision=precision, precond="learned")
+        ba.set_gnn_weights(blob)
+        rep = ba.lm_step(lambda0=lam, pcg_tol=1e-6)
+        assert rep["coarse"] == cols, (precision, lam, rep)
+        assert rep["pcg_rel_residual"] <= 1e-6 and rep["pcg_flags"] == 0, (precision, lam, rep)
+        ba.close()
+
+
 WEIGHTS = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2609_04026_amd",
                        "weights", "gnn_precond.bin")
 

@@ -154,6 +154,87 @@ def test_one_lm_step_matches_exact_schur_step(case, precision):
     ba.close()
 
 
+def _line_points_near_camera(st, c, u, target):
+    """Two points of a line along u beside camera c's centre whose relative
+    image-line normal in camera c is `target`."""
+    R, t = st.cam_R[c], st.cam_t[c]
+    C = -(R.T @ t)
+    off = np.cross(u, [0.3, -0.5, 0.8])
+    off /= np.linalg.norm(off)
+    delta = 1.0
+    for _ in range(60):
+        P = C + delta * off
+        U, w = model.line_from_points(P[None], (P + u)[None])
+        d, m = model.line_plucker(U, w)
+        delta *= target / model.image_line_normal(R[None], t[None], d, m)[0]
+    P = C + delta * off
+    return np.concatenate([P, P + u])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_degenerate_image_line_record(precision):
+    """Two lines moved next to the centres of cameras that observe them, to
+    relative image-line normals 1e-8 (Jacobian scaled by 1e-5) and 5e-3
+    (unscaled; the mixed path evaluates it in FP64): the GPU records match the
+    oracle's, it counts the scaled records, and its LM step matches the
+    oracle's exact Schur step."""
+    s = make_scene(small_config(), seed=2)
+    prob = lm.Problem(s)
+    st = prob.state0()
+    rec = prob.recs["R2"]
+    d, _ = st.plucker()
+    s2 = dict(s)
+    s2["lines"] = np.array(s["lines"], dtype=np.float64, copy=True)
+    j1, c1 = int(rec["ln"][0]), int(rec["cam"][0])
+    k2 = int(np.nonzero(rec["ln"] != j1)[0][0])
+    j2, c2 = int(rec["ln"][k2]), int(rec["cam"][k2])
+    for j, c, target in ((j1, c1, 1e-8), (j2, c2, 5e-3)):
+        s2["lines"][j] = _line_points_near_camera(st, c, d[j] / np.linalg.norm(d[j]), target)
+    prob2 = lm.Problem(s2)
+    st2 = prob2.state0()
+    lin = lm.linearize(prob2, st2)
+    n_deg = sum(int(model.degenerate_line_records(st2, prob2.recs[f], f).sum()) for f in ("R2", "R4", "R7")
+                if prob2.record_count(f))
+    assert n_deg >= 1
+    lam = 1e-3
+    BA = _ba()
+    ba = BA.from_scene(s2, precision=precision)
+    rep = ba.lm_step(lambda0=lam, pcg_tol=1e-12 if precision == "fp64" else 1e-7, pcg_max_iters=2000)
+    assert rep["n_degenerate"] == n_deg and rep["pcg_flags"] == 0, rep
+    keys_or = record_keys(prob2.recs)
+    for fam in (2, 4, 7):
+        fname = f"R{fam}"
+        if prob2.record_count(fname) == 0:
+            continue
+        keys, r, J = ba.export_records(fam)
+        og, oo = _match(keys, keys_or[fname][:, 1:])
+        L = lin.fam[fname]
+        tol = 1e-9 if precision == "fp64" else 1e-4
+        # residual and Jacobian at a nearly degenerate image line are themselves
+        # ill-conditioned (they divide by the image-line normal): 1e-6 there
+        near = model.line_record_normal(st2, {k: v[oo] for k, v in prob2.recs[fname].items()}, fname) < 1e-6
+        rt = L["rt"][oo]
+        err = np.abs(r[og] - rt).max(axis=1) / np.maximum(1.0, np.abs(rt).max(axis=1))
+        assert float(np.max(err[~near], initial=0.0)) <= tol, fname
+        assert float(np.max(err[near], initial=0.0)) <= max(tol, 1e-6), fname
+        for b, sl in _block_cols(fam, prob2.camera_dof).items():
+            Jo, Jg = L["J"][b][oo], J[og][:, :, sl]
+            nrm = np.linalg.norm(Jo, axis=(1, 2))
+            rel = np.linalg.norm(Jg - Jo, axis=(1, 2)) / np.maximum(nrm, 1e-30)
+            assert float(np.max(rel[~near & (nrm > 0)], initial=0.0)) <= tol, (fname, b)
+            assert float(np.max(rel[near & (nrm > 0)], initial=0.0)) <= max(tol, 1e-6), (fname, b)
+    h, _ = lm.solve_schur(prob2, lin, lam)
+    tol = 1e-8 if precision == "fp64" else 1e-4
+    dL = lm.model_decrease(lin, h)
+    assert abs(rep["model_decrease"] - dL) <= 10 * tol * abs(dL), (rep, dL)
+    # the candidate cost is not compared: it holds the residual at the 1e-8 image
+    # line, whose true derivative is ~1e5 times its scaled one, so the step's
+    # rounding moves it by far more than the tolerance
+    assert np.isfinite(rep["E_after"])
+    assert abs(rep["E_before"] - lm.cost(prob2, st2)[0]) <= 1e-8 * rep["E_before"]
+    ba.close()
+
+
 def _oracle_converged():
     with open(os.path.join(GOLDEN, "oracle_converged.json")) as f:
         return json.load(f)

@@ -87,6 +87,110 @@ def test_jacobian_near_degenerate_geometry():
             assert np.abs(fd - J["ln"][:, :, k]).max() <= 1e-5 * max(np.abs(J["ln"]).max(), 1.0)
 
 
+def test_image_line_normal_closed_forms():
+    """Degenerate image lines (a reading; the paper leaves the case open):
+    with the camera at the world frame, the line through (0, y0, Z) along e_x
+    has moment (0, Z, -y0) and image-line normal (0, Z), so the relative
+    normal is Z / sqrt(Z^2 + y0^2).  It is zero for a line through the camera
+    centre and for a line in the principal plane, and invariant to a scaling
+    of the scene."""
+    I, t0 = np.eye(3)[None], np.zeros((1, 3))
+    for y0, Z in ((0.5, 3.0), (-2.0, 0.1), (4.0, 7.5)):
+        P = np.array([[0.0, y0, Z]])
+        U, w = model.line_from_points(P, P + np.array([[1.0, 0.0, 0.0]]))
+        d, m = model.line_plucker(U, w)
+        assert abs(model.image_line_normal(I, t0, d, m)[0] - Z / np.hypot(Z, y0)) < 1e-14
+    rng = np.random.default_rng(4)
+    for _ in range(5):
+        R = model.so3_exp(rng.normal(size=(1, 3)))
+        t = rng.normal(size=(1, 3)) * 3
+        C = -(R[0].T @ t[0])
+        u = rng.normal(size=3)
+        U, w = model.line_from_points(C[None], (C + u)[None])
+        d, m = model.line_plucker(U, w)
+        assert model.image_line_normal(R, t, d, m)[0] < 1e-12
+        # principal plane: the camera-frame line through (0, 2, 0) along e_x
+        P = C + R[0].T @ np.array([0.0, 2.0, 0.0])
+        U, w = model.line_from_points(P[None], (P + R[0].T @ np.array([1.0, 0.0, 0.0]))[None])
+        d, m = model.line_plucker(U, w)
+        assert model.image_line_normal(R, t, d, m)[0] < 1e-12
+        # a generic line, and the same scene scaled by 7
+        P, Q = rng.normal(size=(1, 3)), rng.normal(size=(1, 3))
+        U, w = model.line_from_points(P, Q)
+        d, m = model.line_plucker(U, w)
+        U7, w7 = model.line_from_points(7 * P, 7 * Q)
+        d7, m7 = model.line_plucker(U7, w7)
+        v, v7 = model.image_line_normal(R, t, d, m)[0], model.image_line_normal(R, 7 * t, d7, m7)[0]
+        assert v > 1e-6 and abs(v - v7) < 1e-12 * max(v, 1.0)
+
+
+def _line_near_camera(st, c, u, target):
+    """Line along u placed beside camera c's centre so that its relative
+    image-line normal in camera c is `target` (fixed-point on the offset)."""
+    R, t = st.cam_R[c], st.cam_t[c]
+    C = -(R.T @ t)
+    off = np.cross(u, [0.3, -0.5, 0.8])
+    off /= np.linalg.norm(off)
+    delta = 1.0
+    for _ in range(60):
+        U, w = model.line_from_points((C + delta * off)[None], (C + delta * off + u)[None])
+        d, m = model.line_plucker(U, w)
+        rel = model.image_line_normal(R[None], t[None], d, m)[0]
+        delta *= target / rel
+    return U[0], w[0], rel
+
+
+def test_degenerate_line_record_scales_its_jacobian():
+    """A line moved next to the centre of a camera that observes it.  At a
+    relative image-line normal of 4e-4 that camera's line-projection
+    Jacobians equal 0.4 times central differences; at 1e-8 they stay finite
+    and bounded; the line's records in other cameras keep unscaled
+    Jacobians that match central differences."""
+    s = make_scene(small_config(), seed=2)
+    prob = lm.Problem(s)
+    st0 = prob.state0()
+    rec = prob.recs["R2"]
+    j, c = int(rec["ln"][0]), int(rec["cam"][0])
+    d, _ = st0.plucker()
+    u = d[j] / np.linalg.norm(d[j])
+    norms = {}
+    for target in (4e-4, 1e-8):
+        st = st0.copy()
+        U, w, rel = _line_near_camera(st, c, u, target)
+        assert abs(rel / target - 1) < 1e-6
+        st.line_U[j], st.line_w[j] = U, w
+        for fam in ("R2", "R4", "R7"):
+            rf = prob.recs[fam]
+            sel = np.nonzero(rf["ln"] == j)[0]
+            if sel.size == 0:
+                continue
+            sub = {k: v[sel] for k, v in rf.items()}
+            deg = model.degenerate_line_records(st, sub, fam)
+            assert np.array_equal(deg, sub["cam"] == c), fam
+            assert np.all(np.isfinite(model.residuals(st, sub, fam, prob.cx, prob.cy)))
+            J = model.jacobians(st, sub, fam, prob.cx, prob.cy)
+            assert all(np.all(np.isfinite(v)) for v in J.values())
+            norms[(target, fam)] = max(np.abs(v[deg]).max(initial=0.0) for v in J.values())
+            rows = np.arange(sel.size) if target > 1e-6 else np.nonzero(~deg)[0]
+            factor = np.where(deg, target / model.DEGENERATE_IMAGE_LINE, 1.0)[rows]
+            part = {k: v[rows] for k, v in sub.items()}
+            for b, key in (("ln", "ln"), ("cam", "cam")):
+                for k in range(4):
+                    def cd(hh):
+                        rp = model.residuals(_retract_block(st, prob, b, k, hh), part, fam, prob.cx, prob.cy)
+                        rm = model.residuals(_retract_block(st, prob, b, k, -hh), part, fam, prob.cx, prob.cy)
+                        return (rp - rm) / (2 * hh)
+                    fd = (4 * cd(1e-7) - cd(2e-7)) / 3 * factor[:, None]
+                    Jk = J[b][rows][:, :, k]
+                    assert np.abs(fd - Jk).max() <= 1e-5 * max(np.abs(Jk).max(), 1.0), (target, fam, b, k)
+    # the scaled Jacobian at 1e-8 is no larger than at the threshold's order
+    for fam in ("R2", "R4", "R7"):
+        if (1e-8, fam) in norms and norms[(4e-4, fam)] > 0:
+            assert norms[(1e-8, fam)] <= 10 * norms[(4e-4, fam)] / 0.4, fam
+    lin = lm.linearize(prob, st)
+    assert np.all(np.isfinite(lin.g))
+
+
 # ---------------------------------------------------------------- P2
 @pytest.mark.parametrize("cfg,seed", [(small_config(), 5), (2, 2000)])
 def test_zero_residual_at_ground_truth(cfg, seed):
