@@ -617,41 +617,42 @@ void finalize(ba_handle* h) {
   d.szr = A.get<char>((size_t)nA * 8, TS);
   d.szfp = A.get<char>((size_t)h->np * 3 * 8, TS);
   d.szfl = A.get<char>((size_t)h->nl * 4 * 8, TS);
-  // product tiles: runs of consecutive features whose records split into at
-  // most MV_MAX_CHUNKS single-family chunks of MV_CHUNK records
+  // product tiles: runs of consecutive features with at most MV_TILE records over
+  // all their families, one packed (family, record) slot per record in feature order
   {
-    std::vector<int4> tiles, chunks;
+    std::vector<int4> tiles;
+    std::vector<uint32_t> wrec;
     std::vector<int32_t> bigp, bigl;
-    // BA_TILE_CHUNKS (1..16) lowers the chunk capacity of a tile; used by tests
+    // BA_TILE_RECORDS (1..64) lowers the record capacity of a tile; used by tests
     // to route features through the large-feature path
-    int max_chunks = MV_MAX_CHUNKS;
-    if (const char* e = std::getenv("BA_TILE_CHUNKS")) max_chunks = std::max(1, std::min(MV_MAX_CHUNKS, std::atoi(e)));
+    int cap = MV_TILE;
+    if (const char* e = std::getenv("BA_TILE_RECORDS")) cap = std::max(1, std::min(MV_TILE, std::atoi(e)));
+    for (int fam = 1; fam < NFAM; ++fam)
+      if (d.fn[fam] >= (int64_t)1 << 28) throw BaError(BA_E_INVALID, "more than 2^28 records in one family");
     auto build = [&](const std::vector<int>& fams, int nfeat, std::vector<int32_t>& big) {
       int f = 0;
       while (f < nfeat) {
         const int fb = f;
-        int64_t cnt[NFAM] = {0};
-        while (f < nfeat && f - fb < MV_MAX_TF) {
-          int need_chunks = 0;
-          int64_t c2[NFAM];
-          for (int fam : fams) {
-            c2[fam] = cnt[fam] + (foff_h[fam][f + 1] - foff_h[fam][f]);
-            need_chunks += (int)((c2[fam] + MV_CHUNK - 1) / MV_CHUNK);
-          }
-          if (need_chunks > max_chunks) break;
-          for (int fam : fams) cnt[fam] = c2[fam];
+        int64_t cnt = 0;
+        while (f < nfeat) {
+          int64_t n = 0;
+          for (int fam : fams) n += foff_h[fam][f + 1] - foff_h[fam][f];
+          if (cnt + n > cap) break;
+          cnt += n;
           ++f;
         }
-        if (f == fb) {  // one feature with too many records for a tile
+        if (f == fb) {  // one feature with more records than a tile holds
           big.push_back(f);
           ++f;
           continue;
         }
-        const int cb = (int)chunks.size();
-        for (int fam : fams)
-          for (int64_t r = foff_h[fam][fb]; r < foff_h[fam][f]; r += MV_CHUNK)
-            chunks.push_back(make_int4(fam, (int)r, (int)std::min<int64_t>(MV_CHUNK, foff_h[fam][f] - r), 0));
-        tiles.push_back(make_int4(fb, f, cb, (int)chunks.size() - cb));
+        if (cnt == 0) continue;  // features without records
+        const int first = (int)wrec.size();
+        for (int g = fb; g < f; ++g)
+          for (int fam : fams)
+            for (int64_t r = foff_h[fam][g]; r < foff_h[fam][g + 1]; ++r)
+              wrec.push_back(((uint32_t)fam << 28) | (uint32_t)r);
+        tiles.push_back(make_int4(first, (int)cnt, fb, 0));
       }
     };
     build({1, 3, 6}, h->np, bigp);
@@ -661,24 +662,23 @@ void finalize(ba_handle* h) {
     d.n_bigp = (int)bigp.size();
     d.n_bigl = (int)bigl.size();
     d.tiles = A.get<int4>(tiles.size());
-    d.chunks = A.get<int4>(chunks.size());
+    d.wrec = A.get<uint32_t>(wrec.size());
     d.bigp = A.get<int32_t>(bigp.size());
     d.bigl = A.get<int32_t>(bigl.size());
     upload(h, d.tiles, tiles);
-    upload(h, d.chunks, chunks);
+    upload(h, d.wrec, wrec);
     upload(h, d.bigp, bigp);
     upload(h, d.bigl, bigl);
   }
-  // the workgroup's copy of the reduced vector (and of the product input) in LDS when they fit
+  // the workgroup's copy of the reduced vector in LDS when it fits
   int ncu = 0;
   HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, h->device));
   const int max_lds = matvec_max_lds_bytes();
-  const size_t base = 8 * 4 * MV_MAX_TF, need = (size_t)nA * 8;
-  d.mv_lds = base + need <= (size_t)max_lds ? 1 : 0;
-  d.mv_stage_x = 0;  // two workgroups per CU share the LDS; the input is read through the caches
+  d.mv_lds = (size_t)nA * 8 <= (size_t)max_lds ? 1 : 0;
   const size_t lds_bytes = matvec_lds_bytes(d);
   const int wg_per_cu = (int)std::max<size_t>(1, std::min<size_t>(2, 163840 / std::max<size_t>(lds_bytes, 1)));
-  d.n_mv_wg = std::max(1, std::min(ncu * wg_per_cu, d.n_tiles + (d.n_bigp + d.n_bigl + MV_THREADS - 1) / MV_THREADS));
+  const int64_t waves = d.n_tiles + (d.n_bigp + d.n_bigl + 63) / 64;
+  d.n_mv_wg = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)ncu * wg_per_cu, (waves + MV_THREADS / 64 - 1) / (MV_THREADS / 64)));
   d.mv_part = A.get<double>(d.mv_lds ? (size_t)d.n_mv_wg * nA : (size_t)nA);
   d.cnt = A.get<unsigned int>(4);
   launch_zero(d.cnt, 4 * sizeof(unsigned int), h->stream);
@@ -696,8 +696,8 @@ void finalize(ba_handle* h) {
   if (std::getenv("BA_VERBOSE")) {
     std::fprintf(stderr, "[libba] records:");
     for (int fam = 1; fam < NFAM; ++fam) std::fprintf(stderr, " R%d=%lld", fam, (long long)d.fn[fam]);
-    std::fprintf(stderr, "; nA=%d; product: %s%s, %d workgroups, %d tiles (%d point), %d+%d large features, LDS %zu of %d B\n",
-                 nA, d.mv_lds ? "LDS-private y" : "global atomics", d.mv_stage_x ? " + LDS x" : "", d.n_mv_wg, d.n_tiles,
+    std::fprintf(stderr, "; nA=%d; product: %s, %d workgroups, %d tiles (%d point), %d+%d large features, LDS %zu of %d B\n",
+                 nA, d.mv_lds ? "LDS-private y" : "global atomics", d.n_mv_wg, d.n_tiles,
                  d.n_ptiles, d.n_bigp, d.n_bigl, lds_bytes, max_lds);
   }
   h->need_lin = true;

@@ -95,11 +95,12 @@ struct Dev {
   double *red = nullptr;    // reduction partials
   int n_mv_wg = 0;          // matvec workgroups (partials rows)
   int mv_lds = 0;           // 1: accumulate in LDS
-  int mv_stage_x = 0;       // 1: the product input is staged in LDS as well
-  // feature-aligned tiles of the product: int4 (feat_begin, feat_end, chunk_begin, n_chunks),
-  // point tiles first, then line tiles; chunks int4 (family, record_begin, record_count, 0)
+  // wavefront tiles of the product: int4 (first slot, slots, first feature, 0), point tiles
+  // first, then line tiles; one packed slot per record, (family << 28) | record index, in
+  // feature order
   int n_tiles = 0, n_ptiles = 0;
-  int4 *tiles = nullptr, *chunks = nullptr;
+  int4* tiles = nullptr;
+  uint32_t* wrec = nullptr;
   // features too large for one tile (handled one lane per feature)
   int n_bigp = 0, n_bigl = 0;
   int32_t *bigp = nullptr, *bigl = nullptr;
@@ -107,10 +108,9 @@ struct Dev {
   double *part2 = nullptr;      // per-workgroup partial dot products of the PCG kernels
 };
 
-// product tiles: one 1024-thread workgroup; one 64-lane wavefront per chunk of
-// at most 64 records of one family; at most MV_MAX_TF features per tile
-// (per-workgroup sums are accumulated in FP64 in LDS: FP32 LDS atomics are slow on gfx950)
-constexpr int MV_THREADS = 1024, MV_CHUNK = 64, MV_MAX_CHUNKS = MV_THREADS / MV_CHUNK, MV_MAX_TF = 120;
+// product: 1024-thread workgroups sharing one FP64 copy of y in LDS (FP32 LDS atomics
+// measured 2x slower on gfx950); each wavefront takes tiles of at most MV_TILE records
+constexpr int MV_THREADS = 1024, MV_TILE = 64;
 
 // indices into Dev::scal
 enum PcgScal {

@@ -1150,16 +1150,17 @@ template <typename T, int CD, int NF> __device__ __forceinline__ void mv_feature
 }
 
 // ---------------------------------------------------------------------------
-// Tiled implicit-Schur product.  A tile is a run of consecutive features
-// (<= MV_MAX_TF) whose records (<= 1024) are split into single-family chunks
-// of <= 64 records; wavefront w of the 1024-thread workgroup takes chunk w,
-// one record per lane, and keeps that record's Jacobian in registers across
-// the tile's three phases:
-//   A  t = J_a x;  q_f += J_f^T t          (LDS atomics, per tile feature)
-//   B  s_f = (V_f + lambda D_f)^-1 q_f      (one thread per tile feature)
-//   C  u = t - J_f s_f;  y_a += J_a^T u     (LDS atomics into the workgroup's y)
-// The workgroup's y (and, when it fits, the input x) live in LDS; each
-// workgroup writes its y to its row of the partial buffer.
+// Wavefront-tiled implicit-Schur product.  A tile is a run of consecutive
+// features (points, or lines) with at most 64 records over all their families,
+// stored as one packed (family, record) word per lane in feature order.  Each
+// wavefront takes its own tiles, one record per lane, with no workgroup barrier:
+//   A  t = J_a x;  q_f = sum of J_f^T t over the feature's lanes (segmented
+//      scan across the wavefront; the feature's last lane holds the sum)
+//   B  s_f = (V_f + lambda D_f)^-1 q_f on that last lane, broadcast to the
+//      feature's lanes
+//   C  u = t - J_f s_f;  y_a += J_a^T u   (FP64 LDS atomics into the
+//      workgroup's y, which all its wavefronts share)
+// Each workgroup writes its y to its row of the partial buffer.
 template <int CD> struct MaxSlot { static constexpr int V = Slot<4, CD>::STRIDE; };
 
 template <int FAM, typename T, int CD>
@@ -1210,31 +1211,9 @@ __device__ __forceinline__ void tile_phase_a(const Dev& d, int64_t i, const T* x
 }
 
 template <int FAM, typename T, int CD>
-__device__ __forceinline__ void tile_phase_c(const T (&v)[MaxSlot<CD>::V], const T (&t)[4], int ac, int ag, int lf,
-                                             const double* qs, double* y);
-
-// FP64 records are reloaded for phase C instead of being held across the barriers
-template <int FAM, typename T, int CD>
-__device__ __forceinline__ void tile_phase_c_reload(const Dev& d, int64_t i, const T (&t)[4], int ac, int ag, int lf,
-                                                    const double* qs, double* y) {
+__device__ __forceinline__ void tile_phase_c(const T (&v)[MaxSlot<CD>::V], const T (&t)[4], int ac, int ag,
+                                             const T (&sv)[4], double* y) {
   using SL = Slot<FAM, CD>;
-  T v[MaxSlot<CD>::V];
-  const double2* q2 = reinterpret_cast<const double2*>((const T*)d.frec[FAM] + i * SL::STRIDE);
-#pragma unroll
-  for (int k = 0; k < SL::STRIDE / 2; ++k) {
-    double2 a = q2[k];
-    v[2 * k] = a.x; v[2 * k + 1] = a.y;
-  }
-  tile_phase_c<FAM, T, CD>(v, t, ac, ag, lf, qs, y);
-}
-
-template <int FAM, typename T, int CD>
-__device__ __forceinline__ void tile_phase_c(const T (&v)[MaxSlot<CD>::V], const T (&t)[4], int ac, int ag, int lf,
-                                             const double* qs, double* y) {
-  using SL = Slot<FAM, CD>;
-  T sv[SL::NF];
-#pragma unroll
-  for (int a = 0; a < SL::NF; ++a) sv[a] = (T)qs[4 * lf + a];
   T zc[SL::NC > 0 ? SL::NC : 1], zg[SL::NG > 0 ? SL::NG : 1];
 #pragma unroll
   for (int k = 0; k < SL::NC; ++k) zc[k] = 0;
@@ -1256,132 +1235,129 @@ __device__ __forceinline__ void tile_phase_c(const T (&v)[MaxSlot<CD>::V], const
   for (int k = 0; k < SL::NG; ++k) atomicAdd(y + ag + k, (double)zg[k]);
 }
 
-template <typename T, int CD, bool LDSY, bool STAGEX>
-__global__ __launch_bounds__(MV_THREADS) void k_mv_tiled(Dev d, const double* done) {
+// FP64 records are reloaded for phase C instead of being held in registers
+template <int FAM, typename T, int CD>
+__device__ __forceinline__ void tile_phase_c_reload(const Dev& d, int64_t i, const T (&t)[4], int ac, int ag,
+                                                    const T (&sv)[4], double* y) {
+  using SL = Slot<FAM, CD>;
+  T v[MaxSlot<CD>::V];
+  const double2* q2 = reinterpret_cast<const double2*>((const T*)d.frec[FAM] + i * SL::STRIDE);
+#pragma unroll
+  for (int k = 0; k < SL::STRIDE / 2; ++k) {
+    double2 a = q2[k];
+    v[2 * k] = a.x; v[2 * k + 1] = a.y;
+  }
+  tile_phase_c<FAM, T, CD>(v, t, ac, ag, sv, y);
+}
+
+// s = (V_f + lambda D_f)^-1 q for feature f (FP32 inverse, or the FP64 one of a flagged block)
+template <typename T, int NF> __device__ __forceinline__ void feature_solve(const Dev& d, int f, const T (&q)[4], T (&s)[4]) {
+  T qn[NF], sn[NF];
+#pragma unroll
+  for (int a = 0; a < NF; ++a) qn[a] = q[a];
+  const uint8_t flag = NF == 3 ? d.flp[f] : d.fll[f];
+  if (flag) {
+    apply_vinv<T, NF>(d, f, qn, sn);
+  } else {
+    const T* M = (const T*)(NF == 3 ? d.Vip : d.Vil) + (NF == 3 ? 6 : 10) * (int64_t)f;
+    T Mi[NF == 3 ? 6 : 10];
+#pragma unroll
+    for (int k = 0; k < (NF == 3 ? 6 : 10); ++k) Mi[k] = M[k];
+#pragma unroll
+    for (int a = 0; a < NF; ++a) {
+      T acc = 0;
+#pragma unroll
+      for (int b = 0; b < NF; ++b) acc += Mi[sym<NF>(a, b)] * qn[b];
+      sn[a] = acc;
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a) s[a] = a < NF ? sn[a] : T(0);
+}
+
+template <typename T, int CD, bool LDSY>
+__global__ __launch_bounds__(MV_THREADS) void k_mv_wave(Dev d, const double* done) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   if (done && *done != 0.0) return;
-  double* qs = reinterpret_cast<double*>(smem_raw);
-  double* ys = LDSY ? qs + 4 * MV_MAX_TF : d.mv_part;
-  const T* xg = (const T*)d.xT;
-  T* xs = reinterpret_cast<T*>(qs + 4 * MV_MAX_TF + (LDSY ? d.nA : 0));
-  const T* x = STAGEX ? xs : xg;
+  double* ys = LDSY ? reinterpret_cast<double*>(smem_raw) : d.mv_part;
+  const T* x = (const T*)d.xT;
   if constexpr (LDSY) {
     for (int k = threadIdx.x; k < d.nA; k += blockDim.x) ys[k] = 0;
-  }
-  if constexpr (STAGEX) {
-    for (int k = threadIdx.x; k < d.nA; k += blockDim.x) xs[k] = xg[k];
-  }
-  __syncthreads();
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  for (int tile = blockIdx.x; tile < d.n_tiles; tile += gridDim.x) {
-    const int4 tl = d.tiles[tile];
-    const int fb = tl.x, nf = tl.y - tl.x;
-    for (int k = threadIdx.x; k < 4 * nf; k += blockDim.x) qs[k] = 0;
-    // the damped inverse of this thread's tile feature, fetched while phase A runs
-    const bool ptile = tile < d.n_ptiles;
-    const bool owner = threadIdx.x < nf;
-    T Mi[10];
-    uint8_t mflag = 0;
-    if (owner) {
-      const int f = fb + threadIdx.x;
-      if (ptile) {
-        mflag = d.flp[f];
-        const T* M = (const T*)d.Vip + 6 * (int64_t)f;
-#pragma unroll
-        for (int k = 0; k < 6; ++k) Mi[k] = M[k];
-      } else {
-        mflag = d.fll[f];
-        const T* M = (const T*)d.Vil + 10 * (int64_t)f;
-#pragma unroll
-        for (int k = 0; k < 10; ++k) Mi[k] = M[k];
-      }
-    }
     __syncthreads();
+  }
+  const int lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+  for (int tile = blockIdx.x * nw + (threadIdx.x >> 6); tile < d.n_tiles; tile += gridDim.x * nw) {
+    const int4 tl = d.tiles[tile];  // (first slot, slots, first feature, -)
+    const int fb = tl.z;
+    const bool active = lane < tl.y;
     int fam = 0;
     int64_t i = 0;
-    bool active = false;
-    if (w < tl.w) {
-      const int4 ch = d.chunks[tl.z + w];
-      fam = ch.x;
-      active = lane < ch.z;
-      i = (int64_t)ch.y + lane;
+    if (active) {
+      const uint32_t pk = d.wrec[tl.x + lane];
+      fam = (int)(pk >> 28);
+      i = (int64_t)(pk & 0x0fffffffu);
     }
     T v[MaxSlot<CD>::V];
     T t[4] = {0, 0, 0, 0};
-    T qv[4] = {0, 0, 0, 0};
+    T q[4] = {0, 0, 0, 0};
     int ac = 0, ag = 0, lf = -1;
     if (active) {
       switch (fam) {
-        case 1: tile_phase_a<1, T, CD>(d, i, x, qv, fb, v, t, ac, ag, lf); break;
-        case 2: tile_phase_a<2, T, CD>(d, i, x, qv, fb, v, t, ac, ag, lf); break;
-        case 3: tile_phase_a<3, T, CD>(d, i, x, qv, fb, v, t, ac, ag, lf); break;
-        case 4: tile_phase_a<4, T, CD>(d, i, x, qv, fb, v, t, ac, ag, lf); break;
-        case 5: tile_phase_a<5, T, CD>(d, i, x, qv, fb, v, t, ac, ag, lf); break;
-        case 6: tile_phase_a<6, T, CD>(d, i, x, qv, fb, v, t, ac, ag, lf); break;
-        case 7: tile_phase_a<7, T, CD>(d, i, x, qv, fb, v, t, ac, ag, lf); break;
+        case 1: tile_phase_a<1, T, CD>(d, i, x, q, fb, v, t, ac, ag, lf); break;
+        case 2: tile_phase_a<2, T, CD>(d, i, x, q, fb, v, t, ac, ag, lf); break;
+        case 3: tile_phase_a<3, T, CD>(d, i, x, q, fb, v, t, ac, ag, lf); break;
+        case 4: tile_phase_a<4, T, CD>(d, i, x, q, fb, v, t, ac, ag, lf); break;
+        case 5: tile_phase_a<5, T, CD>(d, i, x, q, fb, v, t, ac, ag, lf); break;
+        case 6: tile_phase_a<6, T, CD>(d, i, x, q, fb, v, t, ac, ag, lf); break;
+        case 7: tile_phase_a<7, T, CD>(d, i, x, q, fb, v, t, ac, ag, lf); break;
       }
     }
-    if (lf >= 0) {
+    // segmented inclusive scan over runs of equal lf (lanes are in feature
+    // order; inactive lanes, lf = -1, come last)
 #pragma unroll
-      for (int a = 0; a < 4; ++a)
-        if (a < 3 || fam == 2 || fam == 4 || fam == 5 || fam == 7) atomicAdd(qs + 4 * lf + a, (double)qv[a]);
-    }
-    __syncthreads();
-    if (owner) {
-      const int k = threadIdx.x;
-      if (ptile) {
-        T q[3] = {(T)qs[4 * k], (T)qs[4 * k + 1], (T)qs[4 * k + 2]}, sv[3];
-        if (mflag) apply_vinv<T, 3>(d, fb + k, q, sv);
-        else {
+    for (int off = 1; off < 64; off <<= 1) {
+      const int of = __shfl_up(lf, off, 64);
+      const bool take = lane >= off && of == lf;
 #pragma unroll
-          for (int i2 = 0; i2 < 3; ++i2) {
-            T acc = 0;
-#pragma unroll
-            for (int j2 = 0; j2 < 3; ++j2) acc += Mi[sym<3>(i2, j2)] * q[j2];
-            sv[i2] = acc;
-          }
-        }
-        qs[4 * k] = sv[0]; qs[4 * k + 1] = sv[1]; qs[4 * k + 2] = sv[2];
-      } else {
-        T q[4] = {(T)qs[4 * k], (T)qs[4 * k + 1], (T)qs[4 * k + 2], (T)qs[4 * k + 3]}, sv[4];
-        if (mflag) apply_vinv<T, 4>(d, fb + k, q, sv);
-        else {
-#pragma unroll
-          for (int i2 = 0; i2 < 4; ++i2) {
-            T acc = 0;
-#pragma unroll
-            for (int j2 = 0; j2 < 4; ++j2) acc += Mi[sym<4>(i2, j2)] * q[j2];
-            sv[i2] = acc;
-          }
-        }
-        qs[4 * k] = sv[0]; qs[4 * k + 1] = sv[1]; qs[4 * k + 2] = sv[2]; qs[4 * k + 3] = sv[3];
+      for (int a = 0; a < 4; ++a) {
+        const T o = __shfl_up(q[a], off, 64);
+        if (take) q[a] += o;
       }
     }
-    __syncthreads();
+    const int next = __shfl_down(lf, 1, 64);
+    const bool last = lf >= 0 && (lane == 63 || next != lf);
+    const unsigned long long lasts = __ballot(last);
+    T s[4] = {0, 0, 0, 0};
+    if (last) {
+      if (tile < d.n_ptiles) feature_solve<T, 3>(d, fb + lf, q, s);
+      else feature_solve<T, 4>(d, fb + lf, q, s);
+    }
+    const int src = lf >= 0 ? __builtin_ctzll(lasts & (~0ull << lane)) : lane;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) s[a] = __shfl(s[a], src, 64);
     if (active) {
       if constexpr (sizeof(T) == 4) {
         switch (fam) {
-          case 1: tile_phase_c<1, T, CD>(v, t, ac, ag, lf, qs, ys); break;
-          case 2: tile_phase_c<2, T, CD>(v, t, ac, ag, lf, qs, ys); break;
-          case 3: tile_phase_c<3, T, CD>(v, t, ac, ag, lf, qs, ys); break;
-          case 4: tile_phase_c<4, T, CD>(v, t, ac, ag, lf, qs, ys); break;
-          case 5: tile_phase_c<5, T, CD>(v, t, ac, ag, lf, qs, ys); break;
-          case 6: tile_phase_c<6, T, CD>(v, t, ac, ag, lf, qs, ys); break;
-          case 7: tile_phase_c<7, T, CD>(v, t, ac, ag, lf, qs, ys); break;
+          case 1: tile_phase_c<1, T, CD>(v, t, ac, ag, s, ys); break;
+          case 2: tile_phase_c<2, T, CD>(v, t, ac, ag, s, ys); break;
+          case 3: tile_phase_c<3, T, CD>(v, t, ac, ag, s, ys); break;
+          case 4: tile_phase_c<4, T, CD>(v, t, ac, ag, s, ys); break;
+          case 5: tile_phase_c<5, T, CD>(v, t, ac, ag, s, ys); break;
+          case 6: tile_phase_c<6, T, CD>(v, t, ac, ag, s, ys); break;
+          case 7: tile_phase_c<7, T, CD>(v, t, ac, ag, s, ys); break;
         }
       } else {
         switch (fam) {
-          case 1: tile_phase_c_reload<1, T, CD>(d, i, t, ac, ag, lf, qs, ys); break;
-          case 2: tile_phase_c_reload<2, T, CD>(d, i, t, ac, ag, lf, qs, ys); break;
-          case 3: tile_phase_c_reload<3, T, CD>(d, i, t, ac, ag, lf, qs, ys); break;
-          case 4: tile_phase_c_reload<4, T, CD>(d, i, t, ac, ag, lf, qs, ys); break;
-          case 5: tile_phase_c_reload<5, T, CD>(d, i, t, ac, ag, lf, qs, ys); break;
-          case 6: tile_phase_c_reload<6, T, CD>(d, i, t, ac, ag, lf, qs, ys); break;
-          case 7: tile_phase_c_reload<7, T, CD>(d, i, t, ac, ag, lf, qs, ys); break;
+          case 1: tile_phase_c_reload<1, T, CD>(d, i, t, ac, ag, s, ys); break;
+          case 2: tile_phase_c_reload<2, T, CD>(d, i, t, ac, ag, s, ys); break;
+          case 3: tile_phase_c_reload<3, T, CD>(d, i, t, ac, ag, s, ys); break;
+          case 4: tile_phase_c_reload<4, T, CD>(d, i, t, ac, ag, s, ys); break;
+          case 5: tile_phase_c_reload<5, T, CD>(d, i, t, ac, ag, s, ys); break;
+          case 6: tile_phase_c_reload<6, T, CD>(d, i, t, ac, ag, s, ys); break;
+          case 7: tile_phase_c_reload<7, T, CD>(d, i, t, ac, ag, s, ys); break;
         }
       }
     }
-    __syncthreads();
   }
   // features whose records do not fit one tile: one lane per feature
   for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < d.n_bigp + d.n_bigl; k += gridDim.x * blockDim.x) {
@@ -1407,25 +1383,21 @@ int matvec_max_lds_bytes() {
   return v;
 }
 
-size_t matvec_lds_bytes(const Dev& d) {
-  const size_t ts = d.fp64 ? 8 : 4;
-  return 8 * (4 * MV_MAX_TF + (d.mv_lds ? (size_t)d.nA : 0)) + (d.mv_stage_x ? ts * (size_t)d.nA : 0);
-}
+size_t matvec_lds_bytes(const Dev& d) { return d.mv_lds ? 8 * (size_t)d.nA : 0; }
 
-template <typename T, int CD, bool LDSY, bool STAGEX> static void launch_mv(const Dev& d, const double* done, hipStream_t s) {
+template <typename T, int CD, bool LDSY> static void launch_mv(const Dev& d, const double* done, hipStream_t s) {
   static bool attr = false;
   if (!attr) {
     // on failure the launch below reports the LDS request through the launch check
-    attr = hipFuncSetAttribute((const void*)k_mv_tiled<T, CD, LDSY, STAGEX>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    attr = hipFuncSetAttribute((const void*)k_mv_wave<T, CD, LDSY>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                matvec_max_lds_bytes()) == hipSuccess;
   }
-  k_mv_tiled<T, CD, LDSY, STAGEX><<<d.n_mv_wg, MV_THREADS, matvec_lds_bytes(d), s>>>(d, done);
+  k_mv_wave<T, CD, LDSY><<<d.n_mv_wg, MV_THREADS, matvec_lds_bytes(d), s>>>(d, done);
 }
 
 template <typename T, int CD> static void run_matvec(const Dev& d, const double* done, hipStream_t s) {
-  if (d.mv_lds && d.mv_stage_x) launch_mv<T, CD, true, true>(d, done, s);
-  else if (d.mv_lds) launch_mv<T, CD, true, false>(d, done, s);
-  else launch_mv<T, CD, false, false>(d, done, s);
+  if (d.mv_lds) launch_mv<T, CD, true>(d, done, s);
+  else launch_mv<T, CD, false>(d, done, s);
 }
 
 // ---------------------------------------------------------------------------

@@ -289,9 +289,9 @@ def test_camera_dof6_and_errors():
 
 def test_large_feature_path_matches(monkeypatch):
     """Features whose records exceed a product tile take the one-lane-per-
-    feature path; with the tile capacity forced to one chunk most features do,
+    feature path; with the tile capacity forced to 8 records most features do,
     and the implicit-Schur product must still equal the dense S x."""
-    monkeypatch.setenv("BA_TILE_CHUNKS", "1")
+    monkeypatch.setenv("BA_TILE_RECORDS", "8")
     from paper_2609_04026_amd.binding import BA
     s = make_scene(2)
     prob = lm.Problem(s)
