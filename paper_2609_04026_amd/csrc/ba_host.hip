@@ -440,7 +440,7 @@ void finalize(ba_handle* h) {
 
   // families
   int64_t max_blocks = 0;
-  std::vector<int32_t> foff_h[NFAM];
+  std::vector<int32_t> foff_h[NFAM], fcam_h[NFAM], fgrp_h[NFAM];
   for (int fam = 1; fam < NFAM; ++fam) {
     const auto& v = R[fam];
     const int64_t n = (int64_t)v.size();
@@ -458,6 +458,8 @@ void finalize(ba_handle* h) {
     }
     for (int f = 0; f < nfeat; ++f) off[f + 1] += off[f];
     foff_h[fam] = off;
+    fcam_h[fam] = cam;
+    fgrp_h[fam] = grp;
     d.fcam[fam] = A.get<int32_t>(n); d.fgrp[fam] = A.get<int32_t>(n); d.ffeat[fam] = A.get<int32_t>(n);
     d.foff[fam] = A.get<int32_t>(nfeat + 1);
     d.fmeas[fam] = A.get<double>((size_t)n * std::max(mw, 1));
@@ -618,10 +620,11 @@ void finalize(ba_handle* h) {
   d.szfp = A.get<char>((size_t)h->np * 3 * 8, TS);
   d.szfl = A.get<char>((size_t)h->nl * 4 * 8, TS);
   // product tiles: runs of consecutive features with at most MV_TILE records over
-  // all their families, one packed (family, record) slot per record in feature order
+  // all their families, one slot per record in feature order: (family << 28 | record,
+  // camera, group, feature - first feature of the tile)
   {
     std::vector<int4> tiles;
-    std::vector<uint32_t> wrec;
+    std::vector<int4> wrec;
     std::vector<int32_t> bigp, bigl;
     // BA_TILE_RECORDS (1..64) lowers the record capacity of a tile; used by tests
     // to route features through the large-feature path
@@ -651,7 +654,7 @@ void finalize(ba_handle* h) {
         for (int g = fb; g < f; ++g)
           for (int fam : fams)
             for (int64_t r = foff_h[fam][g]; r < foff_h[fam][g + 1]; ++r)
-              wrec.push_back(((uint32_t)fam << 28) | (uint32_t)r);
+              wrec.push_back(make_int4((int)(((uint32_t)fam << 28) | (uint32_t)r), fcam_h[fam][r], fgrp_h[fam][r], g - fb));
         tiles.push_back(make_int4(first, (int)cnt, fb, 0));
       }
     };
@@ -662,7 +665,7 @@ void finalize(ba_handle* h) {
     d.n_bigp = (int)bigp.size();
     d.n_bigl = (int)bigl.size();
     d.tiles = A.get<int4>(tiles.size());
-    d.wrec = A.get<uint32_t>(wrec.size());
+    d.wrec = A.get<int4>(wrec.size());
     d.bigp = A.get<int32_t>(bigp.size());
     d.bigl = A.get<int32_t>(bigl.size());
     upload(h, d.tiles, tiles);

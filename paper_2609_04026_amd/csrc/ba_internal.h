@@ -96,11 +96,11 @@ struct Dev {
   int n_mv_wg = 0;          // matvec workgroups (partials rows)
   int mv_lds = 0;           // 1: accumulate in LDS
   // wavefront tiles of the product: int4 (first slot, slots, first feature, 0), point tiles
-  // first, then line tiles; one packed slot per record, (family << 28) | record index, in
-  // feature order
+  // first, then line tiles; one slot per record in feature order, int4 ((family << 28) |
+  // record, camera, group, feature - first feature of the tile)
   int n_tiles = 0, n_ptiles = 0;
   int4* tiles = nullptr;
-  uint32_t* wrec = nullptr;
+  int4* wrec = nullptr;
   // features too large for one tile (handled one lane per feature)
   int n_bigp = 0, n_bigl = 0;
   int32_t *bigp = nullptr, *bigl = nullptr;

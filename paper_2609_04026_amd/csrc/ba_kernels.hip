@@ -1164,8 +1164,8 @@ template <typename T, int CD, int NF> __device__ __forceinline__ void mv_feature
 template <int CD> struct MaxSlot { static constexpr int V = Slot<4, CD>::STRIDE; };
 
 template <int FAM, typename T, int CD>
-__device__ __forceinline__ void tile_phase_a(const Dev& d, int64_t i, const T* x, T (&qv)[4], int fb, T (&v)[MaxSlot<CD>::V],
-                                             T (&t)[4], int& ac, int& ag, int& lf) {
+__device__ __forceinline__ void tile_phase_a(const Dev& d, int64_t i, int cam, int grp, const T* x, T (&qv)[4],
+                                             T (&v)[MaxSlot<CD>::V], T (&t)[4], int& ac, int& ag) {
   using SL = Slot<FAM, CD>;
   using F = Fam<FAM, CD>;
   const T* rec = (const T*)d.frec[FAM] + i * SL::STRIDE;
@@ -1184,9 +1184,8 @@ __device__ __forceinline__ void tile_phase_a(const Dev& d, int64_t i, const T* x
       v[2 * k] = a.x; v[2 * k + 1] = a.y;
     }
   }
-  lf = d.ffeat[FAM][i] - fb;
-  if constexpr (SL::NC > 0) ac = CD * d.fcam[FAM][i];
-  if constexpr (SL::NG > 0) ag = a_grp(d, F::GT, d.fgrp[FAM][i]);
+  if constexpr (SL::NC > 0) ac = CD * cam;
+  if constexpr (SL::NG > 0) ag = a_grp(d, F::GT, grp);
   T xc[SL::NC > 0 ? SL::NC : 1], xg[SL::NG > 0 ? SL::NG : 1];
 #pragma unroll
   for (int k = 0; k < SL::NC; ++k) xc[k] = x[ac + k];
@@ -1250,19 +1249,16 @@ __device__ __forceinline__ void tile_phase_c_reload(const Dev& d, int64_t i, con
   tile_phase_c<FAM, T, CD>(v, t, ac, ag, sv, y);
 }
 
-// s = (V_f + lambda D_f)^-1 q for feature f (FP32 inverse, or the FP64 one of a flagged block)
-template <typename T, int NF> __device__ __forceinline__ void feature_solve(const Dev& d, int f, const T (&q)[4], T (&s)[4]) {
+// s = (V_f + lambda D_f)^-1 q for feature f from its packed FP32 inverse Mi, or
+// the FP64 one of a flagged block
+template <typename T, int NF>
+__device__ __forceinline__ void feature_solve(const Dev& d, int f, bool flag, const T (&Mi)[10], const T (&q)[4], T (&s)[4]) {
   T qn[NF], sn[NF];
 #pragma unroll
   for (int a = 0; a < NF; ++a) qn[a] = q[a];
-  const uint8_t flag = NF == 3 ? d.flp[f] : d.fll[f];
   if (flag) {
     apply_vinv<T, NF>(d, f, qn, sn);
   } else {
-    const T* M = (const T*)(NF == 3 ? d.Vip : d.Vil) + (NF == 3 ? 6 : 10) * (int64_t)f;
-    T Mi[NF == 3 ? 6 : 10];
-#pragma unroll
-    for (int k = 0; k < (NF == 3 ? 6 : 10); ++k) Mi[k] = M[k];
 #pragma unroll
     for (int a = 0; a < NF; ++a) {
       T acc = 0;
@@ -1290,26 +1286,42 @@ __global__ __launch_bounds__(MV_THREADS) void k_mv_wave(Dev d, const double* don
     const int4 tl = d.tiles[tile];  // (first slot, slots, first feature, -)
     const int fb = tl.z;
     const bool active = lane < tl.y;
-    int fam = 0;
-    int64_t i = 0;
-    if (active) {
-      const uint32_t pk = d.wrec[tl.x + lane];
-      fam = (int)(pk >> 28);
-      i = (int64_t)(pk & 0x0fffffffu);
+    const bool ptile = tile < d.n_ptiles;
+    int4 w4 = make_int4(0, 0, 0, -1);
+    if (active) w4 = d.wrec[tl.x + lane];
+    const int fam = (int)((uint32_t)w4.x >> 28), lf = w4.w;
+    const int64_t i = (int64_t)((uint32_t)w4.x & 0x0fffffffu);
+    // the feature's last lane solves with its inverse: fetched now, beside the record
+    const int next = __shfl_down(lf, 1, 64);
+    const bool last = lf >= 0 && (lane == 63 || next != lf);
+    T Mi[10];
+    bool mflag = false;
+    if (last) {
+      const int f = fb + lf;
+      mflag = (ptile ? d.flp[f] : d.fll[f]) != 0;
+      if (ptile) {
+        const T* M = (const T*)d.Vip + 6 * (int64_t)f;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) Mi[k] = M[k];
+      } else {
+        const T* M = (const T*)d.Vil + 10 * (int64_t)f;
+#pragma unroll
+        for (int k = 0; k < 10; ++k) Mi[k] = M[k];
+      }
     }
     T v[MaxSlot<CD>::V];
     T t[4] = {0, 0, 0, 0};
     T q[4] = {0, 0, 0, 0};
-    int ac = 0, ag = 0, lf = -1;
+    int ac = 0, ag = 0;
     if (active) {
       switch (fam) {
-        case 1: tile_phase_a<1, T, CD>(d, i, x, q, fb, v, t, ac, ag, lf); break;
-        case 2: tile_phase_a<2, T, CD>(d, i, x, q, fb, v, t, ac, ag, lf); break;
-        case 3: tile_phase_a<3, T, CD>(d, i, x, q, fb, v, t, ac, ag, lf); break;
-        case 4: tile_phase_a<4, T, CD>(d, i, x, q, fb, v, t, ac, ag, lf); break;
-        case 5: tile_phase_a<5, T, CD>(d, i, x, q, fb, v, t, ac, ag, lf); break;
-        case 6: tile_phase_a<6, T, CD>(d, i, x, q, fb, v, t, ac, ag, lf); break;
-        case 7: tile_phase_a<7, T, CD>(d, i, x, q, fb, v, t, ac, ag, lf); break;
+        case 1: tile_phase_a<1, T, CD>(d, i, w4.y, w4.z, x, q, v, t, ac, ag); break;
+        case 2: tile_phase_a<2, T, CD>(d, i, w4.y, w4.z, x, q, v, t, ac, ag); break;
+        case 3: tile_phase_a<3, T, CD>(d, i, w4.y, w4.z, x, q, v, t, ac, ag); break;
+        case 4: tile_phase_a<4, T, CD>(d, i, w4.y, w4.z, x, q, v, t, ac, ag); break;
+        case 5: tile_phase_a<5, T, CD>(d, i, w4.y, w4.z, x, q, v, t, ac, ag); break;
+        case 6: tile_phase_a<6, T, CD>(d, i, w4.y, w4.z, x, q, v, t, ac, ag); break;
+        case 7: tile_phase_a<7, T, CD>(d, i, w4.y, w4.z, x, q, v, t, ac, ag); break;
       }
     }
     // segmented inclusive scan over runs of equal lf (lanes are in feature
@@ -1324,13 +1336,11 @@ __global__ __launch_bounds__(MV_THREADS) void k_mv_wave(Dev d, const double* don
         if (take) q[a] += o;
       }
     }
-    const int next = __shfl_down(lf, 1, 64);
-    const bool last = lf >= 0 && (lane == 63 || next != lf);
     const unsigned long long lasts = __ballot(last);
     T s[4] = {0, 0, 0, 0};
     if (last) {
-      if (tile < d.n_ptiles) feature_solve<T, 3>(d, fb + lf, q, s);
-      else feature_solve<T, 4>(d, fb + lf, q, s);
+      if (ptile) feature_solve<T, 3>(d, fb + lf, mflag, Mi, q, s);
+      else feature_solve<T, 4>(d, fb + lf, mflag, Mi, q, s);
     }
     const int src = lf >= 0 ? __builtin_ctzll(lasts & (~0ull << lane)) : lane;
 #pragma unroll
