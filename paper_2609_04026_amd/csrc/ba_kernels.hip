@@ -1325,13 +1325,17 @@ __global__ __launch_bounds__(MV_THREADS) void k_mv_wave(Dev d, const double* don
       }
     }
     // segmented inclusive scan over runs of equal lf (lanes are in feature
-    // order; inactive lanes, lf = -1, come last)
+    // order; inactive lanes, lf = -1, come last); a lane adds the value `off`
+    // lanes back while that lane is in its run
+    const int prev = __shfl_up(lf, 1, 64);
+    const unsigned long long heads = __ballot(lf >= 0 && (lane == 0 || prev != lf));
+    const int start = lf >= 0 ? 63 - __builtin_clzll(heads & ((2ull << lane) - 1ull)) : lane;
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) {
-      const int of = __shfl_up(lf, off, 64);
-      const bool take = lane >= off && of == lf;
+      const bool take = lane - off >= start;
 #pragma unroll
       for (int a = 0; a < 4; ++a) {
+        if (a == 3 && ptile) continue;  // points have 3 components
         const T o = __shfl_up(q[a], off, 64);
         if (take) q[a] += o;
       }
