@@ -690,7 +690,8 @@ void finalize(ba_handle* h) {
   d.scal = A.get<double>(SC_COUNT);
   launch_zero(d.scal, SC_COUNT * sizeof(double), h->stream);
   const int64_t fe_blocks = (h->np + 255) / 256 + (h->nl + 255) / 256;
-  d.red = A.get<double>((size_t)std::max<int64_t>(2 * std::max(max_blocks, fe_blocks), 64));
+  d.n_red_max = std::max<int64_t>(std::max(max_blocks, fe_blocks), 32);
+  d.red = A.get<double>((size_t)(2 * d.n_red_max));
   HIPCHK(hipHostMalloc((void**)&h->hscal, SC_COUNT * sizeof(double), hipHostMallocDefault));
   if (h->gnn) ba_gnn_impl::attach(h->gnn, h->graph);
   check_launch("finalize");

@@ -93,6 +93,7 @@ struct Dev {
   double *mv_part = nullptr;  // n_mv_wg x nA partial sums (LDS mode) or nA accumulator (global mode)
   double *scal = nullptr;   // device scalars, see PcgScal
   double *red = nullptr;    // reduction partials
+  int64_t n_red_max = 0;    // pairs of partials red holds
   int n_mv_wg = 0;          // matvec workgroups (partials rows)
   int mv_lds = 0;           // 1: accumulate in LDS
   // wavefront tiles of the product: int4 (first slot, slots, first feature, 0), point tiles

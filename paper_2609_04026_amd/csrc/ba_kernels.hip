@@ -2244,18 +2244,155 @@ template <typename T, int CD, int NF> __device__ __forceinline__ void backsub_on
   }
 }
 
-template <typename T, int CD> __global__ __launch_bounds__(256) void k_backsub(Dev d, int ptiles) {
+// |J h|^2 of one record given t = J_a h_a and the broadcast h_f (FP64 sum)
+template <int FAM, typename T, int CD>
+__device__ __forceinline__ double bs_record(const T (&v)[MaxSlot<CD>::V], const T (&t)[4], const T (&h)[4]) {
+  using SL = Slot<FAM, CD>;
+  double acc = 0;
+#pragma unroll
+  for (int row = 0; row < SL::ROWS; ++row) {
+    double u = (double)t[row];
+#pragma unroll
+    for (int a = 0; a < SL::NF; ++a) u += (double)v[SL::OF + row * SL::NF + a] * (double)h[a];
+    acc += u * u;
+  }
+  return acc;
+}
+
+template <int FAM, typename T, int CD>
+__device__ __forceinline__ double bs_record_reload(const Dev& d, int64_t i, const T (&t)[4], const T (&h)[4]) {
+  using SL = Slot<FAM, CD>;
+  T v[MaxSlot<CD>::V];
+  const double2* q2 = reinterpret_cast<const double2*>((const T*)d.frec[FAM] + i * SL::STRIDE);
+#pragma unroll
+  for (int k = 0; k < SL::STRIDE / 2; ++k) {
+    double2 a = q2[k];
+    v[2 * k] = a.x; v[2 * k + 1] = a.y;
+  }
+  return bs_record<FAM, T, CD>(v, t, h);
+}
+
+// Back-substitution over the product's wavefront tiles: t = J_a h_a and
+// q_f = sum J_f^T t as in the product, h_f = -(V_f + lambda D_f)^-1 (g_f + q_f) on the
+// feature's last lane, then |J_a h_a + J_f h_f|^2 per record; per-workgroup sums of
+// g_f . h_f and |J h|^2 go to d.red
+template <typename T, int CD> __global__ __launch_bounds__(256) void k_backsub_wave(Dev d) {
   __shared__ double lds[2 * 5];
   const T* x = (const T*)d.xT;
-  double v[2] = {0, 0};
-  if ((int)blockIdx.x < ptiles) {
-    const int f = blockIdx.x * blockDim.x + threadIdx.x;
-    if (f < d.np) backsub_one<T, CD, 3>(d, f, x, v[0], v[1]);
-  } else {
-    const int f = (blockIdx.x - ptiles) * blockDim.x + threadIdx.x;
-    if (f < d.nl) backsub_one<T, CD, 4>(d, f, x, v[0], v[1]);
+  const int lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+  double gh = 0, jh2 = 0;
+  for (int tile = blockIdx.x * nw + (threadIdx.x >> 6); tile < d.n_tiles; tile += gridDim.x * nw) {
+    const int4 tl = d.tiles[tile];
+    const int fb = tl.z;
+    const bool active = lane < tl.y;
+    const bool ptile = tile < d.n_ptiles;
+    int4 w4 = make_int4(0, 0, 0, -1);
+    if (active) w4 = d.wrec[tl.x + lane];
+    const int fam = (int)((uint32_t)w4.x >> 28), lf = w4.w;
+    const int64_t i = (int64_t)((uint32_t)w4.x & 0x0fffffffu);
+    const int next = __shfl_down(lf, 1, 64);
+    const bool last = lf >= 0 && (lane == 63 || next != lf);
+    T Mi[10], g[4] = {0, 0, 0, 0};
+    bool mflag = false;
+    if (last) {
+      const int f = fb + lf;
+      mflag = (ptile ? d.flp[f] : d.fll[f]) != 0;
+      if (ptile) {
+        const T* M = (const T*)d.Vip + 6 * (int64_t)f;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) Mi[k] = M[k];
+        const T* gp = (const T*)d.gp + 3 * (int64_t)f;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) g[k] = gp[k];
+      } else {
+        const T* M = (const T*)d.Vil + 10 * (int64_t)f;
+#pragma unroll
+        for (int k = 0; k < 10; ++k) Mi[k] = M[k];
+        const T* gl = (const T*)d.gl + 4 * (int64_t)f;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) g[k] = gl[k];
+      }
+    }
+    T v[MaxSlot<CD>::V];
+    T t[4] = {0, 0, 0, 0};
+    T q[4] = {0, 0, 0, 0};
+    int ac = 0, ag = 0;
+    if (active) {
+      switch (fam) {
+        case 1: tile_phase_a<1, T, CD>(d, i, w4.y, w4.z, x, q, v, t, ac, ag); break;
+        case 2: tile_phase_a<2, T, CD>(d, i, w4.y, w4.z, x, q, v, t, ac, ag); break;
+        case 3: tile_phase_a<3, T, CD>(d, i, w4.y, w4.z, x, q, v, t, ac, ag); break;
+        case 4: tile_phase_a<4, T, CD>(d, i, w4.y, w4.z, x, q, v, t, ac, ag); break;
+        case 5: tile_phase_a<5, T, CD>(d, i, w4.y, w4.z, x, q, v, t, ac, ag); break;
+        case 6: tile_phase_a<6, T, CD>(d, i, w4.y, w4.z, x, q, v, t, ac, ag); break;
+        case 7: tile_phase_a<7, T, CD>(d, i, w4.y, w4.z, x, q, v, t, ac, ag); break;
+      }
+    }
+    const int prev = __shfl_up(lf, 1, 64);
+    const unsigned long long heads = __ballot(lf >= 0 && (lane == 0 || prev != lf));
+    const int start = lf >= 0 ? 63 - __builtin_clzll(heads & ((2ull << lane) - 1ull)) : lane;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const bool take = lane - off >= start;
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        if (a == 3 && ptile) continue;
+        const T o = __shfl_up(q[a], off, 64);
+        if (take) q[a] += o;
+      }
+    }
+    const unsigned long long lasts = __ballot(last);
+    T h[4] = {0, 0, 0, 0};
+    if (last) {
+      T rhs[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) rhs[a] = -(q[a] + g[a]);
+      const int f = fb + lf;
+      if (ptile) feature_solve<T, 3>(d, f, mflag, Mi, rhs, h);
+      else feature_solve<T, 4>(d, f, mflag, Mi, rhs, h);
+      const int nfa = ptile ? 3 : 4;
+      double* ho = (ptile ? d.hp : d.hl) + (int64_t)nfa * f;
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+        if (a < nfa) {
+          ho[a] = (double)h[a];
+          gh += (double)g[a] * (double)h[a];
+        }
+    }
+    const int src = lf >= 0 ? __builtin_ctzll(lasts & (~0ull << lane)) : lane;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) h[a] = __shfl(h[a], src, 64);
+    if (active) {
+      if constexpr (sizeof(T) == 4) {
+        switch (fam) {
+          case 1: jh2 += bs_record<1, T, CD>(v, t, h); break;
+          case 2: jh2 += bs_record<2, T, CD>(v, t, h); break;
+          case 3: jh2 += bs_record<3, T, CD>(v, t, h); break;
+          case 4: jh2 += bs_record<4, T, CD>(v, t, h); break;
+          case 5: jh2 += bs_record<5, T, CD>(v, t, h); break;
+          case 6: jh2 += bs_record<6, T, CD>(v, t, h); break;
+          case 7: jh2 += bs_record<7, T, CD>(v, t, h); break;
+        }
+      } else {
+        switch (fam) {
+          case 1: jh2 += bs_record_reload<1, T, CD>(d, i, t, h); break;
+          case 2: jh2 += bs_record_reload<2, T, CD>(d, i, t, h); break;
+          case 3: jh2 += bs_record_reload<3, T, CD>(d, i, t, h); break;
+          case 4: jh2 += bs_record_reload<4, T, CD>(d, i, t, h); break;
+          case 5: jh2 += bs_record_reload<5, T, CD>(d, i, t, h); break;
+          case 6: jh2 += bs_record_reload<6, T, CD>(d, i, t, h); break;
+          case 7: jh2 += bs_record_reload<7, T, CD>(d, i, t, h); break;
+        }
+      }
+    }
   }
-  double* o = block_sum_arr<double, 2>(v, lds);
+  // features whose records do not fit one tile: one lane per feature
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < d.n_bigp + d.n_bigl; k += gridDim.x * blockDim.x) {
+    if (k < d.n_bigp) backsub_one<T, CD, 3>(d, d.bigp[k], x, gh, jh2);
+    else backsub_one<T, CD, 4>(d, d.bigl[k - d.n_bigp], x, gh, jh2);
+  }
+  double vals[2] = {gh, jh2};
+  double* o = block_sum_arr<double, 2>(vals, lds);
   if (threadIdx.x == 0) { d.red[2 * blockIdx.x] = o[0]; d.red[2 * blockIdx.x + 1] = o[1]; }
 }
 
@@ -2271,12 +2408,12 @@ __global__ __launch_bounds__(1024) void k_md_final(Dev d, int nparts) {
 }
 
 void launch_backsub(const Dev& d, hipStream_t s) {
-  const int pt = (int)nblk(d.np, 256), lt = (int)nblk(d.nl, 256);
+  const int nwg = (int)std::max<int64_t>(1, std::min<int64_t>(4 * (int64_t)d.n_mv_wg, d.n_red_max));
   BA_DISPATCH_T_CD(d, {
     k_to_T<T><<<nblk(d.nA, 256), 256, 0, s>>>(d.x, d.xT, d.nA);
-    if (pt + lt) k_backsub<T, CD><<<pt + lt, 256, 0, s>>>(d, pt);
+    k_backsub_wave<T, CD><<<nwg, 256, 0, s>>>(d);
   });
-  k_md_final<<<1, 1024, 0, s>>>(d, pt + lt);
+  k_md_final<<<1, 1024, 0, s>>>(d, nwg);
 }
 
 // ---------------------------------------------------------------------------
