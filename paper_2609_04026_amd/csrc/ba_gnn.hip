@@ -210,14 +210,27 @@ __global__ void k_edge_msg(const float* Ph, const float* ex, const float* Wx, co
     const float bc = be[c];
     float acc = 0;
     static_assert(EIN == 8, "edge inputs are read as two float4");
-    for (int e = e0; e < e1; ++e) {
-      float z = Ph[(int64_t)src[e] * H + c] + bc;
+    static_assert(H == 64 && EDGE_RUN <= 64, "one wavefront per run, one lane per channel");
+    // the run's source ids, one per lane, so that the rows Ph[src] are fetched
+    // without waiting on each id in turn (every lane of the wavefront has the same run)
+    const int my_src = c < e1 - e0 ? src[e0 + c] : 0;
+    auto edge = [&](int e, float p) {
       const float4 x0 = reinterpret_cast<const float4*>(ex)[2 * (int64_t)e];
       const float4 x1 = reinterpret_cast<const float4*>(ex)[2 * (int64_t)e + 1];
-      z += x0.x * w[0] + x0.y * w[1] + x0.z * w[2] + x0.w * w[3] + x1.x * w[4] + x1.y * w[5] + x1.z * w[6] + x1.w * w[7];
+      const float z = p + bc + x0.x * w[0] + x0.y * w[1] + x0.z * w[2] + x0.w * w[3] + x1.x * w[4] + x1.y * w[5] +
+                      x1.z * w[6] + x1.w * w[7];
       if (Ze) Ze[(int64_t)e * H + c] = z;
       acc += gelu(z);
+    };
+    int e = e0;
+    for (; e + 4 <= e1; e += 4) {  // four rows of Ph in flight
+      const int s0 = __shfl(my_src, e - e0, 64), s1 = __shfl(my_src, e - e0 + 1, 64);
+      const int s2 = __shfl(my_src, e - e0 + 2, 64), s3 = __shfl(my_src, e - e0 + 3, 64);
+      const float p0 = Ph[(int64_t)s0 * H + c], p1 = Ph[(int64_t)s1 * H + c];
+      const float p2 = Ph[(int64_t)s2 * H + c], p3 = Ph[(int64_t)s3 * H + c];
+      edge(e, p0); edge(e + 1, p1); edge(e + 2, p2); edge(e + 3, p3);
     }
+    for (; e < e1; ++e) edge(e, Ph[(int64_t)__shfl(my_src, e - e0, 64) * H + c]);
     atomicAdd(Mm + (int64_t)node * H + c, acc / (float)(off[node + 1] - off[node]));
   }
 }
