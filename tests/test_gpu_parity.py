@@ -287,6 +287,37 @@ def test_camera_dof6_and_errors():
         BA(s["cameras"], s["points"], s["lines"], s["planes"] * 2, s["vps"], s["cx"], s["cy"])
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_empty_and_feature_free_problems(precision):
+    """Degenerate inputs: a problem without observations (zero cost, a zero
+    reduced right-hand side: the step is rejected with no PCG iteration), and
+    one whose only records are point observations of a single point seen by
+    two cameras (one tile holding a partial wavefront) against the oracle."""
+    from paper_2609_04026_amd.binding import BA
+    s = make_scene(small_config(n_cams=4, n_points=6, n_lines=2), seed=9)
+    ba = BA(s["cameras"], s["points"], s["lines"], s["planes"], s["vps"], s["cx"], s["cy"], precision=precision)
+    rep = ba.lm_step(lambda0=1e-3)
+    assert rep["E_before"] == 0.0 and rep["pcg_iters"] == 0 and rep["accepted"] == 0, rep
+    ba.close()
+    # one point seen by two cameras
+    from scenegen import OBS_POINT
+    a, b, m = s["obs"][OBS_POINT]
+    sel = np.flatnonzero(np.asarray(b) == int(np.asarray(b)[0]))[:2]
+    s1 = dict(s)
+    empty = np.zeros(0, dtype=np.int32)
+    s1["obs"] = {k: (empty, empty, None if v[2] is None else np.asarray(v[2])[:0]) for k, v in s["obs"].items()}
+    s1["obs"][OBS_POINT] = (np.asarray(a)[sel], np.asarray(b)[sel], np.asarray(m)[sel])
+    prob = lm.Problem(s1)
+    lin = lm.linearize(prob, prob.state0())
+    ba = BA.from_scene(s1, precision=precision)
+    rep = ba.lm_step(lambda0=1e-3, pcg_tol=1e-12 if precision == "fp64" else 1e-7, pcg_max_iters=200)
+    h, _ = lm.solve_schur(prob, lin, 1e-3)
+    dL = lm.model_decrease(lin, h)
+    tol = 1e-8 if precision == "fp64" else 1e-4
+    assert abs(rep["model_decrease"] - dL) <= 10 * tol * abs(dL), (rep, dL)
+    ba.close()
+
+
 def test_large_feature_path_matches(monkeypatch):
     """Features whose records exceed a product tile take the one-lane-per-
     feature path; with the tile capacity forced to 8 records most features do,
