@@ -569,6 +569,40 @@ void finalize(ba_handle* h) {
   int32_t* dummy = nullptr;
   cam_major(1, false, d.po_idx, dummy, d.po_off);
   cam_major(2, false, d.lo_idx, dummy, d.lo_off);
+  // camera-major copies of the observation slots and their aligned plane slots
+  for (int pair = 0; pair < 2; ++pair) {
+    const int fo = pair == 0 ? 1 : 2, fp = pair == 0 ? 3 : 4;
+    const auto& v = R[fo];
+    if (v.empty()) continue;
+    std::vector<std::vector<int32_t>> bucket(h->nc);
+    for (size_t i = 0; i < v.size(); ++i) bucket[v[i].cam].push_back((int32_t)i);
+    const int64_t n = (int64_t)v.size(), np_ = (int64_t)R[fp].size();
+    std::vector<int32_t> pos(n), feat(n), al(n, -1), ppos(np_, -1), pgrp;
+    int64_t j = 0, k = 0;
+    for (int c = 0; c < h->nc; ++c)
+      for (int32_t i : bucket[c]) {
+        pos[i] = (int32_t)j;
+        feat[j] = v[i].feat;
+        const int f = v[i].feat;
+        if (np_ && foff_h[fp][f + 1] > foff_h[fp][f]) {  // the point / line is in a plane
+          const int64_t ip = foff_h[fp][f] + (i - foff_h[fo][f]);
+          ppos[ip] = (int32_t)k;
+          al[j] = (int32_t)k;
+          pgrp.push_back(R[fp][ip].grp);
+          ++k;
+        }
+        ++j;
+      }
+    d.cmrec[fo] = A.get<char>((size_t)n * slot_stride(fo, h->CD), TS);
+    d.cmpos[fo] = A.get<int32_t>(n); d.cmfeat[fo] = A.get<int32_t>(n); d.cmal[fo] = A.get<int32_t>(n);
+    upload(h, d.cmpos[fo], pos); upload(h, d.cmfeat[fo], feat); upload(h, d.cmal[fo], al);
+    if (np_) {
+      if (k != np_) throw BaError(BA_E_INVALID, "plane records are not aligned with their observations");
+      d.cmrec[fp] = A.get<char>((size_t)np_ * slot_stride(fp, h->CD), TS);
+      d.cmpos[fp] = A.get<int32_t>(np_); d.cmgrp[fp] = A.get<int32_t>(np_);
+      upload(h, d.cmpos[fp], ppos); upload(h, d.cmgrp[fp], pgrp);
+    }
+  }
   cam_major(6, true, d.px_start, d.px_cnt, d.px_off);
   cam_major(7, true, d.lx_start, d.lx_cnt, d.lx_off);
   // group member lists

@@ -357,6 +357,9 @@ template <int FAM, typename T, int CD> __global__ __launch_bounds__(256) void k_
 #pragma unroll
   for (int k = 0; k < SL::USED; ++k) v[k] = jscale > 0.0 ? v[k] * wsT : T(0);
   store_vec(((T*)d.frec[FAM]) + i * SL::STRIDE, v);
+  if constexpr (FAM <= 4) {
+    if (d.cmrec[FAM]) store_vec(((T*)d.cmrec[FAM]) + (int64_t)d.cmpos[FAM][i] * SL::STRIDE, v);
+  }
 }
 
 void launch_linearize(const Dev& d, hipStream_t s) {
@@ -804,6 +807,21 @@ void launch_camera_pass_a(const Dev& d, hipStream_t s) {
 
 // ---------------------------------------------------------------------------
 // camera pass B: damped diagonal blocks of S and b with pair-summed W_af
+template <int FAM, typename T, int CD, int NF> __device__ __forceinline__ void addW_slot(const T* slot, T (&W)[CD][NF]) {
+  using SL = Slot<FAM, CD>;
+  T v[SL::STRIDE];
+  load_vec(slot, v);
+#pragma unroll
+  for (int row = 0; row < SL::ROWS; ++row) {
+    const T* jc = v + SL::OC + row * SL::NC;
+    const T* jf = v + SL::OF + row * NF;
+#pragma unroll
+    for (int a = 0; a < SL::NC; ++a)
+#pragma unroll
+      for (int b = 0; b < NF; ++b) W[a][b] += jc[a] * jf[b];
+  }
+}
+
 template <int FAM, typename T, int CD, int NF> __device__ __forceinline__ void addW_cam(const Dev& d, int64_t i, T (&W)[CD][NF]) {
   using SL = Slot<FAM, CD>;
   T v[SL::STRIDE];
@@ -865,17 +883,17 @@ template <typename T, int CD> __global__ __launch_bounds__(256) void k_cam_b(Dev
   T* C = acc;
   T* bb = acc + NS;
   if (d.fn[1]) {
+    // observation slot and its aligned plane slot from the camera-major copies
     for (int j = d.po_off[c] + threadIdx.x; j < d.po_off[c + 1]; j += blockDim.x) {
-      const int64_t i = d.po_idx[j];
       T W[CD][3];
 #pragma unroll
       for (int a = 0; a < CD; ++a)
 #pragma unroll
         for (int b = 0; b < 3; ++b) W[a][b] = 0;
-      addW_cam<1, T, CD, 3>(d, i, W);
-      const int64_t i3 = aligned(d, 1, 3, i);
-      if (i3 >= 0) addW_cam<3, T, CD, 3>(d, i3, W);
-      pair_contrib<T, CD, 3>(d, d.ffeat[1][i], W, C, bb);
+      addW_slot<1, T, CD, 3>((const T*)d.cmrec[1] + (int64_t)j * Slot<1, CD>::STRIDE, W);
+      const int k = d.cmal[1][j];
+      if (k >= 0) addW_slot<3, T, CD, 3>((const T*)d.cmrec[3] + (int64_t)k * Slot<3, CD>::STRIDE, W);
+      pair_contrib<T, CD, 3>(d, d.cmfeat[1][j], W, C, bb);
     }
   }
   if (d.fn[6]) {
@@ -892,16 +910,15 @@ template <typename T, int CD> __global__ __launch_bounds__(256) void k_cam_b(Dev
   }
   if (d.fn[2]) {
     for (int j = d.lo_off[c] + threadIdx.x; j < d.lo_off[c + 1]; j += blockDim.x) {
-      const int64_t i = d.lo_idx[j];
       T W[CD][4];
 #pragma unroll
       for (int a = 0; a < CD; ++a)
 #pragma unroll
         for (int b = 0; b < 4; ++b) W[a][b] = 0;
-      addW_cam<2, T, CD, 4>(d, i, W);
-      const int64_t i4 = aligned(d, 2, 4, i);
-      if (i4 >= 0) addW_cam<4, T, CD, 4>(d, i4, W);
-      pair_contrib<T, CD, 4>(d, d.ffeat[2][i], W, C, bb);
+      addW_slot<2, T, CD, 4>((const T*)d.cmrec[2] + (int64_t)j * Slot<2, CD>::STRIDE, W);
+      const int k = d.cmal[2][j];
+      if (k >= 0) addW_slot<4, T, CD, 4>((const T*)d.cmrec[4] + (int64_t)k * Slot<4, CD>::STRIDE, W);
+      pair_contrib<T, CD, 4>(d, d.cmfeat[2][j], W, C, bb);
     }
   }
   if (d.fn[7]) {
@@ -2062,6 +2079,61 @@ __device__ __forceinline__ void sz_grp_rec(const Dev& d, int64_t i, const T* Zr,
     }
 }
 
+// the same for a slot read from the camera-major copy, with its camera, group
+// and feature given
+template <int FAM, typename T, int CD>
+__device__ __forceinline__ void sz_cam_slot(const Dev& d, const T* slot, int cam, int grp, int feat, const T* Zr,
+                                            const T* sf, double (&acc)[CD][SZ_COLS]) {
+  using SL = Slot<FAM, CD>;
+  using F = Fam<FAM, CD>;
+  T v[SL::STRIDE], u[4][SZ_COLS];
+  load_vec(slot, v);
+#pragma unroll
+  for (int row = 0; row < 4; ++row)
+#pragma unroll
+    for (int c = 0; c < SZ_COLS; ++c) u[row][c] = 0;
+  {
+    const T* z = Zr + (int64_t)CD * cam * SZ_COLS;
+#pragma unroll
+    for (int k = 0; k < SL::NC; ++k)
+#pragma unroll
+      for (int c = 0; c < SZ_COLS; ++c) {
+        const T zk = z[k * SZ_COLS + c];
+#pragma unroll
+        for (int row = 0; row < SL::ROWS; ++row) u[row][c] += v[SL::OC + row * SL::NC + k] * zk;
+      }
+  }
+  if constexpr (SL::NG > 0) {
+    const T* z = Zr + (int64_t)a_grp(d, F::GT, grp) * SZ_COLS;
+#pragma unroll
+    for (int k = 0; k < SL::NG; ++k)
+#pragma unroll
+      for (int c = 0; c < SZ_COLS; ++c) {
+        const T zk = z[k * SZ_COLS + c];
+#pragma unroll
+        for (int row = 0; row < SL::ROWS; ++row) u[row][c] += v[SL::OG + row * SL::NG + k] * zk;
+      }
+  }
+  const T* s = sf + (int64_t)feat * SL::NF * SZ_COLS;
+#pragma unroll
+  for (int a = 0; a < SL::NF; ++a)
+#pragma unroll
+    for (int c = 0; c < SZ_COLS; ++c) {
+      const T sa = s[a * SZ_COLS + c];
+#pragma unroll
+      for (int row = 0; row < SL::ROWS; ++row) u[row][c] -= v[SL::OF + row * SL::NF + a] * sa;
+    }
+#pragma unroll
+  for (int k = 0; k < SL::NC; ++k)
+#pragma unroll
+    for (int c = 0; c < SZ_COLS; ++c) {
+      T t = 0;
+#pragma unroll
+      for (int row = 0; row < SL::ROWS; ++row) t += v[SL::OC + row * SL::NC + k] * u[row][c];
+      acc[k][c] += t;
+    }
+}
+
 // output rows of one camera (workgroup per camera): SZ = sum over its records J_c^T u + lambda D Z
 template <typename T, int CD>
 __global__ __launch_bounds__(256) void k_sz_cam(Dev d, const T* Zr, const T* sfp, const T* sfl, int col0, int ncol, double lam) {
@@ -2073,22 +2145,25 @@ __global__ __launch_bounds__(256) void k_sz_cam(Dev d, const T* Zr, const T* sfp
   for (int k = 0; k < CD; ++k)
 #pragma unroll
     for (int q = 0; q < SZ_COLS; ++q) acc[k][q] = 0;
+  // observation slots and their aligned plane slots from the camera-major copies
   if (d.fn[1])
     for (int j = d.po_off[c] + threadIdx.x; j < d.po_off[c + 1]; j += blockDim.x) {
-      const int64_t i = d.po_idx[j];
-      sz_cam_rec<1, T, CD>(d, i, Zr, sfp, acc);
-      const int64_t i3 = aligned(d, 1, 3, i);
-      if (i3 >= 0) sz_cam_rec<3, T, CD>(d, i3, Zr, sfp, acc);
+      const int f = d.cmfeat[1][j];
+      sz_cam_slot<1, T, CD>(d, (const T*)d.cmrec[1] + (int64_t)j * Slot<1, CD>::STRIDE, c, 0, f, Zr, sfp, acc);
+      const int k = d.cmal[1][j];
+      if (k >= 0)
+        sz_cam_slot<3, T, CD>(d, (const T*)d.cmrec[3] + (int64_t)k * Slot<3, CD>::STRIDE, c, d.cmgrp[3][k], f, Zr, sfp, acc);
     }
   if (d.fn[6])
     for (int j = d.px_off[c] + threadIdx.x; j < d.px_off[c + 1]; j += blockDim.x)
       for (int64_t i = d.px_start[j]; i < d.px_start[j] + d.px_cnt[j]; ++i) sz_cam_rec<6, T, CD>(d, i, Zr, sfp, acc);
   if (d.fn[2])
     for (int j = d.lo_off[c] + threadIdx.x; j < d.lo_off[c + 1]; j += blockDim.x) {
-      const int64_t i = d.lo_idx[j];
-      sz_cam_rec<2, T, CD>(d, i, Zr, sfl, acc);
-      const int64_t i4 = aligned(d, 2, 4, i);
-      if (i4 >= 0) sz_cam_rec<4, T, CD>(d, i4, Zr, sfl, acc);
+      const int f = d.cmfeat[2][j];
+      sz_cam_slot<2, T, CD>(d, (const T*)d.cmrec[2] + (int64_t)j * Slot<2, CD>::STRIDE, c, 0, f, Zr, sfl, acc);
+      const int k = d.cmal[2][j];
+      if (k >= 0)
+        sz_cam_slot<4, T, CD>(d, (const T*)d.cmrec[4] + (int64_t)k * Slot<4, CD>::STRIDE, c, d.cmgrp[4][k], f, Zr, sfl, acc);
     }
   if (d.fn[7])
     for (int j = d.lx_off[c] + threadIdx.x; j < d.lx_off[c + 1]; j += blockDim.x)
