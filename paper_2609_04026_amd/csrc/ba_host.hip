@@ -594,11 +594,13 @@ void finalize(ba_handle* h) {
         ++j;
       }
     d.cmrec[fo] = A.get<char>((size_t)n * slot_stride(fo, h->CD), TS);
+    d.cmres[fo] = A.get<char>((size_t)n * fam_rows(fo), TS);
     d.cmpos[fo] = A.get<int32_t>(n); d.cmfeat[fo] = A.get<int32_t>(n); d.cmal[fo] = A.get<int32_t>(n);
     upload(h, d.cmpos[fo], pos); upload(h, d.cmfeat[fo], feat); upload(h, d.cmal[fo], al);
     if (np_) {
       if (k != np_) throw BaError(BA_E_INVALID, "plane records are not aligned with their observations");
       d.cmrec[fp] = A.get<char>((size_t)np_ * slot_stride(fp, h->CD), TS);
+      d.cmres[fp] = A.get<char>((size_t)np_ * fam_rows(fp), TS);
       d.cmpos[fp] = A.get<int32_t>(np_); d.cmgrp[fp] = A.get<int32_t>(np_);
       upload(h, d.cmpos[fp], ppos); upload(h, d.cmgrp[fp], pgrp);
     }

@@ -71,7 +71,7 @@ struct Dev {
   // linearisation: cmpos[fam][i] is record i's position, cmfeat[fam][j] its feature,
   // cmal[fam][j] (fam 1, 2) the position of the aligned plane record or -1, cmgrp the
   // plane of a plane-record position
-  void* cmrec[NFAM] = {nullptr};
+  void *cmrec[NFAM] = {nullptr}, *cmres[NFAM] = {nullptr};  // slots and weighted residuals (T)
   int32_t *cmpos[NFAM] = {nullptr}, *cmfeat[NFAM] = {nullptr}, *cmal[NFAM] = {nullptr}, *cmgrp[NFAM] = {nullptr};
   // group member lists
   int32_t *plp_off = nullptr, *plp = nullptr, *pll_off = nullptr, *pll = nullptr;

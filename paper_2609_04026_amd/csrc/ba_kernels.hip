@@ -353,6 +353,13 @@ template <int FAM, typename T, int CD> __global__ __launch_bounds__(256) void k_
   T* ro = ((T*)d.fres[FAM]) + i * F::ROWS;
 #pragma unroll
   for (int k = 0; k < F::ROWS; ++k) ro[k] = (T)(ws * r64[k]);
+  if constexpr (FAM <= 4) {
+    if (d.cmres[FAM]) {
+      T* rc = ((T*)d.cmres[FAM]) + (int64_t)d.cmpos[FAM][i] * F::ROWS;
+#pragma unroll
+      for (int k = 0; k < F::ROWS; ++k) rc[k] = (T)(ws * r64[k]);
+    }
+  }
   const T wsT = (T)(ws * jscale);
 #pragma unroll
   for (int k = 0; k < SL::USED; ++k) v[k] = jscale > 0.0 ? v[k] * wsT : T(0);
@@ -660,6 +667,24 @@ template <typename T, int NF> __device__ __forceinline__ void load_vinv_full(con
 
 // ---------------------------------------------------------------------------
 // camera pass A: U_cc, g_c (one workgroup per camera)
+template <int FAM, typename T, int CD>
+__device__ __forceinline__ void cam_a_slot(const T* slot, const T* res, T (&U)[CD * (CD + 1) / 2], T (&g)[CD]) {
+  using SL = Slot<FAM, CD>;
+  T v[SL::STRIDE];
+  load_vec(slot, v);
+#pragma unroll
+  for (int row = 0; row < SL::ROWS; ++row) {
+    const T* jc = v + SL::OC + row * SL::NC;
+    const T rr = res[row];
+#pragma unroll
+    for (int a = 0; a < SL::NC; ++a) {
+      g[a] += jc[a] * rr;
+#pragma unroll
+      for (int b = a; b < SL::NC; ++b) U[sym<CD>(a, b)] += jc[a] * jc[b];
+    }
+  }
+}
+
 template <int FAM, typename T, int CD> __device__ __forceinline__ void cam_a_rec(const Dev& d, int64_t i, T (&U)[CD * (CD + 1) / 2], T (&g)[CD]) {
   using SL = Slot<FAM, CD>;
   T v[SL::STRIDE];
@@ -698,11 +723,12 @@ template <typename T, int CD> __global__ __launch_bounds__(256) void k_cam_a(Dev
   T(&U)[NS] = *reinterpret_cast<T(*)[NS]>(acc);
   T(&g)[CD] = *reinterpret_cast<T(*)[CD]>(acc + NS);
   if (d.fn[1]) {
+    // observation slots and their aligned plane slots from the camera-major copies
     for (int j = d.po_off[c] + threadIdx.x; j < d.po_off[c + 1]; j += blockDim.x) {
-      const int64_t i = d.po_idx[j];
-      cam_a_rec<1, T, CD>(d, i, U, g);
-      const int64_t i3 = aligned(d, 1, 3, i);
-      if (i3 >= 0) cam_a_rec<3, T, CD>(d, i3, U, g);
+      cam_a_slot<1, T, CD>((const T*)d.cmrec[1] + (int64_t)j * Slot<1, CD>::STRIDE, (const T*)d.cmres[1] + (int64_t)j * Slot<1, CD>::ROWS, U, g);
+      const int k = d.cmal[1][j];
+      if (k >= 0)
+        cam_a_slot<3, T, CD>((const T*)d.cmrec[3] + (int64_t)k * Slot<3, CD>::STRIDE, (const T*)d.cmres[3] + (int64_t)k * Slot<3, CD>::ROWS, U, g);
     }
   }
   if (d.fn[6]) {
@@ -711,10 +737,10 @@ template <typename T, int CD> __global__ __launch_bounds__(256) void k_cam_a(Dev
   }
   if (d.fn[2]) {
     for (int j = d.lo_off[c] + threadIdx.x; j < d.lo_off[c + 1]; j += blockDim.x) {
-      const int64_t i = d.lo_idx[j];
-      cam_a_rec<2, T, CD>(d, i, U, g);
-      const int64_t i4 = aligned(d, 2, 4, i);
-      if (i4 >= 0) cam_a_rec<4, T, CD>(d, i4, U, g);
+      cam_a_slot<2, T, CD>((const T*)d.cmrec[2] + (int64_t)j * Slot<2, CD>::STRIDE, (const T*)d.cmres[2] + (int64_t)j * Slot<2, CD>::ROWS, U, g);
+      const int k = d.cmal[2][j];
+      if (k >= 0)
+        cam_a_slot<4, T, CD>((const T*)d.cmrec[4] + (int64_t)k * Slot<4, CD>::STRIDE, (const T*)d.cmres[4] + (int64_t)k * Slot<4, CD>::ROWS, U, g);
     }
   }
   if (d.fn[7]) {
