@@ -2026,10 +2026,8 @@ __device__ __forceinline__ void sz_feat_family(const Dev& d, int f, const T* Zr,
   }
 }
 
-// s_f (NF x SZ_COLS, T) of every feature of one kind, one lane per feature
-template <typename T, int CD, int NF> __global__ __launch_bounds__(256) void k_sz_feat(Dev d, const T* Zr, T* sf) {
-  const int f = blockIdx.x * blockDim.x + threadIdx.x;
-  if (f >= (NF == 3 ? d.np : d.nl)) return;
+// s_f (NF x SZ_COLS, T) of one feature, one lane
+template <typename T, int CD, int NF> __device__ __forceinline__ void sz_feature(const Dev& d, int f, const T* Zr, T* sf) {
   T q[NF][SZ_COLS];
 #pragma unroll
   for (int a = 0; a < NF; ++a)
@@ -2052,6 +2050,125 @@ template <typename T, int CD, int NF> __global__ __launch_bounds__(256) void k_s
     apply_vinv<T, NF>(d, f, qc, sc);
 #pragma unroll
     for (int a = 0; a < NF; ++a) sf[((int64_t)f * NF + a) * SZ_COLS + c] = sc[a];
+  }
+}
+
+// features larger than a product tile, one lane per listed feature
+template <typename T, int CD, int NF> __global__ __launch_bounds__(256) void k_sz_feat_big(Dev d, const T* Zr, T* sf, const int32_t* list, int n) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) sz_feature<T, CD, NF>(d, list[k], Zr, sf);
+}
+
+// q[a][c] = sum over rows of J_f[row][a] (J_a Z_r)[row][c] for one record
+template <int FAM, typename T, int CD>
+__device__ __forceinline__ void sz_wave_q(const Dev& d, int64_t i, int cam, int grp, const T* Zr, T (&q)[4][SZ_COLS]) {
+  using SL = Slot<FAM, CD>;
+  using F = Fam<FAM, CD>;
+  T v[SL::STRIDE];
+  load_vec(((const T*)d.frec[FAM]) + i * SL::STRIDE, v);
+  T t[4][SZ_COLS];
+#pragma unroll
+  for (int row = 0; row < 4; ++row)
+#pragma unroll
+    for (int c = 0; c < SZ_COLS; ++c) t[row][c] = 0;
+  if constexpr (SL::NC > 0) {
+    const T* z = Zr + (int64_t)CD * cam * SZ_COLS;
+#pragma unroll
+    for (int k = 0; k < SL::NC; ++k)
+#pragma unroll
+      for (int c = 0; c < SZ_COLS; ++c) {
+        const T zk = z[k * SZ_COLS + c];
+#pragma unroll
+        for (int row = 0; row < SL::ROWS; ++row) t[row][c] += v[SL::OC + row * SL::NC + k] * zk;
+      }
+  }
+  if constexpr (SL::NG > 0) {
+    const T* z = Zr + (int64_t)a_grp(d, F::GT, grp) * SZ_COLS;
+#pragma unroll
+    for (int k = 0; k < SL::NG; ++k)
+#pragma unroll
+      for (int c = 0; c < SZ_COLS; ++c) {
+        const T zk = z[k * SZ_COLS + c];
+#pragma unroll
+        for (int row = 0; row < SL::ROWS; ++row) t[row][c] += v[SL::OG + row * SL::NG + k] * zk;
+      }
+  }
+#pragma unroll
+  for (int a = 0; a < SL::NF; ++a)
+#pragma unroll
+    for (int c = 0; c < SZ_COLS; ++c) {
+      T acc = 0;
+#pragma unroll
+      for (int row = 0; row < SL::ROWS; ++row) acc += v[SL::OF + row * SL::NF + a] * t[row][c];
+      q[a][c] = acc;
+    }
+}
+
+// s_f of every feature over the product's wavefront tiles: one record per lane,
+// the feature sums of J_f^T J_a Z by a segmented scan across the wavefront, the
+// solve on the feature's last lane
+template <typename T, int CD> __global__ __launch_bounds__(256) void k_sz_feat_wave(Dev d, const T* Zr, T* sfp, T* sfl) {
+  const int lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+  for (int tile = blockIdx.x * nw + (threadIdx.x >> 6); tile < d.n_tiles; tile += gridDim.x * nw) {
+    const int4 tl = d.tiles[tile];
+    const int fb = tl.z;
+    const bool active = lane < tl.y;
+    const bool ptile = tile < d.n_ptiles;
+    int4 w4 = make_int4(0, 0, 0, -1);
+    if (active) w4 = d.wrec[tl.x + lane];
+    const int fam = (int)((uint32_t)w4.x >> 28), lf = w4.w;
+    const int64_t i = (int64_t)((uint32_t)w4.x & 0x0fffffffu);
+    T q[4][SZ_COLS];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int c = 0; c < SZ_COLS; ++c) q[a][c] = 0;
+    if (active) {
+      switch (fam) {
+        case 1: sz_wave_q<1, T, CD>(d, i, w4.y, w4.z, Zr, q); break;
+        case 2: sz_wave_q<2, T, CD>(d, i, w4.y, w4.z, Zr, q); break;
+        case 3: sz_wave_q<3, T, CD>(d, i, w4.y, w4.z, Zr, q); break;
+        case 4: sz_wave_q<4, T, CD>(d, i, w4.y, w4.z, Zr, q); break;
+        case 5: sz_wave_q<5, T, CD>(d, i, w4.y, w4.z, Zr, q); break;
+        case 6: sz_wave_q<6, T, CD>(d, i, w4.y, w4.z, Zr, q); break;
+        case 7: sz_wave_q<7, T, CD>(d, i, w4.y, w4.z, Zr, q); break;
+      }
+    }
+    const int prev = __shfl_up(lf, 1, 64);
+    const unsigned long long heads = __ballot(lf >= 0 && (lane == 0 || prev != lf));
+    const int start = lf >= 0 ? 63 - __builtin_clzll(heads & ((2ull << lane) - 1ull)) : lane;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const bool take = lane - off >= start;
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        if (a == 3 && ptile) continue;
+#pragma unroll
+        for (int c = 0; c < SZ_COLS; ++c) {
+          const T o = __shfl_up(q[a][c], off, 64);
+          if (take) q[a][c] += o;
+        }
+      }
+    }
+    const int next = __shfl_down(lf, 1, 64);
+    if (lf >= 0 && (lane == 63 || next != lf)) {
+      const int f = fb + lf;
+      if (ptile) {
+        for (int c = 0; c < SZ_COLS; ++c) {
+          T qc[3] = {q[0][c], q[1][c], q[2][c]}, sc[3];
+          apply_vinv<T, 3>(d, f, qc, sc);
+#pragma unroll
+          for (int a = 0; a < 3; ++a) sfp[((int64_t)f * 3 + a) * SZ_COLS + c] = sc[a];
+        }
+      } else {
+        for (int c = 0; c < SZ_COLS; ++c) {
+          T qc[4] = {q[0][c], q[1][c], q[2][c], q[3][c]}, sc[4];
+          apply_vinv<T, 4>(d, f, qc, sc);
+#pragma unroll
+          for (int a = 0; a < 4; ++a) sfl[((int64_t)f * 4 + a) * SZ_COLS + c] = sc[a];
+        }
+      }
+    }
   }
 }
 
@@ -2257,8 +2374,9 @@ template <typename T, int CD> static void launch_sz(const Dev& d, double lambda,
   for (int col0 = 0; col0 < d.coarse_k; col0 += SZ_COLS) {
     const int ncol = std::min(SZ_COLS, d.coarse_k - col0);
     k_sz_rows<T><<<nblk((int64_t)d.nA * SZ_COLS, 256), 256, 0, s>>>(d, Zr, col0, ncol);
-    if (d.np) k_sz_feat<T, CD, 3><<<nblk(d.np, 256), 256, 0, s>>>(d, Zr, sfp);
-    if (d.nl) k_sz_feat<T, CD, 4><<<nblk(d.nl, 256), 256, 0, s>>>(d, Zr, sfl);
+    if (d.n_tiles) k_sz_feat_wave<T, CD><<<(int)std::min<int64_t>(4 * (int64_t)d.n_mv_wg, nblk(d.n_tiles, 4)), 256, 0, s>>>(d, Zr, sfp, sfl);
+    if (d.n_bigp) k_sz_feat_big<T, CD, 3><<<nblk(d.n_bigp, 256), 256, 0, s>>>(d, Zr, sfp, d.bigp, d.n_bigp);
+    if (d.n_bigl) k_sz_feat_big<T, CD, 4><<<nblk(d.n_bigl, 256), 256, 0, s>>>(d, Zr, sfl, d.bigl, d.n_bigl);
     if (d.nc) k_sz_cam<T, CD><<<d.nc, 256, 0, s>>>(d, Zr, sfp, sfl, col0, ncol, lambda);
     if (d.ng + d.nv) k_sz_grp<T, CD><<<d.ng + d.nv, 256, 0, s>>>(d, Zr, sfp, sfl, col0, ncol, lambda);
   }
