@@ -566,9 +566,16 @@ void finalize(ba_handle* h) {
       upload(h, cnt, fc);
     }
   };
-  int32_t* dummy = nullptr;
-  cam_major(1, false, d.po_idx, dummy, d.po_off);
-  cam_major(2, false, d.lo_idx, dummy, d.lo_off);
+  // per camera, the range of its observations in the camera-major copies below
+  auto cam_offsets = [&](int fam, int32_t*& off) {
+    std::vector<int32_t> o(h->nc + 1, 0);
+    for (const auto& rec : R[fam]) o[rec.cam + 1]++;
+    for (int c = 0; c < h->nc; ++c) o[c + 1] += o[c];
+    off = A.get<int32_t>(o.size());
+    upload(h, off, o);
+  };
+  cam_offsets(1, d.po_off);
+  cam_offsets(2, d.lo_off);
   // camera-major copies of the observation slots and their aligned plane slots
   for (int pair = 0; pair < 2; ++pair) {
     const int fo = pair == 0 ? 1 : 2, fp = pair == 0 ? 3 : 4;

@@ -63,14 +63,14 @@ struct Dev {
   int lkind[NFAM] = {0};
   double lscale[NFAM] = {0}, lweight[NFAM] = {0};
   // camera-major lists
-  int32_t *po_idx = nullptr, *po_off = nullptr, *lo_idx = nullptr, *lo_off = nullptr;
+  int32_t *po_off = nullptr, *lo_off = nullptr;  // per camera: range of its R1 / R2 positions
   int32_t *px_start = nullptr, *px_cnt = nullptr, *px_off = nullptr;
   int32_t *lx_start = nullptr, *lx_cnt = nullptr, *lx_off = nullptr;
-  // camera-major copies of the R1 / R2 slots (position j of po_idx / lo_idx) and of
-  // their aligned R3 / R4 slots (compact, in the same order), written by the
-  // linearisation: cmpos[fam][i] is record i's position, cmfeat[fam][j] its feature,
-  // cmal[fam][j] (fam 1, 2) the position of the aligned plane record or -1, cmgrp the
-  // plane of a plane-record position
+  // camera-major copies, written by the linearisation, of the R1 / R2 slots (cameras in
+  // order, each camera's records in record order) and of their aligned R3 / R4 slots
+  // (compact, in the same order): cmpos[fam][i] is record i's position, cmfeat[fam][j] the
+  // feature at position j, cmal[fam][j] (fam 1, 2) the position of the aligned plane
+  // record or -1, cmgrp[fam][k] (fam 3, 4) the plane of a plane-record position
   void *cmrec[NFAM] = {nullptr}, *cmres[NFAM] = {nullptr};  // slots and weighted residuals (T)
   int32_t *cmpos[NFAM] = {nullptr}, *cmfeat[NFAM] = {nullptr}, *cmal[NFAM] = {nullptr}, *cmgrp[NFAM] = {nullptr};
   // group member lists

@@ -703,15 +703,6 @@ template <int FAM, typename T, int CD> __device__ __forceinline__ void cam_a_rec
   }
 }
 
-// aligned plane record of an observation record (same feature, same camera)
-__device__ __forceinline__ int64_t aligned(const Dev& d, int fam_obs, int fam_pl, int64_t i) {
-  if (!d.fn[fam_pl]) return -1;
-  const int f = d.ffeat[fam_obs][i];
-  const int64_t b = d.foff[fam_pl][f];
-  if (d.foff[fam_pl][f + 1] == b) return -1;
-  return b + (i - d.foff[fam_obs][f]);
-}
-
 template <typename T, int CD> __global__ __launch_bounds__(256) void k_cam_a(Dev d) {
   constexpr int NS = CD * (CD + 1) / 2;
   constexpr int K = NS + CD;
