@@ -109,7 +109,8 @@ typedef struct {
 typedef struct {
   int32_t max_iters;      /* ba_solve: attempts (accepted or rejected); default 100 */
   double func_tol;        /* stop after an accepted step with |dE_pix| / E_pix < func_tol; 1e-6 */
-  double grad_tol;        /* stop when |g|_inf < grad_tol; 1e-10 */
+  double grad_tol;        /* ba_solve: stop, before solving, when a fresh linearisation has
+                             |g|_inf < grad_tol, g = J^T W r over all parameters (0: off); 1e-10 */
   double pcg_tol;         /* PCG stops at |r_k| <= pcg_tol |b|; 1e-6 */
   int32_t pcg_max_iters;  /* 1000 */
   double lambda0;         /* initial Marquardt lambda (used on the first step only); 1e-4 */
@@ -148,6 +149,10 @@ typedef struct {
                                     scaled by rel / 1e-3; a record whose working-precision
                                     Jacobian is not finite has it dropped.  Residuals stay in the
                                     cost. */
+  double grad_inf;               /* |g|_inf of the linearisation this step used: g = J^T W r, the
+                                    gradient of E in the local coordinates of every camera,
+                                    point, line, plane and VP (FP64 for the A side, the working
+                                    precision for the features) */
 } ba_step_report;
 
 typedef struct {

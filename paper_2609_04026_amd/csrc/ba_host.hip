@@ -761,6 +761,7 @@ void linearize_all(ba_handle* h) {
   launch_linearize(h->d, h->stream);
   launch_feature_accum(h->d, h->stream);
   launch_camera_pass_a(h->d, h->stream);
+  launch_grad_inf(h->d, h->stream);
   check_launch("linearize");
   h->need_lin = false;
 }
@@ -939,7 +940,9 @@ ba_solve_options opts_or_default(const ba_solve_options* o) {
   return r;
 }
 
-void do_step(ba_handle* h, const ba_solve_options& o, ba_step_report* rep) {
+// one LM step; with stop_grad > 0, a fresh linearisation whose |g|_inf is below it ends
+// the solve instead (returns false: no step taken, nothing changed but the linearisation)
+bool do_step(ba_handle* h, const ba_solve_options& o, ba_step_report* rep, double stop_grad = 0) {
   set_device(h);
   if (!h->finalized) finalize(h);
   if (h->first_step) {
@@ -956,7 +959,21 @@ void do_step(ba_handle* h, const ba_solve_options& o, ba_step_report* rep) {
   r.lambda = h->lambda;
   record(h, 0);
   const bool relin = h->need_lin;
-  if (relin) linearize_all(h);
+  if (relin) {
+    linearize_all(h);
+    if (stop_grad > 0) {
+      read_scal(h);
+      if (h->hscal[SC_GINF] < stop_grad) {
+        r.grad_inf = h->hscal[SC_GINF];
+        r.n_degenerate = (int)h->hscal[SC_NDEG];
+        r.relinearized = 1;
+        r.E_after = r.E_before;
+        r.Epix_after = r.Epix_before;
+        if (rep) *rep = r;
+        return false;
+      }
+    }
+  }
   record(h, 1);
   assemble_schur(h, h->lambda, o.kappa_max);
   record(h, 2);
@@ -983,6 +1000,7 @@ void do_step(ba_handle* h, const ba_solve_options& o, ba_step_report* rep) {
   r.pcg_rel_residual = bb > 0 ? std::sqrt(rr / bb) : 0.0;
   r.n_fp64_blocks = (int)h->hscal[SC_NFLAG];
   r.n_degenerate = (int)h->hscal[SC_NDEG];
+  r.grad_inf = h->hscal[SC_GINF];
   launch_backsub(h->d, h->stream);
   record(h, 5);
   launch_retract(h->d, h->stream);
@@ -1024,6 +1042,7 @@ void do_step(ba_handle* h, const ba_solve_options& o, ba_step_report* rep) {
     r.ms[BA_PHASE_FEATURE] = 0;  // accumulation is timed with linearisation
   }
   if (rep) *rep = r;
+  return true;
 }
 
 void check_index(const int32_t* v, int64_t n, int hi, const char* what) {
@@ -1148,7 +1167,7 @@ ba_status ba_solve(ba_handle* h, const ba_solve_options* opt, ba_summary* sum) {
     s.E_initial = h->E;
     for (int it = 0; it < o.max_iters; ++it) {
       ba_step_report r;
-      do_step(h, o, &r);
+      if (!do_step(h, o, &r, o.grad_tol)) { s.termination = 1; break; }
       s.iters++;
       s.pcg_iters_total += r.pcg_iters;
       if (r.accepted) {

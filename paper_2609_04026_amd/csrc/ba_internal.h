@@ -126,10 +126,12 @@ enum PcgScal {
   SC_GH, SC_JH2, SC_E, SC_EPIX, SC_NFLAG, SC_MAXIT, SC_BREAK,
   SC_COARSE,  // 1: the coarse correction of the preconditioner is active for this solve
   SC_NDEG,    // records of the current linearisation with a scaled or dropped Jacobian
+  SC_GINF,    // |g|_inf of the current linearisation
   // PCG accumulators, three sets rotated by iteration (k mod 3): p.q, r.r, r.(M r),
   // Z^T r, (S Z)^T (M r)
   SC_ACC = 20, SC_COUNT = 128
 };
+static_assert(SC_GINF < SC_ACC, "single scalars overlap the PCG accumulators");
 // coarse space of the two-level preconditioner: 7 similarity-gauge columns, then the
 // network's columns
 constexpr int COARSE_GAUGE = 7, COARSE_NET = 8, COARSE_K = COARSE_GAUGE + COARSE_NET;
@@ -148,6 +150,7 @@ void launch_cast_params(const Dev& d, bool candidate, hipStream_t s);
 void launch_linearize(const Dev& d, hipStream_t s);
 void launch_cost(const Dev& d, bool candidate, hipStream_t s);           // -> scal[SC_E], scal[SC_EPIX]
 void launch_feature_accum(const Dev& d, hipStream_t s);                  // V_f, g_f, D_f
+void launch_grad_inf(const Dev& d, hipStream_t s);                       // -> scal[SC_GINF]
 void launch_camera_pass_a(const Dev& d, hipStream_t s);                  // U_a, g_a, D_a
 void launch_feature_invert(const Dev& d, double lambda, double kappa_max, hipStream_t s);  // V^-1, s_f, flags
 void launch_camera_pass_b(const Dev& d, double lambda, hipStream_t s);   // S diag blocks, b

@@ -518,6 +518,34 @@ void launch_feature_accum(const Dev& d, hipStream_t s) {
   BA_DISPATCH_T_CD(d, k_feat_accum<T, CD><<<pt + lt, 256, 0, s>>>(d, pt));
 }
 
+// |g|_inf over the whole parameter vector: g_a (FP64), then g_f of points and lines (T).
+// Non-negative doubles order as their bit patterns, and a NaN's pattern is above every
+// finite one and infinity, so a maximum over the patterns also carries a NaN through.
+template <typename T> __global__ void k_grad_inf(Dev d) {
+  const int64_t na = d.nA, np = 3 * (int64_t)d.np, n = na + np + 4 * (int64_t)d.nl;
+  unsigned long long m = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const double v = i < na ? d.gA[i] : i < na + np ? (double)((const T*)d.gp)[i - na] : (double)((const T*)d.gl)[i - na - np];
+    const unsigned long long b = (unsigned long long)__double_as_longlong(fabs(v));
+    m = b > m ? b : m;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const unsigned long long u = __shfl_xor(m, o);
+    m = u > m ? u : m;
+  }
+  if ((threadIdx.x & 63) == 0 && m) atomicMax((unsigned long long*)(d.scal + SC_GINF), m);
+}
+
+void launch_grad_inf(const Dev& d, hipStream_t s) {
+  launch_zero(d.scal + SC_GINF, sizeof(double), s);
+  const int64_t n = d.nA + 3 * (int64_t)d.np + 4 * (int64_t)d.nl;
+  if (!n) return;
+  const unsigned nb = std::min<unsigned>(nblk(n, 256), 1024);
+  if (d.fp64) k_grad_inf<double><<<nb, 256, 0, s>>>(d);
+  else k_grad_inf<float><<<nb, 256, 0, s>>>(d);
+}
+
 // damped inverse of one feature block; FP32 blocks whose Cholesky fails or
 // whose estimated condition exceeds kappa_max are redone in FP64 from the
 // stored Jacobians

@@ -32,3 +32,32 @@ def test_binding_signatures_cover_the_header():
     src = open(binding.__file__).read()
     missing = [n for n in declared_functions() if f'"{n}"' not in src]
     assert not missing, missing
+
+
+def test_binding_structures_match_the_header(tmp_path):
+    """Every ctypes structure of the binding has the size and field offsets
+    that a C compiler gives the header's struct of the same name."""
+    import shutil
+    import subprocess
+    import pytest
+    from paper_2609_04026_amd import binding
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc is not available")
+    structs = {"ba_loss": binding.Loss, "ba_problem_desc": binding.ProblemDesc,
+               "ba_solve_options": binding.SolveOptions, "ba_step_report": binding.StepReport,
+               "ba_summary": binding.Summary, "ba_gnn_batch": binding.GnnBatch}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "ba.h"', "int main(void) {"]
+    expect = []
+    for cname, cls in structs.items():
+        lines.append(f'printf("%zu\\n", sizeof({cname}));')
+        expect.append(ctypes.sizeof(cls))
+        for f, _ in cls._fields_:
+            lines.append(f'printf("%zu\\n", offsetof({cname}, {f.rstrip("_")}));')
+            expect.append(getattr(cls, f).offset)
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = [int(v) for v in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()]
+    assert got == expect

@@ -151,6 +151,30 @@ def test_one_lm_step_matches_exact_schur_step(case, precision):
     dL = lm.model_decrease(lin, h)
     assert abs(rep["model_decrease"] - dL) <= 10 * tol * abs(dL)
     assert rep["accepted"] == 1
+    g = np.max(np.abs(lin.g))
+    assert abs(rep["grad_inf"] - g) <= (1e-9 if precision == "fp64" else 1e-4) * g, (rep["grad_inf"], g)
+    ba.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_solve_stops_on_gradient_tolerance(case, precision):
+    """ba_solve ends before solving once a fresh linearisation has
+    |g|_inf < grad_tol (termination 1), leaving the parameters as they were."""
+    name, s, prob, st, lin = case
+    g = np.max(np.abs(lin.g))
+    BA = _ba()
+    ba = BA.from_scene(s, precision=precision)
+    before = ba.get_parameters()
+    out = ba.solve(grad_tol=2.0 * g, max_iters=5)
+    assert out["termination"] == 1 and out["converged"] and out["iters"] == 0, out
+    assert out["E_final"] == out["E_initial"]
+    after = ba.get_parameters()
+    for k in before:
+        assert np.array_equal(before[k], after[k]), k
+    ba.close()
+    ba = BA.from_scene(s, precision=precision)
+    out = ba.solve(grad_tol=0.5 * g, max_iters=3)
+    assert out["iters"] >= 1 and out["E_final"] < out["E_initial"], out
     ba.close()
 
 
