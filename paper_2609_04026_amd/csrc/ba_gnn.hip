@@ -84,14 +84,18 @@ __device__ __forceinline__ uint16_t f2bf(float f) {  // round to nearest even
 }
 __device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
 
-__device__ __forceinline__ float gelu(float x) {
-  const float c = 0.7978845608028654f;
-  return 0.5f * x * (1.0f + tanhf(c * (x + 0.044715f * x * x * x)));
+// (1 + tanh(y)) / 2 is the logistic function of 2y, so gelu(x) = x / (1 + e^(-2y)) and
+// gelu'(x) = s + 2 x s (1 - s) y'(x) with s = 1 / (1 + e^(-2y)): one hardware exp2 and one
+// reciprocal per value (e^(-2y) overflows to inf for large negative x, giving s = 0)
+__device__ __forceinline__ float gelu_s(float x) {
+  const float c = 0.7978845608028654f, k = -2.0f * 1.4426950408889634f;  // -2 log2(e)
+  const float y = c * (x + 0.044715f * x * x * x);
+  return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(k * y));
 }
+__device__ __forceinline__ float gelu(float x) { return x * gelu_s(x); }
 __device__ __forceinline__ float gelu_d(float x) {
-  const float c = 0.7978845608028654f;
-  const float t = tanhf(c * (x + 0.044715f * x * x * x));
-  return 0.5f * (1.0f + t) + 0.5f * x * (1.0f - t * t) * c * (1.0f + 3.0f * 0.044715f * x * x);
+  const float c = 0.7978845608028654f, s = gelu_s(x);
+  return s + 2.0f * x * s * (1.0f - s) * c * (1.0f + 3.0f * 0.044715f * x * x);
 }
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));

@@ -659,9 +659,9 @@ void finalize(ba_handle* h) {
   d.SZc = A.get<double>((size_t)COARSE_K * nA);
   d.Einv = A.get<double>((size_t)COARSE_K * COARSE_K);
   d.Ztb = A.get<double>((size_t)COARSE_K + COARSE_K * COARSE_K);
-  d.szr = A.get<char>((size_t)nA * 8, TS);
-  d.szfp = A.get<char>((size_t)h->np * 3 * 8, TS);
-  d.szfl = A.get<char>((size_t)h->nl * 4 * 8, TS);
+  d.szr = A.get<char>((size_t)nA * SZ_COLS * SZ_PANELS, TS);
+  d.szfp = A.get<char>((size_t)h->np * 3 * SZ_COLS * SZ_PANELS, TS);
+  d.szfl = A.get<char>((size_t)h->nl * 4 * SZ_COLS * SZ_PANELS, TS);
   // product tiles: runs of consecutive features with at most MV_TILE records over
   // all their families, one slot per record in feature order: (family << 28 | record,
   // camera, group, feature - first feature of the tile)

@@ -135,6 +135,10 @@ static_assert(SC_GINF < SC_ACC, "single scalars overlap the PCG accumulators");
 // coarse space of the two-level preconditioner: 7 similarity-gauge columns, then the
 // network's columns
 constexpr int COARSE_GAUGE = 7, COARSE_NET = 8, COARSE_K = COARSE_GAUGE + COARSE_NET;
+// the coarse columns in the S Z sweeps (Z rows, s_f) are stored in panels of SZ_COLS
+// columns, row-major within a panel
+constexpr int SZ_COLS = 8, SZ_PANELS = 2;
+static_assert(COARSE_K <= SZ_COLS * SZ_PANELS, "coarse columns per S Z panel set");
 // With FP32 records the product resolves S Z only to ~1e-7 |S| |Z|, while on the
 // near-null (gauge) directions S Z ~ lambda D_A Z: below this damping the coarse
 // matrix E is not resolved, and the FP32 path preconditions with block-Jacobi alone.

@@ -1975,21 +1975,31 @@ void launch_gauge_basis(const Dev& d, hipStream_t s) {
   if (nb > 0) k_gauge_basis<<<nblk(nb, 64), 64, 0, s>>>(d);
 }
 
-// ---- S Z for up to 8 coarse columns in three sweeps over the records --------
+// ---- S Z for the coarse columns ---------------------------------------------
 // S x = sum_r J_a,r^T (J_a,r x - J_f,r s_f) + lambda D_a x, s_f = V_f^-1 sum_{r in f} J_f,r^T J_a,r x
-// feature sweep: s_f for every column; camera / group sweeps: each workgroup owns one
-// block of the output and walks the records that touch it (no atomics)
-constexpr int SZ_COLS = 8;
+// Z rows and s_f are stored in panels of SZ_COLS columns (row-major in a panel).  Feature
+// sweep, one panel per launch: s_f over the product's wavefront tiles.  Camera / group
+// sweeps, all columns in one launch: a workgroup per camera / group owns that block of the
+// output (no atomics), and each of its records is taken by SZ_LANES lanes per panel.
+// Two lanes of four columns each balance the slot loads, repeated on every lane of a
+// record, against the registers of the FP64 sums (1M-point scene, 15 columns: 1, 2, 4, 8
+// lanes per panel gave 4.9, 4.2, 4.3, 5.1 ms for the preconditioner set-up).
+constexpr int SZ_LANES = 2;
+struct SzPanels {
+  int64_t z, p, l;  // panel strides of Z rows, point s_f, line s_f
+};
+__host__ __device__ inline SzPanels sz_panels(const Dev& d) { return {(int64_t)d.nA * SZ_COLS, (int64_t)d.np * 3 * SZ_COLS, (int64_t)d.nl * 4 * SZ_COLS}; }
 
-// Z rows in T for one sweep: Zr[e][c] = Z[col0 + c][e]
-template <typename T> __global__ void k_sz_rows(Dev d, T* Zr, int col0, int ncol) {
+// Z rows in T: Zr[c / SZ_COLS][e][c % SZ_COLS] = Z[c][e], zero beyond the active columns
+template <typename T> __global__ void k_sz_rows(Dev d, T* Zr) {
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (t >= (int64_t)d.nA * SZ_COLS) return;
-  const int e = (int)(t / SZ_COLS), c = (int)(t % SZ_COLS);
-  Zr[t] = c < ncol ? (T)d.Zc[(int64_t)(col0 + c) * d.nA + e] : (T)0;
+  const int64_t panel = (int64_t)d.nA * SZ_COLS;
+  if (t >= panel * SZ_PANELS) return;
+  const int c = (int)(t / panel) * SZ_COLS + (int)(t % SZ_COLS), e = (int)((t % panel) / SZ_COLS);
+  Zr[t] = c < d.coarse_k ? (T)d.Zc[(int64_t)c * d.nA + e] : (T)0;
 }
 
-// t[row][c] = (J_a Z_r)[row][c] for one record
+// t[row][c] = (J_a Z_r)[row][c] for one record (Zr: one panel)
 template <int FAM, typename T, int CD>
 __device__ __forceinline__ void sz_record_t(const Dev& d, int64_t i, const T* Zr, const T (&v)[Slot<FAM, CD>::STRIDE],
                                             T (&t)[4][SZ_COLS]) {
@@ -2045,7 +2055,7 @@ __device__ __forceinline__ void sz_feat_family(const Dev& d, int f, const T* Zr,
   }
 }
 
-// s_f (NF x SZ_COLS, T) of one feature, one lane
+// s_f (NF x SZ_COLS, T) of one feature, one lane (Zr, sf: one panel)
 template <typename T, int CD, int NF> __device__ __forceinline__ void sz_feature(const Dev& d, int f, const T* Zr, T* sf) {
   T q[NF][SZ_COLS];
 #pragma unroll
@@ -2125,7 +2135,7 @@ __device__ __forceinline__ void sz_wave_q(const Dev& d, int64_t i, int cam, int 
 
 // s_f of every feature over the product's wavefront tiles: one record per lane,
 // the feature sums of J_f^T J_a Z by a segmented scan across the wavefront, the
-// solve on the feature's last lane
+// solve on the feature's last lane (Zr, sfp, sfl: one panel)
 template <typename T, int CD> __global__ __launch_bounds__(256) void k_sz_feat_wave(Dev d, const T* Zr, T* sfp, T* sfl) {
   const int lane = threadIdx.x & 63, nw = blockDim.x >> 6;
   for (int tile = blockIdx.x * nw + (threadIdx.x >> 6); tile < d.n_tiles; tile += gridDim.x * nw) {
@@ -2191,214 +2201,230 @@ template <typename T, int CD> __global__ __launch_bounds__(256) void k_sz_feat_w
   }
 }
 
-// u = J_a Z - J_f s_f of one record (rows x SZ_COLS)
-template <int FAM, typename T, int CD>
-__device__ __forceinline__ void sz_record_u(const Dev& d, int64_t i, const T* Zr, const T* sf, T (&v)[Slot<FAM, CD>::STRIDE],
-                                            T (&u)[4][SZ_COLS]) {
-  using SL = Slot<FAM, CD>;
-  load_vec(((const T*)d.frec[FAM]) + i * SL::STRIDE, v);
-  sz_record_t<FAM, T, CD>(d, i, Zr, v, u);
-  const T* s = sf + (int64_t)d.ffeat[FAM][i] * SL::NF * SZ_COLS;
+// CPL consecutive columns of N rows of Z from row e0 (Zr: the panel, offset to the first
+// of the columns)
+template <int N, int CPL, typename T> __device__ __forceinline__ void z_cols(const T* Zr, int e0, T (&z)[N][CPL]) {
 #pragma unroll
-  for (int a = 0; a < SL::NF; ++a)
+  for (int k = 0; k < N; ++k)
 #pragma unroll
-    for (int c = 0; c < SZ_COLS; ++c) {
-      const T sa = s[a * SZ_COLS + c];
-#pragma unroll
-      for (int row = 0; row < SL::ROWS; ++row) u[row][c] -= v[SL::OF + row * SL::NF + a] * sa;
-    }
+    for (int c = 0; c < CPL; ++c) z[k][c] = Zr[(int64_t)(e0 + k) * SZ_COLS + c];
 }
 
-template <int FAM, typename T, int CD>
-__device__ __forceinline__ void sz_cam_rec(const Dev& d, int64_t i, const T* Zr, const T* sf, double (&acc)[CD][SZ_COLS]) {
+// one record, CPL columns: u = J_a z - J_f s_f (s: the feature's s_f at the first column),
+// then the camera (OUT 0) or group (OUT 1) rows of J^T u added to acc
+template <int FAM, int OUT, typename T, int CD, int NO, int CPL>
+__device__ __forceinline__ void sz_rec_cols(const T* slot, const T (&zc)[CD][CPL], const T (&zg)[3][CPL], const T* s,
+                                            double (&acc)[NO][CPL]) {
   using SL = Slot<FAM, CD>;
-  T v[SL::STRIDE], u[4][SZ_COLS];
-  sz_record_u<FAM, T, CD>(d, i, Zr, sf, v, u);
-#pragma unroll
-  for (int k = 0; k < SL::NC; ++k)
-#pragma unroll
-    for (int c = 0; c < SZ_COLS; ++c) {
-      T s = 0;
-#pragma unroll
-      for (int row = 0; row < SL::ROWS; ++row) s += v[SL::OC + row * SL::NC + k] * u[row][c];
-      acc[k][c] += s;
-    }
-}
-
-template <int FAM, typename T, int CD, int NG>
-__device__ __forceinline__ void sz_grp_rec(const Dev& d, int64_t i, const T* Zr, const T* sf, double (&acc)[NG][SZ_COLS]) {
-  using SL = Slot<FAM, CD>;
-  T v[SL::STRIDE], u[4][SZ_COLS];
-  sz_record_u<FAM, T, CD>(d, i, Zr, sf, v, u);
-#pragma unroll
-  for (int k = 0; k < NG; ++k)
-#pragma unroll
-    for (int c = 0; c < SZ_COLS; ++c) {
-      T s = 0;
-#pragma unroll
-      for (int row = 0; row < SL::ROWS; ++row) s += v[SL::OG + row * NG + k] * u[row][c];
-      acc[k][c] += s;
-    }
-}
-
-// the same for a slot read from the camera-major copy, with its camera, group
-// and feature given
-template <int FAM, typename T, int CD>
-__device__ __forceinline__ void sz_cam_slot(const Dev& d, const T* slot, int cam, int grp, int feat, const T* Zr,
-                                            const T* sf, double (&acc)[CD][SZ_COLS]) {
-  using SL = Slot<FAM, CD>;
-  using F = Fam<FAM, CD>;
-  T v[SL::STRIDE], u[4][SZ_COLS];
+  static_assert(NO >= (OUT == 0 ? SL::NC : SL::NG), "output rows");
+  T v[SL::STRIDE];
   load_vec(slot, v);
-#pragma unroll
-  for (int row = 0; row < 4; ++row)
-#pragma unroll
-    for (int c = 0; c < SZ_COLS; ++c) u[row][c] = 0;
-  {
-    const T* z = Zr + (int64_t)CD * cam * SZ_COLS;
-#pragma unroll
-    for (int k = 0; k < SL::NC; ++k)
-#pragma unroll
-      for (int c = 0; c < SZ_COLS; ++c) {
-        const T zk = z[k * SZ_COLS + c];
-#pragma unroll
-        for (int row = 0; row < SL::ROWS; ++row) u[row][c] += v[SL::OC + row * SL::NC + k] * zk;
-      }
-  }
-  if constexpr (SL::NG > 0) {
-    const T* z = Zr + (int64_t)a_grp(d, F::GT, grp) * SZ_COLS;
-#pragma unroll
-    for (int k = 0; k < SL::NG; ++k)
-#pragma unroll
-      for (int c = 0; c < SZ_COLS; ++c) {
-        const T zk = z[k * SZ_COLS + c];
-#pragma unroll
-        for (int row = 0; row < SL::ROWS; ++row) u[row][c] += v[SL::OG + row * SL::NG + k] * zk;
-      }
-  }
-  const T* s = sf + (int64_t)feat * SL::NF * SZ_COLS;
+  T sf[SL::NF][CPL];
 #pragma unroll
   for (int a = 0; a < SL::NF; ++a)
 #pragma unroll
-    for (int c = 0; c < SZ_COLS; ++c) {
-      const T sa = s[a * SZ_COLS + c];
+    for (int c = 0; c < CPL; ++c) sf[a][c] = s[a * SZ_COLS + c];
+  T u[SL::ROWS][CPL];
 #pragma unroll
-      for (int row = 0; row < SL::ROWS; ++row) u[row][c] -= v[SL::OF + row * SL::NF + a] * sa;
-    }
+  for (int row = 0; row < SL::ROWS; ++row)
 #pragma unroll
-  for (int k = 0; k < SL::NC; ++k)
-#pragma unroll
-    for (int c = 0; c < SZ_COLS; ++c) {
+    for (int c = 0; c < CPL; ++c) {
       T t = 0;
 #pragma unroll
-      for (int row = 0; row < SL::ROWS; ++row) t += v[SL::OC + row * SL::NC + k] * u[row][c];
-      acc[k][c] += t;
+      for (int k = 0; k < SL::NC; ++k) t += v[SL::OC + row * SL::NC + k] * zc[k][c];
+#pragma unroll
+      for (int k = 0; k < SL::NG; ++k) t += v[SL::OG + row * SL::NG + k] * zg[k][c];
+#pragma unroll
+      for (int a = 0; a < SL::NF; ++a) t -= v[SL::OF + row * SL::NF + a] * sf[a][c];
+      u[row][c] = t;
+    }
+  constexpr int NK = OUT == 0 ? SL::NC : SL::NG, O = OUT == 0 ? SL::OC : SL::OG;
+#pragma unroll
+  for (int k = 0; k < NK; ++k)
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) {
+      T t = 0;
+#pragma unroll
+      for (int row = 0; row < SL::ROWS; ++row) t += v[O + row * NK + k] * u[row][c];
+      acc[k][c] += (double)t;
     }
 }
 
-// output rows of one camera (workgroup per camera): SZ = sum over its records J_c^T u + lambda D Z
-template <typename T, int CD>
-__global__ __launch_bounds__(256) void k_sz_cam(Dev d, const T* Zr, const T* sfp, const T* sfl, int col0, int ncol, double lam) {
-  constexpr int NV = CD * SZ_COLS;
-  __shared__ double lds[5 * NV];
-  const int c = blockIdx.x;
-  double acc[CD][SZ_COLS];  // FP64: the gauge columns of S Z are small differences of large sums
+// sum of acc over the lanes of a 256-thread workgroup that hold the same columns (lane
+// mod L, L lanes per record), then out(row, column, sum) on the first NO * L * CPL threads
+template <int NO, int L, int CPL, typename Out>
+__device__ __forceinline__ void sz_block_sum(double (&acc)[NO][CPL], double* lds, Out out) {
+  constexpr int NCOL = L * CPL;
+#pragma unroll
+  for (int k = 0; k < NO; ++k)
+#pragma unroll
+    for (int c = 0; c < CPL; ++c)
+#pragma unroll
+      for (int o = L; o < 64; o <<= 1) acc[k][c] += __shfl_xor(acc[k][c], o, 64);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  if (l < L)
+#pragma unroll
+    for (int k = 0; k < NO; ++k)
+#pragma unroll
+      for (int c = 0; c < CPL; ++c) lds[(w * NO + k) * NCOL + l * CPL + c] = acc[k][c];
+  __syncthreads();
+  for (int t = threadIdx.x; t < NO * NCOL; t += blockDim.x)
+    out(t / NCOL, t % NCOL, lds[t] + lds[NO * NCOL + t] + lds[2 * NO * NCOL + t] + lds[3 * NO * NCOL + t]);
+}
+
+// output rows of one camera (workgroup of 256 per camera): S Z = sum over its records
+// J_c^T u + lambda D Z.  L lanes per record, CPL columns per lane.
+template <typename T, int CD, int L, int CPL>
+__global__ __launch_bounds__(256) void k_sz_cam(Dev d, const T* Zr, const T* sfp, const T* sfl, double lam) {
+  constexpr int R = 256 / L, NCOL = L * CPL;
+  static_assert(SZ_COLS % CPL == 0, "a lane's columns lie in one panel");
+  __shared__ double lds[4 * CD * NCOL];
+  const int c = blockIdx.x, col = (threadIdx.x % L) * CPL, rs = threadIdx.x / L;
+  const SzPanels P = sz_panels(d);
+  const int pn = col / SZ_COLS, pc = col % SZ_COLS;
+  const T* zr = Zr + pn * P.z + pc;
+  const T* sp = sfp + pn * P.p + pc;
+  const T* sl = sfl + pn * P.l + pc;
+  T zc[CD][CPL], z0[3][CPL];
+  z_cols<CD, CPL>(zr, CD * c, zc);
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+#pragma unroll
+    for (int q = 0; q < CPL; ++q) z0[k][q] = 0;
+  double acc[CD][CPL];
 #pragma unroll
   for (int k = 0; k < CD; ++k)
 #pragma unroll
-    for (int q = 0; q < SZ_COLS; ++q) acc[k][q] = 0;
+    for (int q = 0; q < CPL; ++q) acc[k][q] = 0;
   // observation slots and their aligned plane slots from the camera-major copies
   if (d.fn[1])
-    for (int j = d.po_off[c] + threadIdx.x; j < d.po_off[c + 1]; j += blockDim.x) {
+    for (int j = d.po_off[c] + rs; j < d.po_off[c + 1]; j += R) {
       const int f = d.cmfeat[1][j];
-      sz_cam_slot<1, T, CD>(d, (const T*)d.cmrec[1] + (int64_t)j * Slot<1, CD>::STRIDE, c, 0, f, Zr, sfp, acc);
+      sz_rec_cols<1, 0, T, CD>((const T*)d.cmrec[1] + (int64_t)j * Slot<1, CD>::STRIDE, zc, z0, sp + (int64_t)f * 3 * SZ_COLS, acc);
       const int k = d.cmal[1][j];
-      if (k >= 0)
-        sz_cam_slot<3, T, CD>(d, (const T*)d.cmrec[3] + (int64_t)k * Slot<3, CD>::STRIDE, c, d.cmgrp[3][k], f, Zr, sfp, acc);
+      if (k >= 0) {
+        T zg[3][CPL];
+        z_cols<3, CPL>(zr, a_grp(d, Fam<3, CD>::GT, d.cmgrp[3][k]), zg);
+        sz_rec_cols<3, 0, T, CD>((const T*)d.cmrec[3] + (int64_t)k * Slot<3, CD>::STRIDE, zc, zg, sp + (int64_t)f * 3 * SZ_COLS, acc);
+      }
     }
   if (d.fn[6])
-    for (int j = d.px_off[c] + threadIdx.x; j < d.px_off[c + 1]; j += blockDim.x)
-      for (int64_t i = d.px_start[j]; i < d.px_start[j] + d.px_cnt[j]; ++i) sz_cam_rec<6, T, CD>(d, i, Zr, sfp, acc);
+    for (int j = d.px_off[c] + rs; j < d.px_off[c + 1]; j += R)
+      for (int64_t i = d.px_start[j]; i < d.px_start[j] + d.px_cnt[j]; ++i)
+        sz_rec_cols<6, 0, T, CD>((const T*)d.frec[6] + i * Slot<6, CD>::STRIDE, zc, z0, sp + (int64_t)d.ffeat[6][i] * 3 * SZ_COLS, acc);
   if (d.fn[2])
-    for (int j = d.lo_off[c] + threadIdx.x; j < d.lo_off[c + 1]; j += blockDim.x) {
+    for (int j = d.lo_off[c] + rs; j < d.lo_off[c + 1]; j += R) {
       const int f = d.cmfeat[2][j];
-      sz_cam_slot<2, T, CD>(d, (const T*)d.cmrec[2] + (int64_t)j * Slot<2, CD>::STRIDE, c, 0, f, Zr, sfl, acc);
+      sz_rec_cols<2, 0, T, CD>((const T*)d.cmrec[2] + (int64_t)j * Slot<2, CD>::STRIDE, zc, z0, sl + (int64_t)f * 4 * SZ_COLS, acc);
       const int k = d.cmal[2][j];
-      if (k >= 0)
-        sz_cam_slot<4, T, CD>(d, (const T*)d.cmrec[4] + (int64_t)k * Slot<4, CD>::STRIDE, c, d.cmgrp[4][k], f, Zr, sfl, acc);
+      if (k >= 0) {
+        T zg[3][CPL];
+        z_cols<3, CPL>(zr, a_grp(d, Fam<4, CD>::GT, d.cmgrp[4][k]), zg);
+        sz_rec_cols<4, 0, T, CD>((const T*)d.cmrec[4] + (int64_t)k * Slot<4, CD>::STRIDE, zc, zg, sl + (int64_t)f * 4 * SZ_COLS, acc);
+      }
     }
   if (d.fn[7])
-    for (int j = d.lx_off[c] + threadIdx.x; j < d.lx_off[c + 1]; j += blockDim.x)
-      for (int64_t i = d.lx_start[j]; i < d.lx_start[j] + d.lx_cnt[j]; ++i) sz_cam_rec<7, T, CD>(d, i, Zr, sfl, acc);
-  double* o = block_sum_arr<double, NV>(reinterpret_cast<double(&)[NV]>(acc), lds);
-  for (int k = threadIdx.x; k < NV; k += blockDim.x) {
-    const int row = k / SZ_COLS, col = k % SZ_COLS;
-    if (col >= ncol) continue;
+    for (int j = d.lx_off[c] + rs; j < d.lx_off[c + 1]; j += R)
+      for (int64_t i = d.lx_start[j]; i < d.lx_start[j] + d.lx_cnt[j]; ++i)
+        sz_rec_cols<7, 0, T, CD>((const T*)d.frec[7] + i * Slot<7, CD>::STRIDE, zc, z0, sl + (int64_t)d.ffeat[7][i] * 4 * SZ_COLS, acc);
+  sz_block_sum<CD, L, CPL>(acc, lds, [&](int row, int cc, double s) {
+    if (cc >= d.coarse_k) return;
     const int e = CD * c + row;
-    d.SZc[(int64_t)(col0 + col) * d.nA + e] = (double)o[k] + lam * d.DA[e] * d.Zc[(int64_t)(col0 + col) * d.nA + e];
-  }
+    d.SZc[(int64_t)cc * d.nA + e] = s + lam * d.DA[e] * d.Zc[(int64_t)cc * d.nA + e];
+  });
 }
 
-// output rows of one plane or VP (workgroup per group)
-template <typename T, int CD>
-__global__ __launch_bounds__(256) void k_sz_grp(Dev d, const T* Zr, const T* sfp, const T* sfl, int col0, int ncol, double lam) {
-  __shared__ double lds[5 * 3 * SZ_COLS];
+// output rows of one plane or VP (workgroup of 256 per group)
+template <typename T, int CD, int L, int CPL>
+__global__ __launch_bounds__(256) void k_sz_grp(Dev d, const T* Zr, const T* sfp, const T* sfl, double lam) {
+  constexpr int R = 256 / L, NCOL = L * CPL;
+  __shared__ double lds[4 * 3 * NCOL];
+  const int col = (threadIdx.x % L) * CPL, rs = threadIdx.x / L;
+  const SzPanels P = sz_panels(d);
+  const int pn = col / SZ_COLS, pc = col % SZ_COLS;
+  const T* zr = Zr + pn * P.z + pc;
+  const T* sp = sfp + pn * P.p + pc;
+  const T* sl = sfl + pn * P.l + pc;
   if ((int)blockIdx.x < d.ng) {
-    const int g = blockIdx.x;
-    double acc[3][SZ_COLS];
+    const int g = blockIdx.x, e0 = a_grp(d, 1, g);
+    T zg[3][CPL];
+    z_cols<3, CPL>(zr, e0, zg);
+    double acc[3][CPL];
 #pragma unroll
     for (int k = 0; k < 3; ++k)
 #pragma unroll
-      for (int q = 0; q < SZ_COLS; ++q) acc[k][q] = 0;
+      for (int q = 0; q < CPL; ++q) acc[k][q] = 0;
     if (d.fn[3])
-      for (int j = d.plp_off[g] + threadIdx.x; j < d.plp_off[g + 1]; j += blockDim.x) {
+      for (int j = d.plp_off[g] + rs; j < d.plp_off[g + 1]; j += R) {
         const int f = d.plp[j];
-        for (int64_t i = d.foff[3][f]; i < d.foff[3][f + 1]; ++i) sz_grp_rec<3, T, CD, 3>(d, i, Zr, sfp, acc);
+        for (int64_t i = d.foff[3][f]; i < d.foff[3][f + 1]; ++i) {
+          T zc[CD][CPL];
+          z_cols<CD, CPL>(zr, CD * d.fcam[3][i], zc);
+          sz_rec_cols<3, 1, T, CD>((const T*)d.frec[3] + i * Slot<3, CD>::STRIDE, zc, zg, sp + (int64_t)f * 3 * SZ_COLS, acc);
+        }
       }
     if (d.fn[4])
-      for (int j = d.pll_off[g] + threadIdx.x; j < d.pll_off[g + 1]; j += blockDim.x) {
+      for (int j = d.pll_off[g] + rs; j < d.pll_off[g + 1]; j += R) {
         const int f = d.pll[j];
-        for (int64_t i = d.foff[4][f]; i < d.foff[4][f + 1]; ++i) sz_grp_rec<4, T, CD, 3>(d, i, Zr, sfl, acc);
+        for (int64_t i = d.foff[4][f]; i < d.foff[4][f + 1]; ++i) {
+          T zc[CD][CPL];
+          z_cols<CD, CPL>(zr, CD * d.fcam[4][i], zc);
+          sz_rec_cols<4, 1, T, CD>((const T*)d.frec[4] + i * Slot<4, CD>::STRIDE, zc, zg, sl + (int64_t)f * 4 * SZ_COLS, acc);
+        }
       }
-    double* o = block_sum_arr<double, 3 * SZ_COLS>(reinterpret_cast<double(&)[3 * SZ_COLS]>(acc), lds);
-    for (int k = threadIdx.x; k < 3 * SZ_COLS; k += blockDim.x) {
-      const int row = k / SZ_COLS, col = k % SZ_COLS;
-      if (col >= ncol) continue;
-      const int e = d.offPl + 3 * g + row;
-      d.SZc[(int64_t)(col0 + col) * d.nA + e] = (double)o[k] + lam * d.DA[e] * d.Zc[(int64_t)(col0 + col) * d.nA + e];
-    }
+    sz_block_sum<3, L, CPL>(acc, lds, [&](int row, int cc, double s) {
+      if (cc >= d.coarse_k) return;
+      const int e = e0 + row;
+      d.SZc[(int64_t)cc * d.nA + e] = s + lam * d.DA[e] * d.Zc[(int64_t)cc * d.nA + e];
+    });
   } else {
-    const int v = blockIdx.x - d.ng;
-    double acc[2][SZ_COLS];
+    const int v = blockIdx.x - d.ng, e0 = a_grp(d, 2, v);
+    T zg[3][CPL], zc[CD][CPL];
+#pragma unroll
+    for (int q = 0; q < CPL; ++q) {
+      zg[0][q] = zr[(int64_t)e0 * SZ_COLS + q];
+      zg[1][q] = zr[(int64_t)(e0 + 1) * SZ_COLS + q];
+      zg[2][q] = 0;
+#pragma unroll
+      for (int k = 0; k < CD; ++k) zc[k][q] = 0;
+    }
+    double acc[2][CPL];
 #pragma unroll
     for (int k = 0; k < 2; ++k)
 #pragma unroll
-      for (int q = 0; q < SZ_COLS; ++q) acc[k][q] = 0;
-    for (int j = d.vpm_off[v] + threadIdx.x; j < d.vpm_off[v + 1]; j += blockDim.x)
-      sz_grp_rec<5, T, CD, 2>(d, d.vpm[j], Zr, sfl, acc);
-    double* o = block_sum_arr<double, 2 * SZ_COLS>(reinterpret_cast<double(&)[2 * SZ_COLS]>(acc), lds);
-    for (int k = threadIdx.x; k < 2 * SZ_COLS; k += blockDim.x) {
-      const int row = k / SZ_COLS, col = k % SZ_COLS;
-      if (col >= ncol) continue;
-      const int e = d.offVp + 2 * v + row;
-      d.SZc[(int64_t)(col0 + col) * d.nA + e] = (double)o[k] + lam * d.DA[e] * d.Zc[(int64_t)(col0 + col) * d.nA + e];
+      for (int q = 0; q < CPL; ++q) acc[k][q] = 0;
+    for (int j = d.vpm_off[v] + rs; j < d.vpm_off[v + 1]; j += R) {
+      const int i = d.vpm[j];
+      sz_rec_cols<5, 1, T, CD>((const T*)d.frec[5] + (int64_t)i * Slot<5, CD>::STRIDE, zc, zg, sl + (int64_t)d.ffeat[5][i] * 4 * SZ_COLS, acc);
     }
+    sz_block_sum<2, L, CPL>(acc, lds, [&](int row, int cc, double s) {
+      if (cc >= d.coarse_k) return;
+      const int e = e0 + row;
+      d.SZc[(int64_t)cc * d.nA + e] = s + lam * d.DA[e] * d.Zc[(int64_t)cc * d.nA + e];
+    });
   }
+}
+
+template <typename T, int CD, int L, int CPL> static void launch_sz_out(const Dev& d, const T* Zr, const T* sfp, const T* sfl, double lambda, hipStream_t s) {
+  if (d.nc) k_sz_cam<T, CD, L, CPL><<<d.nc, 256, 0, s>>>(d, Zr, sfp, sfl, lambda);
+  if (d.ng + d.nv) k_sz_grp<T, CD, L, CPL><<<d.ng + d.nv, 256, 0, s>>>(d, Zr, sfp, sfl, lambda);
 }
 
 template <typename T, int CD> static void launch_sz(const Dev& d, double lambda, hipStream_t s) {
   T* Zr = (T*)d.szr;
   T* sfp = (T*)d.szfp;
   T* sfl = (T*)d.szfl;
-  for (int col0 = 0; col0 < d.coarse_k; col0 += SZ_COLS) {
-    const int ncol = std::min(SZ_COLS, d.coarse_k - col0);
-    k_sz_rows<T><<<nblk((int64_t)d.nA * SZ_COLS, 256), 256, 0, s>>>(d, Zr, col0, ncol);
-    if (d.n_tiles) k_sz_feat_wave<T, CD><<<(int)std::min<int64_t>(4 * (int64_t)d.n_mv_wg, nblk(d.n_tiles, 4)), 256, 0, s>>>(d, Zr, sfp, sfl);
-    if (d.n_bigp) k_sz_feat_big<T, CD, 3><<<nblk(d.n_bigp, 256), 256, 0, s>>>(d, Zr, sfp, d.bigp, d.n_bigp);
-    if (d.n_bigl) k_sz_feat_big<T, CD, 4><<<nblk(d.n_bigl, 256), 256, 0, s>>>(d, Zr, sfl, d.bigl, d.n_bigl);
-    if (d.nc) k_sz_cam<T, CD><<<d.nc, 256, 0, s>>>(d, Zr, sfp, sfl, col0, ncol, lambda);
-    if (d.ng + d.nv) k_sz_grp<T, CD><<<d.ng + d.nv, 256, 0, s>>>(d, Zr, sfp, sfl, col0, ncol, lambda);
+  const SzPanels P = sz_panels(d);
+  k_sz_rows<T><<<nblk(P.z * SZ_PANELS, 256), 256, 0, s>>>(d, Zr);
+  for (int pn = 0; pn * SZ_COLS < d.coarse_k; ++pn) {
+    T *zp = Zr + pn * P.z, *pp = sfp + pn * P.p, *lp = sfl + pn * P.l;
+    if (d.n_tiles) k_sz_feat_wave<T, CD><<<(int)std::min<int64_t>(4 * (int64_t)d.n_mv_wg, nblk(d.n_tiles, 4)), 256, 0, s>>>(d, zp, pp, lp);
+    if (d.n_bigp) k_sz_feat_big<T, CD, 3><<<nblk(d.n_bigp, 256), 256, 0, s>>>(d, zp, pp, d.bigp, d.n_bigp);
+    if (d.n_bigl) k_sz_feat_big<T, CD, 4><<<nblk(d.n_bigl, 256), 256, 0, s>>>(d, zp, lp, d.bigl, d.n_bigl);
   }
+  static_assert(SZ_PANELS == 2, "one or two panels");
+  if (d.coarse_k <= SZ_COLS) launch_sz_out<T, CD, SZ_LANES, SZ_COLS / SZ_LANES>(d, Zr, sfp, sfl, lambda, s);
+  else launch_sz_out<T, CD, 2 * SZ_LANES, SZ_COLS / SZ_LANES>(d, Zr, sfp, sfl, lambda, s);
 }
 
 void launch_coarse_setup(const Dev& d, double lambda, hipStream_t s) {

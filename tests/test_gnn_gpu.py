@@ -179,11 +179,15 @@ def test_coarse_pcg_matches_oracle():
     assert ref["gauge"] < ref["jacobi"]
 
 
+@pytest.mark.parametrize("tile", ["64", "8"])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_coarse_space_and_products_match_oracle(precision):
+def test_coarse_space_and_products_match_oracle(precision, tile, monkeypatch):
     """The coarse basis the solver assembles (gauge columns exact, network
     columns from the inference path in BF16) and its S Z (three sweeps over
-    the records) against the oracle's gauge, network and dense S."""
+    the records) against the oracle's gauge, network and dense S.  With the
+    product tile capacity forced to 8 records most features take the
+    one-lane-per-feature path of the feature sweep."""
+    monkeypatch.setenv("BA_TILE_RECORDS", tile)
     from paper_2609_04026_amd.binding import BA
     sc = make_scene(small_config(n_cams=12, n_points=80, n_lines=20, n_planes=3, n_vps=3), seed=33)
     lam = 1e-3
@@ -228,9 +232,11 @@ def test_zero_head_falls_back_to_block_jacobi():
         assert rep["coarse"] == 0
         out[precond] = (x, it)
         ba.close()
-    # same iterations; the solutions agree to the accuracy of a 1e-10 solve (FP64 atomic
-    # reductions sum in a different order from run to run)
-    assert out["jacobi"][1] == out["learned"][1]
+    # the block-Jacobi iterations, up to the last few: the product's FP64 LDS atomics sum
+    # in a different order from run to run, and on this ill-conditioned system that moves
+    # the iteration at which a 1e-10 relative residual is reached (65 and 63 have both been
+    # seen for the same handle); the solutions agree to the accuracy of the solve
+    assert abs(out["jacobi"][1] - out["learned"][1]) <= 3, (out["jacobi"][1], out["learned"][1])
     xj, xl = out["jacobi"][0], out["learned"][0]
     assert np.linalg.norm(xj - xl) <= 1e-7 * np.linalg.norm(xj)
 
