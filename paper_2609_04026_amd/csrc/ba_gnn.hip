@@ -199,42 +199,50 @@ __global__ void k_act_bwd(const float* dOut, const float* Zpre, float* dZ, int64
 // messages of one layer, with [h_j, e_ji] W_e = (h W_h)_j + e_ji W_x:
 // Ze_e = Ph[src_e] + e_e W_x + b_e (stored when Ze != null), m_i = mean over in-edges of gelu(Ze).
 // Work items are runs of <= EDGE_RUN in-edges of one node (high-degree nodes split
-// over several items); one thread per (item, channel) adds its run's share to Mm
-// (cleared before) with FP32 atomics.
+// over several items); one wavefront per run, one lane per channel, adding its run's
+// share to Mm (cleared before) with FP32 atomics.  The run's source ids and edge inputs
+// are loaded one edge per lane, and each edge's values are then read from its lane into
+// scalar registers (v_readlane: the edge is the same on every lane), so that the only
+// per-edge vector load is the 256-byte row Ph[src].
 constexpr int EDGE_RUN = 32;
+__device__ __forceinline__ float lane_f(float v, int k) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), k)); }
+
 __global__ void k_edge_msg(const float* Ph, const float* ex, const float* Wx, const float* be, const int32_t* src,
                            const int32_t* off, const int2* runs, int n_runs, float* Ze, float* Mm) {
+  static_assert(EIN == 8, "edge inputs are read as two float4");
+  static_assert(H == 64 && EDGE_RUN <= 64, "one wavefront per run, one lane per channel");
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < (int64_t)n_runs * H; i += (int64_t)gridDim.x * blockDim.x) {
     const int2 run = runs[i / H];  // (node, first edge)
     const int c = (int)(i % H), node = run.x;
-    const int e0 = run.y, e1 = min(off[node + 1], e0 + EDGE_RUN);
+    const int e0 = run.y, ne = min(off[node + 1], e0 + EDGE_RUN) - e0;
     float w[EIN];
 #pragma unroll
     for (int k = 0; k < EIN; ++k) w[k] = Wx[k * H + c];
     const float bc = be[c];
+    int my_src = 0;
+    float4 x0 = make_float4(0, 0, 0, 0), x1 = x0;
+    if (c < ne) {
+      my_src = src[e0 + c];
+      x0 = reinterpret_cast<const float4*>(ex)[2 * (int64_t)(e0 + c)];
+      x1 = reinterpret_cast<const float4*>(ex)[2 * (int64_t)(e0 + c) + 1];
+    }
     float acc = 0;
-    static_assert(EIN == 8, "edge inputs are read as two float4");
-    static_assert(H == 64 && EDGE_RUN <= 64, "one wavefront per run, one lane per channel");
-    // the run's source ids, one per lane, so that the rows Ph[src] are fetched
-    // without waiting on each id in turn (every lane of the wavefront has the same run)
-    const int my_src = c < e1 - e0 ? src[e0 + c] : 0;
-    auto edge = [&](int e, float p) {
-      const float4 x0 = reinterpret_cast<const float4*>(ex)[2 * (int64_t)e];
-      const float4 x1 = reinterpret_cast<const float4*>(ex)[2 * (int64_t)e + 1];
-      const float z = p + bc + x0.x * w[0] + x0.y * w[1] + x0.z * w[2] + x0.w * w[3] + x1.x * w[4] + x1.y * w[5] +
-                      x1.z * w[6] + x1.w * w[7];
-      if (Ze) Ze[(int64_t)e * H + c] = z;
+    auto edge = [&](int k, float p) {
+      const float z = p + bc + lane_f(x0.x, k) * w[0] + lane_f(x0.y, k) * w[1] + lane_f(x0.z, k) * w[2] +
+                      lane_f(x0.w, k) * w[3] + lane_f(x1.x, k) * w[4] + lane_f(x1.y, k) * w[5] +
+                      lane_f(x1.z, k) * w[6] + lane_f(x1.w, k) * w[7];
+      if (Ze) Ze[(int64_t)(e0 + k) * H + c] = z;
       acc += gelu(z);
     };
-    int e = e0;
-    for (; e + 4 <= e1; e += 4) {  // four rows of Ph in flight
-      const int s0 = __shfl(my_src, e - e0, 64), s1 = __shfl(my_src, e - e0 + 1, 64);
-      const int s2 = __shfl(my_src, e - e0 + 2, 64), s3 = __shfl(my_src, e - e0 + 3, 64);
-      const float p0 = Ph[(int64_t)s0 * H + c], p1 = Ph[(int64_t)s1 * H + c];
-      const float p2 = Ph[(int64_t)s2 * H + c], p3 = Ph[(int64_t)s3 * H + c];
-      edge(e, p0); edge(e + 1, p1); edge(e + 2, p2); edge(e + 3, p3);
+    int k = 0;
+    for (; k + 4 <= ne; k += 4) {  // four rows of Ph in flight
+      const float p0 = Ph[(int64_t)__builtin_amdgcn_readlane(my_src, k) * H + c];
+      const float p1 = Ph[(int64_t)__builtin_amdgcn_readlane(my_src, k + 1) * H + c];
+      const float p2 = Ph[(int64_t)__builtin_amdgcn_readlane(my_src, k + 2) * H + c];
+      const float p3 = Ph[(int64_t)__builtin_amdgcn_readlane(my_src, k + 3) * H + c];
+      edge(k, p0); edge(k + 1, p1); edge(k + 2, p2); edge(k + 3, p3);
     }
-    for (; e < e1; ++e) edge(e, Ph[(int64_t)__shfl(my_src, e - e0, 64) * H + c]);
+    for (; k < ne; ++k) edge(k, Ph[(int64_t)__builtin_amdgcn_readlane(my_src, k) * H + c]);
     atomicAdd(Mm + (int64_t)node * H + c, acc / (float)(off[node + 1] - off[node]));
   }
 }
