@@ -170,6 +170,39 @@ def gauge_basis(prob, state):
     return G
 
 
+def gauge_basis_features(prob, state):
+    """G_f ((3 n_pt + 4 n_ln) x 7): the same world rotation, translation and
+    scale as gauge_basis, as first-order motions of the points and lines in
+    their tangent coordinates, so that [G; G_f] is the motion of every
+    parameter.  Points move additively: e_k x X, e_k, X.  A line (d, m) =
+    (w1 U e1, w2 U e2) with m = p x d moves to (d + w x d, m + w x m) under a
+    rotation w, (d, m + t x d) under a translation t and (d, (1 + s) m) under a
+    scale s, each up to the common scale of (d, m); in the tangent
+    (dtheta, dphi) of U <- U Exp(dtheta) and the rotation of (w1, w2) by dphi
+    that is dtheta = U^T e_k for rotation k, dtheta = (-w1 (u2 . e_k) / w2, 0, 0)
+    and dphi = w1^2 (u3 . e_k) for translation k, and dphi = w1 w2 for the scale."""
+    npt, nln = prob.n["pt"], prob.n["ln"]
+    G = np.zeros((3 * npt + 4 * nln, K_GAUGE))
+    E3 = np.eye(3)
+    for j in range(npt):
+        X = state.pts[j]
+        for k in range(3):
+            G[3 * j:3 * j + 3, k] = np.cross(E3[k], X)
+            G[3 * j:3 * j + 3, 3 + k] = E3[k]
+        G[3 * j:3 * j + 3, 6] = X
+    o = 3 * npt
+    for j in range(nln):
+        U, (w1, w2) = state.line_U[j], state.line_w[j]
+        u2, u3 = U[:, 1], U[:, 2]
+        r = o + 4 * j
+        for k in range(3):
+            G[r:r + 3, k] = U.T @ E3[k]
+            G[r, 3 + k] = -w1 * u2[k] / w2
+            G[r + 3, 3 + k] = w1 * w1 * u3[k]
+        G[r + 3, 6] = w1 * w2
+    return G
+
+
 def block_graph(prob):
     """Block graph of the reduced system of an oracle Problem."""
     nc, npl, nvp = prob.n["cam"], prob.n["pl"], prob.n["vp"]

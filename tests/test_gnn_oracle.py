@@ -191,6 +191,27 @@ def test_gauge_basis_is_annihilated_by_the_undamped_reduced_matrix(tiny):
     assert np.linalg.norm(S @ v) / (np.linalg.norm(S) * np.linalg.norm(v)) > 1e-4
 
 
+def test_feature_gauge_motion_is_annihilated_by_the_jacobian():
+    """With the features' motion G_f beside G, the whole similarity [G; G_f]
+    is a null direction of the weighted Jacobian of every family but the VP
+    3-vector (points, lines, planes, junctions; noisy state, robust weights):
+    J [G; G_f] = 0 to rounding.  A wrong sign, index or factor in any of the
+    13 point / line formulas leaves an O(|J| |z|) residual."""
+    sc = make_scene(small_config(n_cams=6, n_points=40, n_lines=14, n_planes=2, n_vps=0, vp_lines=0), seed=9)
+    prob = lm.Problem(sc)
+    st = prob.state0()
+    lin = lm.linearize(prob, st)
+    assert prob.n["ln"] > 0 and prob.record_count("R4") > 0 and prob.record_count("R6") > 0
+    Z = np.vstack([gnn.gauge_basis(prob, st), gnn.gauge_basis_features(prob, st)])
+    J = lin.J.toarray()
+    rel = np.linalg.norm(J @ Z, axis=0) / (np.linalg.norm(J) * np.linalg.norm(Z, axis=0))
+    assert rel.max() < 1e-12, rel
+    # the feature part is needed: the A side alone is not annihilated
+    Za = np.vstack([gnn.gauge_basis(prob, st), np.zeros((prob.nF, gnn.K_GAUGE))])
+    rel_a = np.linalg.norm(J @ Za, axis=0) / (np.linalg.norm(J) * np.linalg.norm(Za, axis=0))
+    assert rel_a.min() > 1e-4, rel_a
+
+
 def test_exact_slow_modes_cut_pcg_iterations(tiny):
     """Textbook PCG with the A-DEF2 two-level preconditioner started from
     x0 = Q b: the gauge basis alone, and the gauge plus the exact next slowest
