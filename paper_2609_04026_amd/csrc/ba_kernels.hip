@@ -1990,13 +1990,88 @@ struct SzPanels {
 };
 __host__ __device__ inline SzPanels sz_panels(const Dev& d) { return {(int64_t)d.nA * SZ_COLS, (int64_t)d.np * 3 * SZ_COLS, (int64_t)d.nl * 4 * SZ_COLS}; }
 
-// Z rows in T: Zr[c / SZ_COLS][e][c % SZ_COLS] = Z[c][e], zero beyond the active columns
-template <typename T> __global__ void k_sz_rows(Dev d, T* Zr) {
+// coarse column held by slot s of panel pn: panel 0 the gauge columns, panel 1 the
+// network's; -1 for an unused slot
+static_assert(SZ_PANELS == 2 && COARSE_GAUGE <= SZ_COLS && COARSE_NET <= SZ_COLS, "gauge panel, network panel");
+__host__ __device__ inline int sz_col(int pn, int s) { return pn == 0 ? (s < COARSE_GAUGE ? s : -1) : COARSE_GAUGE + s; }
+
+// Z rows in T: Zr[pn][e][s] = Z[sz_col(pn, s)][e], zero in unused slots and, with
+// gauge_zero, in the gauge panel (its s_f then come in closed form, see k_sz_gauge_feat)
+template <typename T> __global__ void k_sz_rows(Dev d, T* Zr, int gauge_zero) {
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const int64_t panel = (int64_t)d.nA * SZ_COLS;
   if (t >= panel * SZ_PANELS) return;
-  const int c = (int)(t / panel) * SZ_COLS + (int)(t % SZ_COLS), e = (int)((t % panel) / SZ_COLS);
-  Zr[t] = c < d.coarse_k ? (T)d.Zc[(int64_t)c * d.nA + e] : (T)0;
+  const int pn = (int)(t / panel), e = (int)((t % panel) / SZ_COLS);
+  const int c = sz_col(pn, (int)(t % SZ_COLS));
+  Zr[t] = c < 0 || c >= d.coarse_k || (pn == 0 && gauge_zero) ? (T)0 : (T)d.Zc[(int64_t)c * d.nA + e];
+}
+
+// The gauge panel in closed form.  With z = (z_a, z_f) the first-order motion of every
+// parameter under a world rotation, translation or scale (z_a: the gauge columns of Z),
+// J z = 0 for every family but the VP 3-vector, whose value turns with the world: then
+// W^T z_a = -V z_f and U z_a = -W z_f, so
+//   S z_a = lambda D_a z_a - lambda W (V + lambda D_f)^-1 D_f z_f.
+// The camera / group sweeps form exactly this when the gauge panel's Z rows are zero and
+// its s_f = lambda (V + lambda D_f)^-1 D_f z_f, which this kernel writes (one thread per
+// point, then per line), reading no record.  Points move additively: e_k x X, e_k, X.  A
+// line (U, w1, w2) moves by dtheta = U^T e_k under rotation k, by dtheta =
+// (-w1 (u2 . e_k) / w2, 0, 0) and dphi = w1^2 (u3 . e_k) under translation k, and by
+// dphi = w1 w2 under the scale.
+template <typename T, int NF>
+__device__ __forceinline__ void sz_gauge_solve(const Dev& d, int f, const double (&z)[NF][COARSE_GAUGE], double lam, T* sf) {
+  const double* D = (NF == 3 ? d.Dp : d.Dl) + (int64_t)NF * f;
+  T* o = sf + (int64_t)f * NF * SZ_COLS;
+  for (int c = 0; c < COARSE_GAUGE; ++c) {
+    T q[NF], y[NF];
+#pragma unroll
+    for (int a = 0; a < NF; ++a) q[a] = (T)(D[a] * z[a][c]);
+    apply_vinv<T, NF>(d, f, q, y);
+#pragma unroll
+    for (int a = 0; a < NF; ++a) o[a * SZ_COLS + c] = (T)(lam * (double)y[a]);
+  }
+#pragma unroll
+  for (int a = 0; a < NF; ++a)
+    for (int c = COARSE_GAUGE; c < SZ_COLS; ++c) o[a * SZ_COLS + c] = (T)0;
+}
+
+template <typename T> __global__ void k_sz_gauge_feat(Dev d, T* sfp, T* sfl, double lam) {
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f < d.np) {
+    const double* X = d.pt64 + (int64_t)PT_STRIDE * f;
+    double z[3][COARSE_GAUGE];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int c = 0; c < COARSE_GAUGE; ++c) z[a][c] = 0.0;
+    z[1][0] = -X[2]; z[2][0] = X[1];  // e_0 x X
+    z[0][1] = X[2]; z[2][1] = -X[0];  // e_1 x X
+    z[0][2] = -X[1]; z[1][2] = X[0];  // e_2 x X
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      z[a][3 + a] = 1.0;
+      z[a][6] = X[a];
+    }
+    sz_gauge_solve<T, 3>(d, f, z, lam, sfp);
+  } else if (f < d.np + d.nl) {
+    const int j = f - d.np;
+    const double* L = d.ln64 + (int64_t)LN_STRIDE * j;  // u1, u2, u3, w1, w2
+    const double w1 = L[9], w2 = L[10];
+    double z[4][COARSE_GAUGE];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int c = 0; c < COARSE_GAUGE; ++c) z[a][c] = 0.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      z[0][k] = L[k];
+      z[1][k] = L[3 + k];
+      z[2][k] = L[6 + k];
+      z[0][3 + k] = w2 != 0.0 ? -w1 * L[3 + k] / w2 : 0.0;
+      z[3][3 + k] = w1 * w1 * L[6 + k];
+    }
+    z[3][6] = w1 * w2;
+    sz_gauge_solve<T, 4>(d, j, z, lam, sfl);
+  }
 }
 
 // t[row][c] = (J_a Z_r)[row][c] for one record (Zr: one panel)
@@ -2328,9 +2403,10 @@ __global__ __launch_bounds__(256) void k_sz_cam(Dev d, const T* Zr, const T* sfp
       for (int64_t i = d.lx_start[j]; i < d.lx_start[j] + d.lx_cnt[j]; ++i)
         sz_rec_cols<7, 0, T, CD>((const T*)d.frec[7] + i * Slot<7, CD>::STRIDE, zc, z0, sl + (int64_t)d.ffeat[7][i] * 4 * SZ_COLS, acc);
   sz_block_sum<CD, L, CPL>(acc, lds, [&](int row, int cc, double s) {
-    if (cc >= d.coarse_k) return;
+    const int col = sz_col(cc / SZ_COLS, cc % SZ_COLS);
+    if (col < 0 || col >= d.coarse_k) return;
     const int e = CD * c + row;
-    d.SZc[(int64_t)cc * d.nA + e] = s + lam * d.DA[e] * d.Zc[(int64_t)cc * d.nA + e];
+    d.SZc[(int64_t)col * d.nA + e] = s + lam * d.DA[e] * d.Zc[(int64_t)col * d.nA + e];
   });
 }
 
@@ -2373,9 +2449,10 @@ __global__ __launch_bounds__(256) void k_sz_grp(Dev d, const T* Zr, const T* sfp
         }
       }
     sz_block_sum<3, L, CPL>(acc, lds, [&](int row, int cc, double s) {
-      if (cc >= d.coarse_k) return;
+      const int col = sz_col(cc / SZ_COLS, cc % SZ_COLS);
+      if (col < 0 || col >= d.coarse_k) return;
       const int e = e0 + row;
-      d.SZc[(int64_t)cc * d.nA + e] = s + lam * d.DA[e] * d.Zc[(int64_t)cc * d.nA + e];
+      d.SZc[(int64_t)col * d.nA + e] = s + lam * d.DA[e] * d.Zc[(int64_t)col * d.nA + e];
     });
   } else {
     const int v = blockIdx.x - d.ng, e0 = a_grp(d, 2, v);
@@ -2398,9 +2475,10 @@ __global__ __launch_bounds__(256) void k_sz_grp(Dev d, const T* Zr, const T* sfp
       sz_rec_cols<5, 1, T, CD>((const T*)d.frec[5] + (int64_t)i * Slot<5, CD>::STRIDE, zc, zg, sl + (int64_t)d.ffeat[5][i] * 4 * SZ_COLS, acc);
     }
     sz_block_sum<2, L, CPL>(acc, lds, [&](int row, int cc, double s) {
-      if (cc >= d.coarse_k) return;
+      const int col = sz_col(cc / SZ_COLS, cc % SZ_COLS);
+      if (col < 0 || col >= d.coarse_k) return;
       const int e = e0 + row;
-      d.SZc[(int64_t)cc * d.nA + e] = s + lam * d.DA[e] * d.Zc[(int64_t)cc * d.nA + e];
+      d.SZc[(int64_t)col * d.nA + e] = s + lam * d.DA[e] * d.Zc[(int64_t)col * d.nA + e];
     });
   }
 }
@@ -2415,15 +2493,21 @@ template <typename T, int CD> static void launch_sz(const Dev& d, double lambda,
   T* sfp = (T*)d.szfp;
   T* sfl = (T*)d.szfl;
   const SzPanels P = sz_panels(d);
-  k_sz_rows<T><<<nblk(P.z * SZ_PANELS, 256), 256, 0, s>>>(d, Zr);
-  for (int pn = 0; pn * SZ_COLS < d.coarse_k; ++pn) {
+  // no VP 3-vector records: the gauge panel's s_f in closed form, no record sweep for it
+  const bool closed = d.fn[5] == 0;
+  k_sz_rows<T><<<nblk(P.z * SZ_PANELS, 256), 256, 0, s>>>(d, Zr, closed ? 1 : 0);
+  for (int pn = 0; pn < SZ_PANELS && sz_col(pn, 0) < d.coarse_k; ++pn) {
     T *zp = Zr + pn * P.z, *pp = sfp + pn * P.p, *lp = sfl + pn * P.l;
+    if (pn == 0 && closed) {
+      if (d.np + d.nl) k_sz_gauge_feat<T><<<nblk(d.np + d.nl, 256), 256, 0, s>>>(d, pp, lp, lambda);
+      continue;
+    }
     if (d.n_tiles) k_sz_feat_wave<T, CD><<<(int)std::min<int64_t>(4 * (int64_t)d.n_mv_wg, nblk(d.n_tiles, 4)), 256, 0, s>>>(d, zp, pp, lp);
     if (d.n_bigp) k_sz_feat_big<T, CD, 3><<<nblk(d.n_bigp, 256), 256, 0, s>>>(d, zp, pp, d.bigp, d.n_bigp);
     if (d.n_bigl) k_sz_feat_big<T, CD, 4><<<nblk(d.n_bigl, 256), 256, 0, s>>>(d, zp, lp, d.bigl, d.n_bigl);
   }
   static_assert(SZ_PANELS == 2, "one or two panels");
-  if (d.coarse_k <= SZ_COLS) launch_sz_out<T, CD, SZ_LANES, SZ_COLS / SZ_LANES>(d, Zr, sfp, sfl, lambda, s);
+  if (d.coarse_k <= COARSE_GAUGE) launch_sz_out<T, CD, SZ_LANES, SZ_COLS / SZ_LANES>(d, Zr, sfp, sfl, lambda, s);
   else launch_sz_out<T, CD, 2 * SZ_LANES, SZ_COLS / SZ_LANES>(d, Zr, sfp, sfl, lambda, s);
 }
 

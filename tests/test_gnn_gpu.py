@@ -179,17 +179,22 @@ def test_coarse_pcg_matches_oracle():
     assert ref["gauge"] < ref["jacobi"]
 
 
+@pytest.mark.parametrize("vps", [3, 0])
 @pytest.mark.parametrize("tile", ["64", "8"])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_coarse_space_and_products_match_oracle(precision, tile, monkeypatch):
+def test_coarse_space_and_products_match_oracle(precision, tile, vps, monkeypatch):
     """The coarse basis the solver assembles (gauge columns exact, network
-    columns from the inference path in BF16) and its S Z (three sweeps over
-    the records) against the oracle's gauge, network and dense S.  With the
-    product tile capacity forced to 8 records most features take the
+    columns from the inference path in BF16) and its S Z against the oracle's
+    gauge, network and dense S.  With VP records S Z comes from sweeps over the
+    records for every column; without them the gauge columns' feature terms
+    come in closed form from the features' gauge motion.  With the product
+    tile capacity forced to 8 records most features take the
     one-lane-per-feature path of the feature sweep."""
     monkeypatch.setenv("BA_TILE_RECORDS", tile)
     from paper_2609_04026_amd.binding import BA
-    sc = make_scene(small_config(n_cams=12, n_points=80, n_lines=20, n_planes=3, n_vps=3), seed=33)
+    cfg = small_config(n_cams=12, n_points=80, n_lines=20, n_planes=3, n_vps=vps) if vps else \
+        small_config(n_cams=12, n_points=80, n_lines=20, n_planes=3, n_vps=0, vp_lines=0)
+    sc = make_scene(cfg, seed=33)
     lam = 1e-3
     o = _oracle_system(sc, lam)
     params = gnn.unpack(gnn.pack(gnn.init_params(9, seed=25)).tobytes())

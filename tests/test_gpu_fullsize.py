@@ -182,3 +182,19 @@ def test_fullsize_product_is_symmetric_positive(full):
     a, c = y @ Sx, x @ Sy
     assert abs(a - c) <= 1e-5 * np.sqrt((x @ Sx) * (y @ Sy)), (a, c)
     assert x @ Sx > 0 and y @ Sy > 0
+
+
+def test_fullsize_coarse_columns_of_s_z(full):
+    """S Z of the coarse space at full size (the gauge columns from the
+    features' gauge motion in closed form, as this scene has no VP records; the
+    network columns from the record sweeps) against the implicit-Schur product
+    applied to each column, within 1e-4 of |S| |z| (both are FP32 sums)."""
+    _, ba = full
+    Z, SZ = ba.export_coarse_space()
+    assert Z.shape[1] == 15
+    for k in range(Z.shape[1]):
+        y = ba.schur_matvec(Z[:, k])
+        scale = np.linalg.norm(ba.schur_matvec(np.abs(Z[:, k])))
+        err = np.linalg.norm(SZ[:, k] - y) / scale
+        assert err <= 1e-4, (k, err)
+    print(f"[fullsize] S Z of {Z.shape[1]} coarse columns matches the product", flush=True)
