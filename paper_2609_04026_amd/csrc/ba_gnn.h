@@ -23,6 +23,7 @@ struct Graph {
   std::vector<int32_t> node_type, node_off, node_size, edge_src, edge_dst, edge_rev, dst_off;
   std::vector<float> node_static;  // n x 64: the structural input entries (others zero)
   std::vector<float> edge_x;       // m x 8
+  std::vector<int2> edge_typed;    // m: (bits of edge_x[0], index 1..4 of its one-hot kind column)
   double scale = 1.0;              // scene scale s0 (RMS camera-centre spread of the input cameras)
   bool valid = false;
 };

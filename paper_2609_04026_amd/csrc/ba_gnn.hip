@@ -247,6 +247,45 @@ __global__ void k_edge_msg(const float* Ph, const float* ex, const float* Wx, co
   }
 }
 
+// The same pass for the attached problem graph, whose edge inputs are log1p(shared
+// records) and a one-hot kind (columns 1-4; columns 5-7 zero): e W_x + b_e =
+// e_0 W_x[0] + (W_x[kind] + b_e), so each edge takes its two words (value, kind) from its
+// lane and the lane's four kind rows are selected instead of eight products.
+__global__ void k_edge_msg_typed(const float* Ph, const int2* et, const float* Wx, const float* be, const int32_t* src,
+                                 const int32_t* off, const int2* runs, int n_runs, float* Mm) {
+  static_assert(H == 64 && EDGE_RUN <= 64, "one wavefront per run, one lane per channel");
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < (int64_t)n_runs * H; i += (int64_t)gridDim.x * blockDim.x) {
+    const int2 run = runs[i / H];  // (node, first edge)
+    const int c = (int)(i % H), node = run.x;
+    const int e0 = run.y, ne = min(off[node + 1], e0 + EDGE_RUN) - e0;
+    const float w0 = Wx[c], bc = be[c];
+    const float t1 = Wx[H + c] + bc, t2 = Wx[2 * H + c] + bc, t3 = Wx[3 * H + c] + bc, t4 = Wx[4 * H + c] + bc;
+    int my_src = 0;
+    int2 my_e = make_int2(0, 1);
+    if (c < ne) {
+      my_src = src[e0 + c];
+      my_e = et[e0 + c];
+    }
+    float acc = 0;
+    auto edge = [&](int k, float p) {
+      const float x0 = __int_as_float(__builtin_amdgcn_readlane(my_e.x, k));
+      const int kind = __builtin_amdgcn_readlane(my_e.y, k);
+      const float tk = kind == 1 ? t1 : kind == 2 ? t2 : kind == 3 ? t3 : t4;
+      acc += gelu(p + x0 * w0 + tk);
+    };
+    int k = 0;
+    for (; k + 4 <= ne; k += 4) {  // four rows of Ph in flight
+      const float p0 = Ph[(int64_t)__builtin_amdgcn_readlane(my_src, k) * H + c];
+      const float p1 = Ph[(int64_t)__builtin_amdgcn_readlane(my_src, k + 1) * H + c];
+      const float p2 = Ph[(int64_t)__builtin_amdgcn_readlane(my_src, k + 2) * H + c];
+      const float p3 = Ph[(int64_t)__builtin_amdgcn_readlane(my_src, k + 3) * H + c];
+      edge(k, p0); edge(k + 1, p1); edge(k + 2, p2); edge(k + 3, p3);
+    }
+    for (; k < ne; ++k) edge(k, Ph[(int64_t)__builtin_amdgcn_readlane(my_src, k) * H + c]);
+    atomicAdd(Mm + (int64_t)node * H + c, acc / (float)(off[node + 1] - off[node]));
+  }
+}
+
 // dZe_e = dM[dst_e] / deg(dst_e) * gelu'(Ze_e)   (one thread per edge entry)
 __global__ void k_edge_msg_bwd(const float* dM, const float* Ze, const int32_t* dst, const int32_t* off, float* dZe, int m) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < (int64_t)m * H; i += (int64_t)gridDim.x * blockDim.x) {
@@ -565,6 +604,7 @@ struct ba_gnn {
   int gn = 0, gm = 0, type_end[3] = {0, 0, 0};
   double s0 = 1.0;
   float* gstat = nullptr;
+  int2* etyped = nullptr;  // per edge of the attached graph: (log1p(shared records) bits, kind 1..4)
   std::vector<void*> allocs;
 };
 
@@ -679,8 +719,9 @@ struct Dims {
 
 // forward over the batch currently in the device buffers
 // forward over the batch (or attached graph) in the device buffers; keep_edges stores
-// the edge pre-activations for the backward pass
-void forward(ba_gnn* g, const Dims& D, bool keep_edges) {
+// the edge pre-activations for the backward pass; typed: the attached graph's edges, with
+// the (value, kind) words of k_edge_msg_typed
+void forward(ba_gnn* g, const Dims& D, bool keep_edges, bool typed = false) {
   const int n = D.n, m = D.m;
   const Layout& L = g->L;
   const float* P = g->params;
@@ -698,7 +739,11 @@ void forward(ba_gnn* g, const Dims& D, bool keep_edges) {
     // messages: the h-part of W_e applied per node, then one pass over the edges
     gemm(g, n, H, H, hl, H, 1, P + L.W_e[l], H, 1, Ph, H, 0, true, L.W_e[l]);
     GCHK(hipMemsetAsync(Mm, 0, (size_t)n * H * sizeof(float), g->cur));
-    if (g->n_runs > 0)
+    if (g->n_runs > 0 && typed)
+      hipLaunchKernelGGL(k_edge_msg_typed, dim3(nblk((int64_t)g->n_runs * H, 256)), dim3(256), 0, g->cur, (const float*)Ph,
+                         (const int2*)g->etyped, P + L.W_e[l] + (size_t)H * H, P + L.b_e[l], (const int32_t*)g->src,
+                         (const int32_t*)g->dst_off, (const int2*)g->runs, g->n_runs, Mm);
+    else if (g->n_runs > 0)
       hipLaunchKernelGGL(k_edge_msg, dim3(nblk((int64_t)g->n_runs * H, 256)), dim3(256), 0, g->cur, (const float*)Ph,
                          (const float*)g->ex, P + L.W_e[l] + (size_t)H * H, P + L.b_e[l], (const int32_t*)g->src,
                          (const int32_t*)g->dst_off, (const int2*)g->runs, g->n_runs,
@@ -1017,6 +1062,11 @@ void build_graph(Graph& G, int nc, int ng, int nv, int cd, const std::vector<int
       else if (ts == 0 || td == 0) ef[3] = 1; // camera - VP
       else ef[4] = 1;                          // group - group
       G.edge_x.insert(G.edge_x.end(), ef, ef + EDGE_IN);
+      int kind = 1;
+      while (kind < 4 && ef[kind] == 0.0f) ++kind;
+      int32_t bits;
+      std::memcpy(&bits, &ef[0], sizeof(bits));
+      G.edge_typed.push_back(make_int2(bits, kind));
       deg[d]++;
     }
     G.dst_off[d + 1] = (int32_t)G.edge_src.size();
@@ -1061,6 +1111,9 @@ void attach(ba_gnn* g, const Graph& G) {
     GCHK(hipMemcpyAsync(g->rev, G.edge_rev.data(), G.n_edges * 4, hipMemcpyHostToDevice, s));
     GCHK(hipMemcpyAsync(g->ex, G.edge_x.data(), G.edge_x.size() * 4, hipMemcpyHostToDevice, s));
   }
+  if (g->etyped) dfree(g, g->etyped);
+  g->etyped = dalloc<int2>(g, (size_t)G.n_edges);
+  if (G.n_edges) GCHK(hipMemcpyAsync(g->etyped, G.edge_typed.data(), G.edge_typed.size() * sizeof(int2), hipMemcpyHostToDevice, s));
   upload_runs(g, G.dst_off.data(), G.n_nodes, s);
   GCHK(hipStreamSynchronize(s));
   g->attached_training = false;
@@ -1083,7 +1136,7 @@ void apply(ba_gnn* g, const ba::Dev& d, double lambda, hipStream_t s) {
   g->cur = s;  // ordered after the solver's assembly on its stream
   launch_node_features(d, g->gstat, g->type, g->gn, lambda, g->s0, g->X, s);
   Dims D{g->gn, g->gm, {g->type_end[0], g->type_end[1], g->type_end[2]}};
-  forward(g, D, false);
+  forward(g, D, false, g->etyped != nullptr);
   hipLaunchKernelGGL(k_coarse_basis, dim3(nblk((int64_t)g->gn * HEADP, 256)), dim3(256), 0, s, d,
                      (const float*)g->heads, (const int32_t*)g->type, g->gn, g->s0);
   g->cur = g->stream;
