@@ -2020,7 +2020,10 @@ template <typename T> __global__ void k_sz_rows(Dev d, T* Zr, int gauge_zero) {
 template <typename T, int NF>
 __device__ __forceinline__ void sz_gauge_solve(const Dev& d, int f, const double (&z)[NF][COARSE_GAUGE], double lam, T* sf) {
   const double* D = (NF == 3 ? d.Dp : d.Dl) + (int64_t)NF * f;
-  T* o = sf + (int64_t)f * NF * SZ_COLS;
+  T o[NF * SZ_COLS];  // the feature's rows of the panel, stored in one vector write
+#pragma unroll
+  for (int k = 0; k < NF * SZ_COLS; ++k) o[k] = (T)0;
+#pragma unroll
   for (int c = 0; c < COARSE_GAUGE; ++c) {
     T q[NF], y[NF];
 #pragma unroll
@@ -2029,9 +2032,7 @@ __device__ __forceinline__ void sz_gauge_solve(const Dev& d, int f, const double
 #pragma unroll
     for (int a = 0; a < NF; ++a) o[a * SZ_COLS + c] = (T)(lam * (double)y[a]);
   }
-#pragma unroll
-  for (int a = 0; a < NF; ++a)
-    for (int c = COARSE_GAUGE; c < SZ_COLS; ++c) o[a * SZ_COLS + c] = (T)0;
+  store_vec(sf + (int64_t)f * NF * SZ_COLS, o);
 }
 
 template <typename T> __global__ void k_sz_gauge_feat(Dev d, T* sfp, T* sfl, double lam) {
