@@ -302,3 +302,27 @@ def test_trained_network_gain_over_block_jacobi():
     ref = golden["holistic_30cam"]["E"]
     assert abs(out["E_final"] - ref) <= 1e-6 * ref, (out["E_final"], ref)
     ba.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_gauge_coarse_space_camera_dof6(precision):
+    """Gauge-only two-level preconditioner with pose-only cameras and no VP
+    records (the gauge panel's feature terms in closed form): S Z against the
+    oracle's dense S, and the coarse space active in the LM step."""
+    from paper_2609_04026_amd.binding import BA
+    sc = make_scene(small_config(n_cams=10, n_points=70, n_lines=18, n_planes=2, n_vps=0, vp_lines=0), seed=57)
+    sc["camera_dof"] = 6
+    lam = 1e-3
+    o = _oracle_system(sc, lam)
+    assert o["prob"].camera_dof == 6
+    ba = BA.from_scene(sc, precision=precision, precond="gauge")
+    ba.linearize(lam)
+    Z, SZ = ba.export_coarse_space()
+    assert Z.shape == (o["S"].shape[0], 7)
+    assert np.abs(Z - o["gauge"]).max() <= 1e-12 * np.abs(o["gauge"]).max()
+    tol = 1e-9 if precision == "fp64" else 1e-4
+    col_err = np.linalg.norm(SZ - o["S"] @ Z, axis=0) / np.linalg.norm(o["S"] @ np.abs(Z), axis=0)
+    assert col_err.max() <= tol, col_err
+    rep = ba.lm_step(pcg_tol=1e-8 if precision == "fp64" else 1e-6)
+    assert rep["coarse"] == 7 and rep["pcg_flags"] == 0, rep
+    ba.close()
