@@ -1977,10 +1977,12 @@ void launch_gauge_basis(const Dev& d, hipStream_t s) {
 
 // ---- S Z for the coarse columns ---------------------------------------------
 // S x = sum_r J_a,r^T (J_a,r x - J_f,r s_f) + lambda D_a x, s_f = V_f^-1 sum_{r in f} J_f,r^T J_a,r x
-// Z rows and s_f are stored in panels of SZ_COLS columns (row-major in a panel).  Feature
-// sweep, one panel per launch: s_f over the product's wavefront tiles.  Camera / group
-// sweeps, all columns in one launch: a workgroup per camera / group owns that block of the
-// output (no atomics), and each of its records is taken by SZ_LANES lanes per panel.
+// Z rows and s_f are stored in panels of SZ_COLS columns (row-major in a panel): the gauge
+// columns in panel 0, the network's in panel 1.  s_f of a panel: a feature sweep over the
+// product's wavefront tiles, or, for the gauge panel when no VP 3-vector record exists,
+// the closed form of k_sz_gauge_feat.  Camera / group sweeps, all columns in one launch: a
+// workgroup per camera / group owns that block of the output (no atomics), and each of its
+// records is taken by SZ_LANES lanes per panel.
 // Two lanes of four columns each balance the slot loads, repeated on every lane of a
 // record, against the registers of the FP64 sums (1M-point scene, 15 columns: 1, 2, 4, 8
 // lanes per panel gave 4.9, 4.2, 4.3, 5.1 ms for the preconditioner set-up).
