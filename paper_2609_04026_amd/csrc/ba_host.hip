@@ -307,6 +307,48 @@ void finalize(ba_handle* h) {
       hi[k] = std::max(hi[k], v);
     }
   }
+  // per-camera passes: cameras in Morton order of their centres, dealt to the XCDs in
+  // contiguous runs (workgroup b runs on XCD b mod CU_XCDS)
+  std::vector<int32_t> cam_wg(h->nc);
+  {
+    constexpr int CU_XCDS = 8;
+    std::vector<uint64_t> ckey(h->nc);
+    for (int i = 0; i < h->nc; ++i) {
+      uint32_t q[3];
+      for (int k = 0; k < 3; ++k) {
+        const double span = hi[k] - lo[k];
+        const double u = span > 0 ? (ctr[3 * i + k] - lo[k]) / span : 0.0;
+        q[k] = (uint32_t)std::min(1023.0, std::max(0.0, u * 1024.0));
+      }
+      uint64_t code = 0;
+      for (int bit = 9; bit >= 0; --bit)
+        for (int k = 0; k < 3; ++k) code = (code << 1) | ((q[k] >> bit) & 1u);
+      ckey[i] = code;
+    }
+    std::vector<int32_t> sorted(h->nc);
+    std::iota(sorted.begin(), sorted.end(), 0);
+    std::stable_sort(sorted.begin(), sorted.end(), [&](int a, int b) { return ckey[a] < ckey[b]; });
+    const int chunk = (h->nc + CU_XCDS - 1) / CU_XCDS;
+    std::vector<int> next(CU_XCDS);
+    for (int x = 0; x < CU_XCDS; ++x) next[x] = x * chunk;
+    for (int b = 0; b < h->nc; ++b) {
+      const int x = b % CU_XCDS;
+      cam_wg[b] = next[x] < std::min((x + 1) * chunk, h->nc) ? sorted[next[x]++] : -1;
+    }
+    // a workgroup whose XCD's run is used up takes a camera not dealt out, in order
+    std::vector<char> used(h->nc, 0);
+    for (int b = 0; b < h->nc; ++b)
+      if (cam_wg[b] >= 0) used[cam_wg[b]] = 1;
+    int r = 0;
+    for (int b = 0; b < h->nc; ++b)
+      if (cam_wg[b] < 0) {
+        while (used[sorted[r]]) ++r;
+        cam_wg[b] = sorted[r];
+        used[sorted[r]] = 1;
+      }
+    for (int i = 0; i < h->nc; ++i)
+      if (!used[i]) throw BaError(BA_E_STATE, "camera order is not a permutation");
+  }
   auto morton = [&](const CSR& O, int f) -> uint64_t {
     const int64_t b = O.off[f], e = O.off[f + 1];
     if (e == b) return ~0ull;
@@ -574,6 +616,8 @@ void finalize(ba_handle* h) {
     off = A.get<int32_t>(o.size());
     upload(h, off, o);
   };
+  d.cam_order = A.get<int32_t>(std::max(h->nc, 1));
+  upload(h, d.cam_order, cam_wg);
   cam_offsets(1, d.po_off);
   cam_offsets(2, d.lo_off);
   // camera-major copies of the observation slots and their aligned plane slots

@@ -75,6 +75,10 @@ struct Dev {
   int32_t *cmpos[NFAM] = {nullptr}, *cmfeat[NFAM] = {nullptr}, *cmal[NFAM] = {nullptr}, *cmgrp[NFAM] = {nullptr};
   // group member lists
   int32_t *plp_off = nullptr, *plp = nullptr, *pll_off = nullptr, *pll = nullptr;
+  // camera of each workgroup of the per-camera passes: consecutive workgroups go to
+  // different XCDs, so each XCD is given a run of spatially close cameras (which share
+  // features, whose data its L2 then serves)
+  int32_t* cam_order = nullptr;
   int32_t *vpm_off = nullptr, *vpm = nullptr;
   // feature blocks (T unless noted)
   void *Vp = nullptr, *gp = nullptr, *Vl = nullptr, *gl = nullptr;

@@ -735,7 +735,7 @@ template <typename T, int CD> __global__ __launch_bounds__(256) void k_cam_a(Dev
   constexpr int NS = CD * (CD + 1) / 2;
   constexpr int K = NS + CD;
   __shared__ T lds[(4 + 1) * K];
-  const int c = blockIdx.x;
+  const int c = d.cam_order[blockIdx.x];
   T acc[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) acc[k] = 0;
@@ -921,7 +921,7 @@ template <typename T, int CD> __global__ __launch_bounds__(256) void k_cam_b(Dev
   constexpr int NS = CD * (CD + 1) / 2;
   constexpr int K = NS + CD;
   __shared__ T lds[(4 + 1) * K];
-  const int c = blockIdx.x;
+  const int c = d.cam_order[blockIdx.x];
   T acc[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) acc[k] = 0;
@@ -2357,7 +2357,7 @@ __global__ __launch_bounds__(256) void k_sz_cam(Dev d, const T* Zr, const T* sfp
   constexpr int R = 256 / L, NCOL = L * CPL;
   static_assert(SZ_COLS % CPL == 0, "a lane's columns lie in one panel");
   __shared__ double lds[4 * CD * NCOL];
-  const int c = blockIdx.x, col = (threadIdx.x % L) * CPL, rs = threadIdx.x / L;
+  const int c = d.cam_order[blockIdx.x], col = (threadIdx.x % L) * CPL, rs = threadIdx.x / L;
   const SzPanels P = sz_panels(d);
   const int pn = col / SZ_COLS, pc = col % SZ_COLS;
   const T* zr = Zr + pn * P.z + pc;
