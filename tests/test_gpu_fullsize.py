@@ -12,7 +12,7 @@ compute one by one:
   sub-problem that holds exactly the features camera c observes (those rows
   of S and b depend on no other feature), within 1e-3 relative (the bar of
   the small-scene reduced-system test: FP32 sums of thousands of records,
-  and S is a difference of two such sums);
+  and S is a difference of two such sums; the FP64 path within 1e-8);
 - properties of the whole product: symmetry y.(S x) = x.(S y) and x.(S x) > 0.
 """
 import os
@@ -170,7 +170,16 @@ def _check_records(scene, ba, tol):
 
 @pytest.mark.parametrize("cam", [17, 903])
 def test_fullsize_camera_rows_match_oracle(full, cam):
-    scene, ba = full
+    _check_camera_rows(*full, cam, tol=1e-3)
+
+
+@pytest.mark.parametrize("cam", [17, 903])
+def test_fullsize_fp64_camera_rows_match_oracle(full_fp64, cam):
+    """The same rows on the FP64 path, within 1e-8 relative."""
+    _check_camera_rows(*full_fp64, cam, tol=1e-8)
+
+
+def _check_camera_rows(scene, ba, cam, tol):
     sub, pts, lns = features_of_camera(scene, cam)
     prob = lm.Problem(sub)
     lin = lm.linearize(prob, prob.state0())
@@ -181,16 +190,16 @@ def test_fullsize_camera_rows_match_oracle(full, cam):
     # b_c and the damped diagonal block S_cc
     b, Sc, _, _ = ba.export_reduced()
     b_or = t["b"][rows]
-    assert np.linalg.norm(b[rows] - b_or) <= 1e-3 * np.linalg.norm(b_or), (cam, np.linalg.norm(b[rows] - b_or) / np.linalg.norm(b_or))
+    assert np.linalg.norm(b[rows] - b_or) <= tol * np.linalg.norm(b_or), (cam, np.linalg.norm(b[rows] - b_or) / np.linalg.norm(b_or))
     U = t["U"][rows][:, rows].toarray() + LAM * np.diag(lin.D[rows])
     S_cc = U - t["WVW"][rows][:, rows].toarray()
-    assert np.linalg.norm(Sc[cam] - S_cc) <= 1e-3 * np.linalg.norm(S_cc), cam
+    assert np.linalg.norm(Sc[cam] - S_cc) <= tol * np.linalg.norm(S_cc), (cam, np.linalg.norm(Sc[cam] - S_cc) / np.linalg.norm(S_cc))
     # (S x)_c for a random x over all of A
     x = np.random.default_rng(cam).normal(size=nA)
     y = ba.schur_matvec(x)[rows]
     y_or = (t["U"][rows] @ x + LAM * lin.D[rows] * x[rows] - t["WVW"][rows] @ x)
-    assert np.linalg.norm(y - y_or) <= 1e-3 * np.linalg.norm(y_or), (cam, np.linalg.norm(y - y_or) / np.linalg.norm(y_or))
-    print(f"[fullsize] camera {cam}: {len(pts)} points, {len(lns)} lines, rows of b, S and S x match", flush=True)
+    assert np.linalg.norm(y - y_or) <= tol * np.linalg.norm(y_or), (cam, np.linalg.norm(y - y_or) / np.linalg.norm(y_or))
+    print(f"[fullsize] camera {cam}: {len(pts)} points, {len(lns)} lines, rows of b, S and S x match within {tol:g}", flush=True)
 
 
 def test_fullsize_product_is_symmetric_positive(full):
