@@ -442,14 +442,12 @@ def residuals(state, rec, fam, cx, cy):
     return np.real(fn(gather(state, rec, fam), rec, cx, cy))
 
 
-# Nearly degenerate image lines (a reading: the paper does not treat the
-# case).  At a line through the camera centre, or one lying in the camera's
-# principal plane, the image line has no direction: rho of Eq. 4 and the
-# distance of Eq. 12 stay bounded but are not differentiable, and their
-# derivatives grow like the inverse of the image-line normal.  Below this
-# relative normal a line-projection record keeps its residual, and its
-# Jacobian is scaled by (normal / DEGENERATE_IMAGE_LINE): the same direction,
-# with the magnitude it has at the threshold (continuous there).
+# Nearly degenerate image lines.  At a line through a camera's centre, or one
+# lying in its principal plane, the image line has no direction: rho of Eq. 4
+# and the distances of Eqs. 8 and 12 stay bounded there, and their derivatives
+# grow like the inverse of the image-line normal.  The oracle differentiates
+# the residuals exactly at every configuration; the functions below only
+# measure how close a record is to that case (a diagnostic the solver reports).
 DEGENERATE_IMAGE_LINE = 1e-3
 
 
@@ -485,7 +483,8 @@ def line_record_normal(state, rec, fam):
 
 
 def degenerate_line_records(state, rec, fam):
-    """Mask of the records whose Jacobian jacobians() scales down."""
+    """Mask of the line-projection records whose relative image-line normal
+    is below DEGENERATE_IMAGE_LINE (diagnostic only)."""
     return line_record_normal(state, rec, fam) < DEGENERATE_IMAGE_LINE
 
 
@@ -493,11 +492,10 @@ def jacobians(state, rec, fam, cx, cy, camera_dof=9, h=1e-30):
     """Complex-step Jacobians of a family w.r.t. each of its parameter blocks.
 
     Returns {block: (n, rows, dof)}.  The tangent step is first order, which
-    is all a derivative at zero sees.  Records at a nearly degenerate image
-    line have their rows scaled by normal / DEGENERATE_IMAGE_LINE."""
+    is all a derivative at zero sees; the result is the exact derivative of
+    the residual up to rounding, at every configuration."""
     fn, rows, blocks = FAMILIES[fam]
     n = len(next(iter(rec.values())))
-    scale = np.minimum(line_record_normal(state, rec, fam) / DEGENERATE_IMAGE_LINE, 1.0)
     out = {}
     for b, _, dof in blocks:
         if b == "cam":
@@ -507,7 +505,7 @@ def jacobians(state, rec, fam, cx, cy, camera_dof=9, h=1e-30):
             g = gather(state, rec, fam)
             g.perturb(b, k, 1j * h)
             J[:, :, k] = np.imag(fn(g, rec, cx, cy)) / h
-        out[b] = J * scale[:, None, None]
+        out[b] = J
     return out
 
 

@@ -313,34 +313,40 @@ template <int FAM, typename T, int CD> __global__ __launch_bounds__(256) void k_
       if constexpr (FAM == 7) jac_R7<T, CD>(C, L, mT, r, Jc, Jf);
     }
   }
-  // nearly degenerate image line: FP64 Jacobian below FP64_IMAGE_LINE, scaled
-  // below DEGENERATE_IMAGE_LINE; a Jacobian that is still not finite in T is
-  // dropped (the residual stays in the cost either way)
+  // nearly degenerate image line (relative normal below DEGENERATE_IMAGE_LINE):
+  // counted.  The FP64 path keeps the exact Jacobian.  The FP32 path evaluates
+  // it in FP64 below FP64_IMAGE_LINE and scales it by rel / DEGENERATE_IMAGE_LINE
+  // below the threshold; a Jacobian that is still not finite in T is dropped
+  // (the residual stays in the cost either way)
   double jscale = 1.0;
+  bool degenerate = false;
   if constexpr (FAM == 2 || FAM == 4 || FAM == 7) {
     const double rel = line_record_normal<FAM>(d, i, f);
-    if constexpr ((FAM == 2 || FAM == 7) && sizeof(T) < sizeof(double)) {
-      if (rel < FP64_IMAGE_LINE) {
-        double m64[4] = {0, 0, 0, 0}, r64j[4], jc64[F::ROWS * SL::NC], jf64[F::ROWS * 4];
+    degenerate = rel < DEGENERATE_IMAGE_LINE;
+    if constexpr (sizeof(T) < sizeof(double)) {
+      if constexpr (FAM == 2 || FAM == 7) {
+        if (rel < FP64_IMAGE_LINE) {
+          double m64[4] = {0, 0, 0, 0}, r64j[4], jc64[F::ROWS * SL::NC], jf64[F::ROWS * 4];
 #pragma unroll
-        for (int k = 0; k < F::MEAS; ++k) m64[k] = d.fmeas[FAM][i * F::MEAS + k];
-        const Cam<double> C64 = load_cam<double>(d.cam64 + (int64_t)CAM_STRIDE * d.fcam[FAM][i]);
-        const Line<double> L64 = load_line<double>(d.ln64 + (int64_t)LN_STRIDE * f);
-        if constexpr (FAM == 2) jac_R2<double, CD>(C64, L64, m64, r64j, jc64, jf64);
-        else jac_R7<double, CD>(C64, L64, m64, r64j, jc64, jf64);
+          for (int k = 0; k < F::MEAS; ++k) m64[k] = d.fmeas[FAM][i * F::MEAS + k];
+          const Cam<double> C64 = load_cam<double>(d.cam64 + (int64_t)CAM_STRIDE * d.fcam[FAM][i]);
+          const Line<double> L64 = load_line<double>(d.ln64 + (int64_t)LN_STRIDE * f);
+          if constexpr (FAM == 2) jac_R2<double, CD>(C64, L64, m64, r64j, jc64, jf64);
+          else jac_R7<double, CD>(C64, L64, m64, r64j, jc64, jf64);
 #pragma unroll
-        for (int k = 0; k < F::ROWS * SL::NC; ++k) Jc[k] = (T)jc64[k];
+          for (int k = 0; k < F::ROWS * SL::NC; ++k) Jc[k] = (T)jc64[k];
 #pragma unroll
-        for (int k = 0; k < F::ROWS * 4; ++k) Jf[k] = (T)jf64[k];
+          for (int k = 0; k < F::ROWS * 4; ++k) Jf[k] = (T)jf64[k];
+        }
       }
+      jscale = fmin(1.0, rel / DEGENERATE_IMAGE_LINE);
     }
-    jscale = fmin(1.0, rel / DEGENERATE_IMAGE_LINE);
   }
   bool finite = true;
 #pragma unroll
   for (int k = 0; k < SL::USED; ++k) finite = finite && isfinite(v[k]);
   if (!finite) jscale = 0.0;
-  if (jscale < 1.0) atomicAdd(&d.scal[SC_NDEG], 1.0);
+  if (degenerate || !finite) atomicAdd(&d.scal[SC_NDEG], 1.0);
   // residual in FP64 from the FP64 parameters, robust IRLS scale
   double r64[F::ROWS];
   residual64<FAM>(d, i, d.cam64, d.pt64, d.ln64, d.pl64, d.vp64, r64);
