@@ -141,18 +141,22 @@ typedef struct {
   int32_t matvec_count;          /* number of those products */
   int32_t coarse;                /* columns of the coarse space used by this step's PCG (0: block-Jacobi) */
   int32_t pcg_flags;             /* BA_PCG_* bits */
-  int32_t n_degenerate;          /* records of this step's linearisation whose Jacobian was
-                                    scaled or dropped: a line-projection record (R2, R4, R7) at a
-                                    nearly degenerate image line, normal |(l1, l2)| = rel (|m| +
-                                    |t| |d|) with rel < 1e-3 (the line passes close to the camera
-                                    centre or lies near its principal plane), has its Jacobian
-                                    scaled by rel / 1e-3; a record whose working-precision
-                                    Jacobian is not finite has it dropped.  Residuals stay in the
-                                    cost. */
+  int32_t n_degenerate;          /* line-projection records (R2, R4, R7) of this step's
+                                    linearisation at a nearly degenerate image line: normal
+                                    |(l1, l2)| = rel (|m| + |t| |d|) with rel < 1e-3 (the line
+                                    passes close to the camera centre or lies near its principal
+                                    plane; Eqs. 4, 8 and 12 stay differentiable, with derivatives
+                                    growing like 1 / rel).  The FP64 path keeps their exact
+                                    Jacobian; the FP32 path evaluates it in FP64 and scales it by
+                                    rel / 1e-3 before storing it in FP32.  Also counted: records
+                                    whose working-precision Jacobian is not finite (dropped).
+                                    Residuals stay in the cost. */
   double grad_inf;               /* |g|_inf of the linearisation this step used: g = J^T W r, the
                                     gradient of E in the local coordinates of every camera,
                                     point, line, plane and VP (FP64 for the A side, the working
                                     precision for the features) */
+  int32_t n_fp64_failed;         /* of n_fp64_blocks, feature blocks whose FP64 Cholesky failed too:
+                                    their inverse is zero, so the feature does not move this step */
 } ba_step_report;
 
 typedef struct {
@@ -324,6 +328,7 @@ ba_status ba_export_gnn_graph(ba_handle *h, int32_t *n_nodes, int32_t *n_edges, 
  * implicit-Schur product (n_A products: meant for small systems, e.g.
  * training data and tests).  Temporary device memory: 8 n_A^2 bytes. */
 ba_status ba_export_schur_dense(ba_handle *h, double *S);
+
 
 /* The 7 similarity-gauge directions of the reduced parameters at the current
  * parameters (world rotation about x, y, z; translation along x, y, z;

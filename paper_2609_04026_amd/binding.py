@@ -55,7 +55,8 @@ class StepReport(ctypes.Structure):
                 ("accepted", c_int32), ("pcg_iters", c_int32), ("pcg_rel_residual", c_double),
                 ("n_fp64_blocks", c_int32), ("relinearized", c_int32), ("ms", c_double * 8),
                 ("matvec_ms", c_double), ("matvec_count", c_int32), ("coarse", c_int32),
-                ("pcg_flags", c_int32), ("n_degenerate", c_int32), ("grad_inf", c_double)]
+                ("pcg_flags", c_int32), ("n_degenerate", c_int32), ("grad_inf", c_double),
+                ("n_fp64_failed", c_int32)]
 
 
 class GnnBatch(ctypes.Structure):

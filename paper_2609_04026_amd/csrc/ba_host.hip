@@ -813,6 +813,7 @@ void linearize_all(ba_handle* h) {
 // damped feature inverses, b_a and the diagonal blocks of S
 void assemble_schur(ba_handle* h, double lambda, double kappa_max) {
   launch_zero(h->d.scal + SC_NFLAG, sizeof(double), h->stream);
+  launch_zero(h->d.scal + SC_NFAIL, sizeof(double), h->stream);
   launch_feature_invert(h->d, lambda, kappa_max, h->stream);
   launch_camera_pass_b(h->d, lambda, h->stream);
   check_launch("assemble");
@@ -1043,6 +1044,7 @@ bool do_step(ba_handle* h, const ba_solve_options& o, ba_step_report* rep, doubl
   if (!std::isfinite(bb)) r.pcg_flags |= BA_PCG_NONFINITE_RHS;
   r.pcg_rel_residual = bb > 0 ? std::sqrt(rr / bb) : 0.0;
   r.n_fp64_blocks = (int)h->hscal[SC_NFLAG];
+  r.n_fp64_failed = (int)h->hscal[SC_NFAIL];
   r.n_degenerate = (int)h->hscal[SC_NDEG];
   r.grad_inf = h->hscal[SC_GINF];
   launch_backsub(h->d, h->stream);

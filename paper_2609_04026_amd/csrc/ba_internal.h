@@ -131,11 +131,12 @@ enum PcgScal {
   SC_COARSE,  // 1: the coarse correction of the preconditioner is active for this solve
   SC_NDEG,    // records of the current linearisation with a scaled or dropped Jacobian
   SC_GINF,    // |g|_inf of the current linearisation
+  SC_NFAIL,   // feature blocks whose FP64 Cholesky failed too (zero inverse)
   // PCG accumulators, three sets rotated by iteration (k mod 3): p.q, r.r, r.(M r),
   // Z^T r, (S Z)^T (M r)
-  SC_ACC = 20, SC_COUNT = 128
+  SC_ACC = 24, SC_COUNT = 128
 };
-static_assert(SC_GINF < SC_ACC, "single scalars overlap the PCG accumulators");
+static_assert(SC_NFAIL < SC_ACC, "single scalars overlap the PCG accumulators");
 // coarse space of the two-level preconditioner: 7 similarity-gauge columns, then the
 // network's columns
 constexpr int COARSE_GAUGE = 7, COARSE_NET = 8, COARSE_K = COARSE_GAUGE + COARSE_NET;

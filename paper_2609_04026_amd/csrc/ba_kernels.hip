@@ -624,7 +624,7 @@ template <typename T, int CD, int NF> __device__ __forceinline__ int feature_inv
     for (int j = i; j < NF; ++j) { Vio64[sym<NF>(i, j)] = Bi[i][j]; Vio[sym<NF>(i, j)] = (T)Bi[i][j]; }
   }
   *flag = ok64 ? 1 : 2;
-  return 1;
+  return ok64 ? 1 : 2;
 }
 
 template <typename T, int CD> __global__ __launch_bounds__(256) void k_feat_inv(Dev d, int ptiles, double lam, double kmax) {
@@ -637,13 +637,18 @@ template <typename T, int CD> __global__ __launch_bounds__(256) void k_feat_inv(
     const int f = (blockIdx.x - ptiles) * blockDim.x + threadIdx.x;
     if (f < d.nl) nf = feature_invert_one<T, CD, 4>(d, f, lam, kmax);
   }
-  double c = wave_sum((double)nf);
-  if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = c;
+  // FP64 re-inversions (flag 1 or 2) and, of those, failed FP64 Cholesky (flag 2)
+  const double c = wave_sum((double)(nf != 0)), c2 = wave_sum((double)(nf == 2));
+  if ((threadIdx.x & 63) == 0) {
+    lds[threadIdx.x >> 6] = c;
+    lds[4 + (threadIdx.x >> 6)] = c2;
+  }
   __syncthreads();
   if (threadIdx.x == 0) {
-    double t = 0;
-    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) t += lds[k];
+    double t = 0, t2 = 0;
+    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) { t += lds[k]; t2 += lds[4 + k]; }
     if (t > 0) atomicAdd(&d.scal[SC_NFLAG], t);
+    if (t2 > 0) atomicAdd(&d.scal[SC_NFAIL], t2);
   }
 }
 
