@@ -2,7 +2,10 @@
 
 Calls only the oracle (FP64 LM with exact Schur solves) on the seeded
 scenes; the GPU tests compare their converged cost with these values.
-Run from the repository root:  python tests/golden/make_oracle_values.py
+Run from the repository root:
+    python tests/golden/make_oracle_values.py [scene names]
+With names, only those entries are recomputed (the 200-camera scene takes
+about 40 s per LM iteration on 8 cores); without, every scene.
 """
 import json
 import os
@@ -19,16 +22,19 @@ SCENES = {
     "tiny_holistic": lambda: make_scene(small_config(n_cams=9, n_points=70, n_lines=20), seed=101),
     "points_10cam": lambda: make_scene(1),
     "holistic_30cam": lambda: make_scene(2),
+    "holistic_200cam": lambda: make_scene(3),
 }
 
 if __name__ == "__main__":
-    out = {}
-    for name, fn in SCENES.items():
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "oracle_converged.json")
+    names = sys.argv[1:] or list(SCENES)
+    out = json.load(open(path)) if os.path.exists(path) else {}
+    for name in names:
         t = time.time()
-        prob = lm.Problem(fn())
-        res = lm.lm_solve(prob, func_tol=1e-12, max_iters=200)
+        prob = lm.Problem(SCENES[name]())
+        res = lm.lm_solve(prob, func_tol=1e-12, max_iters=200, verbose=name == "holistic_200cam")
         out[name] = dict(E=res["E"], Epix=res["Epix"], iters=res["iters"], accepted=res["accepted"],
                          reason=res["reason"], seconds=round(time.time() - t, 1))
         print(name, out[name], flush=True)
-    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "oracle_converged.json"), "w") as f:
-        json.dump(out, f, indent=1)
+        with open(path, "w") as f:
+            json.dump(out, f, indent=1)
