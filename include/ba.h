@@ -329,6 +329,16 @@ ba_status ba_export_gnn_graph(ba_handle *h, int32_t *n_nodes, int32_t *n_edges, 
  * training data and tests).  Temporary device memory: 8 n_A^2 bytes. */
 ba_status ba_export_schur_dense(ba_handle *h, double *S);
 
+/* ba_export_schur_dense for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same S, formed by the same products, but staged through a
+ * fixed per-GPU scratch panel of 2^19 doubles (4 MiB, held until the process
+ * ends) in column panels of floor(2^19 / n_A) columns, each copied to S before
+ * the next.  Calls no hipMalloc / hipFree.  BA_E_INVALID when n_A > 2^19;
+ * BA_E_STATE before the first linearisation.  Every handle on one GPU shares
+ * that GPU's panel: calls that overlap on one GPU (from different threads)
+ * race and must be serialised by the caller. */
+ba_status ba_export_schur_dense_noalloc(ba_handle *h, double *S);
 
 /* The 7 similarity-gauge directions of the reduced parameters at the current
  * parameters (world rotation about x, y, z; translation along x, y, z;

@@ -108,6 +108,7 @@ def _load():
         "ba_export_gnn_graph": (c_int32, [H, I32, I32, F, I32, I32, F, I32, I32, I32, F]),
         "ba_normalized_matvec": (c_int32, [H, D, D]),
         "ba_export_schur_dense": (c_int32, [H, D]),
+        "ba_export_schur_dense_noalloc": (c_int32, [H, D]),
         "ba_export_gauge_basis": (c_int32, [H, D]),
         "ba_export_coarse_space": (c_int32, [H, I32, D, D]),
         "ba_gnn_create": (c_int32, [c_int32, c_int32, c_int32, POINTER(c_void_p)]),
@@ -329,6 +330,14 @@ class BA:
         nA, _ = self.reduced_dim()
         S = np.zeros((nA, nA))
         self._check(_lib.ba_export_schur_dense(self._h, _dp(S)))
+        return S
+
+    def export_schur_dense_noalloc(self):
+        """The same S staged through the library's fixed device scratch panel
+        (no device allocation in the call)."""
+        nA, _ = self.reduced_dim()
+        S = np.zeros((nA, nA))
+        self._check(_lib.ba_export_schur_dense_noalloc(self._h, _dp(S)))
         return S
 
     def export_gauge_basis(self):

@@ -11,6 +11,8 @@
 #include <cstdlib>
 #include <cstring>
 #include <functional>
+#include <map>
+#include <mutex>
 #include <numeric>
 #include <stdexcept>
 #include <string>
@@ -21,6 +23,13 @@
 #include "ba_gnn.h"
 
 using namespace ba;
+
+// Device scratch of ba_export_schur_dense_noalloc: one panel of columns of the
+// reduced matrix is formed here and copied out before the next.  Each GPU the
+// library runs on holds its own copy until the process ends; in host code the
+// name is only a stand-in, the device address comes from hipGetSymbolAddress.
+constexpr int64_t NOALLOC_SCRATCH_DOUBLES = int64_t(1) << 19;  // 4 MiB
+static __device__ __align__(256) double scratch[NOALLOC_SCRATCH_DOUBLES];
 
 namespace {
 
@@ -37,6 +46,21 @@ struct BaError : std::runtime_error {
   } while (0)
 
 constexpr int PCG_CHECK_EVERY = 8;
+
+// device address of `scratch` per device, taken once with that device current
+std::mutex g_scratch_mu;
+std::map<int, double*> g_scratch_ptr;
+
+double* noalloc_scratch(int device) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  auto it = g_scratch_ptr.find(device);
+  if (it != g_scratch_ptr.end()) return it->second;
+  void* p = nullptr;
+  HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+  if (!p) throw BaError(BA_E_DEVICE, "no device address for the no-allocation scratch");
+  g_scratch_ptr[device] = static_cast<double*>(p);
+  return static_cast<double*>(p);
+}
 
 // ---------------------------------------------------------------------------
 // parameter conversions (FP64, host)
@@ -1140,6 +1164,7 @@ ba_status ba_create(const ba_problem_desc* desc, ba_handle** out) {
     HIPCHK(hipGetDeviceCount(&ndev));
     if (h->device < 0 || h->device >= ndev) throw BaError(BA_E_INVALID, "bad device index");
     set_device(h);
+    noalloc_scratch(h->device);
     if (desc->hip_stream) {
       h->stream = (hipStream_t)desc->hip_stream;
     } else {
@@ -1599,6 +1624,29 @@ ba_status ba_export_schur_dense(ba_handle* h, double* S) {
       throw;
     }
     HIPCHK(hipFree(Sd));
+  });
+}
+
+ba_status ba_export_schur_dense_noalloc(ba_handle* h, double* S) {
+  if (!h || !S) return BA_E_INVALID;
+  return guard(h, [&] {
+    if (!h->finalized) throw BaError(BA_E_STATE, "no linearisation yet");
+    set_device(h);
+    const Dev& d = h->d;
+    if (d.nA == 0) return;
+    if (d.nA > NOALLOC_SCRATCH_DOUBLES)
+      throw BaError(BA_E_INVALID, "reduced dimension " + std::to_string(d.nA) + " exceeds the no-allocation limit of " +
+                                      std::to_string(NOALLOC_SCRATCH_DOUBLES));
+    double* panel = noalloc_scratch(h->device);
+    const int cols = (int)std::min<int64_t>(NOALLOC_SCRATCH_DOUBLES / d.nA, d.nA);
+    for (int c0 = 0; c0 < d.nA; c0 += cols) {
+      const int nc = std::min(cols, d.nA - c0);
+      launch_dense_schur_columns(d, h->last_lambda, c0, nc, panel, h->stream);
+      check_launch("dense reduced system (no allocation)");
+      HIPCHK(hipMemcpyAsync(S + (int64_t)c0 * d.nA, panel, (size_t)nc * d.nA * sizeof(double), hipMemcpyDeviceToHost,
+                            h->stream));
+      sync(h);
+    }
   });
 }
 

@@ -170,6 +170,8 @@ void launch_pcg_update(const Dev& d, double lambda, int iter, hipStream_t s);  /
 void launch_schur_matvec(const Dev& d, const double* xin, double* yout, double lambda, hipStream_t s);
 // S (nA x nA, device; column c = S e_c) by nA products
 void launch_dense_schur(const Dev& d, double lambda, double* S, hipStream_t s);
+// columns c0 .. c0 + ncols - 1 of the damped reduced matrix into S (ncols x n_A)
+void launch_dense_schur_columns(const Dev& d, double lambda, int c0, int ncols, double* S, hipStream_t s);
 // gauge columns of d.Zc from the current parameters
 void launch_gauge_basis(const Dev& d, hipStream_t s);
 // S Z and E = Z^T S Z for the first d.coarse_k columns of d.Zc, E^-1 and SC_COARSE

@@ -1870,11 +1870,15 @@ __global__ void k_unit_vector(double* v, int n, int c) {
   for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) v[e] = e == c ? 1.0 : 0.0;
 }
 
-void launch_dense_schur(const Dev& d, double lambda, double* S, hipStream_t s) {
-  for (int c = 0; c < d.nA; ++c) {
-    k_unit_vector<<<std::min(64u, nblk(d.nA, 256)), 256, 0, s>>>(d.z, d.nA, c);
+void launch_dense_schur_columns(const Dev& d, double lambda, int c0, int ncols, double* S, hipStream_t s) {
+  for (int c = 0; c < ncols; ++c) {
+    k_unit_vector<<<std::min(64u, nblk(d.nA, 256)), 256, 0, s>>>(d.z, d.nA, c0 + c);
     launch_schur_matvec(d, d.z, S + (int64_t)c * d.nA, lambda, s);
   }
+}
+
+void launch_dense_schur(const Dev& d, double lambda, double* S, hipStream_t s) {
+  launch_dense_schur_columns(d, lambda, 0, d.nA, S, s);
 }
 
 // E[a][b] = Z_a . (S Z)_b for the active columns, one workgroup per entry
