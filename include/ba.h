@@ -65,7 +65,20 @@ typedef enum { BA_PREC_FP64 = 0, BA_PREC_MIXED = 1 } ba_precision;
  * block-Jacobi alone without weights or graph). */
 typedef enum { BA_PC_BLOCK_JACOBI = 0, BA_PC_LEARNED = 1, BA_PC_GAUGE = 2 } ba_precond;
 
-/* Observation / association kinds accepted by ba_add_observations. */
+/* Observation / association kinds accepted by ba_add_observations, and the
+ * residual families each creates (expanded at the first step):
+ *  - BA_OBS_POINT: the measurement x_ij of Sec. 3.1 Eq. 1 (point
+ *    reprojection, R1); its undistorted copy is the observed point of the
+ *    line-to-point distance of Sec. 3.4 Eq. 12 (R7).
+ *  - BA_OBS_LINE: the endpoints of the observed segment l_ik, for the
+ *    perpendicular endpoint vectors of Sec. 3.2 Eq. 4 (R2); their joining
+ *    line is the observed line of Sec. 3.4 Eq. 11 (R6).
+ *  - BA_ASSOC_PLANE_POINT / _PLANE_LINE: coplanarity groups, one record per
+ *    view of the member (Sec. 3.3 Eq. 7, R3; Eq. 8 with the App. B
+ *    plane-line projection, R4).
+ *  - BA_ASSOC_VP_LINE: parallelism group (Sec. 3.3 Eq. 6, R5).
+ *  - BA_ASSOC_JUNCTION: point-line incidence, one record per view that sees
+ *    exactly one of the two (Sec. 3.4 Eqs. 11 and 12, R6 / R7). */
 typedef enum {
   BA_OBS_POINT = 0,         /* a = camera, b = point; meas[4] = x y (distorted px), xu yu (undistorted px) */
   BA_OBS_LINE = 1,          /* a = camera, b = line;  meas[4] = e1x e1y e2x e2y (undistorted px)            */
@@ -118,6 +131,15 @@ typedef struct {
   double kappa_max;       /* FP32 feature blocks with estimated condition above it are redone in FP64; 1e4 */
   int32_t time_kernels;   /* 1: time every implicit-Schur product launch with HIP events
                              (ba_step_report.matvec_ms / matvec_count); 0 */
+  int32_t deterministic;  /* 1: every sum of the step is taken in a fixed order, so that the
+                             same inputs give bit-identical results run after run: the
+                             implicit-Schur product forms s_f per feature and then each
+                             camera / group row of S x over its records in a fixed order
+                             (instead of FP64 LDS atomics), and the PCG dot products are
+                             summed per workgroup and then in workgroup order (instead of
+                             one FP64 atomic per workgroup).  Slower; 0 (the default)
+                             keeps the atomics.  The network's message aggregation of the
+                             learned preconditioner still sums with FP32 atomics. */
 } ba_solve_options;
 
 enum {

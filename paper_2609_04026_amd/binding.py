@@ -46,7 +46,7 @@ class ProblemDesc(ctypes.Structure):
 class SolveOptions(ctypes.Structure):
     _fields_ = [("max_iters", c_int32), ("func_tol", c_double), ("grad_tol", c_double), ("pcg_tol", c_double),
                 ("pcg_max_iters", c_int32), ("lambda0", c_double), ("nu0", c_double), ("kappa_max", c_double),
-                ("time_kernels", c_int32)]
+                ("time_kernels", c_int32), ("deterministic", c_int32)]
 
 
 class StepReport(ctypes.Structure):

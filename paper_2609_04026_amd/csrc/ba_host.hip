@@ -797,6 +797,13 @@ void finalize(ba_handle* h) {
   d.cnt = A.get<unsigned int>(4);
   launch_zero(d.cnt, 4 * sizeof(unsigned int), h->stream);
   d.part2 = A.get<double>(2 * ((size_t)nA / 64 + 2) + 256);
+  // deterministic mode: per-workgroup partials of every accumulator (the widest PCG
+  // kernel has one workgroup per 64 entries) and the product's s_f
+  d.det_stride = (int)std::max<int64_t>(1, ((int64_t)nA + 63) / 64);
+  d.detp = A.get<double>((size_t)(SC_COUNT + COARSE_K) * d.det_stride);
+  launch_zero(d.detp, (size_t)(SC_COUNT + COARSE_K) * d.det_stride * sizeof(double), h->stream);
+  d.sdp = A.get<char>((size_t)h->np * 3, TS);
+  d.sdl = A.get<char>((size_t)h->nl * 4, TS);
   launch_zero(d.mv_part, (d.mv_lds ? (size_t)d.n_mv_wg * nA : (size_t)nA) * sizeof(double), h->stream);
   d.scal = A.get<double>(SC_COUNT);
   launch_zero(d.scal, SC_COUNT * sizeof(double), h->stream);
@@ -1014,6 +1021,7 @@ ba_solve_options opts_or_default(const ba_solve_options* o) {
 bool do_step(ba_handle* h, const ba_solve_options& o, ba_step_report* rep, double stop_grad = 0) {
   set_device(h);
   if (!h->finalized) finalize(h);
+  h->d.det = o.deterministic ? 1 : 0;
   if (h->first_step) {
     h->lambda = o.lambda0;
     h->nu = o.nu0;
@@ -1137,6 +1145,7 @@ void ba_default_options(ba_solve_options* o) {
   o->nu0 = 2.0;
   o->kappa_max = 1e4;
   o->time_kernels = 0;
+  o->deterministic = 0;
 }
 
 ba_status ba_create(const ba_problem_desc* desc, ba_handle** out) {

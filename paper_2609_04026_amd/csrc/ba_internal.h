@@ -116,6 +116,12 @@ struct Dev {
   // features too large for one tile (handled one lane per feature)
   int n_bigp = 0, n_bigl = 0;
   int32_t *bigp = nullptr, *bigl = nullptr;
+  // deterministic mode: the product's s_f per feature (T; points x 3, lines x 4) and the
+  // per-workgroup partials of the PCG dot products (det_stride workgroups per accumulator:
+  // the SC_COUNT scalars, then the COARSE_K entries of Z^T b)
+  int det = 0, det_stride = 0;
+  void *sdp = nullptr, *sdl = nullptr;
+  double* detp = nullptr;
   unsigned int *cnt = nullptr;  // grid-wide "last workgroup" counters (zeroed, self-resetting)
   double *part2 = nullptr;      // per-workgroup partial dot products of the PCG kernels
 };

@@ -1222,6 +1222,28 @@ template <typename T, int CD, int NF> __device__ __forceinline__ void mv_feature
   }
 }
 
+// deterministic product, first pass: s_f = (V_f + lambda D_f)^-1 J_f^T J_a x of one feature
+template <typename T, int CD, int NF> __device__ __forceinline__ void mv_feature_s(const Dev& d, int f, const T* x) {
+  T q[NF];
+#pragma unroll
+  for (int k = 0; k < NF; ++k) q[k] = 0;
+  if constexpr (NF == 3) {
+    mv_first<1, T, CD, 3>(d, f, x, q);
+    mv_first<3, T, CD, 3>(d, f, x, q);
+    mv_first<6, T, CD, 3>(d, f, x, q);
+  } else {
+    mv_first<2, T, CD, 4>(d, f, x, q);
+    mv_first<4, T, CD, 4>(d, f, x, q);
+    mv_first<5, T, CD, 4>(d, f, x, q);
+    mv_first<7, T, CD, 4>(d, f, x, q);
+  }
+  T sv[NF];
+  apply_vinv<T, NF>(d, f, q, sv);
+  T* o = (T*)(NF == 3 ? d.sdp : d.sdl) + (int64_t)NF * f;
+#pragma unroll
+  for (int k = 0; k < NF; ++k) o[k] = sv[k];
+}
+
 // ---------------------------------------------------------------------------
 // Wavefront-tiled implicit-Schur product.  A tile is a run of consecutive
 // features (points, or lines) with at most 64 records over all their families,
@@ -1344,7 +1366,9 @@ __device__ __forceinline__ void feature_solve(const Dev& d, int f, bool flag, co
   for (int a = 0; a < 4; ++a) s[a] = a < NF ? sn[a] : T(0);
 }
 
-template <typename T, int CD, bool LDSY>
+// With SONLY (the deterministic mode's first pass) a tile stops after B: the feature's
+// last lane stores s_f (d.sdp / d.sdl) and nothing is added to y.
+template <typename T, int CD, bool LDSY, bool SONLY = false>
 __global__ __launch_bounds__(MV_THREADS) void k_mv_wave(Dev d, const double* done) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   if (done && *done != 0.0) return;
@@ -1419,6 +1443,18 @@ __global__ __launch_bounds__(MV_THREADS) void k_mv_wave(Dev d, const double* don
       if (ptile) feature_solve<T, 3>(d, fb + lf, mflag, Mi, q, s);
       else feature_solve<T, 4>(d, fb + lf, mflag, Mi, q, s);
     }
+    if constexpr (SONLY) {
+      if (last) {
+        if (ptile) {
+          T* o = (T*)d.sdp + 3 * (int64_t)(fb + lf);
+          o[0] = s[0]; o[1] = s[1]; o[2] = s[2];
+        } else {
+          T* o = (T*)d.sdl + 4 * (int64_t)(fb + lf);
+          o[0] = s[0]; o[1] = s[1]; o[2] = s[2]; o[3] = s[3];
+        }
+      }
+      continue;
+    }
     const int src = lf >= 0 ? __builtin_ctzll(lasts & (~0ull << lane)) : lane;
 #pragma unroll
     for (int a = 0; a < 4; ++a) s[a] = __shfl(s[a], src, 64);
@@ -1448,8 +1484,13 @@ __global__ __launch_bounds__(MV_THREADS) void k_mv_wave(Dev d, const double* don
   }
   // features whose records do not fit one tile: one lane per feature
   for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < d.n_bigp + d.n_bigl; k += gridDim.x * blockDim.x) {
-    if (k < d.n_bigp) mv_feature<T, CD, 3>(d, d.bigp[k], x, ys);
-    else mv_feature<T, CD, 4>(d, d.bigl[k - d.n_bigp], x, ys);
+    if constexpr (SONLY) {
+      if (k < d.n_bigp) mv_feature_s<T, CD, 3>(d, d.bigp[k], x);
+      else mv_feature_s<T, CD, 4>(d, d.bigl[k - d.n_bigp], x);
+    } else {
+      if (k < d.n_bigp) mv_feature<T, CD, 3>(d, d.bigp[k], x, ys);
+      else mv_feature<T, CD, 4>(d, d.bigl[k - d.n_bigp], x, ys);
+    }
   }
   if constexpr (LDSY) {
     __syncthreads();
@@ -1482,9 +1523,19 @@ template <typename T, int CD, bool LDSY> static void launch_mv(const Dev& d, con
   k_mv_wave<T, CD, LDSY><<<d.n_mv_wg, MV_THREADS, matvec_lds_bytes(d), s>>>(d, done);
 }
 
+// deterministic product, second pass (defined with the S Z sweeps, whose record and
+// block-sum helpers it shares): every row of y from its records in a fixed order
+template <typename T, int CD> void launch_det_rows(const Dev& d, const double* done, hipStream_t s);
+
 template <typename T, int CD> static void run_matvec(const Dev& d, const double* done, hipStream_t s) {
-  if (d.mv_lds) launch_mv<T, CD, true>(d, done, s);
-  else launch_mv<T, CD, false>(d, done, s);
+  if (d.det) {
+    k_mv_wave<T, CD, false, true><<<d.n_mv_wg, MV_THREADS, 0, s>>>(d, done);
+    launch_det_rows<T, CD>(d, done, s);
+  } else if (d.mv_lds) {
+    launch_mv<T, CD, true>(d, done, s);
+  } else {
+    launch_mv<T, CD, false>(d, done, s);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1494,13 +1545,6 @@ template <typename T, int CD> static void run_matvec(const Dev& d, const double*
 // whose last reader ran in iteration k - 2.
 __device__ __forceinline__ double* acc_set(const Dev& d, int k) { return d.scal + SC_ACC + ACC_STRIDE * (k % 3); }
 
-// z_b = M_b r_b for A-block b; returns the block's offset and size
-template <int CD> __device__ __forceinline__ void block_of(const Dev& d, int b, int& o, int& n, const double*& M) {
-  if (b < d.nc) { o = CD * b; n = CD; M = d.Mcam + (int64_t)CD * CD * b; }
-  else if (b < d.nc + d.ng) { const int g = b - d.nc; o = d.offPl + 3 * g; n = 3; M = d.Mpl + 9 * g; }
-  else { const int v = b - d.nc - d.ng; o = d.offVp + 2 * v; n = 2; M = d.Mvp + 4 * v; }
-}
-
 // position of entry e of the reduced vector: its block's offset, size and preconditioner block
 template <int CD> __device__ __forceinline__ void entry_block(const Dev& d, int e, int& o, int& n, const double*& M) {
   if (e < d.offPl) { const int b = e / CD; o = CD * b; n = CD; M = d.Mcam + (int64_t)CD * CD * b; }
@@ -1508,24 +1552,41 @@ template <int CD> __device__ __forceinline__ void entry_block(const Dev& d, int 
   else { const int v = (e - d.offVp) / 2; o = d.offVp + 2 * v; n = 2; M = d.Mvp + 4 * v; }
 }
 
-template <int CD> __device__ __forceinline__ void apply_M_block(const Dev& d, int b, const double* r, double* z, double& rz) {
-  int o, n;
-  const double* M;
-  block_of<CD>(d, b, o, n, M);
-  double rr[9];
-  for (int a = 0; a < n; ++a) rr[a] = r[o + a];
-  for (int a = 0; a < n; ++a) {
-    double t = 0;
-    for (int c = 0; c < n; ++c) t += M[a * n + c] * rr[c];
-    z[o + a] = t;
-    rz += rr[a] * t;
-  }
+// Accumulator slot of dst (a scalar of d.scal, or an entry of Z^T b) in the deterministic
+// mode's partial table
+__device__ __forceinline__ int64_t det_slot(const Dev& d, const double* dst) {
+  const int64_t k = dst - d.scal;
+  return (k >= 0 && k < SC_COUNT) ? k : SC_COUNT + (dst - d.Ztb);
 }
 
-// one FP64 atomic per workgroup for each of K block sums
-template <int K> __device__ __forceinline__ void block_atomic_add(double (&v)[K], double* lds, double* const (&dst)[K]) {
+// add this workgroup's sum v to the accumulator dst: one FP64 atomic, or in the
+// deterministic mode the workgroup's entry of the partial table (k_det_sum adds them in
+// workgroup order)
+__device__ __forceinline__ void acc_add(const Dev& d, double* dst, double v) {
+  if (d.det) d.detp[det_slot(d, dst) * d.det_stride + blockIdx.x] = v;
+  else atomicAdd(dst, v);
+}
+
+// deterministic mode: accumulators [lo, lo + n) and [lo2, lo2 + n2) (slot numbers as in
+// det_slot) = the sum of their nwg workgroup partials, in workgroup order.  Skipped when
+// the PCG has stopped, like the kernels that write the partials.
+__global__ void k_det_sum(Dev d, int lo, int n, int lo2, int n2, int nwg) {
+  if (d.scal[SC_DONE] != 0.0 || d.scal[SC_BREAK] != 0.0) return;
+  const int t = threadIdx.x;
+  const int slot = t < n ? lo + t : t < n + n2 ? lo2 + (t - n) : -1;
+  if (slot < 0) return;
+  const double* p = d.detp + (int64_t)slot * d.det_stride;
+  double s = 0;
+  for (int w = 0; w < nwg; ++w) s += p[w];
+  if (slot < SC_COUNT) d.scal[slot] = s;
+  else d.Ztb[slot - SC_COUNT] = s;
+}
+
+// one FP64 atomic (or deterministic partial) per workgroup for each of K block sums
+template <int K> __device__ __forceinline__ void block_atomic_add(const Dev& d, double (&v)[K], double* lds,
+                                                                  double* const (&dst)[K]) {
   double* o = block_sum_arr<double, K>(v, lds);
-  if (threadIdx.x < K) atomicAdd(dst[threadIdx.x], o[threadIdx.x]);
+  if (threadIdx.x < K) acc_add(d, dst[threadIdx.x], o[threadIdx.x]);
 }
 
 // ---- two-level preconditioner (coarse space Z, E = Z^T S Z) -----------------
@@ -1557,22 +1618,6 @@ __device__ __forceinline__ double coarse_rz(const Dev& d, const double* A, doubl
   return rz;
 }
 
-// x = 0, r = b, z = M r, p = z; r.z -> set 2 (read as "previous r.z" by iteration 0), b.b -> SC_BB
-template <typename T, int CD> __global__ __launch_bounds__(256) void k_pcg_init(Dev d) {
-  __shared__ double lds[3 * 5];
-  const int nb = d.nc + d.ng + d.nv;
-  double v[2] = {0, 0};
-  for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < nb; b += gridDim.x * blockDim.x) {
-    int o, n;
-    const double* M;
-    block_of<CD>(d, b, o, n, M);
-    for (int a = 0; a < n; ++a) { d.x[o + a] = 0; d.r[o + a] = d.bA[o + a]; v[1] += d.bA[o + a] * d.bA[o + a]; }
-    apply_M_block<CD>(d, b, d.bA, d.z, v[0]);
-    for (int a = 0; a < n; ++a) { d.p[o + a] = d.z[o + a]; ((T*)d.xT)[o + a] = (T)d.z[o + a]; }
-  }
-  double* const dst[2] = {acc_set(d, 2) + ACC_RZ, d.scal + SC_BB};
-  block_atomic_add<2>(v, lds, dst);
-}
 
 // Ztb = Z^T b (Ztb cleared by k_pcg_reset)
 __global__ __launch_bounds__(256) void k_coarse_ztb(Dev d) {
@@ -1585,7 +1630,7 @@ __global__ __launch_bounds__(256) void k_coarse_ztb(Dev d) {
     for (int a = 0; a < d.coarse_k; ++a) v[a] += d.Zc[(int64_t)a * d.nA + e] * be;
   }
   double* o = block_sum_arr<double, COARSE_K>(v, lds);
-  if (threadIdx.x < d.coarse_k) atomicAdd(d.Ztb + threadIdx.x, o[threadIdx.x]);
+  if (threadIdx.x < d.coarse_k) acc_add(d, d.Ztb + threadIdx.x, o[threadIdx.x]);
 }
 
 // coarse start: u = E^-1 Z^T b, x0 = Z u, r0 = b - (S Z) u, z = M r0 (stored in d.z);
@@ -1593,7 +1638,7 @@ __global__ __launch_bounds__(256) void k_coarse_ztb(Dev d) {
 template <int CD> __global__ __launch_bounds__(256) void k_pcg_init_coarse(Dev d) {
   constexpr int NV = 2 + 2 * COARSE_K;
   __shared__ double lds[5 * NV];
-  const bool on = d.scal[SC_COARSE] != 0.0;
+  const bool on = d.coarse_k > 0 && d.scal[SC_COARSE] != 0.0;
   double u[COARSE_K];
   if (on) coarse_solve(d, d.Ztb, u);
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1630,7 +1675,7 @@ template <int CD> __global__ __launch_bounds__(256) void k_pcg_init_coarse(Dev d
   if (threadIdx.x < NV) {
     const int k = threadIdx.x;
     double* dst = k == 0 ? A + ACC_RZ : k == 1 ? d.scal + SC_BB : k < 2 + COARSE_K ? A + ACC_ZR + (k - 2) : A + ACC_W + (k - 2 - COARSE_K);
-    atomicAdd(dst, o2[k]);
+    acc_add(d, dst, o2[k]);
   }
 }
 
@@ -1639,7 +1684,7 @@ template <typename T> __global__ __launch_bounds__(256) void k_pcg_init_coarse2(
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= d.nA) return;
   double z = d.z[e];
-  if (d.scal[SC_COARSE] != 0.0) {
+  if (d.coarse_k > 0 && d.scal[SC_COARSE] != 0.0) {
     double y[COARSE_K];
     coarse_rz(d, acc_set(d, 2), y);
     z += coarse_combine(d, e, y);
@@ -1688,7 +1733,12 @@ template <typename T> __global__ __launch_bounds__(1024) void k_pcg_q(Dev d, con
   double* part = d.mv_part;
   double s = 0;
   if (e < d.nA) {
-    if (d.mv_lds) {
+    if (d.det) {  // the deterministic product wrote every entry of row 0
+      if (sl == 0) {
+        s = part[e];
+        if (!d.mv_lds) part[e] = 0;  // the atomic product accumulates into a zeroed row
+      }
+    } else if (d.mv_lds) {
       for (int w = sl; w < d.n_mv_wg; w += 16) s += part[(int64_t)w * d.nA + e];
     } else if (sl == 0) {
       s = part[e];
@@ -1708,7 +1758,7 @@ template <typename T> __global__ __launch_bounds__(1024) void k_pcg_q(Dev d, con
   }
   if (k < 0) return;
   double* const dst[1] = {acc_set(d, k) + ACC_PQ};
-  block_atomic_add<1>(dot, lds, dst);
+  block_atomic_add<1>(d, dot, lds, dst);
 }
 
 // alpha = rz / pq; x += alpha p, r -= alpha q; r.r (and Z^T r) -> set k   (one thread per entry)
@@ -1737,7 +1787,7 @@ template <bool COARSE> __global__ __launch_bounds__(256) void k_pcg_xr(Dev d, in
   }
   double* A = acc_set(d, k);
   double* o = block_sum_arr<double, NV>(v, lds);
-  if (threadIdx.x < NV) atomicAdd(threadIdx.x == 0 ? A + ACC_RR : A + ACC_ZR + threadIdx.x - 1, o[threadIdx.x]);
+  if (threadIdx.x < NV) acc_add(d, threadIdx.x == 0 ? A + ACC_RR : A + ACC_ZR + threadIdx.x - 1, o[threadIdx.x]);
 }
 
 // z = M r (block diagonal); r.z -> set k; with the coarse space also (S Z)^T M r
@@ -1765,7 +1815,7 @@ template <int CD, bool COARSE> __global__ __launch_bounds__(256) void k_pcg_z(De
   }
   double* A = acc_set(d, k);
   double* o = block_sum_arr<double, NV>(v, lds);
-  if (threadIdx.x < NV) atomicAdd(threadIdx.x == 0 ? A + ACC_RZ : A + ACC_W + threadIdx.x - 1, o[threadIdx.x]);
+  if (threadIdx.x < NV) acc_add(d, threadIdx.x == 0 ? A + ACC_RZ : A + ACC_W + threadIdx.x - 1, o[threadIdx.x]);
 }
 
 // beta = rz_k / rz_(k-1); p = z + beta p (z completed with the coarse term);
@@ -1825,36 +1875,48 @@ template <typename T, bool COARSE> __global__ __launch_bounds__(256) void k_pcg_
   }
 }
 
-static unsigned pcg_blocks(const Dev& d) { return std::max(1u, std::min(64u, nblk(d.nc + d.ng + d.nv, 256))); }
+// deterministic mode: sum the per-workgroup partials that a kernel of nwg workgroups just
+// wrote for accumulator slots [lo, lo + n) and [lo2, lo2 + n2)
+static void det_sum(const Dev& d, int lo, int n, int lo2, int n2, unsigned nwg, hipStream_t s) {
+  if (d.det) k_det_sum<<<1, 64, 0, s>>>(d, lo, n, lo2, n2, (int)nwg);
+}
 
+static int acc_slot(int iter, int which) { return SC_ACC + ACC_STRIDE * (iter % 3) + which; }
+
+// Every solve starts with the coarse-capable kernels, whose coarse terms are off unless a
+// coarse space is active: block-Jacobi and a two-level solve whose coarse matrix turned
+// out singular then run exactly the same arithmetic.
 void launch_pcg_init(const Dev& d, double tol, int max_iters, hipStream_t s) {
   k_pcg_reset<<<1, 1, 0, s>>>(d, tol, max_iters);
+  const unsigned gz = std::min(64u, nblk(d.nA, 256)), g = nblk(d.nA, 256);
   if (d.coarse_k > 0) {
-    k_coarse_ztb<<<std::min(64u, nblk(d.nA, 256)), 256, 0, s>>>(d);
-    if (d.CD == 9) k_pcg_init_coarse<9><<<nblk(d.nA, 256), 256, 0, s>>>(d);
-    else k_pcg_init_coarse<6><<<nblk(d.nA, 256), 256, 0, s>>>(d);
-    if (d.fp64) k_pcg_init_coarse2<double><<<nblk(d.nA, 256), 256, 0, s>>>(d);
-    else k_pcg_init_coarse2<float><<<nblk(d.nA, 256), 256, 0, s>>>(d);
-  } else {
-    BA_DISPATCH_T_CD(d, k_pcg_init<T, CD><<<pcg_blocks(d), 256, 0, s>>>(d));
+    k_coarse_ztb<<<gz, 256, 0, s>>>(d);
+    det_sum(d, SC_COUNT, COARSE_K, 0, 0, gz, s);
   }
+  if (d.CD == 9) k_pcg_init_coarse<9><<<g, 256, 0, s>>>(d);
+  else k_pcg_init_coarse<6><<<g, 256, 0, s>>>(d);
+  det_sum(d, acc_slot(2, ACC_RZ), ACC_STRIDE - ACC_RZ, SC_BB, 1, g, s);
+  if (d.fp64) k_pcg_init_coarse2<double><<<g, 256, 0, s>>>(d);
+  else k_pcg_init_coarse2<float><<<g, 256, 0, s>>>(d);
   k_pcg_start<<<1, 1, 0, s>>>(d);
 }
 
 void launch_pcg_product(const Dev& d, hipStream_t s) { BA_DISPATCH_T_CD(d, run_matvec<T, CD>(d, d.scal + SC_DONE, s)); }
 
 void launch_pcg_update(const Dev& d, double lambda, int iter, hipStream_t s) {
+  const unsigned gq = nblk(d.nA, 64), g = nblk(d.nA, 256);
+  const int kc = d.coarse_k > 0 ? COARSE_K : 0;
   BA_DISPATCH_T_CD(d, {
-    k_pcg_q<T><<<nblk(d.nA, 64), 1024, 0, s>>>(d, d.scal + SC_DONE, d.p, d.q, lambda, iter);
-    if (d.coarse_k > 0) {
-      k_pcg_xr<true><<<nblk(d.nA, 256), 256, 0, s>>>(d, iter);
-      k_pcg_z<CD, true><<<nblk(d.nA, 256), 256, 0, s>>>(d, iter);
-      k_pcg_p<T, true><<<nblk(d.nA, 256), 256, 0, s>>>(d, iter);
-    } else {
-      k_pcg_xr<false><<<nblk(d.nA, 256), 256, 0, s>>>(d, iter);
-      k_pcg_z<CD, false><<<nblk(d.nA, 256), 256, 0, s>>>(d, iter);
-      k_pcg_p<T, false><<<nblk(d.nA, 256), 256, 0, s>>>(d, iter);
-    }
+    k_pcg_q<T><<<gq, 1024, 0, s>>>(d, d.scal + SC_DONE, d.p, d.q, lambda, iter);
+    det_sum(d, acc_slot(iter, ACC_PQ), 1, 0, 0, gq, s);
+    if (d.coarse_k > 0) k_pcg_xr<true><<<g, 256, 0, s>>>(d, iter);
+    else k_pcg_xr<false><<<g, 256, 0, s>>>(d, iter);
+    det_sum(d, acc_slot(iter, ACC_RR), 1, acc_slot(iter, ACC_ZR), kc, g, s);
+    if (d.coarse_k > 0) k_pcg_z<CD, true><<<g, 256, 0, s>>>(d, iter);
+    else k_pcg_z<CD, false><<<g, 256, 0, s>>>(d, iter);
+    det_sum(d, acc_slot(iter, ACC_RZ), 1, acc_slot(iter, ACC_W), kc, g, s);
+    if (d.coarse_k > 0) k_pcg_p<T, true><<<g, 256, 0, s>>>(d, iter);
+    else k_pcg_p<T, false><<<g, 256, 0, s>>>(d, iter);
   });
 }
 
@@ -2307,7 +2369,7 @@ template <int N, int CPL, typename T> __device__ __forceinline__ void z_cols(con
 // then the camera (OUT 0) or group (OUT 1) rows of J^T u added to acc
 template <int FAM, int OUT, typename T, int CD, int NO, int CPL>
 __device__ __forceinline__ void sz_rec_cols(const T* slot, const T (&zc)[CD][CPL], const T (&zg)[3][CPL], const T* s,
-                                            double (&acc)[NO][CPL]) {
+                                            double (&acc)[NO][CPL], int ss = SZ_COLS) {
   using SL = Slot<FAM, CD>;
   static_assert(NO >= (OUT == 0 ? SL::NC : SL::NG), "output rows");
   T v[SL::STRIDE];
@@ -2316,7 +2378,7 @@ __device__ __forceinline__ void sz_rec_cols(const T* slot, const T (&zc)[CD][CPL
 #pragma unroll
   for (int a = 0; a < SL::NF; ++a)
 #pragma unroll
-    for (int c = 0; c < CPL; ++c) sf[a][c] = s[a * SZ_COLS + c];
+    for (int c = 0; c < CPL; ++c) sf[a][c] = s[a * ss + c];
   T u[SL::ROWS][CPL];
 #pragma unroll
   for (int row = 0; row < SL::ROWS; ++row)
@@ -2499,6 +2561,126 @@ __global__ __launch_bounds__(256) void k_sz_grp(Dev d, const T* Zr, const T* sfp
       d.SZc[(int64_t)col * d.nA + e] = s + lam * d.DA[e] * d.Zc[(int64_t)col * d.nA + e];
     });
   }
+}
+
+// ---------------------------------------------------------------------------
+// Deterministic product, second pass: y = J_a^T (J_a x - J_f s_f) row by row, with s_f
+// from the first pass.  One workgroup per camera, plane or VP walks that block's records
+// (the camera-major copies and the group member lists, as the S Z sweeps do), one record
+// per lane with FP64 sums, and reduces them with a fixed butterfly and a fixed sum over
+// its wavefronts: the order of every addition is set by the problem, not by scheduling.
+// lambda D x is added by k_pcg_q.
+template <typename T, int CD> __global__ __launch_bounds__(256) void k_det_cam(Dev d, const double* done) {
+  __shared__ double lds[4 * CD];
+  if (done && *done != 0.0) return;
+  constexpr int R = 256;
+  const int c = d.cam_order[blockIdx.x], rs = threadIdx.x;
+  const T* x = (const T*)d.xT;
+  const T* sp = (const T*)d.sdp;
+  const T* sl = (const T*)d.sdl;
+  T zc[CD][1], z0[3][1];
+#pragma unroll
+  for (int k = 0; k < CD; ++k) zc[k][0] = x[CD * c + k];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) z0[k][0] = 0;
+  double acc[CD][1];
+#pragma unroll
+  for (int k = 0; k < CD; ++k) acc[k][0] = 0;
+  auto plane_x = [&](int fam, int g, T (&zg)[3][1]) {
+    const int o = a_grp(d, fam == 3 ? Fam<3, CD>::GT : Fam<4, CD>::GT, g);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) zg[k][0] = x[o + k];
+  };
+  if (d.fn[1])
+    for (int j = d.po_off[c] + rs; j < d.po_off[c + 1]; j += R) {
+      const int f = d.cmfeat[1][j];
+      sz_rec_cols<1, 0, T, CD>((const T*)d.cmrec[1] + (int64_t)j * Slot<1, CD>::STRIDE, zc, z0, sp + 3 * (int64_t)f, acc, 1);
+      const int k = d.cmal[1][j];
+      if (k >= 0) {
+        T zg[3][1];
+        plane_x(3, d.cmgrp[3][k], zg);
+        sz_rec_cols<3, 0, T, CD>((const T*)d.cmrec[3] + (int64_t)k * Slot<3, CD>::STRIDE, zc, zg, sp + 3 * (int64_t)f, acc, 1);
+      }
+    }
+  if (d.fn[6])
+    for (int j = d.px_off[c] + rs; j < d.px_off[c + 1]; j += R)
+      for (int64_t i = d.px_start[j]; i < d.px_start[j] + d.px_cnt[j]; ++i)
+        sz_rec_cols<6, 0, T, CD>((const T*)d.frec[6] + i * Slot<6, CD>::STRIDE, zc, z0, sp + 3 * (int64_t)d.ffeat[6][i], acc, 1);
+  if (d.fn[2])
+    for (int j = d.lo_off[c] + rs; j < d.lo_off[c + 1]; j += R) {
+      const int f = d.cmfeat[2][j];
+      sz_rec_cols<2, 0, T, CD>((const T*)d.cmrec[2] + (int64_t)j * Slot<2, CD>::STRIDE, zc, z0, sl + 4 * (int64_t)f, acc, 1);
+      const int k = d.cmal[2][j];
+      if (k >= 0) {
+        T zg[3][1];
+        plane_x(4, d.cmgrp[4][k], zg);
+        sz_rec_cols<4, 0, T, CD>((const T*)d.cmrec[4] + (int64_t)k * Slot<4, CD>::STRIDE, zc, zg, sl + 4 * (int64_t)f, acc, 1);
+      }
+    }
+  if (d.fn[7])
+    for (int j = d.lx_off[c] + rs; j < d.lx_off[c + 1]; j += R)
+      for (int64_t i = d.lx_start[j]; i < d.lx_start[j] + d.lx_cnt[j]; ++i)
+        sz_rec_cols<7, 0, T, CD>((const T*)d.frec[7] + i * Slot<7, CD>::STRIDE, zc, z0, sl + 4 * (int64_t)d.ffeat[7][i], acc, 1);
+  double* y = d.mv_part;
+  sz_block_sum<CD, 1, 1>(acc, lds, [&](int row, int, double v) { y[CD * c + row] = v; });
+}
+
+template <typename T, int CD> __global__ __launch_bounds__(256) void k_det_grp(Dev d, const double* done) {
+  __shared__ double lds[4 * 3];
+  if (done && *done != 0.0) return;
+  constexpr int R = 256;
+  const int rs = threadIdx.x;
+  const T* x = (const T*)d.xT;
+  const T* sp = (const T*)d.sdp;
+  const T* sl = (const T*)d.sdl;
+  double* y = d.mv_part;
+  if ((int)blockIdx.x < d.ng) {
+    const int g = blockIdx.x, e0 = a_grp(d, 1, g);
+    T zg[3][1];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) zg[k][0] = x[e0 + k];
+    double acc[3][1] = {{0}, {0}, {0}};
+    if (d.fn[3])
+      for (int j = d.plp_off[g] + rs; j < d.plp_off[g + 1]; j += R) {
+        const int f = d.plp[j];
+        for (int64_t i = d.foff[3][f]; i < d.foff[3][f + 1]; ++i) {
+          T zc[CD][1];
+#pragma unroll
+          for (int k = 0; k < CD; ++k) zc[k][0] = x[CD * d.fcam[3][i] + k];
+          sz_rec_cols<3, 1, T, CD>((const T*)d.frec[3] + i * Slot<3, CD>::STRIDE, zc, zg, sp + 3 * (int64_t)f, acc, 1);
+        }
+      }
+    if (d.fn[4])
+      for (int j = d.pll_off[g] + rs; j < d.pll_off[g + 1]; j += R) {
+        const int f = d.pll[j];
+        for (int64_t i = d.foff[4][f]; i < d.foff[4][f + 1]; ++i) {
+          T zc[CD][1];
+#pragma unroll
+          for (int k = 0; k < CD; ++k) zc[k][0] = x[CD * d.fcam[4][i] + k];
+          sz_rec_cols<4, 1, T, CD>((const T*)d.frec[4] + i * Slot<4, CD>::STRIDE, zc, zg, sl + 4 * (int64_t)f, acc, 1);
+        }
+      }
+    sz_block_sum<3, 1, 1>(acc, lds, [&](int row, int, double v) { y[e0 + row] = v; });
+  } else {
+    const int v = blockIdx.x - d.ng, e0 = a_grp(d, 2, v);
+    T zg[3][1], zc[CD][1];
+    zg[0][0] = x[e0];
+    zg[1][0] = x[e0 + 1];
+    zg[2][0] = 0;
+#pragma unroll
+    for (int k = 0; k < CD; ++k) zc[k][0] = 0;
+    double acc[2][1] = {{0}, {0}};
+    for (int j = d.vpm_off[v] + rs; j < d.vpm_off[v + 1]; j += R) {
+      const int i = d.vpm[j];
+      sz_rec_cols<5, 1, T, CD>((const T*)d.frec[5] + (int64_t)i * Slot<5, CD>::STRIDE, zc, zg, sl + 4 * (int64_t)d.ffeat[5][i], acc, 1);
+    }
+    sz_block_sum<2, 1, 1>(acc, lds, [&](int row, int, double w) { y[e0 + row] = w; });
+  }
+}
+
+template <typename T, int CD> void launch_det_rows(const Dev& d, const double* done, hipStream_t s) {
+  if (d.nc) k_det_cam<T, CD><<<d.nc, 256, 0, s>>>(d, done);
+  if (d.ng + d.nv) k_det_grp<T, CD><<<d.ng + d.nv, 256, 0, s>>>(d, done);
 }
 
 template <typename T, int CD, int L, int CPL> static void launch_sz_out(const Dev& d, const T* Zr, const T* sfp, const T* sfl, double lambda, hipStream_t s) {

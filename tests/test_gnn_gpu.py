@@ -220,7 +220,9 @@ def test_coarse_space_and_products_match_oracle(precision, tile, vps, monkeypatc
 
 def test_zero_head_falls_back_to_block_jacobi():
     """A zero output head gives zero network columns: E is singular, the
-    coarse term is off and PCG takes the block-Jacobi iterations."""
+    coarse term is off and PCG takes exactly the block-Jacobi iterates: in the
+    deterministic mode (no summation order differs between the two handles)
+    three LM steps agree bit for bit."""
     from paper_2609_04026_amd.binding import BA
     sc = make_scene(small_config(n_cams=10, n_points=60, n_lines=16), seed=41)
     p = gnn.init_params(9, seed=24)
@@ -231,19 +233,15 @@ def test_zero_head_falls_back_to_block_jacobi():
     for precond in ("jacobi", "learned"):
         ba = BA.from_scene(sc, precision="fp64", precond=precond)
         ba.set_gnn_weights(gnn.pack(p).tobytes())
-        ba.linearize(1e-4)
-        x, it, rel = ba.pcg_solve(tol=1e-10, max_iters=500)
-        rep = ba.lm_step(pcg_tol=1e-10)
-        assert rep["coarse"] == 0
-        out[precond] = (x, it)
+        reps = [ba.lm_step(lambda0=1e-4, pcg_tol=1e-10, pcg_max_iters=500, deterministic=1) for _ in range(3)]
+        assert all(r["coarse"] == 0 for r in reps)
+        out[precond] = (reps, ba.get_parameters())
         ba.close()
-    # the block-Jacobi iterations, up to the last few: the product's FP64 LDS atomics sum
-    # in a different order from run to run, and on this ill-conditioned system that moves
-    # the iteration at which a 1e-10 relative residual is reached (65 and 63 have both been
-    # seen for the same handle); the solutions agree to the accuracy of the solve
-    assert abs(out["jacobi"][1] - out["learned"][1]) <= 3, (out["jacobi"][1], out["learned"][1])
-    xj, xl = out["jacobi"][0], out["learned"][0]
-    assert np.linalg.norm(xj - xl) <= 1e-7 * np.linalg.norm(xj)
+    for rj, rl in zip(out["jacobi"][0], out["learned"][0]):
+        for k in ("pcg_iters", "pcg_rel_residual", "model_decrease", "E_after", "lambda"):
+            assert rj[k] == rl[k], (k, rj[k], rl[k])
+    for k, v in out["jacobi"][1].items():
+        assert np.array_equal(v, out["learned"][1][k]), k
 
 
 def test_coarse_space_damping_window():

@@ -1,0 +1,107 @@
+"""Deterministic mode (ba_solve_options.deterministic), through the C ABI.
+
+In that mode every sum of an LM step is taken in an order fixed by the
+problem: the implicit-Schur product forms s_f per feature and then each
+camera / group row over its records, and the PCG dot products are summed
+per workgroup and then in workgroup order.  Checked here: two handles on
+the same scene give bit-identical steps and parameters, and the
+deterministic product and LM step match the oracle's exact Schur terms as
+the default path does.
+"""
+import numpy as np
+import pytest
+
+from scenegen import make_scene, small_config
+from oracle import lm
+
+pytestmark = pytest.mark.gpu
+
+
+def _ba():
+    from paper_2609_04026_amd.binding import BA
+    return BA
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("precond", ["jacobi", "gauge"])
+def test_deterministic_mode_repeats_bit_for_bit(precision, precond):
+    """Two handles, four LM steps each on the 30-camera holistic scene: every
+    reported scalar and every parameter agree bit for bit."""
+    print(f"[det] {precision} {precond}", flush=True)
+    s = make_scene(2)
+    BA = _ba()
+    runs = []
+    for _ in range(2):
+        ba = BA.from_scene(s, precision=precision, precond=precond)
+        reps = [ba.lm_step(deterministic=1, pcg_tol=1e-6) for _ in range(4)]
+        runs.append((reps, ba.get_parameters()))
+        ba.close()
+    (ra, pa), (rb, pb) = runs
+    assert any(r["accepted"] for r in ra)
+    for a, b in zip(ra, rb):
+        for k in ("E_after", "Epix_after", "model_decrease", "gain_ratio", "lambda", "pcg_iters",
+                  "pcg_rel_residual", "accepted", "coarse"):
+            assert a[k] == b[k], (k, a[k], b[k])
+    for k in pa:
+        assert np.array_equal(pa[k], pb[k]), k
+
+
+SCENES = {
+    "tiny_holistic": lambda: make_scene(small_config(n_cams=9, n_points=70, n_lines=20), seed=101),
+    "holistic_30cam": lambda: make_scene(2),
+}
+
+
+@pytest.mark.parametrize("name", list(SCENES))
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_deterministic_step_and_product_match_oracle(name, precision):
+    """One deterministic LM step against the oracle's exact Schur step, then
+    the deterministic product (the handle keeps the mode) against the dense S
+    entry by entry; then a default-mode step on the same handle, whose
+    product must match again (the modes share the product's buffers)."""
+    s = SCENES[name]()
+    prob = lm.Problem(s)
+    st = prob.state0()
+    lin = lm.linearize(prob, st)
+    lam = 1e-3
+    BA = _ba()
+    ba = BA.from_scene(s, precision=precision)
+    rep = ba.lm_step(lambda0=lam, pcg_tol=1e-12 if precision == "fp64" else 1e-7, pcg_max_iters=2000,
+                     deterministic=1)
+    h, sys_ = lm.solve_schur(prob, lin, lam)
+    E1 = lm.cost(prob, prob.retract(st, h))[0]
+    tol = 1e-8 if precision == "fp64" else 1e-4
+    assert rep["accepted"] == 1 and abs(rep["E_after"] - E1) <= tol * E1, (rep, E1)
+    S = sys_["S"]
+    rng = np.random.default_rng(5)
+    ptol = 1e-9 if precision == "fp64" else 1e-3
+
+    def check():
+        for _ in range(3):
+            x = rng.normal(size=prob.nA)
+            y = ba.schur_matvec(x)
+            err = np.abs(y - S @ x) / np.maximum(np.abs(S) @ np.abs(x), 1e-300)
+            assert err.max() <= ptol, err.max()
+
+    check()
+    y1 = ba.schur_matvec(np.ones(prob.nA))
+    y2 = ba.schur_matvec(np.ones(prob.nA))
+    assert np.array_equal(y1, y2)
+    # back to the default (atomic) product on the same handle, relinearised at
+    # its current parameters: the modes share the product's buffers
+    ba.lm_step(pcg_tol=1e-7, deterministic=0)
+    ba.linearize(lam)
+    st2 = _oracle_state(ba)
+    S = lm.schur(prob, lm.linearize(prob, st2), lam)["S"]
+    check()
+    ba.close()
+
+
+def _oracle_state(ba):
+    """The handle's current parameters as an oracle state (lines from their
+    unit direction d and moment m/|d|: the point d x m and that point + d)."""
+    from oracle.model import State
+    p = ba.get_parameters()
+    d, m = p["lines"][:, 0:3], p["lines"][:, 3:6]
+    P = np.cross(d, m)
+    return State.from_arrays(p["cameras"], p["points"], np.concatenate([P, P + d], axis=1), p["planes"], p["vps"])
