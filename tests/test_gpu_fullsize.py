@@ -13,6 +13,9 @@ compute one by one:
   of S and b depend on no other feature), within 1e-3 relative (the bar of
   the small-scene reduced-system test: FP32 sums of thousands of records,
   and S is a difference of two such sums; the FP64 path within 1e-8);
+- S Z of the 15 coarse columns in two cameras' and two planes' rows, against
+  the oracle's Schur terms of the sub-problem holding every feature those rows
+  depend on, entry by entry;
 - properties of the whole product: symmetry y.(S x) = x.(S y) and x.(S x) > 0.
 """
 import os
@@ -194,12 +197,22 @@ def _check_camera_rows(scene, ba, cam, tol):
     U = t["U"][rows][:, rows].toarray() + LAM * np.diag(lin.D[rows])
     S_cc = U - t["WVW"][rows][:, rows].toarray()
     assert np.linalg.norm(Sc[cam] - S_cc) <= tol * np.linalg.norm(S_cc), (cam, np.linalg.norm(Sc[cam] - S_cc) / np.linalg.norm(S_cc))
-    # (S x)_c for a random x over all of A
+    # (S x)_c for a random x over all of A, entry by entry against the size of its terms
     x = np.random.default_rng(cam).normal(size=nA)
     y = ba.schur_matvec(x)[rows]
-    y_or = (t["U"][rows] @ x + LAM * lin.D[rows] * x[rows] - t["WVW"][rows] @ x)
-    assert np.linalg.norm(y - y_or) <= tol * np.linalg.norm(y_or), (cam, np.linalg.norm(y - y_or) / np.linalg.norm(y_or))
+    _check_rows(y[:, None], x[:, None], t, lin, rows, tol, f"camera {cam} S x")
     print(f"[fullsize] camera {cam}: {len(pts)} points, {len(lns)} lines, rows of b, S and S x match within {tol:g}", flush=True)
+
+
+def _check_rows(got, X, t, lin, rows, tol, what):
+    """Rows `rows` of S X (columns of X) from the oracle's sparse Schur terms,
+    S = U + lambda D - W V^-1 W^T, entry by entry: each |got - ref| against
+    (|U| |X| + lambda D |X| + |W V^-1 W^T| |X|), the size of the terms summed."""
+    U, WVW = t["U"][rows], t["WVW"][rows]
+    ref = U @ X + (LAM * lin.D[rows])[:, None] * X[rows] - WVW @ X
+    mag = abs(U) @ np.abs(X) + (LAM * lin.D[rows])[:, None] * np.abs(X[rows]) + abs(WVW) @ np.abs(X)
+    err = np.abs(got - ref) / np.maximum(mag, 1e-300)
+    assert err.max() <= tol, (what, float(err.max()))
 
 
 def test_fullsize_product_is_symmetric_positive(full):
@@ -213,17 +226,38 @@ def test_fullsize_product_is_symmetric_positive(full):
     assert x @ Sx > 0 and y @ Sy > 0
 
 
-def test_fullsize_coarse_columns_of_s_z(full):
-    """S Z of the coarse space at full size (the gauge columns from the
-    features' gauge motion in closed form, as this scene has no VP records; the
-    network columns from the record sweeps) against the implicit-Schur product
-    applied to each column, within 1e-4 of |S| |z| (both are FP32 sums)."""
-    _, ba = full
+def features_of_plane(scene, g):
+    """The sub-problem of the features associated with plane g: the rows of
+    plane g in S and b depend on no other feature."""
+    npt, nln = len(scene["points"]), len(scene["lines"])
+    kp = np.zeros(npt, dtype=bool)
+    kl = np.zeros(nln, dtype=bool)
+    a, b, _ = scene["obs"][ASSOC_PLANE_POINT]
+    kp[np.asarray(b)[np.asarray(a) == g]] = True
+    a, b, _ = scene["obs"][ASSOC_PLANE_LINE]
+    kl[np.asarray(b)[np.asarray(a) == g]] = True
+    return subset(scene, kp, kl)
+
+
+@pytest.mark.parametrize("block", [("cam", 17), ("cam", 903), ("plane", 5), ("plane", 1377)])
+def test_fullsize_coarse_columns_of_s_z(full, block):
+    """S Z of all 15 coarse columns at full size (the gauge columns from the
+    features' gauge motion in closed form, as this scene has no VP records;
+    the network columns from the record sweeps), in the rows of one camera or
+    one plane, against the oracle's exact Schur terms of the sub-problem that
+    holds every feature those rows depend on (the camera's observed features,
+    or the plane's member features), entry by entry within 1e-3 of the size
+    of the summed terms (FP32 records, as for the camera rows of S x)."""
+    scene, ba = full
+    kind, i = block
+    sub, pts, lns = features_of_camera(scene, i) if kind == "cam" else features_of_plane(scene, i)
+    prob = lm.Problem(sub)
+    lin = lm.linearize(prob, prob.state0())
+    t = lm.schur_terms(prob, lin, LAM)
     Z, SZ = ba.export_coarse_space()
     assert Z.shape[1] == 15
-    for k in range(Z.shape[1]):
-        y = ba.schur_matvec(Z[:, k])
-        scale = np.linalg.norm(ba.schur_matvec(np.abs(Z[:, k])))
-        err = np.linalg.norm(SZ[:, k] - y) / scale
-        assert err <= 1e-4, (k, err)
-    print(f"[fullsize] S Z of {Z.shape[1]} coarse columns matches the product", flush=True)
+    cd = prob.camera_dof
+    rows = slice(cd * i, cd * (i + 1)) if kind == "cam" else slice(prob.off["pl"] + 3 * i, prob.off["pl"] + 3 * i + 3)
+    _check_rows(SZ[rows], Z, t, lin, rows, 1e-3, f"{kind} {i} S Z")
+    print(f"[fullsize] S Z of {Z.shape[1]} coarse columns in the rows of {kind} {i} ({len(pts)} points, "
+          f"{len(lns)} lines) matches the oracle", flush=True)
