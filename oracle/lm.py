@@ -95,7 +95,7 @@ def family_cost(prob, state, fam, recs=None):
 
 
 def cost(prob, state):
-    """(E, E_pix): E = 1/2 sum w rho(|r|^2), E_pix without the VP family."""
+    """(E, E_pix): E = 1/2 sum w rho(|r|^2), E_pix without the angular families (VP-line, relations)."""
     E = Epix = 0.0
     for fam in FAMILY_ORDER:
         if prob.record_count(fam) == 0:
@@ -147,7 +147,7 @@ def linearize(prob, state):
             cc = np.broadcast_to(cc, (n, m, dof))
             rows.append(rr.ravel())
             cols.append(cc.ravel())
-            vals.append(L["J"][b].ravel())
+            vals.append(L["J"][key].ravel())
         rts.append(L["rt"].ravel())
         row0 += n * m
     lin.nrows = row0

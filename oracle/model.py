@@ -295,10 +295,20 @@ class State:
 # per-record parameter gathering and first-order tangent perturbation
 # ---------------------------------------------------------------------------
 class Gathered:
-    """Per-record complex copies of the parameter blocks a family touches."""
+    """Per-record complex copies of the parameter blocks a family touches.
 
-    def __init__(self, state: State, cam=None, pt=None, ln=None, pl=None, vp=None):
+    An inter-group relation record touches two groups of one kind (`rel` =
+    (kind "vp" or "pl", index a, index b)): their directions (the VP, or the
+    plane normal) and sphere tangent bases are gathered as ua, Ba, ub, Bb."""
+
+    def __init__(self, state: State, cam=None, pt=None, ln=None, pl=None, vp=None, rel=None):
         c = np.complex128
+        if rel is not None:
+            kind, ia, ib = rel
+            src = state.vp if kind == "vp" else state.pl_n
+            self.ua, self.ub = src[ia].astype(c), src[ib].astype(c)
+            self.Ba, self.Bb = s2_basis(src[ia]), s2_basis(src[ib])
+            return
         self.R = state.cam_R[cam].astype(c) if cam is not None else None
         self.t = state.cam_t[cam].astype(c) if cam is not None else None
         self.f = state.cam_f[cam].astype(c) if cam is not None else None
@@ -352,6 +362,14 @@ class Gathered:
                 self.wp = self.wp + h
         elif block == "vp":
             self.v = self.v + h * self.Bv[:, :, k]
+        elif block in ("ga", "gb"):
+            # a relation's group: the direction moves with the first two tangent
+            # coordinates; a plane's third (the offset w) leaves it unchanged
+            if k < 2:
+                if block == "ga":
+                    self.ua = self.ua + h * self.Ba[:, :, k]
+                else:
+                    self.ub = self.ub + h * self.Bb[:, :, k]
         else:
             raise ValueError(block)
 
@@ -415,7 +433,23 @@ def res_line_to_point(g: Gathered, rec, cx, cy):
     return signed_distance(rec["meas"], l)[..., None]
 
 
-# family name -> (residual fn, rows, [(block, index key, dof)])
+def res_rel_ortho(g: Gathered, rec, cx, cy):
+    """Inter-group orthogonality (Sec. 3.2, inter-group relations): the cosine
+    u_a . u_b of two VP directions or two plane normals, zero when they are
+    perpendicular; angular and scale-free like Eq. 6 (a reading: the paper
+    names the relation, not its residual)."""
+    return dot(g.ua, g.ub)[..., None]
+
+
+def res_rel_parallel(g: Gathered, rec, cx, cy):
+    """Inter-group parallelism (Sec. 3.2): the 3-vector u_a x u_b, whose norm
+    is |sin| of the angle; zero for parallel or opposite directions (a plane's
+    (n, w) and (-n, -w) are one plane), the same vector form as R5."""
+    return cross(g.ua, g.ub)
+
+
+# family name -> (residual fn, rows, [(block type, index key, dof)]); the key also names
+# the block in jacobians() and Gathered.perturb
 FAMILIES = {
     "R1": (res_point, 2, [("cam", "cam", 9), ("pt", "pt", 3)]),
     "R2": (res_line, 4, [("cam", "cam", 9), ("ln", "ln", 4)]),
@@ -424,13 +458,20 @@ FAMILIES = {
     "R5": (res_vp_line, 3, [("ln", "ln", 4), ("vp", "vp", 2)]),
     "R6": (res_point_to_line, 1, [("cam", "cam", 9), ("pt", "pt", 3)]),
     "R7": (res_line_to_point, 1, [("cam", "cam", 9), ("ln", "ln", 4)]),
+    "R8": (res_rel_ortho, 1, [("vp", "ga", 2), ("vp", "gb", 2)]),        # VP _|_ VP
+    "R9": (res_rel_parallel, 3, [("vp", "ga", 2), ("vp", "gb", 2)]),     # VP || VP
+    "R10": (res_rel_ortho, 1, [("pl", "ga", 3), ("pl", "gb", 3)]),       # plane _|_ plane
+    "R11": (res_rel_parallel, 3, [("pl", "ga", 3), ("pl", "gb", 3)]),    # plane || plane
 }
-FAMILY_ORDER = ["R1", "R2", "R3", "R4", "R5", "R6", "R7"]
-PIXEL_FAMILIES = ("R1", "R2", "R3", "R4", "R6", "R7")  # R5 is angular (Sec. 3.5)
+FAMILY_ORDER = ["R1", "R2", "R3", "R4", "R5", "R6", "R7", "R8", "R9", "R10", "R11"]
+RELATION_FAMILIES = ("R8", "R9", "R10", "R11")
+PIXEL_FAMILIES = ("R1", "R2", "R3", "R4", "R6", "R7")  # R5 and the relations are angular (Sec. 3.5)
 
 
 def gather(state, rec, fam):
     blocks = FAMILIES[fam][2]
+    if fam in RELATION_FAMILIES:
+        return Gathered(state, rel=(blocks[0][0], rec["ga"], rec["gb"]))
     kw = {b: rec[key] for b, key, _ in blocks}
     return Gathered(state, **kw)
 
@@ -497,15 +538,15 @@ def jacobians(state, rec, fam, cx, cy, camera_dof=9, h=1e-30):
     fn, rows, blocks = FAMILIES[fam]
     n = len(next(iter(rec.values())))
     out = {}
-    for b, _, dof in blocks:
+    for b, key, dof in blocks:
         if b == "cam":
             dof = camera_dof
         J = np.zeros((n, rows, dof))
         for k in range(dof):
             g = gather(state, rec, fam)
-            g.perturb(b, k, 1j * h)
+            g.perturb(key, k, 1j * h)
             J[:, :, k] = np.imag(fn(g, rec, cx, cy)) / h
-        out[b] = J
+        out[key] = J
     return out
 
 

@@ -16,7 +16,10 @@ The visibility rules are the paper's:
   observed and the line is not, measured at that view's observed point
   (undistorted pixels) (Sec. 3.4 Eq. 12);
 * views that observe both features of a junction get no cross-feature
-  record (Sec. 3.4, after Eq. 12).
+  record (Sec. 3.4, after Eq. 12);
+* R8-R11 one record per inter-group relation: VP-VP orthogonal, VP-VP
+  parallel, plane-plane orthogonal, plane-plane parallel (Sec. 3.2, the
+  inter-group relations between VP pairs and plane-normal pairs).
 
 Each family is a dict of equally long arrays; ``key`` gives a record's
 identity for matching against another implementation:
@@ -27,11 +30,12 @@ from __future__ import annotations
 import numpy as np
 
 from scenegen import (OBS_POINT, OBS_LINE, ASSOC_PLANE_POINT, ASSOC_PLANE_LINE, ASSOC_VP_LINE,
-                      ASSOC_JUNCTION)
+                      ASSOC_JUNCTION, REL_VP_ORTHO, REL_VP_PARALLEL, REL_PLANE_ORTHO, REL_PLANE_PARALLEL)
 
 FAMILY_KIND = {"R1": OBS_POINT, "R2": OBS_LINE, "R3": ASSOC_PLANE_POINT, "R4": ASSOC_PLANE_LINE,
-               "R5": ASSOC_VP_LINE, "R6": ASSOC_JUNCTION, "R7": ASSOC_JUNCTION}
-FAMILY_ID = {"R1": 1, "R2": 2, "R3": 3, "R4": 4, "R5": 5, "R6": 6, "R7": 7}
+               "R5": ASSOC_VP_LINE, "R6": ASSOC_JUNCTION, "R7": ASSOC_JUNCTION,
+               "R8": REL_VP_ORTHO, "R9": REL_VP_PARALLEL, "R10": REL_PLANE_ORTHO, "R11": REL_PLANE_PARALLEL}
+FAMILY_ID = {"R1": 1, "R2": 2, "R3": 3, "R4": 4, "R5": 5, "R6": 6, "R7": 7, "R8": 8, "R9": 9, "R10": 10, "R11": 11}
 
 
 def _views_of(feat_of_obs, n_feat):
@@ -95,6 +99,10 @@ def expand(scene) -> dict:
     cam = pc[o]
     seen = np.isin(jl[a] * ncam + cam, lkeys)
     recs["R7"] = dict(cam=cam[~seen], ln=jl[a][~seen], pt=jp[a][~seen], meas=pm[o][~seen][:, 2:4])
+    # inter-group relations (Sec. 3.2): one record per related pair of groups
+    for fam in ("R8", "R9", "R10", "R11"):
+        a, b, _ = obs.get(FAMILY_KIND[fam], (np.zeros(0), np.zeros(0), None))
+        recs[fam] = dict(ga=np.asarray(a, np.int64), gb=np.asarray(b, np.int64))
     return recs
 
 
@@ -116,11 +124,14 @@ def record_keys(recs) -> dict:
             k = (neg, r["ln"], r["vp"])
         elif fam == "R6":
             k = (r["cam"], r["pt"], r["ln"])
-        else:
+        elif fam == "R7":
             k = (r["cam"], r["ln"], r["pt"])
+        else:  # relations: (-1, group a, group b)
+            k = (neg, r["ga"], r["gb"])
         out[fam] = np.stack([np.full(n, FAMILY_ID[fam], dtype=np.int64), *k], axis=1)
     return out
 
 
 def loss_of(scene, fam):
-    return scene["loss"][FAMILY_KIND[fam]]
+    from scenegen import DEFAULT_LOSS
+    return scene["loss"].get(FAMILY_KIND[fam], DEFAULT_LOSS[FAMILY_KIND[fam]])

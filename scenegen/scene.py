@@ -28,6 +28,9 @@ LOSS_TRIVIAL, LOSS_HUBER, LOSS_CAUCHY = 0, 1, 2
 
 # Observation / association kinds as in the C ABI.
 OBS_POINT, OBS_LINE, ASSOC_PLANE_POINT, ASSOC_PLANE_LINE, ASSOC_VP_LINE, ASSOC_JUNCTION = range(6)
+# Inter-group relations (a, b = two VPs or two planes): orthogonal or parallel directions.
+REL_VP_ORTHO, REL_VP_PARALLEL, REL_PLANE_ORTHO, REL_PLANE_PARALLEL = range(6, 10)
+RELATION_KINDS = (REL_VP_ORTHO, REL_VP_PARALLEL, REL_PLANE_ORTHO, REL_PLANE_PARALLEL)
 
 # Per-kind default (loss kind, scale, weight).  Weights and the VP scale are the
 # paper's (supplementary Section C: VP weight 5e3 with Cauchy scale 0.2; group
@@ -42,6 +45,10 @@ DEFAULT_LOSS = {
     ASSOC_VP_LINE: (LOSS_CAUCHY, 0.2, 5.0e3),
     ASSOC_JUNCTION: (LOSS_CAUCHY, 1.0, 0.1),
 }
+# Inter-group relations are angular like the VP-line term, and take its weight and
+# Cauchy scale (the paper gives none of their own).
+for _k in RELATION_KINDS:
+    DEFAULT_LOSS[_k] = (LOSS_CAUCHY, 0.2, 5.0e3)
 
 # Workload sizes.  Keys:
 #   n_cams, half (cube half extents), radius (camera sphere), K (neighbour pool)
@@ -53,6 +60,11 @@ DEFAULT_LOSS = {
 #   line_outlier_frac (outliers among line observations; default outlier_frac)
 #   min_seg_px (a line is not observed in an image where its projected
 #   segment is shorter than this: a detector finds no such segment)
+#   plane_relations (inter-group relations: every pair of perpendicular VPs
+#   is related orthogonal, and each plane is related to this many others,
+#   parallel when their normals share an axis and orthogonal otherwise;
+#   drawn from a generator of their own, so that the rest of a scene does
+#   not depend on it; 0 or absent: no relations)
 CONFIGS = {
     1: dict(n_cams=10, half=(5.0, 5.0, 2.5), radius=18.0, K=9,
             n_free_points=1000, n_free_lines=0, n_free_vp_lines=0,
@@ -543,21 +555,56 @@ def make_scene(config, seed: int | None = None, noise: bool = True, replica: int
 
     i32 = lambda a: np.ascontiguousarray(a, dtype=np.int32)
     f64 = lambda a: np.ascontiguousarray(a, dtype=np.float64)
+    obs = {
+        OBS_POINT: (i32(op_cam), i32(op_pt), f64(op_meas)),
+        OBS_LINE: (i32(ol_cam), i32(ol_ln), f64(ol_meas)),
+        ASSOC_PLANE_POINT: (i32(pt_plane[pp]), i32(pp), None),
+        ASSOC_PLANE_LINE: (i32(ln_plane[lp]), i32(lp), None),
+        ASSOC_VP_LINE: (i32(ln_vp[lv]), i32(lv), None),
+        ASSOC_JUNCTION: (i32(jn[:, 0]), i32(jn[:, 1]), None),
+    }
+    if cfg.get("plane_relations", 0) > 0:
+        for k, (a, b) in _relations(vps, pl_axis, int(cfg["plane_relations"]), seed).items():
+            obs[k] = (i32(a), i32(b), None)
     return dict(
         config=cfg, seed=seed, cx=CX, cy=CY, camera_dof=9,
         cameras=f64(cams0), points=f64(pts0), lines=f64(lines0), planes=f64(planes0), vps=f64(vps0),
         cameras_gt=f64(cams_gt), points_gt=f64(pts), lines_gt=f64(lines_gt), planes_gt=f64(planes_gt),
         vps_gt=f64(vps),
-        obs={
-            OBS_POINT: (i32(op_cam), i32(op_pt), f64(op_meas)),
-            OBS_LINE: (i32(ol_cam), i32(ol_ln), f64(ol_meas)),
-            ASSOC_PLANE_POINT: (i32(pt_plane[pp]), i32(pp), None),
-            ASSOC_PLANE_LINE: (i32(ln_plane[lp]), i32(lp), None),
-            ASSOC_VP_LINE: (i32(ln_vp[lv]), i32(lv), None),
-            ASSOC_JUNCTION: (i32(jn[:, 0]), i32(jn[:, 1]), None),
-        },
+        obs=obs,
         loss=loss,
     )
+
+
+def _relations(vps, pl_axis, per_plane, seed):
+    """Inter-group relations of a Manhattan / Atlanta scene (exact at the
+    ground truth): every pair of perpendicular VPs; for each plane,
+    `per_plane` distinct partners drawn at random, parallel when the normals
+    share an axis, orthogonal otherwise (each unordered pair once)."""
+    rng = np.random.default_rng(seed + 104729)
+    out = {k: ([], []) for k in RELATION_KINDS}
+    nv = len(vps)
+    for a in range(nv):
+        for b in range(a + 1, nv):
+            if abs(float(vps[a] @ vps[b])) < 1e-12:
+                out[REL_VP_ORTHO][0].append(a)
+                out[REL_VP_ORTHO][1].append(b)
+    npl = len(pl_axis)
+    seen = set()
+    for g in range(npl):
+        if npl < 2:
+            break
+        cand = rng.permutation(npl - 1)[:per_plane]
+        for h in cand:
+            h = int(h) + (1 if h >= g else 0)
+            key = (min(g, h), max(g, h))
+            if key in seen:
+                continue
+            seen.add(key)
+            kind = REL_PLANE_PARALLEL if pl_axis[g] == pl_axis[h] else REL_PLANE_ORTHO
+            out[kind][0].append(key[0])
+            out[kind][1].append(key[1])
+    return {k: (np.asarray(a, np.int64), np.asarray(b, np.int64)) for k, (a, b) in out.items()}
 
 
 def scene_counts(scene: dict) -> dict:
@@ -571,10 +618,19 @@ def scene_counts(scene: dict) -> dict:
 
 def small_config(n_cams=7, n_points=40, n_lines=12, n_planes=2, n_vps=3, grids=1, grid=3,
                  plane_points=10, plane_lines=4, vp_lines=4, rot_deg=1.0, trans=0.05,
-                 struct=0.05, pix=1.0):
-    """Size dict for tiny test scenes with every residual family present."""
+                 struct=0.05, pix=1.0, plane_relations=0):
+    """Size dict for tiny test scenes with every residual family present
+    (the inter-group relations with plane_relations > 0)."""
     return dict(n_cams=n_cams, half=(3.0, 3.0, 3.0), radius=10.0, K=min(n_cams - 1, 4),
                 n_free_points=n_points, n_free_lines=n_lines, n_free_vp_lines=vp_lines,
                 n_planes=n_planes, n_plane_points=plane_points, n_plane_lines=plane_lines,
                 plane_line_axis_frac=0.5, n_grids=grids, grid=grid, n_vps=n_vps,
-                rot_deg=rot_deg, trans=trans, struct=struct, pix=pix, outlier_frac=0.0, huber=False)
+                rot_deg=rot_deg, trans=trans, struct=struct, pix=pix, outlier_frac=0.0, huber=False,
+                plane_relations=plane_relations)
+
+
+def manhattan_config():
+    """A tiny Manhattan scene with inter-group relations: 8 cameras, 3
+    Manhattan VPs and 2 Atlanta ones, 6 planes each related to 2 others."""
+    return small_config(n_cams=8, n_points=40, n_lines=12, n_planes=6, n_vps=5, plane_points=12,
+                        plane_lines=6, vp_lines=6, plane_relations=2)

@@ -15,7 +15,7 @@ import time
 ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
 sys.path.insert(0, ROOT)
 
-from scenegen import make_scene, small_config  # noqa: E402
+from scenegen import make_scene, small_config, manhattan_config  # noqa: E402
 from oracle import lm  # noqa: E402
 
 SCENES = {
@@ -23,6 +23,7 @@ SCENES = {
     "points_10cam": lambda: make_scene(1),
     "holistic_30cam": lambda: make_scene(2),
     "holistic_200cam": lambda: make_scene(3),
+    "manhattan_relations": lambda: make_scene(manhattan_config(), seed=12),
 }
 
 if __name__ == "__main__":

@@ -11,7 +11,7 @@ import os
 import numpy as np
 import pytest
 
-from scenegen import make_scene, small_config, scene_counts, ASSOC_JUNCTION, OBS_POINT, OBS_LINE
+from scenegen import make_scene, small_config, manhattan_config, scene_counts, ASSOC_JUNCTION, OBS_POINT, OBS_LINE
 from oracle import lm, model
 from oracle.records import expand
 
@@ -30,6 +30,13 @@ def _retract_block(st, prob, block, k, h):
     return st.retract(d["cam"], d["pt"], d["ln"], d["pl"], d["vp"])
 
 
+def _retract_one(st, prob, block, i, k, h):
+    """Move only entity i of `block` along tangent coordinate k."""
+    d = _zero_steps(prob)
+    d[block][i, k] = h
+    return st.retract(d["cam"], d["pt"], d["ln"], d["pl"], d["vp"])
+
+
 @pytest.fixture(scope="module")
 def tiny():
     s = make_scene(small_config(), seed=11)
@@ -37,28 +44,53 @@ def tiny():
     return s, prob
 
 
+@pytest.fixture(scope="module")
+def manhattan():
+    """A tiny Manhattan scene with all four inter-group relation families."""
+    s = make_scene(manhattan_config(), seed=12)
+    prob = lm.Problem(s)
+    assert all(prob.record_count(f) > 0 for f in ("R8", "R10", "R11"))
+    return s, prob
+
+
 # ---------------------------------------------------------------- P1
 @pytest.mark.parametrize("fam", model.FAMILY_ORDER)
-def test_jacobian_matches_central_differences(tiny, fam):
+def test_jacobian_matches_central_differences(tiny, manhattan, fam):
     """Complex-step Jacobians vs central differences through the exact
-    retraction, with non-zero distortion (Sec. 3.1-3.4 residuals)."""
-    s, prob = tiny
+    retraction, with non-zero distortion (Sec. 3.1-3.4 residuals; the
+    inter-group relations on the Manhattan scene; a VP-VP parallel pair is
+    made there by relating two Manhattan VPs that are then set parallel)."""
+    s, prob = manhattan if fam in model.RELATION_FAMILIES else tiny
     st = prob.state0()
+    if fam == "R9":
+        prob = lm.Problem(s)
+        prob.recs["R9"] = dict(ga=np.array([0, 1]), gb=np.array([3, 2]))
+        st.vp[3] = st.vp[0] + np.array([0.0, 0.05, -0.03])
+        st.vp[3] /= np.linalg.norm(st.vp[3])
     st.cam_k1 = st.cam_k1 + 0.08
     st.cam_k2 = st.cam_k2 - 0.05
     rec = prob.recs[fam]
     assert prob.record_count(fam) > 0
     J = model.jacobians(st, rec, fam, prob.cx, prob.cy)
-    for b, _, dof in model.FAMILIES[fam][2]:
-        scale = max(np.abs(J[b]).max(), 1.0)
+    for b, key, dof in model.FAMILIES[fam][2]:
+        scale = max(np.abs(J[key]).max(), 1.0)
         for k in range(dof):
-            # Richardson-extrapolated central difference: error O(h^4)
+            # Richardson-extrapolated central difference: error O(h^4); a relation's
+            # group is moved through the retraction of its own index only
             def cd(h):
-                rp = model.residuals(_retract_block(st, prob, b, k, h), rec, fam, prob.cx, prob.cy)
-                rm = model.residuals(_retract_block(st, prob, b, k, -h), rec, fam, prob.cx, prob.cy)
+                if key in ("ga", "gb"):
+                    rp = np.stack([model.residuals(_retract_one(st, prob, b, int(rec[key][i]), k, h),
+                                                   {kk: v[i:i + 1] for kk, v in rec.items()}, fam, prob.cx, prob.cy)[0]
+                                   for i in range(len(rec[key]))])
+                    rm = np.stack([model.residuals(_retract_one(st, prob, b, int(rec[key][i]), k, -h),
+                                                   {kk: v[i:i + 1] for kk, v in rec.items()}, fam, prob.cx, prob.cy)[0]
+                                   for i in range(len(rec[key]))])
+                else:
+                    rp = model.residuals(_retract_block(st, prob, b, k, h), rec, fam, prob.cx, prob.cy)
+                    rm = model.residuals(_retract_block(st, prob, b, k, -h), rec, fam, prob.cx, prob.cy)
                 return (rp - rm) / (2 * h)
             fd = (4 * cd(1e-5) - cd(2e-5)) / 3
-            err = np.abs(fd - J[b][:, :, k]).max()
+            err = np.abs(fd - J[key][:, :, k]).max()
             assert err <= 1e-6 * scale, (fam, b, k, err, scale)
 
 
@@ -206,11 +238,13 @@ def test_degenerate_line_record_jacobian_is_exact():
 
 
 # ---------------------------------------------------------------- P2
-@pytest.mark.parametrize("cfg,seed", [(small_config(), 5), (2, 2000)])
-def test_zero_residual_at_ground_truth(cfg, seed):
+@pytest.mark.parametrize("cfg,seed,families", [(small_config(), 5, 7), (2, 2000, 7), (manhattan_config(), 6, 10)])
+def test_zero_residual_at_ground_truth(cfg, seed, families):
     """Noise-free scene at ground truth: every residual vanishes (members lie
     exactly on their planes, junction points on their lines, VP lines are
-    parallel to their VP) - Eqs. 1, 4, 6, 7, 8, 11, 12."""
+    parallel to their VP, related Manhattan VPs and plane normals are exactly
+    perpendicular or parallel) - Eqs. 1, 4, 6, 7, 8, 11, 12 and the
+    inter-group relations of Sec. 3.2."""
     s = make_scene(cfg, seed=seed, noise=False)
     prob = lm.Problem(s)
     st = prob.state0()
@@ -220,9 +254,32 @@ def test_zero_residual_at_ground_truth(cfg, seed):
             continue
         present += 1
         r = model.residuals(st, prob.recs[fam], fam, prob.cx, prob.cy)
-        tol = 1e-12 if fam == "R5" else 1e-9
+        tol = 1e-12 if fam == "R5" or fam in model.RELATION_FAMILIES else 1e-9
         assert np.abs(r).max() <= tol, fam
-    assert present == 7
+    assert present == families
+
+
+def test_relation_residual_closed_forms():
+    """The relation residuals of two unit directions at angle theta: the
+    orthogonality residual is cos(theta), the parallelism residual has norm
+    |sin(theta)| and is normal to both directions; opposite directions are
+    parallel (a plane's normal is defined up to sign)."""
+    rng = np.random.default_rng(8)
+    for theta in (0.0, 0.3, np.pi / 2, 2.0, np.pi):
+        a = rng.normal(size=3)
+        a /= np.linalg.norm(a)
+        p = np.cross(a, rng.normal(size=3))
+        p /= np.linalg.norm(p)
+        b = np.cos(theta) * a + np.sin(theta) * p
+        st = model.State(np.zeros((0, 3, 3)), np.zeros((0, 3)), np.zeros(0), np.zeros(0), np.zeros(0),
+                         np.zeros((0, 3)), np.zeros((0, 3, 3)), np.zeros((0, 2)), np.zeros((0, 3)), np.zeros(0),
+                         np.stack([a, b]))
+        rec = dict(ga=np.array([0]), gb=np.array([1]))
+        ro = model.residuals(st, rec, "R8", 0.0, 0.0)[0]
+        rp = model.residuals(st, rec, "R9", 0.0, 0.0)[0]
+        assert abs(ro[0] - np.cos(theta)) < 1e-14
+        assert abs(np.linalg.norm(rp) - abs(np.sin(theta))) < 1e-14
+        assert abs(rp @ a) < 1e-14 and abs(rp @ b) < 1e-14
 
 
 # ---------------------------------------------------------------- P3
@@ -248,10 +305,12 @@ def _similarity(s, scale, Q, tr):
     return out
 
 
-def test_cost_invariant_under_similarity():
-    """Pixel residuals and the angular VP residual are invariant to a global
-    similarity (the scale-gauge of Sec. 3.3; intro and Sec. 3.3 discussion)."""
-    s = make_scene(small_config(), seed=7)
+@pytest.mark.parametrize("cfg", [small_config(), manhattan_config()])
+def test_cost_invariant_under_similarity(cfg):
+    """Pixel residuals, the angular VP residual and the inter-group relations
+    are invariant to a global similarity (the scale-gauge of Sec. 3.3; intro
+    and Sec. 3.3 discussion)."""
+    s = make_scene(cfg, seed=7)
     prob = lm.Problem(s)
     E0, Ep0 = lm.cost(prob, prob.state0())
     rng = np.random.default_rng(0)
@@ -334,10 +393,12 @@ def test_vp_residual_is_sine_of_angle():
 
 # ---------------------------------------------------------------- P6
 @pytest.mark.parametrize("lam", [1e-6, 1e-3, 1.0])
-def test_schur_step_equals_full_step(tiny, lam):
+@pytest.mark.parametrize("scene", ["tiny", "manhattan"])
+def test_schur_step_equals_full_step(tiny, manhattan, scene, lam):
     """Eq. 3 (Schur complement) gives the same step as the full damped normal
-    equations of Eq. 2 / Eq. 5."""
-    s, prob = tiny
+    equations of Eq. 2 / Eq. 5, also with the inter-group relations, whose
+    rows touch only groups in A."""
+    s, prob = tiny if scene == "tiny" else manhattan
     st = prob.state0()
     lin = lm.linearize(prob, st)
     h1, _ = lm.solve_schur(prob, lin, lam)
@@ -422,6 +483,38 @@ def test_feature_hessian_block_diagonal_and_Hcg_pattern():
         for c in range(prob.n["cam"]):
             blk = S[c * cd:(c + 1) * cd, o:o + 3]
             assert (np.abs(blk).max() > 0) == (c in cams), (g, c)
+
+
+def test_relations_touch_only_group_blocks(manhattan):
+    """Sec. 3.2, inter-group relations: they add to H_gg only.  With them on,
+    H_ff stays block-diagonal, no relation record has a camera or feature
+    column, and the group-group block of H between two distinct groups is
+    non-zero exactly when they are related (no feature couples two VPs or
+    two planes in this scene)."""
+    s, prob = manhattan
+    lin = lm.linearize(prob, prob.state0())
+    _, _, n_off = lm.feature_blocks(prob, lin)
+    assert n_off == 0
+    H = (lin.J.T @ lin.J).toarray()
+    related = set()
+    for fam in model.RELATION_FAMILIES:
+        b = model.FAMILIES[fam][2][0][0]
+        for a, c in zip(prob.recs[fam]["ga"], prob.recs[fam]["gb"]):
+            related.add((b, int(a), int(c)))
+            related.add((b, int(c), int(a)))
+    # rows of the relation records
+    row0 = sum(prob.record_count(f) * model.FAMILIES[f][1] for f in model.FAMILY_ORDER if f not in model.RELATION_FAMILIES)
+    Jrel = lin.J[row0:].toarray()
+    assert Jrel.shape[0] == sum(prob.record_count(f) * model.FAMILIES[f][1] for f in model.RELATION_FAMILIES) > 0
+    assert np.all(Jrel[:, :prob.off["pl"]] == 0) and np.all(Jrel[:, prob.nA:] == 0)
+    for b in ("pl", "vp"):
+        d, o, n = prob.dof[b], prob.off[b], prob.n[b]
+        for i in range(n):
+            for j in range(n):
+                if i == j:
+                    continue
+                blk = H[o + i * d:o + (i + 1) * d, o + j * d:o + (j + 1) * d]
+                assert (np.abs(blk).max() > 0) == ((b, i, j) in related), (b, i, j)
 
 
 # ---------------------------------------------------------------- P10
