@@ -85,7 +85,18 @@ typedef enum {
   BA_ASSOC_PLANE_POINT = 2, /* a = plane,  b = point; meas = NULL */
   BA_ASSOC_PLANE_LINE = 3,  /* a = plane,  b = line;  meas = NULL */
   BA_ASSOC_VP_LINE = 4,     /* a = vp,     b = line;  meas = NULL */
-  BA_ASSOC_JUNCTION = 5     /* a = point,  b = line;  meas = NULL (the point lies on the line) */
+  BA_ASSOC_JUNCTION = 5,    /* a = point,  b = line;  meas = NULL (the point lies on the line) */
+  /* inter-group relations (Sec. 3.2: orthogonality and parallelism between VP pairs and
+   * between plane-normal pairs, which touch only the group blocks of the reduced
+   * system): a, b = two distinct VPs or planes; meas = NULL.  Residual of the unit
+   * directions: orthogonal u_a . u_b (1 row), parallel u_a x u_b (3 rows; opposite
+   * directions count as parallel).  Default loss: Cauchy 0.2, weight 5e3, as the VP-line
+   * term; left out of E_pix like it.  Residual families 8 (VP orthogonal), 9 (VP
+   * parallel), 10 (plane orthogonal), 11 (plane parallel). */
+  BA_REL_VP_ORTHO = 6,      /* a = vp,     b = vp */
+  BA_REL_VP_PARALLEL = 7,   /* a = vp,     b = vp */
+  BA_REL_PLANE_ORTHO = 8,   /* a = plane,  b = plane */
+  BA_REL_PLANE_PARALLEL = 9 /* a = plane,  b = plane */
 } ba_kind;
 
 typedef enum { BA_LOSS_TRIVIAL = 0, BA_LOSS_HUBER = 1, BA_LOSS_CAUCHY = 2 } ba_loss_kind;
@@ -252,14 +263,19 @@ ba_status ba_set_lm_state(ba_handle *h, double lambda, double nu);
 ba_status ba_linearize(ba_handle *h, double lambda);
 
 /* Number of residual records of a family (1 point, 2 line, 3 plane-point,
- * 4 plane-line, 5 vp-line, 6 point-to-line, 7 line-to-point). */
+ * 4 plane-line, 5 vp-line, 6 point-to-line, 7 line-to-point; inter-group
+ * relations 8 VP orthogonal, 9 VP parallel, 10 plane orthogonal, 11 plane
+ * parallel). */
 ba_status ba_record_count(const ba_handle *h, int32_t family, int64_t *count);
 
 /* Export the last linearisation of a family, in the handle's internal record
  * order.  keys: count x 3 int64 (camera or -1, feature, group / partner
  * feature or -1, in the caller's indices); r: count x rows (IRLS-weighted,
  * as used by the solver); J: count x rows x (camera_dof + feature dof +
- * group dof) in that column order (weighted).  Any output may be NULL. */
+ * group dof) in that column order (weighted).  Relation families 8-11: keys
+ * (-1, group a, group b), rows 1 (orthogonal) or 3 (parallel), J columns
+ * [group a | group b] with 2 per VP and 3 per plane (the offset column is
+ * zero).  Any output may be NULL. */
 ba_status ba_export_records(const ba_handle *h, int32_t family, int64_t *keys, double *r, double *J);
 
 /* Feature blocks of the last linearisation: V_f = sum J~_f^T J~_f (undamped)

@@ -171,7 +171,9 @@ struct ba_handle {
   std::string err;
   // host FP64 parameters in the device layouts (original feature order)
   std::vector<double> cam, pt, ln, pl, vp;
-  Obs obs[6];
+  Obs obs[10];  // ba_kind 0..5 observations and associations, 6..9 inter-group relations
+  // inter-group relations: caller's (group a, group b) and kind 0..3 per record
+  std::vector<int32_t> rel_ga, rel_gb, rel_kind;
   // state
   bool finalized = false, need_lin = true, have_cost = false, first_step = true;
   double lambda = 1e-4, nu = 2.0, E = 0, Epix = 0, last_lambda = 0;
@@ -201,6 +203,8 @@ ba_loss default_loss(int kind) {
     case BA_ASSOC_PLANE_POINT: case BA_ASSOC_PLANE_LINE: return {BA_LOSS_CAUCHY, 1.0, 0.5};
     case BA_ASSOC_VP_LINE: return {BA_LOSS_CAUCHY, 0.2, 5.0e3};
     case BA_ASSOC_JUNCTION: return {BA_LOSS_CAUCHY, 1.0, 0.1};
+    case BA_REL_VP_ORTHO: case BA_REL_VP_PARALLEL: case BA_REL_PLANE_ORTHO: case BA_REL_PLANE_PARALLEL:
+      return {BA_LOSS_CAUCHY, 0.2, 5.0e3};
     default: return {BA_LOSS_TRIVIAL, 1.0, 1.0};
   }
 }
@@ -539,6 +543,41 @@ void finalize(ba_handle* h) {
     d.lkind[fam] = lo.kind; d.lscale[fam] = lo.scale; d.lweight[fam] = lo.weight;
     max_blocks += (n + 255) / 256;
     if (n > INT32_MAX) throw BaError(BA_E_INVALID, "too many records in one family");
+  }
+  // inter-group relations: records, losses per kind, and per group block (planes, then
+  // VPs) the CSR of its entries (2 * record + side)
+  {
+    h->rel_ga.clear(); h->rel_gb.clear(); h->rel_kind.clear();
+    for (int k = 0; k < 4; ++k) {
+      const Obs& o = h->obs[BA_REL_VP_ORTHO + k];
+      const ba_loss lo = o.loss_set ? o.loss : default_loss(BA_REL_VP_ORTHO + k);
+      d.rel_lkind[k] = lo.kind; d.rel_lscale[k] = lo.scale; d.rel_lweight[k] = lo.weight;
+      for (size_t i = 0; i < o.a.size(); ++i) {
+        h->rel_ga.push_back(o.a[i]); h->rel_gb.push_back(o.b[i]); h->rel_kind.push_back(k);
+      }
+    }
+    const int n = (int)h->rel_kind.size();
+    d.n_rel = n;
+    const int nb = h->ng + h->nv;
+    std::vector<int32_t> goff(nb + 1, 0), gent(2 * (size_t)n);
+    auto block = [&](int i, int side) {
+      const int g = side ? h->rel_gb[i] : h->rel_ga[i];
+      return h->rel_kind[i] >= 2 ? g : h->ng + g;
+    };
+    for (int i = 0; i < n; ++i)
+      for (int side = 0; side < 2; ++side) goff[block(i, side) + 1]++;
+    for (int b = 0; b < nb; ++b) goff[b + 1] += goff[b];
+    std::vector<int32_t> fill(goff.begin(), goff.end() - 1);
+    for (int i = 0; i < n; ++i)
+      for (int side = 0; side < 2; ++side) gent[fill[block(i, side)]++] = 2 * i + side;
+    d.rel_ga = A.get<int32_t>(n); d.rel_gb = A.get<int32_t>(n); d.rel_kind = A.get<int32_t>(n);
+    d.rel_goff = A.get<int32_t>(nb + 1); d.rel_gent = A.get<int32_t>(2 * (size_t)n);
+    d.rel_r = A.get<double>(3 * (size_t)n); d.rel_J = A.get<double>(18 * (size_t)n);
+    d.rel_y = A.get<double>(d.nA);
+    launch_zero(d.rel_y, (size_t)std::max(d.nA, 1) * sizeof(double), h->stream);
+    upload(h, d.rel_ga, h->rel_ga); upload(h, d.rel_gb, h->rel_gb); upload(h, d.rel_kind, h->rel_kind);
+    upload(h, d.rel_goff, goff); upload(h, d.rel_gent, gent);
+    if (n) max_blocks += 1;  // one cost partial
   }
   // block graph of the reduced system: blocks are adjacent when they share a feature
   {
@@ -1182,7 +1221,7 @@ ba_status ba_create(const ba_problem_desc* desc, ba_handle** out) {
     }
     for (int k = 0; k <= BA_PHASE_COUNT; ++k) HIPCHK(hipEventCreate(&h->ev[k]));
     h->events = true;
-    for (int k = 0; k < 6; ++k) h->obs[k].loss = default_loss(k);
+    for (int k = 0; k < 10; ++k) h->obs[k].loss = default_loss(k);
   });
   if (st != BA_OK) {
     ba_destroy(h);
@@ -1197,7 +1236,7 @@ ba_status ba_add_observations(ba_handle* h, int32_t kind, int64_t n, const int32
   if (!h) return BA_E_INVALID;
   return guard(h, [&] {
     if (h->finalized) throw BaError(BA_E_STATE, "observations must be added before the first step");
-    if (kind < 0 || kind > 5) throw BaError(BA_E_INVALID, "bad kind");
+    if (kind < 0 || kind > 9) throw BaError(BA_E_INVALID, "bad kind");
     if (n < 0 || (n > 0 && (!a || !b))) throw BaError(BA_E_INVALID, "bad arrays");
     const bool has_meas = kind == BA_OBS_POINT || kind == BA_OBS_LINE;
     if (has_meas && n > 0 && !meas) throw BaError(BA_E_INVALID, "measurements required");
@@ -1209,9 +1248,14 @@ ba_status ba_add_observations(ba_handle* h, int32_t kind, int64_t n, const int32
       case BA_ASSOC_PLANE_LINE: ha = h->ng; hb = h->nl; break;
       case BA_ASSOC_VP_LINE: ha = h->nv; hb = h->nl; break;
       case BA_ASSOC_JUNCTION: ha = h->np; hb = h->nl; break;
+      case BA_REL_VP_ORTHO: case BA_REL_VP_PARALLEL: ha = hb = h->nv; break;
+      case BA_REL_PLANE_ORTHO: case BA_REL_PLANE_PARALLEL: ha = hb = h->ng; break;
     }
     check_index(a, n, ha, "first");
     check_index(b, n, hb, "second");
+    if (kind >= BA_REL_VP_ORTHO)
+      for (int64_t i = 0; i < n; ++i)
+        if (a[i] == b[i]) throw BaError(BA_E_INVALID, "a relation needs two distinct groups");
     if (has_meas && !finite_all(meas, (size_t)n * 4)) throw BaError(BA_E_INVALID, "non-finite measurement");
     if (loss) {
       if (loss->kind < 0 || loss->kind > 2 || !(loss->scale > 0) || !(loss->weight > 0) || !std::isfinite(loss->scale) ||
@@ -1370,15 +1414,48 @@ ba_status ba_linearize(ba_handle* h, double lambda) {
 }
 
 ba_status ba_record_count(const ba_handle* h, int32_t family, int64_t* count) {
-  if (!h || family < 1 || family > 7 || !count) return BA_E_INVALID;
+  if (!h || family < 1 || family > 11 || !count) return BA_E_INVALID;
   if (!h->finalized) { const_cast<ba_handle*>(h)->err = "records exist after the first step"; return BA_E_STATE; }
-  *count = h->d.fn[family];
+  if (family >= 8) *count = std::count(h->rel_kind.begin(), h->rel_kind.end(), family - 8);
+  else *count = h->d.fn[family];
   return BA_OK;
 }
 
+namespace {
+// relation family 8..11: the records of kind family - 8
+ba_status export_relations(ba_handle* h, int32_t fam, int64_t* keys, double* r, double* J) {
+  return guard(h, [&] {
+    if (!h->finalized) throw BaError(BA_E_STATE, "no records yet");
+    const int kind = fam - 8, rows = (kind == 1 || kind == 3) ? 3 : 1, gd = kind >= 2 ? 3 : 2;
+    const int n = h->d.n_rel;
+    std::vector<double> rr(3 * (size_t)n), JJ(18 * (size_t)n);
+    if ((r || J) && n) {
+      set_device(h);
+      HIPCHK(hipMemcpyAsync(rr.data(), h->d.rel_r, rr.size() * 8, hipMemcpyDeviceToHost, h->stream));
+      HIPCHK(hipMemcpyAsync(JJ.data(), h->d.rel_J, JJ.size() * 8, hipMemcpyDeviceToHost, h->stream));
+      sync(h);
+    }
+    int64_t o = 0;
+    for (int i = 0; i < n; ++i) {
+      if (h->rel_kind[i] != kind) continue;
+      if (keys) { keys[3 * o] = -1; keys[3 * o + 1] = h->rel_ga[i]; keys[3 * o + 2] = h->rel_gb[i]; }
+      for (int row = 0; row < rows; ++row) {
+        if (r) r[o * rows + row] = rr[3 * (size_t)i + row];
+        if (J)
+          for (int side = 0; side < 2; ++side)
+            for (int c = 0; c < gd; ++c)
+              J[(o * rows + row) * 2 * gd + side * gd + c] = JJ[((size_t)i * 3 + row) * 6 + 3 * side + c];
+      }
+      ++o;
+    }
+  });
+}
+}  // namespace
+
 ba_status ba_export_records(const ba_handle* hc, int32_t fam, int64_t* keys, double* r, double* J) {
   ba_handle* h = const_cast<ba_handle*>(hc);
-  if (!h || fam < 1 || fam > 7) return BA_E_INVALID;
+  if (!h || fam < 1 || fam > 11) return BA_E_INVALID;
+  if (fam >= 8) return export_relations(h, fam, keys, r, J);
   return guard(h, [&] {
     if (!h->finalized) throw BaError(BA_E_STATE, "no records yet");
     const int64_t n = h->d.fn[fam];

@@ -116,6 +116,17 @@ struct Dev {
   // features too large for one tile (handled one lane per feature)
   int n_bigp = 0, n_bigl = 0;
   int32_t *bigp = nullptr, *bigl = nullptr;
+  // inter-group relations (A-side records, FP64): group indices (planes or VPs), kind
+  // 0 VP orthogonal, 1 VP parallel, 2 plane orthogonal, 3 plane parallel; weighted
+  // residual (3 rows, unused rows zero) and Jacobian (3 rows x [J_a (3) | J_b (3)],
+  // a VP's third column zero); per group block (planes, then VPs) a CSR of its
+  // entries 2 * record + side; rel_y: the relations' part of S x (group rows)
+  int n_rel = 0;
+  int32_t *rel_ga = nullptr, *rel_gb = nullptr, *rel_kind = nullptr;
+  int32_t *rel_goff = nullptr, *rel_gent = nullptr;
+  double *rel_r = nullptr, *rel_J = nullptr, *rel_y = nullptr;
+  int rel_lkind[4] = {0, 0, 0, 0};
+  double rel_lscale[4] = {0, 0, 0, 0}, rel_lweight[4] = {0, 0, 0, 0};
   // deterministic mode: the product's s_f per feature (T; points x 3, lines x 4) and the
   // per-workgroup partials of the PCG dot products (det_stride workgroups per accumulator:
   // the SC_COUNT scalars, then the COARSE_K entries of Z^T b)
@@ -176,6 +187,13 @@ void launch_pcg_update(const Dev& d, double lambda, int iter, hipStream_t s);  /
 void launch_schur_matvec(const Dev& d, const double* xin, double* yout, double lambda, hipStream_t s);
 // S (nA x nA, device; column c = S e_c) by nA products
 void launch_dense_schur(const Dev& d, double lambda, double* S, hipStream_t s);
+// inter-group relations (ba_rel.hip)
+void launch_rel_linearize(const Dev& d, hipStream_t s);
+void launch_rel_a(const Dev& d, hipStream_t s);          // after the group pass A: U_gg, g_g, D_g
+void launch_rel_matvec(const Dev& d, const double* done, hipStream_t s);  // d.rel_y from d.xT
+void launch_rel_sz(const Dev& d, hipStream_t s);         // S Z += U_rel Z on the active columns
+void launch_rel_cost(const Dev& d, bool candidate, double* part, hipStream_t s);  // one partial
+void launch_rel_md(const Dev& d, hipStream_t s);  // after the model decrease: + sum |J~ h_a|^2
 // columns c0 .. c0 + ncols - 1 of the damped reduced matrix into S (ncols x n_A)
 void launch_dense_schur_columns(const Dev& d, double lambda, int c0, int ncols, double* S, hipStream_t s);
 // gauge columns of d.Zc from the current parameters

@@ -385,6 +385,7 @@ void launch_linearize(const Dev& d, hipStream_t s) {
     if (d.fn[6]) k_lin<6, T, CD><<<nblk(d.fn[6], 256), 256, 0, s>>>(d);
     if (d.fn[7]) k_lin<7, T, CD><<<nblk(d.fn[7], 256), 256, 0, s>>>(d);
   });
+  launch_rel_linearize(d, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -428,7 +429,9 @@ __global__ __launch_bounds__(1024) void k_cost_final(const double* part, int n, 
 }
 
 void launch_cost(const Dev& d, bool candidate, hipStream_t s) {
-  int off = 0, x0 = 0, x1 = 0;
+  // the angular terms (VP-line records, then the inter-group relations) take one
+  // contiguous range [x0, x1) of the partials, which E_pix leaves out
+  int off = 0, x0 = -1, x1 = 0;
   auto go = [&](int fam) {
     if (!d.fn[fam]) return;
     unsigned nb = nblk(d.fn[fam], 256);
@@ -445,7 +448,14 @@ void launch_cost(const Dev& d, bool candidate, hipStream_t s) {
     off += (int)nb;
     if (fam == 5) x1 = off;
   };
-  for (int fam = 1; fam <= 7; ++fam) go(fam);
+  for (int fam = 1; fam <= 5; ++fam) go(fam);
+  if (d.n_rel) {
+    if (x0 < 0) x0 = off;
+    launch_rel_cost(d, candidate, d.red + off, s);
+    x1 = ++off;
+  }
+  for (int fam = 6; fam <= 7; ++fam) go(fam);
+  if (x0 < 0) x0 = x1 = 0;
   k_cost_final<<<1, 1024, 0, s>>>(d.red, off, x0, x1, d.scal);
 }
 
@@ -859,6 +869,7 @@ void launch_camera_pass_a(const Dev& d, hipStream_t s) {
     if (d.nc) k_cam_a<T, CD><<<d.nc, 256, 0, s>>>(d);
     if (d.ng + d.nv) k_grp_a<T, CD><<<d.ng + d.nv, 256, 0, s>>>(d);
   });
+  launch_rel_a(d, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -1536,6 +1547,7 @@ template <typename T, int CD> static void run_matvec(const Dev& d, const double*
   } else {
     launch_mv<T, CD, false>(d, done, s);
   }
+  launch_rel_matvec(d, done, s);  // the inter-group relations' rows, added by k_pcg_q
 }
 
 // ---------------------------------------------------------------------------
@@ -1752,7 +1764,7 @@ template <typename T> __global__ __launch_bounds__(1024) void k_pcg_q(Dev d, con
     double t = 0;
 #pragma unroll
     for (int j = 0; j < 16; ++j) t += red[j][lane];
-    const double qv = t + lam * d.DA[e] * xin[e];
+    const double qv = t + lam * d.DA[e] * xin[e] + (d.n_rel ? d.rel_y[e] : 0.0);
     y[e] = qv;
     dot[0] = xin[e] * qv;
   }
@@ -2713,6 +2725,9 @@ template <typename T, int CD> static void launch_sz(const Dev& d, double lambda,
 
 void launch_coarse_setup(const Dev& d, double lambda, hipStream_t s) {
   BA_DISPATCH_T_CD(d, launch_sz<T, CD>(d, lambda, s));
+  // inter-group relations touch no feature: their part of S Z is U_rel Z in the group
+  // rows, for the gauge columns too (the closed form covers the feature records only)
+  launch_rel_sz(d, s);
   double* E = d.Ztb + COARSE_K;  // K x K scratch after Z^T b
   k_coarse_e<<<COARSE_K * COARSE_K, 256, 0, s>>>(d, E);
   k_coarse_inv<<<1, 512, 0, s>>>(d, E);
@@ -2944,8 +2959,9 @@ template <typename T, int CD> __global__ __launch_bounds__(256) void k_backsub_w
   if (threadIdx.x == 0) { d.red[2 * blockIdx.x] = o[0]; d.red[2 * blockIdx.x + 1] = o[1]; }
 }
 
-// camera/group records of no feature do not exist, so J h over all records is
-// covered by the feature pass; this adds g_a . h_a and sums the partials
+// J h over the records of the features is covered by the feature pass (the
+// inter-group relations, which have no feature, are added by launch_rel_md); this
+// adds g_a . h_a and sums the partials
 __global__ __launch_bounds__(1024) void k_md_final(Dev d, int nparts) {
   __shared__ double lds[2 * 17];
   double v[2] = {0, 0};
@@ -2962,6 +2978,7 @@ void launch_backsub(const Dev& d, hipStream_t s) {
     k_backsub_wave<T, CD><<<nwg, 256, 0, s>>>(d);
   });
   k_md_final<<<1, 1024, 0, s>>>(d, nwg);
+  launch_rel_md(d, s);
 }
 
 // ---------------------------------------------------------------------------
