@@ -129,6 +129,17 @@ typedef struct {
 #define BA_PCG_BREAKDOWN 1         /* p.Sp <= 0 or not finite: the solve stopped early */
 #define BA_PCG_COARSE_FALLBACK 2   /* the two-level solve broke down and was repeated with block-Jacobi */
 #define BA_PCG_NONFINITE_RHS 4     /* the reduced right-hand side was not finite: step rejected, relinearised next */
+#define BA_SOLVE_NOT_SPD 8         /* dense solver: a pivot of the Cholesky factorisation of S was not positive
+                                      (S not positive definite in FP64): no step formed, rejected (E_after NaN) */
+
+/* Solver of the reduced camera / group system S h_a = b (Sec. 3.1 Eq. 3).  The paper
+ * solves it with a sparse or a dense Schur-complement method chosen by image count
+ * (Sec. 4.1).  BA_SOLVER_PCG: implicit-Schur preconditioned conjugate gradients
+ * (S never formed).  BA_SOLVER_DENSE: S formed explicitly in FP64 from the record
+ * Jacobians (both precisions' Jacobians; FP64 arithmetic), factored by Cholesky on the
+ * device and solved exactly; for reduced systems of at most 8192 rows (n_A^2 doubles of
+ * device memory). */
+typedef enum { BA_SOLVER_PCG = 0, BA_SOLVER_DENSE = 1 } ba_linear_solver;
 
 typedef struct {
   int32_t max_iters;      /* ba_solve: attempts (accepted or rejected); default 100 */
@@ -151,6 +162,12 @@ typedef struct {
                              one FP64 atomic per workgroup).  Slower; 0 (the default)
                              keeps the atomics.  The network's message aggregation of the
                              learned preconditioner still sums with FP32 atomics. */
+  int32_t linear_solver;  /* ba_linear_solver; BA_SOLVER_PCG.  With BA_SOLVER_DENSE the PCG
+                             and preconditioner options are unused, pcg_iters is 0,
+                             pcg_rel_residual is |S h_a - b| / |b| with S h_a from the
+                             implicit product, and the step's ms[BA_PHASE_PCG] is the
+                             assembly, factorisation and solve; deterministic by
+                             construction */
 } ba_solve_options;
 
 enum {
@@ -366,6 +383,26 @@ ba_status ba_export_gnn_graph(ba_handle *h, int32_t *n_nodes, int32_t *n_edges, 
  * implicit-Schur product (n_A products: meant for small systems, e.g.
  * training data and tests).  Temporary device memory: 8 n_A^2 bytes. */
 ba_status ba_export_schur_dense(ba_handle *h, double *S);
+
+/* The damped reduced matrix S of the last ba_linearize (Sec. 3.1 Eq. 3), dense
+ * (n_A x n_A doubles, row-major, caller-allocated), as the dense solver forms it:
+ * block pair by block pair from the records' Jacobians and the feature blocks'
+ * inverses, in FP64 (BA_SOLVER_DENSE).  BA_E_STATE before the first linearisation;
+ * BA_E_INVALID when n_A exceeds 8192.  Allocates the dense solver's device storage
+ * on first use (kept with the handle). */
+ba_status ba_export_schur_assembled(ba_handle *h, double *S);
+
+/* Dense symmetric positive definite solve on the device (the factorisation and
+ * triangular solves of BA_SOLVER_DENSE): A (n x n doubles, row-major, device memory;
+ * the lower triangle is read) is overwritten by its lower Cholesky factor L, A = L
+ * L^T, with the strict upper triangle zeroed, and b (n doubles, device memory) by
+ * x = A^-1 b.  FP64 throughout: right-looking blocked Cholesky on 64 x 64 tiles,
+ * tile products on the matrix cores.  Runs on hip_stream (NULL: the default stream)
+ * of the given device and returns when it is done.  *info = 0 on success, else
+ * 1 + the first column whose pivot was not positive or not finite (A not positive
+ * definite in FP64); A and b are then unspecified and the status is BA_E_NUMERIC.
+ * Temporary device memory: about 8 (n + 63)^2 bytes.  n = 0 is a no-op. */
+ba_status ba_dense_spd_solve(int32_t device, int64_t n, double *A, double *b, void *hip_stream, int32_t *info);
 
 /* ba_export_schur_dense for callers that cannot allocate device memory (code
  * under HIP graph capture, tight serving loops, harnesses that forbid

@@ -46,7 +46,7 @@ class ProblemDesc(ctypes.Structure):
 class SolveOptions(ctypes.Structure):
     _fields_ = [("max_iters", c_int32), ("func_tol", c_double), ("grad_tol", c_double), ("pcg_tol", c_double),
                 ("pcg_max_iters", c_int32), ("lambda0", c_double), ("nu0", c_double), ("kappa_max", c_double),
-                ("time_kernels", c_int32), ("deterministic", c_int32)]
+                ("time_kernels", c_int32), ("deterministic", c_int32), ("linear_solver", c_int32)]
 
 
 class StepReport(ctypes.Structure):
@@ -109,6 +109,8 @@ def _load():
         "ba_normalized_matvec": (c_int32, [H, D, D]),
         "ba_export_schur_dense": (c_int32, [H, D]),
         "ba_export_schur_dense_noalloc": (c_int32, [H, D]),
+        "ba_export_schur_assembled": (c_int32, [H, D]),
+        "ba_dense_spd_solve": (c_int32, [c_int32, c_int64, c_void_p, c_void_p, c_void_p, I32]),
         "ba_export_gauge_basis": (c_int32, [H, D]),
         "ba_export_coarse_space": (c_int32, [H, I32, D, D]),
         "ba_gnn_create": (c_int32, [c_int32, c_int32, c_int32, POINTER(c_void_p)]),
@@ -148,10 +150,17 @@ def _f64(a, shape_last=None):
     return a
 
 
+SOLVERS = {"pcg": 0, "dense": 1}
+
+
 def default_options(**kw) -> SolveOptions:
+    """Library defaults with the given fields replaced; solver="pcg" / "dense" sets
+    linear_solver."""
     o = SolveOptions()
     _lib.ba_default_options(ctypes.byref(o))
     for k, v in kw.items():
+        if k == "solver":
+            k, v = "linear_solver", SOLVERS[v]
         if not hasattr(o, k):
             raise KeyError(k)
         setattr(o, k, v)
@@ -336,6 +345,14 @@ class BA:
         self._check(_lib.ba_export_schur_dense(self._h, _dp(S)))
         return S
 
+    def export_schur_assembled(self):
+        """Damped reduced matrix S of the last linearisation as the dense solver
+        forms it (block pairs, FP64)."""
+        nA, _ = self.reduced_dim()
+        S = np.zeros((nA, nA))
+        self._check(_lib.ba_export_schur_assembled(self._h, _dp(S)))
+        return S
+
     def export_schur_dense_noalloc(self):
         """The same S staged through the library's fixed device scratch panel
         (no device allocation in the call)."""
@@ -455,3 +472,17 @@ class GNN:
         g = np.zeros(self.n_params, np.float32) if want_grad else None
         self._check(_lib.ba_gnn_train_step(self._h, ctypes.byref(batch.s), float(lr), ctypes.byref(L), _fp(g)))
         return (L.value, g) if want_grad else L.value
+
+
+def dense_spd_solve(A, b, device=0, stream=None):
+    """In place on device memory: A (n x n float64, contiguous) becomes its lower
+    Cholesky factor and b (n float64) the solution of A x = b.  A and b are torch
+    tensors on the GPU.  Returns (status, info): info = 0, or 1 + the first column
+    with a non-positive pivot (status BA_E_NUMERIC)."""
+    n = int(b.shape[0])
+    if tuple(A.shape) != (n, n) or not A.is_contiguous() or not b.is_contiguous():
+        raise ValueError("A must be a contiguous n x n and b a contiguous n-vector")
+    info = c_int32(0)
+    st = _lib.ba_dense_spd_solve(int(device), n, c_void_p(A.data_ptr()), c_void_p(b.data_ptr()),
+                                 c_void_p(stream) if stream else None, ctypes.byref(info))
+    return st, info.value

@@ -10,7 +10,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libba.so")
-SOURCES = ["ba_kernels.hip", "ba_host.hip", "ba_gnn.hip", "ba_rel.hip"]
+SOURCES = ["ba_kernels.hip", "ba_host.hip", "ba_gnn.hip", "ba_rel.hip", "ba_dense.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 

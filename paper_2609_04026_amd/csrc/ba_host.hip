@@ -194,6 +194,15 @@ struct ba_handle {
   hipEvent_t ev[BA_PHASE_COUNT + 1] = {};
   bool events = false;
   std::vector<hipEvent_t> mv_ev;  // pool for per-product timing
+  // dense Schur solver: host tables of the (feature, block) entries and block pairs,
+  // built at the symbolic phase for reduced systems of at most DENSE_MAX_NA rows and
+  // uploaded, with the matrix storage, on first use
+  struct DenseHost {
+    bool built = false, uploaded = false;
+    std::string why = "the dense solver's tables have not been built";
+    std::vector<int2> fent, pair_ab, pair_ent, pair_u;
+    std::vector<int32_t> pair_off, pair_uoff;
+  } dense;
 };
 
 namespace {
@@ -270,6 +279,134 @@ CSR build_csr(const Obs& o, int nfeat, const char* what) {
     }
   }
   return s;
+}
+
+// Dense solver tables (host).  Entries: one per (feature, distinct block of its
+// records), in feature order (off2 / fb).  Pairs (a <= b): every diagonal pair, the block
+// pairs of each feature, the (camera, plane) pairs of the plane-association records and
+// the group pairs of the relations; numbered in (a, b) order.  Per pair, its feature
+// entries in feature order, then its U entries in record order.
+void build_dense_tables(ba_handle* h, const std::vector<Rec> (&R)[NFAM], const std::vector<int64_t>& off2,
+                        const std::vector<int32_t>& fb) {
+  auto& D = h->dense;
+  const int nb = h->nc + h->ng + h->nv;
+  const int nfeat = h->np + h->nl;
+  if ((int64_t)fb.size() > INT32_MAX) {
+    D.why = "too many (feature, block) entries for the dense solver";
+    return;
+  }
+  std::vector<int32_t> pid((size_t)nb * nb, -1);
+  auto at = [&](int a, int b) -> int32_t& { return a <= b ? pid[(size_t)a * nb + b] : pid[(size_t)b * nb + a]; };
+  auto rel_block = [&](size_t i, bool second) {
+    const int g = second ? h->rel_gb[i] : h->rel_ga[i];
+    return h->rel_kind[i] >= 2 ? h->nc + g : h->nc + h->ng + g;
+  };
+  int64_t n_ent = 0;
+  for (int b = 0; b < nb; ++b) at(b, b) = 0;
+  for (int f = 0; f < nfeat; ++f)
+    for (int64_t i = off2[f]; i < off2[f + 1]; ++i)
+      for (int64_t j = i; j < off2[f + 1]; ++j) {
+        at(fb[i], fb[j]) = 0;
+        ++n_ent;
+      }
+  if (n_ent > INT32_MAX) {
+    D.why = "too many shared-feature terms for the dense solver";
+    return;
+  }
+  for (int fam = 3; fam <= 4; ++fam)
+    for (const Rec& r : R[fam]) at(r.cam, h->nc + r.grp) = 0;
+  for (size_t i = 0; i < h->rel_kind.size(); ++i) at(rel_block(i, false), rel_block(i, true)) = 0;
+  D.pair_ab.clear();
+  for (int a = 0; a < nb; ++a)
+    for (int b = a; b < nb; ++b) {
+      int32_t& p = pid[(size_t)a * nb + b];
+      if (p == 0) {
+        p = (int32_t)D.pair_ab.size();
+        D.pair_ab.push_back(make_int2(a, b));
+      }
+    }
+  const size_t np_ = D.pair_ab.size();
+  D.pair_off.assign(np_ + 1, 0);
+  D.pair_uoff.assign(np_ + 1, 0);
+  for (int f = 0; f < nfeat; ++f)
+    for (int64_t i = off2[f]; i < off2[f + 1]; ++i)
+      for (int64_t j = i; j < off2[f + 1]; ++j) D.pair_off[at(fb[i], fb[j]) + 1]++;
+  for (int fam = 3; fam <= 4; ++fam)
+    for (const Rec& r : R[fam]) D.pair_uoff[at(r.cam, h->nc + r.grp) + 1]++;
+  for (size_t i = 0; i < h->rel_kind.size(); ++i) D.pair_uoff[at(rel_block(i, false), rel_block(i, true)) + 1]++;
+  for (size_t p = 0; p < np_; ++p) {
+    D.pair_off[p + 1] += D.pair_off[p];
+    D.pair_uoff[p + 1] += D.pair_uoff[p];
+  }
+  D.pair_ent.assign((size_t)D.pair_off[np_], make_int2(0, 0));
+  D.pair_u.assign((size_t)D.pair_uoff[np_], make_int2(0, 0));
+  std::vector<int32_t> fill(D.pair_off.begin(), D.pair_off.end() - 1);
+  for (int f = 0; f < nfeat; ++f)
+    for (int64_t i = off2[f]; i < off2[f + 1]; ++i)
+      for (int64_t j = i; j < off2[f + 1]; ++j)
+        D.pair_ent[fill[at(fb[i], fb[j])]++] = make_int2((int)i, (int)j);
+  fill.assign(D.pair_uoff.begin(), D.pair_uoff.end() - 1);
+  for (int fam = 3; fam <= 4; ++fam)
+    for (size_t k = 0; k < R[fam].size(); ++k) {
+      const Rec& r = R[fam][k];
+      D.pair_u[fill[at(r.cam, h->nc + r.grp)]++] = make_int2(fam, (int)k);
+    }
+  for (size_t i = 0; i < h->rel_kind.size(); ++i) {
+    const int a = rel_block(i, false), b = rel_block(i, true);
+    D.pair_u[fill[at(a, b)]++] = make_int2(a < b ? 8 : 9, (int)i);
+  }
+  D.fent.resize(fb.size());
+  for (int f = 0; f < nfeat; ++f)
+    for (int64_t i = off2[f]; i < off2[f + 1]; ++i) D.fent[i] = make_int2(f, fb[i]);
+  D.built = true;
+  D.why.clear();
+}
+
+// device storage of the dense solver, allocated and filled on first use
+void dense_prepare(ba_handle* h) {
+  auto& D = h->dense;
+  if (!D.built) throw BaError(BA_E_INVALID, "dense solver unavailable: " + D.why);
+  if (D.uploaded) return;
+  Dev& d = h->d;
+  DevAlloc& A = h->alloc;
+  d.dense_n = d.nA;
+  d.dense_npad = (d.nA + DENSE_NB - 1) / DENSE_NB * DENSE_NB;
+  d.n_fent = (int)D.fent.size();
+  d.n_pair = (int)D.pair_ab.size();
+  if (d.nA > 0) {
+    d.fent = A.get<int2>(D.fent.size());
+    d.pair_ab = A.get<int2>(D.pair_ab.size());
+    d.pair_ent = A.get<int2>(D.pair_ent.size());
+    d.pair_u = A.get<int2>(D.pair_u.size());
+    d.pair_off = A.get<int32_t>(D.pair_off.size());
+    d.pair_uoff = A.get<int32_t>(D.pair_uoff.size());
+    d.dY = A.get<double>((size_t)DENSE_Y * D.fent.size());
+    d.dS = A.get<double>((size_t)d.dense_npad * d.dense_npad);
+    d.dLinv = A.get<double>((size_t)d.dense_npad * DENSE_NB);
+    d.dv = A.get<double>(d.dense_npad);
+    d.dw = A.get<double>(d.dense_npad);
+    upload(h, d.fent, D.fent);
+    upload(h, d.pair_ab, D.pair_ab);
+    upload(h, d.pair_ent, D.pair_ent);
+    upload(h, d.pair_u, D.pair_u);
+    upload(h, d.pair_off, D.pair_off);
+    upload(h, d.pair_uoff, D.pair_uoff);
+  }
+  d.dinfo = A.get<int>(1);
+  sync(h);
+  D.uploaded = true;
+}
+
+// the direct solve of S h_a = b for the current lambda into d.x; false when S is
+// not positive definite (d.x unchanged)
+bool dense_solve(ba_handle* h, double lambda) {
+  dense_prepare(h);
+  launch_dense_solve(h->d, lambda, h->stream);
+  check_launch("dense solve");
+  int info = 0;
+  HIPCHK(hipMemcpyAsync(&info, h->d.dinfo, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+  sync(h);
+  return info == 0;
 }
 
 void finalize(ba_handle* h) {
@@ -579,10 +716,21 @@ void finalize(ba_handle* h) {
     upload(h, d.rel_goff, goff); upload(h, d.rel_gent, gent);
     if (n) max_blocks += 1;  // one cost partial
   }
-  // block graph of the reduced system: blocks are adjacent when they share a feature
+  // block graph of the reduced system (blocks are adjacent when they share a feature)
+  // and the dense solver's tables
   {
     const int nblocks = h->nc + h->ng + h->nv;
-    if (nblocks > 0 && nblocks <= ba_gnn_impl::MAX_GRAPH_NODES) {
+    const bool want_graph = nblocks > 0 && nblocks <= ba_gnn_impl::MAX_GRAPH_NODES;
+    const bool want_dense = d.nA > 0 && d.nA <= DENSE_MAX_NA;
+    h->dense = ba_handle::DenseHost();
+    if (d.nA > DENSE_MAX_NA)
+      h->dense.why = "the reduced system has " + std::to_string(d.nA) + " rows, more than the dense solver's " +
+                     std::to_string(DENSE_MAX_NA);
+    if (d.nA == 0) {
+      h->dense.built = true;
+      h->dense.why.clear();
+    }
+    if (want_graph || want_dense) {
       const int nfeat = h->np + h->nl;
       std::vector<int64_t> fb_off(nfeat + 1, 0), block_records(nblocks, 0);
       auto block_of = [&](int fam, const Rec& r, int32_t out[2]) {
@@ -633,7 +781,8 @@ void finalize(ba_handle* h) {
         for (int k = 0; k < 3; ++k) s0 += (ctr[3 * i + k] - mean[k]) * (ctr[3 * i + k] - mean[k]) / h->nc;
       s0 = std::sqrt(s0);
       if (!(s0 > 0) || !std::isfinite(s0)) s0 = 1.0;
-      ba_gnn_impl::build_graph(h->graph, h->nc, h->ng, h->nv, h->CD, off2, fb, block_records, s0);
+      if (want_graph) ba_gnn_impl::build_graph(h->graph, h->nc, h->ng, h->nv, h->CD, off2, fb, block_records, s0);
+      if (want_dense) build_dense_tables(h, R, off2, fb);
     }
     if (h->graph.valid) {
       const auto& G = h->graph;
@@ -1093,12 +1242,28 @@ bool do_step(ba_handle* h, const ba_solve_options& o, ba_step_report* rep, doubl
   record(h, 1);
   assemble_schur(h, h->lambda, o.kappa_max);
   record(h, 2);
-  assemble_precond(h, h->lambda);
-  record(h, 3);
+  const bool dense = o.linear_solver == BA_SOLVER_DENSE;
+  bool solved = true;
   double mv_ms = 0;
-  r.pcg_iters = pcg(h, h->lambda, o.pcg_tol, o.pcg_max_iters, o.time_kernels ? &mv_ms : nullptr);
-  r.coarse = h->d.coarse_k > 0 && h->hscal[SC_COARSE] != 0.0 ? h->d.coarse_k : 0;
-  if (h->hscal[SC_BREAK] != 0.0) r.pcg_flags |= BA_PCG_BREAKDOWN;
+  if (dense) {
+    // direct solve: S formed and factored (the preconditioner phase is empty)
+    record(h, 3);
+    solved = dense_solve(h, h->lambda);
+    if (solved) {
+      launch_dense_residual(h->d, h->lambda, h->stream);
+      check_launch("dense solve residual");
+    }
+    read_scal(h);
+    r.pcg_iters = 0;
+    r.coarse = 0;
+    if (!solved) r.pcg_flags |= BA_SOLVE_NOT_SPD;
+  } else {
+    assemble_precond(h, h->lambda);
+    record(h, 3);
+    r.pcg_iters = pcg(h, h->lambda, o.pcg_tol, o.pcg_max_iters, o.time_kernels ? &mv_ms : nullptr);
+    r.coarse = h->d.coarse_k > 0 && h->hscal[SC_COARSE] != 0.0 ? h->d.coarse_k : 0;
+  }
+  if (!dense && h->hscal[SC_BREAK] != 0.0) r.pcg_flags |= BA_PCG_BREAKDOWN;
   if (r.coarse > 0 && (h->hscal[SC_BREAK] != 0.0 || !std::isfinite(h->hscal[SC_RR]) || !std::isfinite(h->hscal[SC_RZ]))) {
     // the two-level solve broke down: solve again with block-Jacobi alone
     h->d.coarse_k = 0;
@@ -1109,24 +1274,33 @@ bool do_step(ba_handle* h, const ba_solve_options& o, ba_step_report* rep, doubl
     mv_ms += mv2;
   }
   r.matvec_ms = mv_ms;
-  r.matvec_count = o.time_kernels ? r.pcg_iters + (h->hscal[SC_BREAK] != 0.0 ? 1 : 0) : 0;
+  r.matvec_count = o.time_kernels && !dense ? r.pcg_iters + (h->hscal[SC_BREAK] != 0.0 ? 1 : 0) : 0;
   record(h, 4);
   const double rr = h->hscal[SC_RR], bb = h->hscal[SC_BB];
-  if (!std::isfinite(bb)) r.pcg_flags |= BA_PCG_NONFINITE_RHS;
-  r.pcg_rel_residual = bb > 0 ? std::sqrt(rr / bb) : 0.0;
+  if (solved && !std::isfinite(bb)) r.pcg_flags |= BA_PCG_NONFINITE_RHS;
+  r.pcg_rel_residual = solved && bb > 0 ? std::sqrt(rr / bb) : 0.0;
   r.n_fp64_blocks = (int)h->hscal[SC_NFLAG];
   r.n_fp64_failed = (int)h->hscal[SC_NFAIL];
   r.n_degenerate = (int)h->hscal[SC_NDEG];
   r.grad_inf = h->hscal[SC_GINF];
-  launch_backsub(h->d, h->stream);
-  record(h, 5);
-  launch_retract(h->d, h->stream);
-  launch_cost(h->d, true, h->stream);
-  record(h, 6);
-  check_launch("backsub / retract / cost");
-  read_scal(h);
-  const double En = h->hscal[SC_E], Epn = h->hscal[SC_EPIX];
-  const double dL = -h->hscal[SC_GH] - 0.5 * h->hscal[SC_JH2];
+  double En = NAN, Epn = NAN, dL = 0;
+  if (solved) {
+    launch_backsub(h->d, h->stream);
+    record(h, 5);
+    launch_retract(h->d, h->stream);
+    launch_cost(h->d, true, h->stream);
+    record(h, 6);
+    check_launch("backsub / retract / cost");
+    read_scal(h);
+    En = h->hscal[SC_E];
+    Epn = h->hscal[SC_EPIX];
+    dL = -h->hscal[SC_GH] - 0.5 * h->hscal[SC_JH2];
+  } else {
+    // no step: S is not positive definite; rejected like a step without decrease
+    record(h, 5);
+    record(h, 6);
+    sync(h);
+  }
   const double rho = dL > 0 ? (h->E - En) / dL : -INFINITY;
   r.E_after = En;
   r.Epix_after = Epn;
@@ -1185,6 +1359,7 @@ void ba_default_options(ba_solve_options* o) {
   o->kappa_max = 1e4;
   o->time_kernels = 0;
   o->deterministic = 0;
+  o->linear_solver = BA_SOLVER_PCG;
 }
 
 ba_status ba_create(const ba_problem_desc* desc, ba_handle** out) {
@@ -1711,6 +1886,63 @@ ba_status ba_export_schur_dense(ba_handle* h, double* S) {
     }
     HIPCHK(hipFree(Sd));
   });
+}
+
+ba_status ba_export_schur_assembled(ba_handle* h, double* S) {
+  if (!h || !S) return BA_E_INVALID;
+  return guard(h, [&] {
+    if (!h->finalized) throw BaError(BA_E_STATE, "no linearisation yet");
+    set_device(h);
+    dense_prepare(h);
+    const Dev& d = h->d;
+    if (d.nA == 0) return;
+    launch_dense_assemble(d, h->last_lambda, h->stream);
+    check_launch("dense assembly");
+    HIPCHK(hipMemcpy2DAsync(S, (size_t)d.nA * 8, d.dS, (size_t)d.dense_npad * 8, (size_t)d.nA * 8, d.nA,
+                            hipMemcpyDeviceToHost, h->stream));
+    sync(h);
+  });
+}
+
+ba_status ba_dense_spd_solve(int32_t device, int64_t n, double* A, double* b, void* hip_stream, int32_t* info) {
+  if (info) *info = 0;
+  if (n < 0 || (n > 0 && (!A || !b))) return BA_E_INVALID;
+  if (n == 0) return BA_OK;
+  int hinfo = 0;
+  const ba_status st = guard(nullptr, [&] {
+    if (n > (int64_t)1 << 20) throw BaError(BA_E_INVALID, "matrix too large");
+    int ndev = 0;
+    HIPCHK(hipGetDeviceCount(&ndev));
+    if (device < 0 || device >= ndev) throw BaError(BA_E_INVALID, "bad device index");
+    HIPCHK(hipSetDevice(device));
+    hipStream_t s = (hipStream_t)hip_stream;
+    const int64_t npad = (n + DENSE_NB - 1) / DENSE_NB * DENSE_NB;
+    DevAlloc tmp;
+    struct Release {
+      DevAlloc& a;
+      ~Release() { a.free_all(); }
+    } release{tmp};
+    double* Ap = tmp.get<double>((size_t)npad * npad);
+    double* Linv = tmp.get<double>((size_t)npad * DENSE_NB);
+    double* v = tmp.get<double>(npad);
+    double* w = tmp.get<double>(npad);
+    int* dinfo = tmp.get<int>(1);
+    launch_dense_pad_identity(Ap, (int)n, (int)npad, s);
+    HIPCHK(hipMemcpy2DAsync(Ap, npad * 8, A, n * 8, n * 8, n, hipMemcpyDeviceToDevice, s));
+    launch_dense_zero_upper(Ap, (int)npad, s);
+    launch_zero(v, npad * 8, s);
+    launch_zero(dinfo, sizeof(int), s);
+    HIPCHK(hipMemcpyAsync(v, b, n * 8, hipMemcpyDeviceToDevice, s));
+    launch_dense_factor_solve(Ap, (int)npad, Linv, v, w, dinfo, s);
+    check_launch("dense SPD solve");
+    HIPCHK(hipMemcpy2DAsync(A, n * 8, Ap, npad * 8, n * 8, n, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(b, v, n * 8, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(&hinfo, dinfo, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+  });
+  if (st != BA_OK) return st;
+  if (info) *info = hinfo;
+  return hinfo ? BA_E_NUMERIC : BA_OK;
 }
 
 ba_status ba_export_schur_dense_noalloc(ba_handle* h, double* S) {

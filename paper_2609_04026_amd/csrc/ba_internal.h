@@ -127,6 +127,24 @@ struct Dev {
   double *rel_r = nullptr, *rel_J = nullptr, *rel_y = nullptr;
   int rel_lkind[4] = {0, 0, 0, 0};
   double rel_lscale[4] = {0, 0, 0, 0}, rel_lweight[4] = {0, 0, 0, 0};
+  // dense Schur solver (reduced systems of at most DENSE_MAX_NA rows; the tables exist
+  // when dense_n > 0).  A blocks are numbered cameras, planes, VPs.  fent: one entry per
+  // (feature, distinct block of its records), feature = point index or np + line index;
+  // dY: per entry Y = W_fa G_f (DENSE_Y doubles, element (i, k) at k * 9 + i: i < 9 rows
+  // of the block, k < 4 feature coordinates, zero beyond the block's and the feature's
+  // sizes), with W_fa = sum over the feature's records touching block a of J_a^T J_f and
+  // G_f G_f^T = V_f^-1, so that W_fa V_f^-1 W_fb^T = Y_fa Y_fb^T.  Pairs (a <= b) of
+  // blocks that S couples, every diagonal pair included, sorted by (a, b); per pair the
+  // entries (e_a, e_b) of its shared features (in feature order) and its U entries
+  // (code, index): code 3 / 4 a family-3 / 4 record touching (camera a, plane b), code 8
+  // a relation with block(ga) = a, 9 one with block(gb) = a.  dS: S (dense_npad squared,
+  // row-major; the padding rows are the identity), overwritten by its lower Cholesky
+  // factor; dLinv: the inverse of each 64 x 64 diagonal factor tile; dv, dw: solve vectors
+  int dense_n = 0, dense_npad = 0, n_fent = 0, n_pair = 0;
+  int2 *fent = nullptr, *pair_ab = nullptr, *pair_ent = nullptr, *pair_u = nullptr;
+  int32_t *pair_off = nullptr, *pair_uoff = nullptr;
+  double *dY = nullptr, *dS = nullptr, *dLinv = nullptr, *dv = nullptr, *dw = nullptr;
+  int* dinfo = nullptr;
   // deterministic mode: the product's s_f per feature (T; points x 3, lines x 4) and the
   // per-workgroup partials of the PCG dot products (det_stride workgroups per accumulator:
   // the SC_COUNT scalars, then the COARSE_K entries of Z^T b)
@@ -171,6 +189,20 @@ constexpr double COARSE_MAX_DAMPING = 0.1;
 constexpr int ACC_PQ = 0, ACC_RR = 1, ACC_RZ = 2, ACC_ZR = 4, ACC_W = ACC_ZR + COARSE_K, ACC_STRIDE = ACC_W + COARSE_K;
 static_assert(SC_ACC + 3 * ACC_STRIDE <= SC_COUNT, "PCG scalar area too small");
 
+// runs the statement with T (the working precision) and CD (camera dof) bound
+#define BA_DISPATCH_T_CD(d, ...)                                      \
+  do {                                                                \
+    if ((d).fp64) {                                                   \
+      using T = double;                                               \
+      if ((d).CD == 9) { constexpr int CD = 9; __VA_ARGS__; }         \
+      else { constexpr int CD = 6; __VA_ARGS__; }                     \
+    } else {                                                          \
+      using T = float;                                                \
+      if ((d).CD == 9) { constexpr int CD = 9; __VA_ARGS__; }         \
+      else { constexpr int CD = 6; __VA_ARGS__; }                     \
+    }                                                                 \
+  } while (0)
+
 // ---- launchers (ba_kernels.hip) --------------------------------------------
 void launch_cast_params(const Dev& d, bool candidate, hipStream_t s);
 void launch_linearize(const Dev& d, hipStream_t s);
@@ -187,6 +219,25 @@ void launch_pcg_update(const Dev& d, double lambda, int iter, hipStream_t s);  /
 void launch_schur_matvec(const Dev& d, const double* xin, double* yout, double lambda, hipStream_t s);
 // S (nA x nA, device; column c = S e_c) by nA products
 void launch_dense_schur(const Dev& d, double lambda, double* S, hipStream_t s);
+// dense Schur solver (ba_dense.hip), after the feature inverses and b of the current
+// lambda: launch_dense_assemble forms S in d.dS; launch_dense_solve forms, factors and
+// solves S h_a = b into d.x, leaving *d.dinfo = 1 + the first column with a
+// non-positive pivot (then d.x is unchanged), else 0; launch_dense_residual puts
+// |S x - b|^2 and |b|^2 (S x from the implicit product) into the PCG scalars
+constexpr int DENSE_MAX_NA = 8192, DENSE_Y = 36, DENSE_NB = 64;
+void launch_dense_assemble(const Dev& d, double lambda, hipStream_t s);
+void launch_dense_solve(const Dev& d, double lambda, hipStream_t s);
+void launch_dense_residual(const Dev& d, double lambda, hipStream_t s);
+// Cholesky factorisation of the SPD matrix A (npad x npad, row-major, npad a multiple of
+// DENSE_NB, lower triangle read and overwritten by L) and the solve A x = v (v
+// overwritten by x), with Linv (npad / DENSE_NB tiles of DENSE_NB^2) and w (npad) as
+// work space; *info (device, zero on entry) is set to 1 + the first column with a
+// non-positive pivot
+void launch_dense_factor_solve(double* A, int npad, double* Linv, double* v, double* w, int* info, hipStream_t s);
+// A (npad x npad) = 0 except the identity on rows n .. npad - 1
+void launch_dense_pad_identity(double* A, int n, int npad, hipStream_t s);
+// zero the strict upper triangle of A (npad x npad)
+void launch_dense_zero_upper(double* A, int npad, hipStream_t s);
 // inter-group relations (ba_rel.hip)
 void launch_rel_linearize(const Dev& d, hipStream_t s);
 void launch_rel_a(const Dev& d, hipStream_t s);          // after the group pass A: U_gg, g_g, D_g

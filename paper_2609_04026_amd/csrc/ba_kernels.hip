@@ -44,18 +44,6 @@ int slot_nc(int fam, int cd) {
 int slot_ng(int fam) { return fam == 3 || fam == 4 ? 3 : fam == 5 ? 2 : 0; }
 int slot_nf(int fam) { return fam_is_line(fam) ? 4 : 3; }
 
-#define BA_DISPATCH_T_CD(d, ...)                                      \
-  do {                                                                \
-    if ((d).fp64) {                                                   \
-      using T = double;                                               \
-      if ((d).CD == 9) { constexpr int CD = 9; __VA_ARGS__; }         \
-      else { constexpr int CD = 6; __VA_ARGS__; }                     \
-    } else {                                                          \
-      using T = float;                                                \
-      if ((d).CD == 9) { constexpr int CD = 9; __VA_ARGS__; }         \
-      else { constexpr int CD = 6; __VA_ARGS__; }                     \
-    }                                                                 \
-  } while (0)
 
 static inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 

@@ -123,3 +123,29 @@ def test_cfg3_converged_cost_matches_oracle(precision):
     print("[cfg3]", precision, out, ref["E"], flush=True)
     assert abs(out["E_final"] - ref["E"]) <= 1e-6 * ref["E"], (out["E_final"], ref["E"])
     ba.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_cfg3_dense_solver(scene3, schur3, precision):
+    """The dense solver on the 200-camera scene (2,420 reduced rows): its S
+    against the oracle's entry by entry (scaled by sqrt(S_ii S_jj)), then the
+    converged cost against the oracle's; the solve's time per LM step beside the
+    implicit path's is printed."""
+    s, prob, st, lin = scene3
+    ba = _ba().from_scene(s, precision=precision)
+    ba.linearize(LAM)
+    S = ba.export_schur_assembled()
+    Sref = schur3["S"]
+    d = np.sqrt(np.abs(np.diag(Sref)))
+    err = (np.abs(S - Sref) / np.maximum(np.outer(d, d), 1e-300)).max()
+    print(f"[cfg3] dense {precision}: assembled S within {err:.2e}", flush=True)
+    assert err <= (1e-10 if precision == "fp64" else 1e-4), err
+    ba.close()
+    ref = json.load(open(GOLDEN))["holistic_200cam"]
+    ba = _ba().from_scene(s, precision=precision)
+    out = ba.solve(func_tol=1e-12, max_iters=300, solver="dense")
+    ms = ba.lm_step(solver="dense")["ms"]
+    print("[cfg3] dense", precision, out, ref["E"], "last step ms", ms, flush=True)
+    tol = 1e-9 if precision == "fp64" else 1e-6
+    assert abs(out["E_final"] - ref["E"]) <= tol * ref["E"], (out["E_final"], ref["E"])
+    ba.close()
