@@ -15,8 +15,9 @@
 // Factorisation.  Right-looking blocked Cholesky on 64 x 64 tiles: one wavefront
 // factors the diagonal tile and inverts its factor in LDS, the tiles below it become
 // L_ik = A_ik L_kk^-T, and every trailing lower tile takes A_ij -= L_ik L_jk^T; both
-// tile products are FP64 MFMA from LDS.  The triangular solves take one launch per
-// tile column.  The matrix is padded to a multiple of 64 with identity rows.
+// tile products are FP64 MFMA from LDS.  The forward solve rides along (diagonal tile:
+// y_k = L_kk^-1 v_k; tiles below: v_i -= L_ik y_k); the backward solve takes one launch
+// per tile column.  The matrix is padded to a multiple of 64 with identity rows.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -187,34 +188,69 @@ __global__ __launch_bounds__(256) void k_dense_init(double* S, int n, int npad) 
   }
 }
 
-// one wavefront per block pair (a <= b): S_ab and, for a != b, S_ba = S_ab^T
-template <typename T, int CD> __global__ __launch_bounds__(256) void k_dense_pair(Dev d, double lam) {
-  const int p = blockIdx.x * 4 + (int)(threadIdx.x >> 6);
-  if (p >= d.n_pair) return;
-  const int lane = threadIdx.x & 63, i = lane & 15, k = lane >> 4;
-  const int2 ab = d.pair_ab[p];
+// Consecutive workgroups go to different XCDs: workgroup g works on item group
+// (g % 8) * per + g / 8, so that each XCD takes a contiguous run of block pairs
+// (pairs are sorted by (a, b): a run shares the Y of block a in that XCD's L2).
+// Launched with 8 * per workgroups; a workgroup past the end returns.
+__device__ __forceinline__ int xcd_group(int per) { return (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8); }
+
+// sum over the shared-feature entries [e, e1) of -Y_fa Y_fb^T (the wavefront's MFMA
+// accumulator; lanes with i >= 9 contribute zero rows / columns)
+__device__ __forceinline__ v4d feature_terms(const Dev& d, int32_t e, int32_t e1, int lane) {
+  const int i = lane & 15, k = lane >> 4;
   const bool row = i < 9;
   const int yo = k * 9 + i;
   v4d acc = {0.0, 0.0, 0.0, 0.0};
-  // shared features: -Y_fa Y_fb^T
-  const int32_t e1 = d.pair_off[p + 1];
-  int32_t e = d.pair_off[p];
-  for (; e + 4 <= e1; e += 4) {
-    double a[4], b[4];
+  for (; e + 8 <= e1; e += 8) {
+    int2 q[8];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int2 q = d.pair_ent[e + u];
-      a[u] = row ? d.dY[(int64_t)DENSE_Y * q.x + yo] : 0.0;
-      b[u] = row ? d.dY[(int64_t)DENSE_Y * q.y + yo] : 0.0;
+    for (int u = 0; u < 8; ++u) q[u] = d.pair_ent[e + u];
+    double a[8], b[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      a[u] = row ? d.dY[(int64_t)DENSE_Y * q[u].x + yo] : 0.0;
+      b[u] = row ? d.dY[(int64_t)DENSE_Y * q[u].y + yo] : 0.0;
     }
 #pragma unroll
-    for (int u = 0; u < 4; ++u) acc = mfma16(-a[u], b[u], acc);
+    for (int u = 0; u < 8; ++u) acc = mfma16(-a[u], b[u], acc);
   }
   for (; e < e1; ++e) {
     const int2 q = d.pair_ent[e];
     const double a = row ? d.dY[(int64_t)DENSE_Y * q.x + yo] : 0.0;
     const double b = row ? d.dY[(int64_t)DENSE_Y * q.y + yo] : 0.0;
     acc = mfma16(-a, b, acc);
+  }
+  return acc;
+}
+
+// one wavefront per chunk of a pair with many shared features: its partial sum, rows
+// 0 .. 11 of the accumulator (elements 0 .. 2) stored lane-major
+__global__ __launch_bounds__(256) void k_dense_chunk(Dev d, int per) {
+  const int c = 4 * xcd_group(per) + (int)(threadIdx.x >> 6);
+  if (c >= d.n_chunk) return;
+  const int lane = threadIdx.x & 63;
+  const int2 rg = d.chunk[c];
+  const v4d acc = feature_terms(d, rg.x, rg.y, lane);
+#pragma unroll
+  for (int r = 0; r < 3; ++r) d.dpart[((int64_t)c * 3 + r) * 64 + lane] = acc[r];
+}
+
+// one wavefront per block pair (a <= b): S_ab and, for a != b, S_ba = S_ab^T; the
+// shared features summed here, or (pairs with chunks) their chunks' partials in order
+template <typename T, int CD> __global__ __launch_bounds__(256) void k_dense_pair(Dev d, double lam, int per) {
+  const int p = 4 * xcd_group(per) + (int)(threadIdx.x >> 6);
+  if (p >= d.n_pair) return;
+  const int lane = threadIdx.x & 63, i = lane & 15, k = lane >> 4;
+  const int2 ab = d.pair_ab[p];
+  v4d acc;
+  const int32_t c0 = d.pair_choff[p], c1 = d.pair_choff[p + 1];
+  if (c0 == c1) {
+    acc = feature_terms(d, d.pair_off[p], d.pair_off[p + 1], lane);
+  } else {
+    acc = v4d{0.0, 0.0, 0.0, 0.0};
+    for (int32_t c = c0; c < c1; ++c)
+#pragma unroll
+      for (int r = 0; r < 3; ++r) acc[r] += d.dpart[((int64_t)c * 3 + r) * 64 + lane];
   }
   // U entries coupling two different blocks
   for (int32_t u = d.pair_uoff[p]; u < d.pair_uoff[p + 1]; ++u) {
@@ -267,52 +303,168 @@ template <typename T, int CD> __global__ __launch_bounds__(256) void k_dense_pai
 }
 
 // ---------------------------------------------------------------------------
-// blocked Cholesky
+// blocked Cholesky, with the forward solve L y = v folded into the factorisation
+// (diagonal tile k: y_k = L_kk^-1 v_k; tile below it: v_i -= L_ik y_k)
 
-// diagonal tile k: L_kk (lower, in place; the upper part is zeroed) and L_kk^-1
-// into Linv; *info = 1 + the global column of the first non-positive pivot.  One
-// wavefront; lane t owns row t while factoring and column t while inverting.
-__global__ __launch_bounds__(64) void k_chol_diag(double* A, int ld, int k, double* Linv, int* info) {
+// diagonal tile k: L_kk (lower, in place; the upper part zeroed), L_kk^-1 into Linv,
+// y_k = L_kk^-1 v_k into w; *info = 1 + the global column of the first non-positive
+// pivot.  Block LDL^T elimination in steps of 4 columns, with the identity carried
+// along so that the same steps yield the inverse: at step J the 4 x 4 block D_J (the
+// Schur complement of the earlier columns) is factored D_J = L_D L_D^T in every lane
+// (W = L_D^-1), row t's multipliers are u_t = D_J^-1 r_t (r_t: its entries in the
+// block's columns), and every later row takes row_t -= u_t . [block rows] on its
+// columns and on its carried identity part.  Then L[t][block] = W r_t, and L^-1 is
+// W_J applied to the carried rows of block J.  Four wavefronts; lane t of wavefront h
+// holds columns 16 h .. 16 h + 15 of row t in registers (the steps within one
+// wavefront's columns are unrolled, so register indices are static); one barrier per
+// step (LDS broadcasts double-buffered).
+__global__ __launch_bounds__(256) void k_chol_diag(double* A, int ld, int k, double* Linv, const double* v, double* w,
+                                                   int* info) {
   if (*info) return;
-  __shared__ double L[NB][NB + 1];
-  __shared__ double X[NB][NB + 1];
-  const int t = threadIdx.x;
+  __shared__ double Ls[NB][NB + 1];
+  __shared__ double bufA[2][NB][4];
+  __shared__ double bufX[2][4][NB];
+  __shared__ double Wd[NB / 4][4][4];
+  __shared__ double vk[NB];
+  __shared__ double red[4][NB];
+  const int t = threadIdx.x & 63, h = threadIdx.x >> 6;
   double* Akk = A + (int64_t)NB * k * ld + (int64_t)NB * k;
-  for (int r = 0; r < NB; ++r) L[r][t] = Akk[(int64_t)r * ld + t];
+  if (h == 0) vk[t] = v[NB * k + t];
+#pragma unroll
+  for (int q = 0; q < NB / 4; ++q) Ls[4 * q + h][t] = Akk[(int64_t)(4 * q + h) * ld + t];
   __syncthreads();
-  for (int j = 0; j < NB; ++j) {
-    double s = 0.0;
-    if (t >= j) {
-      s = L[t][j];
-      for (int m = 0; m < j; ++m) s -= L[t][m] * L[j][m];
+  double a[16], x[16];
+#pragma unroll
+  for (int c = 0; c < 16; ++c) {
+    a[c] = Ls[t][16 * h + c];
+    x[c] = 16 * h + c == t ? 1.0 : 0.0;
+  }
+  // outer loop not unrolled: the fully unrolled kernel (90 KB) overflows the 64 KB
+  // instruction cache, and a launch runs it once
+#pragma unroll 1
+  for (int hj = 0; hj < 4; ++hj)
+#pragma unroll
+  for (int jj = 0; jj < 4; ++jj) {
+    const int J = 4 * hj + jj, o = 4 * jj, j0 = 4 * J;
+    double (*bA)[4] = bufA[J & 1];
+    double (*bX)[NB] = bufX[J & 1];
+    if (h == hj)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) bA[t][q] = a[o + q];
+    if ((t >> 2) == J)
+#pragma unroll
+      for (int c = 0; c < 16; ++c) bX[t & 3][16 * h + c] = x[c];
+    __syncthreads();
+    // D_J = L_D L_D^T and W = L_D^-1, the same in every lane
+    double Ld[4][4], W[4][4];
+    int fail = -1;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        Ld[i][q] = i >= q ? bA[j0 + i][q] : 0.0;
+        W[i][q] = 0.0;
+      }
+    // one reciprocal square root per pivot and no divisions: the 4 x 4 factorisation
+    // is the serial part of every step
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      double sj = Ld[j][j];
+#pragma unroll
+      for (int m = 0; m < j; ++m) sj -= Ld[j][m] * Ld[j][m];
+      if ((!(sj > 0.0) || !isfinite(sj)) && fail < 0) fail = j;
+      const double rj = rsqrt(fmax(sj, 1e-300));
+      Ld[j][j] = sj * rj;
+      W[j][j] = rj;
+#pragma unroll
+      for (int i = j + 1; i < 4; ++i) {
+        double si = Ld[i][j];
+#pragma unroll
+        for (int m = 0; m < j; ++m) si -= Ld[i][m] * Ld[j][m];
+        Ld[i][j] = si * rj;
+      }
     }
-    const double piv = __shfl(s, j, 64);
-    if (!(piv > 0.0) || !isfinite(piv)) {
-      if (t == 0) *info = NB * k + j + 1;
+    if (fail >= 0) {
+      if (threadIdx.x == 0) *info = NB * k + j0 + fail + 1;
       return;
     }
-    const double ljj = sqrt(piv);
-    if (t >= j) L[t][j] = t == j ? ljj : s / ljj;
-    __syncthreads();
-  }
-  for (int r = 0; r < NB; ++r) {
-    if (r >= t) {
-      double s = r == t ? 1.0 : 0.0;
-      for (int m = t; m < r; ++m) s -= L[r][m] * X[m][t];
-      X[r][t] = s / L[r][r];
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int i = j + 1; i < 4; ++i) {
+        double si = 0.0;
+#pragma unroll
+        for (int m = j; m < i; ++m) si -= Ld[i][m] * W[m][j];
+        W[i][j] = si * W[i][i];
+      }
+    if (threadIdx.x == 0)
+#pragma unroll
+      for (int q = 0; q < 16; ++q) Wd[J][q >> 2][q & 3] = W[q >> 2][q & 3];
+    double r[4], l[4], u[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) r[q] = bA[t][q];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      l[q] = 0.0;
+#pragma unroll
+      for (int p = 0; p <= q; ++p) l[q] += W[q][p] * r[p];
     }
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      u[p] = 0.0;
+#pragma unroll
+      for (int q = p; q < 4; ++q) u[p] += l[q] * W[q][p];
+    }
+#pragma unroll
+    for (int c = 0; c < 16; ++c)
+      if (16 * h + c >= j0 + 4) {
+        const double* rc = bA[16 * h + c];
+        a[c] -= u[0] * rc[0] + u[1] * rc[1] + u[2] * rc[2] + u[3] * rc[3];
+      }
+    if (t >= j0 + 4) {
+#pragma unroll
+      for (int c = 0; c < 16; ++c)
+        x[c] -= u[0] * bX[0][16 * h + c] + u[1] * bX[1][16 * h + c] + u[2] * bX[2][16 * h + c] +
+                u[3] * bX[3][16 * h + c];
+    }
+    if (h == hj) {
+      if (t >= j0 + 4) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) a[o + q] = l[q];
+      } else if ((t >> 2) == J) {
+        const int i = t & 3;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) a[o + q] = i == 0 ? Ld[0][q] : i == 1 ? Ld[1][q] : i == 2 ? Ld[2][q] : Ld[3][q];
+      }
+    }
+  }
+  // L (zero upper part) back to the tile; the carried rows to LDS for L^-1
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < 16; ++c) {
+    Akk[(int64_t)t * ld + 16 * h + c] = 16 * h + c <= t ? a[c] : 0.0;
+    Ls[t][16 * h + c] = x[c];
   }
   __syncthreads();
   double* Li = Linv + (int64_t)k * NB * NB;
-  for (int r = 0; r < NB; ++r) {
-    Akk[(int64_t)r * ld + t] = t <= r ? L[r][t] : 0.0;
-    Li[r * NB + t] = t <= r ? X[r][t] : 0.0;
+  const int J = t >> 2, i = t & 3;
+  double y = 0.0;
+#pragma unroll
+  for (int c = 0; c < 16; ++c) {
+    double xs = 0.0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) xs += Wd[J][i][q] * Ls[4 * J + q][16 * h + c];
+    Li[t * NB + 16 * h + c] = xs;
+    y += xs * vk[16 * h + c];
   }
+  red[h][t] = y;
+  __syncthreads();
+  if (h == 0) w[NB * k + t] = (red[0][t] + red[1][t]) + (red[2][t] + red[3][t]);
 }
 
 __device__ __forceinline__ void load_tile(double (*S)[LDT], const double* src, int64_t ld) {
   const int t = threadIdx.x;
-#pragma unroll 4
+#pragma unroll
   for (int q = 0; q < NB / 4; ++q) {
     const int r = 4 * q + (t >> 6), c = t & 63;
     S[r][c] = src[r * ld + c];
@@ -332,22 +484,39 @@ __device__ __forceinline__ void gemm_nt(const double (*As)[LDT], const double (*
   }
 }
 
-// the tiles below diagonal tile k: L_ik = A_ik L_kk^-T
-__global__ __launch_bounds__(256) void k_chol_panel(double* A, int ld, int k, const double* Linv, const int* info) {
+// the tiles below diagonal tile k: L_ik = A_ik L_kk^-T, then v_i -= L_ik y_k
+__global__ __launch_bounds__(256) void k_chol_panel(double* A, int ld, int k, const double* Linv, double* v,
+                                                    const double* w, const int* info) {
   if (*info) return;
   __shared__ double As[NB][LDT], Bs[NB][LDT];
+  __shared__ double yk[NB];
+  const int t = threadIdx.x;
   const int I = k + 1 + blockIdx.x;
   double* Aik = A + (int64_t)NB * I * ld + (int64_t)NB * k;
+  if (t < NB) yk[t] = w[NB * k + t];
   load_tile(As, Aik, ld);
   load_tile(Bs, Linv + (int64_t)k * NB * NB, NB);
   __syncthreads();
   v4d acc[4];
   gemm_nt(As, Bs, acc);
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int lane = t & 63, wv = t >> 6;
+  __syncthreads();
 #pragma unroll
   for (int jt = 0; jt < 4; ++jt)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) Aik[(int64_t)(16 * w + (lane >> 4) + 4 * r) * ld + 16 * jt + (lane & 15)] = acc[jt][r];
+    for (int r = 0; r < 4; ++r) {
+      const int row = 16 * wv + (lane >> 4) + 4 * r, c = 16 * jt + (lane & 15);
+      Aik[(int64_t)row * ld + c] = acc[jt][r];
+      As[row][c] = acc[jt][r];
+    }
+  __syncthreads();
+  const int row = t >> 2, part = t & 3;
+  double s = 0.0;
+#pragma unroll
+  for (int m = 0; m < 16; ++m) s += As[row][16 * part + m] * yk[16 * part + m];
+  s += __shfl_xor(s, 1, 64);
+  s += __shfl_xor(s, 2, 64);
+  if (part == 0) v[NB * I + row] -= s;
 }
 
 // trailing lower tiles (I, J), k < J <= I: A_IJ -= L_Ik L_Jk^T; blockIdx = I' (I' + 1) / 2 + J'
@@ -373,53 +542,37 @@ __global__ __launch_bounds__(256) void k_chol_update(double* A, int ld, int k, c
     for (int r = 0; r < 4; ++r) C[(int64_t)(16 * w + (lane >> 4) + 4 * r) * ld + 16 * jt + (lane & 15)] -= acc[jt][r];
 }
 
-// forward solve, tile column k: y_k = L_kk^-1 v_k into w (workgroup 0); the others
-// (I = k + workgroup) take v_I -= L_Ik y_k
-__global__ __launch_bounds__(64) void k_trsv_fwd(const double* A, int ld, int k, const double* Linv, double* v, double* w,
-                                                  const int* info) {
-  if (*info) return;
-  __shared__ double bk[NB], yk[NB];
-  __shared__ double Ls[NB][NB + 1];
-  const int t = threadIdx.x, I = k + blockIdx.x;
-  bk[t] = v[NB * k + t];
-  __syncthreads();
-  const double* Li = Linv + (int64_t)k * NB * NB;
-  double y = 0.0;
-  for (int m = 0; m <= t; ++m) y += Li[t * NB + m] * bk[m];
-  if (blockIdx.x == 0) {
-    w[NB * k + t] = y;
-    return;
-  }
-  yk[t] = y;
-  const double* Lik = A + (int64_t)NB * I * ld + (int64_t)NB * k;
-  for (int r = 0; r < NB; ++r) Ls[r][t] = Lik[(int64_t)r * ld + t];
-  __syncthreads();
-  double s = 0.0;
-  for (int c = 0; c < NB; ++c) s += Ls[t][c] * yk[c];
-  v[NB * I + t] -= s;
-}
-
 // backward solve, tile column k (descending): x_k = L_kk^-T w_k into v (workgroup 0);
-// the others (J = k - workgroup) take w_J -= L_kJ^T x_k
-__global__ __launch_bounds__(64) void k_trsv_bwd(const double* A, int ld, int k, const double* Linv, double* v, double* w,
+// the others (J = k - workgroup) take w_J -= L_kJ^T x_k.  Thread (c, part) sums rows
+// 16 part .. 16 part + 15 of column c.
+__global__ __launch_bounds__(256) void k_trsv_bwd(const double* A, int ld, int k, const double* Linv, double* v, double* w,
                                                   const int* info) {
   if (*info) return;
   __shared__ double yk[NB], xk[NB];
-  const int t = threadIdx.x, J = k - blockIdx.x;
-  yk[t] = w[NB * k + t];
+  __shared__ double red[4][NB];
+  const int t = threadIdx.x, c = t & 63, part = t >> 6, J = k - blockIdx.x;
+  if (t < NB) yk[t] = w[NB * k + t];
   __syncthreads();
   const double* Li = Linv + (int64_t)k * NB * NB;
   double x = 0.0;
-  for (int r = t; r < NB; ++r) x += Li[r * NB + t] * yk[r];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) x += Li[(16 * part + q) * NB + c] * yk[16 * part + q];
+  red[part][c] = x;
+  __syncthreads();
+  x = red[0][c] + red[1][c] + red[2][c] + red[3][c];
   if (blockIdx.x == 0) {
-    v[NB * k + t] = x;
+    if (t < NB) v[NB * k + t] = x;
     return;
   }
-  xk[t] = x;
+  if (t < NB) xk[t] = x;
   __syncthreads();
+  const double* Lk = A + (int64_t)NB * k * ld + (int64_t)NB * J;
   double s = 0.0;
-  for (int r = 0; r < NB; ++r) s += A[(int64_t)(NB * k + r) * ld + (int64_t)NB * J + t] * xk[r];
-  w[NB * J + t] -= s;
+#pragma unroll
+  for (int q = 0; q < 16; ++q) s += Lk[(int64_t)(16 * part + q) * ld + c] * xk[16 * part + q];
+  red[part][c] = s;
+  __syncthreads();
+  if (t < NB) w[NB * J + t] -= red[0][t] + red[1][t] + red[2][t] + red[3][t];
 }
 
 __global__ void k_zero_upper(double* A, int npad) {
@@ -477,22 +630,28 @@ void launch_dense_assemble(const Dev& d, double lambda, hipStream_t s) {
   k_dense_init<<<(unsigned)std::min<int64_t>(nblk_dense(tot, 256), 8192), 256, 0, s>>>(d.dS, d.dense_n, d.dense_npad);
   BA_DISPATCH_T_CD(d, {
     if (d.n_fent) k_dense_y<T, CD><<<nblk_dense(d.n_fent, 256), 256, 0, s>>>(d);
-    if (d.n_pair) k_dense_pair<T, CD><<<nblk_dense(d.n_pair, 4), 256, 0, s>>>(d, lambda);
+    if (d.n_chunk) {
+    const int per = (int)nblk_dense(nblk_dense(d.n_chunk, 4), 8);
+    k_dense_chunk<<<8 * per, 256, 0, s>>>(d, per);
+  }
+  if (d.n_pair) {
+    const int per = (int)nblk_dense(nblk_dense(d.n_pair, 4), 8);
+    k_dense_pair<T, CD><<<8 * per, 256, 0, s>>>(d, lambda, per);
+  }
   });
 }
 
 void launch_dense_factor_solve(double* A, int npad, double* Linv, double* v, double* w, int* info, hipStream_t s) {
   const int nt = npad / NB;
   for (int k = 0; k < nt; ++k) {
-    k_chol_diag<<<1, 64, 0, s>>>(A, npad, k, Linv, info);
+    k_chol_diag<<<1, 256, 0, s>>>(A, npad, k, Linv, v, w, info);
     const int m = nt - k - 1;
     if (m > 0) {
-      k_chol_panel<<<m, 256, 0, s>>>(A, npad, k, Linv, info);
+      k_chol_panel<<<m, 256, 0, s>>>(A, npad, k, Linv, v, w, info);
       k_chol_update<<<m * (m + 1) / 2, 256, 0, s>>>(A, npad, k, info);
     }
   }
-  for (int k = 0; k < nt; ++k) k_trsv_fwd<<<nt - k, 64, 0, s>>>(A, npad, k, Linv, v, w, info);
-  for (int k = nt - 1; k >= 0; --k) k_trsv_bwd<<<k + 1, 64, 0, s>>>(A, npad, k, Linv, v, w, info);
+  for (int k = nt - 1; k >= 0; --k) k_trsv_bwd<<<k + 1, 256, 0, s>>>(A, npad, k, Linv, v, w, info);
 }
 
 void launch_dense_solve(const Dev& d, double lambda, hipStream_t s) {

@@ -200,8 +200,8 @@ struct ba_handle {
   struct DenseHost {
     bool built = false, uploaded = false;
     std::string why = "the dense solver's tables have not been built";
-    std::vector<int2> fent, pair_ab, pair_ent, pair_u;
-    std::vector<int32_t> pair_off, pair_uoff;
+    std::vector<int2> fent, pair_ab, pair_ent, pair_u, chunk;
+    std::vector<int32_t> pair_off, pair_uoff, pair_choff;
   } dense;
 };
 
@@ -355,6 +355,15 @@ void build_dense_tables(ba_handle* h, const std::vector<Rec> (&R)[NFAM], const s
     const int a = rel_block(i, false), b = rel_block(i, true);
     D.pair_u[fill[at(a, b)]++] = make_int2(a < b ? 8 : 9, (int)i);
   }
+  // pairs with many shared features are summed in chunks
+  D.chunk.clear();
+  D.pair_choff.assign(np_ + 1, 0);
+  for (size_t p = 0; p < np_; ++p) {
+    const int32_t b = D.pair_off[p], e = D.pair_off[p + 1];
+    if (e - b > DENSE_CHUNK)
+      for (int32_t c = b; c < e; c += DENSE_CHUNK) D.chunk.push_back(make_int2(c, std::min(e, c + DENSE_CHUNK)));
+    D.pair_choff[p + 1] = (int32_t)D.chunk.size();
+  }
   D.fent.resize(fb.size());
   for (int f = 0; f < nfeat; ++f)
     for (int64_t i = off2[f]; i < off2[f + 1]; ++i) D.fent[i] = make_int2(f, fb[i]);
@@ -373,7 +382,13 @@ void dense_prepare(ba_handle* h) {
   d.dense_npad = (d.nA + DENSE_NB - 1) / DENSE_NB * DENSE_NB;
   d.n_fent = (int)D.fent.size();
   d.n_pair = (int)D.pair_ab.size();
+  d.n_chunk = (int)D.chunk.size();
   if (d.nA > 0) {
+    d.chunk = A.get<int2>(D.chunk.size());
+    d.pair_choff = A.get<int32_t>(D.pair_choff.size());
+    d.dpart = A.get<double>((size_t)3 * 64 * D.chunk.size());
+    upload(h, d.chunk, D.chunk);
+    upload(h, d.pair_choff, D.pair_choff);
     d.fent = A.get<int2>(D.fent.size());
     d.pair_ab = A.get<int2>(D.pair_ab.size());
     d.pair_ent = A.get<int2>(D.pair_ent.size());

@@ -140,10 +140,13 @@ struct Dev {
   // a relation with block(ga) = a, 9 one with block(gb) = a.  dS: S (dense_npad squared,
   // row-major; the padding rows are the identity), overwritten by its lower Cholesky
   // factor; dLinv: the inverse of each 64 x 64 diagonal factor tile; dv, dw: solve vectors
-  int dense_n = 0, dense_npad = 0, n_fent = 0, n_pair = 0;
-  int2 *fent = nullptr, *pair_ab = nullptr, *pair_ent = nullptr, *pair_u = nullptr;
-  int32_t *pair_off = nullptr, *pair_uoff = nullptr;
-  double *dY = nullptr, *dS = nullptr, *dLinv = nullptr, *dv = nullptr, *dw = nullptr;
+  // Pairs with more than DENSE_CHUNK shared features are split into chunks of at most
+  // DENSE_CHUNK entries (chunk: entry range), summed per chunk into dpart (3 x 64 doubles)
+  // and then per pair in chunk order; pair_choff: per pair, its range of chunks.
+  int dense_n = 0, dense_npad = 0, n_fent = 0, n_pair = 0, n_chunk = 0;
+  int2 *fent = nullptr, *pair_ab = nullptr, *pair_ent = nullptr, *pair_u = nullptr, *chunk = nullptr;
+  int32_t *pair_off = nullptr, *pair_uoff = nullptr, *pair_choff = nullptr;
+  double *dY = nullptr, *dS = nullptr, *dLinv = nullptr, *dv = nullptr, *dw = nullptr, *dpart = nullptr;
   int* dinfo = nullptr;
   // deterministic mode: the product's s_f per feature (T; points x 3, lines x 4) and the
   // per-workgroup partials of the PCG dot products (det_stride workgroups per accumulator:
@@ -224,7 +227,7 @@ void launch_dense_schur(const Dev& d, double lambda, double* S, hipStream_t s);
 // solves S h_a = b into d.x, leaving *d.dinfo = 1 + the first column with a
 // non-positive pivot (then d.x is unchanged), else 0; launch_dense_residual puts
 // |S x - b|^2 and |b|^2 (S x from the implicit product) into the PCG scalars
-constexpr int DENSE_MAX_NA = 8192, DENSE_Y = 36, DENSE_NB = 64;
+constexpr int DENSE_MAX_NA = 8192, DENSE_Y = 36, DENSE_NB = 64, DENSE_CHUNK = 64;
 void launch_dense_assemble(const Dev& d, double lambda, hipStream_t s);
 void launch_dense_solve(const Dev& d, double lambda, hipStream_t s);
 void launch_dense_residual(const Dev& d, double lambda, hipStream_t s);
