@@ -168,6 +168,10 @@ typedef struct {
                              implicit product, and the step's ms[BA_PHASE_PCG] is the
                              assembly, factorisation and solve; deterministic by
                              construction */
+  int32_t fix_a_side;     /* 1: cameras, planes and VPs are held fixed and only the features
+                             move (h_a = 0, h_f = -(V_f + lambda D_f)^-1 g_f; the
+                             fixed-pose stage of the reliability-aware refinement); the
+                             linear solver is then unused; 0 */
 } ba_solve_options;
 
 enum {
@@ -216,6 +220,37 @@ typedef struct {
   double total_ms;
   int32_t pcg_iters_total;
 } ba_summary;
+
+/* Reliability-aware two-stage refinement (App. A.2).  The paper classifies feature
+ * tracks as reliable or not from their active observations and their estimated
+ * uncertainty, refines cameras, reliable features, groups and wireframe records
+ * first, then the unreliable features with the poses fixed, and leaves groups with
+ * too little support out of the first stage.  It gives no formulas or thresholds;
+ * this library's readings:
+ *   active observation: an observation record (point: Eq. 1, line: Eq. 4) whose
+ *     residual lies in the quadratic part of its loss, |r|^2 <= scale^2 (every record
+ *     under the trivial loss);
+ *   sigma = lambda_min(V_f)^-1/2, V_f the undamped feature block (sum of J~^T J~ over
+ *     the feature's records, Eq. 3) at the current parameters; for a point divided by
+ *     its mean distance to the cameras observing it; for a line in the tangent
+ *     coordinates of its orthonormal representation;
+ *   reliable: n_active >= min_active_obs and sigma <= max_sigma_point (points) or
+ *     max_sigma_line (lines);
+ *   group support: distinct reliable features associated with the group (planes:
+ *     points and lines; VPs: lines); below min_group_support the group and its
+ *     relations are left out of stage 1. */
+typedef struct {
+  int32_t min_active_obs;     /* 3 */
+  double max_sigma_point;     /* 0.01 (relative to the viewing distance) */
+  double max_sigma_line;      /* 0.1 (tangent coordinates) */
+  int32_t min_group_support;  /* 3 */
+} ba_reliability_options;
+
+typedef struct {
+  int32_t n_points_unreliable, n_lines_unreliable;  /* refined in stage 2 */
+  int32_t n_planes_out, n_vps_out;                  /* left out of stage 1 */
+  ba_summary stage1, stage2;
+} ba_two_stage_summary;
 
 /* Fill *opt with the defaults listed in ba_solve_options. */
 void ba_default_options(ba_solve_options *opt);
@@ -383,6 +418,35 @@ ba_status ba_export_gnn_graph(ba_handle *h, int32_t *n_nodes, int32_t *n_edges, 
  * implicit-Schur product (n_A products: meant for small systems, e.g.
  * training data and tests).  Temporary device memory: 8 n_A^2 bytes. */
 ba_status ba_export_schur_dense(ba_handle *h, double *S);
+
+void ba_default_reliability_options(ba_reliability_options *o);
+
+/* Leave records out of the problem: every record whose parameters include a flagged
+ * point, line, plane or VP (arrays of n_points, n_lines, n_planes, n_vps bytes in the
+ * caller's order, nonzero = left out; NULL = none; all NULL clears the mask) has zero
+ * weight in the linearisation and no cost, so the flagged parameters do not move.  A
+ * junction record (Eqs. 11, 12) belongs to the feature it adjusts; its partner only
+ * supplies the measurement.  Relations are left out with either of their groups.
+ * Takes effect at the next linearisation; the cost is re-evaluated. */
+ba_status ba_set_record_mask(ba_handle *h, const uint8_t *points_out, const uint8_t *lines_out,
+                             const uint8_t *planes_out, const uint8_t *vps_out);
+
+/* Per-feature statistics of the reliability test at the current parameters (see
+ * ba_reliability_options), in the caller's order: active observations, observations
+ * and sigma (infinite when V_f is singular or the feature has no observation) per point
+ * and per line; NULL outputs are skipped.  Linearises first (with the current record
+ * mask).  Sigma is computed from V_f in the working precision. */
+ba_status ba_feature_reliability(ba_handle *h, int32_t *pt_active, int32_t *pt_obs, double *pt_sigma,
+                                 int32_t *ln_active, int32_t *ln_obs, double *ln_sigma);
+
+/* The two-stage refinement from the current parameters: classify (without a mask),
+ * then ba_solve with the unreliable features and the unsupported groups left out,
+ * then ba_solve with fix_a_side over the unreliable features alone (the reliable
+ * features left out), each stage starting from lambda0; the mask is cleared at the
+ * end.  opt's fix_a_side is ignored.  Returns BA_OK unless an error occurred (a stage
+ * that ends on max_iters is reported in its summary). */
+ba_status ba_solve_two_stage(ba_handle *h, const ba_solve_options *opt, const ba_reliability_options *ro,
+                             ba_two_stage_summary *out);
 
 /* The damped reduced matrix S of the last ba_linearize (Sec. 3.1 Eq. 3), dense
  * (n_A x n_A doubles, row-major, caller-allocated), as the dense solver forms it:

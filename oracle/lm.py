@@ -275,6 +275,14 @@ def solve_schur(prob, lin, lam):
     return np.concatenate([ha, hf]), sys_
 
 
+def solve_features(prob, lin, lam):
+    """Step with the A side held fixed (h_a = 0): each feature alone,
+    h_f = -(V_f + lam diag(D_f))^-1 g_f (the fixed-pose refinement of App. A.2)."""
+    Vinv, _ = damped_feature_inverse(prob, lin, lam)
+    hf = Vinv @ (-lin.g[prob.nA:])
+    return np.concatenate([np.zeros(prob.nA), hf])
+
+
 def solve_full(prob, lin, lam):
     """Step from the full damped normal equations (H + lam diag D) h = -g, dense."""
     H = (lin.J.T @ lin.J).toarray() + lam * np.diag(lin.D)
@@ -300,7 +308,9 @@ def diag_blocks(prob, M):
 # Levenberg-Marquardt
 # ---------------------------------------------------------------------------
 def lm_solve(prob, state=None, max_iters=100, func_tol=1e-6, grad_tol=1e-10, lambda0=1e-4, nu0=2.0,
-             lambda_min=1e-10, lambda_max=1e16, verbose=False):
+             lambda_min=1e-10, lambda_max=1e16, verbose=False, fixed_a=False):
+    """LM as above; with fixed_a the cameras and groups are held fixed and only the
+    features move (solve_features instead of the Schur step)."""
     state = prob.state0() if state is None else state
     E, Epix = cost(prob, state)
     lam, nu = lambda0, nu0
@@ -312,7 +322,7 @@ def lm_solve(prob, state=None, max_iters=100, func_tol=1e-6, grad_tol=1e-10, lam
         if np.max(np.abs(lin.g)) < grad_tol:
             reason = "grad_tol"
             break
-        h, _ = solve_schur(prob, lin, lam)
+        h = solve_features(prob, lin, lam) if fixed_a else solve_schur(prob, lin, lam)[0]
         accepted = False
         rel = None
         if h is not None:

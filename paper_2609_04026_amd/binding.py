@@ -46,7 +46,8 @@ class ProblemDesc(ctypes.Structure):
 class SolveOptions(ctypes.Structure):
     _fields_ = [("max_iters", c_int32), ("func_tol", c_double), ("grad_tol", c_double), ("pcg_tol", c_double),
                 ("pcg_max_iters", c_int32), ("lambda0", c_double), ("nu0", c_double), ("kappa_max", c_double),
-                ("time_kernels", c_int32), ("deterministic", c_int32), ("linear_solver", c_int32)]
+                ("time_kernels", c_int32), ("deterministic", c_int32), ("linear_solver", c_int32),
+                ("fix_a_side", c_int32)]
 
 
 class StepReport(ctypes.Structure):
@@ -73,6 +74,16 @@ class Summary(ctypes.Structure):
     _fields_ = [("iters", c_int32), ("accepted", c_int32), ("E_initial", c_double), ("E_final", c_double),
                 ("Epix_final", c_double), ("termination", c_int32), ("total_ms", c_double),
                 ("pcg_iters_total", c_int32)]
+
+
+class ReliabilityOptions(ctypes.Structure):
+    _fields_ = [("min_active_obs", c_int32), ("max_sigma_point", c_double), ("max_sigma_line", c_double),
+                ("min_group_support", c_int32)]
+
+
+class TwoStageSummary(ctypes.Structure):
+    _fields_ = [("n_points_unreliable", c_int32), ("n_lines_unreliable", c_int32), ("n_planes_out", c_int32),
+                ("n_vps_out", c_int32), ("stage1", Summary), ("stage2", Summary)]
 
 
 def _load():
@@ -110,6 +121,11 @@ def _load():
         "ba_export_schur_dense": (c_int32, [H, D]),
         "ba_export_schur_dense_noalloc": (c_int32, [H, D]),
         "ba_export_schur_assembled": (c_int32, [H, D]),
+        "ba_default_reliability_options": (None, [POINTER(ReliabilityOptions)]),
+        "ba_set_record_mask": (c_int32, [H, c_void_p, c_void_p, c_void_p, c_void_p]),
+        "ba_feature_reliability": (c_int32, [H, I32, I32, D, I32, I32, D]),
+        "ba_solve_two_stage": (c_int32, [H, POINTER(SolveOptions), POINTER(ReliabilityOptions),
+                                         POINTER(TwoStageSummary)]),
         "ba_dense_spd_solve": (c_int32, [c_int32, c_int64, c_void_p, c_void_p, c_void_p, I32]),
         "ba_export_gauge_basis": (c_int32, [H, D]),
         "ba_export_coarse_space": (c_int32, [H, I32, D, D]),
@@ -237,6 +253,43 @@ class BA:
             self._check(st)
         out = {k: getattr(s, k) for k, _ in Summary._fields_}
         out["converged"] = st == BA_OK
+        return out
+
+    # -- reliability-aware refinement
+    def set_record_mask(self, points=None, lines=None, planes=None, vps=None):
+        """Leave out the records of the flagged points / lines / planes / VPs (boolean
+        arrays in scene order, None: none)."""
+        keep = [None if m is None else np.ascontiguousarray(m, dtype=np.uint8) for m in (points, lines, planes, vps)]
+        self._check(_lib.ba_set_record_mask(self._h, *(None if m is None else m.ctypes.data_as(c_void_p)
+                                                        for m in keep)))
+
+    def feature_reliability(self):
+        """Per point and per line: active observations, observations, sigma."""
+        n = self.n
+        out = {}
+        for k in ("pt", "ln"):
+            out[k] = dict(n_active=np.zeros(n[k], np.int32), n_obs=np.zeros(n[k], np.int32), sigma=np.zeros(n[k]))
+        self._check(_lib.ba_feature_reliability(self._h, _ip(out["pt"]["n_active"]), _ip(out["pt"]["n_obs"]),
+                                                _dp(out["pt"]["sigma"]), _ip(out["ln"]["n_active"]),
+                                                _ip(out["ln"]["n_obs"]), _dp(out["ln"]["sigma"])))
+        return out
+
+    def solve_two_stage(self, reliability=None, **opts):
+        """Two-stage refinement (see ba_solve_two_stage); reliability: dict of
+        ba_reliability_options fields."""
+        o = default_options(**opts)
+        r = ReliabilityOptions()
+        _lib.ba_default_reliability_options(ctypes.byref(r))
+        for k, v in (reliability or {}).items():
+            if not hasattr(r, k):
+                raise KeyError(k)
+            setattr(r, k, v)
+        t = TwoStageSummary()
+        self._check(_lib.ba_solve_two_stage(self._h, ctypes.byref(o), ctypes.byref(r), ctypes.byref(t)))
+        out = {k: getattr(t, k) for k, _ in TwoStageSummary._fields_ if not k.startswith("stage")}
+        for st in ("stage1", "stage2"):
+            sm = getattr(t, st)
+            out[st] = {k: getattr(sm, k) for k, _ in Summary._fields_}
         return out
 
     def get_parameters(self):

@@ -731,6 +731,12 @@ void finalize(ba_handle* h) {
     upload(h, d.rel_goff, goff); upload(h, d.rel_gent, gent);
     if (n) max_blocks += 1;  // one cost partial
   }
+  // record mask (all clear)
+  d.has_mask = 0;
+  d.mpt = A.get<uint8_t>(h->np); d.mln = A.get<uint8_t>(h->nl);
+  d.mpl = A.get<uint8_t>(h->ng); d.mvp = A.get<uint8_t>(h->nv);
+  launch_zero(d.mpt, std::max(h->np, 1), h->stream); launch_zero(d.mln, std::max(h->nl, 1), h->stream);
+  launch_zero(d.mpl, std::max(h->ng, 1), h->stream); launch_zero(d.mvp, std::max(h->nv, 1), h->stream);
   // block graph of the reduced system (blocks are adjacent when they share a feature)
   // and the dense solver's tables
   {
@@ -1257,10 +1263,18 @@ bool do_step(ba_handle* h, const ba_solve_options& o, ba_step_report* rep, doubl
   record(h, 1);
   assemble_schur(h, h->lambda, o.kappa_max);
   record(h, 2);
-  const bool dense = o.linear_solver == BA_SOLVER_DENSE;
+  const bool fixa = o.fix_a_side != 0;
+  const bool dense = !fixa && o.linear_solver == BA_SOLVER_DENSE;
   bool solved = true;
   double mv_ms = 0;
-  if (dense) {
+  if (fixa) {
+    // cameras and groups held fixed: h_a = 0, the features alone (back-substitution)
+    record(h, 3);
+    if (h->d.nA) launch_zero(h->d.x, (size_t)h->d.nA * sizeof(double), h->stream);
+    read_scal(h);
+    r.pcg_iters = 0;
+    r.coarse = 0;
+  } else if (dense) {
     // direct solve: S formed and factored (the preconditioner phase is empty)
     record(h, 3);
     solved = dense_solve(h, h->lambda);
@@ -1278,7 +1292,7 @@ bool do_step(ba_handle* h, const ba_solve_options& o, ba_step_report* rep, doubl
     r.pcg_iters = pcg(h, h->lambda, o.pcg_tol, o.pcg_max_iters, o.time_kernels ? &mv_ms : nullptr);
     r.coarse = h->d.coarse_k > 0 && h->hscal[SC_COARSE] != 0.0 ? h->d.coarse_k : 0;
   }
-  if (!dense && h->hscal[SC_BREAK] != 0.0) r.pcg_flags |= BA_PCG_BREAKDOWN;
+  if (!dense && !fixa && h->hscal[SC_BREAK] != 0.0) r.pcg_flags |= BA_PCG_BREAKDOWN;
   if (r.coarse > 0 && (h->hscal[SC_BREAK] != 0.0 || !std::isfinite(h->hscal[SC_RR]) || !std::isfinite(h->hscal[SC_RZ]))) {
     // the two-level solve broke down: solve again with block-Jacobi alone
     h->d.coarse_k = 0;
@@ -1289,11 +1303,11 @@ bool do_step(ba_handle* h, const ba_solve_options& o, ba_step_report* rep, doubl
     mv_ms += mv2;
   }
   r.matvec_ms = mv_ms;
-  r.matvec_count = o.time_kernels && !dense ? r.pcg_iters + (h->hscal[SC_BREAK] != 0.0 ? 1 : 0) : 0;
+  r.matvec_count = o.time_kernels && !dense && !fixa ? r.pcg_iters + (h->hscal[SC_BREAK] != 0.0 ? 1 : 0) : 0;
   record(h, 4);
   const double rr = h->hscal[SC_RR], bb = h->hscal[SC_BB];
-  if (solved && !std::isfinite(bb)) r.pcg_flags |= BA_PCG_NONFINITE_RHS;
-  r.pcg_rel_residual = solved && bb > 0 ? std::sqrt(rr / bb) : 0.0;
+  if (solved && !fixa && !std::isfinite(bb)) r.pcg_flags |= BA_PCG_NONFINITE_RHS;
+  r.pcg_rel_residual = solved && !fixa && bb > 0 ? std::sqrt(rr / bb) : 0.0;
   r.n_fp64_blocks = (int)h->hscal[SC_NFLAG];
   r.n_fp64_failed = (int)h->hscal[SC_NFAIL];
   r.n_degenerate = (int)h->hscal[SC_NDEG];
@@ -1375,6 +1389,15 @@ void ba_default_options(ba_solve_options* o) {
   o->time_kernels = 0;
   o->deterministic = 0;
   o->linear_solver = BA_SOLVER_PCG;
+  o->fix_a_side = 0;
+}
+
+void ba_default_reliability_options(ba_reliability_options* o) {
+  if (!o) return;
+  o->min_active_obs = 3;
+  o->max_sigma_point = 0.01;
+  o->max_sigma_line = 0.1;
+  o->min_group_support = 3;
 }
 
 ba_status ba_create(const ba_problem_desc* desc, ba_handle** out) {
@@ -1467,37 +1490,214 @@ ba_status ba_lm_step(ba_handle* h, const ba_solve_options* opt, ba_step_report* 
   return guard(h, [&] { do_step(h, o, rep); });
 }
 
+namespace {
+// LM to termination (see ba_solve)
+void solve_loop(ba_handle* h, const ba_solve_options& o, ba_summary& s) {
+  std::memset(&s, 0, sizeof(s));
+  s.termination = 2;
+  auto t0 = std::chrono::steady_clock::now();
+  set_device(h);
+  if (!h->finalized) finalize(h);
+  if (!h->have_cost) current_cost(h);
+  s.E_initial = h->E;
+  for (int it = 0; it < o.max_iters; ++it) {
+    ba_step_report r;
+    if (!do_step(h, o, &r, o.grad_tol)) { s.termination = 1; break; }
+    s.iters++;
+    s.pcg_iters_total += r.pcg_iters;
+    if (r.accepted) {
+      s.accepted++;
+      const double rel = std::fabs(r.Epix_before - r.Epix_after) / std::max(r.Epix_before, 1e-300);
+      if (rel < o.func_tol) { s.termination = 0; break; }
+    }
+    if (h->lambda > 1e16) { s.termination = 3; break; }
+  }
+  s.E_final = h->E;
+  s.Epix_final = h->Epix;
+  s.total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+// record mask in internal order (empty vector: nothing left out of that kind)
+void apply_mask(ba_handle* h, const std::vector<uint8_t>& pt, const std::vector<uint8_t>& ln,
+                const std::vector<uint8_t>& pl, const std::vector<uint8_t>& vp) {
+  Dev& d = h->d;
+  auto put = [&](uint8_t* dst, const std::vector<uint8_t>& v, int n) {
+    if (!n) return false;
+    if (v.empty()) {
+      launch_zero(dst, n, h->stream);
+      return false;
+    }
+    HIPCHK(hipMemcpyAsync(dst, v.data(), n, hipMemcpyHostToDevice, h->stream));
+    return std::any_of(v.begin(), v.end(), [](uint8_t x) { return x != 0; });
+  };
+  bool any = false;
+  any |= put(d.mpt, pt, h->np);
+  any |= put(d.mln, ln, h->nl);
+  any |= put(d.mpl, pl, h->ng);
+  any |= put(d.mvp, vp, h->nv);
+  sync(h);
+  d.has_mask = any ? 1 : 0;
+  h->need_lin = true;
+  h->have_cost = false;
+}
+
+// per-feature statistics (internal order)
+void feature_stats(ba_handle* h, std::vector<int32_t> (&act)[2], std::vector<int32_t> (&obs)[2],
+                   std::vector<double> (&sig)[2]) {
+  linearize_all(h);
+  const int n[2] = {h->np, h->nl};
+  DevAlloc tmp;
+  struct Release {
+    DevAlloc& a;
+    ~Release() { a.free_all(); }
+  } release{tmp};
+  for (int k = 0; k < 2; ++k) {
+    act[k].assign(n[k], 0); obs[k].assign(n[k], 0); sig[k].assign(n[k], 0.0);
+    if (!n[k]) continue;
+    int32_t* da = tmp.get<int32_t>(n[k]);
+    int32_t* dn = tmp.get<int32_t>(n[k]);
+    double* ds = tmp.get<double>(n[k]);
+    launch_feature_stats(h->d, da, dn, ds, k == 0 ? 3 : 4, h->stream);
+    check_launch("feature statistics");
+    HIPCHK(hipMemcpyAsync(act[k].data(), da, n[k] * 4, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipMemcpyAsync(obs[k].data(), dn, n[k] * 4, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipMemcpyAsync(sig[k].data(), ds, n[k] * 8, hipMemcpyDeviceToHost, h->stream));
+    sync(h);
+  }
+}
+}  // namespace
+
 ba_status ba_solve(ba_handle* h, const ba_solve_options* opt, ba_summary* sum) {
   if (!h) return BA_E_INVALID;
   const ba_solve_options o = opts_or_default(opt);
   ba_summary s;
   std::memset(&s, 0, sizeof(s));
   s.termination = 2;
-  ba_status st = guard(h, [&] {
-    auto t0 = std::chrono::steady_clock::now();
-    set_device(h);
-    if (!h->finalized) finalize(h);
-    if (!h->have_cost) current_cost(h);
-    s.E_initial = h->E;
-    for (int it = 0; it < o.max_iters; ++it) {
-      ba_step_report r;
-      if (!do_step(h, o, &r, o.grad_tol)) { s.termination = 1; break; }
-      s.iters++;
-      s.pcg_iters_total += r.pcg_iters;
-      if (r.accepted) {
-        s.accepted++;
-        const double rel = std::fabs(r.Epix_before - r.Epix_after) / std::max(r.Epix_before, 1e-300);
-        if (rel < o.func_tol) { s.termination = 0; break; }
-      }
-      if (h->lambda > 1e16) { s.termination = 3; break; }
-    }
-    s.E_final = h->E;
-    s.Epix_final = h->Epix;
-    s.total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-  });
+  ba_status st = guard(h, [&] { solve_loop(h, o, s); });
   if (sum) *sum = s;
   if (st != BA_OK) return st;
   return s.termination == 2 ? BA_E_NOT_CONVERGED : BA_OK;
+}
+
+ba_status ba_set_record_mask(ba_handle* h, const uint8_t* points_out, const uint8_t* lines_out,
+                             const uint8_t* planes_out, const uint8_t* vps_out) {
+  if (!h) return BA_E_INVALID;
+  return guard(h, [&] {
+    set_device(h);
+    if (!h->finalized) finalize(h);
+    std::vector<uint8_t> pt, ln, pl, vp;
+    if (points_out) {
+      pt.assign(h->np, 0);
+      for (int j = 0; j < h->np; ++j) pt[h->pt_inv[j]] = points_out[j] ? 1 : 0;
+    }
+    if (lines_out) {
+      ln.assign(h->nl, 0);
+      for (int k = 0; k < h->nl; ++k) ln[h->ln_inv[k]] = lines_out[k] ? 1 : 0;
+    }
+    if (planes_out) pl.assign(planes_out, planes_out + h->ng);
+    if (vps_out) vp.assign(vps_out, vps_out + h->nv);
+    apply_mask(h, pt, ln, pl, vp);
+  });
+}
+
+ba_status ba_feature_reliability(ba_handle* h, int32_t* pt_active, int32_t* pt_obs, double* pt_sigma,
+                                 int32_t* ln_active, int32_t* ln_obs, double* ln_sigma) {
+  if (!h) return BA_E_INVALID;
+  return guard(h, [&] {
+    set_device(h);
+    if (!h->finalized) finalize(h);
+    std::vector<int32_t> act[2], obs[2];
+    std::vector<double> sig[2];
+    feature_stats(h, act, obs, sig);
+    for (int j = 0; j < h->np; ++j) {
+      const int i = h->pt_inv[j];
+      if (pt_active) pt_active[j] = act[0][i];
+      if (pt_obs) pt_obs[j] = obs[0][i];
+      if (pt_sigma) pt_sigma[j] = sig[0][i];
+    }
+    for (int k = 0; k < h->nl; ++k) {
+      const int i = h->ln_inv[k];
+      if (ln_active) ln_active[k] = act[1][i];
+      if (ln_obs) ln_obs[k] = obs[1][i];
+      if (ln_sigma) ln_sigma[k] = sig[1][i];
+    }
+  });
+}
+
+ba_status ba_solve_two_stage(ba_handle* h, const ba_solve_options* opt, const ba_reliability_options* ro,
+                             ba_two_stage_summary* out) {
+  if (!h) return BA_E_INVALID;
+  ba_solve_options o = opts_or_default(opt);
+  ba_reliability_options r;
+  ba_default_reliability_options(&r);
+  if (ro) r = *ro;
+  ba_two_stage_summary sum;
+  std::memset(&sum, 0, sizeof(sum));
+  const ba_status st = guard(h, [&] {
+    if (r.min_active_obs < 0 || !(r.max_sigma_point >= 0) || !(r.max_sigma_line >= 0) || r.min_group_support < 0)
+      throw BaError(BA_E_INVALID, "bad reliability options");
+    set_device(h);
+    if (!h->finalized) finalize(h);
+    const std::vector<uint8_t> none;
+    apply_mask(h, none, none, none, none);
+    std::vector<int32_t> act[2], obs[2];
+    std::vector<double> sig[2];
+    feature_stats(h, act, obs, sig);
+    // reliable flags (internal order)
+    std::vector<uint8_t> rel[2];
+    for (int k = 0; k < 2; ++k) {
+      const double smax = k == 0 ? r.max_sigma_point : r.max_sigma_line;
+      rel[k].resize(act[k].size());
+      for (size_t i = 0; i < act[k].size(); ++i) rel[k][i] = act[k][i] >= r.min_active_obs && sig[k][i] <= smax;
+    }
+    // group support: distinct reliable features associated with each plane / VP
+    auto support = [&](int ngrp, std::initializer_list<std::pair<int, int>> kinds) {
+      std::vector<int> cnt(ngrp, 0);
+      for (auto [kind, fk] : kinds) {
+        const Obs& ob = h->obs[kind];
+        std::vector<std::pair<int, int>> pairs;
+        for (size_t i = 0; i < ob.a.size(); ++i) pairs.emplace_back(ob.a[i], ob.b[i]);
+        std::sort(pairs.begin(), pairs.end());
+        pairs.erase(std::unique(pairs.begin(), pairs.end()), pairs.end());
+        for (auto [g, f] : pairs) {
+          const int fi = fk == 0 ? h->pt_inv[f] : h->ln_inv[f];
+          if (rel[fk][fi]) cnt[g]++;
+        }
+      }
+      return cnt;
+    };
+    const std::vector<int> spl = support(h->ng, {{BA_ASSOC_PLANE_POINT, 0}, {BA_ASSOC_PLANE_LINE, 1}});
+    const std::vector<int> svp = support(h->nv, {{BA_ASSOC_VP_LINE, 1}});
+    std::vector<uint8_t> m1[2], mpl(h->ng), mvp(h->nv), m2[2];
+    for (int k = 0; k < 2; ++k) {
+      m1[k].resize(rel[k].size());
+      m2[k].resize(rel[k].size());
+      for (size_t i = 0; i < rel[k].size(); ++i) {
+        m1[k][i] = !rel[k][i];
+        m2[k][i] = rel[k][i];
+      }
+    }
+    for (int g = 0; g < h->ng; ++g) mpl[g] = spl[g] < r.min_group_support;
+    for (int v = 0; v < h->nv; ++v) mvp[v] = svp[v] < r.min_group_support;
+    sum.n_points_unreliable = (int)std::count(m1[0].begin(), m1[0].end(), 1);
+    sum.n_lines_unreliable = (int)std::count(m1[1].begin(), m1[1].end(), 1);
+    sum.n_planes_out = (int)std::count(mpl.begin(), mpl.end(), 1);
+    sum.n_vps_out = (int)std::count(mvp.begin(), mvp.end(), 1);
+    // stage 1: cameras, reliable features, supported groups
+    o.fix_a_side = 0;
+    apply_mask(h, m1[0], m1[1], mpl, mvp);
+    h->first_step = true;
+    solve_loop(h, o, sum.stage1);
+    // stage 2: the unreliable features with cameras and groups fixed
+    o.fix_a_side = 1;
+    apply_mask(h, m2[0], m2[1], none, none);
+    h->first_step = true;
+    solve_loop(h, o, sum.stage2);
+    apply_mask(h, none, none, none, none);
+    h->first_step = true;
+  });
+  if (out) *out = sum;
+  return st;
 }
 
 ba_status ba_get_parameters(const ba_handle* hc, double* cams, double* pts, double* lines, double* planes, double* vps) {

@@ -148,6 +148,11 @@ struct Dev {
   int32_t *pair_off = nullptr, *pair_uoff = nullptr, *pair_choff = nullptr;
   double *dY = nullptr, *dS = nullptr, *dLinv = nullptr, *dv = nullptr, *dw = nullptr, *dpart = nullptr;
   int* dinfo = nullptr;
+  // records left out (the reliability-aware refinement): with has_mask, a record whose
+  // parameters include a point, line, plane or VP flagged here (internal order) has
+  // zero weight in the linearisation and no cost; the flagged parameters do not move
+  int has_mask = 0;
+  uint8_t *mpt = nullptr, *mln = nullptr, *mpl = nullptr, *mvp = nullptr;
   // deterministic mode: the product's s_f per feature (T; points x 3, lines x 4) and the
   // per-workgroup partials of the PCG dot products (det_stride workgroups per accumulator:
   // the SC_COUNT scalars, then the COARSE_K entries of Z^T b)
@@ -157,6 +162,17 @@ struct Dev {
   unsigned int *cnt = nullptr;  // grid-wide "last workgroup" counters (zeroed, self-resetting)
   double *part2 = nullptr;      // per-workgroup partial dot products of the PCG kernels
 };
+
+// record i of family FAM (feature f) left out by the record mask: its point or line
+// (a junction record's partner feature only supplies the measurement), its plane or VP
+template <int FAM> __device__ __forceinline__ bool record_masked(const Dev& d, int64_t i, int f) {
+  if (!d.has_mask) return false;
+  const bool line = FAM == 2 || FAM == 4 || FAM == 5 || FAM == 7;
+  if ((line ? d.mln : d.mpt)[f]) return true;
+  if constexpr (FAM == 3 || FAM == 4) return d.mpl[d.fgrp[FAM][i]] != 0;
+  if constexpr (FAM == 5) return d.mvp[d.fgrp[FAM][i]] != 0;
+  return false;
+}
 
 // product: 1024-thread workgroups sharing one FP64 copy of y in LDS (FP32 LDS atomics
 // measured 2x slower on gfx950); each wavefront takes tiles of at most MV_TILE records
@@ -257,6 +273,10 @@ void launch_coarse_setup(const Dev& d, double lambda, hipStream_t s);
 void launch_backsub(const Dev& d, hipStream_t s);                        // h_f, model decrease terms
 void launch_retract(const Dev& d, hipStream_t s);                        // candidate = current [+] h
 void launch_zero(void* p, size_t bytes, hipStream_t s);
+// per point (NF 3, observation records R1) or line (NF 4, R2): active observations
+// (residual in the quadratic part of the loss), observations, and sigma =
+// lambda_min(V_f)^-1/2 (points: over the mean distance to the observing cameras)
+void launch_feature_stats(const Dev& d, int32_t* n_active, int32_t* n_obs, double* sigma, int nf, hipStream_t s);
 int matvec_max_lds_bytes();
 size_t matvec_lds_bytes(const Dev& d);
 

@@ -343,7 +343,7 @@ template <int FAM, typename T, int CD> __global__ __launch_bounds__(256) void k_
   for (int k = 0; k < F::ROWS; ++k) s += r64[k] * r64[k];
   double rho, drho;
   loss_eval<double>(d.lkind[FAM], d.lscale[FAM], s, rho, drho);
-  const double ws = sqrt(d.lweight[FAM] * drho);
+  const double ws = record_masked<FAM>(d, i, f) ? 0.0 : sqrt(d.lweight[FAM] * drho);
   T* ro = ((T*)d.fres[FAM]) + i * F::ROWS;
 #pragma unroll
   for (int k = 0; k < F::ROWS; ++k) ro[k] = (T)(ws * r64[k]);
@@ -382,7 +382,7 @@ template <int FAM> __global__ __launch_bounds__(256) void k_cost(Dev d, int cand
   __shared__ double lds[8];
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   double e = 0;
-  if (i < d.fn[FAM]) {
+  if (i < d.fn[FAM] && !record_masked<FAM>(d, i, d.ffeat[FAM][i])) {
     double r[4];
     if (candidate) residual64<FAM>(d, i, d.cam64n, d.pt64n, d.ln64n, d.pl64n, d.vp64n, r);
     else residual64<FAM>(d, i, d.cam64, d.pt64, d.ln64, d.pl64, d.vp64, r);
@@ -2999,6 +2999,10 @@ __device__ void s2_basis(const double* n, double* b1, double* b2) {
 }
 
 __device__ void s2_retract(const double* n, const double* b1, const double* b2, double d0, double d1, double* out) {
+  if (d0 == 0.0 && d1 == 0.0) {  // no step (a fixed group): unchanged, not renormalised
+    for (int i = 0; i < 3; ++i) out[i] = n[i];
+    return;
+  }
   double v[3];
   for (int i = 0; i < 3; ++i) v[i] = b1[i] * d0 + b2[i] * d1;
   const double th = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
@@ -3078,6 +3082,108 @@ void launch_retract(const Dev& d, hipStream_t s) {
 __global__ void k_zero(unsigned char* p, size_t n) {
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = 0;
 }
+// ---------------------------------------------------------------------------
+// feature statistics for the reliability-aware refinement
+
+// smallest eigenvalue of a symmetric N x N matrix (overwritten) by cyclic Jacobi
+// rotations in FP64, until the off-diagonal mass is below 1e-30 of the diagonal's
+template <int N> __device__ double sym_min_eig(double (&A)[N][N]) {
+  for (int sweep = 0; sweep < 30; ++sweep) {
+    double off = 0.0, dia = 0.0;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      dia += A[i][i] * A[i][i];
+#pragma unroll
+      for (int j = i + 1; j < N; ++j) off += A[i][j] * A[i][j];
+    }
+    if (!(off > 1e-30 * dia)) break;
+#pragma unroll
+    for (int p = 0; p < N; ++p)
+#pragma unroll
+      for (int q = p + 1; q < N; ++q) {
+        const double apq = A[p][q];
+        if (fabs(apq) < 1e-300) continue;
+        // rotation angle that zeroes A[p][q]: t = tan(phi), the smaller root
+        const double th = (A[q][q] - A[p][p]) / (2.0 * apq);
+        const double t = fabs(th) > 1e150 ? 0.5 / th : (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+        const double c = 1.0 / sqrt(t * t + 1.0), sn = t * c;
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+          const double akp = A[k][p], akq = A[k][q];
+          A[k][p] = c * akp - sn * akq;
+          A[k][q] = sn * akp + c * akq;
+        }
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+          const double apk = A[p][k], aqk = A[q][k];
+          A[p][k] = c * apk - sn * aqk;
+          A[q][k] = sn * apk + c * aqk;
+        }
+      }
+  }
+  double m = A[0][0];
+#pragma unroll
+  for (int i = 1; i < N; ++i) m = fmin(m, A[i][i]);
+  return m;
+}
+
+// one thread per point (NF 3) or line (NF 4): its observation records (R1 / R2)
+// in the quadratic part of their loss, their count, and sigma from the feature block
+template <typename T, int NF> __global__ __launch_bounds__(256) void k_feat_stats(Dev d, int32_t* nact, int32_t* nobs,
+                                                                                  double* sig) {
+  constexpr int FAM = NF == 3 ? 1 : 2;
+  constexpr int NS = NF * (NF + 1) / 2;
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= (NF == 3 ? d.np : d.nl)) return;
+  const int32_t r0 = d.foff[FAM][f], r1 = d.foff[FAM][f + 1];
+  const double s2 = d.lscale[FAM] * d.lscale[FAM];
+  int act = 0;
+  double dsum = 0.0;
+  for (int32_t r = r0; r < r1; ++r) {
+    double res[4];
+    residual64<FAM>(d, r, d.cam64, d.pt64, d.ln64, d.pl64, d.vp64, res);
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < Fam<FAM, 9>::ROWS; ++k) s += res[k] * res[k];
+    if (d.lkind[FAM] == 0 || s <= s2) ++act;
+    if constexpr (NF == 3) {
+      const double* c = d.cam64 + (int64_t)CAM_STRIDE * d.fcam[FAM][r];
+      const double* X = d.pt64 + (int64_t)PT_STRIDE * f;
+      double e = 0.0;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const double ck = -(c[k] * c[9] + c[3 + k] * c[10] + c[6 + k] * c[11]);
+        e += (X[k] - ck) * (X[k] - ck);
+      }
+      dsum += sqrt(e);
+    }
+  }
+  const T* P = (const T*)(NF == 3 ? d.Vp : d.Vl) + (int64_t)NS * f;
+  double A[NF][NF];
+#pragma unroll
+  for (int i = 0; i < NF; ++i)
+#pragma unroll
+    for (int j = 0; j < NF; ++j) A[i][j] = (double)P[sym<NF>(i, j)];
+  const double lam = sym_min_eig<NF>(A);
+  double sigma = lam > 0.0 ? 1.0 / sqrt(lam) : INFINITY;
+  if constexpr (NF == 3) sigma = r1 > r0 ? sigma / (dsum / (double)(r1 - r0)) : INFINITY;
+  nact[f] = act;
+  nobs[f] = r1 - r0;
+  sig[f] = sigma;
+}
+
+void launch_feature_stats(const Dev& d, int32_t* n_active, int32_t* n_obs, double* sigma, int nf, hipStream_t s) {
+  const int n = nf == 3 ? d.np : d.nl;
+  if (!n) return;
+  if (nf == 3) {
+    if (d.fp64) k_feat_stats<double, 3><<<nblk(n, 256), 256, 0, s>>>(d, n_active, n_obs, sigma);
+    else k_feat_stats<float, 3><<<nblk(n, 256), 256, 0, s>>>(d, n_active, n_obs, sigma);
+  } else {
+    if (d.fp64) k_feat_stats<double, 4><<<nblk(n, 256), 256, 0, s>>>(d, n_active, n_obs, sigma);
+    else k_feat_stats<float, 4><<<nblk(n, 256), 256, 0, s>>>(d, n_active, n_obs, sigma);
+  }
+}
+
 void launch_zero(void* p, size_t bytes, hipStream_t s) {
   if (bytes) k_zero<<<256, 256, 0, s>>>((unsigned char*)p, bytes);
 }

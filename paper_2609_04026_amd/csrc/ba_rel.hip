@@ -35,6 +35,13 @@ __device__ __forceinline__ bool rel_plane(int kind) { return kind >= 2; }
 __device__ __forceinline__ bool rel_parallel(int kind) { return kind == 1 || kind == 3; }
 __device__ __forceinline__ int rel_rows(int kind) { return rel_parallel(kind) ? 3 : 1; }
 
+// a relation whose group (either one) is left out by the record mask
+__device__ __forceinline__ bool rel_masked(const Dev& d, int i) {
+  if (!d.has_mask) return false;
+  const uint8_t* m = rel_plane(d.rel_kind[i]) ? d.mpl : d.mvp;
+  return m[d.rel_ga[i]] != 0 || m[d.rel_gb[i]] != 0;
+}
+
 // direction and tangent basis of group g of a relation kind, from the FP64 parameters
 __device__ __forceinline__ void rel_dir(const Dev& d, int kind, int g, bool candidate, double (&u)[3], double (&b1)[3],
                                         double (&b2)[3]) {
@@ -84,7 +91,7 @@ __global__ __launch_bounds__(256) void k_rel_lin(Dev d) {
   const double s = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
   double rho, drho;
   loss_eval<double>(d.rel_lkind[kind], d.rel_lscale[kind], s, rho, drho);
-  const double ws = sqrt(d.rel_lweight[kind] * drho);
+  const double ws = rel_masked(d, i) ? 0.0 : sqrt(d.rel_lweight[kind] * drho);
 #pragma unroll
   for (int row = 0; row < 3; ++row) {
     d.rel_r[3 * (int64_t)i + row] = ws * r[row];
@@ -185,6 +192,7 @@ __global__ __launch_bounds__(256) void k_rel_cost(Dev d, int candidate, double* 
   __shared__ double lds[5];
   double e = 0;
   for (int i = threadIdx.x; i < d.n_rel; i += blockDim.x) {
+    if (rel_masked(d, i)) continue;
     const int kind = d.rel_kind[i];
     double ua[3], a1[3], a2[3], ub[3], b1[3], b2[3], r[3];
     rel_dir(d, kind, d.rel_ga[i], candidate != 0, ua, a1, a2);

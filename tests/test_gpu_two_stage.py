@@ -1,0 +1,149 @@
+"""Reliability-aware two-stage refinement (App. A.2) on the GPU against the oracle.
+
+On the tiny holistic scene with planted outliers (Huber losses): the per-feature
+statistics (active observations and observations exactly, sigma within 1e-9 on
+the FP64 path), the record mask (one LM step of the masked problem against the
+oracle's exact Schur step on the same masked problem), the fixed-A step, and the
+whole refinement (flags, groups left out, each stage's converged cost, and on the
+FP64 path the final positions of the unreliable points) from the same starting
+parameters.
+"""
+import numpy as np
+import pytest
+
+from oracle import lm, model, reliability as R
+from tests.two_stage_scenes import outlier_scene
+
+pytestmark = pytest.mark.gpu
+
+
+def _BA():
+    from paper_2609_04026_amd.binding import BA
+    return BA
+
+
+def _state(p):
+    """Oracle state from ba_get_parameters' output (lines there are unit d and
+    m / |d|; the oracle takes two points: the foot p0 = d x m and p0 + d)."""
+    d, m = p["lines"][:, 0:3], p["lines"][:, 3:6]
+    p0 = np.cross(d, m)
+    lines = np.concatenate([p0, p0 + d], axis=1)
+    return model.State.from_arrays(p["cameras"], p["points"], lines, p["planes"], p["vps"])
+
+
+def _solved(precision):
+    s, bp, bl = outlier_scene()
+    ba = _BA().from_scene(s, precision=precision)
+    ba.solve(func_tol=1e-12, max_iters=300, pcg_tol=1e-10 if precision == "fp64" else 1e-7, pcg_max_iters=3000)
+    return s, bp, bl, ba
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_feature_statistics_match_oracle(precision):
+    s, bp, bl, ba = _solved(precision)
+    prob = lm.Problem(s)
+    st = _state(ba.get_parameters())
+    ref = R.feature_stats(prob, st)
+    got = ba.feature_reliability()
+    tol = 1e-9 if precision == "fp64" else 1e-3
+    for k in ("pt", "ln"):
+        assert np.array_equal(got[k]["n_obs"], ref[k]["n_obs"]), k
+        assert np.array_equal(got[k]["n_active"], ref[k]["n_active"]), k
+        err = np.abs(got[k]["sigma"] - ref[k]["sigma"]) / ref[k]["sigma"]
+        print(f"[stats] {precision} {k}: sigma within {err.max():.2e}", flush=True)
+        assert err.max() <= tol, (k, err.max())
+    flags = R.classify(ref)
+    assert np.array_equal(np.nonzero(~flags["pt"])[0], bp)
+    assert np.array_equal(np.nonzero(~flags["ln"])[0], bl)
+    ba.close()
+
+
+def _random_masks(prob, seed=4):
+    rng = np.random.default_rng(seed)
+    pt_out = rng.random(prob.n["pt"]) < 0.3
+    ln_out = rng.random(prob.n["ln"]) < 0.3
+    pl_out = np.zeros(prob.n["pl"], bool)
+    pl_out[0] = True
+    vp_out = np.zeros(prob.n["vp"], bool)
+    vp_out[-1] = True
+    return pt_out, ln_out, pl_out, vp_out
+
+
+@pytest.mark.parametrize("solver", ["pcg", "dense"])
+def test_masked_step_matches_oracle(solver):
+    s, _, _ = outlier_scene()
+    prob = lm.Problem(s)
+    st = prob.state0()
+    masks = _random_masks(prob)
+    pm = R.masked_problem(prob, *masks)
+    lam = 1e-3
+    ba = _BA().from_scene(s, precision="fp64")
+    ba.set_record_mask(*masks)
+    before = ba.get_parameters()
+    rep = ba.lm_step(lambda0=lam, pcg_tol=1e-12, pcg_max_iters=3000, solver=solver)
+    lin = lm.linearize(pm, st)
+    h, _ = lm.solve_schur(pm, lin, lam)
+    E0 = lm.cost(pm, st)[0]
+    E1 = lm.cost(pm, pm.retract(st, h))[0]
+    print(f"[mask] {solver}: E {rep['E_before']} -> {rep['E_after']} vs {E0} -> {E1}", flush=True)
+    assert abs(rep["E_before"] - E0) <= 1e-12 * E0
+    assert abs(rep["E_after"] - E1) <= 1e-10 * E1
+    p = ba.get_parameters()
+    pt_out = masks[0]
+    assert np.array_equal(p["points"][pt_out], before["points"][pt_out])
+    ba.close()
+
+
+def test_fixed_a_step_matches_oracle():
+    s, _, _ = outlier_scene()
+    prob = lm.Problem(s)
+    st = prob.state0()
+    lam = 1e-3
+    ba = _BA().from_scene(s, precision="fp64")
+    before = ba.get_parameters()
+    rep = ba.lm_step(lambda0=lam, fix_a_side=1)
+    lin = lm.linearize(prob, st)
+    h = lm.solve_features(prob, lin, lam)
+    E1 = lm.cost(prob, prob.retract(st, h))[0]
+    print(f"[fixed A] {rep['E_after']} vs {E1}", flush=True)
+    assert abs(rep["E_after"] - E1) <= 1e-10 * E1
+    dL = lm.model_decrease(lin, h)
+    assert abs(rep["model_decrease"] - dL) <= 1e-9 * abs(dL)
+    p = ba.get_parameters()
+    for k in ("cameras", "planes", "vps"):
+        assert np.array_equal(p[k], before[k]), k
+    assert not np.array_equal(p["points"], before["points"])
+    ba.close()
+
+
+@pytest.mark.parametrize("precision,solver", [("fp64", "pcg"), ("fp64", "dense"), ("mixed", "pcg")])
+def test_two_stage_matches_oracle(precision, solver):
+    s, bp, bl, ba = _solved(precision)
+    prob = lm.Problem(s)
+    p0 = ba.get_parameters()
+    st0 = _state(p0)
+    kw = dict(func_tol=1e-12, max_iters=200)
+    ref = R.two_stage(prob, st0, **kw)
+    pcg = dict(pcg_tol=1e-10 if precision == "fp64" else 1e-7, pcg_max_iters=3000)
+    out = ba.solve_two_stage(solver=solver, **kw, **pcg)
+    print(f"[two-stage] {precision} {solver}: {out}", flush=True)
+    print(f"[two-stage] oracle: stage 1 {ref['stage1']['E']} ({ref['stage1']['iters']} it), "
+          f"stage 2 {ref['stage2']['E']} ({ref['stage2']['iters']} it)", flush=True)
+    assert out["n_points_unreliable"] == len(bp) and out["n_lines_unreliable"] == len(bl)
+    assert out["n_planes_out"] == int(ref["group_out"]["pl"].sum())
+    assert out["n_vps_out"] == int(ref["group_out"]["vp"].sum()) == 1
+    tol = 1e-9 if precision == "fp64" else 1e-6
+    for st in ("stage1", "stage2"):
+        assert abs(out[st]["E_final"] - ref[st]["E"]) <= tol * ref[st]["E"], (st, out[st]["E_final"], ref[st]["E"])
+    p = ba.get_parameters()
+    st_ref = ref["state"]
+    scale = np.abs(st_ref.pts).max()
+    if precision == "fp64":
+        # the unreliable points have two inlier views: on the FP32 path their optimum
+        # moves along the flat direction by ~1e-3 while the cost agrees to 1e-10
+        assert np.abs(p["points"][bp] - st_ref.pts[bp]).max() <= 1e-7 * scale
+    # the mask is cleared afterwards: the next step sees the whole problem
+    rep = ba.lm_step(lambda0=1e-3, pcg_tol=1e-10)
+    E_all = lm.cost(prob, _state(p))[0]
+    assert abs(rep["E_before"] - E_all) <= 1e-10 * E_all
+    ba.close()
