@@ -96,7 +96,14 @@ typedef enum {
   BA_REL_VP_ORTHO = 6,      /* a = vp,     b = vp */
   BA_REL_VP_PARALLEL = 7,   /* a = vp,     b = vp */
   BA_REL_PLANE_ORTHO = 8,   /* a = plane,  b = plane */
-  BA_REL_PLANE_PARALLEL = 9 /* a = plane,  b = plane */
+  BA_REL_PLANE_PARALLEL = 9, /* a = plane,  b = plane */
+  /* The 3D formulation the paper compares its pixel-space group residuals against
+   * (Sec. 3.3's discussion of 3D regularisation; the 2D-vs-3D ablation of Sec. 4): the
+   * signed metric distance n . X + w of a point to a plane, one record per association,
+   * no camera.  Default loss: trivial, weight 100 (the paper sweeps 1 .. 1000); left out
+   * of E_pix (metric, not pixels).  Residual family 12.  A point may carry it for several
+   * planes; it may carry a BA_ASSOC_PLANE_POINT association too. */
+  BA_ASSOC_PLANE_POINT_3D = 10 /* a = plane, b = point; meas = NULL */
 } ba_kind;
 
 typedef enum { BA_LOSS_TRIVIAL = 0, BA_LOSS_HUBER = 1, BA_LOSS_CAUCHY = 2 } ba_loss_kind;
@@ -317,7 +324,7 @@ ba_status ba_linearize(ba_handle *h, double lambda);
 /* Number of residual records of a family (1 point, 2 line, 3 plane-point,
  * 4 plane-line, 5 vp-line, 6 point-to-line, 7 line-to-point; inter-group
  * relations 8 VP orthogonal, 9 VP parallel, 10 plane orthogonal, 11 plane
- * parallel). */
+ * parallel; 12 3D point-to-plane). */
 ba_status ba_record_count(const ba_handle *h, int32_t family, int64_t *count);
 
 /* Export the last linearisation of a family, in the handle's internal record
@@ -327,7 +334,8 @@ ba_status ba_record_count(const ba_handle *h, int32_t family, int64_t *count);
  * group dof) in that column order (weighted).  Relation families 8-11: keys
  * (-1, group a, group b), rows 1 (orthogonal) or 3 (parallel), J columns
  * [group a | group b] with 2 per VP and 3 per plane (the offset column is
- * zero).  Any output may be NULL. */
+ * zero).  Family 12: keys (-1, point, plane), 1 row, J columns [point (3) |
+ * plane (3)] (no camera, as family 5).  Any output may be NULL. */
 ba_status ba_export_records(const ba_handle *h, int32_t family, int64_t *keys, double *r, double *J);
 
 /* Feature blocks of the last linearisation: V_f = sum J~_f^T J~_f (undamped)

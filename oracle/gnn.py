@@ -215,7 +215,7 @@ def block_graph(prob):
     npt = prob.n["pt"]
     feats, blocks = [], []
     for fam, r in prob.recs.items():
-        if fam not in ("R1", "R2", "R3", "R4", "R5", "R6", "R7"):
+        if fam not in ("R1", "R2", "R3", "R4", "R5", "R6", "R7", "R12"):
             continue  # inter-group relations share no feature
         f = r["ln"] + npt if fam in ("R2", "R4", "R5", "R7") else r["pt"]
         if "cam" in r:

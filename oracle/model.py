@@ -420,6 +420,13 @@ def res_vp_line(g: Gathered, rec, cx, cy):
     return cross(u, g.v)
 
 
+def res_plane_point_3d(g: Gathered, rec, cx, cy):
+    """R12, the 3D formulation the paper compares against (Sec. 3.3 discussion,
+    Sec. 4 ablation): the signed metric distance n . X + w of the point to the
+    plane, in scene units (the weight of the sweep enters through the loss)."""
+    return (dot(g.n, g.X) + g.wp)[..., None]
+
+
 def res_point_to_line(g: Gathered, rec, cx, cy):
     """R6, Sec. 3.4 Eq. 11: d(pi-bar(C_i, X_j), l_ik), observed line l_ik."""
     x = project_pinhole(g.R, g.t, g.f, g.X, cx, cy)
@@ -462,8 +469,9 @@ FAMILIES = {
     "R9": (res_rel_parallel, 3, [("vp", "ga", 2), ("vp", "gb", 2)]),     # VP || VP
     "R10": (res_rel_ortho, 1, [("pl", "ga", 3), ("pl", "gb", 3)]),       # plane _|_ plane
     "R11": (res_rel_parallel, 3, [("pl", "ga", 3), ("pl", "gb", 3)]),    # plane || plane
+    "R12": (res_plane_point_3d, 1, [("pt", "pt", 3), ("pl", "pl", 3)]),  # 3D point-to-plane
 }
-FAMILY_ORDER = ["R1", "R2", "R3", "R4", "R5", "R6", "R7", "R8", "R9", "R10", "R11"]
+FAMILY_ORDER = ["R1", "R2", "R3", "R4", "R5", "R6", "R7", "R8", "R9", "R10", "R11", "R12"]
 RELATION_FAMILIES = ("R8", "R9", "R10", "R11")
 PIXEL_FAMILIES = ("R1", "R2", "R3", "R4", "R6", "R7")  # R5 and the relations are angular (Sec. 3.5)
 

@@ -19,7 +19,9 @@ The visibility rules are the paper's:
   record (Sec. 3.4, after Eq. 12);
 * R8-R11 one record per inter-group relation: VP-VP orthogonal, VP-VP
   parallel, plane-plane orthogonal, plane-plane parallel (Sec. 3.2, the
-  inter-group relations between VP pairs and plane-normal pairs).
+  inter-group relations between VP pairs and plane-normal pairs);
+* R12 one record per 3D point-to-plane association (g, j): the metric
+  distance of the 3D formulation the paper compares against.
 
 Each family is a dict of equally long arrays; ``key`` gives a record's
 identity for matching against another implementation:
@@ -30,12 +32,15 @@ from __future__ import annotations
 import numpy as np
 
 from scenegen import (OBS_POINT, OBS_LINE, ASSOC_PLANE_POINT, ASSOC_PLANE_LINE, ASSOC_VP_LINE,
-                      ASSOC_JUNCTION, REL_VP_ORTHO, REL_VP_PARALLEL, REL_PLANE_ORTHO, REL_PLANE_PARALLEL)
+                      ASSOC_JUNCTION, REL_VP_ORTHO, REL_VP_PARALLEL, REL_PLANE_ORTHO, REL_PLANE_PARALLEL,
+                      ASSOC_PLANE_POINT_3D)
 
 FAMILY_KIND = {"R1": OBS_POINT, "R2": OBS_LINE, "R3": ASSOC_PLANE_POINT, "R4": ASSOC_PLANE_LINE,
                "R5": ASSOC_VP_LINE, "R6": ASSOC_JUNCTION, "R7": ASSOC_JUNCTION,
-               "R8": REL_VP_ORTHO, "R9": REL_VP_PARALLEL, "R10": REL_PLANE_ORTHO, "R11": REL_PLANE_PARALLEL}
-FAMILY_ID = {"R1": 1, "R2": 2, "R3": 3, "R4": 4, "R5": 5, "R6": 6, "R7": 7, "R8": 8, "R9": 9, "R10": 10, "R11": 11}
+               "R8": REL_VP_ORTHO, "R9": REL_VP_PARALLEL, "R10": REL_PLANE_ORTHO, "R11": REL_PLANE_PARALLEL,
+               "R12": ASSOC_PLANE_POINT_3D}
+FAMILY_ID = {"R1": 1, "R2": 2, "R3": 3, "R4": 4, "R5": 5, "R6": 6, "R7": 7, "R8": 8, "R9": 9, "R10": 10, "R11": 11,
+             "R12": 12}
 
 
 def _views_of(feat_of_obs, n_feat):
@@ -103,6 +108,9 @@ def expand(scene) -> dict:
     for fam in ("R8", "R9", "R10", "R11"):
         a, b, _ = obs.get(FAMILY_KIND[fam], (np.zeros(0), np.zeros(0), None))
         recs[fam] = dict(ga=np.asarray(a, np.int64), gb=np.asarray(b, np.int64))
+    # R12: one record per 3D point-to-plane association (g, j), no camera
+    g, j, _ = obs.get(ASSOC_PLANE_POINT_3D, (np.zeros(0), np.zeros(0), None))
+    recs["R12"] = dict(pt=np.asarray(j, np.int64), pl=np.asarray(g, np.int64))
     return recs
 
 
@@ -126,6 +134,8 @@ def record_keys(recs) -> dict:
             k = (r["cam"], r["pt"], r["ln"])
         elif fam == "R7":
             k = (r["cam"], r["ln"], r["pt"])
+        elif fam == "R12":
+            k = (neg, r["pt"], r["pl"])
         else:  # relations: (-1, group a, group b)
             k = (neg, r["ga"], r["gb"])
         out[fam] = np.stack([np.full(n, FAMILY_ID[fam], dtype=np.int64), *k], axis=1)

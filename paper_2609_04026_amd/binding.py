@@ -22,7 +22,7 @@ STATUS_NAMES = ["BA_OK", "BA_E_INVALID", "BA_E_STATE", "BA_E_OOM", "BA_E_DEVICE"
 PREC = {"fp64": 0, "mixed": 1}
 PRECOND = {"jacobi": 0, "learned": 1, "gauge": 2}
 PHASES = ["linearize", "feature", "schur", "precond", "pcg", "backsub", "cost"]
-FAMILY_ROWS = {1: 2, 2: 4, 3: 2, 4: 4, 5: 3, 6: 1, 7: 1, 8: 1, 9: 3, 10: 1, 11: 3}
+FAMILY_ROWS = {1: 2, 2: 4, 3: 2, 4: 4, 5: 3, 6: 1, 7: 1, 8: 1, 9: 3, 10: 1, 11: 3, 12: 1}
 
 
 class BAError(RuntimeError):
@@ -329,12 +329,12 @@ class BA:
     def export_records(self, fam):
         n = self.record_count(fam)
         rows = FAMILY_ROWS[fam]
-        if fam >= 8:  # inter-group relation: [group a | group b]
+        if 8 <= fam <= 11:  # inter-group relation: [group a | group b]
             ncol = 2 * (3 if fam >= 10 else 2)
         else:
-            cd = 0 if fam == 5 else self.camera_dof
+            cd = 0 if fam in (5, 12) else self.camera_dof
             nf = 4 if fam in (2, 4, 5, 7) else 3
-            ng = 3 if fam in (3, 4) else 2 if fam == 5 else 0
+            ng = 3 if fam in (3, 4, 12) else 2 if fam == 5 else 0
             ncol = cd + nf + ng
         keys = np.zeros((n, 3), dtype=np.int64)
         r = np.zeros((n, rows))

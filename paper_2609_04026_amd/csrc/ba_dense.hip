@@ -159,6 +159,7 @@ template <typename T, int CD> __global__ __launch_bounds__(256) void k_dense_y(D
     acc_w<1, T, CD>(d, f, fe.y, W);
     acc_w<3, T, CD>(d, f, fe.y, W);
     acc_w<6, T, CD>(d, f, fe.y, W);
+    acc_w<8, T, CD>(d, f, fe.y, W);
     vinv_factor<T, 3>(d, f, G);
   } else {
     acc_w<2, T, CD>(d, f, fe.y, W);

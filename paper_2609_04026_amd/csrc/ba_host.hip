@@ -171,7 +171,8 @@ struct ba_handle {
   std::string err;
   // host FP64 parameters in the device layouts (original feature order)
   std::vector<double> cam, pt, ln, pl, vp;
-  Obs obs[10];  // ba_kind 0..5 observations and associations, 6..9 inter-group relations
+  Obs obs[11];  // ba_kind 0..5 observations and associations, 6..9 inter-group relations,
+                //  10 3D point-to-plane associations
   // inter-group relations: caller's (group a, group b) and kind 0..3 per record
   std::vector<int32_t> rel_ga, rel_gb, rel_kind;
   // state
@@ -214,6 +215,7 @@ ba_loss default_loss(int kind) {
     case BA_ASSOC_JUNCTION: return {BA_LOSS_CAUCHY, 1.0, 0.1};
     case BA_REL_VP_ORTHO: case BA_REL_VP_PARALLEL: case BA_REL_PLANE_ORTHO: case BA_REL_PLANE_PARALLEL:
       return {BA_LOSS_CAUCHY, 0.2, 5.0e3};
+    case BA_ASSOC_PLANE_POINT_3D: return {BA_LOSS_TRIVIAL, 1.0, 100.0};
     default: return {BA_LOSS_TRIVIAL, 1.0, 1.0};
   }
 }
@@ -629,6 +631,20 @@ void finalize(ba_handle* h) {
       R[7].push_back(r);
     }
   }
+  // family 8 (exported as 12): one record per 3D point-to-plane association, no camera
+  {
+    const Obs& o = h->obs[BA_ASSOC_PLANE_POINT_3D];
+    std::vector<int64_t> pk(o.a.size());
+    for (size_t i = 0; i < o.a.size(); ++i) pk[i] = (int64_t)o.b[i] * std::max(h->ng, 1) + o.a[i];
+    std::sort(pk.begin(), pk.end());
+    if (std::adjacent_find(pk.begin(), pk.end()) != pk.end())
+      throw BaError(BA_E_INVALID, "duplicate 3D point-to-plane association");
+    for (size_t i = 0; i < o.a.size(); ++i) {
+      const int g = o.a[i], j = o.b[i];
+      Rec r8{h->pt_inv[j], -1, g, g, {0, 0, 0, 0}, {-1, j, g}};
+      R[8].push_back(r8);
+    }
+  }
   // feature-major order: (internal feature, camera, other)
   for (int fam = 1; fam < NFAM; ++fam)
     std::sort(R[fam].begin(), R[fam].end(), [](const Rec& a, const Rec& b) {
@@ -690,7 +706,8 @@ void finalize(ba_handle* h) {
     upload(h, d.fcam[fam], cam); upload(h, d.fgrp[fam], grp); upload(h, d.ffeat[fam], feat);
     upload(h, d.foff[fam], off); upload(h, d.fmeas[fam], meas);
     const int kind = fam == 1 ? BA_OBS_POINT : fam == 2 ? BA_OBS_LINE : fam == 3 ? BA_ASSOC_PLANE_POINT
-                     : fam == 4 ? BA_ASSOC_PLANE_LINE : fam == 5 ? BA_ASSOC_VP_LINE : BA_ASSOC_JUNCTION;
+                     : fam == 4 ? BA_ASSOC_PLANE_LINE : fam == 5 ? BA_ASSOC_VP_LINE
+                     : fam == 8 ? BA_ASSOC_PLANE_POINT_3D : BA_ASSOC_JUNCTION;
     const ba_loss lo = h->obs[kind].loss_set ? h->obs[kind].loss : default_loss(kind);
     d.lkind[fam] = lo.kind; d.lscale[fam] = lo.scale; d.lweight[fam] = lo.weight;
     max_blocks += (n + 255) / 256;
@@ -894,8 +911,16 @@ void finalize(ba_handle* h) {
   // group member lists
   {
     std::vector<std::vector<int32_t>> mp(h->ng), ml(h->ng), mv(h->nv);
-    for (size_t i = 0; i < R[3].size(); ++i)
-      if (i == 0 || R[3][i].feat != R[3][i - 1].feat) mp[R[3][i].grp].push_back(R[3][i].feat);
+    // points of a plane: through its plane-association records (R3) or its 3D
+    // point-to-plane records (family 8), each point once, in feature order
+    {
+      std::vector<std::pair<int32_t, int32_t>> gp;
+      for (const Rec& r : R[3]) gp.emplace_back(r.grp, r.feat);
+      for (const Rec& r : R[8]) gp.emplace_back(r.grp, r.feat);
+      std::sort(gp.begin(), gp.end());
+      gp.erase(std::unique(gp.begin(), gp.end()), gp.end());
+      for (auto [g, f] : gp) mp[g].push_back(f);
+    }
     for (size_t i = 0; i < R[4].size(); ++i)
       if (i == 0 || R[4][i].feat != R[4][i - 1].feat) ml[R[4][i].grp].push_back(R[4][i].feat);
     for (size_t i = 0; i < R[5].size(); ++i) mv[R[5][i].grp].push_back((int32_t)i);
@@ -978,7 +1003,7 @@ void finalize(ba_handle* h) {
         tiles.push_back(make_int4(first, (int)cnt, fb, 0));
       }
     };
-    build({1, 3, 6}, h->np, bigp);
+    build({1, 3, 6, 8}, h->np, bigp);
     d.n_ptiles = (int)tiles.size();
     build({2, 4, 5, 7}, h->nl, bigl);
     d.n_tiles = (int)tiles.size();
@@ -1434,7 +1459,7 @@ ba_status ba_create(const ba_problem_desc* desc, ba_handle** out) {
     }
     for (int k = 0; k <= BA_PHASE_COUNT; ++k) HIPCHK(hipEventCreate(&h->ev[k]));
     h->events = true;
-    for (int k = 0; k < 10; ++k) h->obs[k].loss = default_loss(k);
+    for (int k = 0; k < 11; ++k) h->obs[k].loss = default_loss(k);
   });
   if (st != BA_OK) {
     ba_destroy(h);
@@ -1449,7 +1474,7 @@ ba_status ba_add_observations(ba_handle* h, int32_t kind, int64_t n, const int32
   if (!h) return BA_E_INVALID;
   return guard(h, [&] {
     if (h->finalized) throw BaError(BA_E_STATE, "observations must be added before the first step");
-    if (kind < 0 || kind > 9) throw BaError(BA_E_INVALID, "bad kind");
+    if (kind < 0 || kind > 10) throw BaError(BA_E_INVALID, "bad kind");
     if (n < 0 || (n > 0 && (!a || !b))) throw BaError(BA_E_INVALID, "bad arrays");
     const bool has_meas = kind == BA_OBS_POINT || kind == BA_OBS_LINE;
     if (has_meas && n > 0 && !meas) throw BaError(BA_E_INVALID, "measurements required");
@@ -1462,11 +1487,12 @@ ba_status ba_add_observations(ba_handle* h, int32_t kind, int64_t n, const int32
       case BA_ASSOC_VP_LINE: ha = h->nv; hb = h->nl; break;
       case BA_ASSOC_JUNCTION: ha = h->np; hb = h->nl; break;
       case BA_REL_VP_ORTHO: case BA_REL_VP_PARALLEL: ha = hb = h->nv; break;
+      case BA_ASSOC_PLANE_POINT_3D: ha = h->ng; hb = h->np; break;
       case BA_REL_PLANE_ORTHO: case BA_REL_PLANE_PARALLEL: ha = hb = h->ng; break;
     }
     check_index(a, n, ha, "first");
     check_index(b, n, hb, "second");
-    if (kind >= BA_REL_VP_ORTHO)
+    if (kind >= BA_REL_VP_ORTHO && kind <= BA_REL_PLANE_PARALLEL)
       for (int64_t i = 0; i < n; ++i)
         if (a[i] == b[i]) throw BaError(BA_E_INVALID, "a relation needs two distinct groups");
     if (has_meas && !finite_all(meas, (size_t)n * 4)) throw BaError(BA_E_INVALID, "non-finite measurement");
@@ -1804,10 +1830,10 @@ ba_status ba_linearize(ba_handle* h, double lambda) {
 }
 
 ba_status ba_record_count(const ba_handle* h, int32_t family, int64_t* count) {
-  if (!h || family < 1 || family > 11 || !count) return BA_E_INVALID;
+  if (!h || family < 1 || family > 12 || !count) return BA_E_INVALID;
   if (!h->finalized) { const_cast<ba_handle*>(h)->err = "records exist after the first step"; return BA_E_STATE; }
-  if (family >= 8) *count = std::count(h->rel_kind.begin(), h->rel_kind.end(), family - 8);
-  else *count = h->d.fn[family];
+  if (family >= 8 && family <= 11) *count = std::count(h->rel_kind.begin(), h->rel_kind.end(), family - 8);
+  else *count = h->d.fn[family == 12 ? 8 : family];
   return BA_OK;
 }
 
@@ -1844,8 +1870,9 @@ ba_status export_relations(ba_handle* h, int32_t fam, int64_t* keys, double* r, 
 
 ba_status ba_export_records(const ba_handle* hc, int32_t fam, int64_t* keys, double* r, double* J) {
   ba_handle* h = const_cast<ba_handle*>(hc);
-  if (!h || fam < 1 || fam > 11) return BA_E_INVALID;
-  if (fam >= 8) return export_relations(h, fam, keys, r, J);
+  if (!h || fam < 1 || fam > 12) return BA_E_INVALID;
+  if (fam >= 8 && fam <= 11) return export_relations(h, fam, keys, r, J);
+  if (fam == 12) fam = 8;  // the 3D point-to-plane family, stored as family 8
   return guard(h, [&] {
     if (!h->finalized) throw BaError(BA_E_STATE, "no records yet");
     const int64_t n = h->d.fn[fam];
@@ -1853,7 +1880,7 @@ ba_status ba_export_records(const ba_handle* hc, int32_t fam, int64_t* keys, dou
     if (!r && !J) return;
     const int stride = slot_stride(fam, h->CD), rows = fam_rows(fam);
     const int nc = slot_nc(fam, h->CD), ng = slot_ng(fam), nf = slot_nf(fam);
-    const int ncol = (fam == 5 ? 0 : h->CD) + nf + ng;
+    const int ncol = (fam == 5 || fam == 8 ? 0 : h->CD) + nf + ng;
     set_device(h);
     auto fetch = [&](const void* src, size_t cnt) {
       std::vector<double> out(cnt);
@@ -1879,7 +1906,7 @@ ba_status ba_export_records(const ba_handle* hc, int32_t fam, int64_t* keys, dou
         if (J) {
           double* o = J + ((size_t)i * rows + row) * ncol;
           int col = 0;
-          if (fam != 5) {
+          if (fam != 5 && fam != 8) {
             for (int k = 0; k < h->CD; ++k) o[col++] = k < nc ? s[OC + row * nc + k] : 0.0;
           }
           for (int k = 0; k < nf; ++k) o[col++] = s[OF + row * nf + k];

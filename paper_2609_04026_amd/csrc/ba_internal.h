@@ -14,7 +14,9 @@
 
 namespace ba {
 
-constexpr int NFAM = 8;  // families 1..7 (index 0 unused)
+// families 1..7 of Sec. 3 and 8, the 3D point-to-plane distance of the 3D formulation
+// (exported as family 12, after the four relation families); index 0 unused
+constexpr int NFAM = 9;
 
 // compile-time shape of a family's record slot
 template <int FAM, int CD> struct Fam;
@@ -25,6 +27,7 @@ template <int CD> struct Fam<4, CD> { static constexpr int ROWS = 4, NC = CamCol
 template <int CD> struct Fam<5, CD> { static constexpr int ROWS = 3, NC = 0, NG = 2, NF = 4, MEAS = 0, GT = 2, FT = 1; };
 template <int CD> struct Fam<6, CD> { static constexpr int ROWS = 1, NC = CamCols<CD>::PT, NG = 0, NF = 3, MEAS = 3, GT = 0, FT = 0; };
 template <int CD> struct Fam<7, CD> { static constexpr int ROWS = 1, NC = CamCols<CD>::LN, NG = 0, NF = 4, MEAS = 2, GT = 0, FT = 1; };
+template <int CD> struct Fam<8, CD> { static constexpr int ROWS = 1, NC = 0, NG = 3, NF = 3, MEAS = 0, GT = 1, FT = 0; };
 
 // Jacobian slot of one record: [ J_cam (ROWS x NC) | J_group (ROWS x NG) | J_feature (ROWS x NF) | pad ];
 // the weighted residual lives in a separate ROWS-wide array
@@ -36,7 +39,7 @@ template <int FAM, int CD> struct Slot {
   static constexpr int STRIDE = (USED + 3) / 4 * 4;
 };
 
-inline int meas_width(int fam) { return fam == 1 ? 2 : fam == 2 ? 4 : fam == 3 ? 0 : fam == 4 ? 4 : fam == 5 ? 0 : fam == 6 ? 3 : 2; }
+inline int meas_width(int fam) { return fam == 1 ? 2 : fam == 2 ? 4 : fam == 3 ? 0 : fam == 4 ? 4 : fam == 5 ? 0 : fam == 6 ? 3 : fam == 7 ? 2 : 0; }
 inline int fam_rows(int fam) { return fam == 1 ? 2 : fam == 2 ? 4 : fam == 3 ? 2 : fam == 4 ? 4 : fam == 5 ? 3 : 1; }
 inline bool fam_is_line(int fam) { return fam == 2 || fam == 4 || fam == 5 || fam == 7; }
 int slot_stride(int fam, int cd);
@@ -169,7 +172,7 @@ template <int FAM> __device__ __forceinline__ bool record_masked(const Dev& d, i
   if (!d.has_mask) return false;
   const bool line = FAM == 2 || FAM == 4 || FAM == 5 || FAM == 7;
   if ((line ? d.mln : d.mpt)[f]) return true;
-  if constexpr (FAM == 3 || FAM == 4) return d.mpl[d.fgrp[FAM][i]] != 0;
+  if constexpr (FAM == 3 || FAM == 4 || FAM == 8) return d.mpl[d.fgrp[FAM][i]] != 0;
   if constexpr (FAM == 5) return d.mvp[d.fgrp[FAM][i]] != 0;
   return false;
 }

@@ -29,7 +29,7 @@ int slot_stride(int fam, int cd) {
 #define SS(F) (cd == 9 ? Slot<F, 9>::STRIDE : Slot<F, 6>::STRIDE)
   switch (fam) {
     case 1: return SS(1); case 2: return SS(2); case 3: return SS(3); case 4: return SS(4);
-    case 5: return SS(5); case 6: return SS(6); case 7: return SS(7);
+    case 5: return SS(5); case 6: return SS(6); case 7: return SS(7); case 8: return SS(8);
   }
 #undef SS
   return 0;
@@ -41,7 +41,7 @@ int slot_nc(int fam, int cd) {
   }
   return 0;
 }
-int slot_ng(int fam) { return fam == 3 || fam == 4 ? 3 : fam == 5 ? 2 : 0; }
+int slot_ng(int fam) { return fam == 3 || fam == 4 || fam == 8 ? 3 : fam == 5 ? 2 : 0; }
 int slot_nf(int fam) { return fam_is_line(fam) ? 4 : 3; }
 
 
@@ -201,6 +201,8 @@ template <int FAM> __device__ __forceinline__ void residual64(const Dev& d, int6
   if constexpr (FAM == 5) {
     const int g = d.fgrp[FAM][i];
     res_R5<double>(load_line<double>(ln + (int64_t)LN_STRIDE * f), load_vp<double>(vp + (int64_t)VP_STRIDE * g), r);
+  } else if constexpr (FAM == 8) {
+    res_R12<double>(pt + (int64_t)PT_STRIDE * f, load_plane<double>(pl + (int64_t)PL_STRIDE * d.fgrp[FAM][i]), r);
   } else {
     const int c = d.fcam[FAM][i];
     Cam<double> C = load_cam<double>(cam + (int64_t)CAM_STRIDE * c);
@@ -261,6 +263,9 @@ template <int FAM, typename T, int CD> __global__ __launch_bounds__(256) void k_
   if constexpr (FAM == 5) {
     const int g = d.fgrp[FAM][i];
     jac_R5<T>(load_line<T>(lnT + (int64_t)LN_STRIDE * f), load_vp<T>(vpT + (int64_t)VP_STRIDE * g), r, Jg, Jf);
+  } else if constexpr (FAM == 8) {
+    const T X[3] = {ptT[(int64_t)PT_STRIDE * f], ptT[(int64_t)PT_STRIDE * f + 1], ptT[(int64_t)PT_STRIDE * f + 2]};
+    jac_R12<T>(X, load_plane<T>(plT + (int64_t)PL_STRIDE * d.fgrp[FAM][i]), r, Jg, Jf);
   } else {
     const int c = d.fcam[FAM][i];
     Cam<T> C = load_cam<T>(camT + (int64_t)CAM_STRIDE * c);
@@ -372,6 +377,7 @@ void launch_linearize(const Dev& d, hipStream_t s) {
     if (d.fn[5]) k_lin<5, T, CD><<<nblk(d.fn[5], 256), 256, 0, s>>>(d);
     if (d.fn[6]) k_lin<6, T, CD><<<nblk(d.fn[6], 256), 256, 0, s>>>(d);
     if (d.fn[7]) k_lin<7, T, CD><<<nblk(d.fn[7], 256), 256, 0, s>>>(d);
+    if (d.fn[8]) k_lin<8, T, CD><<<nblk(d.fn[8], 256), 256, 0, s>>>(d);
   });
   launch_rel_linearize(d, s);
 }
@@ -417,8 +423,9 @@ __global__ __launch_bounds__(1024) void k_cost_final(const double* part, int n, 
 }
 
 void launch_cost(const Dev& d, bool candidate, hipStream_t s) {
-  // the angular terms (VP-line records, then the inter-group relations) take one
-  // contiguous range [x0, x1) of the partials, which E_pix leaves out
+  // the angular terms (VP-line records, then the inter-group relations) and the metric
+  // 3D point-to-plane records take one contiguous range [x0, x1) of the partials,
+  // which E_pix leaves out
   int off = 0, x0 = -1, x1 = 0;
   auto go = [&](int fam) {
     if (!d.fn[fam]) return;
@@ -432,6 +439,7 @@ void launch_cost(const Dev& d, bool candidate, hipStream_t s) {
       case 5: k_cost<5><<<nb, 256, 0, s>>>(d, candidate, d.red + off); break;
       case 6: k_cost<6><<<nb, 256, 0, s>>>(d, candidate, d.red + off); break;
       case 7: k_cost<7><<<nb, 256, 0, s>>>(d, candidate, d.red + off); break;
+      case 8: k_cost<8><<<nb, 256, 0, s>>>(d, candidate, d.red + off); break;
     }
     off += (int)nb;
     if (fam == 5) x1 = off;
@@ -441,6 +449,12 @@ void launch_cost(const Dev& d, bool candidate, hipStream_t s) {
     if (x0 < 0) x0 = off;
     launch_rel_cost(d, candidate, d.red + off, s);
     x1 = ++off;
+  }
+  // the 3D point-to-plane distances are metric, not pixels: in the same range
+  if (d.fn[8]) {
+    if (x0 < 0) x0 = off;
+    go(8);
+    x1 = off;
   }
   for (int fam = 6; fam <= 7; ++fam) go(fam);
   if (x0 < 0) x0 = x1 = 0;
@@ -478,6 +492,7 @@ template <typename T, int CD, int NF, typename A> __device__ __forceinline__ voi
     acc_feature<1, T, CD, 3>(d, f, V, g);
     acc_feature<3, T, CD, 3>(d, f, V, g);
     acc_feature<6, T, CD, 3>(d, f, V, g);
+    acc_feature<8, T, CD, 3>(d, f, V, g);
   } else {
     acc_feature<2, T, CD, 4>(d, f, V, g);
     acc_feature<4, T, CD, 4>(d, f, V, g);
@@ -812,10 +827,15 @@ template <typename T, int CD> __global__ __launch_bounds__(256) void k_grp_a(Dev
     T acc[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) acc[k] = 0;
-    if (d.fn[3])
+    // points of the plane: its plane-association records (R3) and 3D point-to-plane
+    // records (family 8); a point's records of either family may name other planes
+    if (d.fn[3] || d.fn[8])
       for (int j = d.plp_off[g] + threadIdx.x; j < d.plp_off[g + 1]; j += blockDim.x) {
         const int f = d.plp[j];
-        for (int64_t i = d.foff[3][f]; i < d.foff[3][f + 1]; ++i) grp_a_rec<3, T, CD, 3>(d, i, acc, acc + 6);
+        for (int64_t i = d.foff[3][f]; i < d.foff[3][f + 1]; ++i)
+          if (d.fgrp[3][i] == g) grp_a_rec<3, T, CD, 3>(d, i, acc, acc + 6);
+        for (int64_t i = d.foff[8][f]; i < d.foff[8][f + 1]; ++i)
+          if (d.fgrp[8][i] == g) grp_a_rec<8, T, CD, 3>(d, i, acc, acc + 6);
       }
     if (d.fn[4])
       for (int j = d.pll_off[g] + threadIdx.x; j < d.pll_off[g + 1]; j += blockDim.x) {
@@ -1021,11 +1041,14 @@ template <typename T, int CD> __global__ __launch_bounds__(256) void k_grp_b(Dev
     T acc[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) acc[k] = 0;
-    if (d.fn[3])
+    if (d.fn[3] || d.fn[8])
       for (int j = d.plp_off[g] + threadIdx.x; j < d.plp_off[g + 1]; j += blockDim.x) {
         const int f = d.plp[j];
         T W[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-        for (int64_t i = d.foff[3][f]; i < d.foff[3][f + 1]; ++i) addW_grp<3, T, CD, 3, 3>(d, i, W);
+        for (int64_t i = d.foff[3][f]; i < d.foff[3][f + 1]; ++i)
+          if (d.fgrp[3][i] == g) addW_grp<3, T, CD, 3, 3>(d, i, W);
+        for (int64_t i = d.foff[8][f]; i < d.foff[8][f + 1]; ++i)
+          if (d.fgrp[8][i] == g) addW_grp<8, T, CD, 3, 3>(d, i, W);
         pair_contrib<T, 3, 3>(d, f, W, acc, acc + 6);
       }
     if (d.fn[4])
@@ -1201,6 +1224,7 @@ template <typename T, int CD, int NF> __device__ __forceinline__ void mv_feature
     mv_first<1, T, CD, 3>(d, f, x, q);
     mv_first<3, T, CD, 3>(d, f, x, q);
     mv_first<6, T, CD, 3>(d, f, x, q);
+    mv_first<8, T, CD, 3>(d, f, x, q);
   } else {
     mv_first<2, T, CD, 4>(d, f, x, q);
     mv_first<4, T, CD, 4>(d, f, x, q);
@@ -1213,6 +1237,7 @@ template <typename T, int CD, int NF> __device__ __forceinline__ void mv_feature
     mv_second<1, T, CD, 3>(d, f, x, s, y);
     mv_second<3, T, CD, 3>(d, f, x, s, y);
     mv_second<6, T, CD, 3>(d, f, x, s, y);
+    mv_second<8, T, CD, 3>(d, f, x, s, y);
   } else {
     mv_second<2, T, CD, 4>(d, f, x, s, y);
     mv_second<4, T, CD, 4>(d, f, x, s, y);
@@ -1230,6 +1255,7 @@ template <typename T, int CD, int NF> __device__ __forceinline__ void mv_feature
     mv_first<1, T, CD, 3>(d, f, x, q);
     mv_first<3, T, CD, 3>(d, f, x, q);
     mv_first<6, T, CD, 3>(d, f, x, q);
+    mv_first<8, T, CD, 3>(d, f, x, q);
   } else {
     mv_first<2, T, CD, 4>(d, f, x, q);
     mv_first<4, T, CD, 4>(d, f, x, q);
@@ -1418,6 +1444,7 @@ __global__ __launch_bounds__(MV_THREADS) void k_mv_wave(Dev d, const double* don
         case 5: tile_phase_a<5, T, CD>(d, i, w4.y, w4.z, x, q, v, t, ac, ag); break;
         case 6: tile_phase_a<6, T, CD>(d, i, w4.y, w4.z, x, q, v, t, ac, ag); break;
         case 7: tile_phase_a<7, T, CD>(d, i, w4.y, w4.z, x, q, v, t, ac, ag); break;
+        case 8: tile_phase_a<8, T, CD>(d, i, w4.y, w4.z, x, q, v, t, ac, ag); break;
       }
     }
     // segmented inclusive scan over runs of equal lf (lanes are in feature
@@ -1467,6 +1494,7 @@ __global__ __launch_bounds__(MV_THREADS) void k_mv_wave(Dev d, const double* don
           case 5: tile_phase_c<5, T, CD>(v, t, ac, ag, s, ys); break;
           case 6: tile_phase_c<6, T, CD>(v, t, ac, ag, s, ys); break;
           case 7: tile_phase_c<7, T, CD>(v, t, ac, ag, s, ys); break;
+          case 8: tile_phase_c<8, T, CD>(v, t, ac, ag, s, ys); break;
         }
       } else {
         switch (fam) {
@@ -1477,6 +1505,7 @@ __global__ __launch_bounds__(MV_THREADS) void k_mv_wave(Dev d, const double* don
           case 5: tile_phase_c_reload<5, T, CD>(d, i, t, ac, ag, s, ys); break;
           case 6: tile_phase_c_reload<6, T, CD>(d, i, t, ac, ag, s, ys); break;
           case 7: tile_phase_c_reload<7, T, CD>(d, i, t, ac, ag, s, ys); break;
+          case 8: tile_phase_c_reload<8, T, CD>(d, i, t, ac, ag, s, ys); break;
         }
       }
     }
@@ -2221,6 +2250,7 @@ template <typename T, int CD, int NF> __device__ __forceinline__ void sz_feature
     sz_feat_family<1, T, CD, 3>(d, f, Zr, q);
     sz_feat_family<3, T, CD, 3>(d, f, Zr, q);
     sz_feat_family<6, T, CD, 3>(d, f, Zr, q);
+    sz_feat_family<8, T, CD, 3>(d, f, Zr, q);
   } else {
     sz_feat_family<2, T, CD, 4>(d, f, Zr, q);
     sz_feat_family<4, T, CD, 4>(d, f, Zr, q);
@@ -2316,6 +2346,7 @@ template <typename T, int CD> __global__ __launch_bounds__(256) void k_sz_feat_w
         case 5: sz_wave_q<5, T, CD>(d, i, w4.y, w4.z, Zr, q); break;
         case 6: sz_wave_q<6, T, CD>(d, i, w4.y, w4.z, Zr, q); break;
         case 7: sz_wave_q<7, T, CD>(d, i, w4.y, w4.z, Zr, q); break;
+        case 8: sz_wave_q<8, T, CD>(d, i, w4.y, w4.z, Zr, q); break;
       }
     }
     const int prev = __shfl_up(lf, 1, 64);
@@ -2510,13 +2541,23 @@ __global__ __launch_bounds__(256) void k_sz_grp(Dev d, const T* Zr, const T* sfp
     for (int k = 0; k < 3; ++k)
 #pragma unroll
       for (int q = 0; q < CPL; ++q) acc[k][q] = 0;
-    if (d.fn[3])
+    if (d.fn[3] || d.fn[8])
       for (int j = d.plp_off[g] + rs; j < d.plp_off[g + 1]; j += R) {
         const int f = d.plp[j];
         for (int64_t i = d.foff[3][f]; i < d.foff[3][f + 1]; ++i) {
+          if (d.fgrp[3][i] != g) continue;
           T zc[CD][CPL];
           z_cols<CD, CPL>(zr, CD * d.fcam[3][i], zc);
           sz_rec_cols<3, 1, T, CD>((const T*)d.frec[3] + i * Slot<3, CD>::STRIDE, zc, zg, sp + (int64_t)f * 3 * SZ_COLS, acc);
+        }
+        for (int64_t i = d.foff[8][f]; i < d.foff[8][f + 1]; ++i) {
+          if (d.fgrp[8][i] != g) continue;
+          T zc[CD][CPL];
+#pragma unroll
+          for (int k = 0; k < CD; ++k)
+#pragma unroll
+            for (int q = 0; q < CPL; ++q) zc[k][q] = 0;
+          sz_rec_cols<8, 1, T, CD>((const T*)d.frec[8] + i * Slot<8, CD>::STRIDE, zc, zg, sp + (int64_t)f * 3 * SZ_COLS, acc);
         }
       }
     if (d.fn[4])
@@ -2640,14 +2681,22 @@ template <typename T, int CD> __global__ __launch_bounds__(256) void k_det_grp(D
 #pragma unroll
     for (int k = 0; k < 3; ++k) zg[k][0] = x[e0 + k];
     double acc[3][1] = {{0}, {0}, {0}};
-    if (d.fn[3])
+    if (d.fn[3] || d.fn[8])
       for (int j = d.plp_off[g] + rs; j < d.plp_off[g + 1]; j += R) {
         const int f = d.plp[j];
         for (int64_t i = d.foff[3][f]; i < d.foff[3][f + 1]; ++i) {
+          if (d.fgrp[3][i] != g) continue;
           T zc[CD][1];
 #pragma unroll
           for (int k = 0; k < CD; ++k) zc[k][0] = x[CD * d.fcam[3][i] + k];
           sz_rec_cols<3, 1, T, CD>((const T*)d.frec[3] + i * Slot<3, CD>::STRIDE, zc, zg, sp + 3 * (int64_t)f, acc, 1);
+        }
+        for (int64_t i = d.foff[8][f]; i < d.foff[8][f + 1]; ++i) {
+          if (d.fgrp[8][i] != g) continue;
+          T zc[CD][1];
+#pragma unroll
+          for (int k = 0; k < CD; ++k) zc[k][0] = 0;
+          sz_rec_cols<8, 1, T, CD>((const T*)d.frec[8] + i * Slot<8, CD>::STRIDE, zc, zg, sp + 3 * (int64_t)f, acc, 1);
         }
       }
     if (d.fn[4])
@@ -2694,7 +2743,10 @@ template <typename T, int CD> static void launch_sz(const Dev& d, double lambda,
   T* sfl = (T*)d.szfl;
   const SzPanels P = sz_panels(d);
   // no VP 3-vector records: the gauge panel's s_f in closed form, no record sweep for it
-  const bool closed = d.fn[5] == 0;
+  // the closed form needs J z = 0 for the gauge directions: not so for the VP
+  // 3-vector (turns with the world) nor for the metric 3D point-to-plane distance
+  // (scales with the world)
+  const bool closed = d.fn[5] == 0 && d.fn[8] == 0;
   k_sz_rows<T><<<nblk(P.z * SZ_PANELS, 256), 256, 0, s>>>(d, Zr, closed ? 1 : 0);
   for (int pn = 0; pn < SZ_PANELS && sz_col(pn, 0) < d.coarse_k; ++pn) {
     T *zp = Zr + pn * P.z, *pp = sfp + pn * P.p, *lp = sfl + pn * P.l;
@@ -2766,6 +2818,7 @@ template <typename T, int CD, int NF> __device__ __forceinline__ void backsub_on
     mv_first<1, T, CD, 3>(d, f, x, q);
     mv_first<3, T, CD, 3>(d, f, x, q);
     mv_first<6, T, CD, 3>(d, f, x, q);
+    mv_first<8, T, CD, 3>(d, f, x, q);
   } else {
     mv_first<2, T, CD, 4>(d, f, x, q);
     mv_first<4, T, CD, 4>(d, f, x, q);
@@ -2787,6 +2840,7 @@ template <typename T, int CD, int NF> __device__ __forceinline__ void backsub_on
     bs_second<1, T, CD, 3>(d, f, x, h, jh2);
     bs_second<3, T, CD, 3>(d, f, x, h, jh2);
     bs_second<6, T, CD, 3>(d, f, x, h, jh2);
+    bs_second<8, T, CD, 3>(d, f, x, h, jh2);
   } else {
     bs_second<2, T, CD, 4>(d, f, x, h, jh2);
     bs_second<4, T, CD, 4>(d, f, x, h, jh2);
@@ -2877,6 +2931,7 @@ template <typename T, int CD> __global__ __launch_bounds__(256) void k_backsub_w
         case 5: tile_phase_a<5, T, CD>(d, i, w4.y, w4.z, x, q, v, t, ac, ag); break;
         case 6: tile_phase_a<6, T, CD>(d, i, w4.y, w4.z, x, q, v, t, ac, ag); break;
         case 7: tile_phase_a<7, T, CD>(d, i, w4.y, w4.z, x, q, v, t, ac, ag); break;
+        case 8: tile_phase_a<8, T, CD>(d, i, w4.y, w4.z, x, q, v, t, ac, ag); break;
       }
     }
     const int prev = __shfl_up(lf, 1, 64);
@@ -2923,6 +2978,7 @@ template <typename T, int CD> __global__ __launch_bounds__(256) void k_backsub_w
           case 5: jh2 += bs_record<5, T, CD>(v, t, h); break;
           case 6: jh2 += bs_record<6, T, CD>(v, t, h); break;
           case 7: jh2 += bs_record<7, T, CD>(v, t, h); break;
+          case 8: jh2 += bs_record<8, T, CD>(v, t, h); break;
         }
       } else {
         switch (fam) {
@@ -2933,6 +2989,7 @@ template <typename T, int CD> __global__ __launch_bounds__(256) void k_backsub_w
           case 5: jh2 += bs_record_reload<5, T, CD>(d, i, t, h); break;
           case 6: jh2 += bs_record_reload<6, T, CD>(d, i, t, h); break;
           case 7: jh2 += bs_record_reload<7, T, CD>(d, i, t, h); break;
+          case 8: jh2 += bs_record_reload<8, T, CD>(d, i, t, h); break;
         }
       }
     }

@@ -10,6 +10,7 @@
 //   R5 VP-line  (d/|d|) x v, norm = |sin theta|                    (Eq. 6, App. B)
 //   R6 point -> observed line distance (undistorted)              (Eq. 11)
 //   R7 observed point -> projected line distance (undistorted)    (Eq. 12)
+//   R12 point -> plane metric distance n . X + w (3D formulation baseline)
 //
 // Conventions: X_c = R X + t; pose tangent (dtheta, dt) acts on the camera
 // frame, X_c <- Exp(dtheta) X_c + dt, so dX_c/dtheta_k = e_k x X_c and
@@ -420,6 +421,19 @@ template <typename S> BA_HD void jac_R5(const Line<S>& L, const Vp<S>& V, S* r, 
 
 // ---- R4 -------------------------------------------------------------------
 // plane projection of a Pluecker line (App. B) and its partial derivatives
+// R12: the signed metric distance n . X + w of a point to a plane (the 3D
+// formulation the paper compares against); plane tangent (b1, b2 of the normal, w)
+template <typename S> BA_HD void res_R12(const S* X, const Plane<S>& g, S* r) { r[0] = dot3(g.n, X) + g.w; }
+
+template <typename S> BA_HD void jac_R12(const S* X, const Plane<S>& g, S* r, S* Jg, S* Jf) {
+  r[0] = dot3(g.n, X) + g.w;
+  Jg[0] = dot3(g.b1, X);
+  Jg[1] = dot3(g.b2, X);
+  Jg[2] = S(1);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) Jf[k] = g.n[k];
+}
+
 template <typename S> struct PlaneLine {
   S d2[3], m2[3];
   S Ddd[3][3];      // d d' / d d

@@ -7,4 +7,5 @@ from .scene import (CONFIGS, DEFAULT_LOSS, OBS_POINT, OBS_LINE, ASSOC_PLANE_POIN
                     ASSOC_PLANE_LINE, ASSOC_VP_LINE, ASSOC_JUNCTION, REL_VP_ORTHO, REL_VP_PARALLEL,
                     REL_PLANE_ORTHO, REL_PLANE_PARALLEL, RELATION_KINDS, LOSS_TRIVIAL,
                     LOSS_HUBER, LOSS_CAUCHY, make_scene, scene_counts, small_config, manhattan_config,
-                    config_seed, quaternion_to_matrix, matrix_to_quaternion)
+                    config_seed, quaternion_to_matrix, matrix_to_quaternion, ASSOC_PLANE_POINT_3D,
+                    plane_3d_scene)

@@ -31,6 +31,9 @@ OBS_POINT, OBS_LINE, ASSOC_PLANE_POINT, ASSOC_PLANE_LINE, ASSOC_VP_LINE, ASSOC_J
 # Inter-group relations (a, b = two VPs or two planes): orthogonal or parallel directions.
 REL_VP_ORTHO, REL_VP_PARALLEL, REL_PLANE_ORTHO, REL_PLANE_PARALLEL = range(6, 10)
 RELATION_KINDS = (REL_VP_ORTHO, REL_VP_PARALLEL, REL_PLANE_ORTHO, REL_PLANE_PARALLEL)
+# 3D point-to-plane association (the 3D formulation the paper compares against):
+# a = plane, b = point
+ASSOC_PLANE_POINT_3D = 10
 
 # Per-kind default (loss kind, scale, weight).  Weights and the VP scale are the
 # paper's (supplementary Section C: VP weight 5e3 with Cauchy scale 0.2; group
@@ -49,6 +52,8 @@ DEFAULT_LOSS = {
 # Cauchy scale (the paper gives none of their own).
 for _k in RELATION_KINDS:
     DEFAULT_LOSS[_k] = (LOSS_CAUCHY, 0.2, 5.0e3)
+# the 3D penalty: squared metric distance times a weight (the paper sweeps 1 .. 1000)
+DEFAULT_LOSS[ASSOC_PLANE_POINT_3D] = (LOSS_TRIVIAL, 1.0, 100.0)
 
 # Workload sizes.  Keys:
 #   n_cams, half (cube half extents), radius (camera sphere), K (neighbour pool)
@@ -634,3 +639,20 @@ def manhattan_config():
     Manhattan VPs and 2 Atlanta ones, 6 planes each related to 2 others."""
     return small_config(n_cams=8, n_points=40, n_lines=12, n_planes=6, n_vps=5, plane_points=12,
                         plane_lines=6, vp_lines=6, plane_relations=2)
+
+
+def plane_3d_scene(scene, weight=100.0, keep_2d=False):
+    """The same scene with its plane-point associations in the 3D formulation
+    (kind ASSOC_PLANE_POINT_3D, trivial loss with the given weight) instead of, or
+    with keep_2d beside, the pixel-space ones."""
+    import copy
+    out = copy.copy(scene)
+    out["obs"] = dict(scene["obs"])
+    out["loss"] = dict(scene["loss"])
+    g, j, _ = scene["obs"][ASSOC_PLANE_POINT]
+    out["obs"][ASSOC_PLANE_POINT_3D] = (np.array(g), np.array(j), None)
+    out["loss"][ASSOC_PLANE_POINT_3D] = (LOSS_TRIVIAL, 1.0, float(weight))
+    if not keep_2d:
+        z = np.zeros(0, dtype=np.int32)
+        out["obs"][ASSOC_PLANE_POINT] = (z, z, None)
+    return out

@@ -25,6 +25,7 @@ int eval(int fam, const double* cam, const double* pt, const double* ln, const d
     case 5: jac_R5<S>(L, V, rr, jg, jf); rows = 3; ng = 2; nf = 4; break;
     case 6: jac_R6<S, CD>(C, X, m, rr, jc, jf); rows = 1; nc = CamCols<CD>::PT; nf = 3; break;
     case 7: jac_R7<S, CD>(C, L, m, rr, jc, jf); rows = 1; nc = CamCols<CD>::LN; nf = 4; break;
+    case 12: jac_R12<S>(X, P, rr, jg, jf); rows = 1; ng = 3; nf = 3; break;
     default: return -1;
   }
   for (int i = 0; i < rows; ++i) {
@@ -54,6 +55,7 @@ void res(int fam, const double* cam, const double* pt, const double* ln, const d
     case 5: res_R5<S>(L, V, rr); break;
     case 6: res_R6<S>(C, X, m, rr); break;
     case 7: res_R7<S>(C, L, m, rr); break;
+    case 12: res_R12<S>(X, P, rr); break;
   }
   for (int k = 0; k < 4; ++k) r[k] = rr[k];
 }

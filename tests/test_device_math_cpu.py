@@ -1,6 +1,7 @@
 """The library's analytic residual / Jacobian templates, compiled for the host,
 against the oracle's complex-step Jacobians of the same residual definitions
-(Sec. 3.1 Eq. 1, 3.2 Eq. 4, 3.3 Eqs. 6-8, 3.4 Eqs. 11-12).
+(Sec. 3.1 Eq. 1, 3.2 Eq. 4, 3.3 Eqs. 6-8, 3.4 Eqs. 11-12, and the 3D point-to-plane
+distance of the 3D formulation).
 
 FP64 instantiation: 1e-9 relative.  FP32 instantiation: the per-observation
 bar of 1e-4 relative (residual relative to max(|r|, 1 px); Jacobian relative
@@ -13,7 +14,7 @@ import subprocess
 import numpy as np
 import pytest
 
-from scenegen import make_scene, small_config
+from scenegen import make_scene, small_config, plane_3d_scene
 from oracle import lm, model
 from tests import layout
 
@@ -45,14 +46,14 @@ def _eval(lib, fam, cd, fp64, st, rec, i, cx, cy):
     meas = layout.shifted_meas(fam, rec, i, cx, cy)
     r, Jc, Jg, Jf = np.zeros(4), np.zeros(4 * 9), np.zeros(4 * 3), np.zeros(4 * 4)
     bufs = [cam, pt, ln, pl, vp, meas, r, Jc, Jg, Jf]
-    rows = lib.mc_eval(int(fam[1]), cd, fp64, *[_p(b) for b in bufs[:6]], *[
+    rows = lib.mc_eval(int(fam[1:]), cd, fp64, *[_p(b) for b in bufs[:6]], *[
         b.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) for b in bufs[6:]])
     return rows, r[:rows], Jc.reshape(4, 9)[:rows, :cd], Jg.reshape(4, 3)[:rows], Jf.reshape(4, 4)[:rows]
 
 
 @pytest.fixture(scope="module")
 def setup():
-    s = make_scene(small_config(n_cams=8), seed=31)
+    s = plane_3d_scene(make_scene(small_config(n_cams=8), seed=31), keep_2d=True)
     prob = lm.Problem(s)
     st = prob.state0()
     st.cam_k1 = st.cam_k1 + 0.06

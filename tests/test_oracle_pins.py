@@ -11,7 +11,7 @@ import os
 import numpy as np
 import pytest
 
-from scenegen import make_scene, small_config, manhattan_config, scene_counts, ASSOC_JUNCTION, OBS_POINT, OBS_LINE
+from scenegen import make_scene, small_config, manhattan_config, scene_counts, ASSOC_JUNCTION, OBS_POINT, OBS_LINE, plane_3d_scene
 from oracle import lm, model
 from oracle.records import expand
 
@@ -39,7 +39,8 @@ def _retract_one(st, prob, block, i, k, h):
 
 @pytest.fixture(scope="module")
 def tiny():
-    s = make_scene(small_config(), seed=11)
+    """Every family of Sec. 3 plus the 3D point-to-plane records of the 3D formulation."""
+    s = plane_3d_scene(make_scene(small_config(), seed=11), keep_2d=True)
     prob = lm.Problem(s)
     return s, prob
 
