@@ -47,13 +47,14 @@ class Problem:
         self.loss = {f: loss_of(scene, f) for f in FAMILY_ORDER}
         nc, npt, nln = len(scene["cameras"]), len(scene["points"]), len(scene["lines"])
         npl, nvp = len(scene["planes"]), len(scene["vps"])
-        self.n = dict(cam=nc, pt=npt, ln=nln, pl=npl, vp=nvp)
+        nsh = len(scene["shapes"]["type"]) if scene.get("shapes") is not None else 0
+        self.n = dict(cam=nc, pt=npt, ln=nln, pl=npl, vp=nvp, sh=nsh)
         cd = self.camera_dof
-        self.dof = dict(cam=cd, pt=3, ln=4, pl=3, vp=2)
-        # parameter ordering: A = cameras, planes, vps ; F = points, lines
+        self.dof = dict(cam=cd, pt=3, ln=4, pl=3, vp=2, sh=model.SHAPE_DOF)
+        # parameter ordering: A = cameras, planes, vps, shapes ; F = points, lines
         self.off = {}
         o = 0
-        for b in ("cam", "pl", "vp"):
+        for b in ("cam", "pl", "vp", "sh"):
             self.off[b] = o
             o += self.n[b] * self.dof[b]
         self.nA = o
@@ -72,14 +73,15 @@ class Problem:
     def split(self, h):
         """Full step vector -> per-block arrays for State.retract."""
         out = {}
-        for b in ("cam", "pl", "vp", "pt", "ln"):
+        for b in ("cam", "pl", "vp", "sh", "pt", "ln"):
             o = self.off[b]
             out[b] = h[o:o + self.n[b] * self.dof[b]]
         return out
 
     def retract(self, state, h):
         p = self.split(h)
-        return state.retract(p["cam"], p["pt"], p["ln"], p["pl"], p["vp"], camera_dof=self.camera_dof)
+        return state.retract(p["cam"], p["pt"], p["ln"], p["pl"], p["vp"], camera_dof=self.camera_dof,
+                             dsh=p["sh"])
 
 
 # ---------------------------------------------------------------------------
@@ -295,9 +297,9 @@ def model_decrease(lin, h):
 
 
 def diag_blocks(prob, M):
-    """Diagonal blocks of an A x A matrix: cameras, planes, vps."""
+    """Diagonal blocks of an A x A matrix: cameras, planes, vps, shapes."""
     out = {}
-    for b in ("cam", "pl", "vp"):
+    for b in ("cam", "pl", "vp", "sh"):
         d, o, n = prob.dof[b], prob.off[b], prob.n[b]
         out[b] = np.stack([M[o + i * d:o + (i + 1) * d, o + i * d:o + (i + 1) * d] for i in range(n)]) \
             if n else np.zeros((0, d, d))

@@ -33,6 +33,7 @@ import numpy as np
 
 CAM_DOF_MAX = 9
 POINT_DOF, LINE_DOF, PLANE_DOF, VP_DOF = 3, 4, 3, 2
+SHAPE_DOF = 9  # tangent coordinates of every surface group (oracle.shapes)
 
 
 # ---------------------------------------------------------------------------
@@ -211,16 +212,18 @@ def observed_line(meas4):
 class State:
     """FP64 parameters of a holistic BA problem."""
 
-    def __init__(self, cam_R, cam_t, cam_f, cam_k1, cam_k2, pts, line_U, line_w, pl_n, pl_w, vp):
+    def __init__(self, cam_R, cam_t, cam_f, cam_k1, cam_k2, pts, line_U, line_w, pl_n, pl_w, vp, sh=None):
+        from .shapes import Shapes
         self.cam_R, self.cam_t = cam_R, cam_t
         self.cam_f, self.cam_k1, self.cam_k2 = cam_f, cam_k1, cam_k2
         self.pts = pts
         self.line_U, self.line_w = line_U, line_w
         self.pl_n, self.pl_w = pl_n, pl_w
         self.vp = vp
+        self.sh = Shapes.empty() if sh is None else sh  # surface groups (oracle.shapes)
 
     @staticmethod
-    def from_arrays(cameras, points, lines, planes, vps):
+    def from_arrays(cameras, points, lines, planes, vps, shapes=None):
         from scenegen import quaternion_to_matrix  # input format conversion only
         cameras = np.asarray(cameras, dtype=np.float64).reshape(-1, 10)
         R = quaternion_to_matrix(cameras[:, 0:4]) if len(cameras) else np.zeros((0, 3, 3))
@@ -228,31 +231,37 @@ class State:
         U, w = line_from_points(lines[:, 0:3], lines[:, 3:6])
         planes = np.asarray(planes, dtype=np.float64).reshape(-1, 4)
         vps = np.asarray(vps, dtype=np.float64).reshape(-1, 3)
+        from .shapes import Shapes
+        sh = None if shapes is None else Shapes.from_abi(shapes["type"], shapes["params"])
         return State(R, cameras[:, 4:7].copy(), cameras[:, 7].copy(), cameras[:, 8].copy(),
                      cameras[:, 9].copy(), np.asarray(points, dtype=np.float64).reshape(-1, 3).copy(),
-                     U, w, planes[:, 0:3].copy(), planes[:, 3].copy(), vps.copy())
+                     U, w, planes[:, 0:3].copy(), planes[:, 3].copy(), vps.copy(), sh)
 
     @staticmethod
     def from_scene(scene, gt=False):
         sfx = "_gt" if gt else ""
         return State.from_arrays(scene["cameras" + sfx], scene["points" + sfx], scene["lines" + sfx],
-                                 scene["planes" + sfx], scene["vps" + sfx])
+                                 scene["planes" + sfx], scene["vps" + sfx], scene.get("shapes" + sfx))
 
     def copy(self):
         return State(*(a.copy() for a in (self.cam_R, self.cam_t, self.cam_f, self.cam_k1, self.cam_k2,
-                                          self.pts, self.line_U, self.line_w, self.pl_n, self.pl_w, self.vp)))
+                                          self.pts, self.line_U, self.line_w, self.pl_n, self.pl_w, self.vp)),
+                     self.sh.copy())
 
     @property
     def counts(self):
         return dict(cameras=len(self.cam_R), points=len(self.pts), lines=len(self.line_U),
-                    planes=len(self.pl_n), vps=len(self.vp))
+                    planes=len(self.pl_n), vps=len(self.vp), shapes=len(self.sh))
 
     def plucker(self):
         return line_plucker(self.line_U, self.line_w)
 
-    def retract(self, dcam, dpt, dln, dpl, dvp, camera_dof=9):
-        """x [+] h with the exact manifold updates listed in the module docstring."""
+    def retract(self, dcam, dpt, dln, dpl, dvp, camera_dof=9, dsh=None):
+        """x [+] h with the exact manifold updates listed in the module docstring
+        (shapes: oracle.shapes)."""
         s = self.copy()
+        if len(s.sh) and dsh is not None:
+            s.sh = self.sh.retract(dsh)
         if len(s.cam_R):
             dcam = np.asarray(dcam).reshape(len(s.cam_R), camera_dof)
             E = so3_exp(dcam[:, 0:3])
@@ -301,8 +310,11 @@ class Gathered:
     (kind "vp" or "pl", index a, index b)): their directions (the VP, or the
     plane normal) and sphere tangent bases are gathered as ua, Ba, ub, Bb."""
 
-    def __init__(self, state: State, cam=None, pt=None, ln=None, pl=None, vp=None, rel=None):
+    def __init__(self, state: State, cam=None, pt=None, ln=None, pl=None, vp=None, rel=None, sh=None):
         c = np.complex128
+        if sh is not None:
+            from .shapes import GatheredShapes
+            self.sh = GatheredShapes(state.sh, sh)
         if rel is not None:
             kind, ia, ib = rel
             src = state.vp if kind == "vp" else state.pl_n
@@ -362,6 +374,8 @@ class Gathered:
                 self.wp = self.wp + h
         elif block == "vp":
             self.v = self.v + h * self.Bv[:, :, k]
+        elif block == "sh":
+            self.sh.perturb(k, h)
         elif block in ("ga", "gb"):
             # a relation's group: the direction moves with the first two tangent
             # coordinates; a plane's third (the offset w) leaves it unchanged
@@ -427,6 +441,31 @@ def res_plane_point_3d(g: Gathered, rec, cx, cy):
     return (dot(g.n, g.X) + g.wp)[..., None]
 
 
+def res_shape_point(g: Gathered, rec, cx, cy):
+    """R13, Sec. 3.3 after Eq. 8 (any group with a projection operator) with the
+    projections of App. B: pi_p(C_i, X_j) - pi_p(C_i, Proj_G(X_j)) for a sphere,
+    cylinder, cone, ellipsoid or cuboid (oracle.shapes)."""
+    from .shapes import project_point
+    Xp = project_point(g.sh, g.X)
+    return (project_distorted(g.R, g.t, g.f, g.k1, g.k2, g.X, cx, cy)
+            - project_distorted(g.R, g.t, g.f, g.k1, g.k2, Xp, cx, cy))
+
+
+def res_shape_line(g: Gathered, rec, cx, cy):
+    """R14: Eq. 8 for a line on a cuboid (App. B): the line is projected onto the
+    plane of the face chosen for it (oracle.shapes) with the plane-line
+    projection; a line nearly orthogonal to that face contributes zero, as in R4."""
+    from .shapes import cuboid_line_plane
+    d, m = g.plucker()
+    n, w = cuboid_line_plane(g.sh, d, m)
+    d2, m2 = plane_project_line(d, m, n, w)
+    l1 = image_line(g.R, g.t, g.f, d, m, cx, cy)
+    l2 = image_line(g.R, g.t, g.f, d2, m2, cx, cy)
+    r = rho4(l1, rec["meas"]) - rho4(l2, rec["meas"])
+    deg = np.real(dot(d2, d2)) < 1e-12 * np.real(dot(d, d))
+    return np.where(deg[:, None], 0.0, r)
+
+
 def res_point_to_line(g: Gathered, rec, cx, cy):
     """R6, Sec. 3.4 Eq. 11: d(pi-bar(C_i, X_j), l_ik), observed line l_ik."""
     x = project_pinhole(g.R, g.t, g.f, g.X, cx, cy)
@@ -470,10 +509,12 @@ FAMILIES = {
     "R10": (res_rel_ortho, 1, [("pl", "ga", 3), ("pl", "gb", 3)]),       # plane _|_ plane
     "R11": (res_rel_parallel, 3, [("pl", "ga", 3), ("pl", "gb", 3)]),    # plane || plane
     "R12": (res_plane_point_3d, 1, [("pt", "pt", 3), ("pl", "pl", 3)]),  # 3D point-to-plane
+    "R13": (res_shape_point, 2, [("cam", "cam", 9), ("pt", "pt", 3), ("sh", "sh", 9)]),  # point on a shape
+    "R14": (res_shape_line, 4, [("cam", "cam", 9), ("ln", "ln", 4), ("sh", "sh", 9)]),  # line on a cuboid
 }
-FAMILY_ORDER = ["R1", "R2", "R3", "R4", "R5", "R6", "R7", "R8", "R9", "R10", "R11", "R12"]
+FAMILY_ORDER = ["R1", "R2", "R3", "R4", "R5", "R6", "R7", "R8", "R9", "R10", "R11", "R12", "R13", "R14"]
 RELATION_FAMILIES = ("R8", "R9", "R10", "R11")
-PIXEL_FAMILIES = ("R1", "R2", "R3", "R4", "R6", "R7")  # R5 and the relations are angular (Sec. 3.5)
+PIXEL_FAMILIES = ("R1", "R2", "R3", "R4", "R6", "R7", "R13", "R14")  # R5 and the relations are angular (Sec. 3.5)
 
 
 def gather(state, rec, fam):

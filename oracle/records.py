@@ -21,7 +21,12 @@ The visibility rules are the paper's:
   parallel, plane-plane orthogonal, plane-plane parallel (Sec. 3.2, the
   inter-group relations between VP pairs and plane-normal pairs);
 * R12 one record per 3D point-to-plane association (g, j): the metric
-  distance of the 3D formulation the paper compares against.
+  distance of the 3D formulation the paper compares against;
+* R13 one record per shape-point association (s, j) and per view i that
+  observes the point, like R3 with the shape's projection (Sec. 3.3 after
+  Eq. 8, App. B);
+* R14 one record per shape-line association (s, k) (a cuboid) and per view i
+  that observes the line, with that view's observed endpoints, like R4.
 
 Each family is a dict of equally long arrays; ``key`` gives a record's
 identity for matching against another implementation:
@@ -33,14 +38,14 @@ import numpy as np
 
 from scenegen import (OBS_POINT, OBS_LINE, ASSOC_PLANE_POINT, ASSOC_PLANE_LINE, ASSOC_VP_LINE,
                       ASSOC_JUNCTION, REL_VP_ORTHO, REL_VP_PARALLEL, REL_PLANE_ORTHO, REL_PLANE_PARALLEL,
-                      ASSOC_PLANE_POINT_3D)
+                      ASSOC_PLANE_POINT_3D, ASSOC_SHAPE_POINT, ASSOC_SHAPE_LINE)
 
 FAMILY_KIND = {"R1": OBS_POINT, "R2": OBS_LINE, "R3": ASSOC_PLANE_POINT, "R4": ASSOC_PLANE_LINE,
                "R5": ASSOC_VP_LINE, "R6": ASSOC_JUNCTION, "R7": ASSOC_JUNCTION,
                "R8": REL_VP_ORTHO, "R9": REL_VP_PARALLEL, "R10": REL_PLANE_ORTHO, "R11": REL_PLANE_PARALLEL,
-               "R12": ASSOC_PLANE_POINT_3D}
+               "R12": ASSOC_PLANE_POINT_3D, "R13": ASSOC_SHAPE_POINT, "R14": ASSOC_SHAPE_LINE}
 FAMILY_ID = {"R1": 1, "R2": 2, "R3": 3, "R4": 4, "R5": 5, "R6": 6, "R7": 7, "R8": 8, "R9": 9, "R10": 10, "R11": 11,
-             "R12": 12}
+             "R12": 12, "R13": 13, "R14": 14}
 
 
 def _views_of(feat_of_obs, n_feat):
@@ -111,6 +116,15 @@ def expand(scene) -> dict:
     # R12: one record per 3D point-to-plane association (g, j), no camera
     g, j, _ = obs.get(ASSOC_PLANE_POINT_3D, (np.zeros(0), np.zeros(0), None))
     recs["R12"] = dict(pt=np.asarray(j, np.int64), pl=np.asarray(g, np.int64))
+    # R13 / R14: surface groups, one record per association and view of the feature
+    g, j, _ = obs.get(ASSOC_SHAPE_POINT, (np.zeros(0), np.zeros(0), None))
+    g, j = np.asarray(g, np.int64), np.asarray(j, np.int64)
+    a, o = _expand(j, poff, pord)
+    recs["R13"] = dict(cam=pc[o], pt=j[a], sh=g[a])
+    g, k, _ = obs.get(ASSOC_SHAPE_LINE, (np.zeros(0), np.zeros(0), None))
+    g, k = np.asarray(g, np.int64), np.asarray(k, np.int64)
+    a, o = _expand(k, loff, lord)
+    recs["R14"] = dict(cam=lc[o], ln=k[a], sh=g[a], meas=lm[o])
     return recs
 
 
@@ -136,6 +150,10 @@ def record_keys(recs) -> dict:
             k = (r["cam"], r["ln"], r["pt"])
         elif fam == "R12":
             k = (neg, r["pt"], r["pl"])
+        elif fam == "R13":
+            k = (r["cam"], r["pt"], r["sh"])
+        elif fam == "R14":
+            k = (r["cam"], r["ln"], r["sh"])
         else:  # relations: (-1, group a, group b)
             k = (neg, r["ga"], r["gb"])
         out[fam] = np.stack([np.full(n, FAMILY_ID[fam], dtype=np.int64), *k], axis=1)

@@ -54,6 +54,13 @@ for _k in RELATION_KINDS:
     DEFAULT_LOSS[_k] = (LOSS_CAUCHY, 0.2, 5.0e3)
 # the 3D penalty: squared metric distance times a weight (the paper sweeps 1 .. 1000)
 DEFAULT_LOSS[ASSOC_PLANE_POINT_3D] = (LOSS_TRIVIAL, 1.0, 100.0)
+# Surface groups beyond planes (App. B): sphere, cylinder, cone, ellipsoid, cuboid;
+# associations a = shape, b = point (any type) or line (cuboids).  Their group-induced
+# residuals take the plane associations' losses.
+SHAPE_SPHERE, SHAPE_CYLINDER, SHAPE_CONE, SHAPE_ELLIPSOID, SHAPE_CUBOID = range(5)
+ASSOC_SHAPE_POINT, ASSOC_SHAPE_LINE = 11, 12
+DEFAULT_LOSS[ASSOC_SHAPE_POINT] = DEFAULT_LOSS[ASSOC_PLANE_POINT]
+DEFAULT_LOSS[ASSOC_SHAPE_LINE] = DEFAULT_LOSS[ASSOC_PLANE_LINE]
 
 # Workload sizes.  Keys:
 #   n_cams, half (cube half extents), radius (camera sphere), K (neighbour pool)

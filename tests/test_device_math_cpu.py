@@ -62,7 +62,8 @@ def setup():
 
 
 @pytest.mark.parametrize("cd", [9, 6])
-@pytest.mark.parametrize("fam", [f for f in model.FAMILY_ORDER if f not in model.RELATION_FAMILIES])
+@pytest.mark.parametrize("fam", [f for f in model.FAMILY_ORDER
+                                 if f not in model.RELATION_FAMILIES and f not in ("R13", "R14")])
 def test_device_math_matches_oracle(setup, fam, cd):
     prob, st, lib = setup
     rec = prob.recs[fam]

@@ -11,7 +11,8 @@ import os
 import numpy as np
 import pytest
 
-from scenegen import make_scene, small_config, manhattan_config, scene_counts, ASSOC_JUNCTION, OBS_POINT, OBS_LINE, plane_3d_scene
+from scenegen import (make_scene, small_config, manhattan_config, scene_counts, ASSOC_JUNCTION, OBS_POINT, OBS_LINE,
+                      plane_3d_scene, add_shapes)
 from oracle import lm, model
 from oracle.records import expand
 
@@ -21,26 +22,27 @@ GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 def _zero_steps(prob):
     n = prob.n
     return dict(cam=np.zeros((n["cam"], 9)), pt=np.zeros((n["pt"], 3)), ln=np.zeros((n["ln"], 4)),
-                pl=np.zeros((n["pl"], 3)), vp=np.zeros((n["vp"], 2)))
+                pl=np.zeros((n["pl"], 3)), vp=np.zeros((n["vp"], 2)), sh=np.zeros((n["sh"], 9)))
 
 
 def _retract_block(st, prob, block, k, h):
     d = _zero_steps(prob)
     d[block][:, k] = h
-    return st.retract(d["cam"], d["pt"], d["ln"], d["pl"], d["vp"])
+    return st.retract(d["cam"], d["pt"], d["ln"], d["pl"], d["vp"], dsh=d["sh"])
 
 
 def _retract_one(st, prob, block, i, k, h):
     """Move only entity i of `block` along tangent coordinate k."""
     d = _zero_steps(prob)
     d[block][i, k] = h
-    return st.retract(d["cam"], d["pt"], d["ln"], d["pl"], d["vp"])
+    return st.retract(d["cam"], d["pt"], d["ln"], d["pl"], d["vp"], dsh=d["sh"])
 
 
 @pytest.fixture(scope="module")
 def tiny():
-    """Every family of Sec. 3 plus the 3D point-to-plane records of the 3D formulation."""
-    s = plane_3d_scene(make_scene(small_config(), seed=11), keep_2d=True)
+    """Every family of Sec. 3 plus the 3D point-to-plane records of the 3D formulation
+    and the surface groups of App. B."""
+    s = add_shapes(plane_3d_scene(make_scene(small_config(), seed=11), keep_2d=True), seed=12)
     prob = lm.Problem(s)
     return s, prob
 
