@@ -33,6 +33,7 @@
  *    with m = p x d for p on the line (normalised Pluecker coordinates).
  *  - plane    (4): nx ny nz w with |n| = 1 and n . x + w = 0 (App. B).
  *  - vp       (3): unit direction (App. B).
+ *  - shape   (16): a surface group of App. B, see ba_add_shapes.
  */
 #ifndef BA_H
 #define BA_H
@@ -103,8 +104,38 @@ typedef enum {
    * no camera.  Default loss: trivial, weight 100 (the paper sweeps 1 .. 1000); left out
    * of E_pix (metric, not pixels).  Residual family 12.  A point may carry it for several
    * planes; it may carry a BA_ASSOC_PLANE_POINT association too. */
-  BA_ASSOC_PLANE_POINT_3D = 10 /* a = plane, b = point; meas = NULL */
+  BA_ASSOC_PLANE_POINT_3D = 10, /* a = plane, b = point; meas = NULL */
+  /* Surface groups beyond planes and VPs (App. B; added with ba_add_shapes): the
+   * group-induced reprojection error of Sec. 3.3 with the shape's projection operator,
+   * one record per view of the member, like the plane associations.  A point may be on
+   * at most one shape, a line on at most one cuboid (the other types constrain points
+   * only).  Default loss: that of the plane associations (Cauchy 1 px, weight 0.5).
+   * Residual families 13 (point, 2 rows) and 14 (line, 4 rows). */
+  BA_ASSOC_SHAPE_POINT = 11, /* a = shape, b = point; meas = NULL */
+  BA_ASSOC_SHAPE_LINE = 12   /* a = shape (a cuboid), b = line; meas = NULL */
 } ba_kind;
+
+/* Surface group types (App. B, the table of group types; positive quantities are
+ * optimised in log space) and their 16-double parameter records (unused entries zero):
+ *  - SPHERE    (4 dof): centre c (3), radius r.  A point X goes to c + r (X - c)/|X - c|.
+ *  - CYLINDER  (5 dof): axis direction (3, any length), a point on the axis (3), radius r;
+ *    the axis is optimised in the orthonormal Pluecker form of the lines.  A point keeps
+ *    its position along the axis and goes radially to distance r from it.  Output: the
+ *    unit direction and the foot of the perpendicular from the origin.
+ *  - CONE      (6 dof): apex A (3), axis direction (3), half-angle alpha in (0, pi/2).  A
+ *    point goes to its foot on the generatrix in the half-plane through the axis and
+ *    the point (along the normal of the generatrix).
+ *  - ELLIPSOID (9 dof): rotation R (row-major 9, local to world, orthonormal), centre c
+ *    (3), semi-axes s (3).  A point goes to c + R (s * z / |z|), z = R^T (X - c) / s
+ *    (the scaled-radial projection).
+ *  - CUBOID    (9 dof): rotation R (row-major 9), face offsets e_0 .. e_5: face i is the
+ *    plane n_i . x + e_i = 0 with outward normal n_i = (-1)^i R e_{floor(i/2)}.  A point
+ *    goes to the face of smallest |n_i . X + e_i|; a line to the face nearest to its
+ *    point closest to the cuboid's centre, by the plane-line projection (App. B).
+ * Every shape takes 9 entries of the reduced system (after the VPs); a type with fewer
+ * degrees of freedom leaves the rest at zero step. */
+typedef enum { BA_SHAPE_SPHERE = 0, BA_SHAPE_CYLINDER = 1, BA_SHAPE_CONE = 2, BA_SHAPE_ELLIPSOID = 3,
+               BA_SHAPE_CUBOID = 4 } ba_shape_type;
 
 typedef enum { BA_LOSS_TRIVIAL = 0, BA_LOSS_HUBER = 1, BA_LOSS_CAUCHY = 2 } ba_loss_kind;
 
@@ -299,6 +330,16 @@ ba_status ba_lm_step(ba_handle *h, const ba_solve_options *opt, ba_step_report *
  * BA_E_NOT_CONVERGED (parameters and summary still valid). */
 ba_status ba_solve(ba_handle *h, const ba_solve_options *opt, ba_summary *sum);
 
+/* Add n surface groups (App. B; types and 16-double records above) before the first
+ * step; shapes are numbered in the order added, from 0.  BA_E_INVALID for an unknown
+ * type, a non-positive radius, half-angle or semi-axis, a half-angle of pi/2 or more, a
+ * zero axis direction, a rotation that is not orthonormal to 1e-6, or a non-finite
+ * value; BA_E_STATE after the first step. */
+ba_status ba_add_shapes(ba_handle *h, int64_t n, const int32_t *types, const double *params);
+
+/* Current shape parameters (n_shapes x 16, the format of ba_add_shapes). */
+ba_status ba_get_shapes(const ba_handle *h, double *params);
+
 /* Current parameters (formats above; lines as unit d and m / |d|). */
 ba_status ba_get_parameters(const ba_handle *h, double *cameras, double *points, double *lines,
                             double *planes, double *vps);
@@ -324,7 +365,7 @@ ba_status ba_linearize(ba_handle *h, double lambda);
 /* Number of residual records of a family (1 point, 2 line, 3 plane-point,
  * 4 plane-line, 5 vp-line, 6 point-to-line, 7 line-to-point; inter-group
  * relations 8 VP orthogonal, 9 VP parallel, 10 plane orthogonal, 11 plane
- * parallel; 12 3D point-to-plane). */
+ * parallel; 12 3D point-to-plane; 13 point on a shape, 14 line on a cuboid). */
 ba_status ba_record_count(const ba_handle *h, int32_t family, int64_t *count);
 
 /* Export the last linearisation of a family, in the handle's internal record
@@ -335,7 +376,8 @@ ba_status ba_record_count(const ba_handle *h, int32_t family, int64_t *count);
  * (-1, group a, group b), rows 1 (orthogonal) or 3 (parallel), J columns
  * [group a | group b] with 2 per VP and 3 per plane (the offset column is
  * zero).  Family 12: keys (-1, point, plane), 1 row, J columns [point (3) |
- * plane (3)] (no camera, as family 5).  Any output may be NULL. */
+ * plane (3)] (no camera, as family 5).  Families 13 / 14: keys (camera, point / line,
+ * shape), 2 / 4 rows, J columns [camera | feature | shape (9)].  Any output may be NULL. */
 ba_status ba_export_records(const ba_handle *h, int32_t family, int64_t *keys, double *r, double *J);
 
 /* Feature blocks of the last linearisation: V_f = sum J~_f^T J~_f (undamped)
@@ -347,6 +389,10 @@ ba_status ba_export_feature_blocks(const ba_handle *h, double *Vp, double *gp, d
  * diagonal blocks of S (cameras n_cameras x cd x cd, planes x 3 x 3,
  * vps x 2 x 2), A ordered cameras, planes, vps. */
 ba_status ba_export_reduced(const ba_handle *h, double *b, double *S_cam, double *S_plane, double *S_vp);
+
+/* Diagonal blocks of S of the shapes at the damping of the last ba_linearize
+ * (n_shapes x 9 x 9; their rows of b are the last 9 n_shapes entries of b). */
+ba_status ba_export_shape_blocks(const ba_handle *h, double *S_shape);
 
 /* y = S x with the implicit Schur product at the last linearisation
  * (x, y: n_A doubles on the host). */

@@ -167,6 +167,11 @@ def gauge_basis(prob, state):
         o = prob.off["vp"] + 2 * v
         for k in range(3):
             G[o:o + 2, k] = B.T @ np.cross(E3[k], d)
+    if prob.n.get("sh", 0):
+        from oracle.shapes import gauge_rows
+        rows, _ = gauge_rows(state.sh)
+        o = prob.off["sh"]
+        G[o:o + rows.size // 7] = rows.reshape(-1, 7)
     return G
 
 

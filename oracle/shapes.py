@@ -340,3 +340,46 @@ def similarity(sh: Shapes, s, Q, tau):
             n, e = cuboid_faces(out.R[i][None], sh.q[i][None])
             out.q[i, 0:6] = s * sh.q[i, 0:6] - (n[0] @ tau)
     return out
+
+
+def _ambient(sh: Shapes):
+    """Every stored parameter of each shape, flattened (n, 23)."""
+    n = len(sh)
+    return np.concatenate([sh.R.reshape(n, 9), sh.w, sh.c, sh.d, sh.q], axis=1)
+
+
+def gauge_rows(sh: Shapes, eps=1e-6):
+    """(n, 9, 7): the tangent-coordinate motion of each shape under the world's
+    rotations about e_0..e_2, translations along e_0..e_2 and scale (the similarity
+    gauge of the reduced system), computed numerically: central differences of
+    `similarity` in the stored parameters, solved for the tangent step in the
+    differential of `Shapes.retract` (least squares over the type's own coordinates).
+    Also returns the largest relative residual of those solves (zero when the motion
+    lies in the shape's tangent space)."""
+    n = len(sh)
+    out = np.zeros((n, SHAPE_DOF, 7))
+    if n == 0:
+        return out, 0.0
+    A = np.zeros((n, _ambient(sh).shape[1], SHAPE_DOF))
+    for k in range(SHAPE_DOF):
+        h = np.zeros((n, SHAPE_DOF))
+        h[:, k] = eps
+        A[:, :, k] = (_ambient(sh.retract(h)) - _ambient(sh.retract(-h))) / (2 * eps)
+    E3 = np.eye(3)
+
+    def moved(c, e):
+        if c < 3:
+            return similarity(sh, 1.0, so3_exp(e * E3[c]), np.zeros(3))
+        if c < 6:
+            return similarity(sh, 1.0, np.eye(3), e * E3[c - 3])
+        return similarity(sh, np.exp(e), np.eye(3), np.zeros(3))
+
+    worst = 0.0
+    for c in range(7):
+        b = (_ambient(moved(c, eps)) - _ambient(moved(c, -eps))) / (2 * eps)
+        for i in range(n):
+            used = TYPE_DOF[int(sh.type[i])]
+            x, *_ = np.linalg.lstsq(A[i][:, :used], b[i], rcond=None)
+            out[i, :used, c] = x
+            worst = max(worst, np.linalg.norm(A[i][:, :used] @ x - b[i]) / max(np.linalg.norm(b[i]), 1e-12))
+    return out, worst

@@ -22,7 +22,8 @@ STATUS_NAMES = ["BA_OK", "BA_E_INVALID", "BA_E_STATE", "BA_E_OOM", "BA_E_DEVICE"
 PREC = {"fp64": 0, "mixed": 1}
 PRECOND = {"jacobi": 0, "learned": 1, "gauge": 2}
 PHASES = ["linearize", "feature", "schur", "precond", "pcg", "backsub", "cost"]
-FAMILY_ROWS = {1: 2, 2: 4, 3: 2, 4: 4, 5: 3, 6: 1, 7: 1, 8: 1, 9: 3, 10: 1, 11: 3, 12: 1}
+FAMILY_ROWS = {1: 2, 2: 4, 3: 2, 4: 4, 5: 3, 6: 1, 7: 1, 8: 1, 9: 3, 10: 1, 11: 3, 12: 1, 13: 2, 14: 4}
+SHAPE_DOF, SHAPE_PARAMS = 9, 16
 
 
 class BAError(RuntimeError):
@@ -111,6 +112,9 @@ def _load():
         "ba_export_records": (c_int32, [H, c_int32, I64, D, D]),
         "ba_export_feature_blocks": (c_int32, [H, D, D, D, D]),
         "ba_export_reduced": (c_int32, [H, D, D, D, D]),
+        "ba_export_shape_blocks": (c_int32, [H, D]),
+        "ba_add_shapes": (c_int32, [H, c_int64, I32, D]),
+        "ba_get_shapes": (c_int32, [H, D]),
         "ba_schur_matvec": (c_int32, [H, D, D]),
         "ba_pcg_solve": (c_int32, [H, c_double, c_int32, D, I32, D]),
         "ba_reduced_dim": (c_int32, [H, I64, I32]),
@@ -199,7 +203,7 @@ class BA:
         if st != BA_OK:
             raise BAError(st, "ba_create failed")
         self._h = h
-        self.n = dict(cam=len(c), pt=len(p), ln=len(l), pl=len(g), vp=len(v))
+        self.n = dict(cam=len(c), pt=len(p), ln=len(l), pl=len(g), vp=len(v), sh=0)
         self.camera_dof = int(camera_dof)
         self.precision = precision
 
@@ -222,10 +226,24 @@ class BA:
         ba = cls(scene["cameras"], scene["points"], scene["lines"], scene["planes"], scene["vps"], scene["cx"],
                  scene["cy"], camera_dof=scene.get("camera_dof", 9), precision=precision, precond=precond,
                  device=device, stream=stream)
+        if scene.get("shapes") is not None:
+            ba.add_shapes(scene["shapes"]["type"], scene["shapes"]["params"])
         for kind, (a, b, meas) in scene["obs"].items():
             loss = scene["loss"][kind] if losses else None
             ba.add_observations(kind, a, b, meas, loss)
         return ba
+
+    def add_shapes(self, types, params):
+        """Surface groups (see ba_add_shapes): types (n,), params (n, 16)."""
+        t = np.ascontiguousarray(types, dtype=np.int32).reshape(-1)
+        p = np.ascontiguousarray(params, dtype=np.float64).reshape(-1, SHAPE_PARAMS)
+        self._check(_lib.ba_add_shapes(self._h, len(t), t.ctypes.data_as(POINTER(c_int32)), _dp(p)))
+        self.n["sh"] += len(t)
+
+    def get_shapes(self):
+        out = np.zeros((self.n["sh"], SHAPE_PARAMS))
+        self._check(_lib.ba_get_shapes(self._h, _dp(out)))
+        return out
 
     def add_observations(self, kind, a, b, meas=None, loss=None):
         a = np.ascontiguousarray(a, dtype=np.int32)
@@ -333,8 +351,8 @@ class BA:
             ncol = 2 * (3 if fam >= 10 else 2)
         else:
             cd = 0 if fam in (5, 12) else self.camera_dof
-            nf = 4 if fam in (2, 4, 5, 7) else 3
-            ng = 3 if fam in (3, 4, 12) else 2 if fam == 5 else 0
+            nf = 4 if fam in (2, 4, 5, 7, 14) else 3
+            ng = 3 if fam in (3, 4, 12) else 2 if fam == 5 else SHAPE_DOF if fam in (13, 14) else 0
             ncol = cd + nf + ng
         keys = np.zeros((n, 3), dtype=np.int64)
         r = np.zeros((n, rows))
@@ -357,6 +375,12 @@ class BA:
         Sc, Sp, Sv = np.zeros((n["cam"], cd, cd)), np.zeros((n["pl"], 3, 3)), np.zeros((n["vp"], 2, 2))
         self._check(_lib.ba_export_reduced(self._h, _dp(b), _dp(Sc), _dp(Sp), _dp(Sv)))
         return b, Sc, Sp, Sv
+
+    def export_shape_blocks(self):
+        """Damped diagonal blocks of S of the shapes (n_shapes x 9 x 9)."""
+        S = np.zeros((self.n["sh"], SHAPE_DOF, SHAPE_DOF))
+        self._check(_lib.ba_export_shape_blocks(self._h, _dp(S)))
+        return S
 
     def schur_matvec(self, x):
         x = np.ascontiguousarray(x, dtype=np.float64)

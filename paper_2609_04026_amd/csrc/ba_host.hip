@@ -162,7 +162,7 @@ struct Obs {
 
 struct ba_handle {
   // problem
-  int nc = 0, np = 0, nl = 0, ng = 0, nv = 0, CD = 9;
+  int nc = 0, np = 0, nl = 0, ng = 0, nv = 0, ns = 0, CD = 9;
   double cx = 0, cy = 0;
   int precision = BA_PREC_MIXED, precond = BA_PC_BLOCK_JACOBI;
   int device = 0;
@@ -170,9 +170,9 @@ struct ba_handle {
   bool own_stream = false;
   std::string err;
   // host FP64 parameters in the device layouts (original feature order)
-  std::vector<double> cam, pt, ln, pl, vp;
-  Obs obs[11];  // ba_kind 0..5 observations and associations, 6..9 inter-group relations,
-                //  10 3D point-to-plane associations
+  std::vector<double> cam, pt, ln, pl, vp, sh;  // sh: SH_STRIDE per shape (ba_shape.h)
+  Obs obs[13];  // ba_kind 0..5 observations and associations, 6..9 inter-group relations,
+                //  10 3D point-to-plane associations, 11 / 12 shape associations
   // inter-group relations: caller's (group a, group b) and kind 0..3 per record
   std::vector<int32_t> rel_ga, rel_gb, rel_kind;
   // state
@@ -210,7 +210,8 @@ namespace {
 
 ba_loss default_loss(int kind) {
   switch (kind) {
-    case BA_ASSOC_PLANE_POINT: case BA_ASSOC_PLANE_LINE: return {BA_LOSS_CAUCHY, 1.0, 0.5};
+    case BA_ASSOC_PLANE_POINT: case BA_ASSOC_PLANE_LINE: case BA_ASSOC_SHAPE_POINT: case BA_ASSOC_SHAPE_LINE:
+      return {BA_LOSS_CAUCHY, 1.0, 0.5};
     case BA_ASSOC_VP_LINE: return {BA_LOSS_CAUCHY, 0.2, 5.0e3};
     case BA_ASSOC_JUNCTION: return {BA_LOSS_CAUCHY, 1.0, 0.1};
     case BA_REL_VP_ORTHO: case BA_REL_VP_PARALLEL: case BA_REL_PLANE_ORTHO: case BA_REL_PLANE_PARALLEL:
@@ -452,6 +453,22 @@ void finalize(ba_handle* h) {
       ln_vp[o3.b[i]] = o3.a[i];
     }
   }
+  // surface groups: at most one shape per point, one cuboid per line
+  std::vector<int32_t> pt_shape(h->np, -1), ln_shape(h->nl, -1);
+  {
+    const Obs& o = h->obs[BA_ASSOC_SHAPE_POINT];
+    for (size_t i = 0; i < o.a.size(); ++i) {
+      if (pt_shape[o.b[i]] >= 0) throw BaError(BA_E_INVALID, "point " + std::to_string(o.b[i]) + " is on two shapes");
+      pt_shape[o.b[i]] = o.a[i];
+    }
+    const Obs& o2 = h->obs[BA_ASSOC_SHAPE_LINE];
+    for (size_t i = 0; i < o2.a.size(); ++i) {
+      if (ln_shape[o2.b[i]] >= 0) throw BaError(BA_E_INVALID, "line " + std::to_string(o2.b[i]) + " is on two shapes");
+      if ((int)h->sh[(size_t)SH_STRIDE * o2.a[i] + 15] != SH_CUBOID)
+        throw BaError(BA_E_INVALID, "shape " + std::to_string(o2.a[i]) + " constrains lines but is not a cuboid");
+      ln_shape[o2.b[i]] = o2.a[i];
+    }
+  }
   // junctions, deduplicated check
   const Obs& OJ = h->obs[BA_ASSOC_JUNCTION];
   {
@@ -586,6 +603,10 @@ void finalize(ba_handle* h) {
         Rec r3{h->pt_inv[j], P.cam[p], pt_plane[j], pt_plane[j], {0, 0, 0, 0}, {P.cam[p], j, pt_plane[j]}};
         R[3].push_back(r3);
       }
+      if (pt_shape[j] >= 0) {  // family 9 (exported 13): the shape's projection, as R3
+        Rec r9{h->pt_inv[j], P.cam[p], pt_shape[j], pt_shape[j], {0, 0, 0, 0}, {P.cam[p], j, pt_shape[j]}};
+        R[9].push_back(r9);
+      }
     }
   }
   // R2: line observations;  R4: plane-line association x observing views;  R5: VP-line
@@ -600,6 +621,12 @@ void finalize(ba_handle* h) {
         r4.other = r4.grp = ln_plane[k];
         r4.key[2] = ln_plane[k];
         R[4].push_back(r4);
+      }
+      if (ln_shape[k] >= 0) {  // family 10 (exported 14): the cuboid face's plane projection, as R4
+        Rec r10 = r;
+        r10.other = r10.grp = ln_shape[k];
+        r10.key[2] = ln_shape[k];
+        R[10].push_back(r10);
       }
     }
     if (ln_vp[k] >= 0) {
@@ -655,10 +682,11 @@ void finalize(ba_handle* h) {
 
   // ---- device layout
   Dev& d = h->d;
-  d.CD = h->CD; d.nc = h->nc; d.np = h->np; d.nl = h->nl; d.ng = h->ng; d.nv = h->nv;
+  d.CD = h->CD; d.nc = h->nc; d.np = h->np; d.nl = h->nl; d.ng = h->ng; d.nv = h->nv; d.ns = h->ns;
   d.offPl = h->CD * h->nc;
   d.offVp = d.offPl + 3 * h->ng;
-  d.nA = d.offVp + 2 * h->nv;
+  d.offSh = d.offVp + 2 * h->nv;
+  d.nA = d.offSh + SH_DOF * h->ns;
   d.fp64 = h->precision == BA_PREC_FP64 ? 1 : 0;
   const size_t TS = d.fp64 ? sizeof(double) : sizeof(float);
   DevAlloc& A = h->alloc;
@@ -673,6 +701,8 @@ void finalize(ba_handle* h) {
   d.vp64 = A.get<double>(h->vp.size()); d.vp64n = A.get<double>(h->vp.size());
   upload(h, d.cam64, h->cam); upload(h, d.pt64, ptI); upload(h, d.ln64, lnI);
   upload(h, d.pl64, h->pl); upload(h, d.vp64, h->vp);
+  d.sh64 = A.get<double>(h->sh.size()); d.sh64n = A.get<double>(h->sh.size());
+  upload(h, d.sh64, h->sh);
   d.camT = A.get<char>(h->cam.size(), TS); d.ptT = A.get<char>(ptI.size(), TS); d.lnT = A.get<char>(lnI.size(), TS);
   d.plT = A.get<char>(h->pl.size(), TS); d.vpT = A.get<char>(h->vp.size(), TS);
 
@@ -707,7 +737,8 @@ void finalize(ba_handle* h) {
     upload(h, d.foff[fam], off); upload(h, d.fmeas[fam], meas);
     const int kind = fam == 1 ? BA_OBS_POINT : fam == 2 ? BA_OBS_LINE : fam == 3 ? BA_ASSOC_PLANE_POINT
                      : fam == 4 ? BA_ASSOC_PLANE_LINE : fam == 5 ? BA_ASSOC_VP_LINE
-                     : fam == 8 ? BA_ASSOC_PLANE_POINT_3D : BA_ASSOC_JUNCTION;
+                     : fam == 8 ? BA_ASSOC_PLANE_POINT_3D : fam == 9 ? BA_ASSOC_SHAPE_POINT
+                     : fam == 10 ? BA_ASSOC_SHAPE_LINE : BA_ASSOC_JUNCTION;
     const ba_loss lo = h->obs[kind].loss_set ? h->obs[kind].loss : default_loss(kind);
     d.lkind[fam] = lo.kind; d.lscale[fam] = lo.scale; d.lweight[fam] = lo.weight;
     max_blocks += (n + 255) / 256;
@@ -759,9 +790,10 @@ void finalize(ba_handle* h) {
   {
     const int nblocks = h->nc + h->ng + h->nv;
     const bool want_graph = nblocks > 0 && nblocks <= ba_gnn_impl::MAX_GRAPH_NODES;
-    const bool want_dense = d.nA > 0 && d.nA <= DENSE_MAX_NA;
+    const bool want_dense = d.nA > 0 && d.nA <= DENSE_MAX_NA && h->ns == 0;
     h->dense = ba_handle::DenseHost();
-    if (d.nA > DENSE_MAX_NA)
+    if (h->ns > 0) h->dense.why = "the dense solver does not take surface groups (shapes)";
+    else if (d.nA > DENSE_MAX_NA)
       h->dense.why = "the reduced system has " + std::to_string(d.nA) + " rows, more than the dense solver's " +
                      std::to_string(DENSE_MAX_NA);
     if (d.nA == 0) {
@@ -771,10 +803,11 @@ void finalize(ba_handle* h) {
     if (want_graph || want_dense) {
       const int nfeat = h->np + h->nl;
       std::vector<int64_t> fb_off(nfeat + 1, 0), block_records(nblocks, 0);
+      // blocks of cameras, planes and VPs (the network's graph has no shape nodes)
       auto block_of = [&](int fam, const Rec& r, int32_t out[2]) {
         int k = 0;
         if (r.cam >= 0) out[k++] = r.cam;
-        if (r.grp >= 0) out[k++] = (fam == 5 ? h->nc + h->ng : h->nc) + r.grp;
+        if (r.grp >= 0 && fam != 9 && fam != 10) out[k++] = (fam == 5 ? h->nc + h->ng : h->nc) + r.grp;
         return k;
       };
       auto fid = [&](int fam, const Rec& r) { return fam_is_line(fam) ? h->np + r.feat : r.feat; };
@@ -906,6 +939,52 @@ void finalize(ba_handle* h) {
       upload(h, d.cmpos[fp], ppos); upload(h, d.cmgrp[fp], pgrp);
     }
   }
+  // per R1 / R2 camera-major position, the family 9 / 10 record of the same feature and
+  // camera (a feature's shape records follow its observations one to one)
+  for (int pair = 0; pair < 2; ++pair) {
+    const int fo = pair == 0 ? 1 : 2, fs = pair == 0 ? 9 : 10;
+    if (R[fs].empty()) continue;
+    const auto& v = R[fo];
+    std::vector<int32_t> cmo(h->nc + 1, 0);
+    for (const Rec& r : v) cmo[r.cam + 1]++;
+    for (int c = 0; c < h->nc; ++c) cmo[c + 1] += cmo[c];
+    std::vector<int32_t> al(v.size(), -1);
+    int64_t matched = 0;
+    for (size_t i = 0; i < v.size(); ++i) {
+      const int f = v[i].feat;
+      const int32_t pos = cmo[v[i].cam]++;
+      if (foff_h[fs][f + 1] > foff_h[fs][f]) {
+        const int64_t is = foff_h[fs][f] + ((int64_t)i - foff_h[fo][f]);
+        if (R[fs][is].cam != v[i].cam) throw BaError(BA_E_STATE, "shape records are not aligned with their observations");
+        al[pos] = (int32_t)is;
+        ++matched;
+      }
+    }
+    if (matched != (int64_t)R[fs].size()) throw BaError(BA_E_STATE, "shape records are not aligned with their observations");
+    int32_t*& dst = pair == 0 ? d.shal_p : d.shal_l;
+    dst = A.get<int32_t>(al.size());
+    upload(h, dst, al);
+  }
+  {
+    std::vector<std::vector<int32_t>> mp(h->ns), ml(h->ns);
+    for (size_t i = 0; i < R[9].size(); ++i)
+      if (i == 0 || R[9][i].feat != R[9][i - 1].feat) mp[R[9][i].grp].push_back(R[9][i].feat);
+    for (size_t i = 0; i < R[10].size(); ++i)
+      if (i == 0 || R[10][i].feat != R[10][i - 1].feat) ml[R[10][i].grp].push_back(R[10][i].feat);
+    auto flatten = [&](std::vector<std::vector<int32_t>>& m, int32_t*& list, int32_t*& off) {
+      std::vector<int32_t> o(m.size() + 1, 0), flat;
+      for (size_t g = 0; g < m.size(); ++g) {
+        o[g + 1] = o[g] + (int32_t)m[g].size();
+        flat.insert(flat.end(), m[g].begin(), m[g].end());
+      }
+      list = A.get<int32_t>(flat.size());
+      off = A.get<int32_t>(o.size());
+      upload(h, list, flat);
+      upload(h, off, o);
+    };
+    flatten(mp, d.shp, d.shp_off);
+    flatten(ml, d.shl, d.shl_off);
+  }
   cam_major(6, true, d.px_start, d.px_cnt, d.px_off);
   cam_major(7, true, d.lx_start, d.lx_cnt, d.lx_off);
   // group member lists
@@ -953,12 +1032,17 @@ void finalize(ba_handle* h) {
   d.Ucam = A.get<double>((size_t)h->nc * CD * CD); d.Upl = A.get<double>((size_t)h->ng * 9); d.Uvp = A.get<double>((size_t)h->nv * 4);
   d.Scam = A.get<double>((size_t)h->nc * CD * CD); d.Spl = A.get<double>((size_t)h->ng * 9); d.Svp = A.get<double>((size_t)h->nv * 4);
   d.Mcam = A.get<double>((size_t)h->nc * CD * CD); d.Mpl = A.get<double>((size_t)h->ng * 9); d.Mvp = A.get<double>((size_t)h->nv * 4);
+  d.Ush = A.get<double>((size_t)h->ns * SH_DOF * SH_DOF); d.Ssh = A.get<double>((size_t)h->ns * SH_DOF * SH_DOF);
+  d.Msh = A.get<double>((size_t)h->ns * SH_DOF * SH_DOF);
   d.gA = A.get<double>(nA); d.DA = A.get<double>(nA); d.bA = A.get<double>(nA);
   d.x = A.get<double>(nA); d.r = A.get<double>(nA); d.z = A.get<double>(nA); d.p = A.get<double>(nA); d.q = A.get<double>(nA);
   d.xT = A.get<char>(nA, TS);
   // coarse space of the two-level preconditioners
   d.Zc = A.get<double>((size_t)COARSE_K * nA);
   d.SZc = A.get<double>((size_t)COARSE_K * nA);
+  // the network writes its columns on the rows of its graph's nodes only: the shape
+  // rows of those columns stay zero
+  launch_zero(d.Zc, (size_t)COARSE_K * std::max(nA, 1) * sizeof(double), h->stream);
   d.Einv = A.get<double>((size_t)COARSE_K * COARSE_K);
   d.Ztb = A.get<double>((size_t)COARSE_K + COARSE_K * COARSE_K);
   d.szr = A.get<char>((size_t)nA * SZ_COLS * SZ_PANELS, TS);
@@ -977,19 +1061,22 @@ void finalize(ba_handle* h) {
     if (const char* e = std::getenv("BA_TILE_RECORDS")) cap = std::max(1, std::min(MV_TILE, std::atoi(e)));
     for (int fam = 1; fam < NFAM; ++fam)
       if (d.fn[fam] >= (int64_t)1 << 28) throw BaError(BA_E_INVALID, "more than 2^28 records in one family");
-    auto build = [&](const std::vector<int>& fams, int nfeat, std::vector<int32_t>& big) {
+    // a feature with surface-group records (family 9 / 10) takes the one-lane-per-feature
+    // path too, so that the tiles hold only the smaller slots
+    auto build = [&](const std::vector<int>& fams, int nfeat, std::vector<int32_t>& big, int fam_sh) {
+      auto on_shape = [&](int f) { return foff_h[fam_sh][f + 1] > foff_h[fam_sh][f]; };
       int f = 0;
       while (f < nfeat) {
         const int fb = f;
         int64_t cnt = 0;
-        while (f < nfeat) {
+        while (f < nfeat && !on_shape(f)) {
           int64_t n = 0;
           for (int fam : fams) n += foff_h[fam][f + 1] - foff_h[fam][f];
           if (cnt + n > cap) break;
           cnt += n;
           ++f;
         }
-        if (f == fb) {  // one feature with more records than a tile holds
+        if (f == fb) {  // one feature with more records than a tile holds, or on a shape
           big.push_back(f);
           ++f;
           continue;
@@ -1003,9 +1090,9 @@ void finalize(ba_handle* h) {
         tiles.push_back(make_int4(first, (int)cnt, fb, 0));
       }
     };
-    build({1, 3, 6, 8}, h->np, bigp);
+    build({1, 3, 6, 8}, h->np, bigp, 9);
     d.n_ptiles = (int)tiles.size();
-    build({2, 4, 5, 7}, h->nl, bigl);
+    build({2, 4, 5, 7}, h->nl, bigl, 10);
     d.n_tiles = (int)tiles.size();
     d.n_bigp = (int)bigp.size();
     d.n_bigl = (int)bigl.size();
@@ -1177,6 +1264,81 @@ bool finite_all(const double* p, size_t n) {
   return true;
 }
 
+// one shape from its 16-double C-ABI record into the device layout (ba_shape.h)
+void shape_from_abi(int t, const double* p, double* o) {
+  std::fill(o, o + SH_STRIDE, 0.0);
+  if (!finite_all(p, 16)) throw BaError(BA_E_INVALID, "non-finite shape parameter");
+  auto rotation = [&](const double* R) {
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        const double v = R[3 * i] * R[3 * j] + R[3 * i + 1] * R[3 * j + 1] + R[3 * i + 2] * R[3 * j + 2];
+        if (std::fabs(v - (i == j ? 1.0 : 0.0)) > 1e-6) throw BaError(BA_E_INVALID, "shape rotation is not orthonormal");
+      }
+    double c[3];
+    cross(R, R + 3, c);
+    if (c[0] * R[6] + c[1] * R[7] + c[2] * R[8] < 0) throw BaError(BA_E_INVALID, "shape rotation is a reflection");
+    std::copy_n(R, 9, o);
+  };
+  auto positive = [](double v, const char* what) {
+    if (!(v > 0)) throw BaError(BA_E_INVALID, std::string("shape ") + what + " must be positive");
+    return std::log(v);
+  };
+  switch (t) {
+    case SH_SPHERE:
+      std::copy_n(p, 3, o);
+      o[3] = positive(p[3], "radius");
+      break;
+    case SH_CYLINDER: {
+      const double nd = norm3(p);
+      if (!(nd > 0)) throw BaError(BA_E_INVALID, "cylinder axis direction is zero");
+      const double Q[3] = {p[3] + p[0] / nd, p[4] + p[1] / nd, p[5] + p[2] / nd};
+      if (!line_from_points(p + 3, Q, o)) throw BaError(BA_E_INVALID, "bad cylinder axis");
+      o[11] = positive(p[6], "radius");
+      break;
+    }
+    case SH_CONE: {
+      const double nd = norm3(p + 3);
+      if (!(nd > 0)) throw BaError(BA_E_INVALID, "cone axis direction is zero");
+      if (!(p[6] < 0.5 * M_PI)) throw BaError(BA_E_INVALID, "cone half-angle must be below pi/2");
+      std::copy_n(p, 3, o);
+      for (int k = 0; k < 3; ++k) o[3 + k] = p[3 + k] / nd;
+      sphere_basis(o + 3, o + 6, o + 9);
+      o[12] = positive(p[6], "half-angle");
+      break;
+    }
+    case SH_ELLIPSOID:
+      rotation(p);
+      std::copy_n(p + 9, 3, o + 9);
+      for (int k = 0; k < 3; ++k) o[12 + k] = positive(p[12 + k], "semi-axis");
+      break;
+    case SH_CUBOID:
+      rotation(p);
+      std::copy_n(p + 9, 6, o + 9);
+      break;
+    default:
+      throw BaError(BA_E_INVALID, "unknown shape type " + std::to_string(t));
+  }
+  o[15] = t;
+}
+
+// the device layout of one shape back into its C-ABI record
+void shape_to_abi(const double* o, double* p) {
+  std::fill(p, p + 16, 0.0);
+  switch ((int)o[15]) {
+    case SH_SPHERE: std::copy_n(o, 3, p); p[3] = std::exp(o[3]); break;
+    case SH_CYLINDER:
+      for (int k = 0; k < 3; ++k) { p[k] = o[k]; p[3 + k] = o[10] / o[9] * o[6 + k]; }
+      p[6] = std::exp(o[11]);
+      break;
+    case SH_CONE: std::copy_n(o, 6, p); p[6] = std::exp(o[12]); break;
+    case SH_ELLIPSOID:
+      std::copy_n(o, 12, p);
+      for (int k = 0; k < 3; ++k) p[12 + k] = std::exp(o[12 + k]);
+      break;
+    default: std::copy_n(o, 15, p); break;
+  }
+}
+
 void fill_params(ba_handle* h, const double* cams, const double* pts, const double* lines, const double* planes,
                  const double* vps) {
   if (cams) {
@@ -1232,7 +1394,7 @@ void fill_params(ba_handle* h, const double* cams, const double* pts, const doub
 void accept_candidate(ba_handle* h) {
   Dev& d = h->d;
   std::swap(d.cam64, d.cam64n); std::swap(d.pt64, d.pt64n); std::swap(d.ln64, d.ln64n);
-  std::swap(d.pl64, d.pl64n); std::swap(d.vp64, d.vp64n);
+  std::swap(d.pl64, d.pl64n); std::swap(d.vp64, d.vp64n); std::swap(d.sh64, d.sh64n);
 }
 
 void current_cost(ba_handle* h) {
@@ -1256,6 +1418,7 @@ bool do_step(ba_handle* h, const ba_solve_options& o, ba_step_report* rep, doubl
   set_device(h);
   if (!h->finalized) finalize(h);
   h->d.det = o.deterministic ? 1 : 0;
+  if (h->d.det && h->ns > 0) throw BaError(BA_E_INVALID, "the deterministic mode does not take surface groups (shapes)");
   if (h->first_step) {
     h->lambda = o.lambda0;
     h->nu = o.nu0;
@@ -1459,7 +1622,7 @@ ba_status ba_create(const ba_problem_desc* desc, ba_handle** out) {
     }
     for (int k = 0; k <= BA_PHASE_COUNT; ++k) HIPCHK(hipEventCreate(&h->ev[k]));
     h->events = true;
-    for (int k = 0; k < 11; ++k) h->obs[k].loss = default_loss(k);
+    for (int k = 0; k < 13; ++k) h->obs[k].loss = default_loss(k);
   });
   if (st != BA_OK) {
     ba_destroy(h);
@@ -1474,7 +1637,7 @@ ba_status ba_add_observations(ba_handle* h, int32_t kind, int64_t n, const int32
   if (!h) return BA_E_INVALID;
   return guard(h, [&] {
     if (h->finalized) throw BaError(BA_E_STATE, "observations must be added before the first step");
-    if (kind < 0 || kind > 10) throw BaError(BA_E_INVALID, "bad kind");
+    if (kind < 0 || kind > 12) throw BaError(BA_E_INVALID, "bad kind");
     if (n < 0 || (n > 0 && (!a || !b))) throw BaError(BA_E_INVALID, "bad arrays");
     const bool has_meas = kind == BA_OBS_POINT || kind == BA_OBS_LINE;
     if (has_meas && n > 0 && !meas) throw BaError(BA_E_INVALID, "measurements required");
@@ -1489,6 +1652,8 @@ ba_status ba_add_observations(ba_handle* h, int32_t kind, int64_t n, const int32
       case BA_REL_VP_ORTHO: case BA_REL_VP_PARALLEL: ha = hb = h->nv; break;
       case BA_ASSOC_PLANE_POINT_3D: ha = h->ng; hb = h->np; break;
       case BA_REL_PLANE_ORTHO: case BA_REL_PLANE_PARALLEL: ha = hb = h->ng; break;
+      case BA_ASSOC_SHAPE_POINT: ha = h->ns; hb = h->np; break;
+      case BA_ASSOC_SHAPE_LINE: ha = h->ns; hb = h->nl; break;
     }
     check_index(a, n, ha, "first");
     check_index(b, n, hb, "second");
@@ -1507,6 +1672,34 @@ ba_status ba_add_observations(ba_handle* h, int32_t kind, int64_t n, const int32
     o.a.insert(o.a.end(), a, a + n);
     o.b.insert(o.b.end(), b, b + n);
     if (has_meas) o.meas.insert(o.meas.end(), meas, meas + 4 * n);
+  });
+}
+
+ba_status ba_add_shapes(ba_handle* h, int64_t n, const int32_t* types, const double* params) {
+  if (!h) return BA_E_INVALID;
+  return guard(h, [&] {
+    if (h->finalized) throw BaError(BA_E_STATE, "shapes must be added before the first step");
+    if (n < 0 || (n > 0 && (!types || !params))) throw BaError(BA_E_INVALID, "bad arrays");
+    if ((int64_t)h->ns + n > INT32_MAX / SH_DOF) throw BaError(BA_E_INVALID, "too many shapes");
+    std::vector<double> add((size_t)n * SH_STRIDE);
+    for (int64_t i = 0; i < n; ++i) shape_from_abi(types[i], params + 16 * i, &add[(size_t)SH_STRIDE * i]);
+    h->sh.insert(h->sh.end(), add.begin(), add.end());
+    h->ns += (int)n;
+  });
+}
+
+ba_status ba_get_shapes(const ba_handle* hc, double* params) {
+  ba_handle* h = const_cast<ba_handle*>(hc);
+  if (!h) return BA_E_INVALID;
+  return guard(h, [&] {
+    std::vector<double> sh = h->sh;
+    if (h->finalized && !sh.empty()) {
+      set_device(h);
+      HIPCHK(hipMemcpyAsync(sh.data(), h->d.sh64, sh.size() * 8, hipMemcpyDeviceToHost, h->stream));
+      sync(h);
+    }
+    if (params)
+      for (int i = 0; i < h->ns; ++i) shape_to_abi(&sh[(size_t)SH_STRIDE * i], params + 16 * (size_t)i);
   });
 }
 
@@ -1830,10 +2023,10 @@ ba_status ba_linearize(ba_handle* h, double lambda) {
 }
 
 ba_status ba_record_count(const ba_handle* h, int32_t family, int64_t* count) {
-  if (!h || family < 1 || family > 12 || !count) return BA_E_INVALID;
+  if (!h || family < 1 || family > 14 || !count) return BA_E_INVALID;
   if (!h->finalized) { const_cast<ba_handle*>(h)->err = "records exist after the first step"; return BA_E_STATE; }
   if (family >= 8 && family <= 11) *count = std::count(h->rel_kind.begin(), h->rel_kind.end(), family - 8);
-  else *count = h->d.fn[family == 12 ? 8 : family];
+  else *count = h->d.fn[family >= 12 ? family - 4 : family];
   return BA_OK;
 }
 
@@ -1870,9 +2063,9 @@ ba_status export_relations(ba_handle* h, int32_t fam, int64_t* keys, double* r, 
 
 ba_status ba_export_records(const ba_handle* hc, int32_t fam, int64_t* keys, double* r, double* J) {
   ba_handle* h = const_cast<ba_handle*>(hc);
-  if (!h || fam < 1 || fam > 12) return BA_E_INVALID;
+  if (!h || fam < 1 || fam > 14) return BA_E_INVALID;
   if (fam >= 8 && fam <= 11) return export_relations(h, fam, keys, r, J);
-  if (fam == 12) fam = 8;  // the 3D point-to-plane family, stored as family 8
+  if (fam >= 12) fam -= 4;  // 3D point-to-plane, shape point, shape line: stored as 8, 9, 10
   return guard(h, [&] {
     if (!h->finalized) throw BaError(BA_E_STATE, "no records yet");
     const int64_t n = h->d.fn[fam];
@@ -1977,6 +2170,18 @@ ba_status ba_export_reduced(const ba_handle* hc, double* b, double* Sc, double* 
   });
 }
 
+ba_status ba_export_shape_blocks(const ba_handle* hc, double* S) {
+  ba_handle* h = const_cast<ba_handle*>(hc);
+  if (!h) return BA_E_INVALID;
+  return guard(h, [&] {
+    if (!h->finalized) throw BaError(BA_E_STATE, "no linearisation yet");
+    set_device(h);
+    if (S && h->ns)
+      HIPCHK(hipMemcpyAsync(S, h->d.Ssh, (size_t)h->ns * SH_DOF * SH_DOF * 8, hipMemcpyDeviceToHost, h->stream));
+    sync(h);
+  });
+}
+
 ba_status ba_schur_matvec(ba_handle* h, const double* x, double* y) {
   if (!h || !x || !y) return BA_E_INVALID;
   return guard(h, [&] {
@@ -2013,7 +2218,7 @@ ba_status ba_pcg_solve(ba_handle* h, double tol, int32_t max_iters, double* x, i
 
 ba_status ba_reduced_dim(const ba_handle* h, int64_t* nA, int32_t* cd) {
   if (!h) return BA_E_INVALID;
-  if (nA) *nA = (int64_t)h->CD * h->nc + 3 * h->ng + 2 * h->nv;
+  if (nA) *nA = (int64_t)h->CD * h->nc + 3 * h->ng + 2 * h->nv + (int64_t)SH_DOF * h->ns;
   if (cd) *cd = h->CD;
   return BA_OK;
 }

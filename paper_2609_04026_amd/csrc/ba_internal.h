@@ -14,9 +14,10 @@
 
 namespace ba {
 
-// families 1..7 of Sec. 3 and 8, the 3D point-to-plane distance of the 3D formulation
-// (exported as family 12, after the four relation families); index 0 unused
-constexpr int NFAM = 9;
+// families 1..7 of Sec. 3; 8, the 3D point-to-plane distance of the 3D formulation
+// (exported as family 12, after the four relation families); 9, a point on a surface
+// group (exported 13) and 10, a line on a cuboid (exported 14); index 0 unused
+constexpr int NFAM = 11;
 
 // compile-time shape of a family's record slot
 template <int FAM, int CD> struct Fam;
@@ -28,6 +29,8 @@ template <int CD> struct Fam<5, CD> { static constexpr int ROWS = 3, NC = 0, NG 
 template <int CD> struct Fam<6, CD> { static constexpr int ROWS = 1, NC = CamCols<CD>::PT, NG = 0, NF = 3, MEAS = 3, GT = 0, FT = 0; };
 template <int CD> struct Fam<7, CD> { static constexpr int ROWS = 1, NC = CamCols<CD>::LN, NG = 0, NF = 4, MEAS = 2, GT = 0, FT = 1; };
 template <int CD> struct Fam<8, CD> { static constexpr int ROWS = 1, NC = 0, NG = 3, NF = 3, MEAS = 0, GT = 1, FT = 0; };
+template <int CD> struct Fam<9, CD> { static constexpr int ROWS = 2, NC = CamCols<CD>::PT, NG = SH_DOF, NF = 3, MEAS = 0, GT = 3, FT = 0; };
+template <int CD> struct Fam<10, CD> { static constexpr int ROWS = 4, NC = CamCols<CD>::LN, NG = SH_DOF, NF = 4, MEAS = 4, GT = 3, FT = 1; };
 
 // Jacobian slot of one record: [ J_cam (ROWS x NC) | J_group (ROWS x NG) | J_feature (ROWS x NF) | pad ];
 // the weighted residual lives in a separate ROWS-wide array
@@ -39,9 +42,9 @@ template <int FAM, int CD> struct Slot {
   static constexpr int STRIDE = (USED + 3) / 4 * 4;
 };
 
-inline int meas_width(int fam) { return fam == 1 ? 2 : fam == 2 ? 4 : fam == 3 ? 0 : fam == 4 ? 4 : fam == 5 ? 0 : fam == 6 ? 3 : fam == 7 ? 2 : 0; }
-inline int fam_rows(int fam) { return fam == 1 ? 2 : fam == 2 ? 4 : fam == 3 ? 2 : fam == 4 ? 4 : fam == 5 ? 3 : 1; }
-inline bool fam_is_line(int fam) { return fam == 2 || fam == 4 || fam == 5 || fam == 7; }
+inline int meas_width(int fam) { return fam == 1 ? 2 : fam == 2 ? 4 : fam == 3 ? 0 : fam == 4 ? 4 : fam == 5 ? 0 : fam == 6 ? 3 : fam == 7 ? 2 : fam == 10 ? 4 : 0; }
+inline int fam_rows(int fam) { return fam == 1 ? 2 : fam == 2 ? 4 : fam == 3 ? 2 : fam == 4 ? 4 : fam == 5 ? 3 : fam == 9 ? 2 : fam == 10 ? 4 : 1; }
+inline bool fam_is_line(int fam) { return fam == 2 || fam == 4 || fam == 5 || fam == 7 || fam == 10; }
 int slot_stride(int fam, int cd);
 int slot_nc(int fam, int cd);
 int slot_ng(int fam);
@@ -50,12 +53,13 @@ int slot_nf(int fam);
 // All device pointers of a problem.  Passed by value to kernels.
 struct Dev {
   int CD = 9;
-  int nc = 0, np = 0, nl = 0, ng = 0, nv = 0;
-  int nA = 0, offPl = 0, offVp = 0;
+  int nc = 0, np = 0, nl = 0, ng = 0, nv = 0, ns = 0;
+  int nA = 0, offPl = 0, offVp = 0, offSh = 0;
   int fp64 = 0;  // 1: T = double, 0: T = float
-  // parameters: FP64 master (current and candidate) and work copy in T
-  double *cam64 = nullptr, *pt64 = nullptr, *ln64 = nullptr, *pl64 = nullptr, *vp64 = nullptr;
-  double *cam64n = nullptr, *pt64n = nullptr, *ln64n = nullptr, *pl64n = nullptr, *vp64n = nullptr;
+  // parameters: FP64 master (current and candidate) and work copy in T; shapes
+  // (surface groups, SH_STRIDE doubles each, see ba_shape.h) in FP64 only
+  double *cam64 = nullptr, *pt64 = nullptr, *ln64 = nullptr, *pl64 = nullptr, *vp64 = nullptr, *sh64 = nullptr;
+  double *cam64n = nullptr, *pt64n = nullptr, *ln64n = nullptr, *pl64n = nullptr, *vp64n = nullptr, *sh64n = nullptr;
   void *camT = nullptr, *ptT = nullptr, *lnT = nullptr, *plT = nullptr, *vpT = nullptr;
   // residual families
   int64_t fn[NFAM] = {0};
@@ -83,6 +87,12 @@ struct Dev {
   // features, whose data its L2 then serves)
   int32_t* cam_order = nullptr;
   int32_t *vpm_off = nullptr, *vpm = nullptr;
+  // surface groups: per shape its points (family 9) and lines (family 10) in feature order;
+  // per observation record (camera-major position of R1 / R2) the index of the family 9 /
+  // 10 record of the same camera and feature, or -1.  A point or line is on at most one
+  // shape, and every feature with such records is one of the product's big features.
+  int32_t *shp_off = nullptr, *shp = nullptr, *shl_off = nullptr, *shl = nullptr;
+  int32_t *shal_p = nullptr, *shal_l = nullptr;
   // feature blocks (T unless noted)
   void *Vp = nullptr, *gp = nullptr, *Vl = nullptr, *gl = nullptr;
   void *Vip = nullptr, *Vil = nullptr, *sp = nullptr, *sl = nullptr;
@@ -91,10 +101,10 @@ struct Dev {
   double *Dp = nullptr, *Dl = nullptr;
   double *hp = nullptr, *hl = nullptr;
   // A side (double)
-  double *Ucam = nullptr, *Upl = nullptr, *Uvp = nullptr;  // full blocks
+  double *Ucam = nullptr, *Upl = nullptr, *Uvp = nullptr, *Ush = nullptr;  // full blocks
   double *gA = nullptr, *DA = nullptr, *bA = nullptr;
-  double *Scam = nullptr, *Spl = nullptr, *Svp = nullptr;  // damped diagonal blocks of S
-  double *Mcam = nullptr, *Mpl = nullptr, *Mvp = nullptr;  // preconditioner blocks
+  double *Scam = nullptr, *Spl = nullptr, *Svp = nullptr, *Ssh = nullptr;  // damped diagonal blocks of S
+  double *Mcam = nullptr, *Mpl = nullptr, *Mvp = nullptr, *Msh = nullptr;  // preconditioner blocks
   // two-level preconditioner: Z (coarse_k columns of length nA, column-major; the
   // gauge columns first), S Z, E^-1 = (Z^T S Z)^-1 (COARSE_K x COARSE_K storage),
   // Z^T b; PCG starts from x0 = Z E^-1 Z^T b and applies (I - Q S) M + Q, Q = Z E^-1 Z^T
@@ -170,11 +180,16 @@ struct Dev {
 // (a junction record's partner feature only supplies the measurement), its plane or VP
 template <int FAM> __device__ __forceinline__ bool record_masked(const Dev& d, int64_t i, int f) {
   if (!d.has_mask) return false;
-  const bool line = FAM == 2 || FAM == 4 || FAM == 5 || FAM == 7;
+  const bool line = FAM == 2 || FAM == 4 || FAM == 5 || FAM == 7 || FAM == 10;
   if ((line ? d.mln : d.mpt)[f]) return true;
   if constexpr (FAM == 3 || FAM == 4 || FAM == 8) return d.mpl[d.fgrp[FAM][i]] != 0;
   if constexpr (FAM == 5) return d.mvp[d.fgrp[FAM][i]] != 0;
-  return false;
+  return false;  // shapes are not left out
+}
+
+// first entry of group g of type gt (1 plane, 2 VP, 3 shape) in the reduced vector
+__host__ __device__ __forceinline__ int a_grp(const Dev& d, int gt, int g) {
+  return gt == 1 ? d.offPl + 3 * g : gt == 2 ? d.offVp + 2 * g : d.offSh + SH_DOF * g;
 }
 
 // product: 1024-thread workgroups sharing one FP64 copy of y in LDS (FP32 LDS atomics
@@ -274,6 +289,11 @@ void launch_gauge_basis(const Dev& d, hipStream_t s);
 // S Z and E = Z^T S Z for the first d.coarse_k columns of d.Zc, E^-1 and SC_COARSE
 void launch_coarse_setup(const Dev& d, double lambda, hipStream_t s);
 void launch_backsub(const Dev& d, hipStream_t s);                        // h_f, model decrease terms
+// surface groups (ba_shape.hip): U, g, D of the shape blocks (after the camera pass A);
+// their damped S blocks and b (after the camera pass B); their gauge rows
+void launch_shape_pass_a(const Dev& d, hipStream_t s);
+void launch_shape_pass_b(const Dev& d, double lambda, hipStream_t s);
+void launch_shape_gauge(const Dev& d, hipStream_t s);
 void launch_retract(const Dev& d, hipStream_t s);                        // candidate = current [+] h
 void launch_zero(void* p, size_t bytes, hipStream_t s);
 // per point (NF 3, observation records R1) or line (NF 4, R2): active observations

@@ -30,18 +30,19 @@ int slot_stride(int fam, int cd) {
   switch (fam) {
     case 1: return SS(1); case 2: return SS(2); case 3: return SS(3); case 4: return SS(4);
     case 5: return SS(5); case 6: return SS(6); case 7: return SS(7); case 8: return SS(8);
+    case 9: return SS(9); case 10: return SS(10);
   }
 #undef SS
   return 0;
 }
 int slot_nc(int fam, int cd) {
   switch (fam) {
-    case 1: case 3: case 6: return cd;
-    case 2: case 4: case 7: return cd == 9 ? 7 : 6;
+    case 1: case 3: case 6: case 9: return cd;
+    case 2: case 4: case 7: case 10: return cd == 9 ? 7 : 6;
   }
   return 0;
 }
-int slot_ng(int fam) { return fam == 3 || fam == 4 || fam == 8 ? 3 : fam == 5 ? 2 : 0; }
+int slot_ng(int fam) { return fam == 3 || fam == 4 || fam == 8 ? 3 : fam == 5 ? 2 : fam == 9 || fam == 10 ? SH_DOF : 0; }
 int slot_nf(int fam) { return fam_is_line(fam) ? 4 : 3; }
 
 
@@ -166,7 +167,6 @@ template <typename S, int N> __device__ __forceinline__ void chol_inverse(const 
   }
 }
 
-__device__ __forceinline__ int a_grp(const Dev& d, int gt, int g) { return gt == 1 ? d.offPl + 3 * g : d.offVp + 2 * g; }
 
 // ---------------------------------------------------------------------------
 // parameter cast
@@ -192,7 +192,7 @@ void launch_cast_params(const Dev& d, bool candidate, hipStream_t s) {
 // FP64 residual of one record (shared by linearisation and cost)
 template <int FAM> __device__ __forceinline__ void residual64(const Dev& d, int64_t i, const double* cam, const double* pt,
                                                               const double* ln, const double* pl, const double* vp,
-                                                              double* r) {
+                                                              const double* sh, double* r) {
   using F = Fam<FAM, 9>;
   const int f = d.ffeat[FAM][i];
   double m[4] = {0, 0, 0, 0};
@@ -206,16 +206,26 @@ template <int FAM> __device__ __forceinline__ void residual64(const Dev& d, int6
   } else {
     const int c = d.fcam[FAM][i];
     Cam<double> C = load_cam<double>(cam + (int64_t)CAM_STRIDE * c);
-    if constexpr (FAM == 1 || FAM == 3 || FAM == 6) {
+    if constexpr (FAM == 1 || FAM == 3 || FAM == 6 || FAM == 9) {
       const double* X = pt + (int64_t)PT_STRIDE * f;
       if constexpr (FAM == 1) res_R1<double>(C, X, m, r);
       if constexpr (FAM == 3) res_R3<double>(C, X, load_plane<double>(pl + (int64_t)PL_STRIDE * d.fgrp[FAM][i]), r);
       if constexpr (FAM == 6) res_R6<double>(C, X, m, r);
+      if constexpr (FAM == 9) {
+        const double* S = sh + (int64_t)SH_STRIDE * d.fgrp[FAM][i];
+        res_R13<double>(C, X, S, shape_type(S) == SH_CUBOID ? cuboid_face<double>(S, X) : 0, r);
+      }
     } else {
       Line<double> L = load_line<double>(ln + (int64_t)LN_STRIDE * f);
       if constexpr (FAM == 2) res_R2<double>(C, L, m, r);
       if constexpr (FAM == 4) res_R4<double>(C, L, load_plane<double>(pl + (int64_t)PL_STRIDE * d.fgrp[FAM][i]), m, r);
       if constexpr (FAM == 7) res_R7<double>(C, L, m, r);
+      if constexpr (FAM == 10) {
+        const double* S = sh + (int64_t)SH_STRIDE * d.fgrp[FAM][i];
+        double dl[3], ml[3];
+        line_dm(L, dl, ml);
+        res_R14<double>(C, L, S, cuboid_face_line<double>(S, dl, ml), m, r);
+      }
     }
   }
 }
@@ -269,7 +279,7 @@ template <int FAM, typename T, int CD> __global__ __launch_bounds__(256) void k_
   } else {
     const int c = d.fcam[FAM][i];
     Cam<T> C = load_cam<T>(camT + (int64_t)CAM_STRIDE * c);
-    if constexpr (FAM == 1 || FAM == 3 || FAM == 6) {
+    if constexpr (FAM == 1 || FAM == 3 || FAM == 6 || FAM == 9) {
       T X[3] = {ptT[(int64_t)PT_STRIDE * f], ptT[(int64_t)PT_STRIDE * f + 1], ptT[(int64_t)PT_STRIDE * f + 2]};
       if constexpr (FAM == 1) jac_R1<T, CD>(C, X, mT, r, Jc, Jf);
       if constexpr (FAM == 3) {
@@ -285,6 +295,21 @@ template <int FAM, typename T, int CD> __global__ __launch_bounds__(256) void k_
         for (int k = 0; k < 6; ++k) { Jg[k] = (T)jg3[k]; Jf[k] = (T)jf3[k]; }
       }
       if constexpr (FAM == 6) jac_R6<T, CD>(C, X, mT, r, Jc, Jf);
+      if constexpr (FAM == 9) {
+        // a difference of two nearly equal projections, like R3: FP64 from the master
+        // parameters (the cuboid face chosen in FP64), stored in T
+        double r9[2], jc9[2 * SL::NC], jg9[2 * SH_DOF], jf9[6];
+        const double* X64 = d.pt64 + (int64_t)PT_STRIDE * f;
+        const double* S64 = d.sh64 + (int64_t)SH_STRIDE * d.fgrp[FAM][i];
+        jac_R13<double, CD>(load_cam<double>(d.cam64 + (int64_t)CAM_STRIDE * c), X64, S64,
+                            shape_type(S64) == SH_CUBOID ? cuboid_face<double>(S64, X64) : 0, r9, jc9, jg9, jf9);
+#pragma unroll
+        for (int k = 0; k < 2 * SL::NC; ++k) Jc[k] = (T)jc9[k];
+#pragma unroll
+        for (int k = 0; k < 2 * SH_DOF; ++k) Jg[k] = (T)jg9[k];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) Jf[k] = (T)jf9[k];
+      }
     } else {
       Line<T> L = load_line<T>(lnT + (int64_t)LN_STRIDE * f);
       if constexpr (FAM == 2) jac_R2<T, CD>(C, L, mT, r, Jc, Jf);
@@ -304,6 +329,23 @@ template <int FAM, typename T, int CD> __global__ __launch_bounds__(256) void k_
         for (int k = 0; k < 16; ++k) Jf[k] = (T)jf4[k];
       }
       if constexpr (FAM == 7) jac_R7<T, CD>(C, L, mT, r, Jc, Jf);
+      if constexpr (FAM == 10) {
+        // like R4: FP64 from the master parameters, the face chosen in FP64, stored in T
+        double m64[4], r10[4], jc10[4 * SL::NC], jg10[4 * SH_DOF], jf10[16], dl[3], ml[3];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) m64[k] = d.fmeas[FAM][i * 4 + k];
+        const Line<double> L64 = load_line<double>(d.ln64 + (int64_t)LN_STRIDE * f);
+        const double* S64 = d.sh64 + (int64_t)SH_STRIDE * d.fgrp[FAM][i];
+        line_dm(L64, dl, ml);
+        jac_R14<double, CD>(load_cam<double>(d.cam64 + (int64_t)CAM_STRIDE * c), L64, S64,
+                            cuboid_face_line<double>(S64, dl, ml), m64, r10, jc10, jg10, jf10);
+#pragma unroll
+        for (int k = 0; k < 4 * SL::NC; ++k) Jc[k] = (T)jc10[k];
+#pragma unroll
+        for (int k = 0; k < 4 * SH_DOF; ++k) Jg[k] = (T)jg10[k];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) Jf[k] = (T)jf10[k];
+      }
     }
   }
   // nearly degenerate image line (relative normal below DEGENERATE_IMAGE_LINE):
@@ -342,7 +384,7 @@ template <int FAM, typename T, int CD> __global__ __launch_bounds__(256) void k_
   if (degenerate || !finite) atomicAdd(&d.scal[SC_NDEG], 1.0);
   // residual in FP64 from the FP64 parameters, robust IRLS scale
   double r64[F::ROWS];
-  residual64<FAM>(d, i, d.cam64, d.pt64, d.ln64, d.pl64, d.vp64, r64);
+  residual64<FAM>(d, i, d.cam64, d.pt64, d.ln64, d.pl64, d.vp64, d.sh64, r64);
   double s = 0;
 #pragma unroll
   for (int k = 0; k < F::ROWS; ++k) s += r64[k] * r64[k];
@@ -378,6 +420,8 @@ void launch_linearize(const Dev& d, hipStream_t s) {
     if (d.fn[6]) k_lin<6, T, CD><<<nblk(d.fn[6], 256), 256, 0, s>>>(d);
     if (d.fn[7]) k_lin<7, T, CD><<<nblk(d.fn[7], 256), 256, 0, s>>>(d);
     if (d.fn[8]) k_lin<8, T, CD><<<nblk(d.fn[8], 256), 256, 0, s>>>(d);
+    if (d.fn[9]) k_lin<9, T, CD><<<nblk(d.fn[9], 256), 256, 0, s>>>(d);
+    if (d.fn[10]) k_lin<10, T, CD><<<nblk(d.fn[10], 256), 256, 0, s>>>(d);
   });
   launch_rel_linearize(d, s);
 }
@@ -390,8 +434,8 @@ template <int FAM> __global__ __launch_bounds__(256) void k_cost(Dev d, int cand
   double e = 0;
   if (i < d.fn[FAM] && !record_masked<FAM>(d, i, d.ffeat[FAM][i])) {
     double r[4];
-    if (candidate) residual64<FAM>(d, i, d.cam64n, d.pt64n, d.ln64n, d.pl64n, d.vp64n, r);
-    else residual64<FAM>(d, i, d.cam64, d.pt64, d.ln64, d.pl64, d.vp64, r);
+    if (candidate) residual64<FAM>(d, i, d.cam64n, d.pt64n, d.ln64n, d.pl64n, d.vp64n, d.sh64n, r);
+    else residual64<FAM>(d, i, d.cam64, d.pt64, d.ln64, d.pl64, d.vp64, d.sh64, r);
     double s = 0;
 #pragma unroll
     for (int k = 0; k < Fam<FAM, 9>::ROWS; ++k) s += r[k] * r[k];
@@ -440,6 +484,8 @@ void launch_cost(const Dev& d, bool candidate, hipStream_t s) {
       case 6: k_cost<6><<<nb, 256, 0, s>>>(d, candidate, d.red + off); break;
       case 7: k_cost<7><<<nb, 256, 0, s>>>(d, candidate, d.red + off); break;
       case 8: k_cost<8><<<nb, 256, 0, s>>>(d, candidate, d.red + off); break;
+      case 9: k_cost<9><<<nb, 256, 0, s>>>(d, candidate, d.red + off); break;
+      case 10: k_cost<10><<<nb, 256, 0, s>>>(d, candidate, d.red + off); break;
     }
     off += (int)nb;
     if (fam == 5) x1 = off;
@@ -457,6 +503,7 @@ void launch_cost(const Dev& d, bool candidate, hipStream_t s) {
     x1 = off;
   }
   for (int fam = 6; fam <= 7; ++fam) go(fam);
+  for (int fam = 9; fam <= 10; ++fam) go(fam);  // surface groups: pixels
   if (x0 < 0) x0 = x1 = 0;
   k_cost_final<<<1, 1024, 0, s>>>(d.red, off, x0, x1, d.scal);
 }
@@ -487,17 +534,245 @@ __device__ __forceinline__ void acc_feature(const Dev& d, int f, A (&V)[NF * (NF
   }
 }
 
+// ---------------------------------------------------------------------------
+// Records of the surface-group families (9, 10: SH_DOF group columns, the largest
+// slots) are read one row at a time wherever they are handled, so that they do not
+// raise the register budget of the kernels shared with the other families.
+template <int FAM, typename T, int CD, int NF, typename A>
+__device__ __forceinline__ void acc_feature_rows(const Dev& d, int f, A (&V)[NF * (NF + 1) / 2], A (&g)[NF]) {
+  using SL = Slot<FAM, CD>;
+  if (!d.fn[FAM]) return;
+  const T* rec = (const T*)d.frec[FAM];
+  const T* res = (const T*)d.fres[FAM];
+  for (int64_t i = d.foff[FAM][f]; i < d.foff[FAM][f + 1]; ++i) {
+#pragma unroll 1
+    for (int row = 0; row < SL::ROWS; ++row) {
+      const T* jf = rec + i * SL::STRIDE + SL::OF + row * NF;
+      const A rr = (A)res[i * SL::ROWS + row];
+      A j[NF];
+#pragma unroll
+      for (int a = 0; a < NF; ++a) j[a] = (A)jf[a];
+#pragma unroll
+      for (int a = 0; a < NF; ++a) {
+        g[a] += j[a] * rr;
+#pragma unroll
+        for (int b2 = a; b2 < NF; ++b2) V[sym<NF>(a, b2)] += j[a] * j[b2];
+      }
+    }
+  }
+}
+
+// U_cc, g_c of one surface-group record
+template <int FAM, typename T, int CD>
+__device__ __forceinline__ void cam_a_rows(const Dev& d, int64_t i, T (&U)[CD * (CD + 1) / 2], T (&g)[CD]) {
+  using SL = Slot<FAM, CD>;
+  const T* sl = (const T*)d.frec[FAM] + i * SL::STRIDE;
+  const T* res = (const T*)d.fres[FAM] + i * SL::ROWS;
+#pragma unroll 1
+  for (int row = 0; row < SL::ROWS; ++row) {
+    T jc[SL::NC];
+#pragma unroll
+    for (int k = 0; k < SL::NC; ++k) jc[k] = sl[SL::OC + row * SL::NC + k];
+    const T rr = res[row];
+#pragma unroll
+    for (int a = 0; a < SL::NC; ++a) {
+      g[a] += jc[a] * rr;
+#pragma unroll
+      for (int b = a; b < SL::NC; ++b) U[sym<CD>(a, b)] += jc[a] * jc[b];
+    }
+  }
+}
+
+// W += J_o^T J_f of one surface-group record, o the camera (OUT 0) or shape (OUT 1) columns
+template <int FAM, int OUT, typename T, int CD, int N, int NF>
+__device__ __forceinline__ void addW_rows(const Dev& d, int64_t i, T (&W)[N][NF]) {
+  using SL = Slot<FAM, CD>;
+  constexpr int NK = OUT == 0 ? SL::NC : SL::NG, O = OUT == 0 ? SL::OC : SL::OG;
+  static_assert(N >= NK, "output rows");
+  const T* sl = (const T*)d.frec[FAM] + i * SL::STRIDE;
+#pragma unroll 1
+  for (int row = 0; row < SL::ROWS; ++row) {
+    T jo[NK], jf[NF];
+#pragma unroll
+    for (int k = 0; k < NK; ++k) jo[k] = sl[O + row * NK + k];
+#pragma unroll
+    for (int k = 0; k < NF; ++k) jf[k] = sl[SL::OF + row * NF + k];
+#pragma unroll
+    for (int a = 0; a < NK; ++a)
+#pragma unroll
+      for (int b = 0; b < NF; ++b) W[a][b] += jo[a] * jf[b];
+  }
+}
+
+// product, first half: q += sum over the feature's surface-group records of J_f^T J_a x
+template <int FAM, typename T, int CD, int NF> __device__ __forceinline__ void mv_first_rows(const Dev& d, int f, const T* x, T (&q)[NF]) {
+  using SL = Slot<FAM, CD>;
+  if (!d.fn[FAM]) return;
+  for (int64_t i = d.foff[FAM][f]; i < d.foff[FAM][f + 1]; ++i) {
+    const T* sl = (const T*)d.frec[FAM] + i * SL::STRIDE;
+    const T* xc = x + CD * d.fcam[FAM][i];
+    const T* xg = x + a_grp(d, 3, d.fgrp[FAM][i]);
+#pragma unroll 1
+    for (int row = 0; row < SL::ROWS; ++row) {
+      T t = 0;
+#pragma unroll
+      for (int k = 0; k < SL::NC; ++k) t += sl[SL::OC + row * SL::NC + k] * xc[k];
+#pragma unroll
+      for (int k = 0; k < SL::NG; ++k) t += sl[SL::OG + row * SL::NG + k] * xg[k];
+#pragma unroll
+      for (int a = 0; a < NF; ++a) q[a] += sl[SL::OF + row * NF + a] * t;
+    }
+  }
+}
+
+// product, second half: y_a += J_a^T (J_a x - J_f s) over the feature's surface-group records
+template <int FAM, typename T, int CD, int NF>
+__device__ __forceinline__ void mv_second_rows(const Dev& d, int f, const T* x, const T (&s)[NF], double* y) {
+  using SL = Slot<FAM, CD>;
+  if (!d.fn[FAM]) return;
+  for (int64_t i = d.foff[FAM][f]; i < d.foff[FAM][f + 1]; ++i) {
+    const T* sl = (const T*)d.frec[FAM] + i * SL::STRIDE;
+    const int ac = CD * d.fcam[FAM][i], ag = a_grp(d, 3, d.fgrp[FAM][i]);
+    T zc[SL::NC], zg[SL::NG];
+#pragma unroll
+    for (int k = 0; k < SL::NC; ++k) zc[k] = 0;
+#pragma unroll
+    for (int k = 0; k < SL::NG; ++k) zg[k] = 0;
+#pragma unroll 1
+    for (int row = 0; row < SL::ROWS; ++row) {
+      T t = 0;
+#pragma unroll
+      for (int k = 0; k < SL::NC; ++k) t += sl[SL::OC + row * SL::NC + k] * x[ac + k];
+#pragma unroll
+      for (int k = 0; k < SL::NG; ++k) t += sl[SL::OG + row * SL::NG + k] * x[ag + k];
+#pragma unroll
+      for (int a = 0; a < NF; ++a) t -= sl[SL::OF + row * NF + a] * s[a];
+#pragma unroll
+      for (int k = 0; k < SL::NC; ++k) zc[k] += sl[SL::OC + row * SL::NC + k] * t;
+#pragma unroll
+      for (int k = 0; k < SL::NG; ++k) zg[k] += sl[SL::OG + row * SL::NG + k] * t;
+    }
+#pragma unroll
+    for (int k = 0; k < SL::NC; ++k) atomicAdd(y + ac + k, (double)zc[k]);
+#pragma unroll
+    for (int k = 0; k < SL::NG; ++k) atomicAdd(y + ag + k, (double)zg[k]);
+  }
+}
+
+// back-substitution: |J h|^2 over the feature's surface-group records (FP64 sums)
+template <int FAM, typename T, int CD, int NF>
+__device__ __forceinline__ void bs_second_rows(const Dev& d, int f, const T* x, const T (&h)[NF], double& jh2) {
+  using SL = Slot<FAM, CD>;
+  if (!d.fn[FAM]) return;
+  for (int64_t i = d.foff[FAM][f]; i < d.foff[FAM][f + 1]; ++i) {
+    const T* sl = (const T*)d.frec[FAM] + i * SL::STRIDE;
+    const T* xc = x + CD * d.fcam[FAM][i];
+    const T* xg = x + a_grp(d, 3, d.fgrp[FAM][i]);
+#pragma unroll 1
+    for (int row = 0; row < SL::ROWS; ++row) {
+      double t = 0;
+#pragma unroll
+      for (int k = 0; k < SL::NC; ++k) t += (double)sl[SL::OC + row * SL::NC + k] * (double)xc[k];
+#pragma unroll
+      for (int k = 0; k < SL::NG; ++k) t += (double)sl[SL::OG + row * SL::NG + k] * (double)xg[k];
+#pragma unroll
+      for (int a = 0; a < NF; ++a) t += (double)sl[SL::OF + row * NF + a] * (double)h[a];
+      jh2 += t * t;
+    }
+  }
+}
+
+// S Z sweeps: q[a][c] += J_f^T J_a Z over the feature's surface-group records (Zr: one panel)
+template <int FAM, typename T, int CD, int NF, int NCOL>
+__device__ __forceinline__ void sz_feat_rows(const Dev& d, int f, const T* Zr, T (&q)[NF][NCOL]) {
+  using SL = Slot<FAM, CD>;
+  if (!d.fn[FAM]) return;
+  for (int64_t i = d.foff[FAM][f]; i < d.foff[FAM][f + 1]; ++i) {
+    const T* sl = (const T*)d.frec[FAM] + i * SL::STRIDE;
+    const T* zc = Zr + (int64_t)CD * d.fcam[FAM][i] * NCOL;
+    const T* zg = Zr + (int64_t)a_grp(d, 3, d.fgrp[FAM][i]) * NCOL;
+#pragma unroll 1
+    for (int row = 0; row < SL::ROWS; ++row) {
+      T t[NCOL];
+#pragma unroll
+      for (int c = 0; c < NCOL; ++c) t[c] = 0;
+#pragma unroll 1
+      for (int k = 0; k < SL::NC; ++k) {
+        const T j = sl[SL::OC + row * SL::NC + k];
+#pragma unroll
+        for (int c = 0; c < NCOL; ++c) t[c] += j * zc[k * NCOL + c];
+      }
+#pragma unroll 1
+      for (int k = 0; k < SL::NG; ++k) {
+        const T j = sl[SL::OG + row * SL::NG + k];
+#pragma unroll
+        for (int c = 0; c < NCOL; ++c) t[c] += j * zg[k * NCOL + c];
+      }
+#pragma unroll
+      for (int a = 0; a < NF; ++a) {
+        const T j = sl[SL::OF + row * NF + a];
+#pragma unroll
+        for (int c = 0; c < NCOL; ++c) q[a][c] += j * t[c];
+      }
+    }
+  }
+}
+
+// S Z sweeps, output rows: one surface-group record, CPL columns of the panel zr (offset
+// to the lane's first column), u = J_a z - J_f s_f; the camera (OUT 0) or shape (OUT 1)
+// rows of J^T u added to acc
+template <int FAM, int OUT, typename T, int CD, int NO, int CPL>
+__device__ __forceinline__ void sz_rec_rows(const Dev& d, int64_t i, const T* zr, const T* s, double (&acc)[NO][CPL]) {
+  using SL = Slot<FAM, CD>;
+  constexpr int NK = OUT == 0 ? SL::NC : SL::NG, O = OUT == 0 ? SL::OC : SL::OG;
+  static_assert(NO >= NK, "output rows");
+  const T* sl = (const T*)d.frec[FAM] + i * SL::STRIDE;
+  const int ac = CD * d.fcam[FAM][i], ag = a_grp(d, 3, d.fgrp[FAM][i]);
+#pragma unroll 1
+  for (int row = 0; row < SL::ROWS; ++row) {
+    T u[CPL];
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) u[c] = 0;
+#pragma unroll 1
+    for (int k = 0; k < SL::NC; ++k) {
+      const T j = sl[SL::OC + row * SL::NC + k];
+#pragma unroll
+      for (int c = 0; c < CPL; ++c) u[c] += j * zr[(int64_t)(ac + k) * SZ_COLS + c];
+    }
+#pragma unroll 1
+    for (int k = 0; k < SL::NG; ++k) {
+      const T j = sl[SL::OG + row * SL::NG + k];
+#pragma unroll
+      for (int c = 0; c < CPL; ++c) u[c] += j * zr[(int64_t)(ag + k) * SZ_COLS + c];
+    }
+#pragma unroll
+    for (int a = 0; a < SL::NF; ++a) {
+      const T j = sl[SL::OF + row * SL::NF + a];
+#pragma unroll
+      for (int c = 0; c < CPL; ++c) u[c] -= j * s[a * SZ_COLS + c];
+    }
+#pragma unroll
+    for (int k = 0; k < NK; ++k) {
+      const T j = sl[O + row * NK + k];
+#pragma unroll
+      for (int c = 0; c < CPL; ++c) acc[k][c] += (double)(j * u[c]);
+    }
+  }
+}
+
 template <typename T, int CD, int NF, typename A> __device__ __forceinline__ void acc_feature_all(const Dev& d, int f, A (&V)[NF * (NF + 1) / 2], A (&g)[NF]) {
   if constexpr (NF == 3) {
     acc_feature<1, T, CD, 3>(d, f, V, g);
     acc_feature<3, T, CD, 3>(d, f, V, g);
     acc_feature<6, T, CD, 3>(d, f, V, g);
     acc_feature<8, T, CD, 3>(d, f, V, g);
+    acc_feature_rows<9, T, CD, 3>(d, f, V, g);
   } else {
     acc_feature<2, T, CD, 4>(d, f, V, g);
     acc_feature<4, T, CD, 4>(d, f, V, g);
     acc_feature<5, T, CD, 4>(d, f, V, g);
     acc_feature<7, T, CD, 4>(d, f, V, g);
+    acc_feature_rows<10, T, CD, 4>(d, f, V, g);
   }
 }
 
@@ -772,6 +1047,10 @@ template <typename T, int CD> __global__ __launch_bounds__(256) void k_cam_a(Dev
       const int k = d.cmal[1][j];
       if (k >= 0)
         cam_a_slot<3, T, CD>((const T*)d.cmrec[3] + (int64_t)k * Slot<3, CD>::STRIDE, (const T*)d.cmres[3] + (int64_t)k * Slot<3, CD>::ROWS, U, g);
+      if (d.shal_p) {  // the aligned point-on-shape record
+        const int k9 = d.shal_p[j];
+        if (k9 >= 0) cam_a_rows<9, T, CD>(d, k9, U, g);
+      }
     }
   }
   if (d.fn[6]) {
@@ -784,6 +1063,10 @@ template <typename T, int CD> __global__ __launch_bounds__(256) void k_cam_a(Dev
       const int k = d.cmal[2][j];
       if (k >= 0)
         cam_a_slot<4, T, CD>((const T*)d.cmrec[4] + (int64_t)k * Slot<4, CD>::STRIDE, (const T*)d.cmres[4] + (int64_t)k * Slot<4, CD>::ROWS, U, g);
+      if (d.shal_l) {  // the aligned line-on-cuboid record
+        const int k10 = d.shal_l[j];
+        if (k10 >= 0) cam_a_rows<10, T, CD>(d, k10, U, g);
+      }
     }
   }
   if (d.fn[7]) {
@@ -877,6 +1160,7 @@ void launch_camera_pass_a(const Dev& d, hipStream_t s) {
     if (d.nc) k_cam_a<T, CD><<<d.nc, 256, 0, s>>>(d);
     if (d.ng + d.nv) k_grp_a<T, CD><<<d.ng + d.nv, 256, 0, s>>>(d);
   });
+  launch_shape_pass_a(d, s);
   launch_rel_a(d, s);
 }
 
@@ -968,6 +1252,10 @@ template <typename T, int CD> __global__ __launch_bounds__(256) void k_cam_b(Dev
       addW_slot<1, T, CD, 3>((const T*)d.cmrec[1] + (int64_t)j * Slot<1, CD>::STRIDE, W);
       const int k = d.cmal[1][j];
       if (k >= 0) addW_slot<3, T, CD, 3>((const T*)d.cmrec[3] + (int64_t)k * Slot<3, CD>::STRIDE, W);
+      if (d.shal_p) {
+        const int k9 = d.shal_p[j];
+        if (k9 >= 0) addW_rows<9, 0, T, CD, CD, 3>(d, k9, W);
+      }
       pair_contrib<T, CD, 3>(d, d.cmfeat[1][j], W, C, bb);
     }
   }
@@ -993,6 +1281,10 @@ template <typename T, int CD> __global__ __launch_bounds__(256) void k_cam_b(Dev
       addW_slot<2, T, CD, 4>((const T*)d.cmrec[2] + (int64_t)j * Slot<2, CD>::STRIDE, W);
       const int k = d.cmal[2][j];
       if (k >= 0) addW_slot<4, T, CD, 4>((const T*)d.cmrec[4] + (int64_t)k * Slot<4, CD>::STRIDE, W);
+      if (d.shal_l) {
+        const int k10 = d.shal_l[j];
+        if (k10 >= 0) addW_rows<10, 0, T, CD, CD, 4>(d, k10, W);
+      }
       pair_contrib<T, CD, 4>(d, d.cmfeat[2][j], W, C, bb);
     }
   }
@@ -1093,6 +1385,7 @@ void launch_camera_pass_b(const Dev& d, double lambda, hipStream_t s) {
     if (d.nc) k_cam_b<T, CD><<<d.nc, 256, 0, s>>>(d, lambda);
     if (d.ng + d.nv) k_grp_b<T, CD><<<d.ng + d.nv, 256, 0, s>>>(d, lambda);
   });
+  launch_shape_pass_b(d, lambda, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -1124,10 +1417,14 @@ template <int CD> __global__ void k_precond_bj(Dev d) {
   if (i < d.nc) invert_block<CD>(d.Scam + (int64_t)CD * CD * i, d.Mcam + (int64_t)CD * CD * i);
   else if (i < d.nc + d.ng) invert_block<3>(d.Spl + 9 * (i - d.nc), d.Mpl + 9 * (i - d.nc));
   else if (i < d.nc + d.ng + d.nv) invert_block<2>(d.Svp + 4 * (i - d.nc - d.ng), d.Mvp + 4 * (i - d.nc - d.ng));
+  else if (i < d.nc + d.ng + d.nv + d.ns) {
+    const int q = i - d.nc - d.ng - d.nv;
+    invert_block<SH_DOF>(d.Ssh + SH_DOF * SH_DOF * q, d.Msh + SH_DOF * SH_DOF * q);
+  }
 }
 
 void launch_precond_blockjacobi(const Dev& d, hipStream_t s) {
-  const int n = d.nc + d.ng + d.nv;
+  const int n = d.nc + d.ng + d.nv + d.ns;
   if (!n) return;
   if (d.CD == 9) k_precond_bj<9><<<nblk(n, 64), 64, 0, s>>>(d);
   else k_precond_bj<6><<<nblk(n, 64), 64, 0, s>>>(d);
@@ -1225,11 +1522,13 @@ template <typename T, int CD, int NF> __device__ __forceinline__ void mv_feature
     mv_first<3, T, CD, 3>(d, f, x, q);
     mv_first<6, T, CD, 3>(d, f, x, q);
     mv_first<8, T, CD, 3>(d, f, x, q);
+    mv_first_rows<9, T, CD, 3>(d, f, x, q);
   } else {
     mv_first<2, T, CD, 4>(d, f, x, q);
     mv_first<4, T, CD, 4>(d, f, x, q);
     mv_first<5, T, CD, 4>(d, f, x, q);
     mv_first<7, T, CD, 4>(d, f, x, q);
+    mv_first_rows<10, T, CD, 4>(d, f, x, q);
   }
   T s[NF];
   apply_vinv<T, NF>(d, f, q, s);
@@ -1238,11 +1537,13 @@ template <typename T, int CD, int NF> __device__ __forceinline__ void mv_feature
     mv_second<3, T, CD, 3>(d, f, x, s, y);
     mv_second<6, T, CD, 3>(d, f, x, s, y);
     mv_second<8, T, CD, 3>(d, f, x, s, y);
+    mv_second_rows<9, T, CD, 3>(d, f, x, s, y);
   } else {
     mv_second<2, T, CD, 4>(d, f, x, s, y);
     mv_second<4, T, CD, 4>(d, f, x, s, y);
     mv_second<5, T, CD, 4>(d, f, x, s, y);
     mv_second<7, T, CD, 4>(d, f, x, s, y);
+    mv_second_rows<10, T, CD, 4>(d, f, x, s, y);
   }
 }
 
@@ -1256,11 +1557,13 @@ template <typename T, int CD, int NF> __device__ __forceinline__ void mv_feature
     mv_first<3, T, CD, 3>(d, f, x, q);
     mv_first<6, T, CD, 3>(d, f, x, q);
     mv_first<8, T, CD, 3>(d, f, x, q);
+    mv_first_rows<9, T, CD, 3>(d, f, x, q);
   } else {
     mv_first<2, T, CD, 4>(d, f, x, q);
     mv_first<4, T, CD, 4>(d, f, x, q);
     mv_first<5, T, CD, 4>(d, f, x, q);
     mv_first<7, T, CD, 4>(d, f, x, q);
+    mv_first_rows<10, T, CD, 4>(d, f, x, q);
   }
   T sv[NF];
   apply_vinv<T, NF>(d, f, q, sv);
@@ -1578,7 +1881,8 @@ __device__ __forceinline__ double* acc_set(const Dev& d, int k) { return d.scal 
 template <int CD> __device__ __forceinline__ void entry_block(const Dev& d, int e, int& o, int& n, const double*& M) {
   if (e < d.offPl) { const int b = e / CD; o = CD * b; n = CD; M = d.Mcam + (int64_t)CD * CD * b; }
   else if (e < d.offVp) { const int g = (e - d.offPl) / 3; o = d.offPl + 3 * g; n = 3; M = d.Mpl + 9 * g; }
-  else { const int v = (e - d.offVp) / 2; o = d.offVp + 2 * v; n = 2; M = d.Mvp + 4 * v; }
+  else if (e < d.offSh) { const int v = (e - d.offVp) / 2; o = d.offVp + 2 * v; n = 2; M = d.Mvp + 4 * v; }
+  else { const int q = (e - d.offSh) / SH_DOF; o = d.offSh + SH_DOF * q; n = SH_DOF; M = d.Msh + SH_DOF * SH_DOF * q; }
 }
 
 // Accumulator slot of dst (a scalar of d.scal, or an entry of Z^T b) in the deterministic
@@ -2079,6 +2383,7 @@ __global__ void k_gauge_basis(Dev d) {
 void launch_gauge_basis(const Dev& d, hipStream_t s) {
   const int nb = d.nc + d.ng + d.nv;
   if (nb > 0) k_gauge_basis<<<nblk(nb, 64), 64, 0, s>>>(d);
+  launch_shape_gauge(d, s);
 }
 
 // ---- S Z for the coarse columns ---------------------------------------------
@@ -2251,11 +2556,13 @@ template <typename T, int CD, int NF> __device__ __forceinline__ void sz_feature
     sz_feat_family<3, T, CD, 3>(d, f, Zr, q);
     sz_feat_family<6, T, CD, 3>(d, f, Zr, q);
     sz_feat_family<8, T, CD, 3>(d, f, Zr, q);
+    sz_feat_rows<9, T, CD, 3, SZ_COLS>(d, f, Zr, q);
   } else {
     sz_feat_family<2, T, CD, 4>(d, f, Zr, q);
     sz_feat_family<4, T, CD, 4>(d, f, Zr, q);
     sz_feat_family<5, T, CD, 4>(d, f, Zr, q);
     sz_feat_family<7, T, CD, 4>(d, f, Zr, q);
+    sz_feat_rows<10, T, CD, 4, SZ_COLS>(d, f, Zr, q);
   }
   for (int c = 0; c < SZ_COLS; ++c) {
     T qc[NF], sc[NF];
@@ -2493,6 +2800,10 @@ __global__ __launch_bounds__(256) void k_sz_cam(Dev d, const T* Zr, const T* sfp
         z_cols<3, CPL>(zr, a_grp(d, Fam<3, CD>::GT, d.cmgrp[3][k]), zg);
         sz_rec_cols<3, 0, T, CD>((const T*)d.cmrec[3] + (int64_t)k * Slot<3, CD>::STRIDE, zc, zg, sp + (int64_t)f * 3 * SZ_COLS, acc);
       }
+      if (d.shal_p) {
+        const int k9 = d.shal_p[j];
+        if (k9 >= 0) sz_rec_rows<9, 0, T, CD>(d, k9, zr, sp + (int64_t)f * 3 * SZ_COLS, acc);
+      }
     }
   if (d.fn[6])
     for (int j = d.px_off[c] + rs; j < d.px_off[c + 1]; j += R)
@@ -2507,6 +2818,10 @@ __global__ __launch_bounds__(256) void k_sz_cam(Dev d, const T* Zr, const T* sfp
         T zg[3][CPL];
         z_cols<3, CPL>(zr, a_grp(d, Fam<4, CD>::GT, d.cmgrp[4][k]), zg);
         sz_rec_cols<4, 0, T, CD>((const T*)d.cmrec[4] + (int64_t)k * Slot<4, CD>::STRIDE, zc, zg, sl + (int64_t)f * 4 * SZ_COLS, acc);
+      }
+      if (d.shal_l) {
+        const int k10 = d.shal_l[j];
+        if (k10 >= 0) sz_rec_rows<10, 0, T, CD>(d, k10, zr, sl + (int64_t)f * 4 * SZ_COLS, acc);
       }
     }
   if (d.fn[7])
@@ -2732,9 +3047,13 @@ template <typename T, int CD> void launch_det_rows(const Dev& d, const double* d
   if (d.ng + d.nv) k_det_grp<T, CD><<<d.ng + d.nv, 256, 0, s>>>(d, done);
 }
 
+template <typename T, int CD, int L, int CPL>
+__global__ __launch_bounds__(256) void k_sz_shape(Dev d, const T* Zr, const T* sfp, const T* sfl, double lam);
+
 template <typename T, int CD, int L, int CPL> static void launch_sz_out(const Dev& d, const T* Zr, const T* sfp, const T* sfl, double lambda, hipStream_t s) {
   if (d.nc) k_sz_cam<T, CD, L, CPL><<<d.nc, 256, 0, s>>>(d, Zr, sfp, sfl, lambda);
   if (d.ng + d.nv) k_sz_grp<T, CD, L, CPL><<<d.ng + d.nv, 256, 0, s>>>(d, Zr, sfp, sfl, lambda);
+  if (d.ns) k_sz_shape<T, CD, L, CPL><<<d.ns, 256, 0, s>>>(d, Zr, sfp, sfl, lambda);
 }
 
 template <typename T, int CD> static void launch_sz(const Dev& d, double lambda, hipStream_t s) {
@@ -2746,7 +3065,7 @@ template <typename T, int CD> static void launch_sz(const Dev& d, double lambda,
   // the closed form needs J z = 0 for the gauge directions: not so for the VP
   // 3-vector (turns with the world) nor for the metric 3D point-to-plane distance
   // (scales with the world)
-  const bool closed = d.fn[5] == 0 && d.fn[8] == 0;
+  const bool closed = d.fn[5] == 0 && d.fn[8] == 0 && d.ns == 0;
   k_sz_rows<T><<<nblk(P.z * SZ_PANELS, 256), 256, 0, s>>>(d, Zr, closed ? 1 : 0);
   for (int pn = 0; pn < SZ_PANELS && sz_col(pn, 0) < d.coarse_k; ++pn) {
     T *zp = Zr + pn * P.z, *pp = sfp + pn * P.p, *lp = sfl + pn * P.l;
@@ -2819,11 +3138,13 @@ template <typename T, int CD, int NF> __device__ __forceinline__ void backsub_on
     mv_first<3, T, CD, 3>(d, f, x, q);
     mv_first<6, T, CD, 3>(d, f, x, q);
     mv_first<8, T, CD, 3>(d, f, x, q);
+    mv_first_rows<9, T, CD, 3>(d, f, x, q);
   } else {
     mv_first<2, T, CD, 4>(d, f, x, q);
     mv_first<4, T, CD, 4>(d, f, x, q);
     mv_first<5, T, CD, 4>(d, f, x, q);
     mv_first<7, T, CD, 4>(d, f, x, q);
+    mv_first_rows<10, T, CD, 4>(d, f, x, q);
   }
   const T* g = (const T*)(NF == 3 ? d.gp : d.gl) + (int64_t)NF * f;
 #pragma unroll
@@ -2841,11 +3162,13 @@ template <typename T, int CD, int NF> __device__ __forceinline__ void backsub_on
     bs_second<3, T, CD, 3>(d, f, x, h, jh2);
     bs_second<6, T, CD, 3>(d, f, x, h, jh2);
     bs_second<8, T, CD, 3>(d, f, x, h, jh2);
+    bs_second_rows<9, T, CD, 3>(d, f, x, h, jh2);
   } else {
     bs_second<2, T, CD, 4>(d, f, x, h, jh2);
     bs_second<4, T, CD, 4>(d, f, x, h, jh2);
     bs_second<5, T, CD, 4>(d, f, x, h, jh2);
     bs_second<7, T, CD, 4>(d, f, x, h, jh2);
+    bs_second_rows<10, T, CD, 4>(d, f, x, h, jh2);
   }
 }
 
@@ -3131,9 +3454,12 @@ __global__ void k_retract(Dev d) {
   }
 }
 
+__global__ void k_shape_retract(Dev d);
+
 void launch_retract(const Dev& d, hipStream_t s) {
   const int n = d.nc + d.np + d.nl + d.ng + d.nv;
   if (n) k_retract<<<nblk(n, 256), 256, 0, s>>>(d);
+  if (d.ns) k_shape_retract<<<nblk(d.ns, 64), 64, 0, s>>>(d);
 }
 
 __global__ void k_zero(unsigned char* p, size_t n) {
@@ -3198,7 +3524,7 @@ template <typename T, int NF> __global__ __launch_bounds__(256) void k_feat_stat
   double dsum = 0.0;
   for (int32_t r = r0; r < r1; ++r) {
     double res[4];
-    residual64<FAM>(d, r, d.cam64, d.pt64, d.ln64, d.pl64, d.vp64, res);
+    residual64<FAM>(d, r, d.cam64, d.pt64, d.ln64, d.pl64, d.vp64, d.sh64, res);
     double s = 0.0;
 #pragma unroll
     for (int k = 0; k < Fam<FAM, 9>::ROWS; ++k) s += res[k] * res[k];
@@ -3243,6 +3569,261 @@ void launch_feature_stats(const Dev& d, int32_t* n_active, int32_t* n_obs, doubl
 
 void launch_zero(void* p, size_t bytes, hipStream_t s) {
   if (bytes) k_zero<<<256, 256, 0, s>>>((unsigned char*)p, bytes);
+}
+
+// ---------------------------------------------------------------------------
+// surface groups (App. B): their blocks of the reduced system, one workgroup per shape
+
+// U_ss, g_s of one record (shape columns, one row at a time)
+template <int FAM, typename T, int CD>
+__device__ __forceinline__ void shape_a_rows(const Dev& d, int64_t i, T (&U)[SH_DOF * (SH_DOF + 1) / 2], T (&g)[SH_DOF]) {
+  using SL = Slot<FAM, CD>;
+  const T* sl = (const T*)d.frec[FAM] + i * SL::STRIDE;
+  const T* res = (const T*)d.fres[FAM] + i * SL::ROWS;
+#pragma unroll 1
+  for (int row = 0; row < SL::ROWS; ++row) {
+    T jg[SH_DOF];
+#pragma unroll
+    for (int k = 0; k < SH_DOF; ++k) jg[k] = sl[SL::OG + row * SH_DOF + k];
+    const T rr = res[row];
+#pragma unroll
+    for (int a = 0; a < SH_DOF; ++a) {
+      g[a] += jg[a] * rr;
+#pragma unroll
+      for (int b = a; b < SH_DOF; ++b) U[sym<SH_DOF>(a, b)] += jg[a] * jg[b];
+    }
+  }
+}
+
+template <typename T, int CD> __global__ __launch_bounds__(256) void k_shape_a(Dev d) {
+  constexpr int NS = SH_DOF * (SH_DOF + 1) / 2, K = NS + SH_DOF;
+  __shared__ T lds[(4 + 1) * K];
+  const int q = blockIdx.x;
+  T acc[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) acc[k] = 0;
+  T(&U)[NS] = *reinterpret_cast<T(*)[NS]>(acc);
+  T(&g)[SH_DOF] = *reinterpret_cast<T(*)[SH_DOF]>(acc + NS);
+  if (d.fn[9])
+    for (int j = d.shp_off[q] + threadIdx.x; j < d.shp_off[q + 1]; j += blockDim.x) {
+      const int f = d.shp[j];
+      for (int64_t i = d.foff[9][f]; i < d.foff[9][f + 1]; ++i) shape_a_rows<9, T, CD>(d, i, U, g);
+    }
+  if (d.fn[10])
+    for (int j = d.shl_off[q] + threadIdx.x; j < d.shl_off[q + 1]; j += blockDim.x) {
+      const int f = d.shl[j];
+      for (int64_t i = d.foff[10][f]; i < d.foff[10][f + 1]; ++i) shape_a_rows<10, T, CD>(d, i, U, g);
+    }
+  T* o = block_sum_arr<T, K>(acc, lds);
+  const int e0 = a_grp(d, 3, q);
+  for (int k = threadIdx.x; k < SH_DOF * SH_DOF; k += blockDim.x)
+    d.Ush[(int64_t)SH_DOF * SH_DOF * q + k] = (double)o[sym<SH_DOF>(k / SH_DOF, k % SH_DOF)];
+  for (int k = threadIdx.x; k < SH_DOF; k += blockDim.x) {
+    d.gA[e0 + k] = (double)o[NS + k];
+    d.DA[e0 + k] = fmin(fmax((double)o[sym<SH_DOF>(k, k)], 1e-6), 1e32);
+  }
+}
+
+template <typename T, int CD> __global__ __launch_bounds__(256) void k_shape_b(Dev d, double lam) {
+  constexpr int NS = SH_DOF * (SH_DOF + 1) / 2, K = NS + SH_DOF;
+  __shared__ T lds[(4 + 1) * K];
+  const int q = blockIdx.x;
+  T acc[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) acc[k] = 0;
+  T* C = acc;
+  T* bb = acc + NS;
+  if (d.fn[9])
+    for (int j = d.shp_off[q] + threadIdx.x; j < d.shp_off[q + 1]; j += blockDim.x) {
+      const int f = d.shp[j];
+      T W[SH_DOF][3];
+#pragma unroll
+      for (int a = 0; a < SH_DOF; ++a) W[a][0] = W[a][1] = W[a][2] = 0;
+      for (int64_t i = d.foff[9][f]; i < d.foff[9][f + 1]; ++i) addW_rows<9, 1, T, CD, SH_DOF, 3>(d, i, W);
+      pair_contrib<T, SH_DOF, 3>(d, f, W, C, bb);
+    }
+  if (d.fn[10])
+    for (int j = d.shl_off[q] + threadIdx.x; j < d.shl_off[q + 1]; j += blockDim.x) {
+      const int f = d.shl[j];
+      T W[SH_DOF][4];
+#pragma unroll
+      for (int a = 0; a < SH_DOF; ++a) W[a][0] = W[a][1] = W[a][2] = W[a][3] = 0;
+      for (int64_t i = d.foff[10][f]; i < d.foff[10][f + 1]; ++i) addW_rows<10, 1, T, CD, SH_DOF, 4>(d, i, W);
+      pair_contrib<T, SH_DOF, 4>(d, f, W, C, bb);
+    }
+  T* o = block_sum_arr<T, K>(acc, lds);
+  const int e0 = a_grp(d, 3, q);
+  for (int k = threadIdx.x; k < SH_DOF * SH_DOF; k += blockDim.x) {
+    const int a = k / SH_DOF, b = k % SH_DOF;
+    const int64_t idx = (int64_t)SH_DOF * SH_DOF * q + k;
+    double v = d.Ush[idx] + (double)o[sym<SH_DOF>(a, b)];
+    if (a == b) v += lam * d.DA[e0 + a];
+    d.Ssh[idx] = v;
+  }
+  for (int k = threadIdx.x; k < SH_DOF; k += blockDim.x) d.bA[e0 + k] = -d.gA[e0 + k] + (double)o[NS + k];
+}
+
+void launch_shape_pass_a(const Dev& d, hipStream_t s) {
+  if (d.ns) BA_DISPATCH_T_CD(d, k_shape_a<T, CD><<<d.ns, 256, 0, s>>>(d));
+}
+
+void launch_shape_pass_b(const Dev& d, double lambda, hipStream_t s) {
+  if (d.ns) BA_DISPATCH_T_CD(d, k_shape_b<T, CD><<<d.ns, 256, 0, s>>>(d, lambda));
+}
+
+// S Z rows of one shape (a workgroup per shape, as k_sz_grp for planes)
+template <typename T, int CD, int L, int CPL>
+__global__ __launch_bounds__(256) void k_sz_shape(Dev d, const T* Zr, const T* sfp, const T* sfl, double lam) {
+  constexpr int R = 256 / L, NCOL = L * CPL;
+  __shared__ double lds[4 * SH_DOF * NCOL];
+  const int q = blockIdx.x, col = (threadIdx.x % L) * CPL, rs = threadIdx.x / L;
+  const SzPanels P = sz_panels(d);
+  const int pn = col / SZ_COLS, pc = col % SZ_COLS;
+  const T* zr = Zr + pn * P.z + pc;
+  const T* sp = sfp + pn * P.p + pc;
+  const T* sl = sfl + pn * P.l + pc;
+  double acc[SH_DOF][CPL];
+#pragma unroll
+  for (int k = 0; k < SH_DOF; ++k)
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) acc[k][c] = 0;
+  if (d.fn[9])
+    for (int j = d.shp_off[q] + rs; j < d.shp_off[q + 1]; j += R) {
+      const int f = d.shp[j];
+      for (int64_t i = d.foff[9][f]; i < d.foff[9][f + 1]; ++i)
+        sz_rec_rows<9, 1, T, CD>(d, i, zr, sp + (int64_t)f * 3 * SZ_COLS, acc);
+    }
+  if (d.fn[10])
+    for (int j = d.shl_off[q] + rs; j < d.shl_off[q + 1]; j += R) {
+      const int f = d.shl[j];
+      for (int64_t i = d.foff[10][f]; i < d.foff[10][f + 1]; ++i)
+        sz_rec_rows<10, 1, T, CD>(d, i, zr, sl + (int64_t)f * 4 * SZ_COLS, acc);
+    }
+  const int e0 = a_grp(d, 3, q);
+  sz_block_sum<SH_DOF, L, CPL>(acc, lds, [&](int row, int cc, double v) {
+    const int col = sz_col(cc / SZ_COLS, cc % SZ_COLS);
+    if (col < 0 || col >= d.coarse_k) return;
+    const int e = e0 + row;
+    d.SZc[(int64_t)col * d.nA + e] = v + lam * d.DA[e] * d.Zc[(int64_t)col * d.nA + e];
+  });
+}
+
+// x [+] h of every shape (the tangent updates of ba_shape.h), one thread per shape
+__global__ void k_shape_retract(Dev d) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= d.ns) return;
+  const double* P = d.sh64 + (int64_t)SH_STRIDE * q;
+  double* o = d.sh64n + (int64_t)SH_STRIDE * q;
+  const double* h = d.x + d.offSh + SH_DOF * q;
+  for (int k = 0; k < SH_STRIDE; ++k) o[k] = P[k];
+  const int type = shape_type(P);
+  auto rot_right = [&](const double* w) {  // R' = R Exp(w), R row-major in P[0..8]
+    double E[9];
+    so3_exp(w, E);
+    for (int r = 0; r < 3; ++r)
+      for (int k = 0; k < 3; ++k) o[3 * r + k] = P[3 * r] * E[k] + P[3 * r + 1] * E[3 + k] + P[3 * r + 2] * E[6 + k];
+  };
+  if (type == SH_SPHERE) {
+    for (int k = 0; k < 3; ++k) o[k] = P[k] + h[k];
+    o[3] = P[3] + h[3];
+  } else if (type == SH_CYLINDER) {
+    double E[9];
+    so3_exp(h, E);
+    // U' = U E with U = [u1 u2 u3] (columns stored consecutively), as for the lines
+    for (int col = 0; col < 3; ++col)
+      for (int r = 0; r < 3; ++r) o[3 * col + r] = P[r] * E[col] + P[3 + r] * E[3 + col] + P[6 + r] * E[6 + col];
+    const double cph = cos(h[3]), sph = sin(h[3]);
+    o[9] = P[9] * cph - P[10] * sph;
+    o[10] = P[9] * sph + P[10] * cph;
+    o[11] = P[11] + h[4];
+  } else if (type == SH_CONE) {
+    for (int k = 0; k < 3; ++k) o[k] = P[k] + h[k];
+    s2_retract(P + 3, P + 6, P + 9, h[3], h[4], o + 3);
+    s2_basis(o + 3, o + 6, o + 9);
+    o[12] = P[12] + h[5];
+  } else if (type == SH_ELLIPSOID) {
+    rot_right(h);
+    for (int k = 0; k < 3; ++k) {
+      o[9 + k] = P[9 + k] + h[3 + k];
+      o[12 + k] = P[12 + k] + h[6 + k];
+    }
+  } else {
+    rot_right(h);
+    for (int k = 0; k < 6; ++k) o[9 + k] = P[9 + k] + h[3 + k];
+  }
+}
+
+// similarity-gauge rows of the shapes (rotation e_k about the origin, translation e_k,
+// scale), the motion of each shape's tangent coordinates under the world motion that
+// moves the cameras and groups of k_gauge_basis (one thread per shape)
+__global__ void k_shape_gauge(Dev d) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= d.ns) return;
+  const double* P = d.sh64 + (int64_t)SH_STRIDE * q;
+  double g[SH_DOF][COARSE_GAUGE];
+  for (int r = 0; r < SH_DOF; ++r)
+    for (int c = 0; c < COARSE_GAUGE; ++c) g[r][c] = 0.0;
+  const int type = shape_type(P);
+  // a point c of the shape: e_k x c (rotation), e_k (translation), c (scale)
+  auto point_rows = [&](int r0, const double* c) {
+    for (int k = 0; k < 3; ++k) {
+      double e[3] = {0, 0, 0}, ec[3];
+      e[k] = 1.0;
+      cross3(e, c, ec);
+      for (int i = 0; i < 3; ++i) {
+        g[r0 + i][k] = ec[i];
+        g[r0 + i][3 + k] = e[i];
+        g[r0 + i][6] = c[i];
+      }
+    }
+  };
+  if (type == SH_SPHERE) {
+    point_rows(0, P);
+    g[3][6] = 1.0;
+  } else if (type == SH_CYLINDER) {
+    const double *u1 = P, *u2 = P + 3, *u3 = P + 6, w1 = P[9], w2 = P[10];
+    const double kap = w2 / w1, wn = w1 * w1 / (w1 * w1 + w2 * w2);
+    for (int k = 0; k < 3; ++k) {
+      // rotation: U <- Exp(e_k) U = U Exp(U^T e_k)
+      g[0][k] = u1[k]; g[1][k] = u2[k]; g[2][k] = u3[k];
+      // translation: the foot moves by e_k - (e_k . u1) u1
+      g[0][3 + k] = fabs(kap) > 1e-12 ? -u2[k] / kap : 0.0;
+      g[3][3 + k] = u3[k] * wn;
+    }
+    g[3][6] = kap * wn;  // scale: the foot (w2 / w1) u3 scales
+    g[4][6] = 1.0;
+  } else if (type == SH_CONE) {
+    point_rows(0, P);
+    const double* ax = P + 3;
+    for (int k = 0; k < 3; ++k) {
+      double e[3] = {0, 0, 0}, ea[3];
+      e[k] = 1.0;
+      cross3(e, ax, ea);
+      g[3][k] = dot3(P + 6, ea);
+      g[4][k] = dot3(P + 9, ea);
+    }
+  } else if (type == SH_ELLIPSOID) {
+    for (int k = 0; k < 3; ++k)
+      for (int i = 0; i < 3; ++i) g[i][k] = P[3 * k + i];  // R^T e_k
+    point_rows(3, P + 9);
+    for (int i = 0; i < 3; ++i) g[6 + i][6] = 1.0;
+  } else {
+    for (int k = 0; k < 3; ++k)
+      for (int i = 0; i < 3; ++i) g[i][k] = P[3 * k + i];
+    for (int f = 0; f < 6; ++f) {
+      double n[3];
+      cuboid_normal(P, f, n);
+      for (int k = 0; k < 3; ++k) g[3 + f][3 + k] = -n[k];
+      g[3 + f][6] = P[9 + f];
+    }
+  }
+  const int e0 = a_grp(d, 3, q);
+  for (int c = 0; c < COARSE_GAUGE; ++c)
+    for (int r = 0; r < SH_DOF; ++r) d.Zc[(int64_t)c * d.nA + e0 + r] = g[r][c];
+}
+
+void launch_shape_gauge(const Dev& d, hipStream_t s) {
+  if (d.ns) k_shape_gauge<<<nblk(d.ns, 64), 64, 0, s>>>(d);
 }
 
 }  // namespace ba

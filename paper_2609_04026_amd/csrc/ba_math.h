@@ -626,3 +626,5 @@ template <typename S> BA_HD void loss_eval(int kind, S scale, S s, S& rho, S& dr
 }
 
 }  // namespace ba
+
+#include "ba_shape.h"

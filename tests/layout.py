@@ -46,13 +46,36 @@ def vp_slot(st, v):
     return s
 
 
+def sh_slot(st, i):
+    """Shape i in the device layout (SH_STRIDE = 16 doubles, the type at [15])."""
+    from oracle import shapes as S
+    sh = st.sh
+    s = np.zeros(16)
+    t = int(sh.type[i])
+    s[15] = t
+    if t == S.SPHERE:
+        s[0:3], s[3] = sh.c[i], sh.q[i, 0]
+    elif t == S.CYLINDER:
+        U = sh.R[i]
+        s[0:3], s[3:6], s[6:9] = U[:, 0], U[:, 1], U[:, 2]
+        s[9:11], s[11] = sh.w[i], sh.q[i, 0]
+    elif t == S.CONE:
+        B = model.s2_basis(sh.d[i])
+        s[0:3], s[3:6], s[6:9], s[9:12], s[12] = sh.c[i], sh.d[i], B[:, 0], B[:, 1], sh.q[i, 0]
+    elif t == S.ELLIPSOID:
+        s[0:9], s[9:12], s[12:15] = sh.R[i].reshape(9), sh.c[i], sh.q[i, 0:3]
+    else:
+        s[0:9], s[9:15] = sh.R[i].reshape(9), sh.q[i, 0:6]
+    return s
+
+
 def shifted_meas(fam, rec, i, cx, cy):
     """Measurement of record i as the library stores it (shifted by the
     principal point; the observed line of R6 normalised)."""
     m = np.zeros(4)
     if fam == "R1":
         m[0:2] = rec["meas"][i] - [cx, cy]
-    elif fam in ("R2", "R4"):
+    elif fam in ("R2", "R4", "R14"):
         m[0:4] = rec["meas"][i] - [cx, cy, cx, cy]
     elif fam == "R6":
         e = rec["meas"][i] - [cx, cy, cx, cy]

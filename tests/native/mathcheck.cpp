@@ -76,3 +76,50 @@ extern "C" void mc_residual(int fam, int fp64, const double* cam, const double* 
   if (fp64) res<double>(fam, cam, pt, ln, pl, vp, meas, r);
   else res<float>(fam, cam, pt, ln, pl, vp, meas, r);
 }
+
+// R13 / R14: one record against a shape in its device layout (SH_STRIDE doubles);
+// the cuboid face is chosen in FP64, as the library does.  Jg is 4 x SH_DOF.
+namespace {
+template <typename S, int CD>
+int eval_shape(int fam, const double* cam, const double* pt, const double* ln, const double* sh, const double* meas,
+               double* r, double* Jc, double* Jg, double* Jf) {
+  S rr[4] = {0, 0, 0, 0}, jc[4 * 9] = {0}, jg[4 * SH_DOF] = {0}, jf[4 * 4] = {0}, m[4];
+  S shp[SH_STRIDE];
+  for (int k = 0; k < 4; ++k) m[k] = (S)meas[k];
+  for (int k = 0; k < SH_STRIDE; ++k) shp[k] = (S)sh[k];
+  Cam<S> C = load_cam<S>(cam);
+  int rows = 0, nc = 0, nf = 0, face = 0;
+  if (fam == 13) {
+    S X[3] = {(S)pt[0], (S)pt[1], (S)pt[2]};
+    if (shape_type(sh) == SH_CUBOID) face = cuboid_face<double>(sh, pt);
+    jac_R13<S, CD>(C, X, shp, face, rr, jc, jg, jf);
+    rows = 2; nc = CamCols<CD>::PT; nf = 3;
+  } else if (fam == 14) {
+    Line<S> L = load_line<S>(ln);
+    const Line<double> L64 = load_line<double>(ln);
+    double d[3], mm[3];
+    line_dm(L64, d, mm);
+    face = cuboid_face_line<double>(sh, d, mm);
+    jac_R14<S, CD>(C, L, shp, face, m, rr, jc, jg, jf);
+    rows = 4; nc = CamCols<CD>::LN; nf = 4;
+  } else {
+    return -1;
+  }
+  for (int i = 0; i < rows; ++i) {
+    r[i] = rr[i];
+    for (int k = 0; k < CD; ++k) Jc[i * 9 + k] = k < nc ? (double)jc[i * nc + k] : 0.0;
+    for (int k = 0; k < SH_DOF; ++k) Jg[i * SH_DOF + k] = jg[i * SH_DOF + k];
+    for (int k = 0; k < nf; ++k) Jf[i * 4 + k] = jf[i * nf + k];
+  }
+  return rows;
+}
+}  // namespace
+
+extern "C" int mc_eval_shape(int fam, int cd, int fp64, const double* cam, const double* pt, const double* ln,
+                             const double* sh, const double* meas, double* r, double* Jc, double* Jg, double* Jf) {
+  fp64 = 1;  // the library evaluates these families in FP64 and stores them in the working precision
+  if (fp64) return cd == 9 ? eval_shape<double, 9>(fam, cam, pt, ln, sh, meas, r, Jc, Jg, Jf)
+                           : eval_shape<double, 6>(fam, cam, pt, ln, sh, meas, r, Jc, Jg, Jf);
+  return cd == 9 ? eval_shape<float, 9>(fam, cam, pt, ln, sh, meas, r, Jc, Jg, Jf)
+                 : eval_shape<float, 6>(fam, cam, pt, ln, sh, meas, r, Jc, Jg, Jf);
+}

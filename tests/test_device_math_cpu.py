@@ -14,7 +14,7 @@ import subprocess
 import numpy as np
 import pytest
 
-from scenegen import make_scene, small_config, plane_3d_scene
+from scenegen import make_scene, small_config, plane_3d_scene, add_shapes
 from oracle import lm, model
 from tests import layout
 
@@ -22,14 +22,25 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "native", "libmathcheck.so")
 
 
-def _lib():
+def _stale():
     if not os.path.exists(LIB):
+        return True
+    csrc = os.path.join(HERE, "..", "paper_2609_04026_amd", "csrc")
+    srcs = [os.path.join(HERE, "native", "mathcheck.cpp")] + [os.path.join(csrc, f) for f in os.listdir(csrc)
+                                                               if f.endswith(".h")]
+    return max(os.path.getmtime(f) for f in srcs) > os.path.getmtime(LIB)
+
+
+def _lib():
+    if _stale():
         subprocess.check_call(["hipcc", "-std=c++17", "-O2", "-fPIC", "-shared", "-x", "hip", "--offload-host-only",
                                os.path.join(HERE, "native", "mathcheck.cpp"), "-o", LIB])
     lib = ctypes.CDLL(LIB)
     P = ctypes.POINTER(ctypes.c_double)
     lib.mc_eval.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int] + [P] * 10
     lib.mc_eval.restype = ctypes.c_int
+    lib.mc_eval_shape.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int] + [P] * 9
+    lib.mc_eval_shape.restype = ctypes.c_int
     return lib
 
 
@@ -53,7 +64,7 @@ def _eval(lib, fam, cd, fp64, st, rec, i, cx, cy):
 
 @pytest.fixture(scope="module")
 def setup():
-    s = plane_3d_scene(make_scene(small_config(n_cams=8), seed=31), keep_2d=True)
+    s = add_shapes(plane_3d_scene(make_scene(small_config(n_cams=8), seed=31), keep_2d=True), seed=32)
     prob = lm.Problem(s)
     st = prob.state0()
     st.cam_k1 = st.cam_k1 + 0.06
@@ -87,3 +98,42 @@ def test_device_math_matches_oracle(setup, fam, cd):
                 nrm = np.linalg.norm(ref)
                 tol = (1e-9 if fp64 else 1e-4) * max(nrm, 1e-12)
                 assert np.linalg.norm(got - ref) <= tol + (1e-12 if fp64 else 1e-6), (fam, b, fp64, i, got, ref)
+
+
+@pytest.mark.parametrize("cd", [9, 6])
+@pytest.mark.parametrize("fam", ["R13", "R14"])
+def test_device_shape_math_matches_oracle(setup, fam, cd):
+    """R13 / R14 (the surface groups of App. B): the library evaluates them in FP64
+    from the master parameters on both paths and stores them in the working
+    precision; held to 1e-9."""
+    prob, st, lib = setup
+    rec = prob.recs[fam]
+    n = prob.record_count(fam)
+    assert n > 0
+    r_or = model.residuals(st, rec, fam, prob.cx, prob.cy)
+    J_or = model.jacobians(st, rec, fam, prob.cx, prob.cy, camera_dof=cd)
+    key = "pt" if fam == "R13" else "ln"
+    seen = set()
+    for fp64 in (1, 0):
+        for i in range(n):
+            cam = layout.cam_slot(st, rec["cam"][i])
+            pt = layout.pt_slot(st, rec["pt"][i]) if key == "pt" else np.zeros(4)
+            ln = layout.ln_slot(st, rec["ln"][i]) if key == "ln" else np.zeros(12)
+            sh = layout.sh_slot(st, rec["sh"][i])
+            seen.add(int(sh[15]))
+            meas = layout.shifted_meas(fam, rec, i, prob.cx, prob.cy)
+            r, Jc, Jg, Jf = np.zeros(4), np.zeros(36), np.zeros(36), np.zeros(16)
+            rows = lib.mc_eval_shape(int(fam[1:]), cd, fp64, *[_p(b) for b in (cam, pt, ln, sh, meas)],
+                                     *[b.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) for b in (r, Jc, Jg, Jf)])
+            tol = 1e-9
+            ref_r = r_or[i]
+            assert np.linalg.norm(r[:rows] - ref_r) <= tol * max(np.abs(ref_r).max(), 1.0), (fam, fp64, i)
+            got = {"cam": Jc.reshape(4, 9)[:rows, :cd], "sh": Jg.reshape(4, 9)[:rows],
+                   key: Jf.reshape(4, 4)[:rows, :3 if key == "pt" else 4]}
+            for b in ("cam", "sh", key):
+                ref = J_or[b][i]
+                nrm = np.linalg.norm(ref)
+                assert np.linalg.norm(got[b] - ref) <= tol * max(nrm, 1e-12) + 1e-12, \
+                    (fam, b, fp64, i, int(sh[15]), got[b], ref)
+    if fam == "R13":
+        assert seen == {0, 1, 2, 3, 4}

@@ -1,0 +1,202 @@
+"""Surface groups (App. B: sphere, cylinder, cone, ellipsoid, cuboid; families 13 and
+14) on the GPU against the oracle, through the C ABI.
+
+The tiny holistic scene with the five shapes added (every family of Sec. 3 present):
+per-record residuals and Jacobians (keys exactly; FP64 1e-9, mixed 1e-4), the feature
+blocks, b, the diagonal blocks of S of the cameras and the shapes, the implicit product
+entry by entry against the oracle's S, one LM step against the exact Schur step, ten
+FP64 steps against ten oracle steps (costs, points, shapes), the converged cost of the
+mixed path with the gauge two-level preconditioner, the gauge rows of the shapes and
+S Z of the coarse space, the shape parameters' round trip, and the refusals (dense
+solver, deterministic mode, a line on a non-cuboid).
+"""
+import numpy as np
+import pytest
+
+from scenegen import shape_scene, add_shapes, make_scene, small_config
+from scenegen.scene import ASSOC_SHAPE_LINE
+from oracle import lm, gnn, shapes as S
+from oracle.records import record_keys
+
+pytestmark = pytest.mark.gpu
+
+
+def _BA():
+    from paper_2609_04026_amd.binding import BA
+    return BA
+
+
+@pytest.fixture(scope="module")
+def case():
+    print("[case] shape scene seed 301", flush=True)
+    s = shape_scene(seed=301)
+    prob = lm.Problem(s)
+    st = prob.state0()
+    lin = lm.linearize(prob, st)
+    assert prob.record_count("R13") > 0 and prob.record_count("R14") > 0
+    return s, prob, st, lin
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("fam", [13, 14])
+def test_shape_records_match_oracle(case, precision, fam):
+    s, prob, st, lin = case
+    name = f"R{fam}"
+    ba = _BA().from_scene(s, precision=precision)
+    ba.linearize(1e-3)
+    n = prob.record_count(name)
+    assert ba.record_count(fam) == n
+    keys, r, J = ba.export_records(fam)
+    ko = record_keys(prob.recs)[name][:, 1:]
+    og, oo = np.lexsort(keys.T[::-1]), np.lexsort(ko.T[::-1])
+    assert np.array_equal(keys[og], ko[oo])
+    tol = 1e-9 if precision == "fp64" else 1e-4
+    rt = lin.fam[name]["rt"][oo]
+    err = np.abs(r[og] - rt).max() / max(np.abs(rt).max(), 1e-3)
+    assert err <= tol, err
+    cd = prob.camera_dof
+    nf = 3 if fam == 13 else 4
+    key = "pt" if fam == 13 else "ln"
+    for b, sl in (("cam", slice(0, cd)), (key, slice(cd, cd + nf)), ("sh", slice(cd + nf, cd + nf + 9))):
+        Jo, Jg = lin.fam[name]["J"][b][oo], J[og][:, :, sl]
+        e = np.linalg.norm(Jg - Jo, axis=(1, 2)) / np.maximum(np.linalg.norm(Jo, axis=(1, 2)), 1e-30)
+        assert e.max() <= tol, (b, e.max())
+    ba.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_shape_reduced_system_matches_oracle(case, precision):
+    s, prob, st, lin = case
+    lam = 1e-3
+    ba = _BA().from_scene(s, precision=precision)
+    ba.linearize(lam)
+    tol = 1e-9 if precision == "fp64" else 1e-4
+    Vp, gp, Vl, gl = ba.export_feature_blocks()
+    Vp_o, Vl_o, _ = lm.feature_blocks(prob, lin)
+    for V, Vo in ((Vp, Vp_o), (Vl, Vl_o)):
+        err = np.linalg.norm(V - Vo, axis=(1, 2)) / np.maximum(np.linalg.norm(Vo, axis=(1, 2)), 1e-30)
+        assert err.max() <= tol, err.max()
+    sys_ = lm.schur(prob, lin, lam)
+    Sx = sys_["S"]
+    b, Sc, Sp, Sv = ba.export_reduced()
+    assert b.shape == sys_["b"].shape
+    assert np.abs(b - sys_["b"]).max() <= 10 * tol * np.abs(sys_["b"]).max()
+    blocks = lm.diag_blocks(prob, Sx)
+    for got, ref in ((Sc, blocks["cam"]), (ba.export_shape_blocks(), blocks["sh"])):
+        e = np.linalg.norm(got - ref, axis=(1, 2)) / np.linalg.norm(ref, axis=(1, 2))
+        assert e.max() <= 10 * tol, e.max()
+    rng = np.random.default_rng(2)
+    for _ in range(3):
+        x = rng.normal(size=Sx.shape[0])
+        y = ba.schur_matvec(x)
+        err = np.abs(y - Sx @ x) / np.maximum(np.abs(Sx) @ np.abs(x), 1e-300)
+        assert err.max() <= 10 * tol, err.max()
+    ba.close()
+
+
+@pytest.mark.parametrize("precision,cd", [("fp64", 9), ("fp64", 6), ("mixed", 9)])
+def test_shape_step_matches_exact_schur_step(case, precision, cd):
+    s, prob, st, lin = case
+    if cd != prob.camera_dof:
+        s = dict(s, camera_dof=cd)
+        prob = lm.Problem(s)
+        lin = lm.linearize(prob, st)
+    lam = 1e-3
+    ba = _BA().from_scene(s, precision=precision)
+    rep = ba.lm_step(lambda0=lam, pcg_tol=1e-12 if precision == "fp64" else 1e-7, pcg_max_iters=3000)
+    h, _ = lm.solve_schur(prob, lin, lam)
+    E0, _ = lm.cost(prob, st)
+    E1, Epix1 = lm.cost(prob, prob.retract(st, h))
+    tol = 1e-9 if precision == "fp64" else 1e-4
+    assert abs(rep["E_before"] - E0) <= 1e-12 * E0
+    assert abs(rep["E_after"] - E1) <= tol * E1, (rep["E_after"], E1)
+    assert abs(rep["Epix_after"] - Epix1) <= tol * Epix1, (rep["Epix_after"], Epix1)
+    ba.close()
+
+
+def test_shape_ten_steps_match_oracle(case):
+    s, prob, st, lin = case
+    ref = lm.lm_solve(prob, max_iters=10, func_tol=0.0, grad_tol=0.0)
+    ba = _BA().from_scene(s, precision="fp64")
+    out = ba.solve(max_iters=10, func_tol=0.0, grad_tol=0.0, pcg_tol=1e-12, pcg_max_iters=3000)
+    print(f"[shapes] ten steps: {out['E_final']} vs {ref['E']}", flush=True)
+    assert out["iters"] == ref["iters"] == 10
+    assert abs(out["E_final"] - ref["E"]) <= 1e-9 * ref["E"]
+    p = ba.get_parameters()
+    scale = np.abs(ref["state"].pts).max()
+    assert np.abs(p["points"] - ref["state"].pts).max() <= 1e-7 * scale
+    _, abi = ref["state"].sh.to_abi()
+    got = ba.get_shapes()
+    assert np.abs(got - abi).max() <= 1e-7 * max(1.0, np.abs(abi).max()), np.abs(got - abi).max()
+    ba.close()
+
+
+def test_shape_converged_cost_mixed_gauge(case):
+    s, prob, st, lin = case
+    ref = lm.lm_solve(prob, max_iters=200, func_tol=1e-12)
+    ba = _BA().from_scene(s, precision="mixed", precond="gauge")
+    out = ba.solve(max_iters=200, func_tol=1e-12, pcg_tol=1e-7, pcg_max_iters=3000)
+    print(f"[shapes] converged: {out['E_final']} vs {ref['E']} ({out['iters']} / {ref['iters']})", flush=True)
+    assert abs(out["E_final"] - ref["E"]) <= 1e-6 * ref["E"]
+    ba.close()
+
+
+def test_shape_round_trip(case):
+    s, prob, st, lin = case
+    ba = _BA().from_scene(s, precision="fp64")
+    _, abi = S.Shapes.from_abi(s["shapes"]["type"], s["shapes"]["params"]).to_abi()
+    got = ba.get_shapes()
+    assert np.abs(got - abi).max() <= 1e-12 * max(1.0, np.abs(abi).max())
+    ba.lm_step(lambda0=1e-3, pcg_tol=1e-10)  # finalised: read back from the device
+    assert ba.get_shapes().shape == abi.shape
+    ba.close()
+
+
+def _gauge_scene():
+    base = make_scene(small_config(n_cams=9, n_points=40, n_lines=12, n_vps=0, vp_lines=0), seed=41)
+    return add_shapes(base, seed=42)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_shape_gauge_rows_and_coarse_space(precision):
+    """The shapes' gauge rows against the oracle's (numerical differentiation of the
+    similarity through the retraction), and S Z of the gauge coarse space against the
+    oracle's dense S (k_sz_shape and the aligned records of the camera sweep)."""
+    s = _gauge_scene()
+    prob = lm.Problem(s)
+    st = prob.state0()
+    lam = 1e-3
+    Sx = lm.schur(prob, lm.linearize(prob, st), lam)["S"]
+    G_o = gnn.gauge_basis(prob, st)
+    ba = _BA().from_scene(s, precision=precision, precond="gauge")
+    ba.linearize(lam)
+    G = ba.export_gauge_basis()
+    assert np.abs(G - G_o).max() <= 1e-7 * np.abs(G_o).max(), np.abs(G - G_o).max()
+    Z, SZ = ba.export_coarse_space()
+    assert Z.shape == (Sx.shape[0], 7)
+    tol = 1e-9 if precision == "fp64" else 1e-4
+    col_err = np.linalg.norm(SZ - Sx @ Z, axis=0) / np.linalg.norm(np.abs(Sx) @ np.abs(Z), axis=0)
+    assert col_err.max() <= tol, col_err
+    rep = ba.lm_step(pcg_tol=1e-8 if precision == "fp64" else 1e-6)
+    assert rep["coarse"] == 7 and rep["pcg_flags"] == 0, rep
+    ba.close()
+
+
+def test_shape_refusals(case):
+    from paper_2609_04026_amd.binding import BAError
+    s, prob, st, lin = case
+    ba = _BA().from_scene(s, precision="fp64")
+    with pytest.raises(BAError, match="dense solver"):
+        ba.lm_step(lambda0=1e-3, solver="dense")
+    with pytest.raises(BAError, match="deterministic"):
+        ba.lm_step(lambda0=1e-3, deterministic=1)
+    ba.close()
+    # a line on a sphere: refused at the first step
+    bad = dict(s)
+    bad["obs"] = dict(s["obs"])
+    a, b, _ = s["obs"][ASSOC_SHAPE_LINE]
+    bad["obs"][ASSOC_SHAPE_LINE] = (np.zeros_like(a), b, None)
+    ba = _BA().from_scene(bad, precision="fp64")
+    with pytest.raises(BAError, match="not a cuboid"):
+        ba.lm_step(lambda0=1e-3)
+    ba.close()

@@ -29,7 +29,8 @@ import copy
 import numpy as np
 import pytest
 
-from scenegen import shape_scene, SHAPE_SPHERE, SHAPE_CYLINDER, SHAPE_CONE, SHAPE_ELLIPSOID, SHAPE_CUBOID
+from scenegen import (shape_scene, add_shapes, make_scene, small_config, SHAPE_SPHERE, SHAPE_CYLINDER, SHAPE_CONE,
+                      SHAPE_ELLIPSOID, SHAPE_CUBOID)
 from scenegen.shapes import _sample_surface, _layout, _orthonormal, _cuboid_segments
 from oracle import lm, model, shapes as S
 
@@ -345,3 +346,27 @@ def test_cuboid_centre_is_the_mean_of_its_corners():
                 corners.append(np.linalg.solve(n[0][[i, j, k]], -e[0][[i, j, k]]))
     c = S.cuboid_centre(sh.R, sh.q)[0]
     assert np.abs(c - np.mean(corners, axis=0)).max() <= 1e-12
+
+
+def test_similarity_gauge_is_a_null_vector_of_the_jacobian():
+    """The world rotations, translations and scale, moving every camera, point, line,
+    plane and shape (the shapes' rows by numerical differentiation of their similarity
+    through the retraction), leave every residual of a scene without VP records
+    unchanged to first order: J [G; G_f] = 0 (Sec. 3.1's gauge freedom)."""
+    from oracle import gnn
+    base = make_scene(small_config(n_cams=9, n_points=40, n_lines=12, n_vps=0, vp_lines=0), seed=41)
+    s = add_shapes(base, seed=42)
+    prob = lm.Problem(s)
+    st = prob.state0()
+    rows, worst = S.gauge_rows(st.sh)
+    assert worst <= 1e-8, worst
+    lin = lm.linearize(prob, st)
+    Z = np.concatenate([gnn.gauge_basis(prob, st), gnn.gauge_basis_features(prob, st)])
+    JZ = lin.J @ Z
+    scale = np.abs(lin.J).max() * np.abs(Z).max()
+    assert np.abs(JZ).max() <= 1e-6 * scale, np.abs(JZ).max() / scale
+    # and a wrong shape row is seen: zeroing the shapes' rows breaks it
+    Z2 = Z.copy()
+    o = prob.off["sh"]
+    Z2[o:o + 9 * prob.n["sh"]] = 0
+    assert np.abs(lin.J @ Z2).max() > 1e-3 * scale
