@@ -118,12 +118,17 @@ def test_forward_loss_and_gradient_match_oracle(systems, precision):
     assert abs(L2 - L) <= 1e-6 * abs(L)
     g_o = gnn.pack(grads_o).astype(np.float64)
     o = 0
+    errs = {}
     for name, shp in gnn.param_shapes(9):
         n = int(np.prod(shp))
         a, b = grad[o:o + n].astype(np.float64), g_o[o:o + n]
-        err = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
-        assert err <= tol_g, (name, err)
+        errs[name] = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
         o += n
+    worst = max(errs, key=errs.get)
+    print(f"[gnn] {precision}: heads {err_h:.2e}, loss {abs(L - L_o) / abs(L_o):.2e}, "
+          f"gradient worst {worst} {errs[worst]:.2e}", flush=True)
+    for name, err in errs.items():
+        assert err <= tol_g, (name, err)
     net.close()
 
 
