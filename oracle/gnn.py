@@ -325,8 +325,47 @@ def _t(v):
     return v if torch.is_tensor(v) else torch.as_tensor(np.asarray(v), dtype=torch.float64)
 
 
-def forward(params, node_x, node_type, edge_src, edge_dst, edge_x, camera_dof=9):
-    """Y_i (n_i x K tensors) per node."""
+def _bf(x):
+    """x rounded to bfloat16 (to nearest, ties to even) through FP32, back in float64."""
+    return x.to(torch.float32).to(torch.bfloat16).to(torch.float64)
+
+
+class _Bf16Matmul(torch.autograd.Function):
+    """A @ W on BF16-rounded operands; both backward products (dA = dC W^T,
+    dW = A^T dC) on BF16-rounded operands too.  The network's dense layers in BF16
+    precision: every GEMM operand is rounded, accumulation is wide."""
+
+    @staticmethod
+    def forward(ctx, A, W):
+        ctx.save_for_backward(A, W)
+        return _bf(A) @ _bf(W)
+
+    @staticmethod
+    def backward(ctx, g):
+        A, W = ctx.saved_tensors
+        gb = _bf(g)
+        return gb @ _bf(W).T, _bf(A).T @ gb
+
+
+class _Bf16WeightGrad(torch.autograd.Function):
+    """A @ W unrounded (a product formed inside the edge kernel), whose weight gradient
+    A^T dC is a BF16 GEMM (rounded operands); A takes no gradient."""
+
+    @staticmethod
+    def forward(ctx, A, W):
+        ctx.save_for_backward(A)
+        return A @ W
+
+    @staticmethod
+    def backward(ctx, g):
+        (A,) = ctx.saved_tensors
+        return None, _bf(A).T @ _bf(g)
+
+
+def forward(params, node_x, node_type, edge_src, edge_dst, edge_x, camera_dof=9, bf16=False):
+    """Y_i (n_i x K tensors) per node.  With bf16 the dense products round their
+    operands to BF16 as the BF16 network does (the message layer split into its
+    per-node h-part, a GEMM, and its per-edge input part, formed in full precision)."""
     P = {k: _t(v) for k, v in params.items()}
     x = _t(node_x)
     ex = _t(edge_x).reshape(-1, EDGE_IN)
@@ -334,16 +373,22 @@ def forward(params, node_x, node_type, edge_src, edge_dst, edge_x, camera_dof=9)
     dst = torch.as_tensor(np.asarray(edge_dst), dtype=torch.long)
     n = x.shape[0]
     deg = torch.zeros(n, dtype=torch.float64).index_add_(0, dst, torch.ones(len(dst), dtype=torch.float64))
-    h = gelu(x @ P["W_in"] + P["b_in"])
+    mm = _Bf16Matmul.apply if bf16 else (lambda a, b: a @ b)
+    h = gelu(mm(x, P["W_in"]) + P["b_in"])
     for l in range(LAYERS):
-        msg = gelu(torch.cat([h[src], ex], dim=1) @ P[f"W_e{l}"] + P[f"b_e{l}"])
+        W = P[f"W_e{l}"]
+        if bf16:
+            pre = mm(h, W[:H])[src] + _Bf16WeightGrad.apply(ex, W[H:]) + P[f"b_e{l}"]
+        else:
+            pre = torch.cat([h[src], ex], dim=1) @ W + P[f"b_e{l}"]
+        msg = gelu(pre)
         m = torch.zeros(n, H, dtype=torch.float64).index_add_(0, dst, msg)
         m = m / torch.clamp(deg, min=1.0)[:, None]
-        h = gelu(h @ P[f"W_s{l}"] + P[f"b_s{l}"] + m) + h
+        h = gelu(mm(h, P[f"W_s{l}"]) + P[f"b_s{l}"] + m) + h
     sizes = block_sizes(camera_dof)
     out = []
     for i, t in enumerate(np.asarray(node_type)):
-        y = h[i] @ P[f"W_t{int(t)}"] + P[f"b_t{int(t)}"]
+        y = mm(h[i:i + 1], P[f"W_t{int(t)}"])[0] + P[f"b_t{int(t)}"]
         out.append(y.reshape(sizes[int(t)], K))
     return out
 
@@ -378,19 +423,19 @@ def full_basis(G, Y, units):
     return torch.cat([_t(G), coarse_basis(Y, units)], dim=1)
 
 
-def batch_loss(params, systems, camera_dof=9):
+def batch_loss(params, systems, camera_dof=9, bf16=False):
     """Mean coarse loss over systems; each a dict with node_x, graph, S (dense), units, gauge."""
     total = torch.zeros((), dtype=torch.float64)
     for s in systems:
         g = s["graph"]
-        Y = forward(params, s["node_x"], g["node_type"], g["edge_src"], g["edge_dst"], g["edge_x"], camera_dof)
+        Y = forward(params, s["node_x"], g["node_type"], g["edge_src"], g["edge_dst"], g["edge_x"], camera_dof, bf16)
         total = total + coarse_loss(full_basis(s["gauge"], Y, s["units"]), s["S"], g["sizes"])
     return total / len(systems)
 
 
-def loss_and_grads(params, systems, camera_dof=9):
+def loss_and_grads(params, systems, camera_dof=9, bf16=False):
     P = {k: torch.tensor(np.asarray(v, dtype=np.float64), requires_grad=True) for k, v in params.items()}
-    L = batch_loss(P, systems, camera_dof)
+    L = batch_loss(P, systems, camera_dof, bf16)
     L.backward()
     return float(L.detach()), {k: v.grad.numpy().copy() for k, v in P.items()}
 

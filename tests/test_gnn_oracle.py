@@ -276,3 +276,31 @@ def test_inputs_and_loss_do_not_change_when_the_scene_is_scaled(tiny):
     L2 = float(gnn.batch_loss(p, [dict(node_x=x, graph=g, S=S, units=gnn.unit_scales(g, s0, cd),
                                        gauge=gnn.gauge_basis(prob, st))], cd))
     assert L2 == pytest.approx(L1, rel=1e-7)
+
+
+def test_bf16_mode_with_exact_rounding_is_the_network(tiny, monkeypatch):
+    """The BF16 emulation (operands of every dense product rounded, the message layer
+    split into its per-node h-part and its per-edge input part, custom backward
+    products) reduces to the plain network when rounding is the identity: same heads,
+    loss and gradients to 1e-10 (summation order).  And with true BF16 rounding it stays within BF16's
+    reach of it (heads 5e-2, gradients 0.2)."""
+    cd = tiny["prob"].camera_dof
+    p = gnn.init_params(cd, seed=4)
+    sysd = [dict(node_x=tiny["x"], graph=tiny["graph"], S=tiny["S"], units=tiny["units"], gauge=tiny["gauge"])]
+    g = tiny["graph"]
+    args = (tiny["x"], g["node_type"], g["edge_src"], g["edge_dst"], g["edge_x"], cd)
+    L0, G0 = gnn.loss_and_grads(p, sysd, cd)
+    Y0 = torch.cat([y.reshape(-1) for y in gnn.forward(p, *args)])
+    Lb, Gb = gnn.loss_and_grads(p, sysd, cd, bf16=True)
+    Yb = torch.cat([y.reshape(-1) for y in gnn.forward(p, *args, bf16=True)])
+    assert float(torch.linalg.norm(Yb - Y0) / torch.linalg.norm(Y0)) <= 5e-2
+    for k in G0:
+        assert np.linalg.norm(Gb[k] - G0[k]) <= 0.2 * np.linalg.norm(G0[k]), k
+    assert 0 < float(torch.linalg.norm(Yb - Y0)), "rounding had no effect"
+    monkeypatch.setattr(gnn, "_bf", lambda x: x)
+    L1, G1 = gnn.loss_and_grads(p, sysd, cd, bf16=True)
+    Y1 = torch.cat([y.reshape(-1) for y in gnn.forward(p, *args, bf16=True)])
+    assert float(torch.abs(Y1 - Y0).max()) <= 1e-10 * float(torch.abs(Y0).max())
+    assert abs(L1 - L0) <= 1e-10 * abs(L0)
+    for k in G0:
+        assert np.abs(G1[k] - G0[k]).max() <= 1e-10 * max(np.abs(G0[k]).max(), 1e-30), k
