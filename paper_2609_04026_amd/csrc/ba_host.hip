@@ -984,6 +984,21 @@ void finalize(ba_handle* h) {
     };
     flatten(mp, d.shp, d.shp_off);
     flatten(ml, d.shl, d.shl_off);
+    // chunks of at most SH_CHUNK members of one shape for the shape passes
+    std::vector<int4> ch;
+    for (int kind = 0; kind < 2; ++kind) {
+      int32_t o = 0;
+      for (int q = 0; q < h->ns; ++q) {
+        const int32_t n = (int32_t)(kind == 0 ? mp[q].size() : ml[q].size());
+        for (int32_t c = 0; c < n; c += SH_CHUNK) ch.push_back(make_int4(q, o + c, std::min(SH_CHUNK, n - c), kind));
+        o += n;
+      }
+    }
+    d.n_shch = (int)ch.size();
+    d.shch = A.get<int4>(ch.size());
+    upload(h, d.shch, ch);
+    d.shacc = A.get<double>((size_t)h->ns * SH_ACC);
+    d.shsz = A.get<double>((size_t)h->ns * SH_DOF * SZ_COLS * SZ_PANELS);
   }
   cam_major(6, true, d.px_start, d.px_cnt, d.px_off);
   cam_major(7, true, d.lx_start, d.lx_cnt, d.lx_off);

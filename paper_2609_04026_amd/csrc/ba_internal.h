@@ -93,6 +93,13 @@ struct Dev {
   // shape, and every feature with such records is one of the product's big features.
   int32_t *shp_off = nullptr, *shp = nullptr, *shl_off = nullptr, *shl = nullptr;
   int32_t *shal_p = nullptr, *shal_l = nullptr;
+  // the shape passes take chunks of at most SH_CHUNK members of one shape, a workgroup
+  // each: int4 (shape, first member, members, 0 points / 1 lines); FP64 accumulators
+  // summed over a shape's chunks: U (packed) and g, or the S-block terms and b
+  // (SH_ACC per shape), and the shape rows of S Z (SH_DOF x SZ_COLS x SZ_PANELS)
+  int n_shch = 0;
+  int4* shch = nullptr;
+  double *shacc = nullptr, *shsz = nullptr;
   // feature blocks (T unless noted)
   void *Vp = nullptr, *gp = nullptr, *Vl = nullptr, *gl = nullptr;
   void *Vip = nullptr, *Vil = nullptr, *sp = nullptr, *sl = nullptr;
@@ -215,6 +222,7 @@ constexpr int COARSE_GAUGE = 7, COARSE_NET = 8, COARSE_K = COARSE_GAUGE + COARSE
 // the coarse columns in the S Z sweeps (Z rows, s_f) are stored in panels of SZ_COLS
 // columns, row-major within a panel
 constexpr int SZ_COLS = 8, SZ_PANELS = 2;
+constexpr int SH_CHUNK = 256, SH_ACC = SH_DOF * (SH_DOF + 1) / 2 + SH_DOF;
 static_assert(COARSE_K <= SZ_COLS * SZ_PANELS, "coarse columns per S Z panel set");
 // With FP32 records the product resolves S Z only to ~1e-7 |S| |Z|, while on the
 // near-null (gauge) directions S Z ~ lambda D_A Z: below this damping the coarse

@@ -1813,8 +1813,10 @@ __global__ __launch_bounds__(MV_THREADS) void k_mv_wave(Dev d, const double* don
       }
     }
   }
-  // features whose records do not fit one tile: one lane per feature
-  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < d.n_bigp + d.n_bigl; k += gridDim.x * blockDim.x) {
+  // features whose records do not fit one tile (and features on a shape): one lane per
+  // feature, dealt round-robin over the workgroups (lane t of workgroup b takes
+  // b + t * gridDim.x), so that every CU shares the pass
+  for (int k = blockIdx.x + gridDim.x * threadIdx.x; k < d.n_bigp + d.n_bigl; k += gridDim.x * blockDim.x) {
     if constexpr (SONLY) {
       if (k < d.n_bigp) mv_feature_s<T, CD, 3>(d, d.bigp[k], x);
       else mv_feature_s<T, CD, 4>(d, d.bigl[k - d.n_bigp], x);
@@ -3049,11 +3051,16 @@ template <typename T, int CD> void launch_det_rows(const Dev& d, const double* d
 
 template <typename T, int CD, int L, int CPL>
 __global__ __launch_bounds__(256) void k_sz_shape(Dev d, const T* Zr, const T* sfp, const T* sfl, double lam);
+__global__ void k_sz_shape_fin(Dev d, double lam);
 
 template <typename T, int CD, int L, int CPL> static void launch_sz_out(const Dev& d, const T* Zr, const T* sfp, const T* sfl, double lambda, hipStream_t s) {
   if (d.nc) k_sz_cam<T, CD, L, CPL><<<d.nc, 256, 0, s>>>(d, Zr, sfp, sfl, lambda);
   if (d.ng + d.nv) k_sz_grp<T, CD, L, CPL><<<d.ng + d.nv, 256, 0, s>>>(d, Zr, sfp, sfl, lambda);
-  if (d.ns) k_sz_shape<T, CD, L, CPL><<<d.ns, 256, 0, s>>>(d, Zr, sfp, sfl, lambda);
+  if (d.ns) {
+    launch_zero(d.shsz, (size_t)d.ns * SH_DOF * SZ_COLS * SZ_PANELS * sizeof(double), s);
+    if (d.n_shch) k_sz_shape<T, CD, L, CPL><<<d.n_shch, 256, 0, s>>>(d, Zr, sfp, sfl, lambda);
+    k_sz_shape_fin<<<d.ns, 128, 0, s>>>(d, lambda);
+  }
 }
 
 template <typename T, int CD> static void launch_sz(const Dev& d, double lambda, hipStream_t s) {
@@ -3074,8 +3081,9 @@ template <typename T, int CD> static void launch_sz(const Dev& d, double lambda,
       continue;
     }
     if (d.n_tiles) k_sz_feat_wave<T, CD><<<(int)std::min<int64_t>(4 * (int64_t)d.n_mv_wg, nblk(d.n_tiles, 4)), 256, 0, s>>>(d, zp, pp, lp);
-    if (d.n_bigp) k_sz_feat_big<T, CD, 3><<<nblk(d.n_bigp, 256), 256, 0, s>>>(d, zp, pp, d.bigp, d.n_bigp);
-    if (d.n_bigl) k_sz_feat_big<T, CD, 4><<<nblk(d.n_bigl, 256), 256, 0, s>>>(d, zp, lp, d.bigl, d.n_bigl);
+    // one wavefront per workgroup: the per-lane feature sums are latency-bound, spread them
+    if (d.n_bigp) k_sz_feat_big<T, CD, 3><<<nblk(d.n_bigp, 64), 64, 0, s>>>(d, zp, pp, d.bigp, d.n_bigp);
+    if (d.n_bigl) k_sz_feat_big<T, CD, 4><<<nblk(d.n_bigl, 64), 64, 0, s>>>(d, zp, lp, d.bigl, d.n_bigl);
   }
   static_assert(SZ_PANELS == 2, "one or two panels");
   if (d.coarse_k <= COARSE_GAUGE) launch_sz_out<T, CD, SZ_LANES, SZ_COLS / SZ_LANES>(d, Zr, sfp, sfl, lambda, s);
@@ -3317,8 +3325,10 @@ template <typename T, int CD> __global__ __launch_bounds__(256) void k_backsub_w
       }
     }
   }
-  // features whose records do not fit one tile: one lane per feature
-  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < d.n_bigp + d.n_bigl; k += gridDim.x * blockDim.x) {
+  // features whose records do not fit one tile (and features on a shape): one lane per
+  // feature, dealt round-robin over the workgroups (lane t of workgroup b takes
+  // b + t * gridDim.x), so that every CU shares the pass
+  for (int k = blockIdx.x + gridDim.x * threadIdx.x; k < d.n_bigp + d.n_bigl; k += gridDim.x * blockDim.x) {
     if (k < d.n_bigp) backsub_one<T, CD, 3>(d, d.bigp[k], x, gh, jh2);
     else backsub_one<T, CD, 4>(d, d.bigl[k - d.n_bigp], x, gh, jh2);
   }
@@ -3595,88 +3605,101 @@ __device__ __forceinline__ void shape_a_rows(const Dev& d, int64_t i, T (&U)[SH_
   }
 }
 
-template <typename T, int CD> __global__ __launch_bounds__(256) void k_shape_a(Dev d) {
+// Each pass runs one workgroup per chunk of at most SH_CHUNK members of a shape (a large
+// shape has tens of thousands of points), sums its chunk over the workgroup and adds the
+// sums to the shape's FP64 accumulator with one atomic each; a per-shape kernel then
+// writes the blocks.  The accumulators are cleared first.
+template <typename T, int CD, bool B> __global__ __launch_bounds__(256) void k_shape_chunk(Dev d) {
   constexpr int NS = SH_DOF * (SH_DOF + 1) / 2, K = NS + SH_DOF;
+  static_assert(K == SH_ACC, "accumulator layout");
   __shared__ T lds[(4 + 1) * K];
-  const int q = blockIdx.x;
+  const int4 ch = d.shch[blockIdx.x];  // (shape, first member, members, kind)
   T acc[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) acc[k] = 0;
   T(&U)[NS] = *reinterpret_cast<T(*)[NS]>(acc);
   T(&g)[SH_DOF] = *reinterpret_cast<T(*)[SH_DOF]>(acc + NS);
-  if (d.fn[9])
-    for (int j = d.shp_off[q] + threadIdx.x; j < d.shp_off[q + 1]; j += blockDim.x) {
+  for (int j = ch.y + threadIdx.x; j < ch.y + ch.z; j += blockDim.x) {
+    if (ch.w == 0) {
       const int f = d.shp[j];
-      for (int64_t i = d.foff[9][f]; i < d.foff[9][f + 1]; ++i) shape_a_rows<9, T, CD>(d, i, U, g);
-    }
-  if (d.fn[10])
-    for (int j = d.shl_off[q] + threadIdx.x; j < d.shl_off[q + 1]; j += blockDim.x) {
+      if constexpr (B) {
+        T W[SH_DOF][3];
+#pragma unroll
+        for (int a = 0; a < SH_DOF; ++a) W[a][0] = W[a][1] = W[a][2] = 0;
+        for (int64_t i = d.foff[9][f]; i < d.foff[9][f + 1]; ++i) addW_rows<9, 1, T, CD, SH_DOF, 3>(d, i, W);
+        pair_contrib<T, SH_DOF, 3>(d, f, W, acc, acc + NS);
+      } else {
+        for (int64_t i = d.foff[9][f]; i < d.foff[9][f + 1]; ++i) shape_a_rows<9, T, CD>(d, i, U, g);
+      }
+    } else {
       const int f = d.shl[j];
-      for (int64_t i = d.foff[10][f]; i < d.foff[10][f + 1]; ++i) shape_a_rows<10, T, CD>(d, i, U, g);
+      if constexpr (B) {
+        T W[SH_DOF][4];
+#pragma unroll
+        for (int a = 0; a < SH_DOF; ++a) W[a][0] = W[a][1] = W[a][2] = W[a][3] = 0;
+        for (int64_t i = d.foff[10][f]; i < d.foff[10][f + 1]; ++i) addW_rows<10, 1, T, CD, SH_DOF, 4>(d, i, W);
+        pair_contrib<T, SH_DOF, 4>(d, f, W, acc, acc + NS);
+      } else {
+        for (int64_t i = d.foff[10][f]; i < d.foff[10][f + 1]; ++i) shape_a_rows<10, T, CD>(d, i, U, g);
+      }
     }
+  }
   T* o = block_sum_arr<T, K>(acc, lds);
+  for (int k = threadIdx.x; k < K; k += blockDim.x) atomicAdd(d.shacc + (int64_t)SH_ACC * ch.x + k, (double)o[k]);
+}
+
+// pass A: U_ss, g_s and D_s of each shape from its accumulator
+__global__ void k_shape_a_fin(Dev d) {
+  constexpr int NS = SH_DOF * (SH_DOF + 1) / 2;
+  const int q = blockIdx.x;
+  const double* a = d.shacc + (int64_t)SH_ACC * q;
   const int e0 = a_grp(d, 3, q);
   for (int k = threadIdx.x; k < SH_DOF * SH_DOF; k += blockDim.x)
-    d.Ush[(int64_t)SH_DOF * SH_DOF * q + k] = (double)o[sym<SH_DOF>(k / SH_DOF, k % SH_DOF)];
+    d.Ush[(int64_t)SH_DOF * SH_DOF * q + k] = a[sym<SH_DOF>(k / SH_DOF, k % SH_DOF)];
   for (int k = threadIdx.x; k < SH_DOF; k += blockDim.x) {
-    d.gA[e0 + k] = (double)o[NS + k];
-    d.DA[e0 + k] = fmin(fmax((double)o[sym<SH_DOF>(k, k)], 1e-6), 1e32);
+    d.gA[e0 + k] = a[NS + k];
+    d.DA[e0 + k] = fmin(fmax(a[sym<SH_DOF>(k, k)], 1e-6), 1e32);
   }
 }
 
-template <typename T, int CD> __global__ __launch_bounds__(256) void k_shape_b(Dev d, double lam) {
-  constexpr int NS = SH_DOF * (SH_DOF + 1) / 2, K = NS + SH_DOF;
-  __shared__ T lds[(4 + 1) * K];
+// pass B: the damped diagonal block of S and b of each shape
+__global__ void k_shape_b_fin(Dev d, double lam) {
+  constexpr int NS = SH_DOF * (SH_DOF + 1) / 2;
   const int q = blockIdx.x;
-  T acc[K];
-#pragma unroll
-  for (int k = 0; k < K; ++k) acc[k] = 0;
-  T* C = acc;
-  T* bb = acc + NS;
-  if (d.fn[9])
-    for (int j = d.shp_off[q] + threadIdx.x; j < d.shp_off[q + 1]; j += blockDim.x) {
-      const int f = d.shp[j];
-      T W[SH_DOF][3];
-#pragma unroll
-      for (int a = 0; a < SH_DOF; ++a) W[a][0] = W[a][1] = W[a][2] = 0;
-      for (int64_t i = d.foff[9][f]; i < d.foff[9][f + 1]; ++i) addW_rows<9, 1, T, CD, SH_DOF, 3>(d, i, W);
-      pair_contrib<T, SH_DOF, 3>(d, f, W, C, bb);
-    }
-  if (d.fn[10])
-    for (int j = d.shl_off[q] + threadIdx.x; j < d.shl_off[q + 1]; j += blockDim.x) {
-      const int f = d.shl[j];
-      T W[SH_DOF][4];
-#pragma unroll
-      for (int a = 0; a < SH_DOF; ++a) W[a][0] = W[a][1] = W[a][2] = W[a][3] = 0;
-      for (int64_t i = d.foff[10][f]; i < d.foff[10][f + 1]; ++i) addW_rows<10, 1, T, CD, SH_DOF, 4>(d, i, W);
-      pair_contrib<T, SH_DOF, 4>(d, f, W, C, bb);
-    }
-  T* o = block_sum_arr<T, K>(acc, lds);
+  const double* a = d.shacc + (int64_t)SH_ACC * q;
   const int e0 = a_grp(d, 3, q);
   for (int k = threadIdx.x; k < SH_DOF * SH_DOF; k += blockDim.x) {
-    const int a = k / SH_DOF, b = k % SH_DOF;
+    const int r = k / SH_DOF, c = k % SH_DOF;
     const int64_t idx = (int64_t)SH_DOF * SH_DOF * q + k;
-    double v = d.Ush[idx] + (double)o[sym<SH_DOF>(a, b)];
-    if (a == b) v += lam * d.DA[e0 + a];
+    double v = d.Ush[idx] + a[sym<SH_DOF>(r, c)];
+    if (r == c) v += lam * d.DA[e0 + r];
     d.Ssh[idx] = v;
   }
-  for (int k = threadIdx.x; k < SH_DOF; k += blockDim.x) d.bA[e0 + k] = -d.gA[e0 + k] + (double)o[NS + k];
+  for (int k = threadIdx.x; k < SH_DOF; k += blockDim.x) d.bA[e0 + k] = -d.gA[e0 + k] + a[NS + k];
 }
 
 void launch_shape_pass_a(const Dev& d, hipStream_t s) {
-  if (d.ns) BA_DISPATCH_T_CD(d, k_shape_a<T, CD><<<d.ns, 256, 0, s>>>(d));
+  if (!d.ns) return;
+  launch_zero(d.shacc, (size_t)d.ns * SH_ACC * sizeof(double), s);
+  if (d.n_shch) BA_DISPATCH_T_CD(d, k_shape_chunk<T, CD, false><<<d.n_shch, 256, 0, s>>>(d));
+  k_shape_a_fin<<<d.ns, 128, 0, s>>>(d);
 }
 
 void launch_shape_pass_b(const Dev& d, double lambda, hipStream_t s) {
-  if (d.ns) BA_DISPATCH_T_CD(d, k_shape_b<T, CD><<<d.ns, 256, 0, s>>>(d, lambda));
+  if (!d.ns) return;
+  launch_zero(d.shacc, (size_t)d.ns * SH_ACC * sizeof(double), s);
+  if (d.n_shch) BA_DISPATCH_T_CD(d, k_shape_chunk<T, CD, true><<<d.n_shch, 256, 0, s>>>(d));
+  k_shape_b_fin<<<d.ns, 128, 0, s>>>(d, lambda);
 }
 
-// S Z rows of one shape (a workgroup per shape, as k_sz_grp for planes)
+// S Z rows of the shapes: one workgroup per chunk, as k_sz_grp for a plane, the sums
+// added to the shape's accumulator (d.shsz, cleared first); k_sz_shape_fin writes the rows
 template <typename T, int CD, int L, int CPL>
 __global__ __launch_bounds__(256) void k_sz_shape(Dev d, const T* Zr, const T* sfp, const T* sfl, double lam) {
   constexpr int R = 256 / L, NCOL = L * CPL;
   __shared__ double lds[4 * SH_DOF * NCOL];
-  const int q = blockIdx.x, col = (threadIdx.x % L) * CPL, rs = threadIdx.x / L;
+  const int4 ch = d.shch[blockIdx.x];
+  const int col = (threadIdx.x % L) * CPL, rs = threadIdx.x / L;
   const SzPanels P = sz_panels(d);
   const int pn = col / SZ_COLS, pc = col % SZ_COLS;
   const T* zr = Zr + pn * P.z + pc;
@@ -3687,25 +3710,33 @@ __global__ __launch_bounds__(256) void k_sz_shape(Dev d, const T* Zr, const T* s
   for (int k = 0; k < SH_DOF; ++k)
 #pragma unroll
     for (int c = 0; c < CPL; ++c) acc[k][c] = 0;
-  if (d.fn[9])
-    for (int j = d.shp_off[q] + rs; j < d.shp_off[q + 1]; j += R) {
+  for (int j = ch.y + rs; j < ch.y + ch.z; j += R) {
+    if (ch.w == 0) {
       const int f = d.shp[j];
       for (int64_t i = d.foff[9][f]; i < d.foff[9][f + 1]; ++i)
         sz_rec_rows<9, 1, T, CD>(d, i, zr, sp + (int64_t)f * 3 * SZ_COLS, acc);
-    }
-  if (d.fn[10])
-    for (int j = d.shl_off[q] + rs; j < d.shl_off[q + 1]; j += R) {
+    } else {
       const int f = d.shl[j];
       for (int64_t i = d.foff[10][f]; i < d.foff[10][f + 1]; ++i)
         sz_rec_rows<10, 1, T, CD>(d, i, zr, sl + (int64_t)f * 4 * SZ_COLS, acc);
     }
-  const int e0 = a_grp(d, 3, q);
+  }
+  double* out = d.shsz + (int64_t)SH_DOF * SZ_COLS * SZ_PANELS * ch.x;
   sz_block_sum<SH_DOF, L, CPL>(acc, lds, [&](int row, int cc, double v) {
-    const int col = sz_col(cc / SZ_COLS, cc % SZ_COLS);
-    if (col < 0 || col >= d.coarse_k) return;
-    const int e = e0 + row;
-    d.SZc[(int64_t)col * d.nA + e] = v + lam * d.DA[e] * d.Zc[(int64_t)col * d.nA + e];
+    atomicAdd(out + row * SZ_COLS * SZ_PANELS + cc, v);
   });
+}
+
+__global__ void k_sz_shape_fin(Dev d, double lam) {
+  const int q = blockIdx.x, e0 = a_grp(d, 3, q);
+  const double* a = d.shsz + (int64_t)SH_DOF * SZ_COLS * SZ_PANELS * q;
+  for (int t = threadIdx.x; t < SH_DOF * SZ_COLS * SZ_PANELS; t += blockDim.x) {
+    const int row = t / (SZ_COLS * SZ_PANELS), cc = t % (SZ_COLS * SZ_PANELS);
+    const int col = sz_col(cc / SZ_COLS, cc % SZ_COLS);
+    if (col < 0 || col >= d.coarse_k) continue;
+    const int e = e0 + row;
+    d.SZc[(int64_t)col * d.nA + e] = a[t] + lam * d.DA[e] * d.Zc[(int64_t)col * d.nA + e];
+  }
 }
 
 // x [+] h of every shape (the tangent updates of ba_shape.h), one thread per shape
