@@ -1076,10 +1076,10 @@ void finalize(ba_handle* h) {
     if (const char* e = std::getenv("BA_TILE_RECORDS")) cap = std::max(1, std::min(MV_TILE, std::atoi(e)));
     for (int fam = 1; fam < NFAM; ++fam)
       if (d.fn[fam] >= (int64_t)1 << 28) throw BaError(BA_E_INVALID, "more than 2^28 records in one family");
-    // a feature with surface-group records (family 9 / 10) takes the one-lane-per-feature
-    // path too, so that the tiles hold only the smaller slots
-    auto build = [&](const std::vector<int>& fams, int nfeat, std::vector<int32_t>& big, int fam_sh) {
-      auto on_shape = [&](int f) { return foff_h[fam_sh][f + 1] > foff_h[fam_sh][f]; };
+    // a line on a cuboid (family 10, whose slots exceed the tiles' register budget) takes
+    // the one-lane-per-feature path; points on shapes (family 9) go in the tiles
+    auto build = [&](const std::vector<int>& fams, int nfeat, std::vector<int32_t>& big, int fam_big) {
+      auto on_shape = [&](int f) { return fam_big > 0 && foff_h[fam_big][f + 1] > foff_h[fam_big][f]; };
       int f = 0;
       while (f < nfeat) {
         const int fb = f;
@@ -1105,7 +1105,7 @@ void finalize(ba_handle* h) {
         tiles.push_back(make_int4(first, (int)cnt, fb, 0));
       }
     };
-    build({1, 3, 6, 8}, h->np, bigp, 9);
+    build({1, 3, 6, 8, 9}, h->np, bigp, -1);
     d.n_ptiles = (int)tiles.size();
     build({2, 4, 5, 7}, h->nl, bigl, 10);
     d.n_tiles = (int)tiles.size();

@@ -90,7 +90,7 @@ struct Dev {
   // surface groups: per shape its points (family 9) and lines (family 10) in feature order;
   // per observation record (camera-major position of R1 / R2) the index of the family 9 /
   // 10 record of the same camera and feature, or -1.  A point or line is on at most one
-  // shape, and every feature with such records is one of the product's big features.
+  // shape; a line on a cuboid is one of the product's big features.
   int32_t *shp_off = nullptr, *shp = nullptr, *shl_off = nullptr, *shl = nullptr;
   int32_t *shal_p = nullptr, *shal_l = nullptr;
   // the shape passes take chunks of at most SH_CHUNK members of one shape, a workgroup

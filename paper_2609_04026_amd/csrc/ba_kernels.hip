@@ -1585,6 +1585,8 @@ template <typename T, int CD, int NF> __device__ __forceinline__ void mv_feature
 //      workgroup's y, which all its wavefronts share)
 // Each workgroup writes its y to its row of the partial buffer.
 template <int CD> struct MaxSlot { static constexpr int V = Slot<4, CD>::STRIDE; };
+static_assert(Slot<9, 9>::STRIDE <= MaxSlot<9>::V && Slot<9, 6>::STRIDE <= MaxSlot<6>::V,
+              "point-on-shape records fit the tiles' register slot");
 
 template <int FAM, typename T, int CD>
 __device__ __forceinline__ void tile_phase_a(const Dev& d, int64_t i, int cam, int grp, const T* x, T (&qv)[4],
@@ -1748,6 +1750,7 @@ __global__ __launch_bounds__(MV_THREADS) void k_mv_wave(Dev d, const double* don
         case 6: tile_phase_a<6, T, CD>(d, i, w4.y, w4.z, x, q, v, t, ac, ag); break;
         case 7: tile_phase_a<7, T, CD>(d, i, w4.y, w4.z, x, q, v, t, ac, ag); break;
         case 8: tile_phase_a<8, T, CD>(d, i, w4.y, w4.z, x, q, v, t, ac, ag); break;
+        case 9: tile_phase_a<9, T, CD>(d, i, w4.y, w4.z, x, q, v, t, ac, ag); break;
       }
     }
     // segmented inclusive scan over runs of equal lf (lanes are in feature
@@ -1798,6 +1801,7 @@ __global__ __launch_bounds__(MV_THREADS) void k_mv_wave(Dev d, const double* don
           case 6: tile_phase_c<6, T, CD>(v, t, ac, ag, s, ys); break;
           case 7: tile_phase_c<7, T, CD>(v, t, ac, ag, s, ys); break;
           case 8: tile_phase_c<8, T, CD>(v, t, ac, ag, s, ys); break;
+          case 9: tile_phase_c<9, T, CD>(v, t, ac, ag, s, ys); break;
         }
       } else {
         switch (fam) {
@@ -1809,6 +1813,7 @@ __global__ __launch_bounds__(MV_THREADS) void k_mv_wave(Dev d, const double* don
           case 6: tile_phase_c_reload<6, T, CD>(d, i, t, ac, ag, s, ys); break;
           case 7: tile_phase_c_reload<7, T, CD>(d, i, t, ac, ag, s, ys); break;
           case 8: tile_phase_c_reload<8, T, CD>(d, i, t, ac, ag, s, ys); break;
+          case 9: tile_phase_c_reload<9, T, CD>(d, i, t, ac, ag, s, ys); break;
         }
       }
     }
@@ -2656,6 +2661,7 @@ template <typename T, int CD> __global__ __launch_bounds__(256) void k_sz_feat_w
         case 6: sz_wave_q<6, T, CD>(d, i, w4.y, w4.z, Zr, q); break;
         case 7: sz_wave_q<7, T, CD>(d, i, w4.y, w4.z, Zr, q); break;
         case 8: sz_wave_q<8, T, CD>(d, i, w4.y, w4.z, Zr, q); break;
+        case 9: sz_wave_q<9, T, CD>(d, i, w4.y, w4.z, Zr, q); break;
       }
     }
     const int prev = __shfl_up(lf, 1, 64);
@@ -3263,6 +3269,7 @@ template <typename T, int CD> __global__ __launch_bounds__(256) void k_backsub_w
         case 6: tile_phase_a<6, T, CD>(d, i, w4.y, w4.z, x, q, v, t, ac, ag); break;
         case 7: tile_phase_a<7, T, CD>(d, i, w4.y, w4.z, x, q, v, t, ac, ag); break;
         case 8: tile_phase_a<8, T, CD>(d, i, w4.y, w4.z, x, q, v, t, ac, ag); break;
+        case 9: tile_phase_a<9, T, CD>(d, i, w4.y, w4.z, x, q, v, t, ac, ag); break;
       }
     }
     const int prev = __shfl_up(lf, 1, 64);
@@ -3310,6 +3317,7 @@ template <typename T, int CD> __global__ __launch_bounds__(256) void k_backsub_w
           case 6: jh2 += bs_record<6, T, CD>(v, t, h); break;
           case 7: jh2 += bs_record<7, T, CD>(v, t, h); break;
           case 8: jh2 += bs_record<8, T, CD>(v, t, h); break;
+          case 9: jh2 += bs_record<9, T, CD>(v, t, h); break;
         }
       } else {
         switch (fam) {
@@ -3321,6 +3329,7 @@ template <typename T, int CD> __global__ __launch_bounds__(256) void k_backsub_w
           case 6: jh2 += bs_record_reload<6, T, CD>(d, i, t, h); break;
           case 7: jh2 += bs_record_reload<7, T, CD>(d, i, t, h); break;
           case 8: jh2 += bs_record_reload<8, T, CD>(d, i, t, h); break;
+          case 9: jh2 += bs_record_reload<9, T, CD>(d, i, t, h); break;
         }
       }
     }

@@ -200,3 +200,33 @@ def test_shape_refusals(case):
     with pytest.raises(BAError, match="not a cuboid"):
         ba.lm_step(lambda0=1e-3)
     ba.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_shape_points_on_the_large_feature_path(case, monkeypatch, precision):
+    """Tiles of at most 4 records route most points (shape points included) through the
+    product's one-lane-per-feature path (and the S Z and back-substitution lanes): the
+    product, S Z of the gauge coarse space and one step against the oracle."""
+    s, prob, st, lin = case
+    monkeypatch.setenv("BA_TILE_RECORDS", "4")
+    lam = 1e-3
+    Sx = lm.schur(prob, lin, lam)["S"]
+    ba = _BA().from_scene(s, precision=precision, precond="gauge")
+    ba.linearize(lam)
+    tol = 1e-9 if precision == "fp64" else 1e-4
+    rng = np.random.default_rng(5)
+    x = rng.normal(size=Sx.shape[0])
+    err = np.abs(ba.schur_matvec(x) - Sx @ x) / np.maximum(np.abs(Sx) @ np.abs(x), 1e-300)
+    assert err.max() <= 10 * tol, err.max()
+    cs = ba.export_coarse_space()
+    if cs is not None:
+        Z, SZ = cs
+        col_err = np.linalg.norm(SZ - Sx @ Z, axis=0) / np.linalg.norm(np.abs(Sx) @ np.abs(Z), axis=0)
+        assert col_err.max() <= tol, col_err
+    ba.close()
+    ba = _BA().from_scene(s, precision=precision)
+    rep = ba.lm_step(lambda0=lam, pcg_tol=1e-12 if precision == "fp64" else 1e-7, pcg_max_iters=3000)
+    h, _ = lm.solve_schur(prob, lin, lam)
+    E1 = lm.cost(prob, prob.retract(st, h))[0]
+    assert abs(rep["E_after"] - E1) <= (1e-9 if precision == "fp64" else 1e-4) * E1
+    ba.close()
