@@ -127,6 +127,7 @@ struct Dev {
   int64_t n_red_max = 0;    // pairs of partials red holds
   int n_mv_wg = 0;          // matvec workgroups (partials rows)
   int mv_lds = 0;           // 1: accumulate in LDS
+  int mv_stage = 0;         // 1: FP32 with point-on-shape records (LDS staging of their rows)
   // wavefront tiles of the product: int4 (first slot, slots, first feature, 0), point tiles
   // first, then line tiles; one slot per record in feature order, int4 ((family << 28) |
   // record, camera, group, feature - first feature of the tile)
@@ -202,6 +203,9 @@ __host__ __device__ __forceinline__ int a_grp(const Dev& d, int gt, int g) {
 // product: 1024-thread workgroups sharing one FP64 copy of y in LDS (FP32 LDS atomics
 // measured 2x slower on gfx950); each wavefront takes tiles of at most MV_TILE records
 constexpr int MV_THREADS = 1024, MV_TILE = 64;
+// LDS staging of the FP32 product on scenes with point-on-shape records, after y: the
+// shape rows of each wavefront's lanes (SH_DOF x 64 floats) and each lane's shape offset
+constexpr int MV_STAGE_BYTES = MV_THREADS / 64 * SH_DOF * 64 * 4 + MV_THREADS * 4;
 
 // indices into Dev::scal
 enum PcgScal {
@@ -308,6 +312,8 @@ void launch_zero(void* p, size_t bytes, hipStream_t s);
 // (residual in the quadratic part of the loss), observations, and sigma =
 // lambda_min(V_f)^-1/2 (points: over the mean distance to the observing cameras)
 void launch_feature_stats(const Dev& d, int32_t* n_active, int32_t* n_obs, double* sigma, int nf, hipStream_t s);
+// the product's dynamic LDS: the most a workgroup may take, and what it takes for d (y
+// when accumulated in LDS, then the staging)
 int matvec_max_lds_bytes();
 size_t matvec_lds_bytes(const Dev& d);
 

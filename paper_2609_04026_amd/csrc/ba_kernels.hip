@@ -696,13 +696,13 @@ __device__ __forceinline__ void sz_feat_rows(const Dev& d, int f, const T* Zr, T
       T t[NCOL];
 #pragma unroll
       for (int c = 0; c < NCOL; ++c) t[c] = 0;
-#pragma unroll 1
+#pragma unroll
       for (int k = 0; k < SL::NC; ++k) {
         const T j = sl[SL::OC + row * SL::NC + k];
 #pragma unroll
         for (int c = 0; c < NCOL; ++c) t[c] += j * zc[k * NCOL + c];
       }
-#pragma unroll 1
+#pragma unroll
       for (int k = 0; k < SL::NG; ++k) {
         const T j = sl[SL::OG + row * SL::NG + k];
 #pragma unroll
@@ -718,45 +718,57 @@ __device__ __forceinline__ void sz_feat_rows(const Dev& d, int f, const T* Zr, T
   }
 }
 
-// S Z sweeps, output rows: one surface-group record, CPL columns of the panel zr (offset
-// to the lane's first column), u = J_a z - J_f s_f; the camera (OUT 0) or shape (OUT 1)
-// rows of J^T u added to acc
-template <int FAM, int OUT, typename T, int CD, int NO, int CPL>
-__device__ __forceinline__ void sz_rec_rows(const Dev& d, int64_t i, const T* zr, const T* s, double (&acc)[NO][CPL]) {
+// S Z sweeps, output rows, with the Z rows of the output side in registers: zk holds the
+// rows of the record's camera (OUT 0, a camera's sweep) or of its shape (OUT 1, a shape's
+// chunk), which the caller keeps for all its records; the other side's rows and s_f are
+// read from the panel. The loads of a row are independent of one another, so their
+// latencies overlap; the rows go one at a time to bound the registers.
+template <int FAM, int OUT, typename T, int CD, int CPL, int NK>
+__device__ __forceinline__ void sz_shape_rec(const Dev& d, int64_t i, const T (&zk)[NK][CPL], const T* zr, const T* s,
+                                             double (&acc)[NK][CPL]) {
   using SL = Slot<FAM, CD>;
-  constexpr int NK = OUT == 0 ? SL::NC : SL::NG, O = OUT == 0 ? SL::OC : SL::OG;
-  static_assert(NO >= NK, "output rows");
+  using F = Fam<FAM, CD>;
+  constexpr int NU = OUT == 0 ? SL::NC : SL::NG, NO = OUT == 0 ? SL::NG : SL::NC;
+  static_assert(NK >= NU, "the output side's rows (a line's camera columns are the first NC)");
+  constexpr int OK = OUT == 0 ? SL::OC : SL::OG, OO = OUT == 0 ? SL::OG : SL::OC;
   const T* sl = (const T*)d.frec[FAM] + i * SL::STRIDE;
-  const int ac = CD * d.fcam[FAM][i], ag = a_grp(d, 3, d.fgrp[FAM][i]);
+  const int64_t e = OUT == 0 ? (int64_t)a_grp(d, F::GT, d.fgrp[FAM][i]) : (int64_t)CD * d.fcam[FAM][i];
+  T zo[NO][CPL], sf[SL::NF][CPL];
+#pragma unroll
+  for (int k = 0; k < NO; ++k)
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) zo[k][c] = zr[(e + k) * SZ_COLS + c];
+#pragma unroll
+  for (int a = 0; a < SL::NF; ++a)
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) sf[a][c] = s[a * SZ_COLS + c];
 #pragma unroll 1
   for (int row = 0; row < SL::ROWS; ++row) {
-    T u[CPL];
+    T jk[NU], u[CPL];
 #pragma unroll
     for (int c = 0; c < CPL; ++c) u[c] = 0;
-#pragma unroll 1
-    for (int k = 0; k < SL::NC; ++k) {
-      const T j = sl[SL::OC + row * SL::NC + k];
 #pragma unroll
-      for (int c = 0; c < CPL; ++c) u[c] += j * zr[(int64_t)(ac + k) * SZ_COLS + c];
+    for (int k = 0; k < NU; ++k) {
+      jk[k] = sl[OK + row * NU + k];
+#pragma unroll
+      for (int c = 0; c < CPL; ++c) u[c] += jk[k] * zk[k][c];
     }
-#pragma unroll 1
-    for (int k = 0; k < SL::NG; ++k) {
-      const T j = sl[SL::OG + row * SL::NG + k];
 #pragma unroll
-      for (int c = 0; c < CPL; ++c) u[c] += j * zr[(int64_t)(ag + k) * SZ_COLS + c];
+    for (int k = 0; k < NO; ++k) {
+      const T j = sl[OO + row * NO + k];
+#pragma unroll
+      for (int c = 0; c < CPL; ++c) u[c] += j * zo[k][c];
     }
 #pragma unroll
     for (int a = 0; a < SL::NF; ++a) {
       const T j = sl[SL::OF + row * SL::NF + a];
 #pragma unroll
-      for (int c = 0; c < CPL; ++c) u[c] -= j * s[a * SZ_COLS + c];
+      for (int c = 0; c < CPL; ++c) u[c] -= j * sf[a][c];
     }
 #pragma unroll
-    for (int k = 0; k < NK; ++k) {
-      const T j = sl[O + row * NK + k];
+    for (int k = 0; k < NU; ++k)
 #pragma unroll
-      for (int c = 0; c < CPL; ++c) acc[k][c] += (double)(j * u[c]);
-    }
+      for (int c = 0; c < CPL; ++c) acc[k][c] += (double)(jk[k] * u[c]);
   }
 }
 
@@ -1634,10 +1646,28 @@ __device__ __forceinline__ void tile_phase_a(const Dev& d, int64_t i, int cam, i
   }
 }
 
+// sum of v over the 64 lanes of a wavefront whose lanes are all active, the same on every
+// lane: xor exchanges within each half by ds_swizzle (its lane pattern is an immediate,
+// so no address register is held), then the two halves' sums read from lanes 0 and 32
+__device__ __forceinline__ float wave_sum(float v) {
+  v += __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x1F | (1 << 10)));
+  v += __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x1F | (2 << 10)));
+  v += __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x1F | (4 << 10)));
+  v += __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x1F | (8 << 10)));
+  v += __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x1F | (16 << 10)));
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 0)) +
+         __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 32));
+}
+
+// In FP32 the shape rows (group type 3) are staged in the wavefront's LDS rows gz[k *
+// 64] for the wavefront's sum after the tile (a tile's lanes are mostly points of one
+// shape); every other row is added to y here.
 template <int FAM, typename T, int CD>
 __device__ __forceinline__ void tile_phase_c(const T (&v)[MaxSlot<CD>::V], const T (&t)[4], int ac, int ag,
-                                             const T (&sv)[4], double* y) {
+                                             const T (&sv)[4], double* y, T* gz) {
   using SL = Slot<FAM, CD>;
+  constexpr bool WAVE_G = Fam<FAM, CD>::GT == 3 && sizeof(T) == 4;
+  static_assert(!WAVE_G || SL::NG == SH_DOF, "shape rows");
   T zc[SL::NC > 0 ? SL::NC : 1], zg[SL::NG > 0 ? SL::NG : 1];
 #pragma unroll
   for (int k = 0; k < SL::NC; ++k) zc[k] = 0;
@@ -1655,14 +1685,19 @@ __device__ __forceinline__ void tile_phase_c(const T (&v)[MaxSlot<CD>::V], const
   }
 #pragma unroll
   for (int k = 0; k < SL::NC; ++k) atomicAdd(y + ac + k, (double)zc[k]);
+  if constexpr (WAVE_G) {
 #pragma unroll
-  for (int k = 0; k < SL::NG; ++k) atomicAdd(y + ag + k, (double)zg[k]);
+    for (int k = 0; k < SH_DOF; ++k) gz[k * 64] = zg[k];
+  } else {
+#pragma unroll
+    for (int k = 0; k < SL::NG; ++k) atomicAdd(y + ag + k, (double)zg[k]);
+  }
 }
 
 // FP64 records are reloaded for phase C instead of being held in registers
 template <int FAM, typename T, int CD>
 __device__ __forceinline__ void tile_phase_c_reload(const Dev& d, int64_t i, const T (&t)[4], int ac, int ag,
-                                                    const T (&sv)[4], double* y) {
+                                                    const T (&sv)[4], double* y, T* gz) {
   using SL = Slot<FAM, CD>;
   T v[MaxSlot<CD>::V];
   const double2* q2 = reinterpret_cast<const double2*>((const T*)d.frec[FAM] + i * SL::STRIDE);
@@ -1671,7 +1706,7 @@ __device__ __forceinline__ void tile_phase_c_reload(const Dev& d, int64_t i, con
     double2 a = q2[k];
     v[2 * k] = a.x; v[2 * k + 1] = a.y;
   }
-  tile_phase_c<FAM, T, CD>(v, t, ac, ag, sv, y);
+  tile_phase_c<FAM, T, CD>(v, t, ac, ag, sv, y, gz);
 }
 
 // s = (V_f + lambda D_f)^-1 q for feature f from its packed FP32 inverse Mi, or
@@ -1703,6 +1738,14 @@ __global__ __launch_bounds__(MV_THREADS) void k_mv_wave(Dev d, const double* don
   extern __shared__ __align__(16) unsigned char smem_raw[];
   if (done && *done != 0.0) return;
   double* ys = LDSY ? reinterpret_cast<double*>(smem_raw) : d.mv_part;
+  // FP32 shape rows staged per lane (column lane of the wavefront's SH_DOF x 64 rows),
+  // and the lane's shape offset in y (-1: not a shape record), after y in LDS; present
+  // when d.mv_stage (then every tile writes its offsets). A lane reads back only what it
+  // wrote, and nothing of it stays in registers across the record phases.
+  constexpr bool STAGE = sizeof(T) == 4 && !SONLY;
+  const bool stage = STAGE && d.mv_stage;
+  float* mv_stage = reinterpret_cast<float*>(smem_raw + (LDSY ? 8 * (size_t)d.nA : 0));
+  int* mv_shag = reinterpret_cast<int*>(mv_stage + MV_THREADS / 64 * SH_DOF * 64);
   const T* x = (const T*)d.xT;
   if constexpr (LDSY) {
     for (int k = threadIdx.x; k < d.nA; k += blockDim.x) ys[k] = 0;
@@ -1787,34 +1830,56 @@ __global__ __launch_bounds__(MV_THREADS) void k_mv_wave(Dev d, const double* don
       }
       continue;
     }
+    if (stage) mv_shag[threadIdx.x] = active && fam == 9 ? ag : -1;
     const int src = lf >= 0 ? __builtin_ctzll(lasts & (~0ull << lane)) : lane;
 #pragma unroll
     for (int a = 0; a < 4; ++a) s[a] = __shfl(s[a], src, 64);
     if (active) {
       if constexpr (sizeof(T) == 4) {
         switch (fam) {
-          case 1: tile_phase_c<1, T, CD>(v, t, ac, ag, s, ys); break;
-          case 2: tile_phase_c<2, T, CD>(v, t, ac, ag, s, ys); break;
-          case 3: tile_phase_c<3, T, CD>(v, t, ac, ag, s, ys); break;
-          case 4: tile_phase_c<4, T, CD>(v, t, ac, ag, s, ys); break;
-          case 5: tile_phase_c<5, T, CD>(v, t, ac, ag, s, ys); break;
-          case 6: tile_phase_c<6, T, CD>(v, t, ac, ag, s, ys); break;
-          case 7: tile_phase_c<7, T, CD>(v, t, ac, ag, s, ys); break;
-          case 8: tile_phase_c<8, T, CD>(v, t, ac, ag, s, ys); break;
-          case 9: tile_phase_c<9, T, CD>(v, t, ac, ag, s, ys); break;
+          case 1: tile_phase_c<1, T, CD>(v, t, ac, ag, s, ys, nullptr); break;
+          case 2: tile_phase_c<2, T, CD>(v, t, ac, ag, s, ys, nullptr); break;
+          case 3: tile_phase_c<3, T, CD>(v, t, ac, ag, s, ys, nullptr); break;
+          case 4: tile_phase_c<4, T, CD>(v, t, ac, ag, s, ys, nullptr); break;
+          case 5: tile_phase_c<5, T, CD>(v, t, ac, ag, s, ys, nullptr); break;
+          case 6: tile_phase_c<6, T, CD>(v, t, ac, ag, s, ys, nullptr); break;
+          case 7: tile_phase_c<7, T, CD>(v, t, ac, ag, s, ys, nullptr); break;
+          case 8: tile_phase_c<8, T, CD>(v, t, ac, ag, s, ys, nullptr); break;
+          case 9: tile_phase_c<9, T, CD>(v, t, ac, ag, s, ys, reinterpret_cast<T*>(mv_stage) + (threadIdx.x >> 6) * SH_DOF * 64 + lane); break;
         }
       } else {
         switch (fam) {
-          case 1: tile_phase_c_reload<1, T, CD>(d, i, t, ac, ag, s, ys); break;
-          case 2: tile_phase_c_reload<2, T, CD>(d, i, t, ac, ag, s, ys); break;
-          case 3: tile_phase_c_reload<3, T, CD>(d, i, t, ac, ag, s, ys); break;
-          case 4: tile_phase_c_reload<4, T, CD>(d, i, t, ac, ag, s, ys); break;
-          case 5: tile_phase_c_reload<5, T, CD>(d, i, t, ac, ag, s, ys); break;
-          case 6: tile_phase_c_reload<6, T, CD>(d, i, t, ac, ag, s, ys); break;
-          case 7: tile_phase_c_reload<7, T, CD>(d, i, t, ac, ag, s, ys); break;
-          case 8: tile_phase_c_reload<8, T, CD>(d, i, t, ac, ag, s, ys); break;
-          case 9: tile_phase_c_reload<9, T, CD>(d, i, t, ac, ag, s, ys); break;
+          case 1: tile_phase_c_reload<1, T, CD>(d, i, t, ac, ag, s, ys, nullptr); break;
+          case 2: tile_phase_c_reload<2, T, CD>(d, i, t, ac, ag, s, ys, nullptr); break;
+          case 3: tile_phase_c_reload<3, T, CD>(d, i, t, ac, ag, s, ys, nullptr); break;
+          case 4: tile_phase_c_reload<4, T, CD>(d, i, t, ac, ag, s, ys, nullptr); break;
+          case 5: tile_phase_c_reload<5, T, CD>(d, i, t, ac, ag, s, ys, nullptr); break;
+          case 6: tile_phase_c_reload<6, T, CD>(d, i, t, ac, ag, s, ys, nullptr); break;
+          case 7: tile_phase_c_reload<7, T, CD>(d, i, t, ac, ag, s, ys, nullptr); break;
+          case 8: tile_phase_c_reload<8, T, CD>(d, i, t, ac, ag, s, ys, nullptr); break;
+          case 9: tile_phase_c_reload<9, T, CD>(d, i, t, ac, ag, s, ys, nullptr); break;
         }
+      }
+    }
+    // FP32 shape rows: the lanes on the wavefront's first shape are summed across it and
+    // added once (one LDS add per row, not one per record on the same address); lanes on
+    // another shape add their own. A lane reads back only what it staged itself.
+    if (stage) {
+      const int shag = mv_shag[threadIdx.x];
+      const unsigned long long gm = __ballot(shag >= 0);
+      if (gm) {
+        const int l = threadIdx.x & 63, lead = __builtin_ctzll(gm);
+        const int ag0 = __builtin_amdgcn_readlane(shag, lead);
+        const bool mine = shag == ag0;
+        const float* gst = mv_stage + (threadIdx.x >> 6) * SH_DOF * 64 + l;
+#pragma unroll
+        for (int k = 0; k < SH_DOF; ++k) {
+          const float w = wave_sum(mine ? gst[k * 64] : 0.0f);
+          if (l == lead) atomicAdd(ys + ag0 + k, (double)w);
+        }
+        if (shag >= 0 && !mine)
+#pragma unroll
+          for (int k = 0; k < SH_DOF; ++k) atomicAdd(ys + shag + k, (double)gst[k * 64]);
       }
     }
   }
@@ -1849,7 +1914,7 @@ int matvec_max_lds_bytes() {
   return v;
 }
 
-size_t matvec_lds_bytes(const Dev& d) { return d.mv_lds ? 8 * (size_t)d.nA : 0; }
+size_t matvec_lds_bytes(const Dev& d) { return (d.mv_lds ? 8 * (size_t)d.nA : 0) + (d.mv_stage ? MV_STAGE_BYTES : 0); }
 
 template <typename T, int CD, bool LDSY> static void launch_mv(const Dev& d, const double* done, hipStream_t s) {
   static bool attr = false;
@@ -2810,7 +2875,7 @@ __global__ __launch_bounds__(256) void k_sz_cam(Dev d, const T* Zr, const T* sfp
       }
       if (d.shal_p) {
         const int k9 = d.shal_p[j];
-        if (k9 >= 0) sz_rec_rows<9, 0, T, CD>(d, k9, zr, sp + (int64_t)f * 3 * SZ_COLS, acc);
+        if (k9 >= 0) sz_shape_rec<9, 0, T, CD, CPL>(d, k9, zc, zr, sp + (int64_t)f * 3 * SZ_COLS, acc);
       }
     }
   if (d.fn[6])
@@ -2829,7 +2894,7 @@ __global__ __launch_bounds__(256) void k_sz_cam(Dev d, const T* Zr, const T* sfp
       }
       if (d.shal_l) {
         const int k10 = d.shal_l[j];
-        if (k10 >= 0) sz_rec_rows<10, 0, T, CD>(d, k10, zr, sl + (int64_t)f * 4 * SZ_COLS, acc);
+        if (k10 >= 0) sz_shape_rec<10, 0, T, CD, CPL>(d, k10, zc, zr, sl + (int64_t)f * 4 * SZ_COLS, acc);
       }
     }
   if (d.fn[7])
@@ -3719,15 +3784,18 @@ __global__ __launch_bounds__(256) void k_sz_shape(Dev d, const T* Zr, const T* s
   for (int k = 0; k < SH_DOF; ++k)
 #pragma unroll
     for (int c = 0; c < CPL; ++c) acc[k][c] = 0;
+  // every member of a chunk is on the chunk's shape (one shape per point or line)
+  T zs[SH_DOF][CPL];
+  z_cols<SH_DOF, CPL>(zr, a_grp(d, 3, ch.x), zs);
   for (int j = ch.y + rs; j < ch.y + ch.z; j += R) {
     if (ch.w == 0) {
       const int f = d.shp[j];
       for (int64_t i = d.foff[9][f]; i < d.foff[9][f + 1]; ++i)
-        sz_rec_rows<9, 1, T, CD>(d, i, zr, sp + (int64_t)f * 3 * SZ_COLS, acc);
+        sz_shape_rec<9, 1, T, CD, CPL>(d, i, zs, zr, sp + (int64_t)f * 3 * SZ_COLS, acc);
     } else {
       const int f = d.shl[j];
       for (int64_t i = d.foff[10][f]; i < d.foff[10][f + 1]; ++i)
-        sz_rec_rows<10, 1, T, CD>(d, i, zr, sl + (int64_t)f * 4 * SZ_COLS, acc);
+        sz_shape_rec<10, 1, T, CD, CPL>(d, i, zs, zr, sl + (int64_t)f * 4 * SZ_COLS, acc);
     }
   }
   double* out = d.shsz + (int64_t)SH_DOF * SZ_COLS * SZ_PANELS * ch.x;

@@ -172,8 +172,8 @@ def add_shapes(scene, seed, noise=True, points_per_shape=14, lines_per_cuboid=6)
 
     tr_pt = _sample_tracks(cams, nbrs, pts, None, 3, rng)
     tr_ln = _sample_tracks(cams, nbrs, seg_a, seg_b, 3, rng, min_len=30.0)
-    kp = np.array([len(x) > 0 for x in tr_pt])
-    kl = np.array([len(x) > 0 for x in tr_ln])
+    kp = np.array([len(x) > 0 for x in tr_pt], dtype=bool)
+    kl = np.array([len(x) > 0 for x in tr_ln], dtype=bool)
     pts, sh_of_pt, tr_pt = pts[kp], sh_of_pt[kp], [x for x, k in zip(tr_pt, kp) if k]
     seg_a, seg_b, tr_ln = seg_a[kl], seg_b[kl], [x for x, k in zip(tr_ln, kl) if k]
     pix = cfg["pix"] if noise else 0.0

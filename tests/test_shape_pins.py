@@ -370,3 +370,16 @@ def test_similarity_gauge_is_a_null_vector_of_the_jacobian():
     o = prob.off["sh"]
     Z2[o:o + 9 * prob.n["sh"]] = 0
     assert np.abs(lin.J @ Z2).max() > 1e-3 * scale
+
+
+def test_shapes_without_cuboid_lines():
+    """The generator adds point-on-shape associations only when asked for no lines on the
+    cuboid (an empty line set keeps boolean masks), and the oracle's problem then has R13
+    records and no R14 records."""
+    from scenegen.scene import ASSOC_SHAPE_POINT, ASSOC_SHAPE_LINE
+    base = make_scene(small_config(n_cams=9, n_points=40, n_lines=12, n_vps=0, vp_lines=0), seed=41)
+    s = add_shapes(base, seed=3, points_per_shape=50, lines_per_cuboid=0)
+    assert len(s["obs"][ASSOC_SHAPE_LINE][0]) == 0 and len(s["obs"][ASSOC_SHAPE_POINT][0]) > 0
+    assert len(s["lines"]) == len(base["lines"])
+    prob = lm.Problem(s)
+    assert prob.record_count("R13") > 0 and prob.record_count("R14") == 0
