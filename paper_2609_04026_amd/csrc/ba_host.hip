@@ -1132,7 +1132,8 @@ void finalize(ba_handle* h) {
   const int wg_per_cu = (int)std::max<size_t>(1, std::min<size_t>(2, 163840 / std::max<size_t>(lds_bytes, 1)));
   const int64_t waves = d.n_tiles + (d.n_bigp + d.n_bigl + 63) / 64;
   d.n_mv_wg = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)ncu * wg_per_cu, (waves + MV_THREADS / 64 - 1) / (MV_THREADS / 64)));
-  d.mv_part = A.get<double>(d.mv_lds ? (size_t)d.n_mv_wg * nA : (size_t)nA);
+  const size_t mv_rows = d.mv_lds ? (size_t)d.n_mv_wg : 1;
+  d.mv_part = A.get<double>(mv_rows * nA);
   d.cnt = A.get<unsigned int>(4);
   launch_zero(d.cnt, 4 * sizeof(unsigned int), h->stream);
   d.part2 = A.get<double>(2 * ((size_t)nA / 64 + 2) + 256);
@@ -1143,7 +1144,7 @@ void finalize(ba_handle* h) {
   launch_zero(d.detp, (size_t)(SC_COUNT + COARSE_K) * d.det_stride * sizeof(double), h->stream);
   d.sdp = A.get<char>((size_t)h->np * 3, TS);
   d.sdl = A.get<char>((size_t)h->nl * 4, TS);
-  launch_zero(d.mv_part, (d.mv_lds ? (size_t)d.n_mv_wg * nA : (size_t)nA) * sizeof(double), h->stream);
+  launch_zero(d.mv_part, mv_rows * nA * sizeof(double), h->stream);
   d.scal = A.get<double>(SC_COUNT);
   launch_zero(d.scal, SC_COUNT * sizeof(double), h->stream);
   const int64_t fe_blocks = (h->np + 255) / 256 + (h->nl + 255) / 256;

@@ -203,6 +203,9 @@ __host__ __device__ __forceinline__ int a_grp(const Dev& d, int gt, int g) {
 // product: 1024-thread workgroups sharing one FP64 copy of y in LDS (FP32 LDS atomics
 // measured 2x slower on gfx950); each wavefront takes tiles of at most MV_TILE records
 constexpr int MV_THREADS = 1024, MV_TILE = 64;
+// the product's large features (k_mv_big): 8 wavefronts per workgroup, each one feature,
+// with the shape rows summed in LDS when at most MV_BIG_SH_MAX of them
+constexpr int MV_BIG_THREADS = 512, MV_BIG_SH_MAX = 4096;
 // LDS staging of the FP32 product on scenes with point-on-shape records, after y: the
 // shape rows of each wavefront's lanes (SH_DOF x 64 floats) and each lane's shape offset
 constexpr int MV_STAGE_BYTES = MV_THREADS / 64 * SH_DOF * 64 * 4 + MV_THREADS * 4;

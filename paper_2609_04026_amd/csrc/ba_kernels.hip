@@ -604,60 +604,7 @@ __device__ __forceinline__ void addW_rows(const Dev& d, int64_t i, T (&W)[N][NF]
   }
 }
 
-// product, first half: q += sum over the feature's surface-group records of J_f^T J_a x
-template <int FAM, typename T, int CD, int NF> __device__ __forceinline__ void mv_first_rows(const Dev& d, int f, const T* x, T (&q)[NF]) {
-  using SL = Slot<FAM, CD>;
-  if (!d.fn[FAM]) return;
-  for (int64_t i = d.foff[FAM][f]; i < d.foff[FAM][f + 1]; ++i) {
-    const T* sl = (const T*)d.frec[FAM] + i * SL::STRIDE;
-    const T* xc = x + CD * d.fcam[FAM][i];
-    const T* xg = x + a_grp(d, 3, d.fgrp[FAM][i]);
-#pragma unroll 1
-    for (int row = 0; row < SL::ROWS; ++row) {
-      T t = 0;
-#pragma unroll
-      for (int k = 0; k < SL::NC; ++k) t += sl[SL::OC + row * SL::NC + k] * xc[k];
-#pragma unroll
-      for (int k = 0; k < SL::NG; ++k) t += sl[SL::OG + row * SL::NG + k] * xg[k];
-#pragma unroll
-      for (int a = 0; a < NF; ++a) q[a] += sl[SL::OF + row * NF + a] * t;
-    }
-  }
-}
 
-// product, second half: y_a += J_a^T (J_a x - J_f s) over the feature's surface-group records
-template <int FAM, typename T, int CD, int NF>
-__device__ __forceinline__ void mv_second_rows(const Dev& d, int f, const T* x, const T (&s)[NF], double* y) {
-  using SL = Slot<FAM, CD>;
-  if (!d.fn[FAM]) return;
-  for (int64_t i = d.foff[FAM][f]; i < d.foff[FAM][f + 1]; ++i) {
-    const T* sl = (const T*)d.frec[FAM] + i * SL::STRIDE;
-    const int ac = CD * d.fcam[FAM][i], ag = a_grp(d, 3, d.fgrp[FAM][i]);
-    T zc[SL::NC], zg[SL::NG];
-#pragma unroll
-    for (int k = 0; k < SL::NC; ++k) zc[k] = 0;
-#pragma unroll
-    for (int k = 0; k < SL::NG; ++k) zg[k] = 0;
-#pragma unroll 1
-    for (int row = 0; row < SL::ROWS; ++row) {
-      T t = 0;
-#pragma unroll
-      for (int k = 0; k < SL::NC; ++k) t += sl[SL::OC + row * SL::NC + k] * x[ac + k];
-#pragma unroll
-      for (int k = 0; k < SL::NG; ++k) t += sl[SL::OG + row * SL::NG + k] * x[ag + k];
-#pragma unroll
-      for (int a = 0; a < NF; ++a) t -= sl[SL::OF + row * NF + a] * s[a];
-#pragma unroll
-      for (int k = 0; k < SL::NC; ++k) zc[k] += sl[SL::OC + row * SL::NC + k] * t;
-#pragma unroll
-      for (int k = 0; k < SL::NG; ++k) zg[k] += sl[SL::OG + row * SL::NG + k] * t;
-    }
-#pragma unroll
-    for (int k = 0; k < SL::NC; ++k) atomicAdd(y + ac + k, (double)zc[k]);
-#pragma unroll
-    for (int k = 0; k < SL::NG; ++k) atomicAdd(y + ag + k, (double)zg[k]);
-  }
-}
 
 // back-substitution: |J h|^2 over the feature's surface-group records (FP64 sums)
 template <int FAM, typename T, int CD, int NF>
@@ -1445,15 +1392,30 @@ void launch_precond_blockjacobi(const Dev& d, hipStream_t s) {
 // ---------------------------------------------------------------------------
 // implicit-Schur product y = J_a^T (J_a x - J_f V^-1 J_f^T J_a x) (+ lambda D_a x
 // in the reduction), one lane per feature
-template <int FAM, typename T, int CD, int NF> __device__ __forceinline__ void mv_first(const Dev& d, int f, const T* x, T (&q)[NF]) {
+// One record of the product's first half: q += J_f^T J_a x. The slot is loaded whole,
+// except for the surface-group families, whose slots are read a row at a time (ROWS1;
+// else all rows' loads at once, where registers allow).
+template <int FAM, typename T, int CD, int NF, bool ROWS1 = true>
+__device__ __forceinline__ void rec_first(const Dev& d, int64_t i, const T* x, T (&q)[NF]) {
   using SL = Slot<FAM, CD>;
   using F = Fam<FAM, CD>;
-  if (!d.fn[FAM]) return;
-  const int64_t b = d.foff[FAM][f], e = d.foff[FAM][f + 1];
-  const T* rec = (const T*)d.frec[FAM];
-  for (int64_t i = b; i < e; ++i) {
+  const T* sl = (const T*)d.frec[FAM] + i * SL::STRIDE;
+  if constexpr (F::GT == 3) {
+    const T* xc = x + CD * d.fcam[FAM][i];
+    const T* xg = x + a_grp(d, 3, d.fgrp[FAM][i]);
+#pragma unroll ROWS1 ? 1 : SL::ROWS
+    for (int row = 0; row < SL::ROWS; ++row) {
+      T t = 0;
+#pragma unroll
+      for (int k = 0; k < SL::NC; ++k) t += sl[SL::OC + row * SL::NC + k] * xc[k];
+#pragma unroll
+      for (int k = 0; k < SL::NG; ++k) t += sl[SL::OG + row * SL::NG + k] * xg[k];
+#pragma unroll
+      for (int a = 0; a < NF; ++a) q[a] += sl[SL::OF + row * NF + a] * t;
+    }
+  } else {
     T v[SL::STRIDE];
-    load_vec(rec + i * SL::STRIDE, v);
+    load_vec(sl, v);
     T xc[SL::NC > 0 ? SL::NC : 1], xg[SL::NG > 0 ? SL::NG : 1];
     if constexpr (SL::NC > 0) {
       const T* xp = x + CD * d.fcam[FAM][i];
@@ -1478,32 +1440,44 @@ template <int FAM, typename T, int CD, int NF> __device__ __forceinline__ void m
   }
 }
 
-template <int FAM, typename T, int CD, int NF> __device__ __forceinline__ void mv_second(const Dev& d, int f, const T* x, const T (&s)[NF], double* y) {
+// One record of the second half: y_a += J_a^T (J_a x - J_f s). With gacc, the rows of a
+// surface-group record's shape are added to gacc (SH_DOF values) instead of to y.
+template <int FAM, typename T, int CD, int NF, bool ROWS1 = true>
+__device__ __forceinline__ void rec_second(const Dev& d, int64_t i, const T* x, const T (&s)[NF], double* y, T* gacc = nullptr) {
   using SL = Slot<FAM, CD>;
   using F = Fam<FAM, CD>;
-  if (!d.fn[FAM]) return;
-  const int64_t b = d.foff[FAM][f], e = d.foff[FAM][f + 1];
-  const T* rec = (const T*)d.frec[FAM];
-  for (int64_t i = b; i < e; ++i) {
+  const T* sl = (const T*)d.frec[FAM] + i * SL::STRIDE;
+  int ac = 0, ag = 0;
+  if constexpr (SL::NC > 0) ac = CD * d.fcam[FAM][i];
+  if constexpr (SL::NG > 0) ag = a_grp(d, F::GT, d.fgrp[FAM][i]);
+  T zc[SL::NC > 0 ? SL::NC : 1], zg[SL::NG > 0 ? SL::NG : 1];
+#pragma unroll
+  for (int k = 0; k < SL::NC; ++k) zc[k] = 0;
+#pragma unroll
+  for (int k = 0; k < SL::NG; ++k) zg[k] = 0;
+  if constexpr (F::GT == 3) {
+#pragma unroll ROWS1 ? 1 : SL::ROWS
+    for (int row = 0; row < SL::ROWS; ++row) {
+      T t = 0;
+#pragma unroll
+      for (int k = 0; k < SL::NC; ++k) t += sl[SL::OC + row * SL::NC + k] * x[ac + k];
+#pragma unroll
+      for (int k = 0; k < SL::NG; ++k) t += sl[SL::OG + row * SL::NG + k] * x[ag + k];
+#pragma unroll
+      for (int a = 0; a < NF; ++a) t -= sl[SL::OF + row * NF + a] * s[a];
+#pragma unroll
+      for (int k = 0; k < SL::NC; ++k) zc[k] += sl[SL::OC + row * SL::NC + k] * t;
+#pragma unroll
+      for (int k = 0; k < SL::NG; ++k) zg[k] += sl[SL::OG + row * SL::NG + k] * t;
+    }
+  } else {
     T v[SL::STRIDE];
-    load_vec(rec + i * SL::STRIDE, v);
-    int ac = 0, ag = 0;
+    load_vec(sl, v);
     T xc[SL::NC > 0 ? SL::NC : 1], xg[SL::NG > 0 ? SL::NG : 1];
-    if constexpr (SL::NC > 0) {
-      ac = CD * d.fcam[FAM][i];
 #pragma unroll
-      for (int k = 0; k < SL::NC; ++k) xc[k] = x[ac + k];
-    }
-    if constexpr (SL::NG > 0) {
-      ag = a_grp(d, F::GT, d.fgrp[FAM][i]);
+    for (int k = 0; k < SL::NC; ++k) xc[k] = x[ac + k];
 #pragma unroll
-      for (int k = 0; k < SL::NG; ++k) xg[k] = x[ag + k];
-    }
-    T zc[SL::NC > 0 ? SL::NC : 1], zg[SL::NG > 0 ? SL::NG : 1];
-#pragma unroll
-    for (int k = 0; k < SL::NC; ++k) zc[k] = 0;
-#pragma unroll
-    for (int k = 0; k < SL::NG; ++k) zg[k] = 0;
+    for (int k = 0; k < SL::NG; ++k) xg[k] = x[ag + k];
 #pragma unroll
     for (int row = 0; row < SL::ROWS; ++row) {
       T t = 0;
@@ -1518,45 +1492,120 @@ template <int FAM, typename T, int CD, int NF> __device__ __forceinline__ void m
 #pragma unroll
       for (int k = 0; k < SL::NG; ++k) zg[k] += v[SL::OG + row * SL::NG + k] * t;
     }
-#pragma unroll
-    for (int k = 0; k < SL::NC; ++k) atomicAdd(y + ac + k, (double)zc[k]);
-#pragma unroll
-    for (int k = 0; k < SL::NG; ++k) atomicAdd(y + ag + k, (double)zg[k]);
   }
+#pragma unroll
+  for (int k = 0; k < SL::NC; ++k) atomicAdd(y + ac + k, (double)zc[k]);
+  if constexpr (F::GT == 3) {
+    if (gacc) {
+#pragma unroll
+      for (int k = 0; k < SL::NG; ++k) gacc[k] += zg[k];
+      return;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < SL::NG; ++k) atomicAdd(y + ag + k, (double)zg[k]);
 }
 
-template <typename T, int CD, int NF> __device__ __forceinline__ void mv_feature(const Dev& d, int f, const T* x, double* y) {
+template <int FAM, typename T, int CD, int NF> __device__ __forceinline__ void mv_first(const Dev& d, int f, const T* x, T (&q)[NF]) {
+  if (!d.fn[FAM]) return;
+  for (int64_t i = d.foff[FAM][f]; i < d.foff[FAM][f + 1]; ++i) rec_first<FAM, T, CD, NF>(d, i, x, q);
+}
+
+template <int FAM, typename T, int CD, int NF> __device__ __forceinline__ void mv_second(const Dev& d, int f, const T* x, const T (&s)[NF], double* y) {
+  if (!d.fn[FAM]) return;
+  for (int64_t i = d.foff[FAM][f]; i < d.foff[FAM][f + 1]; ++i) rec_second<FAM, T, CD, NF>(d, i, x, s, y);
+}
+
+// One wavefront per feature (a feature larger than a tile, or a line on a shape): its
+// records, family after family, over the lanes in rounds of 64; q summed across the
+// wavefront, s_f solved on every lane, then each lane's records added to y. The shape
+// rows (a feature is on one shape at most) are summed across the wavefront and added
+// once. Every lane of the wavefront calls this with the same f, and all are active.
+template <int FAM, typename T, int CD, int NF>
+__device__ __forceinline__ void wave_first(const Dev& d, int64_t b, int n, const T* x, int& j0, int lane, T (&q)[NF]) {
+  // the family's records continue the feature's sequence at position j0: record r is on
+  // lane (j0 + r) mod 64
+  for (int r = (lane - j0 % 64 + 64) % 64; r < n; r += 64) rec_first<FAM, T, CD, NF, false>(d, b + r, x, q);
+  j0 += n;
+}
+
+template <int FAM, typename T, int CD, int NF>
+__device__ __forceinline__ void wave_second(const Dev& d, int64_t b, int n, const T* x, const T (&s)[NF], double* y,
+                                            int& j0, int lane, T* gacc = nullptr) {
+  for (int r = (lane - j0 % 64 + 64) % 64; r < n; r += 64) rec_second<FAM, T, CD, NF, false>(d, b + r, x, s, y, gacc);
+  j0 += n;
+}
+
+// shy: when given, the shape rows go to this LDS copy of y's shape block (index from
+// d.offSh) instead of to y
+template <typename T, int CD, int NF>
+__device__ __forceinline__ void mv_feature_wave(const Dev& d, int f, const T* x, double* y, int lane, double* shy = nullptr) {
+  constexpr int F0 = NF == 3 ? 1 : 2, F1 = NF == 3 ? 3 : 4, F2 = NF == 3 ? 6 : 5, F3 = NF == 3 ? 8 : 7;
+  constexpr int FS = NF == 3 ? 9 : 10, NS = NF * (NF + 1) / 2;
+  // every family's record range, the feature's inverse and flag fetched together (one
+  // memory round ahead of the records), then the shape's rows in y
+  int64_t b[5];
+  int n[5];
+  auto range = [&](int k, int F) {
+    if (d.fn[F]) {
+      b[k] = d.foff[F][f];
+      n[k] = (int)(d.foff[F][f + 1] - b[k]);
+    } else {
+      b[k] = 0;
+      n[k] = 0;
+    }
+  };
+  range(0, F0); range(1, F1); range(2, F2); range(3, F3); range(4, FS);
+  const bool flag = (NF == 3 ? d.flp : d.fll)[f] != 0;
+  T m[NS];
+  {
+    const T* M = (const T*)(NF == 3 ? d.Vip : d.Vil) + (int64_t)NS * f;
+#pragma unroll
+    for (int k = 0; k < NS; ++k) m[k] = M[k];
+  }
+  const int ag = n[4] > 0 ? a_grp(d, 3, d.fgrp[FS][b[4]]) : 0;
   T q[NF];
 #pragma unroll
   for (int k = 0; k < NF; ++k) q[k] = 0;
-  if constexpr (NF == 3) {
-    mv_first<1, T, CD, 3>(d, f, x, q);
-    mv_first<3, T, CD, 3>(d, f, x, q);
-    mv_first<6, T, CD, 3>(d, f, x, q);
-    mv_first<8, T, CD, 3>(d, f, x, q);
-    mv_first_rows<9, T, CD, 3>(d, f, x, q);
-  } else {
-    mv_first<2, T, CD, 4>(d, f, x, q);
-    mv_first<4, T, CD, 4>(d, f, x, q);
-    mv_first<5, T, CD, 4>(d, f, x, q);
-    mv_first<7, T, CD, 4>(d, f, x, q);
-    mv_first_rows<10, T, CD, 4>(d, f, x, q);
-  }
+  int j0 = 0;
+  wave_first<F0, T, CD, NF>(d, b[0], n[0], x, j0, lane, q);
+  wave_first<F1, T, CD, NF>(d, b[1], n[1], x, j0, lane, q);
+  wave_first<F2, T, CD, NF>(d, b[2], n[2], x, j0, lane, q);
+  wave_first<F3, T, CD, NF>(d, b[3], n[3], x, j0, lane, q);
+  wave_first<FS, T, CD, NF>(d, b[4], n[4], x, j0, lane, q);
+#pragma unroll
+  for (int k = 0; k < NF; ++k) q[k] = wave_sum(q[k]);
   T s[NF];
-  apply_vinv<T, NF>(d, f, q, s);
-  if constexpr (NF == 3) {
-    mv_second<1, T, CD, 3>(d, f, x, s, y);
-    mv_second<3, T, CD, 3>(d, f, x, s, y);
-    mv_second<6, T, CD, 3>(d, f, x, s, y);
-    mv_second<8, T, CD, 3>(d, f, x, s, y);
-    mv_second_rows<9, T, CD, 3>(d, f, x, s, y);
+  if (flag) {
+    apply_vinv<T, NF>(d, f, q, s);  // a flagged block: its FP64 inverse
   } else {
-    mv_second<2, T, CD, 4>(d, f, x, s, y);
-    mv_second<4, T, CD, 4>(d, f, x, s, y);
-    mv_second<5, T, CD, 4>(d, f, x, s, y);
-    mv_second<7, T, CD, 4>(d, f, x, s, y);
-    mv_second_rows<10, T, CD, 4>(d, f, x, s, y);
+#pragma unroll
+    for (int i = 0; i < NF; ++i) {
+      T t = 0;
+#pragma unroll
+      for (int j = 0; j < NF; ++j) t += m[sym<NF>(i, j)] * q[j];
+      s[i] = t;
+    }
   }
+  // the second half's records in any order: the shape's first, so that their sums are
+  // added (and released) before the other families' records
+  j0 = 0;
+  if (n[4] > 0) {
+    T gacc[SH_DOF];
+#pragma unroll
+    for (int k = 0; k < SH_DOF; ++k) gacc[k] = 0;
+    wave_second<FS, T, CD, NF>(d, b[4], n[4], x, s, y, j0, lane, gacc);
+    double* ys = shy ? shy + (ag - d.offSh) : y + ag;
+#pragma unroll
+    for (int k = 0; k < SH_DOF; ++k) {
+      const T w = wave_sum(gacc[k]);
+      if (lane == 0) atomicAdd(ys + k, (double)w);
+    }
+  }
+  wave_second<F0, T, CD, NF>(d, b[0], n[0], x, s, y, j0, lane);
+  wave_second<F1, T, CD, NF>(d, b[1], n[1], x, s, y, j0, lane);
+  wave_second<F2, T, CD, NF>(d, b[2], n[2], x, s, y, j0, lane);
+  wave_second<F3, T, CD, NF>(d, b[3], n[3], x, s, y, j0, lane);
 }
 
 // deterministic product, first pass: s_f = (V_f + lambda D_f)^-1 J_f^T J_a x of one feature
@@ -1569,13 +1618,13 @@ template <typename T, int CD, int NF> __device__ __forceinline__ void mv_feature
     mv_first<3, T, CD, 3>(d, f, x, q);
     mv_first<6, T, CD, 3>(d, f, x, q);
     mv_first<8, T, CD, 3>(d, f, x, q);
-    mv_first_rows<9, T, CD, 3>(d, f, x, q);
+    mv_first<9, T, CD, 3>(d, f, x, q);
   } else {
     mv_first<2, T, CD, 4>(d, f, x, q);
     mv_first<4, T, CD, 4>(d, f, x, q);
     mv_first<5, T, CD, 4>(d, f, x, q);
     mv_first<7, T, CD, 4>(d, f, x, q);
-    mv_first_rows<10, T, CD, 4>(d, f, x, q);
+    mv_first<10, T, CD, 4>(d, f, x, q);
   }
   T sv[NF];
   apply_vinv<T, NF>(d, f, q, sv);
@@ -1657,6 +1706,28 @@ __device__ __forceinline__ float wave_sum(float v) {
   v += __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x1F | (16 << 10)));
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 0)) +
          __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 32));
+}
+
+template <int XOR> __device__ __forceinline__ double swizzle_xor(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_ds_swizzle((int)(b & 0xffffffffll), 0x1F | (XOR << 10));
+  const int hi = __builtin_amdgcn_ds_swizzle((int)(b >> 32), 0x1F | (XOR << 10));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+  v += swizzle_xor<1>(v);
+  v += swizzle_xor<2>(v);
+  v += swizzle_xor<4>(v);
+  v += swizzle_xor<8>(v);
+  v += swizzle_xor<16>(v);
+  const long long b = __double_as_longlong(v);
+  const int lo = (int)(b & 0xffffffffll), hi = (int)(b >> 32);
+  const double h0 = __longlong_as_double(((long long)__builtin_amdgcn_readlane(hi, 0) << 32) |
+                                         (unsigned int)__builtin_amdgcn_readlane(lo, 0));
+  const double h1 = __longlong_as_double(((long long)__builtin_amdgcn_readlane(hi, 32) << 32) |
+                                         (unsigned int)__builtin_amdgcn_readlane(lo, 32));
+  return h0 + h1;
 }
 
 // In FP32 the shape rows (group type 3) are staged in the wavefront's LDS rows gz[k *
@@ -1883,22 +1954,48 @@ __global__ __launch_bounds__(MV_THREADS) void k_mv_wave(Dev d, const double* don
       }
     }
   }
-  // features whose records do not fit one tile (and features on a shape): one lane per
-  // feature, dealt round-robin over the workgroups (lane t of workgroup b takes
-  // b + t * gridDim.x), so that every CU shares the pass
-  for (int k = blockIdx.x + gridDim.x * threadIdx.x; k < d.n_bigp + d.n_bigl; k += gridDim.x * blockDim.x) {
-    if constexpr (SONLY) {
+  // features whose records do not fit one tile (and the lines on a shape) are k_mv_big's;
+  // the deterministic mode's first pass takes them here, one lane each, dealt round-robin
+  // over the workgroups (lane t of workgroup b takes b + t * gridDim.x)
+  if constexpr (SONLY) {
+    for (int k = blockIdx.x + gridDim.x * threadIdx.x; k < d.n_bigp + d.n_bigl; k += gridDim.x * blockDim.x) {
       if (k < d.n_bigp) mv_feature_s<T, CD, 3>(d, d.bigp[k], x);
       else mv_feature_s<T, CD, 4>(d, d.bigl[k - d.n_bigp], x);
-    } else {
-      if (k < d.n_bigp) mv_feature<T, CD, 3>(d, d.bigp[k], x, ys);
-      else mv_feature<T, CD, 4>(d, d.bigl[k - d.n_bigp], x, ys);
     }
   }
   if constexpr (LDSY) {
     __syncthreads();
     double* out = d.mv_part + (int64_t)blockIdx.x * d.nA;
     for (int k = threadIdx.x; k < d.nA; k += blockDim.x) out[k] = ys[k];
+  }
+}
+
+// The product's features larger than a tile (and the lines on a shape), one wavefront
+// each, launched after k_mv_wave on its stream: FP64 global atomics into row 0 of the
+// product partials, which k_mv_wave has written (LDS y) or accumulated into (global y).
+// A kernel of its own, so that its registers do not add to the tiles'; run alone, so that
+// its chain of dependent memory rounds is not slowed by the tiles' traffic (measured
+// slower beside them on a second stream).
+template <typename T, int CD> __global__ __launch_bounds__(MV_BIG_THREADS) void k_mv_big(Dev d, const double* done) {
+  // the shape rows summed in LDS first and added to y once per workgroup (the features of
+  // one shape would otherwise all add into the same global rows, one after another)
+  extern __shared__ double big_sh[];
+  if (done && *done != 0.0) return;
+  const bool lsh = d.ns > 0 && d.ns * SH_DOF <= MV_BIG_SH_MAX;
+  if (lsh) {
+    for (int k = threadIdx.x; k < d.ns * SH_DOF; k += blockDim.x) big_sh[k] = 0;
+    __syncthreads();
+  }
+  const T* x = (const T*)d.xT;
+  const int lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+  for (int k = blockIdx.x * nw + (threadIdx.x >> 6); k < d.n_bigp + d.n_bigl; k += gridDim.x * nw) {
+    if (k < d.n_bigp) mv_feature_wave<T, CD, 3>(d, d.bigp[k], x, d.mv_part, lane, lsh ? big_sh : nullptr);
+    else mv_feature_wave<T, CD, 4>(d, d.bigl[k - d.n_bigp], x, d.mv_part, lane, lsh ? big_sh : nullptr);
+  }
+  if (lsh) {
+    __syncthreads();
+    for (int k = threadIdx.x; k < d.ns * SH_DOF; k += blockDim.x)
+      if (big_sh[k] != 0.0) atomicAdd(d.mv_part + d.offSh + k, big_sh[k]);
   }
 }
 
@@ -1924,6 +2021,11 @@ template <typename T, int CD, bool LDSY> static void launch_mv(const Dev& d, con
                                matvec_max_lds_bytes()) == hipSuccess;
   }
   k_mv_wave<T, CD, LDSY><<<d.n_mv_wg, MV_THREADS, matvec_lds_bytes(d), s>>>(d, done);
+  const int nbig = d.n_bigp + d.n_bigl;
+  if (nbig) {
+    const size_t sh = d.ns > 0 && d.ns * SH_DOF <= MV_BIG_SH_MAX ? (size_t)d.ns * SH_DOF * sizeof(double) : 0;
+    k_mv_big<T, CD><<<std::min(nblk(nbig, MV_BIG_THREADS / 64), 4096u), MV_BIG_THREADS, sh, s>>>(d, done);
+  }
 }
 
 // deterministic product, second pass (defined with the S Z sweeps, whose record and
@@ -3217,13 +3319,13 @@ template <typename T, int CD, int NF> __device__ __forceinline__ void backsub_on
     mv_first<3, T, CD, 3>(d, f, x, q);
     mv_first<6, T, CD, 3>(d, f, x, q);
     mv_first<8, T, CD, 3>(d, f, x, q);
-    mv_first_rows<9, T, CD, 3>(d, f, x, q);
+    mv_first<9, T, CD, 3>(d, f, x, q);
   } else {
     mv_first<2, T, CD, 4>(d, f, x, q);
     mv_first<4, T, CD, 4>(d, f, x, q);
     mv_first<5, T, CD, 4>(d, f, x, q);
     mv_first<7, T, CD, 4>(d, f, x, q);
-    mv_first_rows<10, T, CD, 4>(d, f, x, q);
+    mv_first<10, T, CD, 4>(d, f, x, q);
   }
   const T* g = (const T*)(NF == 3 ? d.gp : d.gl) + (int64_t)NF * f;
 #pragma unroll
