@@ -1076,8 +1076,9 @@ void finalize(ba_handle* h) {
     if (const char* e = std::getenv("BA_TILE_RECORDS")) cap = std::max(1, std::min(MV_TILE, std::atoi(e)));
     for (int fam = 1; fam < NFAM; ++fam)
       if (d.fn[fam] >= (int64_t)1 << 28) throw BaError(BA_E_INVALID, "more than 2^28 records in one family");
-    // a line on a cuboid (family 10, whose slots exceed the tiles' register budget) takes
-    // the one-lane-per-feature path; points on shapes (family 9) go in the tiles
+    // a line on a cuboid (family 10, whose slots exceed the tiles' register budget) is a
+    // large feature (one wavefront each in k_mv_big); points on shapes (family 9) go in
+    // the tiles
     auto build = [&](const std::vector<int>& fams, int nfeat, std::vector<int32_t>& big, int fam_big) {
       auto on_shape = [&](int f) { return fam_big > 0 && foff_h[fam_big][f + 1] > foff_h[fam_big][f]; };
       int f = 0;
