@@ -2718,6 +2718,45 @@ __device__ __forceinline__ void sz_feat_family(const Dev& d, int f, const T* Zr,
   }
 }
 
+// s_f = (V_f + lambda D_f)^-1 q for the SZ_COLS columns of one feature, stored to its
+// contiguous NF x SZ_COLS block of sf: the feature's FP32 inverse is read once (not per
+// column after the column's stores, which may alias it); a flagged block takes its FP64
+// inverse column by column
+template <typename T, int NF, int QF>
+__device__ __forceinline__ void sz_solve_store(const Dev& d, int f, const T (&q)[QF][SZ_COLS], T* sf) {
+  constexpr int NS = NF * (NF + 1) / 2;
+  T out[NF][SZ_COLS];
+  if ((NF == 3 ? d.flp : d.fll)[f]) {
+    for (int c = 0; c < SZ_COLS; ++c) {
+      T qc[NF], sc[NF];
+#pragma unroll
+      for (int a = 0; a < NF; ++a) qc[a] = q[a][c];
+      apply_vinv<T, NF>(d, f, qc, sc);
+#pragma unroll
+      for (int a = 0; a < NF; ++a) out[a][c] = sc[a];
+    }
+  } else {
+    const T* M = (const T*)(NF == 3 ? d.Vip : d.Vil) + (int64_t)NS * f;
+    T m[NS];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) m[k] = M[k];
+#pragma unroll
+    for (int c = 0; c < SZ_COLS; ++c)
+#pragma unroll
+      for (int a = 0; a < NF; ++a) {
+        T t = 0;
+#pragma unroll
+        for (int b = 0; b < NF; ++b) t += m[sym<NF>(a, b)] * q[b][c];
+        out[a][c] = t;
+      }
+  }
+  T* o = sf + (int64_t)f * NF * SZ_COLS;
+#pragma unroll
+  for (int a = 0; a < NF; ++a)
+#pragma unroll
+    for (int c = 0; c < SZ_COLS; ++c) o[a * SZ_COLS + c] = out[a][c];
+}
+
 // s_f (NF x SZ_COLS, T) of one feature, one lane (Zr, sf: one panel)
 template <typename T, int CD, int NF> __device__ __forceinline__ void sz_feature(const Dev& d, int f, const T* Zr, T* sf) {
   T q[NF][SZ_COLS];
@@ -2738,14 +2777,7 @@ template <typename T, int CD, int NF> __device__ __forceinline__ void sz_feature
     sz_feat_family<7, T, CD, 4>(d, f, Zr, q);
     sz_feat_rows<10, T, CD, 4, SZ_COLS>(d, f, Zr, q);
   }
-  for (int c = 0; c < SZ_COLS; ++c) {
-    T qc[NF], sc[NF];
-#pragma unroll
-    for (int a = 0; a < NF; ++a) qc[a] = q[a][c];
-    apply_vinv<T, NF>(d, f, qc, sc);
-#pragma unroll
-    for (int a = 0; a < NF; ++a) sf[((int64_t)f * NF + a) * SZ_COLS + c] = sc[a];
-  }
+  sz_solve_store<T, NF>(d, f, q, sf);
 }
 
 // features larger than a product tile, one lane per listed feature
@@ -2849,22 +2881,8 @@ template <typename T, int CD> __global__ __launch_bounds__(256) void k_sz_feat_w
     }
     const int next = __shfl_down(lf, 1, 64);
     if (lf >= 0 && (lane == 63 || next != lf)) {
-      const int f = fb + lf;
-      if (ptile) {
-        for (int c = 0; c < SZ_COLS; ++c) {
-          T qc[3] = {q[0][c], q[1][c], q[2][c]}, sc[3];
-          apply_vinv<T, 3>(d, f, qc, sc);
-#pragma unroll
-          for (int a = 0; a < 3; ++a) sfp[((int64_t)f * 3 + a) * SZ_COLS + c] = sc[a];
-        }
-      } else {
-        for (int c = 0; c < SZ_COLS; ++c) {
-          T qc[4] = {q[0][c], q[1][c], q[2][c], q[3][c]}, sc[4];
-          apply_vinv<T, 4>(d, f, qc, sc);
-#pragma unroll
-          for (int a = 0; a < 4; ++a) sfl[((int64_t)f * 4 + a) * SZ_COLS + c] = sc[a];
-        }
-      }
+      if (ptile) sz_solve_store<T, 3>(d, fb + lf, q, sfp);
+      else sz_solve_store<T, 4>(d, fb + lf, q, sfl);
     }
   }
 }
