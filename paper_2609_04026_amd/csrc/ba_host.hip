@@ -964,6 +964,24 @@ void finalize(ba_handle* h) {
     int32_t*& dst = pair == 0 ? d.shal_p : d.shal_l;
     dst = A.get<int32_t>(al.size());
     upload(h, dst, al);
+    // the same records listed per camera, with their features
+    std::vector<int32_t> cnt(h->nc + 1, 0), off(h->nc + 1, 0), rec, feat;
+    for (const Rec& r : v) cnt[r.cam + 1]++;
+    for (int c = 0; c < h->nc; ++c) cnt[c + 1] += cnt[c];
+    for (int c = 0; c < h->nc; ++c) {
+      for (int32_t pos = cnt[c]; pos < cnt[c + 1]; ++pos)
+        if (al[pos] >= 0) {
+          rec.push_back(al[pos]);
+          feat.push_back(R[fs][al[pos]].feat);
+        }
+      off[c + 1] = (int32_t)rec.size();
+    }
+    d.shc_off[pair] = A.get<int32_t>(off.size());
+    d.shc_rec[pair] = A.get<int32_t>(rec.size());
+    d.shc_feat[pair] = A.get<int32_t>(feat.size());
+    upload(h, d.shc_off[pair], off);
+    upload(h, d.shc_rec[pair], rec);
+    upload(h, d.shc_feat[pair], feat);
   }
   {
     std::vector<std::vector<int32_t>> mp(h->ns), ml(h->ns);

@@ -93,6 +93,10 @@ struct Dev {
   // shape; a line on a cuboid is one of the product's big features.
   int32_t *shp_off = nullptr, *shp = nullptr, *shl_off = nullptr, *shl = nullptr;
   int32_t *shal_p = nullptr, *shal_l = nullptr;
+  // per camera (offsets shc_off[k], nc + 1), its point-on-shape (k = 0) or line-on-cuboid
+  // (k = 1) records in camera-major order and their features: the camera sweeps that add
+  // each record on its own take them in a loop of their own
+  int32_t *shc_off[2] = {nullptr, nullptr}, *shc_rec[2] = {nullptr, nullptr}, *shc_feat[2] = {nullptr, nullptr};
   // the shape passes take chunks of at most SH_CHUNK members of one shape, a workgroup
   // each: int4 (shape, first member, members, 0 points / 1 lines); FP64 accumulators
   // summed over a shape's chunks: U (packed) and g, or the S-block terms and b
@@ -229,7 +233,7 @@ constexpr int COARSE_GAUGE = 7, COARSE_NET = 8, COARSE_K = COARSE_GAUGE + COARSE
 // the coarse columns in the S Z sweeps (Z rows, s_f) are stored in panels of SZ_COLS
 // columns, row-major within a panel
 constexpr int SZ_COLS = 8, SZ_PANELS = 2;
-constexpr int SH_CHUNK = 256, SH_ACC = SH_DOF * (SH_DOF + 1) / 2 + SH_DOF;
+constexpr int SH_CHUNK = 128, SH_ACC = SH_DOF * (SH_DOF + 1) / 2 + SH_DOF;
 static_assert(COARSE_K <= SZ_COLS * SZ_PANELS, "coarse columns per S Z panel set");
 // With FP32 records the product resolves S Z only to ~1e-7 |S| |Z|, while on the
 // near-null (gauge) directions S Z ~ lambda D_A Z: below this damping the coarse

@@ -1006,12 +1006,14 @@ template <typename T, int CD> __global__ __launch_bounds__(256) void k_cam_a(Dev
       const int k = d.cmal[1][j];
       if (k >= 0)
         cam_a_slot<3, T, CD>((const T*)d.cmrec[3] + (int64_t)k * Slot<3, CD>::STRIDE, (const T*)d.cmres[3] + (int64_t)k * Slot<3, CD>::ROWS, U, g);
-      if (d.shal_p) {  // the aligned point-on-shape record
-        const int k9 = d.shal_p[j];
-        if (k9 >= 0) cam_a_rows<9, T, CD>(d, k9, U, g);
-      }
     }
   }
+  // the camera's point-on-shape and line-on-cuboid records, in loops of their own (inside
+  // the observation loops every wavefront would take both paths)
+  if (d.shc_off[0])
+    for (int j = d.shc_off[0][c] + threadIdx.x; j < d.shc_off[0][c + 1]; j += blockDim.x) cam_a_rows<9, T, CD>(d, d.shc_rec[0][j], U, g);
+  if (d.shc_off[1])
+    for (int j = d.shc_off[1][c] + threadIdx.x; j < d.shc_off[1][c + 1]; j += blockDim.x) cam_a_rows<10, T, CD>(d, d.shc_rec[1][j], U, g);
   if (d.fn[6]) {
     for (int j = d.px_off[c] + threadIdx.x; j < d.px_off[c + 1]; j += blockDim.x)
       for (int64_t i = d.px_start[j]; i < d.px_start[j] + d.px_cnt[j]; ++i) cam_a_rec<6, T, CD>(d, i, U, g);
@@ -1022,10 +1024,6 @@ template <typename T, int CD> __global__ __launch_bounds__(256) void k_cam_a(Dev
       const int k = d.cmal[2][j];
       if (k >= 0)
         cam_a_slot<4, T, CD>((const T*)d.cmrec[4] + (int64_t)k * Slot<4, CD>::STRIDE, (const T*)d.cmres[4] + (int64_t)k * Slot<4, CD>::ROWS, U, g);
-      if (d.shal_l) {  // the aligned line-on-cuboid record
-        const int k10 = d.shal_l[j];
-        if (k10 >= 0) cam_a_rows<10, T, CD>(d, k10, U, g);
-      }
     }
   }
   if (d.fn[7]) {
@@ -2993,11 +2991,14 @@ __global__ __launch_bounds__(256) void k_sz_cam(Dev d, const T* Zr, const T* sfp
         z_cols<3, CPL>(zr, a_grp(d, Fam<3, CD>::GT, d.cmgrp[3][k]), zg);
         sz_rec_cols<3, 0, T, CD>((const T*)d.cmrec[3] + (int64_t)k * Slot<3, CD>::STRIDE, zc, zg, sp + (int64_t)f * 3 * SZ_COLS, acc);
       }
-      if (d.shal_p) {
-        const int k9 = d.shal_p[j];
-        if (k9 >= 0) sz_shape_rec<9, 0, T, CD, CPL>(d, k9, zc, zr, sp + (int64_t)f * 3 * SZ_COLS, acc);
-      }
     }
+  // the camera's point-on-shape and line-on-cuboid records, in loops of their own
+  if (d.shc_off[0])
+    for (int j = d.shc_off[0][c] + rs; j < d.shc_off[0][c + 1]; j += R)
+      sz_shape_rec<9, 0, T, CD, CPL>(d, d.shc_rec[0][j], zc, zr, sp + (int64_t)d.shc_feat[0][j] * 3 * SZ_COLS, acc);
+  if (d.shc_off[1])
+    for (int j = d.shc_off[1][c] + rs; j < d.shc_off[1][c + 1]; j += R)
+      sz_shape_rec<10, 0, T, CD, CPL>(d, d.shc_rec[1][j], zc, zr, sl + (int64_t)d.shc_feat[1][j] * 4 * SZ_COLS, acc);
   if (d.fn[6])
     for (int j = d.px_off[c] + rs; j < d.px_off[c + 1]; j += R)
       for (int64_t i = d.px_start[j]; i < d.px_start[j] + d.px_cnt[j]; ++i)
@@ -3011,10 +3012,6 @@ __global__ __launch_bounds__(256) void k_sz_cam(Dev d, const T* Zr, const T* sfp
         T zg[3][CPL];
         z_cols<3, CPL>(zr, a_grp(d, Fam<4, CD>::GT, d.cmgrp[4][k]), zg);
         sz_rec_cols<4, 0, T, CD>((const T*)d.cmrec[4] + (int64_t)k * Slot<4, CD>::STRIDE, zc, zg, sl + (int64_t)f * 4 * SZ_COLS, acc);
-      }
-      if (d.shal_l) {
-        const int k10 = d.shal_l[j];
-        if (k10 >= 0) sz_shape_rec<10, 0, T, CD, CPL>(d, k10, zc, zr, sl + (int64_t)f * 4 * SZ_COLS, acc);
       }
     }
   if (d.fn[7])
