@@ -414,9 +414,9 @@ def test_empty_and_feature_free_problems(precision):
 
 
 def test_large_feature_path_matches(monkeypatch):
-    """Features whose records exceed a product tile take the one-lane-per-
-    feature path; with the tile capacity forced to 8 records most features do,
-    and the implicit-Schur product must still equal the dense S x."""
+    """Features whose records exceed a product tile take the large-feature kernel
+    (one wavefront per feature); with the tile capacity forced to 8 records most
+    features do, and the implicit-Schur product must still equal the dense S x."""
     monkeypatch.setenv("BA_TILE_RECORDS", "8")
     from paper_2609_04026_amd.binding import BA
     s = make_scene(2)
@@ -430,4 +430,57 @@ def test_large_feature_path_matches(monkeypatch):
         ref = sys_["S"] @ x
         y = ba.schur_matvec(x)
         assert np.linalg.norm(y - ref) <= 10 * tol * np.linalg.norm(ref)
+        ba.close()
+
+
+def _seen_by_all(n_cams=70, seed=3):
+    """A 70-camera scene whose point 0 (on a plane) is observed, exactly, by every camera
+    in front of it: with its plane records well over 64 records, so that the product's
+    wavefront for it takes several rounds of 64 lanes."""
+    from scenegen import small_config
+    from scenegen.scene import _RenderCams, OBS_POINT, quaternion_to_matrix
+    s = make_scene(small_config(n_cams=n_cams, n_points=40, n_lines=0, n_vps=0, vp_lines=0), seed=seed)
+    cg = np.asarray(s["cameras_gt"])
+    cams = _RenderCams(quaternion_to_matrix(cg[:, 0:4]), cg[:, 4:7], cg[:, 7], cg[:, 8], cg[:, 9])
+    X = np.asarray(s["points_gt"])[0]
+    c_all = np.arange(len(cg))
+    xd, z = cams.pixels(c_all, np.broadcast_to(X, (len(cg), 3)), distort=True)
+    xu, _ = cams.pixels(c_all, np.broadcast_to(X, (len(cg), 3)), distort=False)
+    seen = z > 1.0
+    a, b, m = (np.asarray(v) for v in s["obs"][OBS_POINT])
+    keep = b != 0
+    cams_p = c_all[seen].astype(a.dtype)
+    meas = np.concatenate([xd[seen], xu[seen]], axis=1)
+    obs = dict(s["obs"])
+    obs[OBS_POINT] = (np.concatenate([a[keep], cams_p]), np.concatenate([b[keep], np.zeros(len(cams_p), b.dtype)]),
+                      np.concatenate([m[keep], meas]))
+    return dict(s, obs=obs), int(seen.sum())
+
+
+def test_feature_with_more_records_than_a_wavefront():
+    from paper_2609_04026_amd.binding import BA
+    from scenegen.scene import ASSOC_PLANE_POINT
+    s, n_seen = _seen_by_all()
+    assert 0 in set(np.asarray(s["obs"][ASSOC_PLANE_POINT][1]).tolist())
+    prob = lm.Problem(s)
+    st = prob.state0()
+    lin = lm.linearize(prob, st)
+    keys = record_keys(prob.recs)
+    n0 = sum(int((keys[f][:, 2] == 0).sum()) for f in ("R1", "R3", "R6", "R8") if len(keys[f]))
+    print(f"[case] point 0 seen by {n_seen} cameras, {n0} records", flush=True)
+    assert n0 > 128
+    lam = 1e-3
+    Sx = lm.schur(prob, lin, lam)["S"]
+    h, _ = lm.solve_schur(prob, lin, lam)
+    E1 = lm.cost(prob, prob.retract(st, h))[0]
+    for precision, tol in (("fp64", 1e-9), ("mixed", 1e-4)):
+        ba = BA.from_scene(s, precision=precision)
+        ba.linearize(lam)
+        x = np.random.default_rng(2).normal(size=prob.nA)
+        err = np.abs(ba.schur_matvec(x) - Sx @ x) / np.maximum(np.abs(Sx) @ np.abs(x), 1e-300)
+        assert err.max() <= 10 * tol, (precision, err.max())
+        ba.close()
+        ba = BA.from_scene(s, precision=precision)
+        rep = ba.lm_step(lambda0=lam, pcg_tol=1e-12 if precision == "fp64" else 1e-7, pcg_max_iters=3000)
+        assert abs(rep["E_after"] - E1) <= tol * E1, (precision, rep["E_after"], E1)
         ba.close()
