@@ -3400,7 +3400,11 @@ __device__ __forceinline__ double bs_record_reload(const Dev& d, int64_t i, cons
 // q_f = sum J_f^T t as in the product, h_f = -(V_f + lambda D_f)^-1 (g_f + q_f) on the
 // feature's last lane, then |J_a h_a + J_f h_f|^2 per record; per-workgroup sums of
 // g_f . h_f and |J h|^2 go to d.red
-template <typename T, int CD> __global__ __launch_bounds__(256) void k_backsub_wave(Dev d) {
+// FP32: at most 128 VGPRs (4 wavefronts per SIMD; 132 without the bound, 3 per SIMD);
+// FP64 would spill under it
+template <typename T> constexpr int backsub_min_waves() { return sizeof(T) == 4 ? 4 : 1; }
+
+template <typename T, int CD> __global__ __launch_bounds__(256, backsub_min_waves<T>()) void k_backsub_wave(Dev d) {
   __shared__ double lds[2 * 5];
   const T* x = (const T*)d.xT;
   const int lane = threadIdx.x & 63, nw = blockDim.x >> 6;
