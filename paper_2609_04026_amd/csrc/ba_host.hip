@@ -1147,6 +1147,10 @@ void finalize(ba_handle* h) {
   const size_t stage_bytes = d.mv_stage ? MV_STAGE_BYTES : 0;
   if (stage_bytes > (size_t)max_lds) throw BaError(BA_E_DEVICE, "the product's LDS staging does not fit a workgroup");
   d.mv_lds = (size_t)nA * 8 + stage_bytes <= (size_t)max_lds ? 1 : 0;
+  // BA_PRODUCT_GLOBAL_Y=1 accumulates the product in global memory whatever n_A (the mode
+  // of reduced systems too large for LDS); used by tests
+  if (const char* e = std::getenv("BA_PRODUCT_GLOBAL_Y"))
+    if (std::atoi(e) != 0) d.mv_lds = 0;
   const size_t lds_bytes = matvec_lds_bytes(d);
   const int wg_per_cu = (int)std::max<size_t>(1, std::min<size_t>(2, 163840 / std::max<size_t>(lds_bytes, 1)));
   const int64_t waves = d.n_tiles + (d.n_bigp + d.n_bigl + 63) / 64;

@@ -484,3 +484,27 @@ def test_feature_with_more_records_than_a_wavefront():
         rep = ba.lm_step(lambda0=lam, pcg_tol=1e-12 if precision == "fp64" else 1e-7, pcg_max_iters=3000)
         assert abs(rep["E_after"] - E1) <= tol * E1, (precision, rep["E_after"], E1)
         ba.close()
+
+
+@pytest.mark.parametrize("with_shapes", [False, True])
+def test_product_in_global_memory(monkeypatch, with_shapes):
+    """The product's global-memory mode (reduced systems whose y does not fit in LDS),
+    forced on small scenes: S x entry by entry against the oracle's S, in both
+    precisions; with shapes, the FP32 shape rows staged at the start of the LDS."""
+    monkeypatch.setenv("BA_PRODUCT_GLOBAL_Y", "1")
+    from paper_2609_04026_amd.binding import BA
+    from scenegen import add_shapes
+    s = make_scene(small_config(n_cams=9, n_points=70, n_lines=20), seed=101)
+    if with_shapes:
+        s = add_shapes(s, seed=5, points_per_shape=60, lines_per_cuboid=6)
+    prob = lm.Problem(s)
+    lin = lm.linearize(prob, prob.state0())
+    Sx = lm.schur(prob, lin, 1e-3)["S"]
+    for precision, tol in (("fp64", 1e-9), ("mixed", 1e-4)):
+        ba = BA.from_scene(s, precision=precision)
+        ba.linearize(1e-3)
+        for seed in (1, 2):
+            x = np.random.default_rng(seed).normal(size=Sx.shape[0])
+            err = np.abs(ba.schur_matvec(x) - Sx @ x) / np.maximum(np.abs(Sx) @ np.abs(x), 1e-300)
+            assert err.max() <= 10 * tol, (precision, err.max())
+        ba.close()
