@@ -52,13 +52,18 @@ SCENES = {
 }
 
 
+@pytest.mark.parametrize("tile_records", [None, "8"])
 @pytest.mark.parametrize("name", list(SCENES))
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_deterministic_step_and_product_match_oracle(name, precision):
+def test_deterministic_step_and_product_match_oracle(name, precision, tile_records, monkeypatch):
     """One deterministic LM step against the oracle's exact Schur step, then
     the deterministic product (the handle keeps the mode) against the dense S
     entry by entry; then a default-mode step on the same handle, whose
-    product must match again (the modes share the product's buffers)."""
+    product must match again (the modes share the product's buffers). With
+    tiles of at most 8 records most features are large: the deterministic
+    pass takes them one lane each, the default product one wavefront each."""
+    if tile_records:
+        monkeypatch.setenv("BA_TILE_RECORDS", tile_records)
     s = SCENES[name]()
     prob = lm.Problem(s)
     st = prob.state0()
