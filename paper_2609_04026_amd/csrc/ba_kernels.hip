@@ -629,41 +629,6 @@ __device__ __forceinline__ void bs_second_rows(const Dev& d, int f, const T* x, 
   }
 }
 
-// S Z sweeps: q[a][c] += J_f^T J_a Z over the feature's surface-group records (Zr: one panel)
-template <int FAM, typename T, int CD, int NF, int NCOL>
-__device__ __forceinline__ void sz_feat_rows(const Dev& d, int f, const T* Zr, T (&q)[NF][NCOL]) {
-  using SL = Slot<FAM, CD>;
-  if (!d.fn[FAM]) return;
-  for (int64_t i = d.foff[FAM][f]; i < d.foff[FAM][f + 1]; ++i) {
-    const T* sl = (const T*)d.frec[FAM] + i * SL::STRIDE;
-    const T* zc = Zr + (int64_t)CD * d.fcam[FAM][i] * NCOL;
-    const T* zg = Zr + (int64_t)a_grp(d, 3, d.fgrp[FAM][i]) * NCOL;
-#pragma unroll 1
-    for (int row = 0; row < SL::ROWS; ++row) {
-      T t[NCOL];
-#pragma unroll
-      for (int c = 0; c < NCOL; ++c) t[c] = 0;
-#pragma unroll
-      for (int k = 0; k < SL::NC; ++k) {
-        const T j = sl[SL::OC + row * SL::NC + k];
-#pragma unroll
-        for (int c = 0; c < NCOL; ++c) t[c] += j * zc[k * NCOL + c];
-      }
-#pragma unroll
-      for (int k = 0; k < SL::NG; ++k) {
-        const T j = sl[SL::OG + row * SL::NG + k];
-#pragma unroll
-        for (int c = 0; c < NCOL; ++c) t[c] += j * zg[k * NCOL + c];
-      }
-#pragma unroll
-      for (int a = 0; a < NF; ++a) {
-        const T j = sl[SL::OF + row * NF + a];
-#pragma unroll
-        for (int c = 0; c < NCOL; ++c) q[a][c] += j * t[c];
-      }
-    }
-  }
-}
 
 // S Z sweeps, output rows, with the Z rows of the output side in registers: zk holds the
 // rows of the record's camera (OUT 0, a camera's sweep) or of its shape (OUT 1, a shape's
@@ -2694,27 +2659,6 @@ __device__ __forceinline__ void sz_record_t(const Dev& d, int64_t i, const T* Zr
   }
 }
 
-template <int FAM, typename T, int CD, int NF>
-__device__ __forceinline__ void sz_feat_family(const Dev& d, int f, const T* Zr, T (&q)[NF][SZ_COLS]) {
-  using SL = Slot<FAM, CD>;
-  if (!d.fn[FAM]) return;
-  const T* rec = (const T*)d.frec[FAM];
-  for (int64_t i = d.foff[FAM][f]; i < d.foff[FAM][f + 1]; ++i) {
-    T v[SL::STRIDE];
-    load_vec(rec + i * SL::STRIDE, v);
-    T t[4][SZ_COLS];
-    sz_record_t<FAM, T, CD>(d, i, Zr, v, t);
-#pragma unroll
-    for (int a = 0; a < NF; ++a)
-#pragma unroll
-      for (int c = 0; c < SZ_COLS; ++c) {
-        T s = 0;
-#pragma unroll
-        for (int row = 0; row < SL::ROWS; ++row) s += v[SL::OF + row * NF + a] * t[row][c];
-        q[a][c] += s;
-      }
-  }
-}
 
 // s_f = (V_f + lambda D_f)^-1 q for the SZ_COLS columns of one feature, stored to its
 // contiguous NF x SZ_COLS block of sf: the feature's FP32 inverse is read once (not per
@@ -2755,33 +2699,102 @@ __device__ __forceinline__ void sz_solve_store(const Dev& d, int f, const T (&q)
     for (int c = 0; c < SZ_COLS; ++c) o[a * SZ_COLS + c] = out[a][c];
 }
 
-// s_f (NF x SZ_COLS, T) of one feature, one lane (Zr, sf: one panel)
-template <typename T, int CD, int NF> __device__ __forceinline__ void sz_feature(const Dev& d, int f, const T* Zr, T* sf) {
+// one record's J_f^T J_a Z (SZ_COLS columns of one panel) added to q: the slot loaded
+// whole, or a row at a time for the surface-group families
+template <int FAM, typename T, int CD, int NF>
+__device__ __forceinline__ void sz_rec_q(const Dev& d, int64_t i, const T* Zr, T (&q)[NF][SZ_COLS]) {
+  using SL = Slot<FAM, CD>;
+  if constexpr (Fam<FAM, CD>::GT == 3) {
+    const T* sl = (const T*)d.frec[FAM] + i * SL::STRIDE;
+    const T* zc = Zr + (int64_t)CD * d.fcam[FAM][i] * SZ_COLS;
+    const T* zg = Zr + (int64_t)a_grp(d, 3, d.fgrp[FAM][i]) * SZ_COLS;
+#pragma unroll 1
+    for (int row = 0; row < SL::ROWS; ++row) {
+      T t[SZ_COLS];
+#pragma unroll
+      for (int c = 0; c < SZ_COLS; ++c) t[c] = 0;
+#pragma unroll
+      for (int k = 0; k < SL::NC; ++k) {
+        const T j = sl[SL::OC + row * SL::NC + k];
+#pragma unroll
+        for (int c = 0; c < SZ_COLS; ++c) t[c] += j * zc[k * SZ_COLS + c];
+      }
+#pragma unroll
+      for (int k = 0; k < SL::NG; ++k) {
+        const T j = sl[SL::OG + row * SL::NG + k];
+#pragma unroll
+        for (int c = 0; c < SZ_COLS; ++c) t[c] += j * zg[k * SZ_COLS + c];
+      }
+#pragma unroll
+      for (int a = 0; a < NF; ++a) {
+        const T j = sl[SL::OF + row * NF + a];
+#pragma unroll
+        for (int c = 0; c < SZ_COLS; ++c) q[a][c] += j * t[c];
+      }
+    }
+  } else {
+    T v[SL::STRIDE];
+    load_vec((const T*)d.frec[FAM] + i * SL::STRIDE, v);
+    T t[4][SZ_COLS];
+    sz_record_t<FAM, T, CD>(d, i, Zr, v, t);
+#pragma unroll
+    for (int a = 0; a < NF; ++a)
+#pragma unroll
+      for (int c = 0; c < SZ_COLS; ++c) {
+        T acc = 0;
+#pragma unroll
+        for (int row = 0; row < SL::ROWS; ++row) acc += v[SL::OF + row * NF + a] * t[row][c];
+        q[a][c] += acc;
+      }
+  }
+}
+
+template <int FAM, typename T, int CD, int NF>
+__device__ __forceinline__ void sz_wave_family(const Dev& d, int f, const T* Zr, int& j0, int lane, T (&q)[NF][SZ_COLS]) {
+  if (!d.fn[FAM]) return;
+  const int64_t b = d.foff[FAM][f];
+  const int n = (int)(d.foff[FAM][f + 1] - b);
+  // record r of the family is on lane (j0 + r) mod 64
+  for (int r = (lane - j0 % 64 + 64) % 64; r < n; r += 64) sz_rec_q<FAM, T, CD, NF>(d, b + r, Zr, q);
+  j0 += n;
+}
+
+// s_f of one feature larger than a tile (or a line on a shape), one wavefront: its
+// records over the lanes, q summed across the wavefront, solved and stored by lane 0
+// (Zr, sf: one panel). Every lane calls this with the same f, and all are active.
+template <typename T, int CD, int NF> __device__ __forceinline__ void sz_feature_wave(const Dev& d, int f, const T* Zr, T* sf, int lane) {
   T q[NF][SZ_COLS];
 #pragma unroll
   for (int a = 0; a < NF; ++a)
 #pragma unroll
     for (int c = 0; c < SZ_COLS; ++c) q[a][c] = 0;
+  int j0 = 0;
   if constexpr (NF == 3) {
-    sz_feat_family<1, T, CD, 3>(d, f, Zr, q);
-    sz_feat_family<3, T, CD, 3>(d, f, Zr, q);
-    sz_feat_family<6, T, CD, 3>(d, f, Zr, q);
-    sz_feat_family<8, T, CD, 3>(d, f, Zr, q);
-    sz_feat_rows<9, T, CD, 3, SZ_COLS>(d, f, Zr, q);
+    sz_wave_family<1, T, CD, 3>(d, f, Zr, j0, lane, q);
+    sz_wave_family<3, T, CD, 3>(d, f, Zr, j0, lane, q);
+    sz_wave_family<6, T, CD, 3>(d, f, Zr, j0, lane, q);
+    sz_wave_family<8, T, CD, 3>(d, f, Zr, j0, lane, q);
+    sz_wave_family<9, T, CD, 3>(d, f, Zr, j0, lane, q);
   } else {
-    sz_feat_family<2, T, CD, 4>(d, f, Zr, q);
-    sz_feat_family<4, T, CD, 4>(d, f, Zr, q);
-    sz_feat_family<5, T, CD, 4>(d, f, Zr, q);
-    sz_feat_family<7, T, CD, 4>(d, f, Zr, q);
-    sz_feat_rows<10, T, CD, 4, SZ_COLS>(d, f, Zr, q);
+    sz_wave_family<2, T, CD, 4>(d, f, Zr, j0, lane, q);
+    sz_wave_family<4, T, CD, 4>(d, f, Zr, j0, lane, q);
+    sz_wave_family<5, T, CD, 4>(d, f, Zr, j0, lane, q);
+    sz_wave_family<7, T, CD, 4>(d, f, Zr, j0, lane, q);
+    sz_wave_family<10, T, CD, 4>(d, f, Zr, j0, lane, q);
   }
-  sz_solve_store<T, NF>(d, f, q, sf);
+#pragma unroll
+  for (int a = 0; a < NF; ++a)
+#pragma unroll
+    for (int c = 0; c < SZ_COLS; ++c) q[a][c] = wave_sum(q[a][c]);
+  if (lane == 0) sz_solve_store<T, NF>(d, f, q, sf);
 }
 
-// features larger than a product tile, one lane per listed feature
+
+// features larger than a product tile (and lines on a shape), one wavefront per listed
+// feature
 template <typename T, int CD, int NF> __global__ __launch_bounds__(256) void k_sz_feat_big(Dev d, const T* Zr, T* sf, const int32_t* list, int n) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k < n) sz_feature<T, CD, NF>(d, list[k], Zr, sf);
+  const int lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+  for (int k = blockIdx.x * nw + (threadIdx.x >> 6); k < n; k += gridDim.x * nw) sz_feature_wave<T, CD, NF>(d, list[k], Zr, sf, lane);
 }
 
 // q[a][c] = sum over rows of J_f[row][a] (J_a Z_r)[row][c] for one record
@@ -3269,9 +3282,9 @@ template <typename T, int CD> static void launch_sz(const Dev& d, double lambda,
       continue;
     }
     if (d.n_tiles) k_sz_feat_wave<T, CD><<<(int)std::min<int64_t>(4 * (int64_t)d.n_mv_wg, nblk(d.n_tiles, 4)), 256, 0, s>>>(d, zp, pp, lp);
-    // one wavefront per workgroup: the per-lane feature sums are latency-bound, spread them
-    if (d.n_bigp) k_sz_feat_big<T, CD, 3><<<nblk(d.n_bigp, 64), 64, 0, s>>>(d, zp, pp, d.bigp, d.n_bigp);
-    if (d.n_bigl) k_sz_feat_big<T, CD, 4><<<nblk(d.n_bigl, 64), 64, 0, s>>>(d, zp, lp, d.bigl, d.n_bigl);
+    // one wavefront per large feature
+    if (d.n_bigp) k_sz_feat_big<T, CD, 3><<<std::min(nblk(d.n_bigp, 4), 4096u), 256, 0, s>>>(d, zp, pp, d.bigp, d.n_bigp);
+    if (d.n_bigl) k_sz_feat_big<T, CD, 4><<<std::min(nblk(d.n_bigl, 4), 4096u), 256, 0, s>>>(d, zp, lp, d.bigl, d.n_bigl);
   }
   static_assert(SZ_PANELS == 2, "one or two panels");
   if (d.coarse_k <= COARSE_GAUGE) launch_sz_out<T, CD, SZ_LANES, SZ_COLS / SZ_LANES>(d, Zr, sfp, sfl, lambda, s);
