@@ -606,28 +606,6 @@ __device__ __forceinline__ void addW_rows(const Dev& d, int64_t i, T (&W)[N][NF]
 
 
 
-// back-substitution: |J h|^2 over the feature's surface-group records (FP64 sums)
-template <int FAM, typename T, int CD, int NF>
-__device__ __forceinline__ void bs_second_rows(const Dev& d, int f, const T* x, const T (&h)[NF], double& jh2) {
-  using SL = Slot<FAM, CD>;
-  if (!d.fn[FAM]) return;
-  for (int64_t i = d.foff[FAM][f]; i < d.foff[FAM][f + 1]; ++i) {
-    const T* sl = (const T*)d.frec[FAM] + i * SL::STRIDE;
-    const T* xc = x + CD * d.fcam[FAM][i];
-    const T* xg = x + a_grp(d, 3, d.fgrp[FAM][i]);
-#pragma unroll 1
-    for (int row = 0; row < SL::ROWS; ++row) {
-      double t = 0;
-#pragma unroll
-      for (int k = 0; k < SL::NC; ++k) t += (double)sl[SL::OC + row * SL::NC + k] * (double)xc[k];
-#pragma unroll
-      for (int k = 0; k < SL::NG; ++k) t += (double)sl[SL::OG + row * SL::NG + k] * (double)xg[k];
-#pragma unroll
-      for (int a = 0; a < NF; ++a) t += (double)sl[SL::OF + row * NF + a] * (double)h[a];
-      jh2 += t * t;
-    }
-  }
-}
 
 
 // S Z sweeps, output rows, with the Z rows of the output side in registers: zk holds the
@@ -3301,18 +3279,35 @@ void launch_coarse_setup(const Dev& d, double lambda, hipStream_t s) {
   k_coarse_inv<<<1, 512, 0, s>>>(d, E);
 }
 
+
 // ---------------------------------------------------------------------------
 // back-substitution h_f = -(V_f + lambda D_f)^-1 (g_f + J_f^T J_a h_a), and the
 // model-decrease terms h.g and sum |J h|^2 (FP64 accumulation)
-template <int FAM, typename T, int CD, int NF> __device__ __forceinline__ void bs_second(const Dev& d, int f, const T* x, const T (&h)[NF], double& jh2) {
+// |J x_a + J_f h|^2 of one record (FP64 sums): the slot loaded whole, or a row at a time
+// for the surface-group families
+template <int FAM, typename T, int CD, int NF>
+__device__ __forceinline__ double rec_jh2(const Dev& d, int64_t i, const T* x, const T (&h)[NF]) {
   using SL = Slot<FAM, CD>;
   using F = Fam<FAM, CD>;
-  if (!d.fn[FAM]) return;
-  const int64_t b = d.foff[FAM][f], e = d.foff[FAM][f + 1];
-  const T* rec = (const T*)d.frec[FAM];
-  for (int64_t i = b; i < e; ++i) {
+  const T* sl = (const T*)d.frec[FAM] + i * SL::STRIDE;
+  double jh2 = 0;
+  if constexpr (F::GT == 3) {
+    const T* xc = x + CD * d.fcam[FAM][i];
+    const T* xg = x + a_grp(d, 3, d.fgrp[FAM][i]);
+#pragma unroll 1
+    for (int row = 0; row < SL::ROWS; ++row) {
+      double t = 0;
+#pragma unroll
+      for (int k = 0; k < SL::NC; ++k) t += (double)sl[SL::OC + row * SL::NC + k] * (double)xc[k];
+#pragma unroll
+      for (int k = 0; k < SL::NG; ++k) t += (double)sl[SL::OG + row * SL::NG + k] * (double)xg[k];
+#pragma unroll
+      for (int a = 0; a < NF; ++a) t += (double)sl[SL::OF + row * NF + a] * (double)h[a];
+      jh2 += t * t;
+    }
+  } else {
     T v[SL::STRIDE];
-    load_vec(rec + i * SL::STRIDE, v);
+    load_vec(sl, v);
     T xc[SL::NC > 0 ? SL::NC : 1], xg[SL::NG > 0 ? SL::NG : 1];
     if constexpr (SL::NC > 0) {
       const T* xp = x + CD * d.fcam[FAM][i];
@@ -3336,50 +3331,66 @@ template <int FAM, typename T, int CD, int NF> __device__ __forceinline__ void b
       jh2 += t * t;
     }
   }
+  return jh2;
 }
 
-template <typename T, int CD, int NF> __device__ __forceinline__ void backsub_one(const Dev& d, int f, const T* x, double& gh, double& jh2) {
+template <int FAM, typename T, int CD, int NF>
+__device__ __forceinline__ double wave_jh2(const Dev& d, int64_t b, int n, const T* x, const T (&h)[NF], int& j0, int lane) {
+  double jh2 = 0;
+  for (int r = (lane - j0 % 64 + 64) % 64; r < n; r += 64) jh2 += rec_jh2<FAM, T, CD, NF>(d, b + r, x, h);
+  j0 += n;
+  return jh2;
+}
+
+// back-substitution of one feature larger than a tile (or a line on a shape), one
+// wavefront: q = J_f^T J_a h_a summed across it, h_f = -(V_f + lambda D_f)^-1 (g_f + q)
+// stored and g_f . h_f added by lane 0, |J h|^2 of each lane's records added on that lane
+template <typename T, int CD, int NF>
+__device__ __forceinline__ void backsub_feature_wave(const Dev& d, int f, const T* x, int lane, double& gh, double& jh2) {
+  constexpr int F0 = NF == 3 ? 1 : 2, F1 = NF == 3 ? 3 : 4, F2 = NF == 3 ? 6 : 5, F3 = NF == 3 ? 8 : 7;
+  constexpr int FS = NF == 3 ? 9 : 10;
+  int64_t b[5];
+  int n[5];
+  auto range = [&](int k, int F) {
+    if (d.fn[F]) {
+      b[k] = d.foff[F][f];
+      n[k] = (int)(d.foff[F][f + 1] - b[k]);
+    } else {
+      b[k] = 0;
+      n[k] = 0;
+    }
+  };
+  range(0, F0); range(1, F1); range(2, F2); range(3, F3); range(4, FS);
   T q[NF];
 #pragma unroll
   for (int k = 0; k < NF; ++k) q[k] = 0;
-  if constexpr (NF == 3) {
-    mv_first<1, T, CD, 3>(d, f, x, q);
-    mv_first<3, T, CD, 3>(d, f, x, q);
-    mv_first<6, T, CD, 3>(d, f, x, q);
-    mv_first<8, T, CD, 3>(d, f, x, q);
-    mv_first<9, T, CD, 3>(d, f, x, q);
-  } else {
-    mv_first<2, T, CD, 4>(d, f, x, q);
-    mv_first<4, T, CD, 4>(d, f, x, q);
-    mv_first<5, T, CD, 4>(d, f, x, q);
-    mv_first<7, T, CD, 4>(d, f, x, q);
-    mv_first<10, T, CD, 4>(d, f, x, q);
-  }
+  int j0 = 0;
+  wave_first<F0, T, CD, NF>(d, b[0], n[0], x, j0, lane, q);
+  wave_first<F1, T, CD, NF>(d, b[1], n[1], x, j0, lane, q);
+  wave_first<F2, T, CD, NF>(d, b[2], n[2], x, j0, lane, q);
+  wave_first<F3, T, CD, NF>(d, b[3], n[3], x, j0, lane, q);
+  wave_first<FS, T, CD, NF>(d, b[4], n[4], x, j0, lane, q);
   const T* g = (const T*)(NF == 3 ? d.gp : d.gl) + (int64_t)NF * f;
 #pragma unroll
-  for (int k = 0; k < NF; ++k) q[k] = -(q[k] + g[k]);
+  for (int k = 0; k < NF; ++k) q[k] = -(wave_sum(q[k]) + g[k]);
   T h[NF];
   apply_vinv<T, NF>(d, f, q, h);
-  double* ho = (NF == 3 ? d.hp : d.hl) + (int64_t)NF * f;
+  if (lane == 0) {
+    double* ho = (NF == 3 ? d.hp : d.hl) + (int64_t)NF * f;
 #pragma unroll
-  for (int k = 0; k < NF; ++k) {
-    ho[k] = (double)h[k];
-    gh += (double)g[k] * (double)h[k];
+    for (int k = 0; k < NF; ++k) {
+      ho[k] = (double)h[k];
+      gh += (double)g[k] * (double)h[k];
+    }
   }
-  if constexpr (NF == 3) {
-    bs_second<1, T, CD, 3>(d, f, x, h, jh2);
-    bs_second<3, T, CD, 3>(d, f, x, h, jh2);
-    bs_second<6, T, CD, 3>(d, f, x, h, jh2);
-    bs_second<8, T, CD, 3>(d, f, x, h, jh2);
-    bs_second_rows<9, T, CD, 3>(d, f, x, h, jh2);
-  } else {
-    bs_second<2, T, CD, 4>(d, f, x, h, jh2);
-    bs_second<4, T, CD, 4>(d, f, x, h, jh2);
-    bs_second<5, T, CD, 4>(d, f, x, h, jh2);
-    bs_second<7, T, CD, 4>(d, f, x, h, jh2);
-    bs_second_rows<10, T, CD, 4>(d, f, x, h, jh2);
-  }
+  j0 = 0;
+  jh2 += wave_jh2<F0, T, CD, NF>(d, b[0], n[0], x, h, j0, lane);
+  jh2 += wave_jh2<F1, T, CD, NF>(d, b[1], n[1], x, h, j0, lane);
+  jh2 += wave_jh2<F2, T, CD, NF>(d, b[2], n[2], x, h, j0, lane);
+  jh2 += wave_jh2<F3, T, CD, NF>(d, b[3], n[3], x, h, j0, lane);
+  jh2 += wave_jh2<FS, T, CD, NF>(d, b[4], n[4], x, h, j0, lane);
 }
+
 
 // |J h|^2 of one record given t = J_a h_a and the broadcast h_f (FP64 sum)
 template <int FAM, typename T, int CD>
@@ -3533,16 +3544,30 @@ template <typename T, int CD> __global__ __launch_bounds__(256, backsub_min_wave
       }
     }
   }
-  // features whose records do not fit one tile (and features on a shape): one lane per
-  // feature, dealt round-robin over the workgroups (lane t of workgroup b takes
-  // b + t * gridDim.x), so that every CU shares the pass
-  for (int k = blockIdx.x + gridDim.x * threadIdx.x; k < d.n_bigp + d.n_bigl; k += gridDim.x * blockDim.x) {
-    if (k < d.n_bigp) backsub_one<T, CD, 3>(d, d.bigp[k], x, gh, jh2);
-    else backsub_one<T, CD, 4>(d, d.bigl[k - d.n_bigp], x, gh, jh2);
-  }
+  // features whose records do not fit one tile (and features on a shape) are
+  // k_backsub_big's
   double vals[2] = {gh, jh2};
   double* o = block_sum_arr<double, 2>(vals, lds);
   if (threadIdx.x == 0) { d.red[2 * blockIdx.x] = o[0]; d.red[2 * blockIdx.x + 1] = o[1]; }
+}
+
+// back-substitution of the large features, one wavefront each; its workgroups' (g.h,
+// |J h|^2) partials follow k_backsub_wave's in d.red from slot red0
+template <typename T, int CD> __global__ __launch_bounds__(256) void k_backsub_big(Dev d, int red0) {
+  __shared__ double lds[2 * 5];
+  const T* x = (const T*)d.xT;
+  const int lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+  double gh = 0, jh2 = 0;
+  for (int k = blockIdx.x * nw + (threadIdx.x >> 6); k < d.n_bigp + d.n_bigl; k += gridDim.x * nw) {
+    if (k < d.n_bigp) backsub_feature_wave<T, CD, 3>(d, d.bigp[k], x, lane, gh, jh2);
+    else backsub_feature_wave<T, CD, 4>(d, d.bigl[k - d.n_bigp], x, lane, gh, jh2);
+  }
+  double vals[2] = {gh, jh2};
+  double* o = block_sum_arr<double, 2>(vals, lds);
+  if (threadIdx.x == 0) {
+    d.red[2 * (red0 + blockIdx.x)] = o[0];
+    d.red[2 * (red0 + blockIdx.x) + 1] = o[1];
+  }
 }
 
 // J h over the records of the features is covered by the feature pass (the
@@ -3558,12 +3583,16 @@ __global__ __launch_bounds__(1024) void k_md_final(Dev d, int nparts) {
 }
 
 void launch_backsub(const Dev& d, hipStream_t s) {
-  const int nwg = (int)std::max<int64_t>(1, std::min<int64_t>(4 * (int64_t)d.n_mv_wg, d.n_red_max));
+  // the large features' workgroups take at most half of the partial slots
+  const int nbig = d.n_bigp + d.n_bigl;
+  const int gbig = nbig ? (int)std::min<int64_t>(std::min<int64_t>(nblk(nbig, 4), 64), d.n_red_max / 2) : 0;
+  const int nwg = (int)std::max<int64_t>(1, std::min<int64_t>(4 * (int64_t)d.n_mv_wg, d.n_red_max - gbig));
   BA_DISPATCH_T_CD(d, {
     k_to_T<T><<<nblk(d.nA, 256), 256, 0, s>>>(d.x, d.xT, d.nA);
     k_backsub_wave<T, CD><<<nwg, 256, 0, s>>>(d);
+    if (gbig) k_backsub_big<T, CD><<<gbig, 256, 0, s>>>(d, nwg);
   });
-  k_md_final<<<1, 1024, 0, s>>>(d, nwg);
+  k_md_final<<<1, 1024, 0, s>>>(d, nwg + gbig);
   launch_rel_md(d, s);
 }
 
