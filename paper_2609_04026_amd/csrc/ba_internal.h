@@ -138,7 +138,8 @@ struct Dev {
   int n_tiles = 0, n_ptiles = 0;
   int4* tiles = nullptr;
   int4* wrec = nullptr;
-  // features too large for one tile (handled one lane per feature)
+  // features too large for one tile (and lines on a shape): one wavefront each in the
+  // product, S Z and back-substitution, one lane each in the deterministic pass
   int n_bigp = 0, n_bigl = 0;
   int32_t *bigp = nullptr, *bigl = nullptr;
   // inter-group relations (A-side records, FP64): group indices (planes or VPs), kind

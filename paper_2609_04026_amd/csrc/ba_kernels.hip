@@ -8,10 +8,13 @@
 //             Cholesky with a condition test, FP64 redo of flagged blocks
 //   camera    one workgroup per camera (group): U_aa, g_a, and per lambda the
 //             damped diagonal blocks of S and b with pair-summed W_af
-//   pcg       implicit-Schur product: one lane per feature, J_a x, then
-//             V_f^-1 J_f^T, then J_a^T accumulated into a workgroup-private
-//             copy of the reduced vector in LDS; FP64 vector updates and dots
-//   backsub   one lane per feature: h_f and the model decrease terms
+//   pcg       implicit-Schur product: wavefront tiles of whole features, one
+//             record per lane: J_a x, the feature sums by a segmented scan,
+//             V_f^-1 on the feature's last lane, then J_a^T accumulated into a
+//             workgroup-private copy of the reduced vector in LDS; features too
+//             large for a tile one wavefront each; FP64 vector updates and dots
+//   backsub   the same tiles (and one wavefront per large feature): h_f and the
+//             model decrease terms
 //   cost      one lane per record: FP64 residuals and robust cost
 #include <hip/hip_runtime.h>
 
