@@ -3433,9 +3433,13 @@ template <typename T> constexpr int backsub_min_waves() { return sizeof(T) == 4 
 
 template <typename T, int CD> __global__ __launch_bounds__(256, backsub_min_waves<T>()) void k_backsub_wave(Dev d) {
   __shared__ double lds[2 * 5];
+  // each lane's (g.h, |J h|^2) sums in LDS rather than in registers held across the tiles
+  __shared__ double bs_acc[2 * 256];
   const T* x = (const T*)d.xT;
   const int lane = threadIdx.x & 63, nw = blockDim.x >> 6;
-  double gh = 0, jh2 = 0;
+  double* acc = bs_acc + 2 * threadIdx.x;
+  acc[0] = 0;
+  acc[1] = 0;
   for (int tile = blockIdx.x * nw + (threadIdx.x >> 6); tile < d.n_tiles; tile += gridDim.x * nw) {
     const int4 tl = d.tiles[tile];
     const int fb = tl.z;
@@ -3513,7 +3517,7 @@ template <typename T, int CD> __global__ __launch_bounds__(256, backsub_min_wave
       for (int a = 0; a < 4; ++a)
         if (a < nfa) {
           ho[a] = (double)h[a];
-          gh += (double)g[a] * (double)h[a];
+          acc[0] += (double)g[a] * (double)h[a];
         }
     }
     const int src = lf >= 0 ? __builtin_ctzll(lasts & (~0ull << lane)) : lane;
@@ -3522,34 +3526,34 @@ template <typename T, int CD> __global__ __launch_bounds__(256, backsub_min_wave
     if (active) {
       if constexpr (sizeof(T) == 4) {
         switch (fam) {
-          case 1: jh2 += bs_record<1, T, CD>(v, t, h); break;
-          case 2: jh2 += bs_record<2, T, CD>(v, t, h); break;
-          case 3: jh2 += bs_record<3, T, CD>(v, t, h); break;
-          case 4: jh2 += bs_record<4, T, CD>(v, t, h); break;
-          case 5: jh2 += bs_record<5, T, CD>(v, t, h); break;
-          case 6: jh2 += bs_record<6, T, CD>(v, t, h); break;
-          case 7: jh2 += bs_record<7, T, CD>(v, t, h); break;
-          case 8: jh2 += bs_record<8, T, CD>(v, t, h); break;
-          case 9: jh2 += bs_record<9, T, CD>(v, t, h); break;
+          case 1: acc[1] += bs_record<1, T, CD>(v, t, h); break;
+          case 2: acc[1] += bs_record<2, T, CD>(v, t, h); break;
+          case 3: acc[1] += bs_record<3, T, CD>(v, t, h); break;
+          case 4: acc[1] += bs_record<4, T, CD>(v, t, h); break;
+          case 5: acc[1] += bs_record<5, T, CD>(v, t, h); break;
+          case 6: acc[1] += bs_record<6, T, CD>(v, t, h); break;
+          case 7: acc[1] += bs_record<7, T, CD>(v, t, h); break;
+          case 8: acc[1] += bs_record<8, T, CD>(v, t, h); break;
+          case 9: acc[1] += bs_record<9, T, CD>(v, t, h); break;
         }
       } else {
         switch (fam) {
-          case 1: jh2 += bs_record_reload<1, T, CD>(d, i, t, h); break;
-          case 2: jh2 += bs_record_reload<2, T, CD>(d, i, t, h); break;
-          case 3: jh2 += bs_record_reload<3, T, CD>(d, i, t, h); break;
-          case 4: jh2 += bs_record_reload<4, T, CD>(d, i, t, h); break;
-          case 5: jh2 += bs_record_reload<5, T, CD>(d, i, t, h); break;
-          case 6: jh2 += bs_record_reload<6, T, CD>(d, i, t, h); break;
-          case 7: jh2 += bs_record_reload<7, T, CD>(d, i, t, h); break;
-          case 8: jh2 += bs_record_reload<8, T, CD>(d, i, t, h); break;
-          case 9: jh2 += bs_record_reload<9, T, CD>(d, i, t, h); break;
+          case 1: acc[1] += bs_record_reload<1, T, CD>(d, i, t, h); break;
+          case 2: acc[1] += bs_record_reload<2, T, CD>(d, i, t, h); break;
+          case 3: acc[1] += bs_record_reload<3, T, CD>(d, i, t, h); break;
+          case 4: acc[1] += bs_record_reload<4, T, CD>(d, i, t, h); break;
+          case 5: acc[1] += bs_record_reload<5, T, CD>(d, i, t, h); break;
+          case 6: acc[1] += bs_record_reload<6, T, CD>(d, i, t, h); break;
+          case 7: acc[1] += bs_record_reload<7, T, CD>(d, i, t, h); break;
+          case 8: acc[1] += bs_record_reload<8, T, CD>(d, i, t, h); break;
+          case 9: acc[1] += bs_record_reload<9, T, CD>(d, i, t, h); break;
         }
       }
     }
   }
   // features whose records do not fit one tile (and features on a shape) are
   // k_backsub_big's
-  double vals[2] = {gh, jh2};
+  double vals[2] = {acc[0], acc[1]};
   double* o = block_sum_arr<double, 2>(vals, lds);
   if (threadIdx.x == 0) { d.red[2 * blockIdx.x] = o[0]; d.red[2 * blockIdx.x + 1] = o[1]; }
 }
